@@ -1,0 +1,266 @@
+"""Oracle for the Sinkhorn-based preprocessing of the optimal assignment problem.
+
+TEST INFRASTRUCTURE ONLY: a plain FP64 CPU statement of what the GPU library
+computes, written from the paper (Sharify, Gaubert, Grigori, arXiv:1104.3830).
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may import
+it. It shares no code with the HIP library and never imports it.
+
+Notation: b_ij = log a_ij (-inf where a_ij = 0); the scalings are held as
+ubar = p^-1 log u, vbar = p^-1 log v (Section 4.1.2), so the scaled matrix is
+x_ij(p) = exp(p (b_ij + ubar_i + vbar_j)).
+
+Every function cites the passage it follows; parity status of each part:
+  row/column step, Sinkhorn, ladder ... pinned (worked examples of Section 2.3
+      and Section 4.2, 2x2 closed form, permutation-ratio invariance,
+      brute-force limits)
+  prune ............................... pinned (support of the 5x5 example)
+  certificate ......................... pinned (upper bound vs brute force,
+      tight at convergence)
+  hungarian ........................... pinned (brute force n <= 8, scipy)
+  prescale ............................ pinned (range [1, e], idempotence,
+      invariance under entrywise powers, Section 4.1.1)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import build as _build
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_lib = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.LIB
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SRC):
+            _build.build()
+        L = ctypes.CDLL(path)
+        L.or_row_step.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _dp, _dp]
+        L.or_row_step.restype = ctypes.c_int
+        L.or_col_step.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _dp, _dp]
+        L.or_col_step.restype = ctypes.c_int
+        L.or_sums.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _dp, _dp, _dp, _dp]
+        L.or_sums.restype = None
+        L.or_row_residual.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _dp, _dp]
+        L.or_row_residual.restype = ctypes.c_double
+        L.or_sinkhorn.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _dp, _dp, ctypes.c_double,
+                                  ctypes.c_long, ctypes.POINTER(ctypes.c_long), _dp]
+        L.or_sinkhorn.restype = ctypes.c_int
+        L.or_scale_ladder.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_int, ctypes.c_double,
+                                      ctypes.c_long, _dp, _dp, ctypes.POINTER(ctypes.c_long), _dp]
+        L.or_scale_ladder.restype = ctypes.c_int
+        L.or_prune.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _dp, _dp, ctypes.c_double, _u8p]
+        L.or_prune.restype = ctypes.c_long
+        L.or_certificate.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _dp, _dp]
+        L.or_certificate.restype = ctypes.c_double
+        L.or_prescale.argtypes = [ctypes.c_int, _dp, _dp]
+        L.or_prescale.restype = None
+        L.or_hungarian.argtypes = [ctypes.c_int, _i64p, _u8p, _i32p, _i64p]
+        L.or_hungarian.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    return a.ctypes.data_as(_dp)
+
+
+class NoSupport(RuntimeError):
+    """A row or column of A has no positive entry (Section 2.1: A must have support)."""
+
+
+class Infeasible(RuntimeError):
+    """The (reduced) matrix has no perfect matching."""
+
+
+SENTINEL = -32768
+
+
+def log_weights(W: np.ndarray) -> np.ndarray:
+    """b = log A from int16 log-weights: w as float64, the sentinel as -inf."""
+    B = W.astype(np.float64)
+    B[W == SENTINEL] = -np.inf
+    return np.ascontiguousarray(B)
+
+
+def log_of(A: np.ndarray) -> np.ndarray:
+    """b = log A for a non-negative real matrix (log 0 = -inf)."""
+    with np.errstate(divide="ignore"):
+        return np.ascontiguousarray(np.log(np.asarray(A, dtype=np.float64)))
+
+
+def row_step(B, p, vbar):
+    """u = I(A^(p) v) in log coordinates (eq. dad2, Section 4.1.2)."""
+    n = B.shape[0]
+    vbar = np.ascontiguousarray(vbar, dtype=np.float64)
+    ubar = np.empty(n)
+    if lib().or_row_step(n, float(p), _d(B), _d(vbar), _d(ubar)):
+        raise NoSupport("a row has no finite entry")
+    return ubar
+
+
+def col_step(B, p, ubar):
+    """v = I(A^(p)T u) in log coordinates (eq. dad3, Section 4.1.2)."""
+    n = B.shape[0]
+    ubar = np.ascontiguousarray(ubar, dtype=np.float64)
+    vbar = np.empty(n)
+    if lib().or_col_step(n, float(p), _d(B), _d(ubar), _d(vbar)):
+        raise NoSupport("a column has no finite entry")
+    return vbar
+
+
+def sums(B, p, ubar, vbar):
+    """Row and column sums of X = diag(u) A^(p) diag(v)."""
+    n = B.shape[0]
+    r, c = np.empty(n), np.empty(n)
+    lib().or_sums(n, float(p), _d(B), _d(np.ascontiguousarray(ubar, dtype=np.float64)),
+                  _d(np.ascontiguousarray(vbar, dtype=np.float64)), _d(r), _d(c))
+    return r, c
+
+
+def row_residual(B, p, ubar, vbar):
+    """max_i |r_i - 1| (Section 4.2, epsilon-bistochastic distance)."""
+    n = B.shape[0]
+    return lib().or_row_residual(n, float(p), _d(B),
+                                 _d(np.ascontiguousarray(ubar, dtype=np.float64)),
+                                 _d(np.ascontiguousarray(vbar, dtype=np.float64)))
+
+
+def scaled_matrix(B, p, ubar, vbar):
+    """X = diag(u) A^(p) diag(v), x_ij = exp(p (b_ij + ubar_i + vbar_j))."""
+    with np.errstate(invalid="ignore", over="ignore"):
+        X = np.exp(p * (B + ubar[:, None] + vbar[None, :]))
+    X[np.isneginf(B)] = 0.0
+    return X
+
+
+def sinkhorn(B, p, eps, max_iters, ubar=None, vbar=None):
+    """Sinkhorn iteration on A^(p) (Section 3.1, eqs. dad1-dad3, log form of
+    Section 4.1.2). Rows first; stop when the column-stochastic iterate W_m
+    has max_i |r_i - 1| < eps, or after max_iters iterations.
+    Returns (ubar, vbar, iterations, residual)."""
+    n = B.shape[0]
+    ubar = np.zeros(n) if ubar is None else np.array(ubar, dtype=np.float64)
+    vbar = np.zeros(n) if vbar is None else np.array(vbar, dtype=np.float64)
+    it = ctypes.c_long(0)
+    res = ctypes.c_double(0.0)
+    bad = lib().or_sinkhorn(n, float(p), _d(B), _d(ubar), _d(vbar), float(eps), int(max_iters),
+                            ctypes.byref(it), ctypes.byref(res))
+    if bad:
+        raise NoSupport("a row or column has no finite entry")
+    return ubar, vbar, it.value, res.value
+
+
+def scale_ladder(B, ladder, eps, max_iters, vbar=None):
+    """Continuation in p over the ladder with (ubar, vbar) carried across
+    stages. Returns (ubar, vbar, iterations per stage, residual per stage)."""
+    n = B.shape[0]
+    lad = np.ascontiguousarray(ladder, dtype=np.float64)
+    ubar = np.zeros(n)
+    vbar = np.zeros(n) if vbar is None else np.array(vbar, dtype=np.float64)
+    iters = (ctypes.c_long * len(lad))()
+    res = np.empty(len(lad))
+    if lib().or_scale_ladder(n, _d(B), _d(lad), len(lad), float(eps), int(max_iters),
+                             _d(ubar), _d(vbar), iters, _d(res)):
+        raise NoSupport("a row or column has no finite entry")
+    return ubar, vbar, list(iters), list(res)
+
+
+def prune(B, p, ubar, vbar, t):
+    """Support of the reduced matrix (eq. matrixred): keep (i, j) iff x_ij(p) >= t."""
+    n = B.shape[0]
+    keep = np.empty((n, n), dtype=np.uint8)
+    lib().or_prune(n, float(p), _d(B), _d(np.ascontiguousarray(ubar, dtype=np.float64)),
+                   _d(np.ascontiguousarray(vbar, dtype=np.float64)), float(t),
+                   keep.ctypes.data_as(_u8p))
+    return keep.astype(bool)
+
+
+def certificate(B, p, ubar, vbar):
+    """Upper bound on log omega_opt(A) (Proposition prop:aoc)."""
+    n = B.shape[0]
+    return lib().or_certificate(n, float(p), _d(B),
+                                _d(np.ascontiguousarray(ubar, dtype=np.float64)),
+                                _d(np.ascontiguousarray(vbar, dtype=np.float64)))
+
+
+def prescale(A):
+    """Prescaling into [1, e] (Section 4.1.1)."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    out = np.empty_like(A)
+    lib().or_prescale(A.shape[0], _d(A), _d(out))
+    return out
+
+
+def hungarian(w, allowed=None):
+    """Exact maximum-weight perfect matching, dense O(n^3) (Section 1's
+    Kuhn/Edmonds class). w: int64 n x n; allowed: bool mask (default: all).
+    Returns (perm, weight) with perm[i] the column of row i."""
+    w = np.ascontiguousarray(w, dtype=np.int64)
+    n = w.shape[0]
+    if allowed is None:
+        allowed = np.ones((n, n), dtype=np.uint8)
+    allowed = np.ascontiguousarray(allowed, dtype=np.uint8)
+    perm = np.empty(n, dtype=np.int32)
+    weight = ctypes.c_int64(0)
+    if n == 0:
+        return perm, 0
+    st = lib().or_hungarian(n, w.ctypes.data_as(_i64p), allowed.ctypes.data_as(_u8p),
+                            perm.ctypes.data_as(_i32p), ctypes.byref(weight))
+    if st:
+        raise Infeasible("no perfect matching on the allowed entries")
+    return perm, weight.value
+
+
+def optimum_int(W, allowed=None):
+    """Optimal assignment of int16 log-weights W (sentinel entries excluded)."""
+    mask = W != SENTINEL
+    if allowed is not None:
+        mask = mask & allowed
+    return hungarian(W.astype(np.int64), mask)
+
+
+@dataclass
+class Solution:
+    """Result of the preprocessing pipeline for one instance."""
+    p: float
+    ubar: np.ndarray
+    vbar: np.ndarray
+    iters: list
+    residuals: list
+    keep: np.ndarray
+    nnz: int
+    ub: float
+    perm: np.ndarray | None
+    weight: int | None
+    log_gamma: float | None
+    extra: dict = field(default_factory=dict)
+
+
+def solve(W, ladder, eps, max_iters, t):
+    """The path for one int16 instance, step by step:
+    continuation over the p ladder (Section 3.1 + 4.1.2), reduced matrix
+    (eq. matrixred), exact solve of the reduced instance, certificate
+    (Proposition prop:aoc) and log gamma (eq. optratio)."""
+    B = log_weights(W)
+    ubar, vbar, iters, res = scale_ladder(B, ladder, eps, max_iters)
+    p = float(ladder[-1])
+    keep = prune(B, p, ubar, vbar, t)
+    ub = certificate(B, p, ubar, vbar)
+    try:
+        perm, weight = optimum_int(W, keep)
+        log_gamma = ub - weight
+    except Infeasible:
+        perm, weight, log_gamma = None, None, None
+    return Solution(p, ubar, vbar, iters, res, keep, int(keep.sum()), ub, perm, weight, log_gamma)
