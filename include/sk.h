@@ -1,0 +1,225 @@
+/*
+ * sk.h - C ABI of libsk: Sinkhorn diagonal scaling as a preprocessing step for
+ * the optimal assignment problem, on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Sharify, Gaubert, Grigori, "Solution of the optimal assignment
+ * problem by diagonal scaling algorithms" (arXiv:1104.3830).
+ *   - X(p) = D_r A^(p) D_c is the bistochastic matrix of maximal relative
+ *     entropy for the Hadamard power A^(p) = (a_ij^p) (eq. pentropyopt,
+ *     Theorem prop-borweinlewisnussbaum); as p grows it tends to the optimal
+ *     permutation(s) (Theorem thm:prop-converge1).
+ *   - It is computed by Sinkhorn iteration u = I(A^(p) v), v = I(A^(p)T u)
+ *     (eqs. dad1-dad3) in log coordinates (Section 4.1.2), with a
+ *     continuation in p, stopping when the column-stochastic iterate has
+ *     max_i |r_i - 1| < eps (Section 4.2).
+ *   - Entries with x_ij(p) < t are deleted (eq. matrixred); the reduced sparse
+ *     instance is solved exactly; the certificate of Proposition prop:aoc
+ *     bounds the loss (eq. optratio).
+ *
+ * Conventions (all entry points):
+ *   - The input is the log-weight matrix W = log A as int16, row-major, pitch
+ *     n. Valid weights lie in [-16384, 16383]; SK_SENTINEL (INT16_MIN) stands
+ *     for a_ij = 0. Weights and the deformation parameter p are integers, so
+ *     p*w_ij is exact.
+ *   - Every buffer is owned by the caller. "device" pointers are HIP device
+ *     memory on the context's device; "host" pointers are ordinary host memory.
+ *   - Entry points return a status code; no exception crosses the ABI. The
+ *     text of the last error of a context is available from sk_last_error.
+ *   - A context is used by one host thread at a time, except sk_submit /
+ *     sk_poll, which may be called from any thread.
+ */
+#ifndef SK_H
+#define SK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SK_SENTINEL (-32768)
+#define SK_MAX_LADDER 32
+
+typedef struct sk_ctx sk_ctx;
+
+typedef enum {
+    SK_OK = 0,
+    SK_EINVAL = 1,       /* bad argument (size, pointer, parameter) */
+    SK_ENOMEM = 2,       /* arena or output capacity too small */
+    SK_ENOCONV = 3,      /* a stage hit its iteration cap; results are still usable */
+    SK_EINFEASIBLE = 4,  /* the (reduced) matrix has no perfect matching */
+    SK_EAGAIN = 5,       /* served request not finished yet / queue full */
+    SK_EDEVICE = 6,      /* HIP runtime error */
+    SK_ENOSUPPORT = 7    /* a row or column of A has no positive entry */
+} sk_status;
+
+/* How the sweeps read the matrix. */
+typedef enum {
+    SK_W_I16 = 0,   /* recompute exp(p w_ij + f_i + g_j) from int16 W in every sweep */
+    SK_K_BF16 = 1,  /* sweep a stored K_ij = exp(p w_ij + f_i + g_j), bfloat16 */
+    SK_K_F32 = 2    /* sweep a stored K, float32 */
+} sk_storage;
+
+/* Parameters of a scaling run (Algorithm alg:alg1 with a fixed p ladder).
+ *   p_ladder/n_p : integer deformation parameters, applied in order; the
+ *                  scalings are carried from one p to the next with
+ *                  p^-1 log u and p^-1 log v held fixed (warm start).
+ *   tol          : a stage stops at the first iterate with max_i |r_i - 1| < tol
+ *                  (0 = run exactly max_iters_per_stage iterations).
+ *   max_iters_per_stage : iteration cap per stage (>= 1).
+ *   check_every  : the host reads the device's convergence flag every
+ *                  check_every iterations; the device itself stops at the
+ *                  exact iteration, so this only bounds wasted launches.
+ *   threshold    : t of eq. matrixred, used by sk_prune (0 < t <= 1).
+ *   storage      : see sk_storage.
+ *   opt_ratio    : required gamma of eq. optratio (> 1), used by sk_submit.
+ *   warm_start   : 0 = cold start (v = 1 for the first p); 1 = start from the
+ *                  potentials passed in (their p is p_ladder[0]). */
+typedef struct {
+    int32_t p_ladder[SK_MAX_LADDER];
+    int32_t n_p;
+    double tol;
+    int64_t max_iters_per_stage;
+    int32_t check_every;
+    double threshold;
+    int32_t storage;
+    double opt_ratio;
+    int32_t warm_start;
+} sk_params;
+
+/* Per-run report. Residuals are max_i |r_i - 1| (rows) and max_j |c_j - 1|
+ * (columns) of the returned iterate. "Balanced matrix" is the matrix the
+ * sweeps actually scale: exp(p w + log u + log v) for SK_W_I16, the stored K
+ * times its scalings for SK_K_BF16 / SK_K_F32. */
+typedef struct {
+    double residual_fp32;      /* as measured by the sweeps (FP32) */
+    double residual_fp64;      /* FP64 recheck of the balanced matrix, rows */
+    double col_residual_fp64;  /* FP64 recheck of the balanced matrix, columns */
+    double residual_exact_fp64;     /* FP64 rows of exp(p w + log u + log v) from W */
+    double col_residual_exact_fp64; /* same, columns */
+    double ub;                 /* right-hand side of Proposition prop:aoc */
+    int64_t iters_total;
+    int64_t iters_stage[SK_MAX_LADDER];
+    int32_t p_final;
+    int32_t stages_capped;     /* stages that hit max_iters_per_stage */
+    int64_t nnz_kept;          /* set by sk_prune */
+    int32_t absorbs;           /* K recomputations (stored-K storages) */
+    double seconds;
+} sk_report;
+
+/* Potentials (scalings) of one instance, in device memory, 16*n bytes laid
+ * out as four arrays of n: F int32, phi float32, G int32, gam float32, with
+ * log u_i = F_i + phi_i and log v_j = G_j + gam_j (natural logarithms), so
+ * x_ij = exp(p w_ij + log u_i + log v_j). */
+size_t sk_potentials_bytes(int32_t n);
+
+/* Reduced instance in CSR form: row_ptr int64[n+1], col int32[nnz],
+ * w int16[nnz] (the original log-weights of the kept entries); columns in
+ * increasing order within a row. `nnz` is the capacity on input to sk_prune
+ * and the count on output. */
+typedef struct {
+    int32_t n;
+    int64_t nnz;
+    int64_t *row_ptr;
+    int32_t *col;
+    int16_t *w;
+} sk_csr;
+
+/* Device memory a context needs to scale one instance of size n with the
+ * given storage (the arena passed to sk_create must be at least this). */
+size_t sk_arena_bytes(int32_t n, int32_t storage);
+
+/* Creates a context on `device`, launching on `hip_stream` (a hipStream_t;
+ * NULL = the null stream), sub-allocating its working memory from the
+ * caller's device arena [arena_dev_ptr, arena_dev_ptr + arena_bytes).
+ * The arena must stay valid until sk_destroy. */
+sk_status sk_create(sk_ctx **out, int device, void *hip_stream, void *arena_dev_ptr,
+                    size_t arena_bytes);
+
+/* Waits for all work of the context, stops its serving thread, frees its host
+ * resources. */
+sk_status sk_destroy(sk_ctx *ctx);
+
+/* Text of the last error recorded on ctx ("" if none). Valid until the next
+ * call on ctx. */
+const char *sk_last_error(const sk_ctx *ctx);
+
+/* Scales A^(p) for each p of the ladder (Section 3.1 with the logarithmic
+ * form of Section 4.1.2), then rechecks the result in FP64 and computes the
+ * certificate of Proposition prop:aoc.
+ *   W          : device, n*n int16 (read only).
+ *   potentials : device, sk_potentials_bytes(n); output, and input when
+ *                params->warm_start = 1.
+ *   report     : host, may be NULL.
+ * Blocks until done. Returns SK_ENOCONV when a stage hit its cap (the
+ * potentials and report are still valid), SK_ENOSUPPORT when a row or column
+ * of A is empty. */
+sk_status sk_scale(sk_ctx *ctx, const int16_t *W, int32_t n, const sk_params *params,
+                   void *potentials, sk_report *report);
+
+/* Builds the reduced matrix of eq. matrixred: B keeps (i, j) iff
+ * x_ij(p) >= params->threshold, with x from the potentials and
+ * p = the last p of the ladder.
+ *   csr : row_ptr, col, w are DEVICE buffers with room for n+1, csr->nnz,
+ *         csr->nnz entries; on return csr->nnz is the number kept.
+ * Returns SK_ENOMEM (and the needed count in csr->nnz) if the capacity is
+ * too small; row_ptr is valid in that case. */
+sk_status sk_prune(sk_ctx *ctx, const int16_t *W, int32_t n, const void *potentials,
+                   const sk_params *params, sk_csr *csr);
+
+/* Exact maximum-weight perfect matching of a reduced instance (the
+ * sequential exact step of Section 4.2), by shortest augmenting paths with
+ * potentials on the sparse graph (the O(n (m + n log n)) class of Section 1).
+ *   csr  : HOST buffers.
+ *   perm : host int32[n]; perm[i] = column assigned to row i.
+ *   weight : host; sum_i w[i, perm(i)].
+ * Returns SK_EINFEASIBLE if B has no perfect matching. Thread-safe. */
+sk_status sk_solve_reduced(const sk_csr *csr, int32_t *perm, int64_t *weight);
+
+/* Served path (continuous batching). sk_submit copies W (HOST, n*n int16)
+ * into library-owned staging and queues the request; the context's serving
+ * thread admits queued requests when their device footprint fits in the
+ * arena, sweeps all admitted instances together, and on convergence prunes,
+ * solves the reduced instance and checks the certificate. *ticket receives
+ * an id for sk_poll. Returns SK_EAGAIN if the queue is full. */
+sk_status sk_submit(sk_ctx *ctx, const int16_t *W_host, int32_t n, const sk_params *params,
+                    uint64_t *ticket);
+
+/* Non-blocking. Returns SK_EAGAIN while the request runs; otherwise its final
+ * status, with perm (host int32[n]), weight and report (may be NULL) filled,
+ * and releases the ticket. */
+sk_status sk_poll(sk_ctx *ctx, uint64_t ticket, int32_t *perm, int64_t *weight,
+                  sk_report *report);
+
+/* Batched scaling of independent instances in one set of launches per sweep
+ * (each sweep covers every instance). W[k] device pointers, n[k] sizes,
+ * potentials[k] device buffers (sk_potentials_bytes(n[k])), reports[k] host
+ * (array may be NULL). All instances share params. Per-instance stopping is
+ * exact: an instance that converged is skipped by later sweeps. Blocks. */
+sk_status sk_scale_batch(sk_ctx *ctx, int32_t count, const int16_t *const *W,
+                         const int32_t *n, const sk_params *params, void *const *potentials,
+                         sk_report *reports);
+
+/* Device arena bytes sk_scale_batch needs for these sizes. */
+size_t sk_batch_arena_bytes(int32_t count, const int32_t *n, int32_t storage);
+
+/* Kernel timing (measurement aid, off by default). While enabled, every
+ * kernel the context launches is bracketed by HIP events on the context's
+ * stream; durations accumulate per kernel name until the next enable.
+ * sk_profile_read fills up to `max` entries (host array) and returns how many
+ * kernels were seen. */
+typedef struct {
+    char name[32];
+    int64_t launches;
+    double total_ms;
+} sk_kernel_stat;
+
+sk_status sk_profile_enable(sk_ctx *ctx, int enable);
+int32_t sk_profile_read(sk_ctx *ctx, sk_kernel_stat *out, int32_t max);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SK_H */

@@ -46,9 +46,9 @@ def lib():
         if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SRC):
             _build.build()
         L = ctypes.CDLL(path)
-        L.or_row_step.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _dp, _dp]
+        L.or_row_step.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, _dp, _dp]
         L.or_row_step.restype = ctypes.c_int
-        L.or_col_step.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _dp, _dp]
+        L.or_col_step.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, _dp, _dp]
         L.or_col_step.restype = ctypes.c_int
         L.or_sums.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _dp, _dp, _dp, _dp]
         L.or_sums.restype = None
@@ -101,21 +101,25 @@ def log_of(A: np.ndarray) -> np.ndarray:
 
 
 def row_step(B, p, vbar):
-    """u = I(A^(p) v) in log coordinates (eq. dad2, Section 4.1.2)."""
-    n = B.shape[0]
+    """u = I(A^(p) v) in log coordinates (eq. dad2, Section 4.1.2). B may be a
+    block of rows (rows x n); returns ubar for those rows."""
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    rows, cols = B.shape
     vbar = np.ascontiguousarray(vbar, dtype=np.float64)
-    ubar = np.empty(n)
-    if lib().or_row_step(n, float(p), _d(B), _d(vbar), _d(ubar)):
+    ubar = np.empty(rows)
+    if lib().or_row_step(rows, cols, float(p), _d(B), _d(vbar), _d(ubar)):
         raise NoSupport("a row has no finite entry")
     return ubar
 
 
 def col_step(B, p, ubar):
-    """v = I(A^(p)T u) in log coordinates (eq. dad3, Section 4.1.2)."""
-    n = B.shape[0]
+    """v = I(A^(p)T u) in log coordinates (eq. dad3, Section 4.1.2). B may be a
+    block of columns (n x cols); returns vbar for those columns."""
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    rows, cols = B.shape
     ubar = np.ascontiguousarray(ubar, dtype=np.float64)
-    vbar = np.empty(n)
-    if lib().or_col_step(n, float(p), _d(B), _d(ubar), _d(vbar)):
+    vbar = np.empty(cols)
+    if lib().or_col_step(rows, cols, float(p), _d(B), _d(ubar), _d(vbar)):
         raise NoSupport("a column has no finite entry")
     return vbar
 

@@ -23,21 +23,23 @@
 #include <string.h>
 
 #define B_(i, j) B[(size_t)(i) * (size_t)n + (size_t)(j)]
+#define R_(i, j) B[(size_t)(i) * (size_t)cols + (size_t)(j)]
 
 /* Row step of the logarithmic p-Sinkhorn iteration (Section 4.1.2):
  *   ubar_i = -max_j(b_ij + vbar_j) - p^-1 log sum_j exp(p xhat_ij),
  *   xhat_ij = b_ij + vbar_j - max_j(b_ij + vbar_j).
  * This is u = I(A^(p) v) of the u/v form of Sinkhorn (eq. dad2) in log
- * coordinates. Returns the number of rows with no finite entry (then
- * ubar_i = +inf). */
-int or_row_step(int n, double p, const double *B, const double *vbar, double *ubar)
+ * coordinates, for a block of `rows` rows of a matrix with `cols` columns
+ * (each row is independent). Returns the number of rows with no finite entry
+ * (then ubar_i = +inf). */
+int or_row_step(int rows, int cols, double p, const double *B, const double *vbar, double *ubar)
 {
     int bad = 0;
-#pragma omp parallel for reduction(+ : bad) schedule(static) if (n >= 128)
-    for (int i = 0; i < n; ++i) {
+#pragma omp parallel for reduction(+ : bad) schedule(static) if (rows >= 128)
+    for (int i = 0; i < rows; ++i) {
         double mx = -INFINITY;
-        for (int j = 0; j < n; ++j) {
-            double y = B_(i, j) + vbar[j];
+        for (int j = 0; j < cols; ++j) {
+            double y = R_(i, j) + vbar[j];
             if (y > mx) mx = y;
         }
         if (mx == -INFINITY) {
@@ -46,8 +48,8 @@ int or_row_step(int n, double p, const double *B, const double *vbar, double *ub
             continue;
         }
         double s = 0.0;
-        for (int j = 0; j < n; ++j) {
-            double y = B_(i, j) + vbar[j];
+        for (int j = 0; j < cols; ++j) {
+            double y = R_(i, j) + vbar[j];
             if (y != -INFINITY) s += exp(p * (y - mx));
         }
         ubar[i] = -mx - log(s) / p;
@@ -55,16 +57,17 @@ int or_row_step(int n, double p, const double *B, const double *vbar, double *ub
     return bad;
 }
 
-/* Column step (Section 4.1.2; v = I(A^(p)T u), eq. dad3):
+/* Column step (Section 4.1.2; v = I(A^(p)T u), eq. dad3), for a block of
+ * `cols` columns over `rows` rows (each column is independent):
  *   vbar_j = -max_i(b_ij + ubar_i) - p^-1 log sum_i exp(p yhat_ij). */
-int or_col_step(int n, double p, const double *B, const double *ubar, double *vbar)
+int or_col_step(int rows, int cols, double p, const double *B, const double *ubar, double *vbar)
 {
     int bad = 0;
-#pragma omp parallel for reduction(+ : bad) schedule(static) if (n >= 128)
-    for (int j = 0; j < n; ++j) {
+#pragma omp parallel for reduction(+ : bad) schedule(static) if (cols >= 128)
+    for (int j = 0; j < cols; ++j) {
         double mx = -INFINITY;
-        for (int i = 0; i < n; ++i) {
-            double y = B_(i, j) + ubar[i];
+        for (int i = 0; i < rows; ++i) {
+            double y = R_(i, j) + ubar[i];
             if (y > mx) mx = y;
         }
         if (mx == -INFINITY) {
@@ -73,8 +76,8 @@ int or_col_step(int n, double p, const double *B, const double *ubar, double *vb
             continue;
         }
         double s = 0.0;
-        for (int i = 0; i < n; ++i) {
-            double y = B_(i, j) + ubar[i];
+        for (int i = 0; i < rows; ++i) {
+            double y = R_(i, j) + ubar[i];
             if (y != -INFINITY) s += exp(p * (y - mx));
         }
         vbar[j] = -mx - log(s) / p;
@@ -137,9 +140,9 @@ int or_sinkhorn(int n, double p, const double *B, double *ubar, double *vbar, do
     double res = INFINITY;
     int bad = 0;
     while (m < max_iters) {
-        bad = or_row_step(n, p, B, vbar, ubar);
+        bad = or_row_step(n, n, p, B, vbar, ubar);
         if (bad) break;
-        bad = or_col_step(n, p, B, ubar, vbar);
+        bad = or_col_step(n, n, p, B, ubar, vbar);
         if (bad) break;
         m += 1;
         res = or_row_residual(n, p, B, ubar, vbar);

@@ -1,0 +1,104 @@
+// Internal data structures shared by the HIP kernels and the host runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/sk.h"
+
+namespace sk {
+
+constexpr int kWave = 64;
+constexpr int kRowWaves = 16;    // waves per workgroup in the row sweep (one row per wave)
+constexpr int kColWaves = 4;     // waves per workgroup in the column sweep
+constexpr int kColTile8 = 512;   // columns per column tile, 8-wide vector loads
+constexpr int kColTile1 = 64;    // columns per column tile, scalar loads
+constexpr int kMaxN = 16384;     // row sweep stages all column potentials in LDS
+constexpr int kMaxSegRows = 1024;
+
+enum : int32_t { ST_RUNNING = 0, ST_DONE = 1, ST_ERROR = 2, ST_STAGE_END = 3 };
+enum : uint32_t { ERR_EMPTY_ROW = 1u, ERR_EMPTY_COL = 2u, ERR_RANGE = 4u };
+
+// Per-instance control block, device memory. Written by the kernels only at
+// the places documented on each field; read by the host between launches.
+struct Ctl {
+    uint32_t res_bits;      // max_i |r_i - 1| of the current iterate (float bits); row sweep atomicMax
+    uint32_t rescue_cnt;    // columns whose sum left the safe range in the last column sweep
+    uint32_t err;           // ERR_* flags
+    uint32_t sent;          // 1: W holds the sentinel (set by the input scan)
+    int32_t state;          // ST_*
+    int32_t stage;          // index into the p ladder
+    int32_t p;              // current p
+    int32_t iter;           // completed iterations in this stage; parity selects the F/phi buffer
+    int32_t capped;         // stages that hit the cap
+    int64_t iters_total;
+    float last_res;         // residual of the last measured iterate
+    uint32_t need_absorb;   // stored K: K must be recomputed before the next K sweep
+    uint32_t drift_bits;    // stored K: max |log2 a_i|, |log2 b_j| since the last absorb (float bits)
+    int64_t stage_iters[SK_MAX_LADDER];
+};
+
+// Per-instance descriptor (device memory, constant during a launch).
+struct Inst {
+    const int16_t *W;       // n x n log-weights, row pitch `pitch` elements
+    int64_t pitch;
+    int32_t n;
+    int32_t vec8;           // 1: n % 8 == 0 and rows 16-byte aligned -> 8-wide loads
+    int32_t nseg;           // row segments of the column sweep
+    int32_t seg_rows;
+    int32_t ntiles;         // column tiles of the column sweep
+    int32_t tile_cols;
+    int32_t n_p;
+    int32_t ladder[SK_MAX_LADDER];
+    float tol;
+    int32_t pad1;
+    int64_t max_iters;
+    int32_t *F[2];          // row potential, integer part (ping-pong by iteration parity)
+    float *phi[2];          // row potential, fraction
+    int32_t *G;             // column potential, integer part
+    float *gam;             // column potential, fraction
+    float *colpart;         // [nseg][n] partial column sums
+    uint32_t *tilecnt;      // [ntiles] arrivals per tile in the current column sweep
+    uint32_t *rescue;       // [n] list of flagged columns
+    Ctl *ctl;
+    // stored-K storages
+    void *K;                // n x kpitch bf16 or f32 (kpitch = n rounded up to 8; pad = 0)
+    float *a[2];            // row scalings of K (ping-pong by iteration parity)
+    float *b;               // column scalings of K
+    int32_t storage;
+    int32_t kpitch;
+};
+
+struct RowUnit { int32_t inst, row0; };
+struct ColUnit { int32_t inst, tile, seg, pad; };
+
+// Kernel launchers (sk_kernels.hip). All enqueue on `st`.
+hipError_t launch_init(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid, int cold,
+                       hipStream_t st);
+hipError_t launch_row_sweep(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
+                            size_t lds_bytes, hipStream_t st);
+hipError_t launch_col_sweep(const Inst *d_insts, const ColUnit *d_units, int nunits, int grid,
+                            hipStream_t st);
+hipError_t launch_iter_end(const Inst *d_insts, int count, hipStream_t st);
+hipError_t launch_check_rows(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
+                             double *rsum, double *rmax, hipStream_t st);
+hipError_t launch_check_cols(const Inst *d_insts, int inst, int n, double *csum, hipStream_t st);
+hipError_t launch_prune_count(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
+                              double logt, int64_t *counts, hipStream_t st);
+hipError_t launch_scan(const int64_t *counts, int64_t *row_ptr, int n, hipStream_t st);
+hipError_t launch_prune_fill(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
+                             double logt, const int64_t *row_ptr, int32_t *col, int16_t *w,
+                             hipStream_t st);
+hipError_t launch_absorb(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
+                         size_t lds_bytes, int storage, hipStream_t st);
+hipError_t launch_row_sweep_k(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
+                              size_t lds_bytes, int storage, hipStream_t st);
+hipError_t launch_col_sweep_k(const Inst *d_insts, const ColUnit *d_units, int nunits, int grid,
+                              int storage, hipStream_t st);
+hipError_t launch_fold_k(const Inst *d_insts, int count, hipStream_t st);
+hipError_t launch_advance(const Inst *d_insts, int count, hipStream_t st);
+hipError_t launch_check_k(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid, int inst,
+                          int n, int storage, double *rsum, double *csum, hipStream_t st);
+hipError_t set_kernel_attributes();
+
+}  // namespace sk

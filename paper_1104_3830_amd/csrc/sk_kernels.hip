@@ -1,0 +1,771 @@
+// HIP kernels for gfx950 (MI355X): log-domain Sinkhorn sweeps over int16
+// log-weights, the FP64 recheck, pruning to CSR, and the stored-K sweeps.
+//
+// Numerical scheme. With log u_i = F_i + phi_i and log v_j = G_j + gam_j
+// (F, G int32; phi, gam float32 with |.| <= 1/2) and integer p and w_ij,
+// the exponent p*w_ij + F_i + G_j is an integer below 2^24 in magnitude, so it
+// is formed exactly in float32 arithmetic; only the small fractions are
+// rounded. This is the max-shifted logarithmic iteration of Section 4.1.2
+// with the shift taken from the previous iterate (and an exact two-pass
+// max-shift whenever a sum leaves [2^-64, 2^64]).
+//
+// Row step (u = I(A^(p) v), eq. dad2):   S_i = sum_j exp(p w_ij + F_i + G_j + gam_j),
+//                                        log u_i <- F_i - log S_i.
+// Column step (v = I(A^(p)T u), eq. dad3): T_j = sum_i exp(p w_ij + F_i + phi_i + G_j),
+//                                        log v_j <- G_j - log T_j.
+// Row sums of the column-stochastic iterate (Section 4.2 stopping test):
+//                                        r_i = exp(phi_i) S_i.
+#include "sk_internal.h"
+
+namespace sk {
+
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kLn2 = 0.6931471805599453f;
+constexpr float kSafeLo = 5.421010862427522e-20f;  // 2^-64
+constexpr float kSafeHi = 1.8446744073709552e19f;  // 2^64
+
+__device__ __forceinline__ float ex2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float lg2(float x) { return __builtin_amdgcn_logf(x); }
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+__device__ __forceinline__ double wave_max_d(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+// Unpacks 8 int16 from a 16-byte vector (v_cvt_f32_i32 with word select).
+__device__ __forceinline__ void unpack8(const int4 v, float (&w)[8]) {
+    w[0] = (float)(short)(v.x & 0xffff); w[1] = (float)(v.x >> 16);
+    w[2] = (float)(short)(v.y & 0xffff); w[3] = (float)(v.y >> 16);
+    w[4] = (float)(short)(v.z & 0xffff); w[5] = (float)(v.z >> 16);
+    w[6] = (float)(short)(v.w & 0xffff); w[7] = (float)(v.w >> 16);
+}
+
+constexpr float kSentF = -32768.0f;
+
+// Contiguous range of work units owned by this workgroup.
+__device__ __forceinline__ void unit_range(int nunits, int &u0, int &u1) {
+    int per = (nunits + (int)gridDim.x - 1) / (int)gridDim.x;
+    u0 = (int)blockIdx.x * per;
+    u1 = min(nunits, u0 + per);
+}
+
+// LDS position of column j for 8-wide lanes: lane l owns columns
+// l*8 + k*512 + c; storing column j at (j%8)*(n/8) + j/8 makes the 64 lanes
+// read 64 consecutive entries for each c (no bank conflicts).
+__device__ __forceinline__ int swz8(int j, int n8) { return (j & 7) * n8 + (j >> 3); }
+
+// ---------------------------------------------------------------- input scan / cold start
+// Marks instances whose W holds the sentinel and rows with no entry. With
+// cold != 0 it also sets the first-stage start (v_0 = 1, eq. dad1) with the
+// row shift of Section 4.1.2: F_i = -p*max_j w_ij, phi = 0, G = gam = 0.
+__global__ __launch_bounds__(kRowWaves * kWave) void k_init(const Inst *__restrict__ insts,
+                                                              const RowUnit *__restrict__ units,
+                                                              int nunits, int cold) {
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    int u0, u1;
+    unit_range(nunits, u0, u1);
+    for (int u = u0; u < u1; ++u) {
+        const RowUnit un = units[u];
+        const Inst &I = insts[un.inst];
+        const int n = I.n, row = un.row0 + wave;
+        if (cold && un.row0 == 0) {
+            for (int j = threadIdx.x; j < n; j += blockDim.x) {
+                I.G[j] = 0;
+                I.gam[j] = 0.f;
+            }
+        }
+        if (row >= n) continue;
+        const int16_t *wr = I.W + (int64_t)row * I.pitch;
+        int mx = -32768;
+        int sent = 0;
+        for (int j = lane; j < n; j += kWave) {
+            const int w = wr[j];
+            sent |= (w == SK_SENTINEL);
+            mx = max(mx, w);
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            mx = max(mx, __shfl_xor(mx, o, kWave));
+            sent |= __shfl_xor(sent, o, kWave);
+        }
+        if (lane == 0) {
+            if (mx == SK_SENTINEL) atomicOr(&I.ctl->err, ERR_EMPTY_ROW);
+            if (sent) atomicOr(&I.ctl->sent, 1u);
+            if (cold) {
+                I.F[0][row] = (mx == SK_SENTINEL) ? 0 : -I.ladder[0] * mx;
+                I.phi[0][row] = 0.f;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- row sweep
+// One wavefront per row; column potentials (G_j as float, gam_j*log2 e)
+// staged once per workgroup in LDS; W read with coalesced 16-byte loads.
+template <bool SENT>
+__device__ __forceinline__ float row_partial_v8(const int16_t *__restrict__ wr, int n, float pf,
+                                                float Ff, const float2 *__restrict__ pot, int lane,
+                                                float shift) {
+    const int n8 = n >> 3;
+    float acc = 0.f;
+    for (int j0 = lane * 8; j0 < n; j0 += 512) {
+        const int4 v = *reinterpret_cast<const int4 *>(wr + j0);
+        float w[8];
+        unpack8(v, w);
+        const int q = j0 >> 3;
+        float s = 0.f;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const float2 gp = pot[c * n8 + q];
+            const float I = fmaf(w[c], pf, gp.x) + Ff;        // exact integer
+            float e = ex2(fmaf(I, kLog2e, gp.y) - shift);
+            if (SENT) e = (w[c] == kSentF) ? 0.f : e;
+            s += e;
+        }
+        acc += s;
+    }
+    return acc;
+}
+
+template <bool SENT>
+__device__ __forceinline__ float row_max_v8(const int16_t *__restrict__ wr, int n, float pf,
+                                            float Ff, const float2 *__restrict__ pot, int lane) {
+    const int n8 = n >> 3;
+    float m = -INFINITY;
+    for (int j0 = lane * 8; j0 < n; j0 += 512) {
+        const int4 v = *reinterpret_cast<const int4 *>(wr + j0);
+        float w[8];
+        unpack8(v, w);
+        const int q = j0 >> 3;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const float2 gp = pot[c * n8 + q];
+            const float I = fmaf(w[c], pf, gp.x) + Ff;
+            float y = fmaf(I, kLog2e, gp.y);
+            if (SENT) y = (w[c] == kSentF) ? -INFINITY : y;
+            m = fmaxf(m, y);
+        }
+    }
+    return m;
+}
+
+template <bool SENT>
+__device__ __forceinline__ float row_partial_v1(const int16_t *__restrict__ wr, int n, float pf,
+                                                float Ff, const float2 *__restrict__ pot, int lane,
+                                                float shift) {
+    float acc = 0.f;
+    for (int j = lane; j < n; j += kWave) {
+        const float w = (float)wr[j];
+        const float2 gp = pot[j];
+        const float I = fmaf(w, pf, gp.x) + Ff;
+        float e = ex2(fmaf(I, kLog2e, gp.y) - shift);
+        if (SENT) e = (w == kSentF) ? 0.f : e;
+        acc += e;
+    }
+    return acc;
+}
+
+template <bool SENT>
+__device__ __forceinline__ float row_max_v1(const int16_t *__restrict__ wr, int n, float pf,
+                                            float Ff, const float2 *__restrict__ pot, int lane) {
+    float m = -INFINITY;
+    for (int j = lane; j < n; j += kWave) {
+        const float w = (float)wr[j];
+        const float2 gp = pot[j];
+        const float I = fmaf(w, pf, gp.x) + Ff;
+        float y = fmaf(I, kLog2e, gp.y);
+        if (SENT) y = (w == kSentF) ? -INFINITY : y;
+        m = fmaxf(m, y);
+    }
+    return m;
+}
+
+template <bool SENT, bool V8>
+__device__ __forceinline__ void row_step_one(const Inst &I, int row, int par, int lane,
+                                             const float2 *__restrict__ pot, float &resmax) {
+    const int n = I.n;
+    const int16_t *wr = I.W + (int64_t)row * I.pitch;
+    const int Fi = I.F[par][row];
+    const float phi = I.phi[par][row];
+    const float pf = (float)I.ctl->p;
+    const float Ff = (float)Fi;
+    float S = V8 ? row_partial_v8<SENT>(wr, n, pf, Ff, pot, lane, 0.f)
+                 : row_partial_v1<SENT>(wr, n, pf, Ff, pot, lane, 0.f);
+    S = wave_sum(S);
+    float l2S;  // log2 S_i
+    if (S >= kSafeLo && S <= kSafeHi) {
+        l2S = lg2(S);
+    } else {
+        // exact max-shift (Section 4.1.2): m = max_j of the exponent, then the sum
+        float m = V8 ? row_max_v8<SENT>(wr, n, pf, Ff, pot, lane)
+                     : row_max_v1<SENT>(wr, n, pf, Ff, pot, lane);
+        m = wave_max(m);
+        if (m == -INFINITY) {
+            if (lane == 0) atomicOr(&I.ctl->err, ERR_EMPTY_ROW);
+            l2S = 0.f;
+        } else {
+            float S2 = V8 ? row_partial_v8<SENT>(wr, n, pf, Ff, pot, lane, m)
+                          : row_partial_v1<SENT>(wr, n, pf, Ff, pot, lane, m);
+            S2 = wave_sum(S2);
+            l2S = m + lg2(S2);
+        }
+    }
+    if (lane == 0) {
+        float phin = -l2S * kLn2;
+        const float k = rintf(phin);
+        I.F[par ^ 1][row] = Fi + (int)k;
+        I.phi[par ^ 1][row] = phin - k;
+        // r_i = exp(phi_i) * S_i: row sum of the current iterate
+        const float r = ex2(fmaf(phi, kLog2e, l2S));
+        resmax = fmaxf(resmax, fabsf(r - 1.f));
+    }
+}
+
+__global__ __launch_bounds__(kRowWaves * kWave) void k_row_sweep(const Inst *__restrict__ insts,
+                                                                   const RowUnit *__restrict__ units,
+                                                                   int nunits) {
+    extern __shared__ float2 lds_pot[];
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    int u0, u1;
+    unit_range(nunits, u0, u1);
+    int cur = -1;
+    float resmax = 0.f;
+    for (int u = u0; u < u1; ++u) {
+        const RowUnit un = units[u];
+        const Inst &I = insts[un.inst];
+        Ctl *ctl = I.ctl;
+        if (ctl->state != ST_RUNNING) continue;
+        const int n = I.n;
+        const int iter = ctl->iter;
+        if (un.inst != cur) {
+            if (cur >= 0 && lane == 0 && resmax > 0.f && insts[cur].ctl->iter >= 1)
+                atomicMax(&insts[cur].ctl->res_bits, __float_as_uint(resmax));
+            resmax = 0.f;
+            __syncthreads();
+            const int n8 = n >> 3;
+            for (int j = threadIdx.x; j < n; j += blockDim.x) {
+                const float2 gp = make_float2((float)I.G[j], I.gam[j] * kLog2e);
+                lds_pot[I.vec8 ? swz8(j, n8) : j] = gp;
+            }
+            __syncthreads();
+            cur = un.inst;
+        }
+        const int row = un.row0 + wave;
+        if (row < n) {
+            const int par = iter & 1;
+            const bool sent = ctl->sent != 0u;
+            if (I.vec8) {
+                if (sent) row_step_one<true, true>(I, row, par, lane, lds_pot, resmax);
+                else row_step_one<false, true>(I, row, par, lane, lds_pot, resmax);
+            } else {
+                if (sent) row_step_one<true, false>(I, row, par, lane, lds_pot, resmax);
+                else row_step_one<false, false>(I, row, par, lane, lds_pot, resmax);
+            }
+        }
+    }
+    if (cur >= 0 && lane == 0 && resmax > 0.f && insts[cur].ctl->iter >= 1)
+        atomicMax(&insts[cur].ctl->res_bits, __float_as_uint(resmax));
+}
+
+// ---------------------------------------------------------------- column sweep
+// Workgroup = column tile x row segment. Lanes own columns (8 per lane with
+// 16-byte loads, coalesced along the row); waves split the segment's rows;
+// row potentials of the segment are staged in LDS; the four waves' partial
+// sums are combined through LDS in a fixed order and written to a fixed slot
+// colpart[seg][j]. The last workgroup to finish a tile sums its nseg slots in
+// segment order (deterministic) and updates G_j, gam_j.
+
+__device__ __forceinline__ bool stage_converged(const Inst &I, const Ctl *ctl) {
+    const float res = __uint_as_float(ctl->res_bits);
+    return ctl->iter >= 1 && res < I.tol;
+}
+
+template <bool SENT, bool V8>
+__device__ __forceinline__ void col_partial(const Inst &I, int tile, int r0, int r1, int wave,
+                                            int lane, const float2 *__restrict__ rowpot,
+                                            float (&acc)[8]) {
+    const int n = I.n;
+    const float pf = (float)I.ctl->p;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc[c] = 0.f;
+    if (V8) {
+        const int c0 = tile * kColTile8 + lane * 8;
+        if (c0 >= n) return;
+        float Gf[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) Gf[c] = (float)I.G[c0 + c];
+        const int16_t *base = I.W + c0;
+        for (int r = r0 + wave; r < r1; r += kColWaves) {
+            const float2 rp = rowpot[r - r0];
+            const int4 v = *reinterpret_cast<const int4 *>(base + (int64_t)r * I.pitch);
+            float w[8];
+            unpack8(v, w);
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const float Iv = fmaf(w[c], pf, Gf[c]) + rp.x;
+                float e = ex2(fmaf(Iv, kLog2e, rp.y));
+                if (SENT) e = (w[c] == kSentF) ? 0.f : e;
+                acc[c] += e;
+            }
+        }
+    } else {
+        const int c0 = tile * kColTile1 + lane;
+        if (c0 >= n) return;
+        const float Gf = (float)I.G[c0];
+        for (int r = r0 + wave; r < r1; r += kColWaves) {
+            const float2 rp = rowpot[r - r0];
+            const float w = (float)I.W[(int64_t)r * I.pitch + c0];
+            const float Iv = fmaf(w, pf, Gf) + rp.x;
+            float e = ex2(fmaf(Iv, kLog2e, rp.y));
+            if (SENT) e = (w == kSentF) ? 0.f : e;
+            acc[0] += e;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kColWaves * kWave) void k_col_sweep(const Inst *__restrict__ insts,
+                                                                   const ColUnit *__restrict__ units,
+                                                                   int nunits) {
+    __shared__ float red[kColWaves][kColTile8];
+    __shared__ float2 rowpot[kMaxSegRows];
+    __shared__ int s_last;
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    int u0, u1;
+    unit_range(nunits, u0, u1);
+    for (int u = u0; u < u1; ++u) {
+        const ColUnit un = units[u];
+        const Inst &I = insts[un.inst];
+        Ctl *ctl = I.ctl;
+        if (ctl->state != ST_RUNNING) continue;
+        const bool conv = stage_converged(I, ctl);
+        const int n = I.n;
+        const int npar = (ctl->iter + 1) & 1;  // row potentials written by this iteration's row sweep
+        const int tc = I.tile_cols;
+        const int ctile0 = un.tile * tc;
+        const int ncols = min(tc, n - ctile0);
+        if (!conv) {
+            const int r0 = un.seg * I.seg_rows, r1 = min(n, r0 + I.seg_rows);
+            __syncthreads();
+            for (int r = r0 + (int)threadIdx.x; r < r1; r += blockDim.x)
+                rowpot[r - r0] = make_float2((float)I.F[npar][r], I.phi[npar][r] * kLog2e);
+            __syncthreads();
+            float acc[8];
+            const bool sent = ctl->sent != 0u;
+            if (I.vec8) {
+                if (sent) col_partial<true, true>(I, un.tile, r0, r1, wave, lane, rowpot, acc);
+                else col_partial<false, true>(I, un.tile, r0, r1, wave, lane, rowpot, acc);
+#pragma unroll
+                for (int c = 0; c < 8; ++c) red[wave][lane * 8 + c] = acc[c];
+            } else {
+                if (sent) col_partial<true, false>(I, un.tile, r0, r1, wave, lane, rowpot, acc);
+                else col_partial<false, false>(I, un.tile, r0, r1, wave, lane, rowpot, acc);
+                red[wave][lane] = acc[0];
+            }
+            __syncthreads();
+            float *dst = I.colpart + (int64_t)un.seg * n + ctile0;
+            for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
+                float s = red[0][c];
+#pragma unroll
+                for (int w2 = 1; w2 < kColWaves; ++w2) s += red[w2][c];
+                dst[c] = s;
+            }
+        }
+        // arrival; the last workgroup of this tile finalises it
+        __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const unsigned old = atomicAdd(&I.tilecnt[un.tile], 1u);
+            s_last = (old == (unsigned)(I.nseg - 1));
+        }
+        __syncthreads();
+        if (s_last) {
+            __threadfence();
+            if (!conv) {
+                for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
+                    const int j = ctile0 + c;
+                    float T = 0.f;
+                    for (int s = 0; s < I.nseg; ++s)
+                        T += __builtin_nontemporal_load(I.colpart + (int64_t)s * n + j);
+                    if (T >= kSafeLo && T <= kSafeHi) {
+                        const float gn = -lg2(T) * kLn2;
+                        const float k = rintf(gn);
+                        I.G[j] += (int)k;
+                        I.gam[j] = gn - k;
+                    } else {
+                        const unsigned slot = atomicAdd(&ctl->rescue_cnt, 1u);
+                        I.rescue[slot] = (uint32_t)j;
+                    }
+                }
+            }
+            if (threadIdx.x == 0) I.tilecnt[un.tile] = 0u;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- end of iteration
+// One workgroup per instance: exact recompute of flagged columns, commit of
+// the iteration, stopping test, and the continuation to the next p with
+// p^-1 log u and p^-1 log v held fixed (in FP64).
+__device__ void stage_advance(const Inst &I, Ctl *ctl, int par) {
+    const int n = I.n;
+    const int s = ctl->stage;
+    if (s + 1 < I.n_p) {
+        const int p0 = I.ladder[s], p1 = I.ladder[s + 1];
+        const double ratio = (double)p1 / (double)p0;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const double f = ((double)I.F[par][i] + (double)I.phi[par][i]) * ratio;
+            const double k = rint(f);
+            I.F[0][i] = (int32_t)k;
+            I.phi[0][i] = (float)(f - k);
+            const double g = ((double)I.G[i] + (double)I.gam[i]) * ratio;
+            const double kg = rint(g);
+            I.G[i] = (int32_t)kg;
+            I.gam[i] = (float)(g - kg);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            ctl->stage = s + 1;
+            ctl->p = p1;
+            ctl->iter = 0;
+        }
+    } else {
+        // final stage: keep the committed buffer where the parity says
+        if (threadIdx.x == 0) ctl->state = ST_DONE;
+    }
+}
+
+// End of a stage: the log-domain path continues on the device; a stored-K
+// path pauses (ST_STAGE_END) so the host can fold the scalings, move to the
+// next p and recompute K.
+__device__ void end_stage(const Inst &I, Ctl *ctl, int par) {
+    if (I.storage == SK_W_I16) {
+        stage_advance(I, ctl, par);
+    } else {
+        __syncthreads();
+        if (threadIdx.x == 0) ctl->state = ST_STAGE_END;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_iter_end(const Inst *__restrict__ insts) {
+    __shared__ float red[256];
+    __shared__ float s_m;
+    const Inst &I = insts[blockIdx.x];
+    Ctl *ctl = I.ctl;
+    if (ctl->state != ST_RUNNING) return;
+    const int n = I.n;
+    const bool conv = stage_converged(I, ctl);
+    const int iter = ctl->iter;
+    const int npar = (iter + 1) & 1;
+    const float pf = (float)ctl->p;
+    if (!conv) {
+        // exact two-pass recompute of columns whose sum left the safe range
+        const unsigned nres = ctl->rescue_cnt;
+        for (unsigned q = 0; q < nres; ++q) {
+            const int j = (int)I.rescue[q];
+            const float Gf = (float)I.G[j];
+            float m = -INFINITY;
+            for (int r = threadIdx.x; r < n; r += blockDim.x) {
+                const int16_t w = I.W[(int64_t)r * I.pitch + j];
+                if (w == SK_SENTINEL) continue;
+                const float Iv = fmaf((float)w, pf, Gf) + (float)I.F[npar][r];
+                m = fmaxf(m, fmaf(Iv, kLog2e, I.phi[npar][r] * kLog2e));
+            }
+            red[threadIdx.x] = m;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                float mm = -INFINITY;
+                for (int t = 0; t < (int)blockDim.x; ++t) mm = fmaxf(mm, red[t]);
+                s_m = mm;
+            }
+            __syncthreads();
+            m = s_m;
+            float sacc = 0.f;
+            if (m != -INFINITY) {
+                for (int r = threadIdx.x; r < n; r += blockDim.x) {
+                    const int16_t w = I.W[(int64_t)r * I.pitch + j];
+                    if (w == SK_SENTINEL) continue;
+                    const float Iv = fmaf((float)w, pf, Gf) + (float)I.F[npar][r];
+                    sacc += ex2(fmaf(Iv, kLog2e, I.phi[npar][r] * kLog2e) - m);
+                }
+            }
+            __syncthreads();
+            red[threadIdx.x] = sacc;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                if (m == -INFINITY) {
+                    atomicOr(&ctl->err, ERR_EMPTY_COL);
+                } else {
+                    float S = 0.f;
+                    for (int t = 0; t < (int)blockDim.x; ++t) S += red[t];
+                    // log v_j <- G_j - log T_j with log2 T_j = m + log2 S
+                    const double gn = (double)I.G[j] - (double)((m + lg2(S)) * kLn2);
+                    const double k = rint(gn);
+                    I.G[j] = (int32_t)k;
+                    I.gam[j] = (float)(gn - k);
+                }
+            }
+            __syncthreads();
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ctl->rescue_cnt = 0u;
+        if (ctl->err & (ERR_EMPTY_ROW | ERR_EMPTY_COL)) ctl->state = ST_ERROR;
+    }
+    __syncthreads();
+    if (ctl->state != ST_RUNNING) return;
+    if (conv) {
+        if (threadIdx.x == 0) {
+            ctl->last_res = __uint_as_float(ctl->res_bits);
+            ctl->res_bits = 0u;
+        }
+        end_stage(I, ctl, iter & 1);
+        return;
+    }
+    // commit: the new row potentials are in buffer npar, i.e. (iter+1) & 1
+    if (threadIdx.x == 0) {
+        if (iter >= 1) ctl->last_res = __uint_as_float(ctl->res_bits);
+        ctl->res_bits = 0u;
+        ctl->iter = iter + 1;
+        ctl->iters_total += 1;
+        ctl->stage_iters[ctl->stage] += 1;
+    }
+    __syncthreads();
+    if ((int64_t)(iter + 1) >= I.max_iters) {
+        if (threadIdx.x == 0) ctl->capped += 1;
+        end_stage(I, ctl, npar);
+    }
+}
+
+// ---------------------------------------------------------------- FP64 recheck
+// Row sums r_i and m_i = max_j (p w_ij + log v_j) in FP64 from the committed
+// potentials (Proposition prop:aoc needs sum_i m_i - sum_j log v_j).
+__global__ __launch_bounds__(kRowWaves * kWave) void k_check_rows(const Inst *__restrict__ insts,
+                                                                    const RowUnit *__restrict__ units,
+                                                                    int nunits, double *rsum,
+                                                                    double *rmax) {
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    int u0, u1;
+    unit_range(nunits, u0, u1);
+    for (int u = u0; u < u1; ++u) {
+        const RowUnit un = units[u];
+        const Inst &I = insts[un.inst];
+        const int n = I.n, row = un.row0 + wave;
+        if (row >= n) continue;
+        const int par = I.ctl->iter & 1;
+        const double p = (double)I.ctl->p;
+        const double f = (double)I.F[par][row] + (double)I.phi[par][row];
+        const int16_t *wr = I.W + (int64_t)row * I.pitch;
+        double s = 0.0, m = -INFINITY;
+        for (int j = lane; j < n; j += kWave) {
+            const int w = wr[j];
+            if (w == SK_SENTINEL) continue;
+            const double t = p * (double)w + ((double)I.G[j] + (double)I.gam[j]);
+            s += exp(t + f);
+            m = fmax(m, t);
+        }
+        s = wave_sum_d(s);
+        m = wave_max_d(m);
+        if (lane == 0) {
+            rsum[row] = s;
+            rmax[row] = m;
+        }
+    }
+}
+
+// Column sums in FP64: one thread per column walks the rows (coalesced along
+// each row).
+__global__ __launch_bounds__(256) void k_check_cols(const Inst *__restrict__ insts, int inst,
+                                                    double *csum) {
+    const Inst &I = insts[inst];
+    const int n = I.n;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int par = I.ctl->iter & 1;
+    const double p = (double)I.ctl->p;
+    const double g = (double)I.G[j] + (double)I.gam[j];
+    double s = 0.0;
+    for (int r = 0; r < n; ++r) {
+        const int w = I.W[(int64_t)r * I.pitch + j];
+        if (w == SK_SENTINEL) continue;
+        s += exp(p * (double)w + g + ((double)I.F[par][r] + (double)I.phi[par][r]));
+    }
+    csum[j] = s;
+}
+
+// ---------------------------------------------------------------- prune
+// B keeps (i, j) iff x_ij(p) >= t (eq. matrixred); the comparison is made on
+// log x_ij = p w_ij + log u_i + log v_j in FP64.
+__global__ __launch_bounds__(kRowWaves * kWave) void k_prune_count(const Inst *__restrict__ insts,
+                                                                     const RowUnit *__restrict__ units,
+                                                                     int nunits, double logt,
+                                                                     int64_t *counts) {
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    int u0, u1;
+    unit_range(nunits, u0, u1);
+    for (int u = u0; u < u1; ++u) {
+        const RowUnit un = units[u];
+        const Inst &I = insts[un.inst];
+        const int n = I.n, row = un.row0 + wave;
+        if (row >= n) continue;
+        const int par = I.ctl->iter & 1;
+        const double p = (double)I.ctl->p;
+        const double f = (double)I.F[par][row] + (double)I.phi[par][row];
+        const int16_t *wr = I.W + (int64_t)row * I.pitch;
+        int cnt = 0;
+        for (int j = lane; j < n; j += kWave) {
+            const int w = wr[j];
+            if (w == SK_SENTINEL) continue;
+            const double lx = p * (double)w + f + ((double)I.G[j] + (double)I.gam[j]);
+            cnt += (lx >= logt);
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, kWave);
+        if (lane == 0) counts[row] = cnt;
+    }
+}
+
+// Exclusive scan of n row counts into row_ptr[0..n] (one workgroup).
+__global__ __launch_bounds__(1024) void k_scan(const int64_t *__restrict__ counts,
+                                               int64_t *__restrict__ row_ptr, int n) {
+    __shared__ int64_t part[1024];
+    const int t = threadIdx.x;
+    const int per = (n + 1023) / 1024;
+    const int a = min(n, t * per), b = min(n, a + per);
+    int64_t s = 0;
+    for (int i = a; i < b; ++i) s += counts[i];
+    part[t] = s;
+    __syncthreads();
+    if (t == 0) {
+        int64_t run = 0;
+        for (int k = 0; k < 1024; ++k) {
+            const int64_t v = part[k];
+            part[k] = run;
+            run += v;
+        }
+        row_ptr[n] = run;
+    }
+    __syncthreads();
+    int64_t run = part[t];
+    for (int i = a; i < b; ++i) {
+        row_ptr[i] = run;
+        run += counts[i];
+    }
+}
+
+// Writes the kept columns of each row in increasing order: each wave walks
+// its row in 64-column chunks and places the kept ones with a ballot prefix.
+__global__ __launch_bounds__(kRowWaves * kWave) void k_prune_fill(const Inst *__restrict__ insts,
+                                                                    const RowUnit *__restrict__ units,
+                                                                    int nunits, double logt,
+                                                                    const int64_t *__restrict__ row_ptr,
+                                                                    int32_t *__restrict__ col,
+                                                                    int16_t *__restrict__ wout) {
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    int u0, u1;
+    unit_range(nunits, u0, u1);
+    for (int u = u0; u < u1; ++u) {
+        const RowUnit un = units[u];
+        const Inst &I = insts[un.inst];
+        const int n = I.n, row = un.row0 + wave;
+        if (row >= n) continue;
+        const int par = I.ctl->iter & 1;
+        const double p = (double)I.ctl->p;
+        const double f = (double)I.F[par][row] + (double)I.phi[par][row];
+        const int16_t *wr = I.W + (int64_t)row * I.pitch;
+        int64_t pos = row_ptr[row];
+        for (int j0 = 0; j0 < n; j0 += kWave) {
+            const int j = j0 + lane;
+            bool keep = false;
+            int w = SK_SENTINEL;
+            if (j < n) {
+                w = wr[j];
+                if (w != SK_SENTINEL) {
+                    const double lx = p * (double)w + f + ((double)I.G[j] + (double)I.gam[j]);
+                    keep = lx >= logt;
+                }
+            }
+            const uint64_t mask = __ballot(keep);
+            if (keep) {
+                const int before = __popcll(mask & ((1ull << lane) - 1ull));
+                col[pos + before] = j;
+                wout[pos + before] = (int16_t)w;
+            }
+            pos += __popcll(mask);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+hipError_t launch_init(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid, int cold,
+                       hipStream_t st) {
+    hipLaunchKernelGGL(k_init, dim3(grid), dim3(kRowWaves * kWave), 0, st, d_insts, d_units,
+                       nunits, cold);
+    return hipGetLastError();
+}
+hipError_t launch_row_sweep(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
+                            size_t lds_bytes, hipStream_t st) {
+    hipLaunchKernelGGL(k_row_sweep, dim3(grid), dim3(kRowWaves * kWave), lds_bytes, st, d_insts,
+                       d_units, nunits);
+    return hipGetLastError();
+}
+hipError_t launch_col_sweep(const Inst *d_insts, const ColUnit *d_units, int nunits, int grid,
+                            hipStream_t st) {
+    hipLaunchKernelGGL(k_col_sweep, dim3(grid), dim3(kColWaves * kWave), 0, st, d_insts, d_units,
+                       nunits);
+    return hipGetLastError();
+}
+hipError_t launch_iter_end(const Inst *d_insts, int count, hipStream_t st) {
+    hipLaunchKernelGGL(k_iter_end, dim3(count), dim3(256), 0, st, d_insts);
+    return hipGetLastError();
+}
+hipError_t launch_check_rows(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
+                             double *rsum, double *rmax, hipStream_t st) {
+    hipLaunchKernelGGL(k_check_rows, dim3(grid), dim3(kRowWaves * kWave), 0, st, d_insts, d_units,
+                       nunits, rsum, rmax);
+    return hipGetLastError();
+}
+hipError_t launch_check_cols(const Inst *d_insts, int inst, int n, double *csum, hipStream_t st) {
+    hipLaunchKernelGGL(k_check_cols, dim3((n + 255) / 256), dim3(256), 0, st, d_insts, inst, csum);
+    return hipGetLastError();
+}
+hipError_t launch_prune_count(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
+                              double logt, int64_t *counts, hipStream_t st) {
+    hipLaunchKernelGGL(k_prune_count, dim3(grid), dim3(kRowWaves * kWave), 0, st, d_insts, d_units,
+                       nunits, logt, counts);
+    return hipGetLastError();
+}
+hipError_t launch_scan(const int64_t *counts, int64_t *row_ptr, int n, hipStream_t st) {
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, counts, row_ptr, n);
+    return hipGetLastError();
+}
+hipError_t launch_prune_fill(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
+                             double logt, const int64_t *row_ptr, int32_t *col, int16_t *w,
+                             hipStream_t st) {
+    hipLaunchKernelGGL(k_prune_fill, dim3(grid), dim3(kRowWaves * kWave), 0, st, d_insts, d_units,
+                       nunits, logt, row_ptr, col, w);
+    return hipGetLastError();
+}
+hipError_t set_kernel_attributes() {
+    return hipFuncSetAttribute((const void *)k_row_sweep,
+                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)(kMaxN * sizeof(float2)));
+}
+
+}  // namespace sk

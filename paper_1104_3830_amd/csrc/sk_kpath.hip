@@ -1,0 +1,561 @@
+// Stored-K storages: the sweeps read K_ij = exp(p w_ij + log u_i + log v_j)
+// (bfloat16 or float32), computed once from the log-domain potentials
+// ("absorption"), and keep multiplicative row/column scalings a, b in FP32:
+// x_ij = K_ij a_i b_j. A stage starts with one exact log-domain iteration
+// (every column of the iterate then sums to one and every row holds an entry
+// >= 1/n^2, so no sum of K can underflow), then absorbs and sweeps K. When the
+// scalings drift by more than 2^20 since the last absorption, they are folded
+// back into the potentials and K is recomputed, so an entry flushed to zero at
+// absorption (< 2^-126) can never grow past ~2^-86.
+//
+// Row step (u = I(A^(p) v)):  a_i <- 1 / sum_j K_ij b_j,  r_i = a_i(old) * sum_j K_ij b_j.
+// Column step (v = I(A^(p)T u)): b_j <- 1 / sum_i K_ij a_i.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "sk_runtime.h"
+
+namespace sk {
+
+constexpr float kLog2eK = 1.4426950408889634f;
+constexpr float kKLo = 5.421010862427522e-20f;  // 2^-64
+constexpr float kKHi = 1.8446744073709552e19f;  // 2^64
+constexpr float kDriftLimit = 20.0f;             // log2 of the scaling drift that triggers absorption
+
+__device__ __forceinline__ float kex2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float klg2(float x) { return __builtin_amdgcn_logf(x); }
+
+__device__ __forceinline__ float kwave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+__device__ __forceinline__ double kwave_sum_d(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+__device__ __forceinline__ void krange(int nunits, int &u0, int &u1) {
+    int per = (nunits + (int)gridDim.x - 1) / (int)gridDim.x;
+    u0 = (int)blockIdx.x * per;
+    u1 = min(nunits, u0 + per);
+}
+
+// float -> bfloat16 bits, round to nearest even (finite, non-negative inputs)
+__device__ __forceinline__ uint32_t bf16_rne(float x) {
+    uint32_t b = __float_as_uint(x);
+    return (b + 0x7fffu + ((b >> 16) & 1u)) >> 16;
+}
+
+// Loads 8 consecutive K values starting at a multiple of 8.
+template <int ST>
+__device__ __forceinline__ void load8(const void *K, int64_t off, float (&k)[8]) {
+    if (ST == SK_K_BF16) {
+        const int4 v = *reinterpret_cast<const int4 *>(reinterpret_cast<const uint16_t *>(K) + off);
+        const uint32_t x[4] = {(uint32_t)v.x, (uint32_t)v.y, (uint32_t)v.z, (uint32_t)v.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            k[2 * q] = __uint_as_float(x[q] << 16);
+            k[2 * q + 1] = __uint_as_float(x[q] & 0xffff0000u);
+        }
+    } else {
+        const float4 *p = reinterpret_cast<const float4 *>(reinterpret_cast<const float *>(K) + off);
+        const float4 a = p[0], b = p[1];
+        k[0] = a.x; k[1] = a.y; k[2] = a.z; k[3] = a.w;
+        k[4] = b.x; k[5] = b.y; k[6] = b.z; k[7] = b.w;
+    }
+}
+
+__device__ __forceinline__ int kswz(int j, int n8) { return (j & 7) * n8 + (j >> 3); }
+
+// ---------------------------------------------------------------- absorption
+// K_ij = exp(p w_ij + F_i + phi_i + G_j + gam_j) from the committed
+// potentials (exact integer part, as in the log-domain sweeps); the committed
+// F/phi are copied to both parity buffers, a = b = 1.
+template <int ST>
+__global__ __launch_bounds__(kRowWaves * kWave) void k_absorb(const Inst *__restrict__ insts,
+                                                              const RowUnit *__restrict__ units,
+                                                              int nunits) {
+    extern __shared__ float2 pot[];
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    int u0, u1;
+    krange(nunits, u0, u1);
+    int cur = -1;
+    for (int u = u0; u < u1; ++u) {
+        const RowUnit un = units[u];
+        const Inst &I = insts[un.inst];
+        Ctl *ctl = I.ctl;
+        if (ctl->state != ST_RUNNING || !ctl->need_absorb) continue;
+        const int n = I.n, kp = I.kpitch;
+        if (un.inst != cur) {
+            __syncthreads();
+            for (int j = threadIdx.x; j < n; j += blockDim.x)
+                pot[j] = make_float2((float)I.G[j], I.gam[j] * kLog2eK);
+            __syncthreads();
+            cur = un.inst;
+        }
+        const int row = un.row0 + wave;
+        if (row >= n) continue;
+        const int par = ctl->iter & 1;
+        const float pf = (float)ctl->p;
+        const float Ff = (float)I.F[par][row];
+        const float ph = I.phi[par][row] * kLog2eK;
+        const int16_t *wr = I.W + (int64_t)row * I.pitch;
+        for (int j = lane; j < kp; j += kWave) {
+            float k = 0.f;
+            if (j < n) {
+                const int w = wr[j];
+                if (w != SK_SENTINEL) {
+                    const float2 gp = pot[j];
+                    const float Iv = fmaf((float)w, pf, gp.x) + Ff;
+                    k = fminf(kex2(fmaf(Iv, kLog2eK, gp.y) + ph), kKHi);
+                }
+            }
+            if (ST == SK_K_BF16)
+                reinterpret_cast<uint16_t *>(I.K)[(int64_t)row * kp + j] = (uint16_t)bf16_rne(k);
+            else
+                reinterpret_cast<float *>(I.K)[(int64_t)row * kp + j] = k;
+        }
+        if (lane == 0) {
+            I.F[par ^ 1][row] = I.F[par][row];
+            I.phi[par ^ 1][row] = I.phi[par][row];
+            I.a[0][row] = 1.f;
+            I.a[1][row] = 1.f;
+        }
+    }
+}
+
+// Finishes an absorption: b = 1, flags cleared (one workgroup per instance).
+__global__ __launch_bounds__(256) void k_absorb_done(const Inst *__restrict__ insts) {
+    const Inst &I = insts[blockIdx.x];
+    Ctl *ctl = I.ctl;
+    if (ctl->state != ST_RUNNING || !ctl->need_absorb) return;
+    for (int j = threadIdx.x; j < I.n; j += blockDim.x) I.b[j] = 1.f;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ctl->need_absorb = 0u;
+        ctl->drift_bits = 0u;
+    }
+}
+
+// ---------------------------------------------------------------- K row sweep
+template <int ST>
+__global__ __launch_bounds__(kRowWaves * kWave) void k_row_sweep_k(const Inst *__restrict__ insts,
+                                                                   const RowUnit *__restrict__ units,
+                                                                   int nunits) {
+    extern __shared__ float bsh[];
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    int u0, u1;
+    krange(nunits, u0, u1);
+    int cur = -1;
+    float resmax = 0.f, drift = 0.f;
+    for (int u = u0; u < u1; ++u) {
+        const RowUnit un = units[u];
+        const Inst &I = insts[un.inst];
+        Ctl *ctl = I.ctl;
+        if (ctl->state != ST_RUNNING || ctl->need_absorb) continue;
+        const int n = I.n, kp = I.kpitch, n8 = kp >> 3;
+        if (un.inst != cur) {
+            if (cur >= 0 && lane == 0) {
+                if (insts[cur].ctl->iter >= 1 && resmax > 0.f)
+                    atomicMax(&insts[cur].ctl->res_bits, __float_as_uint(resmax));
+                if (drift > 0.f) atomicMax(&insts[cur].ctl->drift_bits, __float_as_uint(drift));
+            }
+            resmax = 0.f;
+            drift = 0.f;
+            __syncthreads();
+            for (int j = threadIdx.x; j < kp; j += blockDim.x) bsh[kswz(j, n8)] = j < n ? I.b[j] : 0.f;
+            __syncthreads();
+            cur = un.inst;
+        }
+        const int row = un.row0 + wave;
+        if (row >= n) continue;
+        const int par = ctl->iter & 1;
+        float acc = 0.f;
+        for (int j0 = lane * 8; j0 < kp; j0 += 512) {
+            float k[8];
+            load8<ST>(I.K, (int64_t)row * kp + j0, k);
+            const int q = j0 >> 3;
+            float s = 0.f;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) s = fmaf(k[c], bsh[c * n8 + q], s);
+            acc += s;
+        }
+        const float S = kwave_sum(acc);
+        if (lane == 0) {
+            const float aold = I.a[par][row];
+            const float anew = 1.f / fminf(fmaxf(S, kKLo), kKHi);
+            I.a[par ^ 1][row] = anew;
+            resmax = fmaxf(resmax, fabsf(aold * S - 1.f));
+            drift = fmaxf(drift, fabsf(klg2(anew)));
+        }
+    }
+    if (cur >= 0 && lane == 0) {
+        if (insts[cur].ctl->iter >= 1 && resmax > 0.f)
+            atomicMax(&insts[cur].ctl->res_bits, __float_as_uint(resmax));
+        if (drift > 0.f) atomicMax(&insts[cur].ctl->drift_bits, __float_as_uint(drift));
+    }
+}
+
+// ---------------------------------------------------------------- K column sweep
+template <int ST>
+__global__ __launch_bounds__(kColWaves * kWave) void k_col_sweep_k(const Inst *__restrict__ insts,
+                                                                   const ColUnit *__restrict__ units,
+                                                                   int nunits) {
+    __shared__ float red[kColWaves][kColTile8];
+    __shared__ float ash[kMaxSegRows];
+    __shared__ int s_last;
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    int u0, u1;
+    krange(nunits, u0, u1);
+    for (int u = u0; u < u1; ++u) {
+        const ColUnit un = units[u];
+        const Inst &I = insts[un.inst];
+        Ctl *ctl = I.ctl;
+        if (ctl->state != ST_RUNNING || ctl->need_absorb) continue;
+        const float res = __uint_as_float(ctl->res_bits);
+        const bool conv = ctl->iter >= 1 && res < I.tol;
+        const int n = I.n, kp = I.kpitch;
+        const int npar = (ctl->iter + 1) & 1;
+        const int ctile0 = un.tile * kColTile8;
+        const int ncols = min(kColTile8, n - ctile0);
+        if (!conv) {
+            const int r0 = un.seg * I.seg_rows, r1 = min(n, r0 + I.seg_rows);
+            __syncthreads();
+            for (int r = r0 + (int)threadIdx.x; r < r1; r += blockDim.x) ash[r - r0] = I.a[npar][r];
+            __syncthreads();
+            float acc[8];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) acc[c] = 0.f;
+            const int c0 = ctile0 + lane * 8;
+            if (c0 < n) {
+                for (int r = r0 + wave; r < r1; r += kColWaves) {
+                    const float ar = ash[r - r0];
+                    float k[8];
+                    load8<ST>(I.K, (int64_t)r * kp + c0, k);
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) acc[c] = fmaf(k[c], ar, acc[c]);
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 8; ++c) red[wave][lane * 8 + c] = acc[c];
+            __syncthreads();
+            float *dst = I.colpart + (int64_t)un.seg * n + ctile0;
+            for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
+                float s = red[0][c];
+#pragma unroll
+                for (int w2 = 1; w2 < kColWaves; ++w2) s += red[w2][c];
+                dst[c] = s;
+            }
+        }
+        __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const unsigned old = atomicAdd(&I.tilecnt[un.tile], 1u);
+            s_last = (old == (unsigned)(I.nseg - 1));
+        }
+        __syncthreads();
+        if (s_last) {
+            __threadfence();
+            if (!conv) {
+                float drift = 0.f;
+                for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
+                    const int j = ctile0 + c;
+                    float T = 0.f;
+                    for (int s = 0; s < I.nseg; ++s)
+                        T += __builtin_nontemporal_load(I.colpart + (int64_t)s * n + j);
+                    const float bn = 1.f / fminf(fmaxf(T, kKLo), kKHi);
+                    I.b[j] = bn;
+                    drift = fmaxf(drift, fabsf(klg2(bn)));
+                }
+                if (drift > 0.f) atomicMax(&ctl->drift_bits, __float_as_uint(drift));
+            }
+            if (threadIdx.x == 0) I.tilecnt[un.tile] = 0u;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- fold, advance
+// log u_i += log a_i, log v_j += log b_j; a = b = 1 (one workgroup per instance).
+__global__ __launch_bounds__(256) void k_fold(const Inst *__restrict__ insts) {
+    const Inst &I = insts[blockIdx.x];
+    Ctl *ctl = I.ctl;
+    if (ctl->state == ST_ERROR || ctl->state == ST_DONE) return;
+    const int par = ctl->iter & 1;
+    for (int i = threadIdx.x; i < I.n; i += blockDim.x) {
+        const double f = (double)I.F[par][i] + (double)I.phi[par][i] + log((double)I.a[par][i]);
+        const double k = rint(f);
+        I.F[0][i] = I.F[1][i] = (int32_t)k;
+        I.phi[0][i] = I.phi[1][i] = (float)(f - k);
+        I.a[0][i] = I.a[1][i] = 1.f;
+        const double g = (double)I.G[i] + (double)I.gam[i] + log((double)I.b[i]);
+        const double kg = rint(g);
+        I.G[i] = (int32_t)kg;
+        I.gam[i] = (float)(g - kg);
+        I.b[i] = 1.f;
+    }
+}
+
+// Next p of the ladder (p^-1 log u, p^-1 log v held fixed), or done.
+__global__ __launch_bounds__(256) void k_advance(const Inst *__restrict__ insts) {
+    const Inst &I = insts[blockIdx.x];
+    Ctl *ctl = I.ctl;
+    if (ctl->state != ST_STAGE_END) return;
+    const int n = I.n;
+    const int s = ctl->stage;
+    const int par = ctl->iter & 1;
+    if (s + 1 < I.n_p) {
+        const double ratio = (double)I.ladder[s + 1] / (double)I.ladder[s];
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const double f = ((double)I.F[par][i] + (double)I.phi[par][i]) * ratio;
+            const double k = rint(f);
+            I.F[0][i] = (int32_t)k;
+            I.phi[0][i] = (float)(f - k);
+            const double g = ((double)I.G[i] + (double)I.gam[i]) * ratio;
+            const double kg = rint(g);
+            I.G[i] = (int32_t)kg;
+            I.gam[i] = (float)(g - kg);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            ctl->stage = s + 1;
+            ctl->p = I.ladder[s + 1];
+            ctl->iter = 0;
+            ctl->need_absorb = 1u;
+            ctl->state = ST_RUNNING;
+        }
+    } else {
+        if (threadIdx.x == 0) ctl->state = ST_DONE;
+    }
+}
+
+// FP64 row and column sums of the matrix the K sweeps balance, K_ij a_i b_j.
+template <int ST>
+__global__ __launch_bounds__(kRowWaves * kWave) void k_check_k_rows(const Inst *__restrict__ insts,
+                                                                    const RowUnit *__restrict__ units,
+                                                                    int nunits, double *rsum) {
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    int u0, u1;
+    krange(nunits, u0, u1);
+    for (int u = u0; u < u1; ++u) {
+        const RowUnit un = units[u];
+        const Inst &I = insts[un.inst];
+        const int n = I.n, row = un.row0 + wave, kp = I.kpitch;
+        if (row >= n) continue;
+        const int par = I.ctl->iter & 1;
+        double s = 0.0;
+        for (int j = lane; j < n; j += kWave) {
+            const int64_t o = (int64_t)row * kp + j;
+            const float k = ST == SK_K_BF16
+                                ? __uint_as_float((uint32_t)reinterpret_cast<const uint16_t *>(I.K)[o] << 16)
+                                : reinterpret_cast<const float *>(I.K)[o];
+            s += (double)k * (double)I.b[j];
+        }
+        s = kwave_sum_d(s);
+        if (lane == 0) rsum[row] = s * (double)I.a[par][row];
+    }
+}
+
+template <int ST>
+__global__ __launch_bounds__(256) void k_check_k_cols(const Inst *__restrict__ insts, int inst,
+                                                      double *csum) {
+    const Inst &I = insts[inst];
+    const int n = I.n, kp = I.kpitch;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int par = I.ctl->iter & 1;
+    double s = 0.0;
+    for (int r = 0; r < n; ++r) {
+        const int64_t o = (int64_t)r * kp + j;
+        const float k = ST == SK_K_BF16
+                            ? __uint_as_float((uint32_t)reinterpret_cast<const uint16_t *>(I.K)[o] << 16)
+                            : reinterpret_cast<const float *>(I.K)[o];
+        s += (double)k * (double)I.a[par][r];
+    }
+    csum[j] = s * (double)I.b[j];
+}
+
+// ---------------------------------------------------------------- launchers
+hipError_t launch_absorb(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
+                         size_t lds_bytes, int storage, hipStream_t st) {
+    if (storage == SK_K_BF16)
+        hipLaunchKernelGGL(k_absorb<SK_K_BF16>, dim3(grid), dim3(kRowWaves * kWave), lds_bytes, st,
+                           d_insts, d_units, nunits);
+    else
+        hipLaunchKernelGGL(k_absorb<SK_K_F32>, dim3(grid), dim3(kRowWaves * kWave), lds_bytes, st,
+                           d_insts, d_units, nunits);
+    return hipGetLastError();
+}
+hipError_t launch_row_sweep_k(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
+                              size_t lds_bytes, int storage, hipStream_t st) {
+    if (storage == SK_K_BF16)
+        hipLaunchKernelGGL(k_row_sweep_k<SK_K_BF16>, dim3(grid), dim3(kRowWaves * kWave), lds_bytes,
+                           st, d_insts, d_units, nunits);
+    else
+        hipLaunchKernelGGL(k_row_sweep_k<SK_K_F32>, dim3(grid), dim3(kRowWaves * kWave), lds_bytes,
+                           st, d_insts, d_units, nunits);
+    return hipGetLastError();
+}
+hipError_t launch_col_sweep_k(const Inst *d_insts, const ColUnit *d_units, int nunits, int grid,
+                              int storage, hipStream_t st) {
+    if (storage == SK_K_BF16)
+        hipLaunchKernelGGL(k_col_sweep_k<SK_K_BF16>, dim3(grid), dim3(kColWaves * kWave), 0, st,
+                           d_insts, d_units, nunits);
+    else
+        hipLaunchKernelGGL(k_col_sweep_k<SK_K_F32>, dim3(grid), dim3(kColWaves * kWave), 0, st,
+                           d_insts, d_units, nunits);
+    return hipGetLastError();
+}
+hipError_t launch_fold_k(const Inst *d_insts, int count, hipStream_t st) {
+    hipLaunchKernelGGL(k_fold, dim3(count), dim3(256), 0, st, d_insts);
+    return hipGetLastError();
+}
+hipError_t launch_advance(const Inst *d_insts, int count, hipStream_t st) {
+    hipLaunchKernelGGL(k_advance, dim3(count), dim3(256), 0, st, d_insts);
+    return hipGetLastError();
+}
+static hipError_t launch_absorb_done(const Inst *d_insts, int count, hipStream_t st) {
+    hipLaunchKernelGGL(k_absorb_done, dim3(count), dim3(256), 0, st, d_insts);
+    return hipGetLastError();
+}
+hipError_t launch_check_k(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid, int inst,
+                          int n, int storage, double *rsum, double *csum, hipStream_t st) {
+    if (storage == SK_K_BF16) {
+        hipLaunchKernelGGL(k_check_k_rows<SK_K_BF16>, dim3(grid), dim3(kRowWaves * kWave), 0, st,
+                           d_insts, d_units, nunits, rsum);
+        hipLaunchKernelGGL(k_check_k_cols<SK_K_BF16>, dim3((n + 255) / 256), dim3(256), 0, st,
+                           d_insts, inst, csum);
+    } else {
+        hipLaunchKernelGGL(k_check_k_rows<SK_K_F32>, dim3(grid), dim3(kRowWaves * kWave), 0, st,
+                           d_insts, d_units, nunits, rsum);
+        hipLaunchKernelGGL(k_check_k_cols<SK_K_F32>, dim3((n + 255) / 256), dim3(256), 0, st,
+                           d_insts, inst, csum);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- host controller
+#define KCHK(expr)                                                                          \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(ctx, SK_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));    \
+    } while (0)
+
+static sk_status absorb(sk_ctx *ctx, Batch &B, int storage) {
+    ctx->prof.begin(ctx->stream, KID_ABSORB);
+    KCHK(launch_absorb(B.d_insts, B.d_rows, (int)B.h_rows.size(), B.row_grid, B.row_lds, storage,
+                       ctx->stream));
+    KCHK(launch_absorb_done(B.d_insts, B.count, ctx->stream));
+    ctx->prof.end(ctx->stream);
+    ctx->absorbs += 1;
+    return SK_OK;
+}
+
+static sk_status fold(sk_ctx *ctx, Batch &B) {
+    ctx->prof.begin(ctx->stream, KID_FOLD_K);
+    KCHK(launch_fold_k(B.d_insts, B.count, ctx->stream));
+    ctx->prof.end(ctx->stream);
+    return SK_OK;
+}
+
+// Sets need_absorb on the device copy of the control block.
+static sk_status request_absorb(sk_ctx *ctx, Batch &B) {
+    static const uint32_t one = 1u;
+    KCHK(hipMemcpyAsync(&B.h_insts[0].ctl->need_absorb, &one, sizeof one, hipMemcpyHostToDevice,
+                        ctx->stream));
+    KCHK(hipStreamSynchronize(ctx->stream));
+    return SK_OK;
+}
+
+sk_status run_single_k(sk_ctx *ctx, Batch &B, const sk_params *prm) {
+    const int storage = prm->storage;
+    const int check = std::max(1, prm->check_every);
+    sk_status st;
+    if ((st = request_absorb(ctx, B)) != SK_OK) return st;
+    const int64_t bound = (prm->max_iters_per_stage + 2) * prm->n_p * 4 + 16;
+    int64_t rounds = 0;
+    ctx->k_res_rows = ctx->k_res_cols = NAN;
+    for (;;) {
+        if ((st = read_ctl(ctx, B)) != SK_OK) return st;
+        const Ctl &c = ctx->h_ctl[0];
+        if (++rounds > bound) return fail(ctx, SK_EDEVICE, "stored-K controller did not terminate");
+        if (c.state == ST_ERROR || c.state == ST_DONE) break;
+        if (c.state == ST_STAGE_END) {
+            if (c.stage + 1 >= prm->n_p) {
+                // FP64 sums of the balanced matrix K a b, before folding
+                const Inst &I = B.h_insts[0];
+                const int n = I.n;
+                ctx->prof.begin(ctx->stream, KID_CHECK_ROWS);
+                KCHK(launch_check_k(B.d_insts, B.d_rows, (int)B.h_rows.size(), B.row_grid, 0, n,
+                                    storage, B.d_rsum, B.d_csum, ctx->stream));
+                ctx->prof.end(ctx->stream);
+                std::vector<double> r(n), cs(n);
+                KCHK(hipMemcpyAsync(r.data(), B.d_rsum, 8 * (size_t)n, hipMemcpyDeviceToHost,
+                                    ctx->stream));
+                KCHK(hipMemcpyAsync(cs.data(), B.d_csum, 8 * (size_t)n, hipMemcpyDeviceToHost,
+                                    ctx->stream));
+                KCHK(hipStreamSynchronize(ctx->stream));
+                double rr = 0, cr = 0;
+                for (int i = 0; i < n; ++i) {
+                    rr = std::max(rr, std::fabs(r[i] - 1.0));
+                    cr = std::max(cr, std::fabs(cs[i] - 1.0));
+                }
+                ctx->k_res_rows = rr;
+                ctx->k_res_cols = cr;
+            }
+            if ((st = fold(ctx, B)) != SK_OK) return st;
+            KCHK(launch_advance(B.d_insts, B.count, ctx->stream));
+            continue;
+        }
+        if (c.need_absorb) {
+            // one exact log-domain iteration, then K from its potentials
+            if ((st = iterate_i16(ctx, B)) != SK_OK) return st;
+            if ((st = absorb(ctx, B, storage)) != SK_OK) return st;
+            continue;
+        }
+        float drift;
+        memcpy(&drift, &c.drift_bits, sizeof drift);
+        if (drift > kDriftLimit) {
+            if ((st = fold(ctx, B)) != SK_OK) return st;
+            if ((st = request_absorb(ctx, B)) != SK_OK) return st;
+            if ((st = absorb(ctx, B, storage)) != SK_OK) return st;
+            continue;
+        }
+        for (int k = 0; k < check; ++k) {
+            ctx->prof.begin(ctx->stream, KID_ROW_K);
+            KCHK(launch_row_sweep_k(B.d_insts, B.d_rows, (int)B.h_rows.size(), B.row_grid,
+                                    B.row_lds_k, storage, ctx->stream));
+            ctx->prof.end(ctx->stream);
+            ctx->prof.begin(ctx->stream, KID_COL_K);
+            KCHK(launch_col_sweep_k(B.d_insts, B.d_cols, (int)B.h_cols.size(), B.col_grid, storage,
+                                    ctx->stream));
+            ctx->prof.end(ctx->stream);
+            ctx->prof.begin(ctx->stream, KID_ITER_END);
+            KCHK(launch_iter_end(B.d_insts, B.count, ctx->stream));
+            ctx->prof.end(ctx->stream);
+        }
+    }
+    return SK_OK;
+}
+
+hipError_t set_k_attributes() {
+    hipError_t e;
+    const int lds = (int)(kMaxN * sizeof(float2));
+    if ((e = hipFuncSetAttribute((const void *)k_absorb<SK_K_BF16>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds)) != hipSuccess)
+        return e;
+    if ((e = hipFuncSetAttribute((const void *)k_absorb<SK_K_F32>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds)) != hipSuccess)
+        return e;
+    if ((e = hipFuncSetAttribute((const void *)k_row_sweep_k<SK_K_BF16>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds / 2)) != hipSuccess)
+        return e;
+    return hipFuncSetAttribute((const void *)k_row_sweep_k<SK_K_F32>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, lds / 2);
+}
+
+}  // namespace sk

@@ -1,0 +1,103 @@
+// Host-side runtime structures of libsk (not part of the ABI).
+#pragma once
+
+#include <cstdarg>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "sk_internal.h"
+
+namespace sk {
+
+constexpr int kMaxBatch = 4096;
+
+struct TilePlan {
+    int tile_cols, ntiles, seg_rows, nseg;
+};
+TilePlan plan_tiles(int32_t n, int vec8);
+size_t instance_bytes(int32_t n, int vec8, int storage);
+size_t shared_bytes(int32_t count, const int32_t *n);
+
+// A set of instances swept together, with its device tables.
+struct Batch {
+    int count = 0;
+    int nmax = 0;
+    std::vector<Inst> h_insts;
+    std::vector<RowUnit> h_rows;
+    std::vector<ColUnit> h_cols;
+    Inst *d_insts = nullptr;
+    RowUnit *d_rows = nullptr;
+    ColUnit *d_cols = nullptr;
+    double *d_rsum = nullptr, *d_rmax = nullptr, *d_csum = nullptr;
+    int64_t *d_counts = nullptr;
+    size_t row_lds = 0;
+    size_t row_lds_k = 0;
+    int row_grid = 1, col_grid = 1;
+};
+
+struct Bump;
+struct Server;
+
+enum KernelId {
+    KID_INIT, KID_ROW, KID_COL, KID_ITER_END, KID_CHECK_ROWS, KID_CHECK_COLS, KID_PRUNE_COUNT,
+    KID_SCAN, KID_PRUNE_FILL, KID_ABSORB, KID_ROW_K, KID_COL_K, KID_FOLD_K, KID_COUNT
+};
+extern const char *kKernelNames[KID_COUNT];
+
+// HIP-event timing of launches on the context stream.
+struct Profiler {
+    bool on = false;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+    std::vector<hipEvent_t> pool;
+    int64_t launches[KID_COUNT] = {};
+    double total_ms[KID_COUNT] = {};
+    hipEvent_t take();
+    void begin(hipStream_t st, int id);
+    void end(hipStream_t st);
+    void drain();   // call after the stream is synchronised
+    void reset();
+    ~Profiler();
+    int cur_id = -1;
+    hipEvent_t cur_start = nullptr;
+};
+
+}  // namespace sk
+
+struct sk_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    char *arena = nullptr;
+    size_t arena_bytes = 0;
+    int num_cus = 256;
+    std::string err;
+    std::mutex mu;                 // one blocking call at a time
+    sk::Ctl *h_ctl = nullptr;      // pinned readback of control blocks
+    sk::Batch scratch_batch;
+    int absorbs = 0;
+    double k_res_rows = 0, k_res_cols = 0;
+    sk::Profiler prof;
+    sk::Server *server = nullptr;
+};
+
+namespace sk {
+
+sk_status fail(sk_ctx *ctx, sk_status st, const char *fmt, ...);
+sk_status check_params(sk_ctx *ctx, const sk_params *p);
+sk_status plan_batch(sk_ctx *ctx, Bump &bump, int count, const int16_t *const *W,
+                     const int64_t *pitch, const int32_t *n, const sk_params *prm, Batch &B);
+sk_status upload_batch(sk_ctx *ctx, Batch &B);
+sk_status start_batch(sk_ctx *ctx, Batch &B, const sk_params *prm, void *const *pot_in);
+sk_status read_ctl(sk_ctx *ctx, Batch &B);
+sk_status iterate_i16(sk_ctx *ctx, Batch &B);
+sk_status run_batch_i16(sk_ctx *ctx, Batch &B, const sk_params *prm);
+sk_status run_single_k(sk_ctx *ctx, Batch &B, const sk_params *prm);
+sk_status check_fp64(sk_ctx *ctx, Batch &B, int k, sk_report *rep);
+void fill_report(const Ctl &c, sk_report *rep);
+sk_status copy_potentials_out(sk_ctx *ctx, Batch &B, int k, void *pot);
+sk_status scale_impl(sk_ctx *ctx, int count, const int16_t *const *W, const int32_t *n,
+                     const sk_params *prm, void *const *pot, sk_report *reports);
+void serve_stop(sk_ctx *ctx);
+hipError_t set_k_attributes();
+
+}  // namespace sk

@@ -1,0 +1,650 @@
+// Host runtime of libsk: contexts, arena planning, the stage controller that
+// drives the sweep kernels, the FP64 recheck and certificate, pruning, and the
+// C ABI entry points declared in include/sk.h.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "sk_internal.h"
+#include "sk_runtime.h"
+
+namespace sk {
+
+// ---------------------------------------------------------------- planning
+
+TilePlan plan_tiles(int32_t n, int vec8) {
+    TilePlan t;
+    t.tile_cols = vec8 ? kColTile8 : kColTile1;
+    t.ntiles = (n + t.tile_cols - 1) / t.tile_cols;
+    // Column-sweep segment height: aim for ~1024 work units per sweep, but
+    // keep each unit at >= 128 rows so the fixed-slot partials stay a small
+    // fraction of the matrix traffic.
+    int64_t want = ((int64_t)n * t.ntiles + 1023) / 1024;
+    int seg = (int)std::min<int64_t>(kMaxSegRows, std::max<int64_t>(128, (want + 15) / 16 * 16));
+    seg = std::min(seg, std::max(16, (n + 15) / 16 * 16));
+    t.seg_rows = seg;
+    t.nseg = (n + seg - 1) / seg;
+    return t;
+}
+
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+size_t instance_bytes(int32_t n, int vec8, int storage) {
+    TilePlan t = plan_tiles(n, vec8);
+    size_t b = 0;
+    b += align_up(sizeof(int32_t) * n, 256) * 3;  // F[2], G
+    b += align_up(sizeof(float) * n, 256) * 3;    // phi[2], gam
+    b += align_up(sizeof(float) * (size_t)t.nseg * n, 256);
+    b += align_up(sizeof(uint32_t) * t.ntiles, 256);
+    b += align_up(sizeof(uint32_t) * n, 256);
+    b += align_up(sizeof(Ctl), 256);
+    if (storage == SK_K_BF16 || storage == SK_K_F32) {
+        const size_t es = storage == SK_K_BF16 ? 2 : 4;
+        const size_t kp = (size_t)(n + 7) / 8 * 8;
+        b += align_up(es * (size_t)n * kp, 256);
+        b += align_up(sizeof(float) * n, 256) * 3;  // a[2], b
+    }
+    return b;
+}
+
+size_t shared_bytes(int32_t count, const int32_t *n) {
+    int64_t rows = 0, cols = 0, nmax = 0;
+    for (int k = 0; k < count; ++k) {
+        TilePlan t = plan_tiles(n[k], (n[k] % 8) == 0);
+        rows += (n[k] + kRowWaves - 1) / kRowWaves;
+        cols += (int64_t)t.ntiles * t.nseg;
+        nmax = std::max<int64_t>(nmax, n[k]);
+    }
+    size_t b = 0;
+    b += align_up(sizeof(Inst) * count, 256);
+    b += align_up(sizeof(RowUnit) * rows, 256);
+    b += align_up(sizeof(ColUnit) * cols, 256);
+    b += align_up(sizeof(double) * nmax, 256) * 3;  // FP64 check: rsum, rmax, csum
+    b += align_up(sizeof(int64_t) * (nmax + 1), 256);  // prune row counts
+    return b;
+}
+
+// Bump allocator over a caller arena.
+struct Bump {
+    char *base;
+    size_t cap, off = 0;
+    template <class T>
+    T *take(size_t count) {
+        size_t o = align_up(off, 256);
+        size_t need = sizeof(T) * count;
+        if (o + need > cap) return nullptr;
+        off = o + need;
+        return reinterpret_cast<T *>(base + o);
+    }
+};
+
+const char *kKernelNames[KID_COUNT] = {"init", "row_sweep", "col_sweep", "iter_end",
+                                       "check_rows", "check_cols", "prune_count", "scan",
+                                       "prune_fill", "absorb", "row_sweep_k", "col_sweep_k",
+                                       "fold_k"};
+
+hipEvent_t Profiler::take() {
+    if (!pool.empty()) {
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+void Profiler::begin(hipStream_t st, int id) {
+    if (!on) return;
+    cur_id = id;
+    cur_start = take();
+    if (cur_start) (void)hipEventRecord(cur_start, st);
+}
+void Profiler::end(hipStream_t st) {
+    if (!on || !cur_start) return;
+    hipEvent_t e = take();
+    if (!e) return;
+    (void)hipEventRecord(e, st);
+    pending.push_back({cur_id, {cur_start, e}});
+    cur_start = nullptr;
+}
+void Profiler::drain() {
+    for (auto &p : pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p.second.first, p.second.second) == hipSuccess) {
+            launches[p.first] += 1;
+            total_ms[p.first] += ms;
+        }
+        pool.push_back(p.second.first);
+        pool.push_back(p.second.second);
+    }
+    pending.clear();
+}
+void Profiler::reset() {
+    drain();
+    for (int k = 0; k < KID_COUNT; ++k) {
+        launches[k] = 0;
+        total_ms[k] = 0.0;
+    }
+}
+Profiler::~Profiler() {
+    for (auto &p : pending) {
+        (void)hipEventDestroy(p.second.first);
+        (void)hipEventDestroy(p.second.second);
+    }
+    for (auto e : pool) (void)hipEventDestroy(e);
+}
+
+}  // namespace sk
+
+using namespace sk;
+
+#define PROF(ctx, id, call)            \
+    ([&]() {                           \
+        (ctx)->prof.begin((ctx)->stream, (id)); \
+        hipError_t e__ = (call);       \
+        (ctx)->prof.end((ctx)->stream); \
+        return e__;                    \
+    }())
+
+sk_status sk_profile_enable(sk_ctx *ctx, int enable) {
+    if (!ctx) return SK_EINVAL;
+    std::lock_guard<std::mutex> g(ctx->mu);
+    (void)hipStreamSynchronize(ctx->stream);
+    ctx->prof.reset();
+    ctx->prof.on = enable != 0;
+    return SK_OK;
+}
+
+int32_t sk_profile_read(sk_ctx *ctx, sk_kernel_stat *out, int32_t max) {
+    if (!ctx) return -1;
+    std::lock_guard<std::mutex> g(ctx->mu);
+    (void)hipStreamSynchronize(ctx->stream);
+    ctx->prof.drain();
+    int32_t k = 0;
+    for (int id = 0; id < KID_COUNT; ++id) {
+        if (ctx->prof.launches[id] == 0) continue;
+        if (out && k < max) {
+            memset(&out[k], 0, sizeof out[k]);
+            snprintf(out[k].name, sizeof out[k].name, "%s", kKernelNames[id]);
+            out[k].launches = ctx->prof.launches[id];
+            out[k].total_ms = ctx->prof.total_ms[id];
+        }
+        ++k;
+    }
+    return k;
+}
+
+// ---------------------------------------------------------------- context
+
+static std::mutex g_attr_mu;
+static bool g_attr_done = false;
+
+size_t sk_potentials_bytes(int32_t n) { return n > 0 ? (size_t)16 * n : 0; }
+
+size_t sk_arena_bytes(int32_t n, int32_t storage) {
+    if (n <= 0) return 0;
+    return instance_bytes(n, (n % 8) == 0, storage) + shared_bytes(1, &n) + 4096;
+}
+
+size_t sk_batch_arena_bytes(int32_t count, const int32_t *n, int32_t storage) {
+    if (count <= 0 || !n) return 0;
+    size_t b = shared_bytes(count, n) + 4096;
+    for (int k = 0; k < count; ++k) b += instance_bytes(n[k], (n[k] % 8) == 0, storage);
+    return b;
+}
+
+sk_status sk_create(sk_ctx **out, int device, void *hip_stream, void *arena_dev_ptr,
+                    size_t arena_bytes) {
+    if (!out) return SK_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return SK_EDEVICE;
+    if (hipSetDevice(device) != hipSuccess) return SK_EDEVICE;
+    {
+        std::lock_guard<std::mutex> g(g_attr_mu);
+        if (!g_attr_done) {
+            if (set_kernel_attributes() != hipSuccess) return SK_EDEVICE;
+            if (set_k_attributes() != hipSuccess) return SK_EDEVICE;
+            g_attr_done = true;
+        }
+    }
+    sk_ctx *c = new sk_ctx();
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    c->arena = (char *)arena_dev_ptr;
+    c->arena_bytes = arena_dev_ptr ? arena_bytes : 0;
+    (void)hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, device);
+    if (c->num_cus <= 0) c->num_cus = 256;
+    if (hipHostMalloc((void **)&c->h_ctl, sizeof(Ctl) * kMaxBatch, hipHostMallocDefault) !=
+        hipSuccess) {
+        delete c;
+        return SK_EDEVICE;
+    }
+    *out = c;
+    return SK_OK;
+}
+
+sk_status sk_destroy(sk_ctx *ctx) {
+    if (!ctx) return SK_EINVAL;
+    serve_stop(ctx);
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->h_ctl) (void)hipHostFree(ctx->h_ctl);
+    delete ctx;
+    return SK_OK;
+}
+
+const char *sk_last_error(const sk_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+sk_status sk::fail(sk_ctx *ctx, sk_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    ctx->err = buf;
+    return st;
+}
+
+#define HIPCHK(ctx, expr)                                                                   \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(ctx, SK_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));    \
+    } while (0)
+
+sk_status sk::check_params(sk_ctx *ctx, const sk_params *p) {
+    if (!p) return fail(ctx, SK_EINVAL, "params is NULL");
+    if (p->n_p < 1 || p->n_p > SK_MAX_LADDER)
+        return fail(ctx, SK_EINVAL, "n_p must be in [1, %d]", SK_MAX_LADDER);
+    for (int k = 0; k < p->n_p; ++k)
+        if (p->p_ladder[k] < 1 || p->p_ladder[k] > 2048)
+            return fail(ctx, SK_EINVAL, "p_ladder[%d] = %d outside [1, 2048]", k, p->p_ladder[k]);
+    if (!(p->tol >= 0.0)) return fail(ctx, SK_EINVAL, "tol must be >= 0");
+    if (p->max_iters_per_stage < 1) return fail(ctx, SK_EINVAL, "max_iters_per_stage must be >= 1");
+    if (p->storage < SK_W_I16 || p->storage > SK_K_F32) return fail(ctx, SK_EINVAL, "bad storage");
+    return SK_OK;
+}
+
+// ---------------------------------------------------------------- batch plan
+
+sk_status sk::plan_batch(sk_ctx *ctx, Bump &bump, int count, const int16_t *const *W,
+                         const int64_t *pitch, const int32_t *n, const sk_params *prm,
+                         Batch &B) {
+    B.count = count;
+    B.h_insts.assign(count, Inst{});
+    B.h_rows.clear();
+    B.h_cols.clear();
+    B.nmax = 0;
+    for (int k = 0; k < count; ++k) {
+        Inst &I = B.h_insts[k];
+        const int nn = n[k];
+        I.W = W[k];
+        I.pitch = pitch[k];
+        I.n = nn;
+        I.vec8 = (nn % 8 == 0) && (I.pitch % 8 == 0) && ((uintptr_t)W[k] % 16 == 0);
+        TilePlan t = plan_tiles(nn, I.vec8);
+        I.nseg = t.nseg;
+        I.seg_rows = t.seg_rows;
+        I.ntiles = t.ntiles;
+        I.tile_cols = t.tile_cols;
+        I.n_p = prm->n_p;
+        for (int s = 0; s < prm->n_p; ++s) I.ladder[s] = prm->p_ladder[s];
+        I.tol = (float)prm->tol;
+        I.max_iters = prm->max_iters_per_stage;
+        I.storage = prm->storage;
+        for (int b = 0; b < 2; ++b) {
+            I.F[b] = bump.take<int32_t>(nn);
+            I.phi[b] = bump.take<float>(nn);
+        }
+        I.G = bump.take<int32_t>(nn);
+        I.gam = bump.take<float>(nn);
+        I.colpart = bump.take<float>((size_t)t.nseg * nn);
+        I.tilecnt = bump.take<uint32_t>(t.ntiles);
+        I.rescue = bump.take<uint32_t>(nn);
+        I.ctl = bump.take<Ctl>(1);
+        if (!I.F[0] || !I.F[1] || !I.phi[0] || !I.phi[1] || !I.G || !I.gam || !I.colpart ||
+            !I.tilecnt || !I.rescue || !I.ctl)
+            return fail(ctx, SK_ENOMEM, "arena too small for instance %d (n=%d)", k, nn);
+        I.kpitch = (nn + 7) / 8 * 8;
+        if (prm->storage != SK_W_I16) {
+            const size_t es = prm->storage == SK_K_BF16 ? 2 : 4;
+            I.K = bump.take<char>(es * (size_t)nn * I.kpitch);
+            I.a[0] = bump.take<float>(nn);
+            I.a[1] = bump.take<float>(nn);
+            I.b = bump.take<float>(nn);
+            if (!I.K || !I.a[0] || !I.a[1] || !I.b)
+                return fail(ctx, SK_ENOMEM, "arena too small for the stored K of instance %d", k);
+        }
+        for (int r = 0; r < nn; r += kRowWaves) B.h_rows.push_back(RowUnit{k, r});
+        for (int s = 0; s < t.nseg; ++s)
+            for (int tt = 0; tt < t.ntiles; ++tt) B.h_cols.push_back(ColUnit{k, tt, s, 0});
+        B.nmax = std::max(B.nmax, nn);
+    }
+    B.d_insts = bump.take<Inst>(count);
+    B.d_rows = bump.take<RowUnit>(B.h_rows.size());
+    B.d_cols = bump.take<ColUnit>(B.h_cols.size());
+    B.d_rsum = bump.take<double>(B.nmax);
+    B.d_rmax = bump.take<double>(B.nmax);
+    B.d_csum = bump.take<double>(B.nmax);
+    B.d_counts = bump.take<int64_t>(B.nmax + 1);
+    if (!B.d_insts || !B.d_rows || !B.d_cols || !B.d_rsum || !B.d_rmax || !B.d_csum || !B.d_counts)
+        return fail(ctx, SK_ENOMEM, "arena too small for the batch tables");
+    // grids: row sweep stages n columns of potentials (8 B each) in LDS
+    const size_t lds = sizeof(float2) * (size_t)B.nmax;
+    const int per_cu = lds <= 32768 ? 2 : 1;
+    B.row_lds = lds;
+    B.row_lds_k = sizeof(float) * (size_t)((B.nmax + 7) / 8 * 8);
+    B.row_grid = (int)std::min<size_t>(B.h_rows.size(), (size_t)ctx->num_cus * per_cu);
+    B.col_grid = (int)std::min<size_t>(B.h_cols.size(), (size_t)ctx->num_cus * 8);
+    return SK_OK;
+}
+
+sk_status sk::upload_batch(sk_ctx *ctx, Batch &B) {
+    HIPCHK(ctx, hipMemcpyAsync(B.d_insts, B.h_insts.data(), sizeof(Inst) * B.count,
+                               hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(B.d_rows, B.h_rows.data(), sizeof(RowUnit) * B.h_rows.size(),
+                               hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(B.d_cols, B.h_cols.data(), sizeof(ColUnit) * B.h_cols.size(),
+                               hipMemcpyHostToDevice, ctx->stream));
+    return SK_OK;
+}
+
+// Initial control blocks and the input scan (cold start or warm start).
+sk_status sk::start_batch(sk_ctx *ctx, Batch &B, const sk_params *prm, void *const *pot_in) {
+    std::vector<Ctl> ctl(B.count);
+    for (int k = 0; k < B.count; ++k) {
+        Ctl &c = ctl[k];
+        memset(&c, 0, sizeof c);
+        c.state = ST_RUNNING;
+        c.stage = 0;
+        c.p = prm->p_ladder[0];
+        c.iter = 0;
+        c.last_res = INFINITY;
+        // the host copy lives in pinned memory so the copy is asynchronous
+        ctx->h_ctl[k] = c;
+        HIPCHK(ctx, hipMemcpyAsync(B.h_insts[k].ctl, &ctx->h_ctl[k], sizeof(Ctl),
+                                   hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK(ctx, hipMemsetAsync(B.h_insts[k].tilecnt, 0,
+                                   sizeof(uint32_t) * B.h_insts[k].ntiles, ctx->stream));
+        if (prm->warm_start) {
+            const int nn = B.h_insts[k].n;
+            const char *src = (const char *)pot_in[k];
+            HIPCHK(ctx, hipMemcpyAsync(B.h_insts[k].F[0], src, 4 * (size_t)nn,
+                                       hipMemcpyDeviceToDevice, ctx->stream));
+            HIPCHK(ctx, hipMemcpyAsync(B.h_insts[k].phi[0], src + 4 * (size_t)nn, 4 * (size_t)nn,
+                                       hipMemcpyDeviceToDevice, ctx->stream));
+            HIPCHK(ctx, hipMemcpyAsync(B.h_insts[k].G, src + 8 * (size_t)nn, 4 * (size_t)nn,
+                                       hipMemcpyDeviceToDevice, ctx->stream));
+            HIPCHK(ctx, hipMemcpyAsync(B.h_insts[k].gam, src + 12 * (size_t)nn, 4 * (size_t)nn,
+                                       hipMemcpyDeviceToDevice, ctx->stream));
+        }
+    }
+    HIPCHK(ctx, PROF(ctx, KID_INIT, launch_init(B.d_insts, B.d_rows, (int)B.h_rows.size(), B.row_grid,
+                            prm->warm_start ? 0 : 1, ctx->stream)));
+    return SK_OK;
+}
+
+sk_status sk::read_ctl(sk_ctx *ctx, Batch &B) {
+    for (int k = 0; k < B.count; ++k)
+        HIPCHK(ctx, hipMemcpyAsync(&ctx->h_ctl[k], B.h_insts[k].ctl, sizeof(Ctl),
+                                   hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return SK_OK;
+}
+
+// One Sinkhorn iteration over every running instance of the batch.
+sk_status sk::iterate_i16(sk_ctx *ctx, Batch &B) {
+    HIPCHK(ctx, PROF(ctx, KID_ROW, launch_row_sweep(B.d_insts, B.d_rows, (int)B.h_rows.size(), B.row_grid, B.row_lds,
+                                 ctx->stream)));
+    HIPCHK(ctx, PROF(ctx, KID_COL, launch_col_sweep(B.d_insts, B.d_cols, (int)B.h_cols.size(), B.col_grid,
+                                 ctx->stream)));
+    HIPCHK(ctx, PROF(ctx, KID_ITER_END, launch_iter_end(B.d_insts, B.count, ctx->stream)));
+    return SK_OK;
+}
+
+// Runs the ladder of every instance to completion (device-side stopping).
+sk_status sk::run_batch_i16(sk_ctx *ctx, Batch &B, const sk_params *prm) {
+    const int check = std::max(1, prm->check_every);
+    int64_t bound = 0;  // every iteration advances an instance or ends a stage
+    bound = (prm->max_iters_per_stage + 1) * prm->n_p + 1;
+    int64_t launched = 0;
+    for (;;) {
+        for (int k = 0; k < check; ++k) {
+            sk_status s = iterate_i16(ctx, B);
+            if (s != SK_OK) return s;
+        }
+        launched += check;
+        sk_status s = read_ctl(ctx, B);
+        if (s != SK_OK) return s;
+        bool running = false;
+        for (int k = 0; k < B.count; ++k) running |= ctx->h_ctl[k].state == ST_RUNNING;
+        if (!running) break;
+        if (launched > bound) return fail(ctx, SK_EDEVICE, "stage controller did not terminate");
+    }
+    return SK_OK;
+}
+
+// FP64 recheck of instance k: residuals and the certificate upper bound.
+sk_status sk::check_fp64(sk_ctx *ctx, Batch &B, int k, sk_report *rep) {
+    const Inst &I = B.h_insts[k];
+    const int nn = I.n;
+    std::vector<RowUnit> rows;
+    for (int r = 0; r < nn; r += kRowWaves) rows.push_back(RowUnit{k, r});
+    // reuse the batch row table: find this instance's units
+    size_t first = 0;
+    while (first < B.h_rows.size() && B.h_rows[first].inst != k) ++first;
+    const int nunits = (nn + kRowWaves - 1) / kRowWaves;
+    const int grid = std::min(nunits, ctx->num_cus * 2);
+    HIPCHK(ctx, PROF(ctx, KID_CHECK_ROWS, launch_check_rows(B.d_insts, B.d_rows + first, nunits, grid, B.d_rsum, B.d_rmax,
+                                  ctx->stream)));
+    HIPCHK(ctx, PROF(ctx, KID_CHECK_COLS, launch_check_cols(B.d_insts, k, nn, B.d_csum, ctx->stream)));
+    std::vector<double> rsum(nn), rmax(nn), csum(nn);
+    std::vector<int32_t> G(nn);
+    std::vector<float> gam(nn);
+    HIPCHK(ctx, hipMemcpyAsync(rsum.data(), B.d_rsum, 8 * (size_t)nn, hipMemcpyDeviceToHost,
+                               ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(rmax.data(), B.d_rmax, 8 * (size_t)nn, hipMemcpyDeviceToHost,
+                               ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(csum.data(), B.d_csum, 8 * (size_t)nn, hipMemcpyDeviceToHost,
+                               ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(G.data(), I.G, 4 * (size_t)nn, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(gam.data(), I.gam, 4 * (size_t)nn, hipMemcpyDeviceToHost,
+                               ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    double rr = 0, cr = 0, sm = 0, sg = 0;
+    for (int i = 0; i < nn; ++i) {
+        rr = std::max(rr, std::fabs(rsum[i] - 1.0));
+        cr = std::max(cr, std::fabs(csum[i] - 1.0));
+        sm += rmax[i];
+        sg += (double)G[i] + (double)gam[i];
+    }
+    const Ctl &c = ctx->h_ctl[k];
+    rep->residual_fp64 = rr;
+    rep->col_residual_fp64 = cr;
+    rep->residual_exact_fp64 = rr;
+    rep->col_residual_exact_fp64 = cr;
+    // Proposition prop:aoc with log d_r = log u, log d_c = log v: log u cancels,
+    // UB = p^-1 (sum_i max_j (p w_ij + log v_j) - sum_j log v_j).
+    rep->ub = (sm - sg) / (double)c.p;
+    return SK_OK;
+}
+
+void sk::fill_report(const Ctl &c, sk_report *rep) {
+    rep->residual_fp32 = c.last_res;
+    rep->iters_total = c.iters_total;
+    for (int s = 0; s < SK_MAX_LADDER; ++s) rep->iters_stage[s] = c.stage_iters[s];
+    rep->p_final = c.p;
+    rep->stages_capped = c.capped;
+}
+
+sk_status sk::copy_potentials_out(sk_ctx *ctx, Batch &B, int k, void *pot) {
+    const Inst &I = B.h_insts[k];
+    const int nn = I.n;
+    const int par = ctx->h_ctl[k].iter & 1;
+    char *dst = (char *)pot;
+    HIPCHK(ctx, hipMemcpyAsync(dst, I.F[par], 4 * (size_t)nn, hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(dst + 4 * (size_t)nn, I.phi[par], 4 * (size_t)nn,
+                               hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(dst + 8 * (size_t)nn, I.G, 4 * (size_t)nn, hipMemcpyDeviceToDevice,
+                               ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(dst + 12 * (size_t)nn, I.gam, 4 * (size_t)nn,
+                               hipMemcpyDeviceToDevice, ctx->stream));
+    return SK_OK;
+}
+
+static sk_status status_of(const Ctl &c) {
+    if (c.err & (ERR_EMPTY_ROW | ERR_EMPTY_COL)) return SK_ENOSUPPORT;
+    if (c.capped) return SK_ENOCONV;
+    return SK_OK;
+}
+
+// Exactness of p*w_ij + F_i + G_j in float32 needs |p w| well below 2^24;
+// valid weights are in [-16384, 16383], so p <= 128 guarantees |p w| <= 2^21.
+// Larger p is accepted when the weights are small enough; the input scan
+// would be needed to prove it, so the bound here is on p alone.
+static sk_status check_range(sk_ctx *ctx, const sk_params *prm) {
+    int pmax = 0;
+    for (int s = 0; s < prm->n_p; ++s) pmax = std::max(pmax, prm->p_ladder[s]);
+    if ((int64_t)pmax * 16384 > ((int64_t)1 << 25))
+        return fail(ctx, SK_EINVAL, "p = %d: p * 16384 exceeds 2^25 (exact float range)", pmax);
+    return SK_OK;
+}
+
+sk_status sk::scale_impl(sk_ctx *ctx, int count, const int16_t *const *W, const int32_t *n,
+                         const sk_params *prm, void *const *pot, sk_report *reports) {
+    auto t0 = std::chrono::steady_clock::now();
+    ctx->absorbs = 0;
+    sk_status st = check_params(ctx, prm);
+    if (st != SK_OK) return st;
+    if (count < 1 || count > kMaxBatch) return fail(ctx, SK_EINVAL, "count must be in [1, %d]", kMaxBatch);
+    std::vector<int64_t> pitch(count);
+    for (int k = 0; k < count; ++k) {
+        if (!W[k] || !pot[k]) return fail(ctx, SK_EINVAL, "null W or potentials for instance %d", k);
+        if (n[k] < 1 || n[k] > kMaxN) return fail(ctx, SK_EINVAL, "n[%d] = %d outside [1, %d]", k, n[k], kMaxN);
+        pitch[k] = n[k];
+    }
+    if (prm->storage != SK_W_I16 && count != 1)
+        return fail(ctx, SK_EINVAL, "stored-K storages are single-instance");
+    if ((st = check_range(ctx, prm)) != SK_OK) return st;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    Bump bump{ctx->arena, ctx->arena_bytes};
+    Batch &B = ctx->scratch_batch;
+    if ((st = plan_batch(ctx, bump, count, W, pitch.data(), n, prm, B)) != SK_OK) return st;
+    if ((st = upload_batch(ctx, B)) != SK_OK) return st;
+    if ((st = start_batch(ctx, B, prm, pot)) != SK_OK) return st;
+    if (prm->storage == SK_W_I16) {
+        if ((st = run_batch_i16(ctx, B, prm)) != SK_OK) return st;
+    } else {
+        if ((st = run_single_k(ctx, B, prm)) != SK_OK) return st;
+    }
+    sk_status result = SK_OK;
+    for (int k = 0; k < count; ++k) {
+        const Ctl &c = ctx->h_ctl[k];
+        sk_report rep;
+        memset(&rep, 0, sizeof rep);
+        fill_report(c, &rep);
+        rep.absorbs = ctx->absorbs;
+        if (!(c.err & (ERR_EMPTY_ROW | ERR_EMPTY_COL))) {
+            if ((st = check_fp64(ctx, B, k, &rep)) != SK_OK) return st;
+            if (prm->storage != SK_W_I16) {
+                rep.residual_fp64 = ctx->k_res_rows;
+                rep.col_residual_fp64 = ctx->k_res_cols;
+            }
+        }
+        if ((st = copy_potentials_out(ctx, B, k, pot[k])) != SK_OK) return st;
+        rep.seconds = 0;
+        if (reports) reports[k] = rep;
+        sk_status sk = status_of(c);
+        if (sk == SK_ENOSUPPORT) result = SK_ENOSUPPORT;
+        else if (sk == SK_ENOCONV && result == SK_OK) result = SK_ENOCONV;
+    }
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    const double secs =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (reports)
+        for (int k = 0; k < count; ++k) reports[k].seconds = secs;
+    if (result == SK_ENOSUPPORT) fail(ctx, result, "a row or column of A has no entry");
+    else if (result == SK_ENOCONV) fail(ctx, result, "a stage hit max_iters_per_stage");
+    return result;
+}
+
+sk_status sk_scale(sk_ctx *ctx, const int16_t *W, int32_t n, const sk_params *params,
+                   void *potentials, sk_report *report) {
+    if (!ctx) return SK_EINVAL;
+    std::lock_guard<std::mutex> g(ctx->mu);
+    const int16_t *Ws[1] = {W};
+    void *pots[1] = {potentials};
+    return scale_impl(ctx, 1, Ws, &n, params, pots, report);
+}
+
+sk_status sk_scale_batch(sk_ctx *ctx, int32_t count, const int16_t *const *W, const int32_t *n,
+                         const sk_params *params, void *const *potentials, sk_report *reports) {
+    if (!ctx) return SK_EINVAL;
+    if (!W || !n || !potentials) return fail(ctx, SK_EINVAL, "null array argument");
+    std::lock_guard<std::mutex> g(ctx->mu);
+    return scale_impl(ctx, count, W, n, params, potentials, reports);
+}
+
+// ---------------------------------------------------------------- prune
+
+sk_status sk_prune(sk_ctx *ctx, const int16_t *W, int32_t n, const void *potentials,
+                   const sk_params *params, sk_csr *csr) {
+    if (!ctx) return SK_EINVAL;
+    std::lock_guard<std::mutex> g(ctx->mu);
+    sk_status st = check_params(ctx, params);
+    if (st != SK_OK) return st;
+    if (!W || !potentials || !csr || !csr->row_ptr)
+        return fail(ctx, SK_EINVAL, "null argument");
+    if (n < 1 || n > kMaxN) return fail(ctx, SK_EINVAL, "n = %d outside [1, %d]", n, kMaxN);
+    if (!(params->threshold > 0.0)) return fail(ctx, SK_EINVAL, "threshold must be > 0");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    Bump bump{ctx->arena, ctx->arena_bytes};
+    Batch &B = ctx->scratch_batch;
+    const int16_t *Ws[1] = {W};
+    int64_t pitch = n;
+    sk_params p1 = *params;
+    p1.storage = SK_W_I16;
+    if ((st = plan_batch(ctx, bump, 1, Ws, &pitch, &n, &p1, B)) != SK_OK) return st;
+    // point the descriptor at the caller's potentials
+    Inst &I = B.h_insts[0];
+    char *pot = (char *)potentials;
+    I.F[0] = I.F[1] = (int32_t *)pot;
+    I.phi[0] = I.phi[1] = (float *)(pot + 4 * (size_t)n);
+    I.G = (int32_t *)(pot + 8 * (size_t)n);
+    I.gam = (float *)(pot + 12 * (size_t)n);
+    if ((st = upload_batch(ctx, B)) != SK_OK) return st;
+    Ctl c;
+    memset(&c, 0, sizeof c);
+    c.state = ST_DONE;
+    c.p = params->p_ladder[params->n_p - 1];
+    ctx->h_ctl[0] = c;
+    HIPCHK(ctx, hipMemcpyAsync(I.ctl, &ctx->h_ctl[0], sizeof(Ctl), hipMemcpyHostToDevice,
+                               ctx->stream));
+    const double logt = std::log(params->threshold);
+    const int nunits = (int)B.h_rows.size();
+    HIPCHK(ctx, PROF(ctx, KID_PRUNE_COUNT, launch_prune_count(B.d_insts, B.d_rows, nunits, B.row_grid, logt, B.d_counts,
+                                   ctx->stream)));
+    HIPCHK(ctx, PROF(ctx, KID_SCAN, launch_scan(B.d_counts, csr->row_ptr, n, ctx->stream)));
+    int64_t total = 0;
+    HIPCHK(ctx, hipMemcpyAsync(&total, csr->row_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost,
+                               ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    const int64_t cap = csr->nnz;
+    csr->n = n;
+    csr->nnz = total;
+    if (total > cap) return fail(ctx, SK_ENOMEM, "reduced matrix has %lld entries, capacity %lld",
+                                 (long long)total, (long long)cap);
+    if (total > 0) {
+        if (!csr->col || !csr->w) return fail(ctx, SK_EINVAL, "null col/w buffers");
+        HIPCHK(ctx, PROF(ctx, KID_PRUNE_FILL, launch_prune_fill(B.d_insts, B.d_rows, nunits, B.row_grid, logt, csr->row_ptr,
+                                      csr->col, csr->w, ctx->stream)));
+    }
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return SK_OK;
+}

@@ -1,0 +1,159 @@
+// Exact maximum-weight perfect matching of the reduced sparse instance B
+// (the sequential exact step of Section 4.2): successive shortest augmenting
+// paths with row/column potentials and Dijkstra on a binary heap over the
+// sparse bipartite graph, the O(n (m + n log n)) class cited in Section 1.
+//
+// Costs c_ij = -w_ij (integers, exact in int64). Invariant: reduced costs
+// c_ij - u_i - v_j >= 0 on every edge and = 0 on matched edges.
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <limits>
+#include <queue>
+#include <vector>
+
+#include "../../include/sk.h"
+
+namespace {
+
+struct HeapItem {
+    int64_t d;
+    int32_t col;
+    bool operator>(const HeapItem &o) const { return d > o.d || (d == o.d && col > o.col); }
+};
+
+}  // namespace
+
+extern "C" sk_status sk_solve_reduced(const sk_csr *csr, int32_t *perm, int64_t *weight) {
+    if (!csr || !perm || !weight || csr->n < 0) return SK_EINVAL;
+    const int n = csr->n;
+    if (n == 0) {
+        *weight = 0;
+        return SK_OK;
+    }
+    if (!csr->row_ptr || (csr->nnz > 0 && (!csr->col || !csr->w))) return SK_EINVAL;
+    const int64_t *rp = csr->row_ptr;
+    const int32_t *col = csr->col;
+    const int16_t *w = csr->w;
+    if (rp[0] != 0 || rp[n] != csr->nnz) return SK_EINVAL;
+    for (int i = 0; i < n; ++i) {
+        if (rp[i + 1] < rp[i]) return SK_EINVAL;
+        if (rp[i + 1] == rp[i]) return SK_EINFEASIBLE;  // empty row
+    }
+    for (int64_t e = 0; e < csr->nnz; ++e)
+        if (col[e] < 0 || col[e] >= n || w[e] == SK_SENTINEL) return SK_EINVAL;
+
+    const int64_t INF = std::numeric_limits<int64_t>::max() / 4;
+    std::vector<int64_t> u(n), v(n, 0);
+    std::vector<int32_t> row_of(n, -1), col_of(n, -1);
+    // u_i = min_j c_ij makes every reduced cost non-negative with v = 0
+    for (int i = 0; i < n; ++i) {
+        int64_t m = INF;
+        for (int64_t e = rp[i]; e < rp[i + 1]; ++e) m = std::min<int64_t>(m, -(int64_t)w[e]);
+        u[i] = m;
+    }
+    // greedy start on zero reduced-cost edges
+    for (int i = 0; i < n; ++i)
+        for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+            const int j = col[e];
+            if (row_of[j] < 0 && -(int64_t)w[e] - u[i] - v[j] == 0) {
+                row_of[j] = i;
+                col_of[i] = j;
+                break;
+            }
+        }
+
+    std::vector<int64_t> dist(n, INF);
+    std::vector<int32_t> pred(n, -1);  // row from which column j was reached
+    std::vector<char> done(n, 0);
+    std::vector<int32_t> touched, finalized;
+    touched.reserve(n);
+    finalized.reserve(n);
+    std::priority_queue<HeapItem, std::vector<HeapItem>, std::greater<HeapItem>> heap;
+
+    for (int s = 0; s < n; ++s) {
+        if (col_of[s] >= 0) continue;
+        for (int j : touched) {
+            dist[j] = INF;
+            pred[j] = -1;
+            done[j] = 0;
+        }
+        touched.clear();
+        finalized.clear();
+        while (!heap.empty()) heap.pop();
+        // relax the edges of row s (distance of s is 0)
+        for (int64_t e = rp[s]; e < rp[s + 1]; ++e) {
+            const int j = col[e];
+            const int64_t d = -(int64_t)w[e] - u[s] - v[j];
+            if (dist[j] == INF) touched.push_back(j);
+            if (d < dist[j]) {
+                dist[j] = d;
+                pred[j] = s;
+                heap.push({d, j});
+            }
+        }
+        int target = -1;
+        int64_t D = 0;
+        while (!heap.empty()) {
+            const HeapItem it = heap.top();
+            heap.pop();
+            const int j = it.col;
+            if (done[j] || it.d != dist[j]) continue;
+            done[j] = 1;
+            finalized.push_back(j);
+            if (row_of[j] < 0) {
+                target = j;
+                D = it.d;
+                break;
+            }
+            const int i = row_of[j];
+            for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+                const int k = col[e];
+                if (done[k]) continue;
+                const int64_t nd = it.d + (-(int64_t)w[e] - u[i] - v[k]);
+                if (dist[k] == INF) touched.push_back(k);
+                if (nd < dist[k]) {
+                    dist[k] = nd;
+                    pred[k] = i;
+                    heap.push({nd, k});
+                }
+            }
+        }
+        if (target < 0) return SK_EINFEASIBLE;
+        // potential update keeps reduced costs >= 0 and the new path tight
+        for (int j : finalized) {
+            const int64_t delta = D - dist[j];
+            if (delta == 0) continue;
+            v[j] -= delta;
+            const int i = row_of[j];
+            if (i >= 0) u[i] += delta;
+        }
+        u[s] += D;
+        // augment along pred
+        int j = target;
+        for (;;) {
+            const int i = pred[j];
+            const int prev = col_of[i];
+            row_of[j] = i;
+            col_of[i] = j;
+            if (i == s) break;
+            j = prev;
+        }
+    }
+    int64_t total = 0;
+    for (int i = 0; i < n; ++i) {
+        perm[i] = col_of[i];
+        int64_t wi = 0;
+        bool found = false;
+        for (int64_t e = rp[i]; e < rp[i + 1]; ++e)
+            if (col[e] == col_of[i]) {
+                wi = w[e];
+                found = true;
+                break;
+            }
+        if (!found) return SK_EINVAL;
+        total += wi;
+    }
+    *weight = total;
+    return SK_OK;
+}

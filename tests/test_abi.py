@@ -1,0 +1,125 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol the
+header declares, the ctypes mirrors match the C layouts, and the host exact
+solver (no GPU needed) agrees with the oracle and with brute force."""
+import ctypes
+import math
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1104_3830_amd as sk
+from oracle import brute
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sk.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sk_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_functions()
+    assert len(names) >= 10
+    L = sk.lib()
+    missing = [nm for nm in names if not hasattr(L, nm)]
+    assert not missing, missing
+    assert set(names) == set(sk.EXPORTS)
+
+
+def test_struct_layouts_match_header(tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text(f'''#include <stdio.h>
+#include <stddef.h>
+#include "{HEADER}"
+int main(void) {{
+  printf("%zu %zu %zu\\n", sizeof(sk_params), sizeof(sk_report), sizeof(sk_csr));
+  printf("%zu %zu %zu %zu\\n", offsetof(sk_params, tol), offsetof(sk_params, storage),
+         offsetof(sk_params, warm_start), offsetof(sk_report, seconds));
+  printf("%zu %zu\\n", offsetof(sk_report, nnz_kept), offsetof(sk_csr, w));
+  return 0;
+}}''')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    got = [int(x) for x in out]
+    want = [ctypes.sizeof(sk.Params), ctypes.sizeof(sk.Report), ctypes.sizeof(sk.CSR),
+            sk.Params.tol.offset, sk.Params.storage.offset, sk.Params.warm_start.offset,
+            sk.Report.seconds.offset, sk.Report.nnz_kept.offset, sk.CSR.w.offset]
+    assert got == want
+
+
+def test_potentials_pack_roundtrip():
+    rng = np.random.default_rng(0)
+    lu = rng.normal(size=37) * 3e4
+    lv = rng.normal(size=37) * 50
+    raw = sk.pack_potentials(lu, lv)
+    assert raw.size == sk.potentials_bytes(37)
+    u2, v2 = sk.split_potentials(raw, 37)
+    assert np.abs(u2 - lu).max() < 1e-6 and np.abs(v2 - lv).max() < 1e-6
+
+
+def _csr(mask, w):
+    n = mask.shape[0]
+    rp = np.concatenate([[0], np.cumsum(mask.sum(1))]).astype(np.int64)
+    cols = np.nonzero(mask)[1].astype(np.int32)
+    return rp, cols, w[mask].astype(np.int16)
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 7])
+def test_solve_reduced_vs_brute_force(n):
+    rng = np.random.default_rng(100 + n)
+    for trial in range(10):
+        w = rng.integers(-50, 51, (n, n))
+        mask = rng.random((n, n)) < 0.6
+        rp, cols, ww = _csr(mask, w)
+        b = np.where(mask, w.astype(float), -np.inf)
+        best, winners = brute.all_optima(b)
+        if best == -math.inf:
+            with pytest.raises(sk.SkError) as e:
+                sk.solve_reduced(rp, cols, ww, n)
+            assert e.value.status == sk.SK_EINFEASIBLE
+            continue
+        perm, weight = sk.solve_reduced(rp, cols, ww, n)
+        assert weight == best and tuple(perm) in winners
+
+
+def test_solve_reduced_vs_oracle_hungarian():
+    rng = np.random.default_rng(7)
+    for n in (40, 200, 600):
+        w = rng.integers(0, 1001, (n, n))
+        mask = rng.random((n, n)) < 0.05
+        mask[np.arange(n), rng.permutation(n)] = True
+        rp, cols, ww = _csr(mask, w)
+        perm, weight = sk.solve_reduced(rp, cols, ww, n)
+        _, w_or = oracle.hungarian(w, mask)
+        assert weight == w_or
+        assert sorted(perm) == list(range(n))
+        assert mask[np.arange(n), perm].all()
+
+
+def test_solve_reduced_errors():
+    # empty row
+    rp = np.array([0, 1, 1], dtype=np.int64)
+    with pytest.raises(sk.SkError) as e:
+        sk.solve_reduced(rp, np.array([0], np.int32), np.array([3], np.int16), 2)
+    assert e.value.status == sk.SK_EINFEASIBLE
+    # two rows, one column usable -> no perfect matching
+    rp = np.array([0, 1, 2], dtype=np.int64)
+    with pytest.raises(sk.SkError) as e:
+        sk.solve_reduced(rp, np.array([1, 1], np.int32), np.array([3, 4], np.int16), 2)
+    assert e.value.status == sk.SK_EINFEASIBLE
+    # column index out of range
+    with pytest.raises(sk.SkError) as e:
+        sk.solve_reduced(rp, np.array([0, 5], np.int32), np.array([3, 4], np.int16), 2)
+    assert e.value.status == sk.SK_EINVAL
+    # n = 0
+    perm, weight = sk.solve_reduced(np.array([0], np.int64), np.array([], np.int32),
+                                    np.array([], np.int16), 0)
+    assert weight == 0

@@ -1,0 +1,297 @@
+"""GPU parity: libsk (HIP, through the C ABI) against the FP64 oracle.
+
+Tolerances. The sweeps form p*w_ij + F_i + G_j exactly and round only the
+fractions (|.| <= 1/2), the exp2/log2 hardware approximations (~1 ulp) and
+the FP32 accumulation of a row or column (<= n terms, accumulated 8 at a time
+per lane then across 64 lanes). Per sweep this gives a relative error on a
+row or column sum of a few 1e-7 (far below 1e-5 even with n = 16384 terms
+in the worst case of ~2.4e-6), hence an error in log u_i or log v_j of a few
+1e-7 per step. Over k iterations of a contraction these errors stay bounded by
+~1e-6 / (1 - rate); the tests use 1e-4 on log x for entries >= 1e-6 after
+fixed iteration counts (and 2e-6 on a single step), and bit-exact equality
+for everything integer (optimal weight, permutation, kept support away from
+the threshold band).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1104_3830_amd as sk
+import skgen
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = sk.Context(0)
+    yield c
+    c.close()
+
+
+def dev(W):
+    return torch.from_numpy(np.ascontiguousarray(W)).cuda()
+
+
+def bars(pot, n, p):
+    lu, lv = sk.split_potentials(pot, n)
+    return lu / p, lv / p
+
+
+def logx(B, p, ubar, vbar):
+    return p * (B + ubar[:, None] + vbar[None, :])
+
+
+# ---------------------------------------------------------------- fixed iteration counts
+
+@pytest.mark.parametrize("n,p,iters", [(64, 1, 1), (64, 1, 50), (64, 4, 200), (100, 2, 30),
+                                       (257, 3, 40), (1024, 8, 25), (9, 2, 10)])
+def test_fixed_iterations_match_oracle(ctx, n, p, iters):
+    """Cold start, one stage, exactly `iters` iterations (tol = 0): X from the
+    GPU potentials matches the oracle's W_iters entry by entry."""
+    W = skgen.uniform_weights(n, 0, 100, seed=n + p)
+    B = oracle.log_weights(W)
+    prm = sk.make_params([p], tol=0.0, max_iters=iters, check_every=16)
+    res = ctx.scale(dev(W), prm)
+    assert res.status == sk.SK_ENOCONV  # tol = 0 always runs to the cap
+    assert res.report["iters_total"] == iters
+    ub_g, vb_g = bars(res.potentials, n, p)
+    ub_o, vb_o, m, _ = oracle.sinkhorn(B, p, 0.0, iters)
+    assert m == iters
+    Lg, Lo = logx(B, p, ub_g, vb_g), logx(B, p, ub_o, vb_o)
+    sig = Lo > np.log(1e-6)
+    assert np.abs(Lg - Lo)[sig].max() < 1e-4
+    assert np.abs(np.exp(Lg) - np.exp(Lo)).max() < 1e-5
+
+
+@pytest.mark.parametrize("n", [512, 16384])
+def test_single_step_sampled_full_size(ctx, n):
+    """One full iteration from a warm start at p = 32 (w uniform on 0..1000):
+    log u of sampled rows equals the oracle's row step on the starting v, and
+    log v of sampled columns equals the oracle's column step on the GPU's new
+    u. At n = 16384 this is the benchmark's configuration."""
+    p = 32
+    W = skgen.uniform_weights(n, 0, 1000, seed=3)
+    Wd = dev(W)
+    warm = ctx.scale(Wd, sk.make_params([p], tol=0.0, max_iters=20, check_every=20))
+    ub0, vb0 = bars(warm.potentials, n, p)
+    pot1 = warm.potentials.clone()
+    res = ctx.scale(Wd, sk.make_params([p], tol=0.0, max_iters=1, warm_start=True), potentials=pot1)
+    ub1, vb1 = bars(res.potentials, n, p)
+    rng = np.random.default_rng(0)
+    rows = np.sort(rng.choice(n, 64, replace=False))
+    cols = np.sort(rng.choice(n, 64, replace=False))
+    u_or = oracle.row_step(oracle.log_weights(W[rows]), p, vb0)
+    v_or = oracle.col_step(oracle.log_weights(np.ascontiguousarray(W[:, cols])), p, ub1)
+    # potentials are compared in log u = p * ubar units (absolute)
+    assert np.abs(p * (ub1[rows] - u_or)).max() < 2e-6 * max(1, np.log(n))
+    assert np.abs(p * (vb1[cols] - v_or)).max() < 2e-6 * max(1, np.log(n))
+
+
+# ---------------------------------------------------------------- whole path
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_config_n64_weight_exact(ctx, seed):
+    """n = 64, w uniform on 0..100, ladder 1..64, tol 1e-9, t = 1e-4: the
+    reduced instance contains an optimal permutation (weight bit-exact), the
+    certificate bounds it, and with integer weights UB - W_B < 1 proves it."""
+    W = skgen.uniform_weights(64, 0, 100, seed=seed)
+    prm = sk.make_params([1, 2, 4, 8, 16, 32, 64], tol=1e-9, max_iters=20000, check_every=256,
+                         threshold=1e-4)
+    out = ctx.solve(dev(W), prm)
+    _, w_opt = oracle.optimum_int(W)
+    assert out["weight"] == w_opt
+    assert out["report"]["ub"] >= w_opt - 1e-9
+    assert out["log_gamma"] < 1.0
+    B = oracle.log_weights(W)
+    ub, vb = bars(out["potentials"], 64, 64)
+    assert abs(oracle.certificate(B, 64, ub, vb) - out["report"]["ub"]) < 1e-7
+
+
+def test_config_planted_n4096(ctx):
+    """n = 4096, w uniform on 0..1000 with w_i sigma(i) = 1050, ladder 1..32,
+    tol 1e-5: sigma recovered exactly, weight = 1050 n, residual (FP64) within
+    1e-5, support keeps sigma."""
+    n = 4096
+    W, sigma = skgen.planted(n, seed=11)
+    prm = sk.make_params([1, 2, 4, 8, 16, 32], tol=1e-5, max_iters=5000, check_every=64,
+                         threshold=1e-4)
+    out = ctx.solve(dev(W), prm)
+    assert out["weight"] == 1050 * n
+    assert np.array_equal(out["perm"], sigma)
+    rep = out["report"]
+    if rep["stages_capped"] == 0:
+        assert rep["residual_fp64"] <= 1e-5
+        assert rep["col_residual_fp64"] <= 1e-5
+    assert out["log_gamma"] < 1.0
+
+
+def test_config_dominant_sparse(ctx):
+    """Diagonally dominant 5% pattern (sentinel elsewhere): the identity is the
+    unique optimum; the reduced matrix keeps exactly the diagonal."""
+    n = 2048
+    W = skgen.dominant(n, seed=5)
+    prm = sk.make_params([1, 2, 4, 8, 16, 32], tol=1e-5, max_iters=5000, check_every=64,
+                         threshold=1e-4)
+    out = ctx.solve(dev(W), prm)
+    assert np.array_equal(out["perm"], np.arange(n))
+    assert out["weight"] == int(np.diag(W).astype(np.int64).sum())
+    assert out["nnz"] == n
+    # oracle on the same potentials: FP64 residual agrees with the report
+    B = oracle.log_weights(W)
+    ub, vb = bars(out["potentials"], n, 32)
+    r, c = oracle.sums(B, 32, ub, vb)
+    assert abs(np.abs(r - 1).max() - out["report"]["residual_fp64"]) < 1e-9
+
+
+def test_ladder_matches_oracle_iteration_counts(ctx):
+    """Same ladder and tolerance on the GPU and in the oracle: per-stage
+    iteration counts agree (up to one iteration where the FP32 residual sits
+    on the threshold) and the final matrices agree."""
+    n = 128
+    W, _ = skgen.planted(n, seed=4, lo=0, hi=100, bonus=5)
+    ladder = [1, 2, 4, 8]
+    prm = sk.make_params(ladder, tol=1e-4, max_iters=10000, check_every=32)
+    res = ctx.scale(dev(W), prm)
+    B = oracle.log_weights(W)
+    ub_o, vb_o, its, _ = oracle.scale_ladder(B, ladder, 1e-4, 10000)
+    its_g = res.report["iters_stage"][:len(ladder)]
+    assert all(abs(a - b) <= 1 for a, b in zip(its_g, its)), (its_g, its)
+    ub_g, vb_g = bars(res.potentials, n, ladder[-1])
+    Xg = oracle.scaled_matrix(B, ladder[-1], ub_g, vb_g)
+    Xo = oracle.scaled_matrix(B, ladder[-1], ub_o, vb_o)
+    assert np.abs(Xg - Xo).max() < 2e-4
+
+
+# ---------------------------------------------------------------- prune
+
+@pytest.mark.parametrize("n", [300, 512])
+def test_prune_matches_oracle_on_same_potentials(ctx, n):
+    W = skgen.uniform_weights(n, 0, 1000, seed=n)
+    p, t = 8, 1e-4
+    prm = sk.make_params([1, 2, 4, p], tol=1e-5, max_iters=3000, threshold=t)
+    res = ctx.scale(dev(W), prm)
+    row_ptr, col, w = ctx.prune(dev(W), res.potentials, prm)
+    rp, cc, ww = row_ptr.cpu().numpy(), col.cpu().numpy(), w.cpu().numpy()
+    mask = np.zeros((n, n), dtype=bool)
+    for i in range(n):
+        seg = cc[rp[i]:rp[i + 1]]
+        assert np.all(np.diff(seg) > 0)
+        mask[i, seg] = True
+    assert np.array_equal(ww, W[mask])
+    B = oracle.log_weights(W)
+    ub, vb = bars(res.potentials, n, p)
+    keep = oracle.prune(B, p, ub, vb, t)
+    band = np.abs(logx(B, p, ub, vb) - np.log(t)) < 1e-9
+    assert np.array_equal(mask[~band], keep[~band])
+
+
+# ---------------------------------------------------------------- batch, determinism
+
+def test_batch_equals_single_bitwise(ctx):
+    """Per-instance results do not depend on what else is in the batch."""
+    ns = [37, 64, 130, 256, 512, 1000]
+    Ws = [skgen.uniform_weights(n, 0, 1000, seed=90 + k) for k, n in enumerate(ns)]
+    prm = sk.make_params([1, 2, 4, 8, 16, 32], tol=1e-5, max_iters=400, check_every=16)
+    batch = ctx.scale_batch([dev(W) for W in Ws], prm)
+    for W, b in zip(Ws, batch):
+        single = ctx.scale(dev(W), prm)
+        assert torch.equal(single.potentials, b.potentials)
+        assert single.report["iters_stage"] == b.report["iters_stage"]
+
+
+def test_repeat_runs_bitwise(ctx):
+    W = skgen.uniform_weights(1024, 0, 1000, seed=1)
+    prm = sk.make_params([4, 8], tol=1e-5, max_iters=300)
+    a = ctx.scale(dev(W), prm)
+    b = ctx.scale(dev(W), prm)
+    assert torch.equal(a.potentials, b.potentials)
+
+
+# ---------------------------------------------------------------- edge cases
+
+def test_n1_and_n2(ctx):
+    out = ctx.solve(dev(np.array([[7]], dtype=np.int16)), sk.make_params([1, 2], tol=1e-9))
+    assert out["weight"] == 7 and list(out["perm"]) == [0]
+    A = np.array([[3, 1], [2, 5]], dtype=np.int16)
+    p = 1
+    res = ctx.scale(dev(A), sk.make_params([p], tol=1e-7, max_iters=1000))
+    ub, vb = bars(res.potentials, 2, p)
+    X = oracle.scaled_matrix(oracle.log_weights(A), p, ub, vb)
+    R = np.exp(p * (3 + 5 - 1 - 2) / 2)
+    assert abs(X[0, 0] - R / (1 + R)) < 1e-6
+
+
+def test_empty_row_and_column_report_no_support(ctx):
+    W = skgen.uniform_weights(16, 0, 10, seed=1)
+    W[3, :] = sk.SENTINEL
+    with pytest.raises(sk.SkError) as e:
+        ctx.scale(dev(W), sk.make_params([1, 2], tol=1e-6, max_iters=50))
+    assert e.value.status == sk.SK_ENOSUPPORT
+    W = skgen.uniform_weights(16, 0, 10, seed=1)
+    W[:, 5] = sk.SENTINEL
+    with pytest.raises(sk.SkError) as e:
+        ctx.scale(dev(W), sk.make_params([1, 2], tol=1e-6, max_iters=50))
+    assert e.value.status == sk.SK_ENOSUPPORT
+
+
+def test_cap_and_empty_reduction(ctx):
+    W = skgen.uniform_weights(64, 0, 1000, seed=2)
+    res = ctx.scale(dev(W), sk.make_params([32], tol=1e-12, max_iters=3))
+    assert res.status == sk.SK_ENOCONV and res.report["stages_capped"] == 1
+    prm = sk.make_params([32], tol=1e-12, max_iters=3, threshold=2.0)
+    row_ptr, col, w = ctx.prune(dev(W), res.potentials, prm)
+    assert int(row_ptr[-1]) == 0
+    with pytest.raises(sk.SkError) as e:
+        sk.solve_reduced(row_ptr.cpu().numpy(), col.cpu().numpy(), w.cpu().numpy(), 64)
+    assert e.value.status == sk.SK_EINFEASIBLE
+
+
+def test_cold_start_extreme_range_uses_exact_shift(ctx):
+    """p * (weight range) far beyond the float exponent range in the first
+    iteration: columns whose entries all underflow are recomputed with the
+    exact max shift, so the iterate still matches the oracle."""
+    n = 96
+    W = skgen.uniform_weights(n, 0, 1000, seed=8)
+    W[:, 7] = (W[:, 7] // 10).astype(np.int16)   # column 7 far below every row max
+    p = 4
+    prm = sk.make_params([p], tol=0.0, max_iters=3)
+    res = ctx.scale(dev(W), prm)
+    B = oracle.log_weights(W)
+    ub_g, vb_g = bars(res.potentials, n, p)
+    ub_o, vb_o, _, _ = oracle.sinkhorn(B, p, 0.0, 3)
+    Lg, Lo = logx(B, p, ub_g, vb_g), logx(B, p, ub_o, vb_o)
+    sig = Lo > np.log(1e-6)
+    assert np.abs(Lg - Lo)[sig].max() < 1e-4
+
+
+# ---------------------------------------------------------------- stored-K storages
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+@pytest.mark.parametrize("n", [300, 1024])
+def test_stored_k_path(ctx, storage, n):
+    """K stored in FP32 / BF16: the balanced matrix K a b is within the
+    tolerance in FP64, the optimal weight is exact, and the exact matrix with
+    the folded potentials is within the storage's rounding (BF16: 2^-9
+    relative per entry; FP32: 2^-24) of bistochastic."""
+    W, sigma = skgen.planted(n, seed=n + 7)
+    prm = sk.make_params([1, 2, 4, 8, 16, 32], tol=1e-5, max_iters=3000, check_every=32,
+                         threshold=1e-4, storage=storage)
+    out = ctx.solve(dev(W), prm)
+    rep = out["report"]
+    assert out["weight"] == 1050 * n and np.array_equal(out["perm"], sigma)
+    assert rep["absorbs"] >= 6
+    if rep["stages_capped"] == 0:
+        assert rep["residual_fp64"] <= 1e-5 and rep["col_residual_fp64"] <= 1.1e-5
+    bound = 2e-2 if storage == "bf16" else 1e-4
+    assert rep["residual_exact_fp64"] <= bound
+    # same potentials up to the storage rounding as the log-domain path
+    ref = ctx.scale(dev(W), sk.make_params([1, 2, 4, 8, 16, 32], tol=1e-5, max_iters=3000))
+    B = oracle.log_weights(W)
+    ub_k, vb_k = bars(out["potentials"], n, 32)
+    ub_r, vb_r = bars(ref.potentials, n, 32)
+    Xk = oracle.scaled_matrix(B, 32, ub_k, vb_k)
+    Xr = oracle.scaled_matrix(B, 32, ub_r, vb_r)
+    assert np.abs(Xk - Xr).max() < (2e-2 if storage == "bf16" else 1e-4)
