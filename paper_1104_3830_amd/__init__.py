@@ -276,6 +276,30 @@ class Context:
         self._check(st, "sk_scale_batch", ok=(SK_OK, SK_ENOCONV))
         return [Result(st, reps[k].as_dict(), pots[k]) for k in range(count)]
 
+    def submit(self, W, params):
+        """Queues a served request (W: int16 numpy array, host). Returns a ticket;
+        raises SkError(SK_EAGAIN) when the queue is full."""
+        W = np.ascontiguousarray(W, dtype=np.int16)
+        t = ctypes.c_uint64(0)
+        st = lib().sk_submit(self._ptr, W.ctypes.data, int(W.shape[0]), ctypes.byref(params),
+                             ctypes.byref(t))
+        self._check(st, "sk_submit")
+        return t.value
+
+    def poll(self, ticket, n):
+        """None while the request runs, else (status, perm, weight, report)."""
+        perm = np.empty(int(n), dtype=np.int32)
+        weight = ctypes.c_int64(0)
+        rep = Report()
+        st = lib().sk_poll(self._ptr, ctypes.c_uint64(ticket),
+                           perm.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                           ctypes.byref(weight), ctypes.byref(rep))
+        if st == SK_EAGAIN:
+            return None
+        if st == SK_EINVAL:
+            raise SkError(st, f"sk_poll: {self.last_error()}")
+        return st, perm, weight.value, rep.as_dict()
+
     def prune(self, W, potentials, params, capacity=None):
         """Reduced matrix as device tensors (row_ptr int64, col int32, w int16)."""
         torch = self.torch

@@ -36,7 +36,21 @@ struct Batch {
     int row_grid = 1, col_grid = 1;
 };
 
-struct Bump;
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Bump allocator over a region of the caller's arena.
+struct Bump {
+    char *base;
+    size_t cap, off = 0;
+    template <class T>
+    T *take(size_t count) {
+        size_t o = align_up(off, 256);
+        size_t need = sizeof(T) * count;
+        if (o + need > cap) return nullptr;
+        off = o + need;
+        return reinterpret_cast<T *>(base + o);
+    }
+};
 struct Server;
 
 enum KernelId {
@@ -84,6 +98,9 @@ namespace sk {
 
 sk_status fail(sk_ctx *ctx, sk_status st, const char *fmt, ...);
 sk_status check_params(sk_ctx *ctx, const sk_params *p);
+bool carve_instance(Bump &bump, const int16_t *W, int64_t pitch, int32_t n, const sk_params *prm,
+                    Inst &I);
+sk_status finish_tables(sk_ctx *ctx, Bump &bump, Batch &B);
 sk_status plan_batch(sk_ctx *ctx, Bump &bump, int count, const int16_t *const *W,
                      const int64_t *pitch, const int32_t *n, const sk_params *prm, Batch &B);
 sk_status upload_batch(sk_ctx *ctx, Batch &B);
@@ -98,6 +115,7 @@ sk_status copy_potentials_out(sk_ctx *ctx, Batch &B, int k, void *pot);
 sk_status scale_impl(sk_ctx *ctx, int count, const int16_t *const *W, const int32_t *n,
                      const sk_params *prm, void *const *pot, sk_report *reports);
 void serve_stop(sk_ctx *ctx);
+bool serving(const sk_ctx *ctx);
 hipError_t set_k_attributes();
 
 }  // namespace sk

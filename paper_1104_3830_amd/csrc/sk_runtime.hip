@@ -32,7 +32,6 @@ TilePlan plan_tiles(int32_t n, int vec8) {
     return t;
 }
 
-static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 size_t instance_bytes(int32_t n, int vec8, int storage) {
     TilePlan t = plan_tiles(n, vec8);
@@ -69,19 +68,7 @@ size_t shared_bytes(int32_t count, const int32_t *n) {
     return b;
 }
 
-// Bump allocator over a caller arena.
-struct Bump {
-    char *base;
-    size_t cap, off = 0;
-    template <class T>
-    T *take(size_t count) {
-        size_t o = align_up(off, 256);
-        size_t need = sizeof(T) * count;
-        if (o + need > cap) return nullptr;
-        off = o + need;
-        return reinterpret_cast<T *>(base + o);
-    }
-};
+
 
 const char *kKernelNames[KID_COUNT] = {"init", "row_sweep", "col_sweep", "iter_end",
                                        "check_rows", "check_cols", "prune_count", "scan",
@@ -273,60 +260,63 @@ sk_status sk::check_params(sk_ctx *ctx, const sk_params *p) {
 
 // ---------------------------------------------------------------- batch plan
 
-sk_status sk::plan_batch(sk_ctx *ctx, Bump &bump, int count, const int16_t *const *W,
-                         const int64_t *pitch, const int32_t *n, const sk_params *prm,
-                         Batch &B) {
-    B.count = count;
-    B.h_insts.assign(count, Inst{});
+// Fills the descriptor of one instance and carves its buffers from `bump`.
+bool sk::carve_instance(Bump &bump, const int16_t *W, int64_t pitch, int32_t nn,
+                        const sk_params *prm, Inst &I) {
+    I = Inst{};
+    I.W = W;
+    I.pitch = pitch;
+    I.n = nn;
+    I.vec8 = (nn % 8 == 0) && (pitch % 8 == 0) && ((uintptr_t)W % 16 == 0);
+    TilePlan t = plan_tiles(nn, I.vec8);
+    I.nseg = t.nseg;
+    I.seg_rows = t.seg_rows;
+    I.ntiles = t.ntiles;
+    I.tile_cols = t.tile_cols;
+    I.n_p = prm->n_p;
+    for (int s = 0; s < prm->n_p; ++s) I.ladder[s] = prm->p_ladder[s];
+    I.tol = (float)prm->tol;
+    I.max_iters = prm->max_iters_per_stage;
+    I.storage = prm->storage;
+    for (int b = 0; b < 2; ++b) {
+        I.F[b] = bump.take<int32_t>(nn);
+        I.phi[b] = bump.take<float>(nn);
+    }
+    I.G = bump.take<int32_t>(nn);
+    I.gam = bump.take<float>(nn);
+    I.colpart = bump.take<float>((size_t)t.nseg * nn);
+    I.tilecnt = bump.take<uint32_t>(t.ntiles);
+    I.rescue = bump.take<uint32_t>(nn);
+    I.ctl = bump.take<Ctl>(1);
+    if (!I.F[0] || !I.F[1] || !I.phi[0] || !I.phi[1] || !I.G || !I.gam || !I.colpart ||
+        !I.tilecnt || !I.rescue || !I.ctl)
+        return false;
+    I.kpitch = (nn + 7) / 8 * 8;
+    if (prm->storage != SK_W_I16) {
+        const size_t es = prm->storage == SK_K_BF16 ? 2 : 4;
+        I.K = bump.take<char>(es * (size_t)nn * I.kpitch);
+        I.a[0] = bump.take<float>(nn);
+        I.a[1] = bump.take<float>(nn);
+        I.b = bump.take<float>(nn);
+        if (!I.K || !I.a[0] || !I.a[1] || !I.b) return false;
+    }
+    return true;
+}
+
+// Work-unit tables, shared scratch and launch grids for the instances in B.h_insts.
+sk_status sk::finish_tables(sk_ctx *ctx, Bump &bump, Batch &B) {
+    B.count = (int)B.h_insts.size();
     B.h_rows.clear();
     B.h_cols.clear();
     B.nmax = 0;
-    for (int k = 0; k < count; ++k) {
-        Inst &I = B.h_insts[k];
-        const int nn = n[k];
-        I.W = W[k];
-        I.pitch = pitch[k];
-        I.n = nn;
-        I.vec8 = (nn % 8 == 0) && (I.pitch % 8 == 0) && ((uintptr_t)W[k] % 16 == 0);
-        TilePlan t = plan_tiles(nn, I.vec8);
-        I.nseg = t.nseg;
-        I.seg_rows = t.seg_rows;
-        I.ntiles = t.ntiles;
-        I.tile_cols = t.tile_cols;
-        I.n_p = prm->n_p;
-        for (int s = 0; s < prm->n_p; ++s) I.ladder[s] = prm->p_ladder[s];
-        I.tol = (float)prm->tol;
-        I.max_iters = prm->max_iters_per_stage;
-        I.storage = prm->storage;
-        for (int b = 0; b < 2; ++b) {
-            I.F[b] = bump.take<int32_t>(nn);
-            I.phi[b] = bump.take<float>(nn);
-        }
-        I.G = bump.take<int32_t>(nn);
-        I.gam = bump.take<float>(nn);
-        I.colpart = bump.take<float>((size_t)t.nseg * nn);
-        I.tilecnt = bump.take<uint32_t>(t.ntiles);
-        I.rescue = bump.take<uint32_t>(nn);
-        I.ctl = bump.take<Ctl>(1);
-        if (!I.F[0] || !I.F[1] || !I.phi[0] || !I.phi[1] || !I.G || !I.gam || !I.colpart ||
-            !I.tilecnt || !I.rescue || !I.ctl)
-            return fail(ctx, SK_ENOMEM, "arena too small for instance %d (n=%d)", k, nn);
-        I.kpitch = (nn + 7) / 8 * 8;
-        if (prm->storage != SK_W_I16) {
-            const size_t es = prm->storage == SK_K_BF16 ? 2 : 4;
-            I.K = bump.take<char>(es * (size_t)nn * I.kpitch);
-            I.a[0] = bump.take<float>(nn);
-            I.a[1] = bump.take<float>(nn);
-            I.b = bump.take<float>(nn);
-            if (!I.K || !I.a[0] || !I.a[1] || !I.b)
-                return fail(ctx, SK_ENOMEM, "arena too small for the stored K of instance %d", k);
-        }
-        for (int r = 0; r < nn; r += kRowWaves) B.h_rows.push_back(RowUnit{k, r});
-        for (int s = 0; s < t.nseg; ++s)
-            for (int tt = 0; tt < t.ntiles; ++tt) B.h_cols.push_back(ColUnit{k, tt, s, 0});
-        B.nmax = std::max(B.nmax, nn);
+    for (int k = 0; k < B.count; ++k) {
+        const Inst &I = B.h_insts[k];
+        for (int r = 0; r < I.n; r += kRowWaves) B.h_rows.push_back(RowUnit{k, r});
+        for (int s = 0; s < I.nseg; ++s)
+            for (int tt = 0; tt < I.ntiles; ++tt) B.h_cols.push_back(ColUnit{k, tt, s, 0});
+        B.nmax = std::max(B.nmax, I.n);
     }
-    B.d_insts = bump.take<Inst>(count);
+    B.d_insts = bump.take<Inst>(B.count);
     B.d_rows = bump.take<RowUnit>(B.h_rows.size());
     B.d_cols = bump.take<ColUnit>(B.h_cols.size());
     B.d_rsum = bump.take<double>(B.nmax);
@@ -340,9 +330,19 @@ sk_status sk::plan_batch(sk_ctx *ctx, Bump &bump, int count, const int16_t *cons
     const int per_cu = lds <= 32768 ? 2 : 1;
     B.row_lds = lds;
     B.row_lds_k = sizeof(float) * (size_t)((B.nmax + 7) / 8 * 8);
-    B.row_grid = (int)std::min<size_t>(B.h_rows.size(), (size_t)ctx->num_cus * per_cu);
-    B.col_grid = (int)std::min<size_t>(B.h_cols.size(), (size_t)ctx->num_cus * 8);
+    B.row_grid = (int)std::max<size_t>(1, std::min<size_t>(B.h_rows.size(), (size_t)ctx->num_cus * per_cu));
+    B.col_grid = (int)std::max<size_t>(1, std::min<size_t>(B.h_cols.size(), (size_t)ctx->num_cus * 8));
     return SK_OK;
+}
+
+sk_status sk::plan_batch(sk_ctx *ctx, Bump &bump, int count, const int16_t *const *W,
+                         const int64_t *pitch, const int32_t *n, const sk_params *prm,
+                         Batch &B) {
+    B.h_insts.assign(count, Inst{});
+    for (int k = 0; k < count; ++k)
+        if (!carve_instance(bump, W[k], pitch[k], n[k], prm, B.h_insts[k]))
+            return fail(ctx, SK_ENOMEM, "arena too small for instance %d (n=%d)", k, n[k]);
+    return finish_tables(ctx, bump, B);
 }
 
 sk_status sk::upload_batch(sk_ctx *ctx, Batch &B) {
@@ -519,6 +519,7 @@ static sk_status check_range(sk_ctx *ctx, const sk_params *prm) {
 sk_status sk::scale_impl(sk_ctx *ctx, int count, const int16_t *const *W, const int32_t *n,
                          const sk_params *prm, void *const *pot, sk_report *reports) {
     auto t0 = std::chrono::steady_clock::now();
+    if (serving(ctx)) return fail(ctx, SK_EINVAL, "context is serving; blocking calls are disabled");
     ctx->absorbs = 0;
     sk_status st = check_params(ctx, prm);
     if (st != SK_OK) return st;
@@ -597,6 +598,7 @@ sk_status sk_prune(sk_ctx *ctx, const int16_t *W, int32_t n, const void *potenti
                    const sk_params *params, sk_csr *csr) {
     if (!ctx) return SK_EINVAL;
     std::lock_guard<std::mutex> g(ctx->mu);
+    if (serving(ctx)) return fail(ctx, SK_EINVAL, "context is serving; blocking calls are disabled");
     sk_status st = check_params(ctx, params);
     if (st != SK_OK) return st;
     if (!W || !potentials || !csr || !csr->row_ptr)

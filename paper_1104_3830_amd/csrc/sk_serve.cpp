@@ -1,15 +1,459 @@
-// Served path (continuous batching): placeholder until the scheduler lands.
+// Served path: continuous batching of assignment solves on one GPU.
+//
+// sk_submit copies a request's W into pinned staging and queues it. A serving
+// thread repeats a tick:
+//   1. admit queued requests (FIFO) while their device footprint (W plus the
+//      instance state) fits in the free part of the context arena;
+//   2. copy the admitted W to the device and cold-start them;
+//   3. run a block of Sinkhorn iterations over every admitted instance at
+//      once (one row-sweep launch and one column-sweep launch per iteration
+//      cover all of them; each instance follows its own p ladder, tolerance
+//      and cap on the device);
+//   4. retire instances whose ladder finished: FP64 recheck and certificate,
+//      reduction to CSR on the device, copy of the CSR to the host, release of
+//      the device region; the exact solve of the reduced instance runs on a
+//      host thread pool while the GPU keeps sweeping the others.
+// Every per-instance computation depends only on that instance (work units,
+// tile plan and reduction order are functions of n), so a request's result is
+// the same alone and in any mix.
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
 #include "sk_runtime.h"
 
 namespace sk {
-void serve_stop(sk_ctx *) {}
+
+// First-fit allocator over [0, cap) of the arena, 256-byte granules, coalescing.
+struct RangeAlloc {
+    std::map<size_t, size_t> free_;
+    void init(size_t base, size_t cap) {
+        free_.clear();
+        if (cap > base) free_[base] = cap - base;
+    }
+    bool alloc(size_t len, size_t &off) {
+        len = align_up(len, 256);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= len) {
+                off = it->first;
+                const size_t rest = it->second - len;
+                free_.erase(it);
+                if (rest) free_[off + len] = rest;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t len) {
+        len = align_up(len, 256);
+        auto it = free_.emplace(off, len).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+struct Request {
+    uint64_t id = 0;
+    int32_t n = 0;
+    sk_params prm{};
+    int16_t *staging = nullptr;  // pinned host copy of W
+    size_t off = 0, len = 0;     // device region in the arena
+    Inst inst{};
+    int phase = 0;               // 0 queued, 1 active, 2 solving, 3 done
+    sk_status status = SK_OK;
+    std::vector<int32_t> perm;
+    int64_t weight = 0;
+    sk_report rep{};
+    std::vector<int64_t> rp;
+    std::vector<int32_t> col;
+    std::vector<int16_t> w;
+    std::chrono::steady_clock::time_point t_submit;
+};
+
+struct Server {
+    sk_ctx *ctx = nullptr;
+    std::thread th;
+    std::vector<std::thread> solvers;
+    std::mutex mu;
+    std::condition_variable cv, cv_solve;
+    bool stop = false;
+    uint64_t next_id = 1;
+    std::deque<Request *> queue;
+    std::vector<Request *> active;
+    std::unordered_map<uint64_t, Request *> reqs;
+    std::deque<Request *> solve_q;
+    RangeAlloc ralloc;
+    size_t tables_len = 0;
+    Batch B;
+    std::vector<RowUnit> init_units;
+    RowUnit *d_init_units = nullptr;
+    std::string error;
+    int iters_per_tick = 4;
+};
+
+static const size_t kTablesBytes = size_t(64) << 20;
+
+static size_t footprint(int32_t n) {
+    return align_up((size_t)n * n * 2, 256) + instance_bytes(n, (n % 8) == 0, SK_W_I16) + 4096;
+}
+
+static void solver_loop(Server *S) {
+    for (;;) {
+        Request *r = nullptr;
+        {
+            std::unique_lock<std::mutex> g(S->mu);
+            S->cv_solve.wait(g, [&] { return S->stop || !S->solve_q.empty(); });
+            if (S->solve_q.empty()) return;
+            r = S->solve_q.front();
+            S->solve_q.pop_front();
+        }
+        sk_csr csr{r->n, (int64_t)r->col.size(), r->rp.data(), r->col.data(), r->w.data()};
+        r->perm.assign(r->n, -1);
+        int64_t weight = 0;
+        sk_status st = sk_solve_reduced(&csr, r->perm.data(), &weight);
+        {
+            std::lock_guard<std::mutex> g(S->mu);
+            r->weight = weight;
+            if (st != SK_OK) r->status = st;
+            r->rep.seconds =
+                std::chrono::duration<double>(std::chrono::steady_clock::now() - r->t_submit).count();
+            r->rp.clear();
+            r->rp.shrink_to_fit();
+            r->col.clear();
+            r->col.shrink_to_fit();
+            r->w.clear();
+            r->w.shrink_to_fit();
+            r->phase = 3;
+        }
+    }
+}
+
+// Rebuilds the batch tables for the active set (serving thread only).
+static sk_status rebuild(Server *S) {
+    sk_ctx *ctx = S->ctx;
+    S->B.h_insts.clear();
+    for (Request *r : S->active) S->B.h_insts.push_back(r->inst);
+    Bump tb{ctx->arena, S->tables_len};
+    // the first part of the tables region holds the init-unit table
+    S->d_init_units = tb.take<RowUnit>(kMaxN / kRowWaves * 64);
+    sk_status st = finish_tables(ctx, tb, S->B);
+    if (st != SK_OK) return st;
+    return upload_batch(ctx, S->B);
+}
+
+// Retires instance k of the batch: report, FP64 check, CSR to the host.
+static sk_status retire(Server *S, int k, Request *r) {
+    sk_ctx *ctx = S->ctx;
+    Batch &B = S->B;
+    const Ctl &c = ctx->h_ctl[k];
+    memset(&r->rep, 0, sizeof r->rep);
+    fill_report(c, &r->rep);
+    if (c.err & (ERR_EMPTY_ROW | ERR_EMPTY_COL)) {
+        r->status = SK_ENOSUPPORT;
+        return SK_OK;
+    }
+    if (c.capped) r->status = SK_ENOCONV;
+    sk_status st = check_fp64(ctx, B, k, &r->rep);
+    if (st != SK_OK) return st;
+    const int n = r->n;
+    size_t first = 0;
+    while (first < B.h_rows.size() && B.h_rows[first].inst != k) ++first;
+    const int nunits = (n + kRowWaves - 1) / kRowWaves;
+    const int grid = std::min(nunits, ctx->num_cus * 2);
+    const double logt = std::log(r->prm.threshold);
+    // row_ptr, col and w are transient allocations from the free arena space
+    size_t rp_off = 0;
+    const size_t rp_len = sizeof(int64_t) * (n + 1);
+    bool have_rp;
+    {
+        std::lock_guard<std::mutex> g(S->mu);
+        have_rp = S->ralloc.alloc(rp_len, rp_off);
+    }
+    if (!have_rp) return fail(ctx, SK_ENOMEM, "no device memory for a CSR row pointer");
+    int64_t *d_rp = (int64_t *)(ctx->arena + rp_off);
+    hipError_t e = launch_prune_count(B.d_insts, B.d_rows + first, nunits, grid, logt, B.d_counts,
+                                      ctx->stream);
+    if (e == hipSuccess) e = launch_scan(B.d_counts, d_rp, n, ctx->stream);
+    r->rp.resize(n + 1);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(r->rp.data(), d_rp, rp_len, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    const int64_t nnz = r->rp[n];
+    size_t cw_off = 0;
+    const size_t col_bytes = align_up(sizeof(int32_t) * (size_t)std::max<int64_t>(nnz, 1), 256);
+    const size_t cw_len = col_bytes + sizeof(int16_t) * (size_t)std::max<int64_t>(nnz, 1);
+    bool have_cw = false;
+    if (e == hipSuccess) {
+        std::lock_guard<std::mutex> g(S->mu);
+        have_cw = S->ralloc.alloc(cw_len, cw_off);
+    }
+    if (e == hipSuccess && have_cw && nnz > 0) {
+        int32_t *d_col = (int32_t *)(ctx->arena + cw_off);
+        int16_t *d_w = (int16_t *)(ctx->arena + cw_off + col_bytes);
+        {
+            r->col.resize(nnz);
+            r->w.resize(nnz);
+            e = launch_prune_fill(B.d_insts, B.d_rows + first, nunits, grid, logt, d_rp, d_col, d_w,
+                                  ctx->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(r->col.data(), d_col, sizeof(int32_t) * nnz,
+                                   hipMemcpyDeviceToHost, ctx->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(r->w.data(), d_w, sizeof(int16_t) * nnz, hipMemcpyDeviceToHost,
+                                   ctx->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        }
+    } else if (e == hipSuccess && !have_cw) {
+        r->status = SK_ENOMEM;
+    }
+    {
+        std::lock_guard<std::mutex> g(S->mu);
+        S->ralloc.release(rp_off, rp_len);
+        if (have_cw) S->ralloc.release(cw_off, cw_len);
+    }
+    if (e != hipSuccess) return fail(ctx, SK_EDEVICE, "retire: %s", hipGetErrorString(e));
+    r->rep.nnz_kept = nnz;
+    return SK_OK;
+}
+
+static void serve_loop(Server *S) {
+    sk_ctx *ctx = S->ctx;
+    (void)hipSetDevice(ctx->device);
+    bool dirty = false;
+    for (;;) {
+        std::vector<Request *> fresh;
+        {
+            std::unique_lock<std::mutex> g(S->mu);
+            if (S->stop) break;
+            while (!S->queue.empty() && S->active.size() + fresh.size() < (size_t)kMaxBatch) {
+                Request *r = S->queue.front();
+                size_t off;
+                if (!S->ralloc.alloc(r->len, off)) break;
+                r->off = off;
+                Bump bump{ctx->arena + off, r->len};
+                int16_t *dW = bump.take<int16_t>((size_t)r->n * r->n);
+                carve_instance(bump, dW, r->n, r->n, &r->prm, r->inst);
+                r->phase = 1;
+                S->queue.pop_front();
+                fresh.push_back(r);
+            }
+            if (S->active.empty() && fresh.empty()) {
+                S->cv.wait_for(g, std::chrono::milliseconds(1));
+                continue;
+            }
+        }
+        sk_status st = SK_OK;
+        hipError_t e = hipSuccess;
+        if (!fresh.empty()) {
+            for (Request *r : fresh)
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync((void *)r->inst.W, r->staging, (size_t)r->n * r->n * 2,
+                                       hipMemcpyHostToDevice, ctx->stream);
+            const int base = (int)S->active.size();
+            for (Request *r : fresh) S->active.push_back(r);
+            st = rebuild(S);
+            // cold start of the new instances only
+            S->init_units.clear();
+            for (size_t q = 0; q < fresh.size(); ++q) {
+                const int k = base + (int)q;
+                Ctl c;
+                memset(&c, 0, sizeof c);
+                c.state = ST_RUNNING;
+                c.p = fresh[q]->prm.p_ladder[0];
+                c.last_res = INFINITY;
+                ctx->h_ctl[k] = c;
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(S->B.h_insts[k].ctl, &ctx->h_ctl[k], sizeof(Ctl),
+                                       hipMemcpyHostToDevice, ctx->stream);
+                if (e == hipSuccess)
+                    e = hipMemsetAsync(S->B.h_insts[k].tilecnt, 0,
+                                       sizeof(uint32_t) * S->B.h_insts[k].ntiles, ctx->stream);
+                for (int r0 = 0; r0 < fresh[q]->n; r0 += kRowWaves)
+                    S->init_units.push_back(RowUnit{k, r0});
+            }
+            size_t done = 0;
+            while (e == hipSuccess && st == SK_OK && done < S->init_units.size()) {
+                const size_t chunk = std::min<size_t>(S->init_units.size() - done,
+                                                      (size_t)kMaxN / kRowWaves * 64);
+                e = hipMemcpyAsync(S->d_init_units, S->init_units.data() + done,
+                                   sizeof(RowUnit) * chunk, hipMemcpyHostToDevice, ctx->stream);
+                if (e == hipSuccess)
+                    e = launch_init(S->B.d_insts, S->d_init_units, (int)chunk,
+                                    (int)std::min<size_t>(chunk, (size_t)ctx->num_cus * 2), 1,
+                                    ctx->stream);
+                if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+                done += chunk;
+            }
+            for (Request *r : fresh) {
+                (void)hipHostFree(r->staging);
+                r->staging = nullptr;
+            }
+            dirty = false;
+        } else if (dirty) {
+            st = rebuild(S);
+            dirty = false;
+        }
+        for (int it = 0; it < S->iters_per_tick && st == SK_OK && e == hipSuccess; ++it)
+            st = iterate_i16(ctx, S->B);
+        if (st == SK_OK && e == hipSuccess) st = read_ctl(ctx, S->B);
+        if (st != SK_OK || e != hipSuccess) {
+            std::lock_guard<std::mutex> g(S->mu);
+            S->error = e != hipSuccess ? hipGetErrorString(e) : ctx->err;
+            for (Request *r : S->active) {
+                r->status = SK_EDEVICE;
+                r->phase = 3;
+            }
+            S->active.clear();
+            break;
+        }
+        // retire finished instances
+        std::vector<Request *> keep;
+        for (int k = 0; k < (int)S->active.size(); ++k) {
+            Request *r = S->active[k];
+            if (ctx->h_ctl[k].state == ST_RUNNING) {
+                keep.push_back(r);
+                continue;
+            }
+            st = retire(S, k, r);
+            std::lock_guard<std::mutex> g(S->mu);
+            S->ralloc.release(r->off, r->len);
+            if (st != SK_OK || r->status == SK_ENOSUPPORT || r->status == SK_ENOMEM) {
+                if (st != SK_OK) r->status = SK_EDEVICE;
+                r->phase = 3;
+            } else {
+                r->phase = 2;
+                S->solve_q.push_back(r);
+                S->cv_solve.notify_one();
+            }
+            dirty = true;
+        }
+        if (dirty) {
+            std::lock_guard<std::mutex> g(S->mu);
+            S->active.swap(keep);
+        }
+    }
+}
+
+static Server *ensure_server(sk_ctx *ctx) {
+    if (ctx->server) return ctx->server;
+    Server *S = new Server();
+    S->ctx = ctx;
+    S->tables_len = std::min(kTablesBytes, ctx->arena_bytes / 4);
+    S->ralloc.init(align_up(S->tables_len, 256), ctx->arena_bytes);
+    const char *env = getenv("SK_SERVE_ITERS_PER_TICK");
+    if (env && atoi(env) > 0) S->iters_per_tick = atoi(env);
+    ctx->server = S;
+    S->th = std::thread(serve_loop, S);
+    for (int k = 0; k < 4; ++k) S->solvers.emplace_back(solver_loop, S);
+    return S;
+}
+
+void serve_stop(sk_ctx *ctx) {
+    Server *S = ctx->server;
+    if (!S) return;
+    {
+        std::lock_guard<std::mutex> g(S->mu);
+        S->stop = true;
+    }
+    S->cv.notify_all();
+    S->cv_solve.notify_all();
+    if (S->th.joinable()) S->th.join();
+    for (auto &t : S->solvers)
+        if (t.joinable()) t.join();
+    for (auto &kv : S->reqs) {
+        if (kv.second->staging) (void)hipHostFree(kv.second->staging);
+        delete kv.second;
+    }
+    delete S;
+    ctx->server = nullptr;
+}
+
+bool serving(const sk_ctx *ctx) { return ctx->server != nullptr; }
+
 }  // namespace sk
 
-extern "C" sk_status sk_submit(sk_ctx *ctx, const int16_t *, int32_t, const sk_params *, uint64_t *) {
+using namespace sk;
+
+extern "C" sk_status sk_submit(sk_ctx *ctx, const int16_t *W_host, int32_t n, const sk_params *params,
+                               uint64_t *ticket) {
     if (!ctx) return SK_EINVAL;
-    return sk::fail(ctx, SK_EINVAL, "serving is not available in this build");
+    if (!W_host || !ticket) return fail(ctx, SK_EINVAL, "null argument");
+    sk_status st = check_params(ctx, params);
+    if (st != SK_OK) return st;
+    if (params->storage != SK_W_I16) return fail(ctx, SK_EINVAL, "served path sweeps int16 W");
+    if (n < 1 || n > kMaxN) return fail(ctx, SK_EINVAL, "n = %d outside [1, %d]", n, kMaxN);
+    if (!(params->threshold > 0.0)) return fail(ctx, SK_EINVAL, "threshold must be > 0");
+    std::lock_guard<std::mutex> call(ctx->mu);
+    Server *S = ensure_server(ctx);
+    const size_t len = footprint(n);
+    if (len + S->tables_len > ctx->arena_bytes)
+        return fail(ctx, SK_ENOMEM, "n = %d can never fit in the arena", n);
+    Request *r = new Request();
+    r->n = n;
+    r->prm = *params;
+    r->len = len;
+    r->t_submit = std::chrono::steady_clock::now();
+    if (hipHostMalloc((void **)&r->staging, (size_t)n * n * 2, hipHostMallocDefault) != hipSuccess) {
+        delete r;
+        return fail(ctx, SK_ENOMEM, "pinned staging allocation failed");
+    }
+    memcpy(r->staging, W_host, (size_t)n * n * 2);
+    {
+        std::lock_guard<std::mutex> g(S->mu);
+        if (!S->error.empty()) {
+            (void)hipHostFree(r->staging);
+            delete r;
+            return fail(ctx, SK_EDEVICE, "serving thread stopped: %s", S->error.c_str());
+        }
+        if (S->queue.size() >= (size_t)kMaxBatch) {
+            (void)hipHostFree(r->staging);
+            delete r;
+            return SK_EAGAIN;
+        }
+        r->id = S->next_id++;
+        S->queue.push_back(r);
+        S->reqs[r->id] = r;
+        *ticket = r->id;
+    }
+    S->cv.notify_one();
+    return SK_OK;
 }
-extern "C" sk_status sk_poll(sk_ctx *ctx, uint64_t, int32_t *, int64_t *, sk_report *) {
+
+extern "C" sk_status sk_poll(sk_ctx *ctx, uint64_t ticket, int32_t *perm, int64_t *weight,
+                             sk_report *report) {
     if (!ctx) return SK_EINVAL;
-    return sk::fail(ctx, SK_EINVAL, "serving is not available in this build");
+    Server *S = ctx->server;
+    if (!S) return fail(ctx, SK_EINVAL, "no request was submitted");
+    Request *r = nullptr;
+    {
+        std::lock_guard<std::mutex> g(S->mu);
+        auto it = S->reqs.find(ticket);
+        if (it == S->reqs.end()) return SK_EINVAL;
+        r = it->second;
+        if (r->phase != 3) return SK_EAGAIN;
+        S->reqs.erase(it);
+    }
+    if (perm && r->perm.size() == (size_t)r->n) memcpy(perm, r->perm.data(), sizeof(int32_t) * r->n);
+    if (weight) *weight = r->weight;
+    if (report) *report = r->rep;
+    const sk_status st = r->status;
+    delete r;
+    return st;
 }

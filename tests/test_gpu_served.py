@@ -1,0 +1,87 @@
+"""GPU tests of the served path (continuous batching through sk_submit/sk_poll)."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1104_3830_amd as sk
+import skgen
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+LADDER = [1, 2, 4, 8, 16, 32]
+
+
+def wait_all(ctx, tickets, ns, timeout=120.0):
+    out = {}
+    t0 = time.time()
+    while len(out) < len(tickets):
+        for t, n in zip(tickets, ns):
+            if t in out:
+                continue
+            r = ctx.poll(t, n)
+            if r is not None:
+                out[t] = r
+        if time.time() - t0 > timeout:
+            raise TimeoutError(f"{len(out)}/{len(tickets)} requests finished")
+        time.sleep(0.002)
+    return [out[t] for t in tickets]
+
+
+def test_served_results_equal_alone_and_in_the_mix():
+    """Each request's result (permutation, weight, certificate, iteration
+    counts) is bitwise the same when served in a mix as when solved alone."""
+    ns = [64, 100, 256, 333, 512, 1000, 2048]
+    insts = [skgen.planted(n, seed=500 + k) for k, n in enumerate(ns)]
+    prm = sk.make_params(LADDER, tol=1e-5, max_iters=2000, threshold=1e-4)
+    alone = sk.Context(0)
+    ref = [alone.solve(torch.from_numpy(W).cuda(), prm) for W, _ in insts]
+    alone.close()
+    srv = sk.Context(0, arena_bytes=1 << 30)
+    tickets = [srv.submit(W, prm) for W, _ in insts]
+    res = wait_all(srv, tickets, ns)
+    srv.close()
+    for (W, sigma), r, (st, perm, weight, rep) in zip(insts, ref, res):
+        assert st in (sk.SK_OK, sk.SK_ENOCONV)
+        assert weight == r["weight"] == 1050 * W.shape[0]
+        assert np.array_equal(perm, r["perm"]) and np.array_equal(perm, sigma)
+        assert rep["ub"] == r["report"]["ub"]
+        assert rep["iters_stage"] == r["report"]["iters_stage"]
+        assert rep["residual_fp64"] == r["report"]["residual_fp64"]
+        assert rep["nnz_kept"] == r["nnz"]
+
+
+def test_served_admission_with_small_arena():
+    """An arena that holds about one instance at a time still serves every
+    request (admission waits for memory to free up)."""
+    ns = [512, 512, 400, 512]
+    insts = [skgen.uniform_weights(n, 0, 1000, seed=20 + k) for k, n in enumerate(ns)]
+    prm = sk.make_params(LADDER, tol=1e-5, max_iters=300, threshold=1e-4)
+    need = int(sk.lib().sk_arena_bytes(512, 0)) + 512 * 512 * 2
+    srv = sk.Context(0, arena_bytes=(64 << 20) * 4 // 4 + 2 * need)
+    tickets = [srv.submit(W, prm) for W in insts]
+    res = wait_all(srv, tickets, ns)
+    srv.close()
+    for W, (st, perm, weight, rep) in zip(insts, res):
+        assert st in (sk.SK_OK, sk.SK_ENOCONV, sk.SK_EINFEASIBLE)
+        if st != sk.SK_EINFEASIBLE:
+            _, w_opt = oracle.optimum_int(W)
+            assert weight <= w_opt
+            assert rep["ub"] >= w_opt - 1e-6
+
+
+def test_served_bad_request_does_not_block_others():
+    good = [skgen.planted(128, seed=k)[0] for k in range(3)]
+    bad = skgen.uniform_weights(128, 0, 10, seed=9)
+    bad[5, :] = sk.SENTINEL
+    prm = sk.make_params(LADDER, tol=1e-5, max_iters=2000, threshold=1e-4)
+    srv = sk.Context(0, arena_bytes=256 << 20)
+    tickets = [srv.submit(good[0], prm), srv.submit(bad, prm), srv.submit(good[1], prm),
+               srv.submit(good[2], prm)]
+    res = wait_all(srv, tickets, [128] * 4)
+    srv.close()
+    assert res[1][0] == sk.SK_ENOSUPPORT
+    for r in (res[0], res[2], res[3]):
+        assert r[0] in (sk.SK_OK, sk.SK_ENOCONV) and r[2] == 1050 * 128
