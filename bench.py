@@ -18,6 +18,17 @@ launch on the library's stream during the timed region.
 cpu_baseline: the FP64 oracle, as it stands, timed on this host's cores on a
 bounded sample of the same workload (a few full iterations at n = 16384),
 converted to the same unit.
+
+batched: 512 independent instances, n log-uniform on [32, 1024], weights
+uniform 0..1000; sk_scale_batch (one launch per sweep across all instances)
+against 512 sequential sk_scale calls with the same parameters.
+
+served: Poisson arrivals of planted instances with n log-uniform on
+[64, 8192], tolerance 1e-5; requests through sk_submit/sk_poll (continuous
+batching) against a plain FIFO loop that solves one request at a time
+(scale, prune, exact solve) on the same GPU; solves/s and p50/p99 latency
+(completion minus arrival) for both, arrival rate set from the FIFO loop's
+measured capacity.
 """
 from __future__ import annotations
 
@@ -35,8 +46,9 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "Sinkhorn sweep HBM GB/s at n=16384; served solves/s + p99 vs plain loop"
 ELEM_BYTES = {"i16": 2, "bf16": 2, "f32": 4}
-SWEEP_KERNELS = {"i16": ("row_sweep", "col_sweep"), "bf16": ("row_sweep_k", "col_sweep_k"),
-                 "f32": ("row_sweep_k", "col_sweep_k")}
+SWEEP_KERNELS = {"i16": ("row_sweep", "col_sweep", "fused"),
+                 "bf16": ("row_sweep_k", "col_sweep_k", "fused"),
+                 "f32": ("row_sweep_k", "col_sweep_k", "fused")}
 
 
 def parse():
@@ -53,7 +65,147 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--served-requests", type=int, default=160)
+    ap.add_argument("--served-load", type=float, default=1.5,
+                    help="arrival rate as a multiple of the FIFO loop's capacity")
+    ap.add_argument("--fused", action="store_true",
+                    help="single-pass iteration (one matrix read per iteration)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy 5 times (the reference "
+                         "kernel for scaling HBM byte counters)")
     return ap.parse_args()
+
+
+def calibrate_copy():
+    """A plain copy kernel of known size: 1 GiB read + 1 GiB written per launch."""
+    import torch
+    src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    src.fill_(1)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / 5
+    print(json.dumps({"copy_bytes": 1 << 30, "launches": 5, "avg_ms": round(el * 1e3, 3),
+                      "gbs_read_plus_write": round(2 * (1 << 30) / el / 1e9, 1)}), flush=True)
+
+
+def batched_leg(sk, torch, seed=1):
+    """512 ragged instances: one batched run vs 512 sequential runs."""
+    import skgen
+    ns = skgen.sizes_loguniform(512, 32, 1024, seed)
+    Ws = [torch.from_numpy(skgen.uniform_weights(int(n), 0, 1000, seed * 100003 + k)).cuda()
+          for k, n in enumerate(ns)]
+    prm = sk.make_params([1, 2, 4, 8, 16, 32], tol=1e-5, max_iters=500, check_every=32)
+    ctx = sk.Context(0)
+    ctx.scale_batch(Ws[:8], prm)  # warm-up
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    res_b = ctx.scale_batch(Ws, prm)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    t0 = time.perf_counter()
+    res_s = [ctx.scale(W, prm) for W in Ws]
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    same = all(torch.equal(a.potentials, b.potentials) for a, b in zip(res_b, res_s))
+    ctx.close()
+    elems = int(sum(int(n) * int(n) for n in ns))
+    return {"instances": 512, "n_range": [32, 1024], "matrix_MB": round(elems * 2 / 1e6, 1),
+            "batched_solves_per_s": round(512 / tb, 1), "sequential_solves_per_s": round(512 / ts, 1),
+            "speedup": round(ts / tb, 2), "batched_s": round(tb, 3), "sequential_s": round(ts, 3),
+            "iters_total": int(sum(r.report["iters_total"] for r in res_b)),
+            "iters_max": int(max(r.report["iters_total"] for r in res_b)),
+            "identical_to_sequential": bool(same),
+            "kernels": {k: {"launches": v[0], "avg_us": round(v[1] / max(v[0], 1) * 1e3, 2)}
+                        for k, v in prof.items()}}
+
+
+def served_leg(sk, torch, n_requests, load, seed=2):
+    """Poisson arrivals; continuous batching vs a FIFO one-at-a-time loop."""
+    import skgen
+    # a pool of planted instances with log-uniform sizes; requests draw from it
+    pool_n = skgen.sizes_loguniform(32, 64, 8192, seed)
+    pool = [skgen.planted(int(n), seed * 100003 + k) for k, n in enumerate(pool_n)]
+    pick = skgen.bounded(skgen.stream(seed, 99, n_requests), len(pool)).astype(np.int64)
+    reqs = [pool[int(k)] for k in pick]
+    prm = sk.make_params([1, 2, 4, 8, 16, 32], tol=1e-5, max_iters=2000, check_every=32,
+                         threshold=1e-4)
+    fifo = sk.Context(0)
+
+    def fifo_one(W):
+        # a request arrives as host memory, like sk_submit's input
+        return fifo.solve(torch.from_numpy(W).cuda(), prm)
+
+    for W, _ in pool[:4]:
+        fifo_one(W)  # warm-up
+    # FIFO capacity: back-to-back service time
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in pick[: min(48, n_requests)]:
+        fifo_one(pool[int(k)][0])
+    torch.cuda.synchronize()
+    mu = min(48, n_requests) / (time.perf_counter() - t0)
+    lam = load * mu
+    arrivals = skgen.poisson_arrivals(lam, n_requests, seed)
+    # FIFO loop on the arrival trace (live)
+    lat_f = []
+    ok_f = 0
+    t_start = time.perf_counter()
+    for k, a in zip(pick, arrivals):
+        now = time.perf_counter() - t_start
+        if now < a:
+            time.sleep(a - now)
+        W = pool[int(k)][0]
+        out = fifo_one(W)
+        ok_f += out["weight"] == 1050 * W.shape[0]
+        lat_f.append(time.perf_counter() - t_start - a)
+    span_f = time.perf_counter() - t_start
+    fifo.close()
+    # served loop on the same trace
+    srv = sk.Context(0, arena_bytes=4 << 30)
+    # warm-up request
+    t = srv.submit(pool[0][0], prm)
+    while srv.poll(t, pool[0][0].shape[0]) is None:
+        time.sleep(0.0005)
+    pending = {}
+    lat_s = [None] * n_requests
+    ok_s = 0
+    t_start = time.perf_counter()
+    nxt = 0
+    while nxt < n_requests or pending:
+        now = time.perf_counter() - t_start
+        while nxt < n_requests and arrivals[nxt] <= now:
+            W, _ = reqs[nxt]
+            pending[srv.submit(W, prm)] = (nxt, W.shape[0])
+            nxt += 1
+        for tk in list(pending):
+            idx, n = pending[tk]
+            r = srv.poll(tk, n)
+            if r is not None:
+                lat_s[idx] = time.perf_counter() - t_start - arrivals[idx]
+                ok_s += r[2] == 1050 * n
+                del pending[tk]
+        time.sleep(0.0002)
+    span_s = time.perf_counter() - t_start
+    srv.close()
+    q = lambda v, p: float(np.percentile(np.asarray(v), p))
+    return {"requests": n_requests, "n_range": [64, 8192], "pool_instances": len(pool),
+            "fifo_capacity_solves_per_s": round(mu, 2), "arrival_rate_per_s": round(lam, 2),
+            "served": {"solves_per_s": round(n_requests / span_s, 2),
+                       "p50_ms": round(q(lat_s, 50) * 1e3, 2), "p99_ms": round(q(lat_s, 99) * 1e3, 2),
+                       "optimal": ok_s},
+            "fifo": {"solves_per_s": round(n_requests / span_f, 2),
+                     "p50_ms": round(q(lat_f, 50) * 1e3, 2), "p99_ms": round(q(lat_f, 99) * 1e3, 2),
+                     "optimal": ok_f},
+            "speedup_solves_per_s": round(span_f / span_s, 2)}
 
 
 def cpu_baseline(W, p, seconds):
@@ -82,6 +234,9 @@ def cpu_baseline(W, p, seconds):
 
 def main():
     args = parse()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
                           "n_gpus": args.gpus}))
@@ -96,7 +251,7 @@ def main():
     W = skgen.uniform_weights(n, 0, 1000, seed=args.seed)
     Wd = torch.from_numpy(W).cuda()
     prm = sk.make_params(ladder, tol=args.tol, max_iters=args.cap, check_every=32,
-                         threshold=args.threshold, storage=args.storage)
+                         threshold=args.threshold, storage=args.storage, fused=args.fused)
     ctx = sk.Context(0)
     torch.cuda.synchronize()
 
@@ -127,10 +282,14 @@ def main():
     ctx.profile(False)
 
     es = ELEM_BYTES[args.storage]
-    sweep_bytes = 2 * iters * n * n * es
+    # matrix reads per iteration: two sweeps, or one single-pass launch
+    reads = 1 if args.fused else 2
+    sweep_bytes = reads * iters * n * n * es
     value = sweep_bytes / el / 1e9
-    # dominant kernel and its live average duration
-    dom = max(prof.items(), key=lambda kv: kv[1][1])
+    # dominant kernel (full-work launches only; launches that only detected
+    # convergence or came after the ladder finished are tagged apart)
+    full = {k: v for k, v in prof.items() if ":" not in k}
+    dom = max(full.items(), key=lambda kv: kv[1][1])
     dom_name, (dom_launches, dom_ms) = dom
     avg_s = dom_ms / dom_launches / 1e3
     per_launch = n * n * es if dom_name in SWEEP_KERNELS[args.storage] else None
@@ -150,16 +309,24 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"dense n={n}, int16 w uniform 0..1000 (seed {args.seed}), "
                                f"ladder {ladder}, tol {args.tol}, {args.cap} iterations/stage cap, "
-                               f"t={args.threshold}, storage {args.storage}; scale+recheck+prune+"
-                               f"exact solve per step", "n": n, "storage": args.storage},
-        "iters_per_step": iters // args.steps, "sweeps_per_s": round(2 * iters / el, 1),
+                               f"t={args.threshold}, storage {args.storage}"
+                               f"{', single-pass iteration' if args.fused else ''}; scale+recheck+"
+                               f"prune+exact solve per step", "n": n, "storage": args.storage,
+                   "fused": bool(args.fused)},
+        "iters_per_step": iters // args.steps, "iters_per_s": round(iters / el, 1),
+        "matrix_reads_per_iter": reads,
         "nnz_kept": nnz, "weight": weight, "log_gamma": lg,
         "residual_fp64": rep["residual_fp64"],
         "roofline": roofline, "kernels": kernels,
     }
+    ctx.close()
+    del Wd
+    if not args.no_batched:
+        out["batched"] = batched_leg(sk, torch)
+    if not args.no_served:
+        out["served"] = served_leg(sk, torch, args.served_requests, args.served_load)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W, ladder[-1], args.cpu_seconds)
-    ctx.close()
     print(json.dumps(out), flush=True)
 
 

@@ -75,7 +75,13 @@ typedef enum {
  *   storage      : see sk_storage.
  *   opt_ratio    : required gamma of eq. optratio (> 1), used by sk_submit.
  *   warm_start   : 0 = cold start (v = 1 for the first p); 1 = start from the
- *                  potentials passed in (their p is p_ladder[0]). */
+ *                  potentials passed in (their p is p_ladder[0]).
+ *   fused        : 0 = a row-sweep launch and a column-sweep launch per
+ *                  iteration (each reads the matrix); 1 = one single-pass
+ *                  launch per iteration that forms the row sums and the new
+ *                  column sums from one read of the matrix (single instance,
+ *                  n % 8 == 0 for int16 W). Both give the same iterates up to
+ *                  FP32 summation order. */
 typedef struct {
     int32_t p_ladder[SK_MAX_LADDER];
     int32_t n_p;
@@ -86,6 +92,7 @@ typedef struct {
     int32_t storage;
     double opt_ratio;
     int32_t warm_start;
+    int32_t fused;
 } sk_params;
 
 /* Per-run report. Residuals are max_i |r_i - 1| (rows) and max_j |c_j - 1|

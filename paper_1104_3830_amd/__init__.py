@@ -40,7 +40,7 @@ class Params(ctypes.Structure):
                 ("tol", ctypes.c_double), ("max_iters_per_stage", ctypes.c_int64),
                 ("check_every", ctypes.c_int32), ("threshold", ctypes.c_double),
                 ("storage", ctypes.c_int32), ("opt_ratio", ctypes.c_double),
-                ("warm_start", ctypes.c_int32)]
+                ("warm_start", ctypes.c_int32), ("fused", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):
@@ -117,7 +117,7 @@ def lib():
 
 
 def make_params(ladder, tol=1e-5, max_iters=20000, check_every=32, threshold=1e-4,
-                storage="i16", opt_ratio=2.0, warm_start=False) -> Params:
+                storage="i16", opt_ratio=2.0, warm_start=False, fused=False) -> Params:
     p = Params()
     ladder = [int(x) for x in ladder]
     if not 1 <= len(ladder) <= MAX_LADDER:
@@ -132,6 +132,7 @@ def make_params(ladder, tol=1e-5, max_iters=20000, check_every=32, threshold=1e-
     p.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
     p.opt_ratio = float(opt_ratio)
     p.warm_start = 1 if warm_start else 0
+    p.fused = 1 if fused else 0
     return p
 
 

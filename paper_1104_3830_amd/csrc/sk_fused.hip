@@ -1,0 +1,333 @@
+// Single-pass Sinkhorn iteration: one read of the matrix per iteration.
+//
+// A workgroup of 1024 threads owns a contiguous block of rows and every
+// column; thread t owns the 8-column chunks t, t + 1024 (n <= 16384). For
+// each group of R rows it
+//   A. forms s_ij for its columns (I16: exp(p w_ij + F_i + G_j + gam_j) with
+//      the exact integer part; stored K: K_ij b_j), keeps them in registers and
+//      reduces the row sums S_i across the workgroup (the row step,
+//      eq. dad2: log u_i <- F_i - log S_i, resp. a_i <- 1 / S_i);
+//   B. adds s_ij / S_i into per-thread column accumulators: this is the
+//      column sum of the new row-stochastic iterate, since
+//      exp(p w_ij + log u_i(new) + log v_j) = s_ij / S_i (resp. K_ij a_i(new)
+//      = s_ij / (S_i b_j)).
+// The accumulators go to fixed slots colpart[workgroup][j]; a second kernel
+// adds the slots of each column in workgroup order (deterministic) and
+// applies the column step (eq. dad3). The result equals a row sweep followed
+// by a column sweep, with half the matrix traffic.
+#include "sk_runtime.h"
+
+namespace sk {
+
+constexpr int kFT = 1024;    // threads per workgroup
+constexpr int kFR = 2;       // rows per group
+constexpr float kL2e = 1.4426950408889634f;
+constexpr float kLn2f = 0.6931471805599453f;
+constexpr float kLo = 5.421010862427522e-20f;  // 2^-64
+constexpr float kHi = 1.8446744073709552e19f;  // 2^64
+
+__device__ __forceinline__ float fex2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float flg2(float x) { return __builtin_amdgcn_logf(x); }
+__device__ __forceinline__ float fwsum(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+__device__ __forceinline__ float fwmax(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+// 8 values of one chunk as floats: int16 w (I16) or K (BF16 / F32).
+template <int ST>
+__device__ __forceinline__ void fload(const void *base, int64_t off, float (&x)[8]) {
+    if (ST == SK_W_I16) {
+        const int4 v = gload(reinterpret_cast<const int4 *>(reinterpret_cast<const int16_t *>(base) + off));
+        x[0] = (float)(short)(v.x & 0xffff); x[1] = (float)(v.x >> 16);
+        x[2] = (float)(short)(v.y & 0xffff); x[3] = (float)(v.y >> 16);
+        x[4] = (float)(short)(v.z & 0xffff); x[5] = (float)(v.z >> 16);
+        x[6] = (float)(short)(v.w & 0xffff); x[7] = (float)(v.w >> 16);
+    } else if (ST == SK_K_BF16) {
+        const int4 v = gload(reinterpret_cast<const int4 *>(reinterpret_cast<const uint16_t *>(base) + off));
+        const uint32_t q[4] = {(uint32_t)v.x, (uint32_t)v.y, (uint32_t)v.z, (uint32_t)v.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            x[2 * k] = __uint_as_float(q[k] << 16);
+            x[2 * k + 1] = __uint_as_float(q[k] & 0xffff0000u);
+        }
+    } else {
+        const float4 *p = reinterpret_cast<const float4 *>(reinterpret_cast<const float *>(base) + off);
+        const float4 a = gload(p), b = gload(p + 1);
+        x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
+        x[4] = b.x; x[5] = b.y; x[6] = b.z; x[7] = b.w;
+    }
+}
+
+template <int ST, int CPT>
+__global__ __launch_bounds__(kFT) void k_fused(const Inst *__restrict__ insts, int inst) {
+    __shared__ float red[kFT / kWave][kFR];
+    __shared__ float rowinv[kFR];
+    __shared__ int rowbad[kFR];
+    const Inst &I = insts[inst];
+    Ctl *ctl = I.ctl;
+    if (ctl->state != ST_RUNNING) return;
+    if (ST != SK_W_I16 && ctl->need_absorb) return;
+    const int n = I.n;
+    const int t = threadIdx.x, wave = t / kWave, lane = t % kWave;
+    const int iter = ctl->iter;
+    const int par = iter & 1;
+    const bool sent = ST == SK_W_I16 && ctl->sent != 0u;
+    const float pf = (float)ctl->p;
+    const int64_t pitch = ST == SK_W_I16 ? I.pitch : I.kpitch;
+    const void *base = ST == SK_W_I16 ? (const void *)I.W : (const void *)I.K;
+    // rows of this workgroup
+    const int per = (n + (int)gridDim.x - 1) / (int)gridDim.x;
+    const int r0 = blockIdx.x * per, r1 = min(n, r0 + per);
+    // owned columns and their potentials
+    int c0[CPT];
+    bool own[CPT];
+    float gx[CPT][8], gy[CPT][8], acc[CPT][8];
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+        c0[k] = (t + k * kFT) * 8;
+        own[k] = c0[k] < n;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            acc[k][c] = 0.f;
+            if (ST == SK_W_I16) {
+                gx[k][c] = own[k] ? (float)I.G[c0[k] + c] : 0.f;
+                gy[k][c] = own[k] ? I.gam[c0[k] + c] * kL2e : 0.f;
+            } else {
+                gx[k][c] = own[k] && c0[k] + c < n ? I.b[c0[k] + c] : 0.f;
+                gy[k][c] = 0.f;
+            }
+        }
+    }
+    float resmax = 0.f, drift = 0.f;
+    for (int rb = r0; rb < r1; rb += kFR) {
+        float s[kFR][CPT][8];
+        float part[kFR];
+        float Ff[kFR];
+        // A: s_ij and row partials
+#pragma unroll
+        for (int rr = 0; rr < kFR; ++rr) {
+            const int row = rb + rr;
+            part[rr] = 0.f;
+            Ff[rr] = (ST == SK_W_I16 && row < r1) ? (float)I.F[par][row] : 0.f;
+#pragma unroll
+            for (int k = 0; k < CPT; ++k) {
+#pragma unroll
+                for (int c = 0; c < 8; ++c) s[rr][k][c] = 0.f;
+                if (row < r1 && own[k]) {
+                    float x[8];
+                    fload<ST>(base, (int64_t)row * pitch + c0[k], x);
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) {
+                        float e;
+                        if (ST == SK_W_I16) {
+                            const float Iv = fmaf(x[c], pf, gx[k][c]) + Ff[rr];
+                            e = fex2(fmaf(Iv, kL2e, gy[k][c]));
+                            if (sent && x[c] == -32768.0f) e = 0.f;
+                        } else {
+                            e = x[c] * gx[k][c];
+                        }
+                        s[rr][k][c] = e;
+                        part[rr] += e;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int rr = 0; rr < kFR; ++rr) {
+            const float v = fwsum(part[rr]);
+            if (lane == 0) red[wave][rr] = v;
+        }
+        __syncthreads();
+        if (t < kFR) {
+            const int row = rb + t;
+            float S = 0.f;
+            for (int w = 0; w < kFT / kWave; ++w) S += red[w][t];
+            int bad = 0;
+            if (row < r1) {
+                if (ST == SK_W_I16) {
+                    bad = !(S >= kLo && S <= kHi);
+                    if (!bad) {
+                        const float l2S = flg2(S);
+                        float phin = -l2S * kLn2f;
+                        const float kk = rintf(phin);
+                        I.F[par ^ 1][row] = I.F[par][row] + (int)kk;
+                        I.phi[par ^ 1][row] = phin - kk;
+                        const float r = fex2(fmaf(I.phi[par][row], kL2e, l2S));
+                        resmax = fmaxf(resmax, fabsf(r - 1.f));
+                    }
+                    rowinv[t] = bad ? 0.f : 1.f / S;
+                } else {
+                    const float Sc = fminf(fmaxf(S, kLo), kHi);
+                    const float anew = 1.f / Sc;
+                    I.a[par ^ 1][row] = anew;
+                    resmax = fmaxf(resmax, fabsf(I.a[par][row] * S - 1.f));
+                    drift = fmaxf(drift, fabsf(flg2(anew)));
+                    rowinv[t] = anew;
+                }
+            } else {
+                rowinv[t] = 0.f;
+            }
+            rowbad[t] = bad;
+        }
+        __syncthreads();
+        // exact max shift for a row whose sum left the safe range (I16 only)
+        if (ST == SK_W_I16) {
+#pragma unroll
+            for (int rr = 0; rr < kFR; ++rr) {
+                if (!rowbad[rr]) continue;  // uniform across the workgroup
+                const int row = rb + rr;
+                float m = -INFINITY;
+#pragma unroll
+                for (int k = 0; k < CPT; ++k) {
+                    if (!own[k]) continue;
+                    float x[8];
+                    fload<ST>(base, (int64_t)row * pitch + c0[k], x);
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) {
+                        const float Iv = fmaf(x[c], pf, gx[k][c]) + Ff[rr];
+                        float y = fmaf(Iv, kL2e, gy[k][c]);
+                        if (sent && x[c] == -32768.0f) y = -INFINITY;
+                        m = fmaxf(m, y);
+                        s[rr][k][c] = y;  // exponent, shifted below
+                    }
+                }
+                m = fwmax(m);
+                __syncthreads();
+                if (lane == 0) red[wave][0] = m;
+                __syncthreads();
+                float M = -INFINITY;
+                for (int w = 0; w < kFT / kWave; ++w) M = fmaxf(M, red[w][0]);
+                float pp = 0.f;
+#pragma unroll
+                for (int k = 0; k < CPT; ++k)
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) {
+                        const float e = own[k] && M != -INFINITY ? fex2(s[rr][k][c] - M) : 0.f;
+                        s[rr][k][c] = e;
+                        pp += e;
+                    }
+                pp = fwsum(pp);
+                __syncthreads();
+                if (lane == 0) red[wave][1] = pp;
+                __syncthreads();
+                if (t == 0) {
+                    float S2 = 0.f;
+                    for (int w = 0; w < kFT / kWave; ++w) S2 += red[w][1];
+                    if (M == -INFINITY) {
+                        atomicOr(&ctl->err, ERR_EMPTY_ROW);
+                        rowinv[rr] = 0.f;
+                    } else {
+                        const float l2S = M + flg2(S2);
+                        const double phin = -(double)l2S * (double)kLn2f;
+                        const double kk = rint(phin);
+                        I.F[par ^ 1][row] = I.F[par][row] + (int)kk;
+                        I.phi[par ^ 1][row] = (float)(phin - kk);
+                        const float r = fex2(fmaf(I.phi[par][row], kL2e, l2S));
+                        resmax = fmaxf(resmax, fabsf(r - 1.f));
+                        rowinv[rr] = 1.f / S2;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        // B: column accumulation with the new row scalings
+#pragma unroll
+        for (int rr = 0; rr < kFR; ++rr) {
+            const float inv = rowinv[rr];
+#pragma unroll
+            for (int k = 0; k < CPT; ++k)
+#pragma unroll
+                for (int c = 0; c < 8; ++c) acc[k][c] = fmaf(s[rr][k][c], inv, acc[k][c]);
+        }
+        __syncthreads();  // red / rowinv are reused by the next group
+    }
+    // fixed-slot column partials of this workgroup
+    float *dst = I.colpart + (int64_t)blockIdx.x * n;
+#pragma unroll
+    for (int k = 0; k < CPT; ++k)
+        if (own[k]) {
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+                if (c0[k] + c < n) dst[c0[k] + c] = acc[k][c];
+        }
+    if (t < kFR) {
+        if (iter >= 1 && resmax > 0.f) atomicMax(&ctl->res_bits, __float_as_uint(resmax));
+        if (ST != SK_W_I16 && drift > 0.f) atomicMax(&ctl->drift_bits, __float_as_uint(drift));
+    }
+}
+
+// Column step from the fixed slots: C_j = sum over workgroups in order.
+// I16: log v_j <- log v_j - log C_j (exact split kept); stored K: b_j <- b_j / C_j.
+template <int ST>
+__global__ __launch_bounds__(256) void k_fused_cols(const Inst *__restrict__ insts, int inst,
+                                                    int nslots) {
+    const Inst &I = insts[inst];
+    Ctl *ctl = I.ctl;
+    if (ctl->state != ST_RUNNING) return;
+    if (ST != SK_W_I16 && ctl->need_absorb) return;
+    const float res = __uint_as_float(ctl->res_bits);
+    if (ctl->iter >= 1 && res < I.tol) return;  // converged: this iteration is discarded
+    const int n = I.n;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    float drift = 0.f;
+    if (j < n) {
+        float C = 0.f;
+        for (int s = 0; s < nslots; ++s) C += I.colpart[(int64_t)s * n + j];
+        if (ST == SK_W_I16) {
+            if (C >= kLo && C <= kHi) {
+                const float gn = I.gam[j] - flg2(C) * kLn2f;
+                const float kk = rintf(gn);
+                I.G[j] += (int)kk;
+                I.gam[j] = gn - kk;
+            } else {
+                const unsigned slot = atomicAdd(&ctl->rescue_cnt, 1u);
+                I.rescue[slot] = (uint32_t)j;
+            }
+        } else {
+            const float bn = I.b[j] / fminf(fmaxf(C, kLo), kHi);
+            I.b[j] = fminf(fmaxf(bn, kLo), kHi);
+            drift = fabsf(flg2(I.b[j]));
+        }
+    }
+    if (ST != SK_W_I16) {
+        drift = fwmax(drift);
+        if ((threadIdx.x % kWave) == 0 && drift > 0.f) atomicMax(&ctl->drift_bits, __float_as_uint(drift));
+    }
+}
+
+template <int ST>
+static hipError_t launch_fused_st(const Inst *d_insts, int inst, int n, int grid, hipStream_t st) {
+    const int cpt = (n / 8 + kFT - 1) / kFT;
+    if (cpt <= 1)
+        hipLaunchKernelGGL((k_fused<ST, 1>), dim3(grid), dim3(kFT), 0, st, d_insts, inst);
+    else
+        hipLaunchKernelGGL((k_fused<ST, 2>), dim3(grid), dim3(kFT), 0, st, d_insts, inst);
+    return hipGetLastError();
+}
+
+hipError_t launch_fused(const Inst *d_insts, int inst, int n, int grid, int storage,
+                        hipStream_t st) {
+    if (storage == SK_W_I16) return launch_fused_st<SK_W_I16>(d_insts, inst, n, grid, st);
+    if (storage == SK_K_BF16) return launch_fused_st<SK_K_BF16>(d_insts, inst, n, grid, st);
+    return launch_fused_st<SK_K_F32>(d_insts, inst, n, grid, st);
+}
+
+hipError_t launch_fused_cols(const Inst *d_insts, int inst, int n, int nslots, int storage,
+                             hipStream_t st) {
+    const dim3 g((n + 255) / 256);
+    if (storage == SK_W_I16)
+        hipLaunchKernelGGL(k_fused_cols<SK_W_I16>, g, dim3(256), 0, st, d_insts, inst, nslots);
+    else if (storage == SK_K_BF16)
+        hipLaunchKernelGGL(k_fused_cols<SK_K_BF16>, g, dim3(256), 0, st, d_insts, inst, nslots);
+    else
+        hipLaunchKernelGGL(k_fused_cols<SK_K_F32>, g, dim3(256), 0, st, d_insts, inst, nslots);
+    return hipGetLastError();
+}
+
+}  // namespace sk

@@ -15,6 +15,7 @@ constexpr int kColTile8 = 512;   // columns per column tile, 8-wide vector loads
 constexpr int kColTile1 = 64;    // columns per column tile, scalar loads
 constexpr int kMaxN = 16384;     // row sweep stages all column potentials in LDS
 constexpr int kMaxSegRows = 1024;
+constexpr int kFusedSlots = 256;  // workgroups (and column-partial slots) of the fused kernel
 
 enum : int32_t { ST_RUNNING = 0, ST_DONE = 1, ST_ERROR = 2, ST_STAGE_END = 3 };
 enum : uint32_t { ERR_EMPTY_ROW = 1u, ERR_EMPTY_COL = 2u, ERR_RANGE = 4u };
@@ -67,7 +68,25 @@ struct Inst {
     float *b;               // column scalings of K
     int32_t storage;
     int32_t kpitch;
+    int32_t fused;          // single-pass iteration (colpart holds kFusedSlots rows)
+    int32_t fused_grid;
 };
+
+// Loads through a global-address-space pointer, so the compiler emits
+// global_load (counted by vmcnt only) instead of flat_load (also counted by
+// lgkmcnt, which would make every LDS wait drain the outstanding HBM loads).
+typedef int sk_gi4 __attribute__((ext_vector_type(4)));
+typedef float sk_gf4 __attribute__((ext_vector_type(4)));
+#define SK_GLOBAL __attribute__((address_space(1)))
+__device__ __forceinline__ int4 gload(const int4 *p) {
+    const sk_gi4 v = *(const SK_GLOBAL sk_gi4 *)p;
+    return make_int4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ float4 gload(const float4 *p) {
+    const sk_gf4 v = *(const SK_GLOBAL sk_gf4 *)p;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ int16_t gload(const int16_t *p) { return *(const SK_GLOBAL int16_t *)p; }
 
 struct RowUnit { int32_t inst, row0; };
 struct ColUnit { int32_t inst, tile, seg, pad; };
@@ -82,7 +101,8 @@ hipError_t launch_col_sweep(const Inst *d_insts, const ColUnit *d_units, int nun
 hipError_t launch_iter_end(const Inst *d_insts, int count, hipStream_t st);
 hipError_t launch_check_rows(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
                              double *rsum, double *rmax, hipStream_t st);
-hipError_t launch_check_cols(const Inst *d_insts, int inst, int n, double *csum, hipStream_t st);
+hipError_t launch_check_cols(const Inst *d_insts, int inst, int n, int nseg, double *part,
+                             double *csum, hipStream_t st);
 hipError_t launch_prune_count(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
                               double logt, int64_t *counts, hipStream_t st);
 hipError_t launch_scan(const int64_t *counts, int64_t *row_ptr, int n, hipStream_t st);
@@ -98,7 +118,14 @@ hipError_t launch_col_sweep_k(const Inst *d_insts, const ColUnit *d_units, int n
 hipError_t launch_fold_k(const Inst *d_insts, int count, hipStream_t st);
 hipError_t launch_advance(const Inst *d_insts, int count, hipStream_t st);
 hipError_t launch_check_k(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid, int inst,
-                          int n, int storage, double *rsum, double *csum, hipStream_t st);
+                          int n, int nseg, int storage, double *rsum, double *part, double *csum,
+                          hipStream_t st);
+hipError_t launch_fused(const Inst *d_insts, int inst, int n, int grid, int storage,
+                        hipStream_t st);
+hipError_t launch_fused_cols(const Inst *d_insts, int inst, int n, int nslots, int storage,
+                             hipStream_t st);
+hipError_t launch_gather_ctl(const Inst *d_insts, int count, Ctl *out, hipStream_t st);
+hipError_t launch_reset_ctl(const Inst *d_insts, const int *idx, int m, hipStream_t st);
 hipError_t set_kernel_attributes();
 
 }  // namespace sk

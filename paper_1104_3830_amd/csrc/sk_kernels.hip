@@ -15,6 +15,8 @@
 //                                        log v_j <- G_j - log T_j.
 // Row sums of the column-stochastic iterate (Section 4.2 stopping test):
 //                                        r_i = exp(phi_i) S_i.
+#include <algorithm>
+
 #include "sk_internal.h"
 
 namespace sk {
@@ -118,27 +120,47 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_init(const Inst *__restri
 // ---------------------------------------------------------------- row sweep
 // One wavefront per row; column potentials (G_j as float, gam_j*log2 e)
 // staged once per workgroup in LDS; W read with coalesced 16-byte loads.
+// Sum over 8 consecutive columns q*8 .. q*8+7 of one 16-byte chunk.
+template <bool SENT>
+__device__ __forceinline__ float chunk8(const int4 v, int q, int n8, float pf, float Ff,
+                                        const float2 *__restrict__ pot, float shift) {
+    float w[8];
+    unpack8(v, w);
+    float s = 0.f;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const float2 gp = pot[c * n8 + q];
+        const float I = fmaf(w[c], pf, gp.x) + Ff;        // exact integer
+        float e = ex2(fmaf(I, kLog2e, gp.y) - shift);
+        if (SENT) e = (w[c] == kSentF) ? 0.f : e;
+        s += e;
+    }
+    return s;
+}
+
+// Row partial sum for one lane: chunks lane*8 + k*512, four 16-byte loads
+// in flight per lane.
 template <bool SENT>
 __device__ __forceinline__ float row_partial_v8(const int16_t *__restrict__ wr, int n, float pf,
                                                 float Ff, const float2 *__restrict__ pot, int lane,
                                                 float shift) {
     const int n8 = n >> 3;
     float acc = 0.f;
-    for (int j0 = lane * 8; j0 < n; j0 += 512) {
-        const int4 v = *reinterpret_cast<const int4 *>(wr + j0);
-        float w[8];
-        unpack8(v, w);
+    int j0 = lane * 8;
+    for (; j0 + 3 * 512 < n; j0 += 4 * 512) {
+        const int4 v0 = gload(reinterpret_cast<const int4 *>(wr + j0));
+        const int4 v1 = gload(reinterpret_cast<const int4 *>(wr + j0 + 512));
+        const int4 v2 = gload(reinterpret_cast<const int4 *>(wr + j0 + 1024));
+        const int4 v3 = gload(reinterpret_cast<const int4 *>(wr + j0 + 1536));
         const int q = j0 >> 3;
-        float s = 0.f;
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            const float2 gp = pot[c * n8 + q];
-            const float I = fmaf(w[c], pf, gp.x) + Ff;        // exact integer
-            float e = ex2(fmaf(I, kLog2e, gp.y) - shift);
-            if (SENT) e = (w[c] == kSentF) ? 0.f : e;
-            s += e;
-        }
-        acc += s;
+        acc += chunk8<SENT>(v0, q, n8, pf, Ff, pot, shift);
+        acc += chunk8<SENT>(v1, q + 64, n8, pf, Ff, pot, shift);
+        acc += chunk8<SENT>(v2, q + 128, n8, pf, Ff, pot, shift);
+        acc += chunk8<SENT>(v3, q + 192, n8, pf, Ff, pot, shift);
+    }
+    for (; j0 < n; j0 += 512) {
+        const int4 v = gload(reinterpret_cast<const int4 *>(wr + j0));
+        acc += chunk8<SENT>(v, j0 >> 3, n8, pf, Ff, pot, shift);
     }
     return acc;
 }
@@ -149,7 +171,7 @@ __device__ __forceinline__ float row_max_v8(const int16_t *__restrict__ wr, int 
     const int n8 = n >> 3;
     float m = -INFINITY;
     for (int j0 = lane * 8; j0 < n; j0 += 512) {
-        const int4 v = *reinterpret_cast<const int4 *>(wr + j0);
+        const int4 v = gload(reinterpret_cast<const int4 *>(wr + j0));
         float w[8];
         unpack8(v, w);
         const int q = j0 >> 3;
@@ -171,7 +193,7 @@ __device__ __forceinline__ float row_partial_v1(const int16_t *__restrict__ wr, 
                                                 float shift) {
     float acc = 0.f;
     for (int j = lane; j < n; j += kWave) {
-        const float w = (float)wr[j];
+        const float w = (float)gload(wr + j);
         const float2 gp = pot[j];
         const float I = fmaf(w, pf, gp.x) + Ff;
         float e = ex2(fmaf(I, kLog2e, gp.y) - shift);
@@ -186,7 +208,7 @@ __device__ __forceinline__ float row_max_v1(const int16_t *__restrict__ wr, int 
                                             float Ff, const float2 *__restrict__ pot, int lane) {
     float m = -INFINITY;
     for (int j = lane; j < n; j += kWave) {
-        const float w = (float)wr[j];
+        const float w = (float)gload(wr + j);
         const float2 gp = pot[j];
         const float I = fmaf(w, pf, gp.x) + Ff;
         float y = fmaf(I, kLog2e, gp.y);
@@ -311,9 +333,8 @@ __device__ __forceinline__ void col_partial(const Inst &I, int tile, int r0, int
 #pragma unroll
         for (int c = 0; c < 8; ++c) Gf[c] = (float)I.G[c0 + c];
         const int16_t *base = I.W + c0;
-        for (int r = r0 + wave; r < r1; r += kColWaves) {
-            const float2 rp = rowpot[r - r0];
-            const int4 v = *reinterpret_cast<const int4 *>(base + (int64_t)r * I.pitch);
+        const int64_t pitch = I.pitch;
+        auto body = [&](const int4 v, const float2 rp) {
             float w[8];
             unpack8(v, w);
 #pragma unroll
@@ -323,14 +344,28 @@ __device__ __forceinline__ void col_partial(const Inst &I, int tile, int r0, int
                 if (SENT) e = (w[c] == kSentF) ? 0.f : e;
                 acc[c] += e;
             }
+        };
+        int r = r0 + wave;
+        constexpr int S = kColWaves;
+        for (; r + 3 * S < r1; r += 4 * S) {
+            const int4 v0 = gload(reinterpret_cast<const int4 *>(base + (int64_t)r * pitch));
+            const int4 v1 = gload(reinterpret_cast<const int4 *>(base + (int64_t)(r + S) * pitch));
+            const int4 v2 = gload(reinterpret_cast<const int4 *>(base + (int64_t)(r + 2 * S) * pitch));
+            const int4 v3 = gload(reinterpret_cast<const int4 *>(base + (int64_t)(r + 3 * S) * pitch));
+            body(v0, rowpot[r - r0]);
+            body(v1, rowpot[r + S - r0]);
+            body(v2, rowpot[r + 2 * S - r0]);
+            body(v3, rowpot[r + 3 * S - r0]);
         }
+        for (; r < r1; r += S) body(gload(reinterpret_cast<const int4 *>(base + (int64_t)r * pitch)),
+                                    rowpot[r - r0]);
     } else {
         const int c0 = tile * kColTile1 + lane;
         if (c0 >= n) return;
         const float Gf = (float)I.G[c0];
         for (int r = r0 + wave; r < r1; r += kColWaves) {
             const float2 rp = rowpot[r - r0];
-            const float w = (float)I.W[(int64_t)r * I.pitch + c0];
+            const float w = (float)gload(I.W + (int64_t)r * I.pitch + c0);
             const float Iv = fmaf(w, pf, Gf) + rp.x;
             float e = ex2(fmaf(Iv, kLog2e, rp.y));
             if (SENT) e = (w == kSentF) ? 0.f : e;
@@ -589,23 +624,38 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_check_rows(const Inst *__
     }
 }
 
-// Column sums in FP64: one thread per column walks the rows (coalesced along
-// each row).
-__global__ __launch_bounds__(256) void k_check_cols(const Inst *__restrict__ insts, int inst,
-                                                    double *csum) {
+// Column sums in FP64, two passes: workgroup (256-column tile, row segment)
+// with one thread per column writes a partial to slot [segment][column]
+// (coalesced along each row); then one thread per column adds its slots in
+// segment order.
+__global__ __launch_bounds__(256) void k_check_cols_part(const Inst *__restrict__ insts, int inst,
+                                                         double *part) {
     const Inst &I = insts[inst];
     const int n = I.n;
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int seg = blockIdx.y;
     if (j >= n) return;
+    const int r0 = seg * I.seg_rows, r1 = min(n, r0 + I.seg_rows);
     const int par = I.ctl->iter & 1;
     const double p = (double)I.ctl->p;
     const double g = (double)I.G[j] + (double)I.gam[j];
     double s = 0.0;
-    for (int r = 0; r < n; ++r) {
+    for (int r = r0; r < r1; ++r) {
         const int w = I.W[(int64_t)r * I.pitch + j];
         if (w == SK_SENTINEL) continue;
         s += exp(p * (double)w + g + ((double)I.F[par][r] + (double)I.phi[par][r]));
     }
+    part[(int64_t)seg * n + j] = s;
+}
+
+__global__ __launch_bounds__(256) void k_check_cols_sum(const Inst *__restrict__ insts, int inst,
+                                                        const double *part, double *csum) {
+    const Inst &I = insts[inst];
+    const int n = I.n;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    double s = 0.0;
+    for (int seg = 0; seg < I.nseg; ++seg) s += part[(int64_t)seg * n + j];
     csum[j] = s;
 }
 
@@ -712,7 +762,49 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_prune_fill(const Inst *__
     }
 }
 
+// ---------------------------------------------------------------- control blocks
+// Copies every instance's control block into one contiguous array (one
+// device-to-host copy per check instead of one per instance).
+__global__ __launch_bounds__(256) void k_gather_ctl(const Inst *__restrict__ insts, int count,
+                                                    Ctl *out) {
+    const int words = (int)(sizeof(Ctl) / sizeof(uint32_t));
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < count * words;
+         q += gridDim.x * blockDim.x) {
+        const int k = q / words, w = q % words;
+        reinterpret_cast<uint32_t *>(out + k)[w] =
+            reinterpret_cast<const volatile uint32_t *>(insts[k].ctl)[w];
+    }
+}
+
+// Resets the control blocks and tile counters of instances idx[0..m) for a
+// cold start at the first p of their ladders.
+__global__ __launch_bounds__(256) void k_reset_ctl(const Inst *__restrict__ insts, const int *idx,
+                                                   int m) {
+    for (int q = blockIdx.x; q < m; q += gridDim.x) {
+        const Inst &I = insts[idx ? idx[q] : q];
+        if (threadIdx.x == 0) {
+            Ctl c;
+            memset(&c, 0, sizeof c);
+            c.state = ST_RUNNING;
+            c.p = I.ladder[0];
+            c.last_res = INFINITY;
+            *I.ctl = c;
+        }
+        for (int t = threadIdx.x; t < I.ntiles; t += blockDim.x) I.tilecnt[t] = 0u;
+    }
+}
+
 // ---------------------------------------------------------------- launchers
+hipError_t launch_gather_ctl(const Inst *d_insts, int count, Ctl *out, hipStream_t st) {
+    const int words = count * (int)(sizeof(Ctl) / sizeof(uint32_t));
+    hipLaunchKernelGGL(k_gather_ctl, dim3(std::min(1024, (words + 255) / 256)), dim3(256), 0, st,
+                       d_insts, count, out);
+    return hipGetLastError();
+}
+hipError_t launch_reset_ctl(const Inst *d_insts, const int *idx, int m, hipStream_t st) {
+    hipLaunchKernelGGL(k_reset_ctl, dim3(std::min(m, 1024)), dim3(256), 0, st, d_insts, idx, m);
+    return hipGetLastError();
+}
 hipError_t launch_init(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid, int cold,
                        hipStream_t st) {
     hipLaunchKernelGGL(k_init, dim3(grid), dim3(kRowWaves * kWave), 0, st, d_insts, d_units,
@@ -741,8 +833,12 @@ hipError_t launch_check_rows(const Inst *d_insts, const RowUnit *d_units, int nu
                        nunits, rsum, rmax);
     return hipGetLastError();
 }
-hipError_t launch_check_cols(const Inst *d_insts, int inst, int n, double *csum, hipStream_t st) {
-    hipLaunchKernelGGL(k_check_cols, dim3((n + 255) / 256), dim3(256), 0, st, d_insts, inst, csum);
+hipError_t launch_check_cols(const Inst *d_insts, int inst, int n, int nseg, double *part,
+                             double *csum, hipStream_t st) {
+    hipLaunchKernelGGL(k_check_cols_part, dim3((n + 255) / 256, nseg), dim3(256), 0, st, d_insts,
+                       inst, part);
+    hipLaunchKernelGGL(k_check_cols_sum, dim3((n + 255) / 256), dim3(256), 0, st, d_insts, inst,
+                       part, csum);
     return hipGetLastError();
 }
 hipError_t launch_prune_count(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,

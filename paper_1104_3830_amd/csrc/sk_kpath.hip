@@ -54,7 +54,7 @@ __device__ __forceinline__ uint32_t bf16_rne(float x) {
 template <int ST>
 __device__ __forceinline__ void load8(const void *K, int64_t off, float (&k)[8]) {
     if (ST == SK_K_BF16) {
-        const int4 v = *reinterpret_cast<const int4 *>(reinterpret_cast<const uint16_t *>(K) + off);
+        const int4 v = gload(reinterpret_cast<const int4 *>(reinterpret_cast<const uint16_t *>(K) + off));
         const uint32_t x[4] = {(uint32_t)v.x, (uint32_t)v.y, (uint32_t)v.z, (uint32_t)v.w};
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -63,7 +63,7 @@ __device__ __forceinline__ void load8(const void *K, int64_t off, float (&k)[8])
         }
     } else {
         const float4 *p = reinterpret_cast<const float4 *>(reinterpret_cast<const float *>(K) + off);
-        const float4 a = p[0], b = p[1];
+        const float4 a = gload(p), b = gload(p + 1);
         k[0] = a.x; k[1] = a.y; k[2] = a.z; k[3] = a.w;
         k[4] = b.x; k[5] = b.y; k[6] = b.z; k[7] = b.w;
     }
@@ -175,9 +175,28 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_row_sweep_k(const Inst *_
         if (row >= n) continue;
         const int par = ctl->iter & 1;
         float acc = 0.f;
-        for (int j0 = lane * 8; j0 < kp; j0 += 512) {
+        const int64_t rbase = (int64_t)row * kp;
+        int j0 = lane * 8;
+        for (; j0 + 3 * 512 < kp; j0 += 4 * 512) {
+            float k0[8], k1[8], k2[8], k3[8];
+            load8<ST>(I.K, rbase + j0, k0);
+            load8<ST>(I.K, rbase + j0 + 512, k1);
+            load8<ST>(I.K, rbase + j0 + 1024, k2);
+            load8<ST>(I.K, rbase + j0 + 1536, k3);
+            const int q = j0 >> 3;
+            float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                s0 = fmaf(k0[c], bsh[c * n8 + q], s0);
+                s1 = fmaf(k1[c], bsh[c * n8 + q + 64], s1);
+                s2 = fmaf(k2[c], bsh[c * n8 + q + 128], s2);
+                s3 = fmaf(k3[c], bsh[c * n8 + q + 192], s3);
+            }
+            acc += (s0 + s1) + (s2 + s3);
+        }
+        for (; j0 < kp; j0 += 512) {
             float k[8];
-            load8<ST>(I.K, (int64_t)row * kp + j0, k);
+            load8<ST>(I.K, rbase + j0, k);
             const int q = j0 >> 3;
             float s = 0.f;
 #pragma unroll
@@ -232,10 +251,24 @@ __global__ __launch_bounds__(kColWaves * kWave) void k_col_sweep_k(const Inst *_
             for (int c = 0; c < 8; ++c) acc[c] = 0.f;
             const int c0 = ctile0 + lane * 8;
             if (c0 < n) {
-                for (int r = r0 + wave; r < r1; r += kColWaves) {
-                    const float ar = ash[r - r0];
+                constexpr int S = kColWaves;
+                int r = r0 + wave;
+                for (; r + 3 * S < r1; r += 4 * S) {
+                    float k0[8], k1[8], k2[8], k3[8];
+                    load8<ST>(I.K, (int64_t)r * kp + c0, k0);
+                    load8<ST>(I.K, (int64_t)(r + S) * kp + c0, k1);
+                    load8<ST>(I.K, (int64_t)(r + 2 * S) * kp + c0, k2);
+                    load8<ST>(I.K, (int64_t)(r + 3 * S) * kp + c0, k3);
+                    const float a0 = ash[r - r0], a1 = ash[r + S - r0];
+                    const float a2 = ash[r + 2 * S - r0], a3 = ash[r + 3 * S - r0];
+#pragma unroll
+                    for (int c = 0; c < 8; ++c)
+                        acc[c] = fmaf(k3[c], a3, fmaf(k2[c], a2, fmaf(k1[c], a1, fmaf(k0[c], a0, acc[c]))));
+                }
+                for (; r < r1; r += S) {
                     float k[8];
                     load8<ST>(I.K, (int64_t)r * kp + c0, k);
+                    const float ar = ash[r - r0];
 #pragma unroll
                     for (int c = 0; c < 8; ++c) acc[c] = fmaf(k[c], ar, acc[c]);
                 }
@@ -361,20 +394,33 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_check_k_rows(const Inst *
 
 template <int ST>
 __global__ __launch_bounds__(256) void k_check_k_cols(const Inst *__restrict__ insts, int inst,
-                                                      double *csum) {
+                                                      double *part) {
     const Inst &I = insts[inst];
     const int n = I.n, kp = I.kpitch;
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int seg = blockIdx.y;
     if (j >= n) return;
+    const int r0 = seg * I.seg_rows, r1 = min(n, r0 + I.seg_rows);
     const int par = I.ctl->iter & 1;
     double s = 0.0;
-    for (int r = 0; r < n; ++r) {
+    for (int r = r0; r < r1; ++r) {
         const int64_t o = (int64_t)r * kp + j;
         const float k = ST == SK_K_BF16
                             ? __uint_as_float((uint32_t)reinterpret_cast<const uint16_t *>(I.K)[o] << 16)
                             : reinterpret_cast<const float *>(I.K)[o];
         s += (double)k * (double)I.a[par][r];
     }
+    part[(int64_t)seg * n + j] = s;
+}
+
+__global__ __launch_bounds__(256) void k_check_k_cols_sum(const Inst *__restrict__ insts, int inst,
+                                                          const double *part, double *csum) {
+    const Inst &I = insts[inst];
+    const int n = I.n;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    double s = 0.0;
+    for (int seg = 0; seg < I.nseg; ++seg) s += part[(int64_t)seg * n + j];
     csum[j] = s * (double)I.b[j];
 }
 
@@ -422,18 +468,20 @@ static hipError_t launch_absorb_done(const Inst *d_insts, int count, hipStream_t
     return hipGetLastError();
 }
 hipError_t launch_check_k(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid, int inst,
-                          int n, int storage, double *rsum, double *csum, hipStream_t st) {
+                          int n, int nseg, int storage, double *rsum, double *part, double *csum,
+                          hipStream_t st) {
+    const dim3 cg((n + 255) / 256, nseg);
     if (storage == SK_K_BF16) {
         hipLaunchKernelGGL(k_check_k_rows<SK_K_BF16>, dim3(grid), dim3(kRowWaves * kWave), 0, st,
                            d_insts, d_units, nunits, rsum);
-        hipLaunchKernelGGL(k_check_k_cols<SK_K_BF16>, dim3((n + 255) / 256), dim3(256), 0, st,
-                           d_insts, inst, csum);
+        hipLaunchKernelGGL(k_check_k_cols<SK_K_BF16>, cg, dim3(256), 0, st, d_insts, inst, part);
     } else {
         hipLaunchKernelGGL(k_check_k_rows<SK_K_F32>, dim3(grid), dim3(kRowWaves * kWave), 0, st,
                            d_insts, d_units, nunits, rsum);
-        hipLaunchKernelGGL(k_check_k_cols<SK_K_F32>, dim3((n + 255) / 256), dim3(256), 0, st,
-                           d_insts, inst, csum);
+        hipLaunchKernelGGL(k_check_k_cols<SK_K_F32>, cg, dim3(256), 0, st, d_insts, inst, part);
     }
+    hipLaunchKernelGGL(k_check_k_cols_sum, dim3((n + 255) / 256), dim3(256), 0, st, d_insts, inst,
+                       part, csum);
     return hipGetLastError();
 }
 
@@ -491,7 +539,7 @@ sk_status run_single_k(sk_ctx *ctx, Batch &B, const sk_params *prm) {
                 const int n = I.n;
                 ctx->prof.begin(ctx->stream, KID_CHECK_ROWS);
                 KCHK(launch_check_k(B.d_insts, B.d_rows, (int)B.h_rows.size(), B.row_grid, 0, n,
-                                    storage, B.d_rsum, B.d_csum, ctx->stream));
+                                    I.nseg, storage, B.d_rsum, B.d_cpart, B.d_csum, ctx->stream));
                 ctx->prof.end(ctx->stream);
                 std::vector<double> r(n), cs(n);
                 KCHK(hipMemcpyAsync(r.data(), B.d_rsum, 8 * (size_t)n, hipMemcpyDeviceToHost,
@@ -525,18 +573,51 @@ sk_status run_single_k(sk_ctx *ctx, Batch &B, const sk_params *prm) {
             if ((st = absorb(ctx, B, storage)) != SK_OK) return st;
             continue;
         }
+        // a block of K iterations; afterwards the launches past the point
+        // where the stage ended are tagged (detection / idle)
+        const size_t pstart = ctx->prof.pending.size();
+        const int64_t it0 = c.iters_total;
+        const int stage0 = c.stage;
+        const Inst &I0 = B.h_insts[0];
         for (int k = 0; k < check; ++k) {
-            ctx->prof.begin(ctx->stream, KID_ROW_K);
-            KCHK(launch_row_sweep_k(B.d_insts, B.d_rows, (int)B.h_rows.size(), B.row_grid,
-                                    B.row_lds_k, storage, ctx->stream));
-            ctx->prof.end(ctx->stream);
-            ctx->prof.begin(ctx->stream, KID_COL_K);
-            KCHK(launch_col_sweep_k(B.d_insts, B.d_cols, (int)B.h_cols.size(), B.col_grid, storage,
-                                    ctx->stream));
-            ctx->prof.end(ctx->stream);
+            if (I0.fused) {
+                ctx->prof.begin(ctx->stream, KID_FUSED);
+                KCHK(launch_fused(B.d_insts, 0, I0.n, I0.fused_grid, storage, ctx->stream));
+                ctx->prof.end(ctx->stream);
+                ctx->prof.begin(ctx->stream, KID_FUSED_COLS);
+                KCHK(launch_fused_cols(B.d_insts, 0, I0.n, I0.fused_grid, storage, ctx->stream));
+                ctx->prof.end(ctx->stream);
+            } else {
+                ctx->prof.begin(ctx->stream, KID_ROW_K);
+                KCHK(launch_row_sweep_k(B.d_insts, B.d_rows, (int)B.h_rows.size(), B.row_grid_k,
+                                        B.row_lds_k, storage, ctx->stream));
+                ctx->prof.end(ctx->stream);
+                ctx->prof.begin(ctx->stream, KID_COL_K);
+                KCHK(launch_col_sweep_k(B.d_insts, B.d_cols, (int)B.h_cols.size(), B.col_grid,
+                                        storage, ctx->stream));
+                ctx->prof.end(ctx->stream);
+            }
             ctx->prof.begin(ctx->stream, KID_ITER_END);
             KCHK(launch_iter_end(B.d_insts, B.count, ctx->stream));
             ctx->prof.end(ctx->stream);
+        }
+        if (ctx->prof.on) {
+            if ((st = read_ctl(ctx, B)) != SK_OK) return st;
+            const Ctl &c2 = ctx->h_ctl[0];
+            const int64_t did = c2.iters_total - it0;
+            // the stage ended inside this block by convergence: one detection triple
+            const bool ended = c2.state != ST_RUNNING || c2.stage != stage0;
+            const bool conv = ended && c2.stage_iters[stage0] < prm->max_iters_per_stage;
+            const int64_t det = conv ? did : -1;
+            const int64_t work = did + (conv ? 1 : 0);
+            auto tag = [&](int dk, int ik) {
+                return [=](int64_t t) { return t == det ? dk : (t >= work ? ik : -1); };
+            };
+            ctx->prof.retag(pstart, KID_ROW_K, tag(KID_ROW_K_DETECT, KID_ROW_K_IDLE));
+            ctx->prof.retag(pstart, KID_COL_K, tag(KID_COL_K_DETECT, KID_COL_K_IDLE));
+            ctx->prof.retag(pstart, KID_ITER_END, tag(KID_ITER_END_DETECT, KID_ITER_END_IDLE));
+            ctx->prof.retag(pstart, KID_FUSED, tag(KID_FUSED_DETECT, KID_FUSED_IDLE));
+            ctx->prof.retag(pstart, KID_FUSED_COLS, tag(KID_FUSED_COLS_DETECT, KID_FUSED_COLS_IDLE));
         }
     }
     return SK_OK;

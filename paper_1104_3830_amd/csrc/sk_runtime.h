@@ -16,7 +16,7 @@ struct TilePlan {
     int tile_cols, ntiles, seg_rows, nseg;
 };
 TilePlan plan_tiles(int32_t n, int vec8);
-size_t instance_bytes(int32_t n, int vec8, int storage);
+size_t instance_bytes(int32_t n, int vec8, int storage, int fused = 0);
 size_t shared_bytes(int32_t count, const int32_t *n);
 
 // A set of instances swept together, with its device tables.
@@ -30,10 +30,12 @@ struct Batch {
     RowUnit *d_rows = nullptr;
     ColUnit *d_cols = nullptr;
     double *d_rsum = nullptr, *d_rmax = nullptr, *d_csum = nullptr;
+    double *d_cpart = nullptr;     // FP64 column partials [nseg][n] of the checked instance
+    Ctl *d_ctl_all = nullptr;      // gathered control blocks (one copy per check)
     int64_t *d_counts = nullptr;
     size_t row_lds = 0;
     size_t row_lds_k = 0;
-    int row_grid = 1, col_grid = 1;
+    int row_grid = 1, col_grid = 1, row_grid_k = 1;
 };
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -55,7 +57,11 @@ struct Server;
 
 enum KernelId {
     KID_INIT, KID_ROW, KID_COL, KID_ITER_END, KID_CHECK_ROWS, KID_CHECK_COLS, KID_PRUNE_COUNT,
-    KID_SCAN, KID_PRUNE_FILL, KID_ABSORB, KID_ROW_K, KID_COL_K, KID_FOLD_K, KID_COUNT
+    KID_SCAN, KID_PRUNE_FILL, KID_ABSORB, KID_ROW_K, KID_COL_K, KID_FOLD_K,
+    KID_ROW_DETECT, KID_COL_DETECT, KID_ITER_END_DETECT, KID_ROW_IDLE, KID_COL_IDLE,
+    KID_ITER_END_IDLE, KID_ROW_K_DETECT, KID_COL_K_DETECT, KID_ROW_K_IDLE, KID_COL_K_IDLE,
+    KID_FUSED, KID_FUSED_COLS, KID_FUSED_DETECT, KID_FUSED_COLS_DETECT, KID_FUSED_IDLE,
+    KID_FUSED_COLS_IDLE, KID_COUNT
 };
 extern const char *kKernelNames[KID_COUNT];
 
@@ -71,6 +77,17 @@ struct Profiler {
     void end(hipStream_t st);
     void drain();   // call after the stream is synchronised
     void reset();
+    // Re-tags the pending launches of kernel `kid` recorded at or after
+    // position `start`: occurrence t (0-based) gets tag(t) (or stays if -1).
+    template <class F>
+    void retag(size_t start, int kid, F tag) {
+        int64_t t = 0;
+        for (size_t q = start; q < pending.size(); ++q) {
+            if (pending[q].first != kid) continue;
+            const int nk = tag(t++);
+            if (nk >= 0) pending[q].first = nk;
+        }
+    }
     ~Profiler();
     int cur_id = -1;
     hipEvent_t cur_start = nullptr;

@@ -33,12 +33,13 @@ TilePlan plan_tiles(int32_t n, int vec8) {
 }
 
 
-size_t instance_bytes(int32_t n, int vec8, int storage) {
+size_t instance_bytes(int32_t n, int vec8, int storage, int fused) {
     TilePlan t = plan_tiles(n, vec8);
     size_t b = 0;
     b += align_up(sizeof(int32_t) * n, 256) * 3;  // F[2], G
     b += align_up(sizeof(float) * n, 256) * 3;    // phi[2], gam
-    b += align_up(sizeof(float) * (size_t)t.nseg * n, 256);
+    const size_t slots = fused ? std::max(t.nseg, kFusedSlots) : t.nseg;
+    b += align_up(sizeof(float) * slots * n, 256);
     b += align_up(sizeof(uint32_t) * t.ntiles, 256);
     b += align_up(sizeof(uint32_t) * n, 256);
     b += align_up(sizeof(Ctl), 256);
@@ -52,18 +53,21 @@ size_t instance_bytes(int32_t n, int vec8, int storage) {
 }
 
 size_t shared_bytes(int32_t count, const int32_t *n) {
-    int64_t rows = 0, cols = 0, nmax = 0;
+    int64_t rows = 0, cols = 0, nmax = 0, cpart = 0;
     for (int k = 0; k < count; ++k) {
         TilePlan t = plan_tiles(n[k], (n[k] % 8) == 0);
+        cpart = std::max<int64_t>(cpart, (int64_t)t.nseg * n[k]);
         rows += (n[k] + kRowWaves - 1) / kRowWaves;
         cols += (int64_t)t.ntiles * t.nseg;
         nmax = std::max<int64_t>(nmax, n[k]);
     }
     size_t b = 0;
     b += align_up(sizeof(Inst) * count, 256);
+    b += align_up(sizeof(Ctl) * count, 256);
     b += align_up(sizeof(RowUnit) * rows, 256);
     b += align_up(sizeof(ColUnit) * cols, 256);
     b += align_up(sizeof(double) * nmax, 256) * 3;  // FP64 check: rsum, rmax, csum
+    b += align_up(sizeof(double) * (size_t)cpart, 256);  // FP64 column partials
     b += align_up(sizeof(int64_t) * (nmax + 1), 256);  // prune row counts
     return b;
 }
@@ -73,7 +77,12 @@ size_t shared_bytes(int32_t count, const int32_t *n) {
 const char *kKernelNames[KID_COUNT] = {"init", "row_sweep", "col_sweep", "iter_end",
                                        "check_rows", "check_cols", "prune_count", "scan",
                                        "prune_fill", "absorb", "row_sweep_k", "col_sweep_k",
-                                       "fold_k"};
+                                       "fold_k", "row_sweep:detect", "col_sweep:detect",
+                                       "iter_end:detect", "row_sweep:idle", "col_sweep:idle",
+                                       "iter_end:idle", "row_sweep_k:detect", "col_sweep_k:detect",
+                                       "row_sweep_k:idle", "col_sweep_k:idle", "fused",
+                                       "fused_cols", "fused:detect", "fused_cols:detect",
+                                       "fused:idle", "fused_cols:idle"};
 
 hipEvent_t Profiler::take() {
     if (!pool.empty()) {
@@ -175,7 +184,7 @@ size_t sk_potentials_bytes(int32_t n) { return n > 0 ? (size_t)16 * n : 0; }
 
 size_t sk_arena_bytes(int32_t n, int32_t storage) {
     if (n <= 0) return 0;
-    return instance_bytes(n, (n % 8) == 0, storage) + shared_bytes(1, &n) + 4096;
+    return instance_bytes(n, (n % 8) == 0, storage, 1) + shared_bytes(1, &n) + 4096;
 }
 
 size_t sk_batch_arena_bytes(int32_t count, const int32_t *n, int32_t storage) {
@@ -278,13 +287,16 @@ bool sk::carve_instance(Bump &bump, const int16_t *W, int64_t pitch, int32_t nn,
     I.tol = (float)prm->tol;
     I.max_iters = prm->max_iters_per_stage;
     I.storage = prm->storage;
+    I.fused = prm->fused ? 1 : 0;
+    I.fused_grid = std::min(kFusedSlots, std::max(1, nn / 2));
     for (int b = 0; b < 2; ++b) {
         I.F[b] = bump.take<int32_t>(nn);
         I.phi[b] = bump.take<float>(nn);
     }
     I.G = bump.take<int32_t>(nn);
     I.gam = bump.take<float>(nn);
-    I.colpart = bump.take<float>((size_t)t.nseg * nn);
+    const size_t slots = I.fused ? std::max(t.nseg, kFusedSlots) : t.nseg;
+    I.colpart = bump.take<float>(slots * nn);
     I.tilecnt = bump.take<uint32_t>(t.ntiles);
     I.rescue = bump.take<uint32_t>(nn);
     I.ctl = bump.take<Ctl>(1);
@@ -309,21 +321,26 @@ sk_status sk::finish_tables(sk_ctx *ctx, Bump &bump, Batch &B) {
     B.h_rows.clear();
     B.h_cols.clear();
     B.nmax = 0;
+    int64_t cpart = 0;
     for (int k = 0; k < B.count; ++k) {
         const Inst &I = B.h_insts[k];
+        cpart = std::max<int64_t>(cpart, (int64_t)I.nseg * I.n);
         for (int r = 0; r < I.n; r += kRowWaves) B.h_rows.push_back(RowUnit{k, r});
         for (int s = 0; s < I.nseg; ++s)
             for (int tt = 0; tt < I.ntiles; ++tt) B.h_cols.push_back(ColUnit{k, tt, s, 0});
         B.nmax = std::max(B.nmax, I.n);
     }
     B.d_insts = bump.take<Inst>(B.count);
+    B.d_ctl_all = bump.take<Ctl>(B.count);
     B.d_rows = bump.take<RowUnit>(B.h_rows.size());
     B.d_cols = bump.take<ColUnit>(B.h_cols.size());
     B.d_rsum = bump.take<double>(B.nmax);
     B.d_rmax = bump.take<double>(B.nmax);
     B.d_csum = bump.take<double>(B.nmax);
     B.d_counts = bump.take<int64_t>(B.nmax + 1);
-    if (!B.d_insts || !B.d_rows || !B.d_cols || !B.d_rsum || !B.d_rmax || !B.d_csum || !B.d_counts)
+    B.d_cpart = bump.take<double>(cpart);
+    if (!B.d_insts || !B.d_rows || !B.d_cols || !B.d_rsum || !B.d_rmax || !B.d_csum || !B.d_counts ||
+        !B.d_cpart || !B.d_ctl_all)
         return fail(ctx, SK_ENOMEM, "arena too small for the batch tables");
     // grids: row sweep stages n columns of potentials (8 B each) in LDS
     const size_t lds = sizeof(float2) * (size_t)B.nmax;
@@ -331,6 +348,8 @@ sk_status sk::finish_tables(sk_ctx *ctx, Bump &bump, Batch &B) {
     B.row_lds = lds;
     B.row_lds_k = sizeof(float) * (size_t)((B.nmax + 7) / 8 * 8);
     B.row_grid = (int)std::max<size_t>(1, std::min<size_t>(B.h_rows.size(), (size_t)ctx->num_cus * per_cu));
+    const int per_cu_k = B.row_lds_k <= 65536 ? 2 : 1;
+    B.row_grid_k = (int)std::max<size_t>(1, std::min<size_t>(B.h_rows.size(), (size_t)ctx->num_cus * per_cu_k));
     B.col_grid = (int)std::max<size_t>(1, std::min<size_t>(B.h_cols.size(), (size_t)ctx->num_cus * 8));
     return SK_OK;
 }
@@ -357,22 +376,9 @@ sk_status sk::upload_batch(sk_ctx *ctx, Batch &B) {
 
 // Initial control blocks and the input scan (cold start or warm start).
 sk_status sk::start_batch(sk_ctx *ctx, Batch &B, const sk_params *prm, void *const *pot_in) {
-    std::vector<Ctl> ctl(B.count);
-    for (int k = 0; k < B.count; ++k) {
-        Ctl &c = ctl[k];
-        memset(&c, 0, sizeof c);
-        c.state = ST_RUNNING;
-        c.stage = 0;
-        c.p = prm->p_ladder[0];
-        c.iter = 0;
-        c.last_res = INFINITY;
-        // the host copy lives in pinned memory so the copy is asynchronous
-        ctx->h_ctl[k] = c;
-        HIPCHK(ctx, hipMemcpyAsync(B.h_insts[k].ctl, &ctx->h_ctl[k], sizeof(Ctl),
-                                   hipMemcpyHostToDevice, ctx->stream));
-        HIPCHK(ctx, hipMemsetAsync(B.h_insts[k].tilecnt, 0,
-                                   sizeof(uint32_t) * B.h_insts[k].ntiles, ctx->stream));
-        if (prm->warm_start) {
+    HIPCHK(ctx, launch_reset_ctl(B.d_insts, nullptr, B.count, ctx->stream));
+    if (prm->warm_start) {
+        for (int k = 0; k < B.count; ++k) {
             const int nn = B.h_insts[k].n;
             const char *src = (const char *)pot_in[k];
             HIPCHK(ctx, hipMemcpyAsync(B.h_insts[k].F[0], src, 4 * (size_t)nn,
@@ -391,15 +397,29 @@ sk_status sk::start_batch(sk_ctx *ctx, Batch &B, const sk_params *prm, void *con
 }
 
 sk_status sk::read_ctl(sk_ctx *ctx, Batch &B) {
-    for (int k = 0; k < B.count; ++k)
-        HIPCHK(ctx, hipMemcpyAsync(&ctx->h_ctl[k], B.h_insts[k].ctl, sizeof(Ctl),
+    if (B.count == 1) {
+        HIPCHK(ctx, hipMemcpyAsync(&ctx->h_ctl[0], B.h_insts[0].ctl, sizeof(Ctl),
                                    hipMemcpyDeviceToHost, ctx->stream));
+    } else {
+        HIPCHK(ctx, launch_gather_ctl(B.d_insts, B.count, B.d_ctl_all, ctx->stream));
+        HIPCHK(ctx, hipMemcpyAsync(ctx->h_ctl, B.d_ctl_all, sizeof(Ctl) * B.count,
+                                   hipMemcpyDeviceToHost, ctx->stream));
+    }
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     return SK_OK;
 }
 
 // One Sinkhorn iteration over every running instance of the batch.
 sk_status sk::iterate_i16(sk_ctx *ctx, Batch &B) {
+    if (B.count == 1 && B.h_insts[0].fused) {
+        const Inst &I = B.h_insts[0];
+        HIPCHK(ctx, PROF(ctx, KID_FUSED, launch_fused(B.d_insts, 0, I.n, I.fused_grid, SK_W_I16,
+                                                      ctx->stream)));
+        HIPCHK(ctx, PROF(ctx, KID_FUSED_COLS, launch_fused_cols(B.d_insts, 0, I.n, I.fused_grid,
+                                                                SK_W_I16, ctx->stream)));
+        HIPCHK(ctx, PROF(ctx, KID_ITER_END, launch_iter_end(B.d_insts, B.count, ctx->stream)));
+        return SK_OK;
+    }
     HIPCHK(ctx, PROF(ctx, KID_ROW, launch_row_sweep(B.d_insts, B.d_rows, (int)B.h_rows.size(), B.row_grid, B.row_lds,
                                  ctx->stream)));
     HIPCHK(ctx, PROF(ctx, KID_COL, launch_col_sweep(B.d_insts, B.d_cols, (int)B.h_cols.size(), B.col_grid,
@@ -409,10 +429,13 @@ sk_status sk::iterate_i16(sk_ctx *ctx, Batch &B) {
 }
 
 // Runs the ladder of every instance to completion (device-side stopping).
+// With timing on, launches are tagged afterwards: a triple (row, column,
+// end) either did an iteration, or only detected that a stage had converged
+// (its column sweep does no sums), or came after every instance finished.
 sk_status sk::run_batch_i16(sk_ctx *ctx, Batch &B, const sk_params *prm) {
     const int check = std::max(1, prm->check_every);
-    int64_t bound = 0;  // every iteration advances an instance or ends a stage
-    bound = (prm->max_iters_per_stage + 1) * prm->n_p + 1;
+    const int64_t bound = (prm->max_iters_per_stage + 1) * prm->n_p + 1;
+    const size_t pstart = ctx->prof.pending.size();
     int64_t launched = 0;
     for (;;) {
         for (int k = 0; k < check; ++k) {
@@ -426,6 +449,40 @@ sk_status sk::run_batch_i16(sk_ctx *ctx, Batch &B, const sk_params *prm) {
         for (int k = 0; k < B.count; ++k) running |= ctx->h_ctl[k].state == ST_RUNNING;
         if (!running) break;
         if (launched > bound) return fail(ctx, SK_EDEVICE, "stage controller did not terminate");
+    }
+    if (ctx->prof.on) {
+        // triple index of each convergence detection, and the number of
+        // triples that advanced some instance
+        std::vector<int64_t> detect;
+        int64_t working = 0;
+        for (int k = 0; k < B.count; ++k) {
+            const Ctl &c = ctx->h_ctl[k];
+            int64_t t = 0;
+            for (int s = 0; s <= std::min(c.stage, prm->n_p - 1); ++s) {
+                t += c.stage_iters[s];
+                const bool conv = c.stage_iters[s] < prm->max_iters_per_stage &&
+                                  (s < c.stage || c.state == ST_DONE);
+                if (conv) {
+                    if (B.count == 1) detect.push_back(t);
+                    t += 1;
+                }
+            }
+            working = std::max(working, t);
+        }
+        if (B.count > 1) detect.clear();
+        auto tagger = [&](int det, int idle) {
+            return [&, det, idle](int64_t t) {
+                if (t >= working) return idle;
+                for (int64_t d : detect)
+                    if (d == t) return det;
+                return -1;
+            };
+        };
+        ctx->prof.retag(pstart, KID_ROW, tagger(KID_ROW_DETECT, KID_ROW_IDLE));
+        ctx->prof.retag(pstart, KID_COL, tagger(KID_COL_DETECT, KID_COL_IDLE));
+        ctx->prof.retag(pstart, KID_ITER_END, tagger(KID_ITER_END_DETECT, KID_ITER_END_IDLE));
+        ctx->prof.retag(pstart, KID_FUSED, tagger(KID_FUSED_DETECT, KID_FUSED_IDLE));
+        ctx->prof.retag(pstart, KID_FUSED_COLS, tagger(KID_FUSED_COLS_DETECT, KID_FUSED_COLS_IDLE));
     }
     return SK_OK;
 }
@@ -443,7 +500,7 @@ sk_status sk::check_fp64(sk_ctx *ctx, Batch &B, int k, sk_report *rep) {
     const int grid = std::min(nunits, ctx->num_cus * 2);
     HIPCHK(ctx, PROF(ctx, KID_CHECK_ROWS, launch_check_rows(B.d_insts, B.d_rows + first, nunits, grid, B.d_rsum, B.d_rmax,
                                   ctx->stream)));
-    HIPCHK(ctx, PROF(ctx, KID_CHECK_COLS, launch_check_cols(B.d_insts, k, nn, B.d_csum, ctx->stream)));
+    HIPCHK(ctx, PROF(ctx, KID_CHECK_COLS, launch_check_cols(B.d_insts, k, nn, I.nseg, B.d_cpart, B.d_csum, ctx->stream)));
     std::vector<double> rsum(nn), rmax(nn), csum(nn);
     std::vector<int32_t> G(nn);
     std::vector<float> gam(nn);
@@ -532,6 +589,10 @@ sk_status sk::scale_impl(sk_ctx *ctx, int count, const int16_t *const *W, const 
     }
     if (prm->storage != SK_W_I16 && count != 1)
         return fail(ctx, SK_EINVAL, "stored-K storages are single-instance");
+    if (prm->fused && count != 1)
+        return fail(ctx, SK_EINVAL, "the single-pass iteration is single-instance");
+    if (prm->fused && prm->storage == SK_W_I16 && (n[0] % 8 != 0 || (uintptr_t)W[0] % 16 != 0))
+        return fail(ctx, SK_EINVAL, "the single-pass iteration over int16 W needs n %% 8 == 0");
     if ((st = check_range(ctx, prm)) != SK_OK) return st;
     HIPCHK(ctx, hipSetDevice(ctx->device));
     Bump bump{ctx->arena, ctx->arena_bytes};

@@ -73,7 +73,9 @@ struct Request {
     uint64_t id = 0;
     int32_t n = 0;
     sk_params prm{};
-    int16_t *staging = nullptr;  // pinned host copy of W
+    int16_t *staging = nullptr;  // host copy of W (in the pinned ring, or heap)
+    size_t ring_off = 0;         // offset in the pinned ring
+    bool in_ring = false;
     size_t off = 0, len = 0;     // device region in the arena
     Inst inst{};
     int phase = 0;               // 0 queued, 1 active, 2 solving, 3 done
@@ -105,8 +107,24 @@ struct Server {
     std::vector<RowUnit> init_units;
     RowUnit *d_init_units = nullptr;
     std::string error;
-    int iters_per_tick = 4;
+    int iters_per_tick = 16;
+    char *ring = nullptr;        // pinned staging for submitted W
+    size_t ring_bytes = 0;
+    RangeAlloc ring_alloc;
+    int *d_fresh = nullptr;      // indices of admitted instances (device)
 };
+
+static const size_t kRingBytes = size_t(512) << 20;
+
+static void release_staging(Server *S, Request *r) {
+    if (!r->staging) return;
+    if (r->in_ring) {
+        S->ring_alloc.release(r->ring_off, (size_t)r->n * r->n * 2);
+    } else {
+        free(r->staging);
+    }
+    r->staging = nullptr;
+}
 
 static const size_t kTablesBytes = size_t(64) << 20;
 
@@ -153,6 +171,7 @@ static sk_status rebuild(Server *S) {
     Bump tb{ctx->arena, S->tables_len};
     // the first part of the tables region holds the init-unit table
     S->d_init_units = tb.take<RowUnit>(kMaxN / kRowWaves * 64);
+    S->d_fresh = tb.take<int>(kMaxBatch);
     sk_status st = finish_tables(ctx, tb, S->B);
     if (st != SK_OK) return st;
     return upload_batch(ctx, S->B);
@@ -271,23 +290,18 @@ static void serve_loop(Server *S) {
             st = rebuild(S);
             // cold start of the new instances only
             S->init_units.clear();
+            std::vector<int> idx;
             for (size_t q = 0; q < fresh.size(); ++q) {
                 const int k = base + (int)q;
-                Ctl c;
-                memset(&c, 0, sizeof c);
-                c.state = ST_RUNNING;
-                c.p = fresh[q]->prm.p_ladder[0];
-                c.last_res = INFINITY;
-                ctx->h_ctl[k] = c;
-                if (e == hipSuccess)
-                    e = hipMemcpyAsync(S->B.h_insts[k].ctl, &ctx->h_ctl[k], sizeof(Ctl),
-                                       hipMemcpyHostToDevice, ctx->stream);
-                if (e == hipSuccess)
-                    e = hipMemsetAsync(S->B.h_insts[k].tilecnt, 0,
-                                       sizeof(uint32_t) * S->B.h_insts[k].ntiles, ctx->stream);
+                idx.push_back(k);
                 for (int r0 = 0; r0 < fresh[q]->n; r0 += kRowWaves)
                     S->init_units.push_back(RowUnit{k, r0});
             }
+            if (e == hipSuccess && st == SK_OK)
+                e = hipMemcpyAsync(S->d_fresh, idx.data(), sizeof(int) * idx.size(),
+                                   hipMemcpyHostToDevice, ctx->stream);
+            if (e == hipSuccess && st == SK_OK)
+                e = launch_reset_ctl(S->B.d_insts, S->d_fresh, (int)idx.size(), ctx->stream);
             size_t done = 0;
             while (e == hipSuccess && st == SK_OK && done < S->init_units.size()) {
                 const size_t chunk = std::min<size_t>(S->init_units.size() - done,
@@ -301,9 +315,9 @@ static void serve_loop(Server *S) {
                 if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
                 done += chunk;
             }
-            for (Request *r : fresh) {
-                (void)hipHostFree(r->staging);
-                r->staging = nullptr;
+            {
+                std::lock_guard<std::mutex> g(S->mu);
+                for (Request *r : fresh) release_staging(S, r);
             }
             dirty = false;
         } else if (dirty) {
@@ -359,6 +373,12 @@ static Server *ensure_server(sk_ctx *ctx) {
     S->ralloc.init(align_up(S->tables_len, 256), ctx->arena_bytes);
     const char *env = getenv("SK_SERVE_ITERS_PER_TICK");
     if (env && atoi(env) > 0) S->iters_per_tick = atoi(env);
+    if (hipHostMalloc((void **)&S->ring, kRingBytes, hipHostMallocDefault) == hipSuccess) {
+        S->ring_bytes = kRingBytes;
+        S->ring_alloc.init(0, kRingBytes);
+    } else {
+        S->ring = nullptr;
+    }
     ctx->server = S;
     S->th = std::thread(serve_loop, S);
     for (int k = 0; k < 4; ++k) S->solvers.emplace_back(solver_loop, S);
@@ -378,9 +398,10 @@ void serve_stop(sk_ctx *ctx) {
     for (auto &t : S->solvers)
         if (t.joinable()) t.join();
     for (auto &kv : S->reqs) {
-        if (kv.second->staging) (void)hipHostFree(kv.second->staging);
+        release_staging(S, kv.second);
         delete kv.second;
     }
+    if (S->ring) (void)hipHostFree(S->ring);
     delete S;
     ctx->server = nullptr;
 }
@@ -410,20 +431,30 @@ extern "C" sk_status sk_submit(sk_ctx *ctx, const int16_t *W_host, int32_t n, co
     r->prm = *params;
     r->len = len;
     r->t_submit = std::chrono::steady_clock::now();
-    if (hipHostMalloc((void **)&r->staging, (size_t)n * n * 2, hipHostMallocDefault) != hipSuccess) {
+    {
+        std::lock_guard<std::mutex> g(S->mu);
+        size_t off;
+        if (S->ring && S->ring_alloc.alloc((size_t)n * n * 2, off)) {
+            r->staging = (int16_t *)(S->ring + off);
+            r->ring_off = off;
+            r->in_ring = true;
+        }
+    }
+    if (!r->staging) r->staging = (int16_t *)malloc((size_t)n * n * 2);
+    if (!r->staging) {
         delete r;
-        return fail(ctx, SK_ENOMEM, "pinned staging allocation failed");
+        return fail(ctx, SK_ENOMEM, "host staging allocation failed");
     }
     memcpy(r->staging, W_host, (size_t)n * n * 2);
     {
         std::lock_guard<std::mutex> g(S->mu);
         if (!S->error.empty()) {
-            (void)hipHostFree(r->staging);
+            release_staging(S, r);
             delete r;
             return fail(ctx, SK_EDEVICE, "serving thread stopped: %s", S->error.c_str());
         }
         if (S->queue.size() >= (size_t)kMaxBatch) {
-            (void)hipHostFree(r->staging);
+            release_staging(S, r);
             delete r;
             return SK_EAGAIN;
         }

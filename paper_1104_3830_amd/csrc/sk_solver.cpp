@@ -52,16 +52,89 @@ extern "C" sk_status sk_solve_reduced(const sk_csr *csr, int32_t *perm, int64_t 
         for (int64_t e = rp[i]; e < rp[i + 1]; ++e) m = std::min<int64_t>(m, -(int64_t)w[e]);
         u[i] = m;
     }
-    // greedy start on zero reduced-cost edges
+    // column reduction: v_j = min over edges into j of c_ij - u_i keeps every
+    // reduced cost non-negative and makes more edges tight
+    for (int j = 0; j < n; ++j) v[j] = INF;
     for (int i = 0; i < n; ++i)
         for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
             const int j = col[e];
-            if (row_of[j] < 0 && -(int64_t)w[e] - u[i] - v[j] == 0) {
-                row_of[j] = i;
-                col_of[i] = j;
-                break;
+            v[j] = std::min<int64_t>(v[j], -(int64_t)w[e] - u[i]);
+        }
+    for (int j = 0; j < n; ++j)
+        if (v[j] == INF) return SK_EINFEASIBLE;  // empty column
+    // maximum matching on the tight edges (reduced cost 0), Hopcroft-Karp
+    {
+        std::vector<int64_t> tp(n + 1, 0);
+        std::vector<int32_t> tc;
+        tc.reserve((size_t)csr->nnz / 4 + n);
+        for (int i = 0; i < n; ++i) {
+            for (int64_t e = rp[i]; e < rp[i + 1]; ++e)
+                if (-(int64_t)w[e] - u[i] - v[col[e]] == 0) tc.push_back(col[e]);
+            tp[i + 1] = (int64_t)tc.size();
+        }
+        const int NIL = std::numeric_limits<int>::max();
+        std::vector<int> dist(n), q(n), stack;
+        std::vector<int64_t> it(n);
+        stack.reserve(n);
+        for (;;) {
+            // BFS layers from the free rows
+            int qh = 0, qt = 0;
+            for (int i = 0; i < n; ++i) {
+                if (col_of[i] < 0) {
+                    dist[i] = 0;
+                    q[qt++] = i;
+                } else {
+                    dist[i] = NIL;
+                }
+            }
+            bool found = false;
+            while (qh < qt) {
+                const int i = q[qh++];
+                for (int64_t e = tp[i]; e < tp[i + 1]; ++e) {
+                    const int i2 = row_of[tc[e]];
+                    if (i2 < 0) {
+                        found = true;
+                    } else if (dist[i2] == NIL) {
+                        dist[i2] = dist[i] + 1;
+                        q[qt++] = i2;
+                    }
+                }
+            }
+            if (!found) break;
+            // vertex-disjoint shortest augmenting paths, iterative DFS
+            for (int i = 0; i < n; ++i) it[i] = tp[i];
+            for (int s0 = 0; s0 < n; ++s0) {
+                if (col_of[s0] >= 0 || dist[s0] != 0) continue;
+                stack.clear();
+                stack.push_back(s0);
+                while (!stack.empty()) {
+                    const int i = stack.back();
+                    if (it[i] == tp[i + 1]) {
+                        dist[i] = NIL;  // dead end
+                        stack.pop_back();
+                        continue;
+                    }
+                    const int j = tc[it[i]];
+                    const int i2 = row_of[j];
+                    if (i2 < 0) {
+                        for (int r : stack) {
+                            const int jj = tc[it[r]];
+                            col_of[r] = jj;
+                            row_of[jj] = r;
+                        }
+                        for (int r : stack) dist[r] = NIL;  // used this phase
+                        stack.clear();
+                        break;
+                    }
+                    if (dist[i2] != NIL && dist[i2] == dist[i] + 1) {
+                        stack.push_back(i2);
+                    } else {
+                        ++it[i];
+                    }
+                }
             }
         }
+    }
 
     std::vector<int64_t> dist(n, INF);
     std::vector<int32_t> pred(n, -1);  // row from which column j was reached

@@ -40,8 +40,8 @@ def test_struct_layouts_match_header(tmp_path):
 #include "{HEADER}"
 int main(void) {{
   printf("%zu %zu %zu\\n", sizeof(sk_params), sizeof(sk_report), sizeof(sk_csr));
-  printf("%zu %zu %zu %zu\\n", offsetof(sk_params, tol), offsetof(sk_params, storage),
-         offsetof(sk_params, warm_start), offsetof(sk_report, seconds));
+  printf("%zu %zu %zu %zu %zu\\n", offsetof(sk_params, tol), offsetof(sk_params, storage),
+         offsetof(sk_params, warm_start), offsetof(sk_params, fused), offsetof(sk_report, seconds));
   printf("%zu %zu\\n", offsetof(sk_report, nnz_kept), offsetof(sk_csr, w));
   return 0;
 }}''')
@@ -51,7 +51,7 @@ int main(void) {{
     got = [int(x) for x in out]
     want = [ctypes.sizeof(sk.Params), ctypes.sizeof(sk.Report), ctypes.sizeof(sk.CSR),
             sk.Params.tol.offset, sk.Params.storage.offset, sk.Params.warm_start.offset,
-            sk.Report.seconds.offset, sk.Report.nnz_kept.offset, sk.CSR.w.offset]
+            sk.Params.fused.offset, sk.Report.seconds.offset, sk.Report.nnz_kept.offset, sk.CSR.w.offset]
     assert got == want
 
 

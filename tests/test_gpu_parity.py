@@ -295,3 +295,56 @@ def test_stored_k_path(ctx, storage, n):
     Xk = oracle.scaled_matrix(B, 32, ub_k, vb_k)
     Xr = oracle.scaled_matrix(B, 32, ub_r, vb_r)
     assert np.abs(Xk - Xr).max() < (2e-2 if storage == "bf16" else 1e-4)
+
+
+# ---------------------------------------------------------------- single-pass iteration
+
+@pytest.mark.parametrize("n,p,iters", [(64, 1, 50), (1024, 8, 25), (2048, 32, 10)])
+def test_fused_fixed_iterations_match_oracle(ctx, n, p, iters):
+    """The single-pass iteration gives the oracle's iterate W_iters."""
+    W = skgen.uniform_weights(n, 0, 100 if n <= 1024 else 1000, seed=n + p + 1)
+    B = oracle.log_weights(W)
+    prm = sk.make_params([p], tol=0.0, max_iters=iters, check_every=16, fused=True)
+    res = ctx.scale(dev(W), prm)
+    assert res.report["iters_total"] == iters
+    ub_g, vb_g = bars(res.potentials, n, p)
+    ub_o, vb_o, m, _ = oracle.sinkhorn(B, p, 0.0, iters)
+    Lg, Lo = logx(B, p, ub_g, vb_g), logx(B, p, ub_o, vb_o)
+    sig = Lo > np.log(1e-6)
+    assert np.abs(Lg - Lo)[sig].max() < 1e-4
+    assert np.abs(np.exp(Lg) - np.exp(Lo)).max() < 1e-5
+
+
+@pytest.mark.parametrize("storage", ["i16", "bf16", "f32"])
+def test_fused_matches_split(ctx, storage):
+    n = 2048
+    W, sigma = skgen.planted(n, seed=77)
+    ladder = [1, 2, 4, 8, 16, 32]
+    split = ctx.solve(dev(W), sk.make_params(ladder, tol=1e-5, max_iters=1000, storage=storage))
+    fused = ctx.solve(dev(W), sk.make_params(ladder, tol=1e-5, max_iters=1000, storage=storage,
+                                             fused=True))
+    assert fused["weight"] == split["weight"] == 1050 * n
+    assert np.array_equal(fused["perm"], sigma)
+    a, b = split["report"]["iters_stage"], fused["report"]["iters_stage"]
+    assert all(abs(x - y) <= 1 for x, y in zip(a, b)), (a, b)
+    B = oracle.log_weights(W)
+    Xs = oracle.scaled_matrix(B, 32, *bars(split["potentials"], n, 32))
+    Xf = oracle.scaled_matrix(B, 32, *bars(fused["potentials"], n, 32))
+    assert np.abs(Xs - Xf).max() < 1e-4
+    if fused["report"]["stages_capped"] == 0:
+        assert fused["report"]["residual_fp64"] <= 1e-5
+
+
+def test_fused_cold_start_exact_shift(ctx):
+    n = 96 * 8
+    W = skgen.uniform_weights(n, 0, 1000, seed=8)
+    W[:, 7] = (W[:, 7] // 10).astype(np.int16)
+    W[11, :] = (W[11, :] // 10).astype(np.int16)
+    p = 4
+    res = ctx.scale(dev(W), sk.make_params([p], tol=0.0, max_iters=3, fused=True))
+    B = oracle.log_weights(W)
+    ub_g, vb_g = bars(res.potentials, n, p)
+    ub_o, vb_o, _, _ = oracle.sinkhorn(B, p, 0.0, 3)
+    Lg, Lo = logx(B, p, ub_g, vb_g), logx(B, p, ub_o, vb_o)
+    sig = Lo > np.log(1e-6)
+    assert np.abs(Lg - Lo)[sig].max() < 1e-4
