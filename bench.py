@@ -72,10 +72,25 @@ def parse():
                     help="arrival rate as a multiple of the FIFO loop's capacity")
     ap.add_argument("--fused", action="store_true",
                     help="single-pass iteration (one matrix read per iteration)")
+    ap.add_argument("--trace-summary", metavar="CSV",
+                    help="only summarise a rocprofv3 kernel-trace CSV: per kernel, all dispatches "
+                         "and those longer than 20 us (launches that did work)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (the reference "
                          "kernel for scaling HBM byte counters)")
     return ap.parse_args()
+
+
+def trace_summary(path):
+    import csv
+    per = {}
+    for r in csv.DictReader(open(path)):
+        d = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+        per.setdefault(r["Kernel_Name"].split("(")[0], []).append(d)
+    for k, v in sorted(per.items(), key=lambda kv: -sum(kv[1])):
+        big = [x for x in v if x > 20000]
+        print(f"{k} calls={len(v)} avg_ns={sum(v) / len(v):.0f} calls_over_20us={len(big)} "
+              f"avg_over_20us_ns={(sum(big) / len(big) if big else 0):.0f}")
 
 
 def calibrate_copy():
@@ -236,6 +251,9 @@ def main():
     args = parse()
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.trace_summary:
+        trace_summary(args.trace_summary)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",

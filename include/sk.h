@@ -211,6 +211,15 @@ sk_status sk_scale_batch(sk_ctx *ctx, int32_t count, const int16_t *const *W,
 /* Device arena bytes sk_scale_batch needs for these sizes. */
 size_t sk_batch_arena_bytes(int32_t count, const int32_t *n, int32_t storage);
 
+/* Tile-shape table (process-wide). The column sweep splits the rows of an
+ * instance of size n into segments of seg_rows[k] rows for the first k with
+ * n <= n_max[k] (n_max ascending; seg_rows a multiple of 16 in [16, 1024]);
+ * sizes above the last entry, or an empty table, use the built-in rule.
+ * The shape depends only on n, so an instance's result does not depend on
+ * what else runs with it. Call before any sk_scale / sk_submit; not
+ * thread-safe with running calls. count = 0 restores the built-in rule. */
+sk_status sk_set_tile_table(const int32_t *n_max, const int32_t *seg_rows, int32_t count);
+
 /* Kernel timing (measurement aid, off by default). While enabled, every
  * kernel the context launches is bracketed by HIP events on the context's
  * stream; durations accumulate per kernel name until the next enable.

@@ -25,7 +25,8 @@ SENTINEL = -32768
 
 EXPORTS = ["sk_potentials_bytes", "sk_arena_bytes", "sk_create", "sk_destroy", "sk_last_error",
            "sk_scale", "sk_prune", "sk_solve_reduced", "sk_submit", "sk_poll", "sk_scale_batch",
-           "sk_batch_arena_bytes", "sk_profile_enable", "sk_profile_read"]
+           "sk_batch_arena_bytes", "sk_profile_enable", "sk_profile_read", "sk_set_tile_table"]
+TILE_TABLE = os.path.join(HERE, "tile_table_gfx950.json")
 
 
 class SkError(RuntimeError):
@@ -112,8 +113,28 @@ def lib():
         L.sk_profile_enable.restype = ctypes.c_int
         L.sk_profile_read.argtypes = [vp, ctypes.POINTER(KernelStat), i32]
         L.sk_profile_read.restype = i32
+        L.sk_set_tile_table.argtypes = [ctypes.POINTER(i32), ctypes.POINTER(i32), i32]
+        L.sk_set_tile_table.restype = ctypes.c_int
         _lib = L
+        if os.path.exists(TILE_TABLE) and not os.environ.get("SK_NO_TILE_TABLE"):
+            load_tile_table(TILE_TABLE)
     return _lib
+
+
+def set_tile_table(entries):
+    """entries: list of (n_max, seg_rows), n_max ascending; [] = built-in rule."""
+    nm = (ctypes.c_int32 * max(len(entries), 1))(*[int(a) for a, _ in entries])
+    sr = (ctypes.c_int32 * max(len(entries), 1))(*[int(b) for _, b in entries])
+    st = lib().sk_set_tile_table(nm, sr, len(entries))
+    if st != SK_OK:
+        raise SkError(st, "sk_set_tile_table")
+
+
+def load_tile_table(path):
+    import json
+    with open(path) as f:
+        tab = json.load(f)
+    set_tile_table([(e["n_max"], e["seg_rows"]) for e in tab["entries"]])
 
 
 def make_params(ladder, tol=1e-5, max_iters=20000, check_every=32, threshold=1e-4,

@@ -256,48 +256,15 @@ __global__ __launch_bounds__(kFT) void k_fused(const Inst *__restrict__ insts, i
             for (int c = 0; c < 8; ++c)
                 if (c0[k] + c < n) dst[c0[k] + c] = acc[k][c];
         }
+    // residual (and drift) slot of this workgroup, reduced by the finaliser
     if (t < kFR) {
-        if (iter >= 1 && resmax > 0.f) atomicMax(&ctl->res_bits, __float_as_uint(resmax));
-        if (ST != SK_W_I16 && drift > 0.f) atomicMax(&ctl->drift_bits, __float_as_uint(drift));
+        red[0][t] = resmax;
+        red[1][t] = drift;
     }
-}
-
-// Column step from the fixed slots: C_j = sum over workgroups in order.
-// I16: log v_j <- log v_j - log C_j (exact split kept); stored K: b_j <- b_j / C_j.
-template <int ST>
-__global__ __launch_bounds__(256) void k_fused_cols(const Inst *__restrict__ insts, int inst,
-                                                    int nslots) {
-    const Inst &I = insts[inst];
-    Ctl *ctl = I.ctl;
-    if (ctl->state != ST_RUNNING) return;
-    if (ST != SK_W_I16 && ctl->need_absorb) return;
-    const float res = __uint_as_float(ctl->res_bits);
-    if (ctl->iter >= 1 && res < I.tol) return;  // converged: this iteration is discarded
-    const int n = I.n;
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    float drift = 0.f;
-    if (j < n) {
-        float C = 0.f;
-        for (int s = 0; s < nslots; ++s) C += I.colpart[(int64_t)s * n + j];
-        if (ST == SK_W_I16) {
-            if (C >= kLo && C <= kHi) {
-                const float gn = I.gam[j] - flg2(C) * kLn2f;
-                const float kk = rintf(gn);
-                I.G[j] += (int)kk;
-                I.gam[j] = gn - kk;
-            } else {
-                const unsigned slot = atomicAdd(&ctl->rescue_cnt, 1u);
-                I.rescue[slot] = (uint32_t)j;
-            }
-        } else {
-            const float bn = I.b[j] / fminf(fmaxf(C, kLo), kHi);
-            I.b[j] = fminf(fmaxf(bn, kLo), kHi);
-            drift = fabsf(flg2(I.b[j]));
-        }
-    }
-    if (ST != SK_W_I16) {
-        drift = fwmax(drift);
-        if ((threadIdx.x % kWave) == 0 && drift > 0.f) atomicMax(&ctl->drift_bits, __float_as_uint(drift));
+    __syncthreads();
+    if (t == 0) {
+        I.res_slots[blockIdx.x] = fmaxf(red[0][0], red[0][1]);
+        if (ST != SK_W_I16) I.drift_slots[blockIdx.x] = fmaxf(red[1][0], red[1][1]);
     }
 }
 
@@ -316,18 +283,6 @@ hipError_t launch_fused(const Inst *d_insts, int inst, int n, int grid, int stor
     if (storage == SK_W_I16) return launch_fused_st<SK_W_I16>(d_insts, inst, n, grid, st);
     if (storage == SK_K_BF16) return launch_fused_st<SK_K_BF16>(d_insts, inst, n, grid, st);
     return launch_fused_st<SK_K_F32>(d_insts, inst, n, grid, st);
-}
-
-hipError_t launch_fused_cols(const Inst *d_insts, int inst, int n, int nslots, int storage,
-                             hipStream_t st) {
-    const dim3 g((n + 255) / 256);
-    if (storage == SK_W_I16)
-        hipLaunchKernelGGL(k_fused_cols<SK_W_I16>, g, dim3(256), 0, st, d_insts, inst, nslots);
-    else if (storage == SK_K_BF16)
-        hipLaunchKernelGGL(k_fused_cols<SK_K_BF16>, g, dim3(256), 0, st, d_insts, inst, nslots);
-    else
-        hipLaunchKernelGGL(k_fused_cols<SK_K_F32>, g, dim3(256), 0, st, d_insts, inst, nslots);
-    return hipGetLastError();
 }
 
 }  // namespace sk

@@ -59,7 +59,6 @@ struct Inst {
     int32_t *G;             // column potential, integer part
     float *gam;             // column potential, fraction
     float *colpart;         // [nseg][n] partial column sums
-    uint32_t *tilecnt;      // [ntiles] arrivals per tile in the current column sweep
     uint32_t *rescue;       // [n] list of flagged columns
     Ctl *ctl;
     // stored-K storages
@@ -70,6 +69,10 @@ struct Inst {
     int32_t kpitch;
     int32_t fused;          // single-pass iteration (colpart holds kFusedSlots rows)
     int32_t fused_grid;
+    int32_t ncolslots;      // rows of colpart in use: nseg (sweeps) or fused_grid (single pass)
+    int32_t nresslots;      // residual slots in use: row units (sweeps) or fused_grid
+    float *res_slots;       // per row unit (or workgroup): max |r_i - 1| of the current iterate
+    float *drift_slots;     // stored K: per row unit max |log2 a_i|
 };
 
 // Loads through a global-address-space pointer, so the compiler emits
@@ -90,6 +93,8 @@ __device__ __forceinline__ int16_t gload(const int16_t *p) { return *(const SK_G
 
 struct RowUnit { int32_t inst, row0; };
 struct ColUnit { int32_t inst, tile, seg, pad; };
+struct FinUnit { int32_t inst, group; };  // 64 columns of one instance
+constexpr int kFinCols = 64;
 
 // Kernel launchers (sk_kernels.hip). All enqueue on `st`.
 hipError_t launch_init(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid, int cold,
@@ -99,6 +104,9 @@ hipError_t launch_row_sweep(const Inst *d_insts, const RowUnit *d_units, int nun
 hipError_t launch_col_sweep(const Inst *d_insts, const ColUnit *d_units, int nunits, int grid,
                             hipStream_t st);
 hipError_t launch_iter_end(const Inst *d_insts, int count, hipStream_t st);
+enum : int { kFinOnePass = 1, kFinStoredK = 2 };
+hipError_t launch_col_finalize(const Inst *d_insts, const FinUnit *d_units, int nunits, int grid,
+                               int mode, hipStream_t st);
 hipError_t launch_check_rows(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
                              double *rsum, double *rmax, hipStream_t st);
 hipError_t launch_check_cols(const Inst *d_insts, int inst, int n, int nseg, double *part,
@@ -122,8 +130,6 @@ hipError_t launch_check_k(const Inst *d_insts, const RowUnit *d_units, int nunit
                           hipStream_t st);
 hipError_t launch_fused(const Inst *d_insts, int inst, int n, int grid, int storage,
                         hipStream_t st);
-hipError_t launch_fused_cols(const Inst *d_insts, int inst, int n, int nslots, int storage,
-                             hipStream_t st);
 hipError_t launch_gather_ctl(const Inst *d_insts, int count, Ctl *out, hipStream_t st);
 hipError_t launch_reset_ctl(const Inst *d_insts, const int *idx, int m, hipStream_t st);
 hipError_t set_kernel_attributes();

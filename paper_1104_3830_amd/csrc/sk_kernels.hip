@@ -72,6 +72,26 @@ __device__ __forceinline__ void unit_range(int nunits, int &u0, int &u1) {
 // read 64 consecutive entries for each c (no bank conflicts).
 __device__ __forceinline__ int swz8(int j, int n8) { return (j & 7) * n8 + (j >> 3); }
 
+// Visits the entries of one row: lane-strided 8-wide chunks with 16-byte
+// loads when the instance allows it, single entries otherwise. f(j, w).
+template <class Fn>
+__device__ __forceinline__ void visit_row(const Inst &I, const int16_t *wr, int lane, Fn f) {
+    const int n = I.n;
+    if (I.vec8) {
+        for (int j0 = lane * 8; j0 < n; j0 += 512) {
+            const int4 v = gload(reinterpret_cast<const int4 *>(wr + j0));
+            const int q[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                f(j0 + 2 * c, (int)(short)(q[c] & 0xffff));
+                f(j0 + 2 * c + 1, q[c] >> 16);
+            }
+        }
+    } else {
+        for (int j = lane; j < n; j += kWave) f(j, (int)gload(wr + j));
+    }
+}
+
 // ---------------------------------------------------------------- input scan / cold start
 // Marks instances whose W holds the sentinel and rows with no entry. With
 // cold != 0 it also sets the first-stage start (v_0 = 1, eq. dad1) with the
@@ -96,11 +116,10 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_init(const Inst *__restri
         const int16_t *wr = I.W + (int64_t)row * I.pitch;
         int mx = -32768;
         int sent = 0;
-        for (int j = lane; j < n; j += kWave) {
-            const int w = wr[j];
+        visit_row(I, wr, lane, [&](int, int w) {
             sent |= (w == SK_SENTINEL);
             mx = max(mx, w);
-        }
+        });
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
             mx = max(mx, __shfl_xor(mx, o, kWave));
@@ -263,11 +282,11 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_row_sweep(const Inst *__r
                                                                    const RowUnit *__restrict__ units,
                                                                    int nunits) {
     extern __shared__ float2 lds_pot[];
+    __shared__ float wres[2][kRowWaves];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     int u0, u1;
     unit_range(nunits, u0, u1);
     int cur = -1;
-    float resmax = 0.f;
     for (int u = u0; u < u1; ++u) {
         const RowUnit un = units[u];
         const Inst &I = insts[un.inst];
@@ -276,9 +295,6 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_row_sweep(const Inst *__r
         const int n = I.n;
         const int iter = ctl->iter;
         if (un.inst != cur) {
-            if (cur >= 0 && lane == 0 && resmax > 0.f && insts[cur].ctl->iter >= 1)
-                atomicMax(&insts[cur].ctl->res_bits, __float_as_uint(resmax));
-            resmax = 0.f;
             __syncthreads();
             const int n8 = n >> 3;
             for (int j = threadIdx.x; j < n; j += blockDim.x) {
@@ -289,6 +305,7 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_row_sweep(const Inst *__r
             cur = un.inst;
         }
         const int row = un.row0 + wave;
+        float resmax = 0.f;
         if (row < n) {
             const int par = iter & 1;
             const bool sent = ctl->sent != 0u;
@@ -300,9 +317,16 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_row_sweep(const Inst *__r
                 else row_step_one<false, false>(I, row, par, lane, lds_pot, resmax);
             }
         }
+        // residual slot of this unit (no atomics: the finaliser reduces the slots)
+        const int b = (u - u0) & 1;
+        if (lane == 0) wres[b][wave] = resmax;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float m = 0.f;
+            for (int w = 0; w < kRowWaves; ++w) m = fmaxf(m, wres[b][w]);
+            I.res_slots[un.row0 / kRowWaves] = m;
+        }
     }
-    if (cur >= 0 && lane == 0 && resmax > 0.f && insts[cur].ctl->iter >= 1)
-        atomicMax(&insts[cur].ctl->res_bits, __float_as_uint(resmax));
 }
 
 // ---------------------------------------------------------------- column sweep
@@ -379,7 +403,6 @@ __global__ __launch_bounds__(kColWaves * kWave) void k_col_sweep(const Inst *__r
                                                                    int nunits) {
     __shared__ float red[kColWaves][kColTile8];
     __shared__ float2 rowpot[kMaxSegRows];
-    __shared__ int s_last;
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     int u0, u1;
     unit_range(nunits, u0, u1);
@@ -388,67 +411,129 @@ __global__ __launch_bounds__(kColWaves * kWave) void k_col_sweep(const Inst *__r
         const Inst &I = insts[un.inst];
         Ctl *ctl = I.ctl;
         if (ctl->state != ST_RUNNING) continue;
-        const bool conv = stage_converged(I, ctl);
         const int n = I.n;
         const int npar = (ctl->iter + 1) & 1;  // row potentials written by this iteration's row sweep
         const int tc = I.tile_cols;
         const int ctile0 = un.tile * tc;
         const int ncols = min(tc, n - ctile0);
-        if (!conv) {
-            const int r0 = un.seg * I.seg_rows, r1 = min(n, r0 + I.seg_rows);
-            __syncthreads();
-            for (int r = r0 + (int)threadIdx.x; r < r1; r += blockDim.x)
-                rowpot[r - r0] = make_float2((float)I.F[npar][r], I.phi[npar][r] * kLog2e);
-            __syncthreads();
-            float acc[8];
-            const bool sent = ctl->sent != 0u;
-            if (I.vec8) {
-                if (sent) col_partial<true, true>(I, un.tile, r0, r1, wave, lane, rowpot, acc);
-                else col_partial<false, true>(I, un.tile, r0, r1, wave, lane, rowpot, acc);
-#pragma unroll
-                for (int c = 0; c < 8; ++c) red[wave][lane * 8 + c] = acc[c];
-            } else {
-                if (sent) col_partial<true, false>(I, un.tile, r0, r1, wave, lane, rowpot, acc);
-                else col_partial<false, false>(I, un.tile, r0, r1, wave, lane, rowpot, acc);
-                red[wave][lane] = acc[0];
-            }
-            __syncthreads();
-            float *dst = I.colpart + (int64_t)un.seg * n + ctile0;
-            for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
-                float s = red[0][c];
-#pragma unroll
-                for (int w2 = 1; w2 < kColWaves; ++w2) s += red[w2][c];
-                dst[c] = s;
-            }
-        }
-        // arrival; the last workgroup of this tile finalises it
-        __threadfence();
+        const int r0 = un.seg * I.seg_rows, r1 = min(n, r0 + I.seg_rows);
         __syncthreads();
-        if (threadIdx.x == 0) {
-            const unsigned old = atomicAdd(&I.tilecnt[un.tile], 1u);
-            s_last = (old == (unsigned)(I.nseg - 1));
+        for (int r = r0 + (int)threadIdx.x; r < r1; r += blockDim.x)
+            rowpot[r - r0] = make_float2((float)I.F[npar][r], I.phi[npar][r] * kLog2e);
+        __syncthreads();
+        float acc[8];
+        const bool sent = ctl->sent != 0u;
+        if (I.vec8) {
+            if (sent) col_partial<true, true>(I, un.tile, r0, r1, wave, lane, rowpot, acc);
+            else col_partial<false, true>(I, un.tile, r0, r1, wave, lane, rowpot, acc);
+#pragma unroll
+            for (int c = 0; c < 8; ++c) red[wave][lane * 8 + c] = acc[c];
+        } else {
+            if (sent) col_partial<true, false>(I, un.tile, r0, r1, wave, lane, rowpot, acc);
+            else col_partial<false, false>(I, un.tile, r0, r1, wave, lane, rowpot, acc);
+            red[wave][lane] = acc[0];
         }
         __syncthreads();
-        if (s_last) {
-            __threadfence();
-            if (!conv) {
-                for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
-                    const int j = ctile0 + c;
-                    float T = 0.f;
-                    for (int s = 0; s < I.nseg; ++s)
-                        T += __builtin_nontemporal_load(I.colpart + (int64_t)s * n + j);
-                    if (T >= kSafeLo && T <= kSafeHi) {
-                        const float gn = -lg2(T) * kLn2;
-                        const float k = rintf(gn);
-                        I.G[j] += (int)k;
-                        I.gam[j] = gn - k;
-                    } else {
-                        const unsigned slot = atomicAdd(&ctl->rescue_cnt, 1u);
-                        I.rescue[slot] = (uint32_t)j;
-                    }
+        float *dst = I.colpart + (int64_t)un.seg * n + ctile0;
+        for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
+            float s = red[0][c];
+#pragma unroll
+            for (int w2 = 1; w2 < kColWaves; ++w2) s += red[w2][c];
+            dst[c] = s;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- column step (finalise)
+// Workgroup = 64 columns of one instance, four threads per column. It reduces
+// the residual slots of the current iterate (stopping test; group 0 publishes
+// the value for the end-of-iteration kernel), and unless the stage has
+// converged adds each column's fixed slots in slot order and applies the
+// column step (eq. dad3):
+//   log-domain sweeps:   slots hold sum_i exp(p w_ij + log u_i + G_j):  gam_j <- -log C_j
+//   log-domain 1 pass:   slots hold the column sum of the iterate:       gam_j <- gam_j - log C_j
+//   stored K sweeps:     slots hold sum_i K_ij a_i:                      b_j <- 1 / C_j
+//   stored K 1 pass:     slots hold b_j sum_i K_ij a_i:                  b_j <- b_j / C_j
+// A log-domain column whose sum leaves [2^-64, 2^64] is queued for the exact
+// recompute of the end-of-iteration kernel.
+__global__ __launch_bounds__(256) void k_col_finalize(const Inst *__restrict__ insts,
+                                                      const FinUnit *__restrict__ units, int nunits,
+                                                      int mode) {
+    __shared__ float part[4][kFinCols];
+    __shared__ float rmax[256], dmax[256];
+    const int t = threadIdx.x;
+    int u0, u1;
+    unit_range(nunits, u0, u1);
+    for (int u = u0; u < u1; ++u) {
+        const FinUnit un = units[u];
+        const Inst &I = insts[un.inst];
+        Ctl *ctl = I.ctl;
+        if (ctl->state != ST_RUNNING) continue;
+        const bool kpath = (mode & kFinStoredK) != 0;   // slots written by the stored-K kernels
+        const bool onepass = (mode & kFinOnePass) != 0; // slots written by the single-pass kernel
+        if (kpath && ctl->need_absorb) continue;
+        // residual (and drift) of this iteration's row step
+        float m = 0.f, d = 0.f;
+        for (int q = t; q < I.nresslots; q += 256) {
+            m = fmaxf(m, I.res_slots[q]);
+            if (kpath) d = fmaxf(d, I.drift_slots[q]);
+        }
+        __syncthreads();
+        rmax[t] = m;
+        dmax[t] = d;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if (t < o) {
+                rmax[t] = fmaxf(rmax[t], rmax[t + o]);
+                dmax[t] = fmaxf(dmax[t], dmax[t + o]);
+            }
+            __syncthreads();
+        }
+        const float res = rmax[0];
+        const bool conv = ctl->iter >= 1 && res < I.tol;
+        if (un.group == 0 && t == 0) {
+            ctl->res_bits = __float_as_uint(res);
+            if (kpath && dmax[0] > 0.f) atomicMax(&ctl->drift_bits, __float_as_uint(dmax[0]));
+        }
+        if (conv) continue;
+        const int n = I.n;
+        const int c = t & (kFinCols - 1), g = t / kFinCols;
+        const int j = un.group * kFinCols + c;
+        float s0 = 0.f, s1 = 0.f;
+        if (j < n) {
+            int q = g;
+            for (; q + 4 < I.ncolslots; q += 8) {
+                s0 += I.colpart[(int64_t)q * n + j];
+                s1 += I.colpart[(int64_t)(q + 4) * n + j];
+            }
+            for (; q < I.ncolslots; q += 4) s0 += I.colpart[(int64_t)q * n + j];
+        }
+        __syncthreads();
+        part[g][c] = s0 + s1;
+        __syncthreads();
+        float drift = 0.f;
+        if (g == 0 && j < n) {
+            const float C = (part[0][c] + part[1][c]) + (part[2][c] + part[3][c]);
+            if (!kpath) {
+                if (C >= kSafeLo && C <= kSafeHi) {
+                    const float gn = (onepass ? I.gam[j] : 0.f) - lg2(C) * kLn2;
+                    const float k = rintf(gn);
+                    I.G[j] += (int)k;
+                    I.gam[j] = gn - k;
+                } else {
+                    const unsigned slot = atomicAdd(&ctl->rescue_cnt, 1u);
+                    I.rescue[slot] = (uint32_t)j;
                 }
+            } else {
+                const float Cc = fminf(fmaxf(C, kSafeLo), kSafeHi);
+                const float bn = fminf(fmaxf((onepass ? I.b[j] : 1.f) / Cc, kSafeLo), kSafeHi);
+                I.b[j] = bn;
+                drift = fabsf(lg2(bn));
             }
-            if (threadIdx.x == 0) I.tilecnt[un.tile] = 0u;
+        }
+        if (kpath) {
+            drift = wave_max(drift);
+            if ((t % kWave) == 0 && drift > 0.f) atomicMax(&ctl->drift_bits, __float_as_uint(drift));
         }
     }
 }
@@ -608,13 +693,12 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_check_rows(const Inst *__
         const double f = (double)I.F[par][row] + (double)I.phi[par][row];
         const int16_t *wr = I.W + (int64_t)row * I.pitch;
         double s = 0.0, m = -INFINITY;
-        for (int j = lane; j < n; j += kWave) {
-            const int w = wr[j];
-            if (w == SK_SENTINEL) continue;
+        visit_row(I, wr, lane, [&](int j, int w) {
+            if (w == SK_SENTINEL) return;
             const double t = p * (double)w + ((double)I.G[j] + (double)I.gam[j]);
             s += exp(t + f);
             m = fmax(m, t);
-        }
+        });
         s = wave_sum_d(s);
         m = wave_max_d(m);
         if (lane == 0) {
@@ -679,12 +763,11 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_prune_count(const Inst *_
         const double f = (double)I.F[par][row] + (double)I.phi[par][row];
         const int16_t *wr = I.W + (int64_t)row * I.pitch;
         int cnt = 0;
-        for (int j = lane; j < n; j += kWave) {
-            const int w = wr[j];
-            if (w == SK_SENTINEL) continue;
+        visit_row(I, wr, lane, [&](int j, int w) {
+            if (w == SK_SENTINEL) return;
             const double lx = p * (double)w + f + ((double)I.G[j] + (double)I.gam[j]);
             cnt += (lx >= logt);
-        }
+        });
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, kWave);
         if (lane == 0) counts[row] = cnt;
@@ -740,6 +823,51 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_prune_fill(const Inst *__
         const double f = (double)I.F[par][row] + (double)I.phi[par][row];
         const int16_t *wr = I.W + (int64_t)row * I.pitch;
         int64_t pos = row_ptr[row];
+        if (I.vec8) {
+            // each lane tests 8 consecutive columns; kept entries are placed
+            // by a wave prefix sum of the per-lane counts (column order kept)
+            for (int j0b = 0; j0b < n; j0b += 512) {
+                const int j0 = j0b + lane * 8;
+                int wv[8];
+                unsigned keep = 0;
+                if (j0 < n) {
+                    const int4 v = gload(reinterpret_cast<const int4 *>(wr + j0));
+                    const int q[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        wv[2 * c] = (int)(short)(q[c] & 0xffff);
+                        wv[2 * c + 1] = q[c] >> 16;
+                    }
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) {
+                        const int j = j0 + c;
+                        if (wv[c] != SK_SENTINEL) {
+                            const double lx =
+                                p * (double)wv[c] + f + ((double)I.G[j] + (double)I.gam[j]);
+                            if (lx >= logt) keep |= 1u << c;
+                        }
+                    }
+                }
+                const int cnt = __popc(keep);
+                int incl = cnt;
+#pragma unroll
+                for (int o = 1; o < kWave; o <<= 1) {
+                    const int y = __shfl_up(incl, o, kWave);
+                    if (lane >= o) incl += y;
+                }
+                const int total = __shfl(incl, kWave - 1, kWave);
+                int64_t q = pos + (incl - cnt);
+#pragma unroll
+                for (int c = 0; c < 8; ++c)
+                    if (keep & (1u << c)) {
+                        col[q] = j0 + c;
+                        wout[q] = (int16_t)wv[c];
+                        ++q;
+                    }
+                pos += total;
+            }
+            continue;
+        }
         for (int j0 = 0; j0 < n; j0 += kWave) {
             const int j = j0 + lane;
             bool keep = false;
@@ -776,7 +904,7 @@ __global__ __launch_bounds__(256) void k_gather_ctl(const Inst *__restrict__ ins
     }
 }
 
-// Resets the control blocks and tile counters of instances idx[0..m) for a
+// Resets the control blocks of instances idx[0..m) (all when idx is null) for a
 // cold start at the first p of their ladders.
 __global__ __launch_bounds__(256) void k_reset_ctl(const Inst *__restrict__ insts, const int *idx,
                                                    int m) {
@@ -790,7 +918,6 @@ __global__ __launch_bounds__(256) void k_reset_ctl(const Inst *__restrict__ inst
             c.last_res = INFINITY;
             *I.ctl = c;
         }
-        for (int t = threadIdx.x; t < I.ntiles; t += blockDim.x) I.tilecnt[t] = 0u;
     }
 }
 
@@ -821,6 +948,11 @@ hipError_t launch_col_sweep(const Inst *d_insts, const ColUnit *d_units, int nun
                             hipStream_t st) {
     hipLaunchKernelGGL(k_col_sweep, dim3(grid), dim3(kColWaves * kWave), 0, st, d_insts, d_units,
                        nunits);
+    return hipGetLastError();
+}
+hipError_t launch_col_finalize(const Inst *d_insts, const FinUnit *d_units, int nunits, int grid,
+                               int mode, hipStream_t st) {
+    hipLaunchKernelGGL(k_col_finalize, dim3(grid), dim3(256), 0, st, d_insts, d_units, nunits, mode);
     return hipGetLastError();
 }
 hipError_t launch_iter_end(const Inst *d_insts, int count, hipStream_t st) {

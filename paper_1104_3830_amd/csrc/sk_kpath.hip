@@ -92,8 +92,9 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_absorb(const Inst *__rest
         const int n = I.n, kp = I.kpitch;
         if (un.inst != cur) {
             __syncthreads();
+            const int n8 = n >> 3;
             for (int j = threadIdx.x; j < n; j += blockDim.x)
-                pot[j] = make_float2((float)I.G[j], I.gam[j] * kLog2eK);
+                pot[I.vec8 ? kswz(j, n8) : j] = make_float2((float)I.G[j], I.gam[j] * kLog2eK);
             __syncthreads();
             cur = un.inst;
         }
@@ -104,20 +105,49 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_absorb(const Inst *__rest
         const float Ff = (float)I.F[par][row];
         const float ph = I.phi[par][row] * kLog2eK;
         const int16_t *wr = I.W + (int64_t)row * I.pitch;
-        for (int j = lane; j < kp; j += kWave) {
-            float k = 0.f;
-            if (j < n) {
-                const int w = wr[j];
-                if (w != SK_SENTINEL) {
-                    const float2 gp = pot[j];
+        if (I.vec8) {
+            // 8 columns per lane: one 16-byte load of W, one 16/32-byte store of K
+            const int n8 = n >> 3;
+            for (int j0 = lane * 8; j0 < n; j0 += 512) {
+                const int4 v = gload(reinterpret_cast<const int4 *>(wr + j0));
+                const int q[4] = {v.x, v.y, v.z, v.w};
+                float k[8];
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    const int w = (c & 1) ? (q[c >> 1] >> 16) : (int)(short)(q[c >> 1] & 0xffff);
+                    const float2 gp = pot[c * n8 + (j0 >> 3)];
                     const float Iv = fmaf((float)w, pf, gp.x) + Ff;
-                    k = fminf(kex2(fmaf(Iv, kLog2eK, gp.y) + ph), kKHi);
+                    const float e = fminf(kex2(fmaf(Iv, kLog2eK, gp.y) + ph), kKHi);
+                    k[c] = (w == SK_SENTINEL) ? 0.f : e;
+                }
+                if (ST == SK_K_BF16) {
+                    uint32_t o[4];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) o[c] = bf16_rne(k[2 * c]) | (bf16_rne(k[2 * c + 1]) << 16);
+                    *reinterpret_cast<int4 *>(reinterpret_cast<uint16_t *>(I.K) + (int64_t)row * kp + j0) =
+                        make_int4((int)o[0], (int)o[1], (int)o[2], (int)o[3]);
+                } else {
+                    float4 *dst = reinterpret_cast<float4 *>(reinterpret_cast<float *>(I.K) + (int64_t)row * kp + j0);
+                    dst[0] = make_float4(k[0], k[1], k[2], k[3]);
+                    dst[1] = make_float4(k[4], k[5], k[6], k[7]);
                 }
             }
-            if (ST == SK_K_BF16)
-                reinterpret_cast<uint16_t *>(I.K)[(int64_t)row * kp + j] = (uint16_t)bf16_rne(k);
-            else
-                reinterpret_cast<float *>(I.K)[(int64_t)row * kp + j] = k;
+        } else {
+            for (int j = lane; j < kp; j += kWave) {
+                float k = 0.f;
+                if (j < n) {
+                    const int w = wr[j];
+                    if (w != SK_SENTINEL) {
+                        const float2 gp = pot[j];
+                        const float Iv = fmaf((float)w, pf, gp.x) + Ff;
+                        k = fminf(kex2(fmaf(Iv, kLog2eK, gp.y) + ph), kKHi);
+                    }
+                }
+                if (ST == SK_K_BF16)
+                    reinterpret_cast<uint16_t *>(I.K)[(int64_t)row * kp + j] = (uint16_t)bf16_rne(k);
+                else
+                    reinterpret_cast<float *>(I.K)[(int64_t)row * kp + j] = k;
+            }
         }
         if (lane == 0) {
             I.F[par ^ 1][row] = I.F[par][row];
@@ -147,11 +177,11 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_row_sweep_k(const Inst *_
                                                                    const RowUnit *__restrict__ units,
                                                                    int nunits) {
     extern __shared__ float bsh[];
+    __shared__ float wres[2][kRowWaves], wdrift[2][kRowWaves];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     int u0, u1;
     krange(nunits, u0, u1);
     int cur = -1;
-    float resmax = 0.f, drift = 0.f;
     for (int u = u0; u < u1; ++u) {
         const RowUnit un = units[u];
         const Inst &I = insts[un.inst];
@@ -159,63 +189,68 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_row_sweep_k(const Inst *_
         if (ctl->state != ST_RUNNING || ctl->need_absorb) continue;
         const int n = I.n, kp = I.kpitch, n8 = kp >> 3;
         if (un.inst != cur) {
-            if (cur >= 0 && lane == 0) {
-                if (insts[cur].ctl->iter >= 1 && resmax > 0.f)
-                    atomicMax(&insts[cur].ctl->res_bits, __float_as_uint(resmax));
-                if (drift > 0.f) atomicMax(&insts[cur].ctl->drift_bits, __float_as_uint(drift));
-            }
-            resmax = 0.f;
-            drift = 0.f;
             __syncthreads();
             for (int j = threadIdx.x; j < kp; j += blockDim.x) bsh[kswz(j, n8)] = j < n ? I.b[j] : 0.f;
             __syncthreads();
             cur = un.inst;
         }
         const int row = un.row0 + wave;
-        if (row >= n) continue;
-        const int par = ctl->iter & 1;
-        float acc = 0.f;
-        const int64_t rbase = (int64_t)row * kp;
-        int j0 = lane * 8;
-        for (; j0 + 3 * 512 < kp; j0 += 4 * 512) {
-            float k0[8], k1[8], k2[8], k3[8];
-            load8<ST>(I.K, rbase + j0, k0);
-            load8<ST>(I.K, rbase + j0 + 512, k1);
-            load8<ST>(I.K, rbase + j0 + 1024, k2);
-            load8<ST>(I.K, rbase + j0 + 1536, k3);
-            const int q = j0 >> 3;
-            float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+        float resmax = 0.f, drift = 0.f;
+        if (row < n) {
+            const int par = ctl->iter & 1;
+            float acc = 0.f;
+            const int64_t rbase = (int64_t)row * kp;
+            int j0 = lane * 8;
+            for (; j0 + 3 * 512 < kp; j0 += 4 * 512) {
+                float k0[8], k1[8], k2[8], k3[8];
+                load8<ST>(I.K, rbase + j0, k0);
+                load8<ST>(I.K, rbase + j0 + 512, k1);
+                load8<ST>(I.K, rbase + j0 + 1024, k2);
+                load8<ST>(I.K, rbase + j0 + 1536, k3);
+                const int q = j0 >> 3;
+                float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
 #pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                s0 = fmaf(k0[c], bsh[c * n8 + q], s0);
-                s1 = fmaf(k1[c], bsh[c * n8 + q + 64], s1);
-                s2 = fmaf(k2[c], bsh[c * n8 + q + 128], s2);
-                s3 = fmaf(k3[c], bsh[c * n8 + q + 192], s3);
+                for (int c = 0; c < 8; ++c) {
+                    s0 = fmaf(k0[c], bsh[c * n8 + q], s0);
+                    s1 = fmaf(k1[c], bsh[c * n8 + q + 64], s1);
+                    s2 = fmaf(k2[c], bsh[c * n8 + q + 128], s2);
+                    s3 = fmaf(k3[c], bsh[c * n8 + q + 192], s3);
+                }
+                acc += (s0 + s1) + (s2 + s3);
             }
-            acc += (s0 + s1) + (s2 + s3);
-        }
-        for (; j0 < kp; j0 += 512) {
-            float k[8];
-            load8<ST>(I.K, rbase + j0, k);
-            const int q = j0 >> 3;
-            float s = 0.f;
+            for (; j0 < kp; j0 += 512) {
+                float k[8];
+                load8<ST>(I.K, rbase + j0, k);
+                const int q = j0 >> 3;
+                float s = 0.f;
 #pragma unroll
-            for (int c = 0; c < 8; ++c) s = fmaf(k[c], bsh[c * n8 + q], s);
-            acc += s;
+                for (int c = 0; c < 8; ++c) s = fmaf(k[c], bsh[c * n8 + q], s);
+                acc += s;
+            }
+            const float S = kwave_sum(acc);
+            if (lane == 0) {
+                const float aold = I.a[par][row];
+                const float anew = 1.f / fminf(fmaxf(S, kKLo), kKHi);
+                I.a[par ^ 1][row] = anew;
+                resmax = fabsf(aold * S - 1.f);
+                drift = fabsf(klg2(anew));
+            }
         }
-        const float S = kwave_sum(acc);
+        const int b = (u - u0) & 1;
         if (lane == 0) {
-            const float aold = I.a[par][row];
-            const float anew = 1.f / fminf(fmaxf(S, kKLo), kKHi);
-            I.a[par ^ 1][row] = anew;
-            resmax = fmaxf(resmax, fabsf(aold * S - 1.f));
-            drift = fmaxf(drift, fabsf(klg2(anew)));
+            wres[b][wave] = resmax;
+            wdrift[b][wave] = drift;
         }
-    }
-    if (cur >= 0 && lane == 0) {
-        if (insts[cur].ctl->iter >= 1 && resmax > 0.f)
-            atomicMax(&insts[cur].ctl->res_bits, __float_as_uint(resmax));
-        if (drift > 0.f) atomicMax(&insts[cur].ctl->drift_bits, __float_as_uint(drift));
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float m = 0.f, d = 0.f;
+            for (int w = 0; w < kRowWaves; ++w) {
+                m = fmaxf(m, wres[b][w]);
+                d = fmaxf(d, wdrift[b][w]);
+            }
+            I.res_slots[un.row0 / kRowWaves] = m;
+            I.drift_slots[un.row0 / kRowWaves] = d;
+        }
     }
 }
 
@@ -226,7 +261,6 @@ __global__ __launch_bounds__(kColWaves * kWave) void k_col_sweep_k(const Inst *_
                                                                    int nunits) {
     __shared__ float red[kColWaves][kColTile8];
     __shared__ float ash[kMaxSegRows];
-    __shared__ int s_last;
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     int u0, u1;
     krange(nunits, u0, u1);
@@ -235,78 +269,50 @@ __global__ __launch_bounds__(kColWaves * kWave) void k_col_sweep_k(const Inst *_
         const Inst &I = insts[un.inst];
         Ctl *ctl = I.ctl;
         if (ctl->state != ST_RUNNING || ctl->need_absorb) continue;
-        const float res = __uint_as_float(ctl->res_bits);
-        const bool conv = ctl->iter >= 1 && res < I.tol;
         const int n = I.n, kp = I.kpitch;
         const int npar = (ctl->iter + 1) & 1;
         const int ctile0 = un.tile * kColTile8;
         const int ncols = min(kColTile8, n - ctile0);
-        if (!conv) {
-            const int r0 = un.seg * I.seg_rows, r1 = min(n, r0 + I.seg_rows);
-            __syncthreads();
-            for (int r = r0 + (int)threadIdx.x; r < r1; r += blockDim.x) ash[r - r0] = I.a[npar][r];
-            __syncthreads();
-            float acc[8];
+        const int r0 = un.seg * I.seg_rows, r1 = min(n, r0 + I.seg_rows);
+        __syncthreads();
+        for (int r = r0 + (int)threadIdx.x; r < r1; r += blockDim.x) ash[r - r0] = I.a[npar][r];
+        __syncthreads();
+        float acc[8];
 #pragma unroll
-            for (int c = 0; c < 8; ++c) acc[c] = 0.f;
-            const int c0 = ctile0 + lane * 8;
-            if (c0 < n) {
-                constexpr int S = kColWaves;
-                int r = r0 + wave;
-                for (; r + 3 * S < r1; r += 4 * S) {
-                    float k0[8], k1[8], k2[8], k3[8];
-                    load8<ST>(I.K, (int64_t)r * kp + c0, k0);
-                    load8<ST>(I.K, (int64_t)(r + S) * kp + c0, k1);
-                    load8<ST>(I.K, (int64_t)(r + 2 * S) * kp + c0, k2);
-                    load8<ST>(I.K, (int64_t)(r + 3 * S) * kp + c0, k3);
-                    const float a0 = ash[r - r0], a1 = ash[r + S - r0];
-                    const float a2 = ash[r + 2 * S - r0], a3 = ash[r + 3 * S - r0];
+        for (int c = 0; c < 8; ++c) acc[c] = 0.f;
+        const int c0 = ctile0 + lane * 8;
+        if (c0 < n) {
+            constexpr int S = kColWaves;
+            int r = r0 + wave;
+            for (; r + 3 * S < r1; r += 4 * S) {
+                float k0[8], k1[8], k2[8], k3[8];
+                load8<ST>(I.K, (int64_t)r * kp + c0, k0);
+                load8<ST>(I.K, (int64_t)(r + S) * kp + c0, k1);
+                load8<ST>(I.K, (int64_t)(r + 2 * S) * kp + c0, k2);
+                load8<ST>(I.K, (int64_t)(r + 3 * S) * kp + c0, k3);
+                const float a0 = ash[r - r0], a1 = ash[r + S - r0];
+                const float a2 = ash[r + 2 * S - r0], a3 = ash[r + 3 * S - r0];
 #pragma unroll
-                    for (int c = 0; c < 8; ++c)
-                        acc[c] = fmaf(k3[c], a3, fmaf(k2[c], a2, fmaf(k1[c], a1, fmaf(k0[c], a0, acc[c]))));
-                }
-                for (; r < r1; r += S) {
-                    float k[8];
-                    load8<ST>(I.K, (int64_t)r * kp + c0, k);
-                    const float ar = ash[r - r0];
-#pragma unroll
-                    for (int c = 0; c < 8; ++c) acc[c] = fmaf(k[c], ar, acc[c]);
-                }
+                for (int c = 0; c < 8; ++c)
+                    acc[c] = fmaf(k3[c], a3, fmaf(k2[c], a2, fmaf(k1[c], a1, fmaf(k0[c], a0, acc[c]))));
             }
+            for (; r < r1; r += S) {
+                float k[8];
+                load8<ST>(I.K, (int64_t)r * kp + c0, k);
+                const float ar = ash[r - r0];
 #pragma unroll
-            for (int c = 0; c < 8; ++c) red[wave][lane * 8 + c] = acc[c];
-            __syncthreads();
-            float *dst = I.colpart + (int64_t)un.seg * n + ctile0;
-            for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
-                float s = red[0][c];
-#pragma unroll
-                for (int w2 = 1; w2 < kColWaves; ++w2) s += red[w2][c];
-                dst[c] = s;
+                for (int c = 0; c < 8; ++c) acc[c] = fmaf(k[c], ar, acc[c]);
             }
         }
-        __threadfence();
+#pragma unroll
+        for (int c = 0; c < 8; ++c) red[wave][lane * 8 + c] = acc[c];
         __syncthreads();
-        if (threadIdx.x == 0) {
-            const unsigned old = atomicAdd(&I.tilecnt[un.tile], 1u);
-            s_last = (old == (unsigned)(I.nseg - 1));
-        }
-        __syncthreads();
-        if (s_last) {
-            __threadfence();
-            if (!conv) {
-                float drift = 0.f;
-                for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
-                    const int j = ctile0 + c;
-                    float T = 0.f;
-                    for (int s = 0; s < I.nseg; ++s)
-                        T += __builtin_nontemporal_load(I.colpart + (int64_t)s * n + j);
-                    const float bn = 1.f / fminf(fmaxf(T, kKLo), kKHi);
-                    I.b[j] = bn;
-                    drift = fmaxf(drift, fabsf(klg2(bn)));
-                }
-                if (drift > 0.f) atomicMax(&ctl->drift_bits, __float_as_uint(drift));
-            }
-            if (threadIdx.x == 0) I.tilecnt[un.tile] = 0u;
+        float *dst = I.colpart + (int64_t)un.seg * n + ctile0;
+        for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
+            float s = red[0][c];
+#pragma unroll
+            for (int w2 = 1; w2 < kColWaves; ++w2) s += red[w2][c];
+            dst[c] = s;
         }
     }
 }
@@ -584,9 +590,7 @@ sk_status run_single_k(sk_ctx *ctx, Batch &B, const sk_params *prm) {
                 ctx->prof.begin(ctx->stream, KID_FUSED);
                 KCHK(launch_fused(B.d_insts, 0, I0.n, I0.fused_grid, storage, ctx->stream));
                 ctx->prof.end(ctx->stream);
-                ctx->prof.begin(ctx->stream, KID_FUSED_COLS);
-                KCHK(launch_fused_cols(B.d_insts, 0, I0.n, I0.fused_grid, storage, ctx->stream));
-                ctx->prof.end(ctx->stream);
+
             } else {
                 ctx->prof.begin(ctx->stream, KID_ROW_K);
                 KCHK(launch_row_sweep_k(B.d_insts, B.d_rows, (int)B.h_rows.size(), B.row_grid_k,
@@ -597,6 +601,10 @@ sk_status run_single_k(sk_ctx *ctx, Batch &B, const sk_params *prm) {
                                         storage, ctx->stream));
                 ctx->prof.end(ctx->stream);
             }
+            ctx->prof.begin(ctx->stream, KID_FINALIZE);
+            KCHK(launch_col_finalize(B.d_insts, B.d_fins, (int)B.h_fins.size(), B.fin_grid,
+                                     kFinStoredK | (I0.fused ? kFinOnePass : 0), ctx->stream));
+            ctx->prof.end(ctx->stream);
             ctx->prof.begin(ctx->stream, KID_ITER_END);
             KCHK(launch_iter_end(B.d_insts, B.count, ctx->stream));
             ctx->prof.end(ctx->stream);
@@ -617,7 +625,7 @@ sk_status run_single_k(sk_ctx *ctx, Batch &B, const sk_params *prm) {
             ctx->prof.retag(pstart, KID_COL_K, tag(KID_COL_K_DETECT, KID_COL_K_IDLE));
             ctx->prof.retag(pstart, KID_ITER_END, tag(KID_ITER_END_DETECT, KID_ITER_END_IDLE));
             ctx->prof.retag(pstart, KID_FUSED, tag(KID_FUSED_DETECT, KID_FUSED_IDLE));
-            ctx->prof.retag(pstart, KID_FUSED_COLS, tag(KID_FUSED_COLS_DETECT, KID_FUSED_COLS_IDLE));
+            ctx->prof.retag(pstart, KID_FINALIZE, tag(KID_FINALIZE_DETECT, KID_FINALIZE_IDLE));
         }
     }
     return SK_OK;

@@ -26,16 +26,18 @@ struct Batch {
     std::vector<Inst> h_insts;
     std::vector<RowUnit> h_rows;
     std::vector<ColUnit> h_cols;
+    std::vector<FinUnit> h_fins;
     Inst *d_insts = nullptr;
     RowUnit *d_rows = nullptr;
     ColUnit *d_cols = nullptr;
+    FinUnit *d_fins = nullptr;
     double *d_rsum = nullptr, *d_rmax = nullptr, *d_csum = nullptr;
     double *d_cpart = nullptr;     // FP64 column partials [nseg][n] of the checked instance
     Ctl *d_ctl_all = nullptr;      // gathered control blocks (one copy per check)
     int64_t *d_counts = nullptr;
     size_t row_lds = 0;
     size_t row_lds_k = 0;
-    int row_grid = 1, col_grid = 1, row_grid_k = 1;
+    int row_grid = 1, col_grid = 1, row_grid_k = 1, fin_grid = 1;
 };
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -60,8 +62,8 @@ enum KernelId {
     KID_SCAN, KID_PRUNE_FILL, KID_ABSORB, KID_ROW_K, KID_COL_K, KID_FOLD_K,
     KID_ROW_DETECT, KID_COL_DETECT, KID_ITER_END_DETECT, KID_ROW_IDLE, KID_COL_IDLE,
     KID_ITER_END_IDLE, KID_ROW_K_DETECT, KID_COL_K_DETECT, KID_ROW_K_IDLE, KID_COL_K_IDLE,
-    KID_FUSED, KID_FUSED_COLS, KID_FUSED_DETECT, KID_FUSED_COLS_DETECT, KID_FUSED_IDLE,
-    KID_FUSED_COLS_IDLE, KID_COUNT
+    KID_FUSED, KID_FINALIZE, KID_FUSED_DETECT, KID_FINALIZE_DETECT, KID_FUSED_IDLE,
+    KID_FINALIZE_IDLE, KID_COUNT
 };
 extern const char *kKernelNames[KID_COUNT];
 

@@ -17,10 +17,20 @@ namespace sk {
 
 // ---------------------------------------------------------------- planning
 
+// Tuned segment heights (sk_set_tile_table); empty = built-in rule.
+static std::vector<std::pair<int32_t, int32_t>> g_tile_table;
+
 TilePlan plan_tiles(int32_t n, int vec8) {
     TilePlan t;
     t.tile_cols = vec8 ? kColTile8 : kColTile1;
     t.ntiles = (n + t.tile_cols - 1) / t.tile_cols;
+    for (const auto &e : g_tile_table) {
+        if (n <= e.first) {
+            t.seg_rows = std::min(e.second, std::max(16, (n + 15) / 16 * 16));
+            t.nseg = (n + t.seg_rows - 1) / t.seg_rows;
+            return t;
+        }
+    }
     // Column-sweep segment height: aim for ~1024 work units per sweep, but
     // keep each unit at >= 128 rows so the fixed-slot partials stay a small
     // fraction of the matrix traffic.
@@ -40,9 +50,9 @@ size_t instance_bytes(int32_t n, int vec8, int storage, int fused) {
     b += align_up(sizeof(float) * n, 256) * 3;    // phi[2], gam
     const size_t slots = fused ? std::max(t.nseg, kFusedSlots) : t.nseg;
     b += align_up(sizeof(float) * slots * n, 256);
-    b += align_up(sizeof(uint32_t) * t.ntiles, 256);
     b += align_up(sizeof(uint32_t) * n, 256);
     b += align_up(sizeof(Ctl), 256);
+    b += align_up(sizeof(float) * std::max((n + kRowWaves - 1) / kRowWaves, kFusedSlots), 256) * 2;
     if (storage == SK_K_BF16 || storage == SK_K_F32) {
         const size_t es = storage == SK_K_BF16 ? 2 : 4;
         const size_t kp = (size_t)(n + 7) / 8 * 8;
@@ -53,12 +63,13 @@ size_t instance_bytes(int32_t n, int vec8, int storage, int fused) {
 }
 
 size_t shared_bytes(int32_t count, const int32_t *n) {
-    int64_t rows = 0, cols = 0, nmax = 0, cpart = 0;
+    int64_t rows = 0, cols = 0, nmax = 0, cpart = 0, fins = 0;
     for (int k = 0; k < count; ++k) {
         TilePlan t = plan_tiles(n[k], (n[k] % 8) == 0);
         cpart = std::max<int64_t>(cpart, (int64_t)t.nseg * n[k]);
         rows += (n[k] + kRowWaves - 1) / kRowWaves;
         cols += (int64_t)t.ntiles * t.nseg;
+        fins += (n[k] + kFinCols - 1) / kFinCols;
         nmax = std::max<int64_t>(nmax, n[k]);
     }
     size_t b = 0;
@@ -66,6 +77,7 @@ size_t shared_bytes(int32_t count, const int32_t *n) {
     b += align_up(sizeof(Ctl) * count, 256);
     b += align_up(sizeof(RowUnit) * rows, 256);
     b += align_up(sizeof(ColUnit) * cols, 256);
+    b += align_up(sizeof(FinUnit) * fins, 256);
     b += align_up(sizeof(double) * nmax, 256) * 3;  // FP64 check: rsum, rmax, csum
     b += align_up(sizeof(double) * (size_t)cpart, 256);  // FP64 column partials
     b += align_up(sizeof(int64_t) * (nmax + 1), 256);  // prune row counts
@@ -81,8 +93,8 @@ const char *kKernelNames[KID_COUNT] = {"init", "row_sweep", "col_sweep", "iter_e
                                        "iter_end:detect", "row_sweep:idle", "col_sweep:idle",
                                        "iter_end:idle", "row_sweep_k:detect", "col_sweep_k:detect",
                                        "row_sweep_k:idle", "col_sweep_k:idle", "fused",
-                                       "fused_cols", "fused:detect", "fused_cols:detect",
-                                       "fused:idle", "fused_cols:idle"};
+                                       "finalize", "fused:detect", "finalize:detect",
+                                       "fused:idle", "finalize:idle"};
 
 hipEvent_t Profiler::take() {
     if (!pool.empty()) {
@@ -146,6 +158,18 @@ using namespace sk;
         (ctx)->prof.end((ctx)->stream); \
         return e__;                    \
     }())
+
+sk_status sk_set_tile_table(const int32_t *n_max, const int32_t *seg_rows, int32_t count) {
+    if (count < 0 || (count > 0 && (!n_max || !seg_rows))) return SK_EINVAL;
+    std::vector<std::pair<int32_t, int32_t>> t;
+    for (int k = 0; k < count; ++k) {
+        if (seg_rows[k] < 16 || seg_rows[k] > kMaxSegRows || seg_rows[k] % 16 != 0) return SK_EINVAL;
+        if (k > 0 && n_max[k] <= n_max[k - 1]) return SK_EINVAL;
+        t.push_back({n_max[k], seg_rows[k]});
+    }
+    g_tile_table = t;
+    return SK_OK;
+}
 
 sk_status sk_profile_enable(sk_ctx *ctx, int enable) {
     if (!ctx) return SK_EINVAL;
@@ -297,11 +321,16 @@ bool sk::carve_instance(Bump &bump, const int16_t *W, int64_t pitch, int32_t nn,
     I.gam = bump.take<float>(nn);
     const size_t slots = I.fused ? std::max(t.nseg, kFusedSlots) : t.nseg;
     I.colpart = bump.take<float>(slots * nn);
-    I.tilecnt = bump.take<uint32_t>(t.ntiles);
     I.rescue = bump.take<uint32_t>(nn);
     I.ctl = bump.take<Ctl>(1);
+    const int nrows_units = (nn + kRowWaves - 1) / kRowWaves;
+    I.ncolslots = I.fused ? I.fused_grid : t.nseg;
+    I.nresslots = I.fused ? I.fused_grid : nrows_units;
+    I.res_slots = bump.take<float>(std::max(nrows_units, kFusedSlots));
+    I.drift_slots = bump.take<float>(std::max(nrows_units, kFusedSlots));
+    if (!I.res_slots || !I.drift_slots) return false;
     if (!I.F[0] || !I.F[1] || !I.phi[0] || !I.phi[1] || !I.G || !I.gam || !I.colpart ||
-        !I.tilecnt || !I.rescue || !I.ctl)
+        !I.rescue || !I.ctl)
         return false;
     I.kpitch = (nn + 7) / 8 * 8;
     if (prm->storage != SK_W_I16) {
@@ -320,6 +349,7 @@ sk_status sk::finish_tables(sk_ctx *ctx, Bump &bump, Batch &B) {
     B.count = (int)B.h_insts.size();
     B.h_rows.clear();
     B.h_cols.clear();
+    B.h_fins.clear();
     B.nmax = 0;
     int64_t cpart = 0;
     for (int k = 0; k < B.count; ++k) {
@@ -328,19 +358,21 @@ sk_status sk::finish_tables(sk_ctx *ctx, Bump &bump, Batch &B) {
         for (int r = 0; r < I.n; r += kRowWaves) B.h_rows.push_back(RowUnit{k, r});
         for (int s = 0; s < I.nseg; ++s)
             for (int tt = 0; tt < I.ntiles; ++tt) B.h_cols.push_back(ColUnit{k, tt, s, 0});
+        for (int g = 0; g * kFinCols < I.n; ++g) B.h_fins.push_back(FinUnit{k, g});
         B.nmax = std::max(B.nmax, I.n);
     }
     B.d_insts = bump.take<Inst>(B.count);
     B.d_ctl_all = bump.take<Ctl>(B.count);
     B.d_rows = bump.take<RowUnit>(B.h_rows.size());
     B.d_cols = bump.take<ColUnit>(B.h_cols.size());
+    B.d_fins = bump.take<FinUnit>(B.h_fins.size());
     B.d_rsum = bump.take<double>(B.nmax);
     B.d_rmax = bump.take<double>(B.nmax);
     B.d_csum = bump.take<double>(B.nmax);
     B.d_counts = bump.take<int64_t>(B.nmax + 1);
     B.d_cpart = bump.take<double>(cpart);
-    if (!B.d_insts || !B.d_rows || !B.d_cols || !B.d_rsum || !B.d_rmax || !B.d_csum || !B.d_counts ||
-        !B.d_cpart || !B.d_ctl_all)
+    if (!B.d_insts || !B.d_rows || !B.d_cols || !B.d_fins || !B.d_rsum || !B.d_rmax || !B.d_csum ||
+        !B.d_counts || !B.d_cpart || !B.d_ctl_all)
         return fail(ctx, SK_ENOMEM, "arena too small for the batch tables");
     // grids: row sweep stages n columns of potentials (8 B each) in LDS
     const size_t lds = sizeof(float2) * (size_t)B.nmax;
@@ -351,6 +383,7 @@ sk_status sk::finish_tables(sk_ctx *ctx, Bump &bump, Batch &B) {
     const int per_cu_k = B.row_lds_k <= 65536 ? 2 : 1;
     B.row_grid_k = (int)std::max<size_t>(1, std::min<size_t>(B.h_rows.size(), (size_t)ctx->num_cus * per_cu_k));
     B.col_grid = (int)std::max<size_t>(1, std::min<size_t>(B.h_cols.size(), (size_t)ctx->num_cus * 8));
+    B.fin_grid = (int)std::max<size_t>(1, std::min<size_t>(B.h_fins.size(), (size_t)ctx->num_cus * 4));
     return SK_OK;
 }
 
@@ -370,6 +403,8 @@ sk_status sk::upload_batch(sk_ctx *ctx, Batch &B) {
     HIPCHK(ctx, hipMemcpyAsync(B.d_rows, B.h_rows.data(), sizeof(RowUnit) * B.h_rows.size(),
                                hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(ctx, hipMemcpyAsync(B.d_cols, B.h_cols.data(), sizeof(ColUnit) * B.h_cols.size(),
+                               hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(B.d_fins, B.h_fins.data(), sizeof(FinUnit) * B.h_fins.size(),
                                hipMemcpyHostToDevice, ctx->stream));
     return SK_OK;
 }
@@ -415,8 +450,9 @@ sk_status sk::iterate_i16(sk_ctx *ctx, Batch &B) {
         const Inst &I = B.h_insts[0];
         HIPCHK(ctx, PROF(ctx, KID_FUSED, launch_fused(B.d_insts, 0, I.n, I.fused_grid, SK_W_I16,
                                                       ctx->stream)));
-        HIPCHK(ctx, PROF(ctx, KID_FUSED_COLS, launch_fused_cols(B.d_insts, 0, I.n, I.fused_grid,
-                                                                SK_W_I16, ctx->stream)));
+        HIPCHK(ctx, PROF(ctx, KID_FINALIZE, launch_col_finalize(B.d_insts, B.d_fins,
+                                                                (int)B.h_fins.size(), B.fin_grid,
+                                                                kFinOnePass, ctx->stream)));
         HIPCHK(ctx, PROF(ctx, KID_ITER_END, launch_iter_end(B.d_insts, B.count, ctx->stream)));
         return SK_OK;
     }
@@ -424,6 +460,8 @@ sk_status sk::iterate_i16(sk_ctx *ctx, Batch &B) {
                                  ctx->stream)));
     HIPCHK(ctx, PROF(ctx, KID_COL, launch_col_sweep(B.d_insts, B.d_cols, (int)B.h_cols.size(), B.col_grid,
                                  ctx->stream)));
+    HIPCHK(ctx, PROF(ctx, KID_FINALIZE, launch_col_finalize(B.d_insts, B.d_fins, (int)B.h_fins.size(),
+                                                            B.fin_grid, 0, ctx->stream)));
     HIPCHK(ctx, PROF(ctx, KID_ITER_END, launch_iter_end(B.d_insts, B.count, ctx->stream)));
     return SK_OK;
 }
@@ -482,7 +520,7 @@ sk_status sk::run_batch_i16(sk_ctx *ctx, Batch &B, const sk_params *prm) {
         ctx->prof.retag(pstart, KID_COL, tagger(KID_COL_DETECT, KID_COL_IDLE));
         ctx->prof.retag(pstart, KID_ITER_END, tagger(KID_ITER_END_DETECT, KID_ITER_END_IDLE));
         ctx->prof.retag(pstart, KID_FUSED, tagger(KID_FUSED_DETECT, KID_FUSED_IDLE));
-        ctx->prof.retag(pstart, KID_FUSED_COLS, tagger(KID_FUSED_COLS_DETECT, KID_FUSED_COLS_IDLE));
+        ctx->prof.retag(pstart, KID_FINALIZE, tagger(KID_FINALIZE_DETECT, KID_FINALIZE_IDLE));
     }
     return SK_OK;
 }

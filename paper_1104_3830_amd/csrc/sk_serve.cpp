@@ -27,47 +27,10 @@
 #include <unordered_map>
 #include <vector>
 
+#include "sk_alloc.h"
 #include "sk_runtime.h"
 
 namespace sk {
-
-// First-fit allocator over [0, cap) of the arena, 256-byte granules, coalescing.
-struct RangeAlloc {
-    std::map<size_t, size_t> free_;
-    void init(size_t base, size_t cap) {
-        free_.clear();
-        if (cap > base) free_[base] = cap - base;
-    }
-    bool alloc(size_t len, size_t &off) {
-        len = align_up(len, 256);
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= len) {
-                off = it->first;
-                const size_t rest = it->second - len;
-                free_.erase(it);
-                if (rest) free_[off + len] = rest;
-                return true;
-            }
-        }
-        return false;
-    }
-    void release(size_t off, size_t len) {
-        len = align_up(len, 256);
-        auto it = free_.emplace(off, len).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
-        }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-};
 
 struct Request {
     uint64_t id = 0;
