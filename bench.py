@@ -13,7 +13,11 @@ the scaling phase with everything else of the path counted as overhead.
 
 roofline: the dominant kernel (most total time), its algorithmic bytes per
 launch / its average launch duration from HIP events recorded around every
-launch on the library's stream during the timed region.
+launch on the library's stream during the timed region. `traffic` is the HBM
+bytes per launch of that kernel measured with rocprofv3 FETCH_SIZE and
+WRITE_SIZE counters (each scaled by what the same counter reads for a plain
+1 GiB copy), taken from the committed summary in profiles/ only while the
+kernel sources still hash to the value recorded there; otherwise null.
 
 cpu_baseline: the FP64 oracle, as it stands, timed on this host's cores on a
 bounded sample of the same workload (a few full iterations at n = 16384),
@@ -75,6 +79,14 @@ def parse():
     ap.add_argument("--trace-summary", metavar="CSV",
                     help="only summarise a rocprofv3 kernel-trace CSV: per kernel, all dispatches "
                          "and those longer than 20 us (launches that did work)")
+    ap.add_argument("--counter-summary", metavar="CSV",
+                    help="only summarise a rocprofv3 --pmc counter CSV: per kernel and counter, the "
+                         "mean over dispatches that did work (value above 1%% of the kernel's max)")
+    ap.add_argument("--traffic-report", nargs=6,
+                    metavar=("KERNEL", "WORKLOAD", "FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV",
+                             "COPY_WRITE_CSV"),
+                    help="only write the HBM traffic summary of one kernel from two --pmc runs of "
+                         "the benchmark and two of --calibrate-copy")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (the reference "
                          "kernel for scaling HBM byte counters)")
@@ -91,6 +103,90 @@ def trace_summary(path):
         big = [x for x in v if x > 20000]
         print(f"{k} calls={len(v)} avg_ns={sum(v) / len(v):.0f} calls_over_20us={len(big)} "
               f"avg_over_20us_ns={(sum(big) / len(big) if big else 0):.0f}")
+
+
+def counter_summary(path):
+    import csv
+    per = {}
+    for r in csv.DictReader(open(path)):
+        key = (r["Kernel_Name"].split("(")[0], r["Counter_Name"])
+        per.setdefault(key, {}).setdefault(r["Dispatch_Id"], 0.0)
+        per[key][r["Dispatch_Id"]] += float(r["Counter_Value"])
+    for (k, c), d in sorted(per.items()):
+        v = list(d.values())
+        hi = max(v) if v else 0.0
+        work = [x for x in v if x > 0.01 * hi]
+        print(f"{k} {c} dispatches={len(v)} working={len(work)} "
+              f"mean_working={(sum(work) / len(work) if work else 0):.1f}")
+
+
+def source_hash():
+    """sha256 over the library's kernel and runtime sources."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_1104_3830_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h", ".cpp")):
+            h.update(f.encode())
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()
+
+
+def _counter_means(path, counter):
+    import csv
+    per = {}
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] != counter:
+            continue
+        k = r["Kernel_Name"].split("(")[0]
+        per.setdefault(k, {}).setdefault(r["Dispatch_Id"], 0.0)
+        per[k][r["Dispatch_Id"]] += float(r["Counter_Value"])
+    out = {}
+    for k, d in per.items():
+        v = list(d.values())
+        hi = max(v) if v else 0.0
+        work = [x for x in v if x > 0.01 * hi]
+        out[k] = (sum(work) / len(work) if work else 0.0, len(work), len(v))
+    return out
+
+
+def traffic_report(kernel, workload, fcsv, wcsv, cfcsv, cwcsv):
+    copy_kib = (1 << 30) / 1024.0
+    cf = _counter_means(cfcsv, "FETCH_SIZE")["__amd_rocclr_copyBuffer"][0]
+    cw = _counter_means(cwcsv, "WRITE_SIZE")["__amd_rocclr_copyBuffer"][0]
+    fs, ws = copy_kib / cf, copy_kib / cw
+    f = _counter_means(fcsv, "FETCH_SIZE")["sk::" + kernel]
+    w = _counter_means(wcsv, "WRITE_SIZE")["sk::" + kernel]
+    total = (f[0] * fs + w[0] * ws) * 1024.0
+    print(f"kernel: {kernel}")
+    print(f"workload: {workload}")
+    print(f"source_sha256: {source_hash()}")
+    print(f"copy_bytes_read_and_written: {1 << 30}")
+    print(f"copy_fetch_kib: {cf:.1f}")
+    print(f"copy_write_kib: {cw:.1f}")
+    print(f"fetch_scale: {fs:.4f}")
+    print(f"write_scale: {ws:.4f}")
+    print(f"fetch_kib_per_launch_raw: {f[0]:.1f} (mean over {f[1]} of {f[2]} dispatches that did work)")
+    print(f"write_kib_per_launch_raw: {w[0]:.1f} (mean over {w[1]} of {w[2]} dispatches that did work)")
+    print(f"bytes_per_launch: {total:.0f}")
+
+
+def committed_traffic(kernel, storage, n):
+    """HBM bytes per launch from profiles/, or None if the sources changed since."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{kernel}_{storage}_n{n}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha256") != source_hash():
+        return None
+    try:
+        return int(float(kv["bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
 
 
 def calibrate_copy():
@@ -255,6 +351,12 @@ def main():
     if args.trace_summary:
         trace_summary(args.trace_summary)
         return
+    if args.counter_summary:
+        counter_summary(args.counter_summary)
+        return
+    if args.traffic_report:
+        traffic_report(*args.traffic_report)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
                           "n_gpus": args.gpus}))
@@ -315,7 +417,7 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1) if achieved else None,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-                "traffic": None, "kernel": dom_name,
+                "traffic": committed_traffic(dom_name, args.storage, n), "kernel": dom_name,
                 "avg_us": round(avg_s * 1e6, 2), "launches": dom_launches}
     kernels = {k: {"launches": v[0], "avg_us": round(v[1] / max(v[0], 1) * 1e3, 2)}
                for k, v in prof.items()}

@@ -18,28 +18,30 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              "-Wall", "-Wno-unused-function"]
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
+    """Compiles every source and links `out` (defines: extra -D flags)."""
     objs = []
-    bdir = os.path.join(HERE, "_build")
+    bdir = os.path.join(os.path.dirname(out) if out != LIB else HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
     for src in SOURCES:
         path = os.path.join(CSRC, src)
         obj = os.path.join(bdir, src + ".o")
         if src.endswith(".hip"):
-            cmd = ["hipcc", "-x", "hip", *HIP_FLAGS, "-c", path, "-o", obj]
+            cmd = ["hipcc", "-x", "hip", *HIP_FLAGS, *[f"-D{d}" for d in defines], "-c", path,
+                   "-o", obj]
         else:
             cmd = ["hipcc", "-O3", "-std=c++17", "-fPIC", "-Wall", "-c", path, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
         objs.append(obj)
-    tmp = LIB + ".tmp"
+    tmp = out + ".tmp"
     cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp, "-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -108,15 +108,18 @@ enum : int { kFinOnePass = 1, kFinStoredK = 2 };
 hipError_t launch_col_finalize(const Inst *d_insts, const FinUnit *d_units, int nunits, int grid,
                                int mode, hipStream_t st);
 hipError_t launch_check_rows(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
-                             double *rsum, double *rmax, hipStream_t st);
+                             double *rsum, double *rmax, size_t lds_bytes, hipStream_t st);
 hipError_t launch_check_cols(const Inst *d_insts, int inst, int n, int nseg, double *part,
                              double *csum, hipStream_t st);
 hipError_t launch_prune_count(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
-                              double logt, int64_t *counts, hipStream_t st);
-hipError_t launch_scan(const int64_t *counts, int64_t *row_ptr, int n, hipStream_t st);
+                              double logt, int64_t *counts, size_t lds_bytes, hipStream_t st);
+hipError_t launch_scan(const int64_t *counts, int64_t *row_ptr, int n, hipStream_t st,
+                       int64_t *total_out = nullptr);
+hipError_t launch_check_reduce(const Inst *d_insts, int inst, const double *rsum,
+                               const double *rmax, const double *csum, double *out, hipStream_t st);
 hipError_t launch_prune_fill(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
                              double logt, const int64_t *row_ptr, int32_t *col, int16_t *w,
-                             hipStream_t st);
+                             size_t lds_bytes, hipStream_t st);
 hipError_t launch_absorb(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
                          size_t lds_bytes, int storage, hipStream_t st);
 hipError_t launch_row_sweep_k(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,

@@ -157,25 +157,31 @@ __device__ __forceinline__ float chunk8(const int4 v, int q, int n8, float pf, f
     return s;
 }
 
-// Row partial sum for one lane: chunks lane*8 + k*512, four 16-byte loads
-// in flight per lane.
+// Loads in flight per lane in the sweeps (build-time tuning knobs).
+#ifndef SK_ROW_UNROLL
+#define SK_ROW_UNROLL 4
+#endif
+#ifndef SK_COL_UNROLL
+#define SK_COL_UNROLL 2
+#endif
+
+// Row partial sum for one lane: chunks lane*8 + k*512, SK_ROW_UNROLL 16-byte
+// loads in flight per lane.
 template <bool SENT>
 __device__ __forceinline__ float row_partial_v8(const int16_t *__restrict__ wr, int n, float pf,
                                                 float Ff, const float2 *__restrict__ pot, int lane,
                                                 float shift) {
+    constexpr int U = SK_ROW_UNROLL;
     const int n8 = n >> 3;
     float acc = 0.f;
     int j0 = lane * 8;
-    for (; j0 + 3 * 512 < n; j0 += 4 * 512) {
-        const int4 v0 = gload(reinterpret_cast<const int4 *>(wr + j0));
-        const int4 v1 = gload(reinterpret_cast<const int4 *>(wr + j0 + 512));
-        const int4 v2 = gload(reinterpret_cast<const int4 *>(wr + j0 + 1024));
-        const int4 v3 = gload(reinterpret_cast<const int4 *>(wr + j0 + 1536));
+    for (; j0 + (U - 1) * 512 < n; j0 += U * 512) {
+        int4 v[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) v[k] = gload(reinterpret_cast<const int4 *>(wr + j0 + k * 512));
         const int q = j0 >> 3;
-        acc += chunk8<SENT>(v0, q, n8, pf, Ff, pot, shift);
-        acc += chunk8<SENT>(v1, q + 64, n8, pf, Ff, pot, shift);
-        acc += chunk8<SENT>(v2, q + 128, n8, pf, Ff, pot, shift);
-        acc += chunk8<SENT>(v3, q + 192, n8, pf, Ff, pot, shift);
+#pragma unroll
+        for (int k = 0; k < U; ++k) acc += chunk8<SENT>(v[k], q + 64 * k, n8, pf, Ff, pot, shift);
     }
     for (; j0 < n; j0 += 512) {
         const int4 v = gload(reinterpret_cast<const int4 *>(wr + j0));
@@ -371,15 +377,14 @@ __device__ __forceinline__ void col_partial(const Inst &I, int tile, int r0, int
         };
         int r = r0 + wave;
         constexpr int S = kColWaves;
-        for (; r + 3 * S < r1; r += 4 * S) {
-            const int4 v0 = gload(reinterpret_cast<const int4 *>(base + (int64_t)r * pitch));
-            const int4 v1 = gload(reinterpret_cast<const int4 *>(base + (int64_t)(r + S) * pitch));
-            const int4 v2 = gload(reinterpret_cast<const int4 *>(base + (int64_t)(r + 2 * S) * pitch));
-            const int4 v3 = gload(reinterpret_cast<const int4 *>(base + (int64_t)(r + 3 * S) * pitch));
-            body(v0, rowpot[r - r0]);
-            body(v1, rowpot[r + S - r0]);
-            body(v2, rowpot[r + 2 * S - r0]);
-            body(v3, rowpot[r + 3 * S - r0]);
+        constexpr int U = SK_COL_UNROLL;
+        for (; r + (U - 1) * S < r1; r += U * S) {
+            int4 v[U];
+#pragma unroll
+            for (int k = 0; k < U; ++k)
+                v[k] = gload(reinterpret_cast<const int4 *>(base + (int64_t)(r + k * S) * pitch));
+#pragma unroll
+            for (int k = 0; k < U; ++k) body(v[k], rowpot[r + k * S - r0]);
         }
         for (; r < r1; r += S) body(gload(reinterpret_cast<const int4 *>(base + (int64_t)r * pitch)),
                                     rowpot[r - r0]);
@@ -676,16 +681,40 @@ __global__ __launch_bounds__(256) void k_iter_end(const Inst *__restrict__ insts
 // ---------------------------------------------------------------- FP64 recheck
 // Row sums r_i and m_i = max_j (p w_ij + log v_j) in FP64 from the committed
 // potentials (Proposition prop:aoc needs sum_i m_i - sum_j log v_j).
+// Entries with log x_ij below this contribute less than e^-46 each, i.e. at
+// most n e^-46 < 2^-52 to a row or column sum of 1 for n <= 16384 (below one
+// FP64 ulp of the sum); their exp is not evaluated.
+constexpr double kNegligibleLog = -46.0;
+
+// Stages log v_j = G_j + gam_j (FP64) for the instance in LDS; swizzled like
+// the row sweep when 8-wide chunks are used.
+__device__ __forceinline__ void stage_logv(const Inst &I, double *lv) {
+    const int n = I.n, n8 = n >> 3;
+    for (int j = threadIdx.x; j < n; j += blockDim.x)
+        lv[I.vec8 ? swz8(j, n8) : j] = (double)I.G[j] + (double)I.gam[j];
+}
+__device__ __forceinline__ double logv_at(const Inst &I, const double *lv, int j) {
+    return lv[I.vec8 ? swz8(j, I.n >> 3) : j];
+}
+
 __global__ __launch_bounds__(kRowWaves * kWave) void k_check_rows(const Inst *__restrict__ insts,
                                                                     const RowUnit *__restrict__ units,
                                                                     int nunits, double *rsum,
                                                                     double *rmax) {
+    extern __shared__ double lv[];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     int u0, u1;
     unit_range(nunits, u0, u1);
+    int cur = -1;
     for (int u = u0; u < u1; ++u) {
         const RowUnit un = units[u];
         const Inst &I = insts[un.inst];
+        if (un.inst != cur) {
+            __syncthreads();
+            stage_logv(I, lv);
+            __syncthreads();
+            cur = un.inst;
+        }
         const int n = I.n, row = un.row0 + wave;
         if (row >= n) continue;
         const int par = I.ctl->iter & 1;
@@ -695,8 +724,9 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_check_rows(const Inst *__
         double s = 0.0, m = -INFINITY;
         visit_row(I, wr, lane, [&](int j, int w) {
             if (w == SK_SENTINEL) return;
-            const double t = p * (double)w + ((double)I.G[j] + (double)I.gam[j]);
-            s += exp(t + f);
+            const double t = p * (double)w + logv_at(I, lv, j);
+            const double lx = t + f;
+            if (lx > kNegligibleLog) s += exp(lx);
             m = fmax(m, t);
         });
         s = wave_sum_d(s);
@@ -727,7 +757,8 @@ __global__ __launch_bounds__(256) void k_check_cols_part(const Inst *__restrict_
     for (int r = r0; r < r1; ++r) {
         const int w = I.W[(int64_t)r * I.pitch + j];
         if (w == SK_SENTINEL) continue;
-        s += exp(p * (double)w + g + ((double)I.F[par][r] + (double)I.phi[par][r]));
+        const double lx = p * (double)w + g + ((double)I.F[par][r] + (double)I.phi[par][r]);
+        if (lx > kNegligibleLog) s += exp(lx);
     }
     part[(int64_t)seg * n + j] = s;
 }
@@ -743,6 +774,42 @@ __global__ __launch_bounds__(256) void k_check_cols_sum(const Inst *__restrict__
     csum[j] = s;
 }
 
+// Reduces the FP64 check of one instance to four numbers, in a fixed order:
+// out[0] = max_i |r_i - 1|, out[1] = max_j |c_j - 1|, out[2] = sum_i m_i,
+// out[3] = sum_j log v_j (the certificate is (out[2] - out[3]) / p).
+__global__ __launch_bounds__(256) void k_check_reduce(const Inst *__restrict__ insts, int inst,
+                                                      const double *rsum, const double *rmax,
+                                                      const double *csum, double *out) {
+    __shared__ double a[256], b[256], c[256], d[256];
+    const Inst &I = insts[inst];
+    const int n = I.n, t = threadIdx.x;
+    double ra = 0.0, ca = 0.0, sm = 0.0, sg = 0.0;
+    for (int i = t; i < n; i += 256) {
+        ra = fmax(ra, fabs(rsum[i] - 1.0));
+        ca = fmax(ca, fabs(csum[i] - 1.0));
+        sm += rmax[i];
+        sg += (double)I.G[i] + (double)I.gam[i];
+    }
+    a[t] = ra;
+    b[t] = ca;
+    c[t] = sm;
+    d[t] = sg;
+    __syncthreads();
+    if (t == 0) {
+        double A = 0.0, Bm = 0.0, C = 0.0, D = 0.0;
+        for (int k = 0; k < 256; ++k) {
+            A = fmax(A, a[k]);
+            Bm = fmax(Bm, b[k]);
+            C += c[k];
+            D += d[k];
+        }
+        out[0] = A;
+        out[1] = Bm;
+        out[2] = C;
+        out[3] = D;
+    }
+}
+
 // ---------------------------------------------------------------- prune
 // B keeps (i, j) iff x_ij(p) >= t (eq. matrixred); the comparison is made on
 // log x_ij = p w_ij + log u_i + log v_j in FP64.
@@ -750,12 +817,20 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_prune_count(const Inst *_
                                                                      const RowUnit *__restrict__ units,
                                                                      int nunits, double logt,
                                                                      int64_t *counts) {
+    extern __shared__ double lv[];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     int u0, u1;
     unit_range(nunits, u0, u1);
+    int cur = -1;
     for (int u = u0; u < u1; ++u) {
         const RowUnit un = units[u];
         const Inst &I = insts[un.inst];
+        if (un.inst != cur) {
+            __syncthreads();
+            stage_logv(I, lv);
+            __syncthreads();
+            cur = un.inst;
+        }
         const int n = I.n, row = un.row0 + wave;
         if (row >= n) continue;
         const int par = I.ctl->iter & 1;
@@ -765,7 +840,7 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_prune_count(const Inst *_
         int cnt = 0;
         visit_row(I, wr, lane, [&](int j, int w) {
             if (w == SK_SENTINEL) return;
-            const double lx = p * (double)w + f + ((double)I.G[j] + (double)I.gam[j]);
+            const double lx = p * (double)w + f + logv_at(I, lv, j);
             cnt += (lx >= logt);
         });
 #pragma unroll
@@ -776,7 +851,8 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_prune_count(const Inst *_
 
 // Exclusive scan of n row counts into row_ptr[0..n] (one workgroup).
 __global__ __launch_bounds__(1024) void k_scan(const int64_t *__restrict__ counts,
-                                               int64_t *__restrict__ row_ptr, int n) {
+                                               int64_t *__restrict__ row_ptr, int n,
+                                               int64_t *total_out) {
     __shared__ int64_t part[1024];
     const int t = threadIdx.x;
     const int per = (n + 1023) / 1024;
@@ -793,6 +869,7 @@ __global__ __launch_bounds__(1024) void k_scan(const int64_t *__restrict__ count
             run += v;
         }
         row_ptr[n] = run;
+        if (total_out) *total_out = run;
     }
     __syncthreads();
     int64_t run = part[t];
@@ -810,12 +887,20 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_prune_fill(const Inst *__
                                                                     const int64_t *__restrict__ row_ptr,
                                                                     int32_t *__restrict__ col,
                                                                     int16_t *__restrict__ wout) {
+    extern __shared__ double lv[];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     int u0, u1;
     unit_range(nunits, u0, u1);
+    int cur = -1;
     for (int u = u0; u < u1; ++u) {
         const RowUnit un = units[u];
         const Inst &I = insts[un.inst];
+        if (un.inst != cur) {
+            __syncthreads();
+            stage_logv(I, lv);
+            __syncthreads();
+            cur = un.inst;
+        }
         const int n = I.n, row = un.row0 + wave;
         if (row >= n) continue;
         const int par = I.ctl->iter & 1;
@@ -842,8 +927,7 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_prune_fill(const Inst *__
                     for (int c = 0; c < 8; ++c) {
                         const int j = j0 + c;
                         if (wv[c] != SK_SENTINEL) {
-                            const double lx =
-                                p * (double)wv[c] + f + ((double)I.G[j] + (double)I.gam[j]);
+                            const double lx = p * (double)wv[c] + f + logv_at(I, lv, j);
                             if (lx >= logt) keep |= 1u << c;
                         }
                     }
@@ -875,7 +959,7 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_prune_fill(const Inst *__
             if (j < n) {
                 w = wr[j];
                 if (w != SK_SENTINEL) {
-                    const double lx = p * (double)w + f + ((double)I.G[j] + (double)I.gam[j]);
+                    const double lx = p * (double)w + f + logv_at(I, lv, j);
                     keep = lx >= logt;
                 }
             }
@@ -960,9 +1044,14 @@ hipError_t launch_iter_end(const Inst *d_insts, int count, hipStream_t st) {
     return hipGetLastError();
 }
 hipError_t launch_check_rows(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
-                             double *rsum, double *rmax, hipStream_t st) {
-    hipLaunchKernelGGL(k_check_rows, dim3(grid), dim3(kRowWaves * kWave), 0, st, d_insts, d_units,
+                             double *rsum, double *rmax, size_t lds_bytes, hipStream_t st) {
+    hipLaunchKernelGGL(k_check_rows, dim3(grid), dim3(kRowWaves * kWave), lds_bytes, st, d_insts, d_units,
                        nunits, rsum, rmax);
+    return hipGetLastError();
+}
+hipError_t launch_check_reduce(const Inst *d_insts, int inst, const double *rsum,
+                               const double *rmax, const double *csum, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_check_reduce, dim3(1), dim3(256), 0, st, d_insts, inst, rsum, rmax, csum, out);
     return hipGetLastError();
 }
 hipError_t launch_check_cols(const Inst *d_insts, int inst, int n, int nseg, double *part,
@@ -974,26 +1063,37 @@ hipError_t launch_check_cols(const Inst *d_insts, int inst, int n, int nseg, dou
     return hipGetLastError();
 }
 hipError_t launch_prune_count(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
-                              double logt, int64_t *counts, hipStream_t st) {
-    hipLaunchKernelGGL(k_prune_count, dim3(grid), dim3(kRowWaves * kWave), 0, st, d_insts, d_units,
+                              double logt, int64_t *counts, size_t lds_bytes, hipStream_t st) {
+    hipLaunchKernelGGL(k_prune_count, dim3(grid), dim3(kRowWaves * kWave), lds_bytes, st, d_insts, d_units,
                        nunits, logt, counts);
     return hipGetLastError();
 }
-hipError_t launch_scan(const int64_t *counts, int64_t *row_ptr, int n, hipStream_t st) {
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, counts, row_ptr, n);
+hipError_t launch_scan(const int64_t *counts, int64_t *row_ptr, int n, hipStream_t st,
+                       int64_t *total_out) {
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, counts, row_ptr, n, total_out);
     return hipGetLastError();
 }
 hipError_t launch_prune_fill(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
                              double logt, const int64_t *row_ptr, int32_t *col, int16_t *w,
-                             hipStream_t st) {
-    hipLaunchKernelGGL(k_prune_fill, dim3(grid), dim3(kRowWaves * kWave), 0, st, d_insts, d_units,
+                             size_t lds_bytes, hipStream_t st) {
+    hipLaunchKernelGGL(k_prune_fill, dim3(grid), dim3(kRowWaves * kWave), lds_bytes, st, d_insts, d_units,
                        nunits, logt, row_ptr, col, w);
     return hipGetLastError();
 }
 hipError_t set_kernel_attributes() {
-    return hipFuncSetAttribute((const void *)k_row_sweep,
-                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)(kMaxN * sizeof(float2)));
+    const int lds = (int)(kMaxN * sizeof(double));
+    hipError_t e;
+    if ((e = hipFuncSetAttribute((const void *)k_row_sweep, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 lds)) != hipSuccess)
+        return e;
+    if ((e = hipFuncSetAttribute((const void *)k_check_rows,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds)) != hipSuccess)
+        return e;
+    if ((e = hipFuncSetAttribute((const void *)k_prune_count,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds)) != hipSuccess)
+        return e;
+    return hipFuncSetAttribute((const void *)k_prune_fill, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               lds);
 }
 
 }  // namespace sk

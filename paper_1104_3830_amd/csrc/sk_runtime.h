@@ -34,6 +34,8 @@ struct Batch {
     double *d_rsum = nullptr, *d_rmax = nullptr, *d_csum = nullptr;
     double *d_cpart = nullptr;     // FP64 column partials [nseg][n] of the checked instance
     Ctl *d_ctl_all = nullptr;      // gathered control blocks (one copy per check)
+    double *d_checkout = nullptr;  // [count][4] reduced FP64 checks
+    int64_t *d_nnz = nullptr;      // [count] kept entries per instance
     int64_t *d_counts = nullptr;
     size_t row_lds = 0;
     size_t row_lds_k = 0;
@@ -106,6 +108,8 @@ struct sk_ctx {
     std::string err;
     std::mutex mu;                 // one blocking call at a time
     sk::Ctl *h_ctl = nullptr;      // pinned readback of control blocks
+    double *h_checkout = nullptr;  // pinned readback of reduced checks [kMaxBatch][4]
+    int64_t *h_nnz = nullptr;      // pinned readback of kept counts [kMaxBatch]
     sk::Batch scratch_batch;
     int absorbs = 0;
     double k_res_rows = 0, k_res_cols = 0;
@@ -129,6 +133,8 @@ sk_status iterate_i16(sk_ctx *ctx, Batch &B);
 sk_status run_batch_i16(sk_ctx *ctx, Batch &B, const sk_params *prm);
 sk_status run_single_k(sk_ctx *ctx, Batch &B, const sk_params *prm);
 sk_status check_fp64(sk_ctx *ctx, Batch &B, int k, sk_report *rep);
+sk_status enqueue_check(sk_ctx *ctx, Batch &B, int k);  // writes B.d_checkout[k]
+void report_from_check(const double *out4, int p, sk_report *rep);
 void fill_report(const Ctl &c, sk_report *rep);
 sk_status copy_potentials_out(sk_ctx *ctx, Batch &B, int k, void *pot);
 sk_status scale_impl(sk_ctx *ctx, int count, const int16_t *const *W, const int32_t *n,

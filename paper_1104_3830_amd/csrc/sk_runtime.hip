@@ -75,6 +75,7 @@ size_t shared_bytes(int32_t count, const int32_t *n) {
     size_t b = 0;
     b += align_up(sizeof(Inst) * count, 256);
     b += align_up(sizeof(Ctl) * count, 256);
+    b += align_up(sizeof(double) * 4 * count, 256) + align_up(sizeof(int64_t) * count, 256);
     b += align_up(sizeof(RowUnit) * rows, 256);
     b += align_up(sizeof(ColUnit) * cols, 256);
     b += align_up(sizeof(FinUnit) * fins, 256);
@@ -241,7 +242,11 @@ sk_status sk_create(sk_ctx **out, int device, void *hip_stream, void *arena_dev_
     (void)hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, device);
     if (c->num_cus <= 0) c->num_cus = 256;
     if (hipHostMalloc((void **)&c->h_ctl, sizeof(Ctl) * kMaxBatch, hipHostMallocDefault) !=
-        hipSuccess) {
+            hipSuccess ||
+        hipHostMalloc((void **)&c->h_checkout, sizeof(double) * 4 * kMaxBatch,
+                      hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&c->h_nnz, sizeof(int64_t) * kMaxBatch, hipHostMallocDefault) !=
+            hipSuccess) {
         delete c;
         return SK_EDEVICE;
     }
@@ -255,6 +260,8 @@ sk_status sk_destroy(sk_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->h_ctl) (void)hipHostFree(ctx->h_ctl);
+    if (ctx->h_checkout) (void)hipHostFree(ctx->h_checkout);
+    if (ctx->h_nnz) (void)hipHostFree(ctx->h_nnz);
     delete ctx;
     return SK_OK;
 }
@@ -363,6 +370,8 @@ sk_status sk::finish_tables(sk_ctx *ctx, Bump &bump, Batch &B) {
     }
     B.d_insts = bump.take<Inst>(B.count);
     B.d_ctl_all = bump.take<Ctl>(B.count);
+    B.d_checkout = bump.take<double>(4 * (size_t)B.count);
+    B.d_nnz = bump.take<int64_t>(B.count);
     B.d_rows = bump.take<RowUnit>(B.h_rows.size());
     B.d_cols = bump.take<ColUnit>(B.h_cols.size());
     B.d_fins = bump.take<FinUnit>(B.h_fins.size());
@@ -372,7 +381,7 @@ sk_status sk::finish_tables(sk_ctx *ctx, Bump &bump, Batch &B) {
     B.d_counts = bump.take<int64_t>(B.nmax + 1);
     B.d_cpart = bump.take<double>(cpart);
     if (!B.d_insts || !B.d_rows || !B.d_cols || !B.d_fins || !B.d_rsum || !B.d_rmax || !B.d_csum ||
-        !B.d_counts || !B.d_cpart || !B.d_ctl_all)
+        !B.d_counts || !B.d_cpart || !B.d_ctl_all || !B.d_checkout || !B.d_nnz)
         return fail(ctx, SK_ENOMEM, "arena too small for the batch tables");
     // grids: row sweep stages n columns of potentials (8 B each) in LDS
     const size_t lds = sizeof(float2) * (size_t)B.nmax;
@@ -525,48 +534,42 @@ sk_status sk::run_batch_i16(sk_ctx *ctx, Batch &B, const sk_params *prm) {
     return SK_OK;
 }
 
-// FP64 recheck of instance k: residuals and the certificate upper bound.
-sk_status sk::check_fp64(sk_ctx *ctx, Batch &B, int k, sk_report *rep) {
+// FP64 recheck of instance k (enqueued): row and column sums of the balanced
+// matrix and the certificate terms, reduced on the device into B.d_checkout[k].
+sk_status sk::enqueue_check(sk_ctx *ctx, Batch &B, int k) {
     const Inst &I = B.h_insts[k];
     const int nn = I.n;
-    std::vector<RowUnit> rows;
-    for (int r = 0; r < nn; r += kRowWaves) rows.push_back(RowUnit{k, r});
-    // reuse the batch row table: find this instance's units
     size_t first = 0;
     while (first < B.h_rows.size() && B.h_rows[first].inst != k) ++first;
     const int nunits = (nn + kRowWaves - 1) / kRowWaves;
     const int grid = std::min(nunits, ctx->num_cus * 2);
-    HIPCHK(ctx, PROF(ctx, KID_CHECK_ROWS, launch_check_rows(B.d_insts, B.d_rows + first, nunits, grid, B.d_rsum, B.d_rmax,
-                                  ctx->stream)));
-    HIPCHK(ctx, PROF(ctx, KID_CHECK_COLS, launch_check_cols(B.d_insts, k, nn, I.nseg, B.d_cpart, B.d_csum, ctx->stream)));
-    std::vector<double> rsum(nn), rmax(nn), csum(nn);
-    std::vector<int32_t> G(nn);
-    std::vector<float> gam(nn);
-    HIPCHK(ctx, hipMemcpyAsync(rsum.data(), B.d_rsum, 8 * (size_t)nn, hipMemcpyDeviceToHost,
-                               ctx->stream));
-    HIPCHK(ctx, hipMemcpyAsync(rmax.data(), B.d_rmax, 8 * (size_t)nn, hipMemcpyDeviceToHost,
-                               ctx->stream));
-    HIPCHK(ctx, hipMemcpyAsync(csum.data(), B.d_csum, 8 * (size_t)nn, hipMemcpyDeviceToHost,
-                               ctx->stream));
-    HIPCHK(ctx, hipMemcpyAsync(G.data(), I.G, 4 * (size_t)nn, hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(ctx, hipMemcpyAsync(gam.data(), I.gam, 4 * (size_t)nn, hipMemcpyDeviceToHost,
-                               ctx->stream));
+    HIPCHK(ctx, PROF(ctx, KID_CHECK_ROWS, launch_check_rows(B.d_insts, B.d_rows + first, nunits, grid,
+                                                            B.d_rsum, B.d_rmax,
+                                                            sizeof(double) * (size_t)nn, ctx->stream)));
+    HIPCHK(ctx, PROF(ctx, KID_CHECK_COLS, launch_check_cols(B.d_insts, k, nn, I.nseg, B.d_cpart,
+                                                            B.d_csum, ctx->stream)));
+    HIPCHK(ctx, launch_check_reduce(B.d_insts, k, B.d_rsum, B.d_rmax, B.d_csum,
+                                    B.d_checkout + 4 * (size_t)k, ctx->stream));
+    return SK_OK;
+}
+
+// Proposition prop:aoc with log d_r = log u, log d_c = log v: log u cancels,
+// UB = p^-1 (sum_i max_j (p w_ij + log v_j) - sum_j log v_j).
+void sk::report_from_check(const double *o, int p, sk_report *rep) {
+    rep->residual_fp64 = o[0];
+    rep->col_residual_fp64 = o[1];
+    rep->residual_exact_fp64 = o[0];
+    rep->col_residual_exact_fp64 = o[1];
+    rep->ub = (o[2] - o[3]) / (double)p;
+}
+
+sk_status sk::check_fp64(sk_ctx *ctx, Batch &B, int k, sk_report *rep) {
+    sk_status st = enqueue_check(ctx, B, k);
+    if (st != SK_OK) return st;
+    HIPCHK(ctx, hipMemcpyAsync(ctx->h_checkout + 4 * (size_t)k, B.d_checkout + 4 * (size_t)k,
+                               4 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-    double rr = 0, cr = 0, sm = 0, sg = 0;
-    for (int i = 0; i < nn; ++i) {
-        rr = std::max(rr, std::fabs(rsum[i] - 1.0));
-        cr = std::max(cr, std::fabs(csum[i] - 1.0));
-        sm += rmax[i];
-        sg += (double)G[i] + (double)gam[i];
-    }
-    const Ctl &c = ctx->h_ctl[k];
-    rep->residual_fp64 = rr;
-    rep->col_residual_fp64 = cr;
-    rep->residual_exact_fp64 = rr;
-    rep->col_residual_exact_fp64 = cr;
-    // Proposition prop:aoc with log d_r = log u, log d_c = log v: log u cancels,
-    // UB = p^-1 (sum_i max_j (p w_ij + log v_j) - sum_j log v_j).
-    rep->ub = (sm - sg) / (double)c.p;
+    report_from_check(ctx->h_checkout + 4 * (size_t)k, ctx->h_ctl[k].p, rep);
     return SK_OK;
 }
 
@@ -644,6 +647,18 @@ sk_status sk::scale_impl(sk_ctx *ctx, int count, const int16_t *const *W, const 
         if ((st = run_single_k(ctx, B, prm)) != SK_OK) return st;
     }
     sk_status result = SK_OK;
+    // FP64 checks of every instance, reduced on the device; one copy back
+    bool any_check = false;
+    for (int k = 0; k < count; ++k) {
+        if (ctx->h_ctl[k].err & (ERR_EMPTY_ROW | ERR_EMPTY_COL)) continue;
+        if ((st = enqueue_check(ctx, B, k)) != SK_OK) return st;
+        any_check = true;
+    }
+    if (any_check) {
+        HIPCHK(ctx, hipMemcpyAsync(ctx->h_checkout, B.d_checkout, sizeof(double) * 4 * count,
+                                   hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    }
     for (int k = 0; k < count; ++k) {
         const Ctl &c = ctx->h_ctl[k];
         sk_report rep;
@@ -651,7 +666,7 @@ sk_status sk::scale_impl(sk_ctx *ctx, int count, const int16_t *const *W, const 
         fill_report(c, &rep);
         rep.absorbs = ctx->absorbs;
         if (!(c.err & (ERR_EMPTY_ROW | ERR_EMPTY_COL))) {
-            if ((st = check_fp64(ctx, B, k, &rep)) != SK_OK) return st;
+            report_from_check(ctx->h_checkout + 4 * (size_t)k, c.p, &rep);
             if (prm->storage != SK_W_I16) {
                 rep.residual_fp64 = ctx->k_res_rows;
                 rep.col_residual_fp64 = ctx->k_res_cols;
@@ -730,7 +745,7 @@ sk_status sk_prune(sk_ctx *ctx, const int16_t *W, int32_t n, const void *potenti
     const double logt = std::log(params->threshold);
     const int nunits = (int)B.h_rows.size();
     HIPCHK(ctx, PROF(ctx, KID_PRUNE_COUNT, launch_prune_count(B.d_insts, B.d_rows, nunits, B.row_grid, logt, B.d_counts,
-                                   ctx->stream)));
+                                   sizeof(double) * (size_t)n, ctx->stream)));
     HIPCHK(ctx, PROF(ctx, KID_SCAN, launch_scan(B.d_counts, csr->row_ptr, n, ctx->stream)));
     int64_t total = 0;
     HIPCHK(ctx, hipMemcpyAsync(&total, csr->row_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost,
@@ -744,7 +759,7 @@ sk_status sk_prune(sk_ctx *ctx, const int16_t *W, int32_t n, const void *potenti
     if (total > 0) {
         if (!csr->col || !csr->w) return fail(ctx, SK_EINVAL, "null col/w buffers");
         HIPCHK(ctx, PROF(ctx, KID_PRUNE_FILL, launch_prune_fill(B.d_insts, B.d_rows, nunits, B.row_grid, logt, csr->row_ptr,
-                                      csr->col, csr->w, ctx->stream)));
+                                      csr->col, csr->w, sizeof(double) * (size_t)n, ctx->stream)));
     }
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     return SK_OK;

@@ -140,78 +140,112 @@ static sk_status rebuild(Server *S) {
     return upload_batch(ctx, S->B);
 }
 
-// Retires instance k of the batch: report, FP64 check, CSR to the host.
-static sk_status retire(Server *S, int k, Request *r) {
+// Retires the finished instances fin[] of the batch in two device phases:
+// (1) FP64 checks and kept-entry counts of all of them, one copy + one sync;
+// (2) CSR fills and copies to the host. Their device regions are released
+// afterwards and the exact solves go to the host pool.
+static sk_status retire_all(Server *S, const std::vector<int> &fin) {
     sk_ctx *ctx = S->ctx;
     Batch &B = S->B;
-    const Ctl &c = ctx->h_ctl[k];
-    memset(&r->rep, 0, sizeof r->rep);
-    fill_report(c, &r->rep);
-    if (c.err & (ERR_EMPTY_ROW | ERR_EMPTY_COL)) {
-        r->status = SK_ENOSUPPORT;
-        return SK_OK;
-    }
-    if (c.capped) r->status = SK_ENOCONV;
-    sk_status st = check_fp64(ctx, B, k, &r->rep);
-    if (st != SK_OK) return st;
-    const int n = r->n;
-    size_t first = 0;
-    while (first < B.h_rows.size() && B.h_rows[first].inst != k) ++first;
-    const int nunits = (n + kRowWaves - 1) / kRowWaves;
-    const int grid = std::min(nunits, ctx->num_cus * 2);
-    const double logt = std::log(r->prm.threshold);
-    // row_ptr, col and w are transient allocations from the free arena space
-    size_t rp_off = 0;
-    const size_t rp_len = sizeof(int64_t) * (n + 1);
-    bool have_rp;
-    {
-        std::lock_guard<std::mutex> g(S->mu);
-        have_rp = S->ralloc.alloc(rp_len, rp_off);
-    }
-    if (!have_rp) return fail(ctx, SK_ENOMEM, "no device memory for a CSR row pointer");
-    int64_t *d_rp = (int64_t *)(ctx->arena + rp_off);
-    hipError_t e = launch_prune_count(B.d_insts, B.d_rows + first, nunits, grid, logt, B.d_counts,
-                                      ctx->stream);
-    if (e == hipSuccess) e = launch_scan(B.d_counts, d_rp, n, ctx->stream);
-    r->rp.resize(n + 1);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(r->rp.data(), d_rp, rp_len, hipMemcpyDeviceToHost, ctx->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-    const int64_t nnz = r->rp[n];
-    size_t cw_off = 0;
-    const size_t col_bytes = align_up(sizeof(int32_t) * (size_t)std::max<int64_t>(nnz, 1), 256);
-    const size_t cw_len = col_bytes + sizeof(int16_t) * (size_t)std::max<int64_t>(nnz, 1);
-    bool have_cw = false;
-    if (e == hipSuccess) {
-        std::lock_guard<std::mutex> g(S->mu);
-        have_cw = S->ralloc.alloc(cw_len, cw_off);
-    }
-    if (e == hipSuccess && have_cw && nnz > 0) {
-        int32_t *d_col = (int32_t *)(ctx->arena + cw_off);
-        int16_t *d_w = (int16_t *)(ctx->arena + cw_off + col_bytes);
+    const size_t m = fin.size();
+    std::vector<size_t> rp_off(m, 0), rp_len(m, 0);
+    std::vector<char> live(m, 0);
+    hipError_t e = hipSuccess;
+    sk_status st = SK_OK;
+    for (size_t q = 0; q < m && st == SK_OK && e == hipSuccess; ++q) {
+        const int k = fin[q];
+        Request *r = S->active[k];
+        const Ctl &c = ctx->h_ctl[k];
+        memset(&r->rep, 0, sizeof r->rep);
+        fill_report(c, &r->rep);
+        if (c.err & (ERR_EMPTY_ROW | ERR_EMPTY_COL)) {
+            r->status = SK_ENOSUPPORT;
+            continue;
+        }
+        if (c.capped) r->status = SK_ENOCONV;
+        rp_len[q] = sizeof(int64_t) * (r->n + 1);
         {
+            std::lock_guard<std::mutex> g(S->mu);
+            if (!S->ralloc.alloc(rp_len[q], rp_off[q])) {
+                r->status = SK_ENOMEM;
+                continue;
+            }
+        }
+        live[q] = 1;
+        st = enqueue_check(ctx, B, k);
+        if (st != SK_OK) break;
+        size_t first = 0;
+        while (first < B.h_rows.size() && B.h_rows[first].inst != k) ++first;
+        const int nunits = (r->n + kRowWaves - 1) / kRowWaves;
+        const int grid = std::min(nunits, ctx->num_cus * 2);
+        const double logt = std::log(r->prm.threshold);
+        int64_t *d_rp = (int64_t *)(ctx->arena + rp_off[q]);
+        e = launch_prune_count(B.d_insts, B.d_rows + first, nunits, grid, logt, B.d_counts,
+                               sizeof(double) * (size_t)r->n, ctx->stream);
+        if (e == hipSuccess) e = launch_scan(B.d_counts, d_rp, r->n, ctx->stream, B.d_nnz + k);
+    }
+    if (st == SK_OK && e == hipSuccess)
+        e = hipMemcpyAsync(ctx->h_checkout, B.d_checkout, sizeof(double) * 4 * B.count,
+                           hipMemcpyDeviceToHost, ctx->stream);
+    if (st == SK_OK && e == hipSuccess)
+        e = hipMemcpyAsync(ctx->h_nnz, B.d_nnz, sizeof(int64_t) * B.count, hipMemcpyDeviceToHost,
+                           ctx->stream);
+    if (st == SK_OK && e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    // phase 2: fills
+    std::vector<size_t> cw_off(m, 0), cw_len(m, 0);
+    for (size_t q = 0; q < m && st == SK_OK && e == hipSuccess; ++q) {
+        if (!live[q]) continue;
+        const int k = fin[q];
+        Request *r = S->active[k];
+        report_from_check(ctx->h_checkout + 4 * (size_t)k, ctx->h_ctl[k].p, &r->rep);
+        const int64_t nnz = ctx->h_nnz[k];
+        r->rep.nnz_kept = nnz;
+        r->rp.resize(r->n + 1);
+        int64_t *d_rp = (int64_t *)(ctx->arena + rp_off[q]);
+        if (nnz > 0) {
+            const size_t col_bytes = align_up(sizeof(int32_t) * (size_t)nnz, 256);
+            cw_len[q] = col_bytes + sizeof(int16_t) * (size_t)nnz;
+            bool ok;
+            {
+                std::lock_guard<std::mutex> g(S->mu);
+                ok = S->ralloc.alloc(cw_len[q], cw_off[q]);
+            }
+            if (!ok) {
+                cw_len[q] = 0;
+                r->status = SK_ENOMEM;
+                continue;
+            }
+            int32_t *d_col = (int32_t *)(ctx->arena + cw_off[q]);
+            int16_t *d_w = (int16_t *)(ctx->arena + cw_off[q] + col_bytes);
+            size_t first = 0;
+            while (first < B.h_rows.size() && B.h_rows[first].inst != k) ++first;
+            const int nunits = (r->n + kRowWaves - 1) / kRowWaves;
+            const int grid = std::min(nunits, ctx->num_cus * 2);
+            e = launch_prune_fill(B.d_insts, B.d_rows + first, nunits, grid,
+                                  std::log(r->prm.threshold), d_rp, d_col, d_w,
+                                  sizeof(double) * (size_t)r->n, ctx->stream);
             r->col.resize(nnz);
             r->w.resize(nnz);
-            e = launch_prune_fill(B.d_insts, B.d_rows + first, nunits, grid, logt, d_rp, d_col, d_w,
-                                  ctx->stream);
             if (e == hipSuccess)
                 e = hipMemcpyAsync(r->col.data(), d_col, sizeof(int32_t) * nnz,
                                    hipMemcpyDeviceToHost, ctx->stream);
             if (e == hipSuccess)
                 e = hipMemcpyAsync(r->w.data(), d_w, sizeof(int16_t) * nnz, hipMemcpyDeviceToHost,
                                    ctx->stream);
-            if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
         }
-    } else if (e == hipSuccess && !have_cw) {
-        r->status = SK_ENOMEM;
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(r->rp.data(), d_rp, rp_len[q], hipMemcpyDeviceToHost, ctx->stream);
     }
+    if (st == SK_OK && e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     {
         std::lock_guard<std::mutex> g(S->mu);
-        S->ralloc.release(rp_off, rp_len);
-        if (have_cw) S->ralloc.release(cw_off, cw_len);
+        for (size_t q = 0; q < m; ++q) {
+            if (rp_len[q]) S->ralloc.release(rp_off[q], rp_len[q]);
+            if (cw_len[q]) S->ralloc.release(cw_off[q], cw_len[q]);
+        }
     }
+    if (st != SK_OK) return st;
     if (e != hipSuccess) return fail(ctx, SK_EDEVICE, "retire: %s", hipGetErrorString(e));
-    r->rep.nnz_kept = nnz;
     return SK_OK;
 }
 
@@ -301,29 +335,29 @@ static void serve_loop(Server *S) {
             break;
         }
         // retire finished instances
+        std::vector<int> fin;
         std::vector<Request *> keep;
         for (int k = 0; k < (int)S->active.size(); ++k) {
-            Request *r = S->active[k];
-            if (ctx->h_ctl[k].state == ST_RUNNING) {
-                keep.push_back(r);
-                continue;
-            }
-            st = retire(S, k, r);
-            std::lock_guard<std::mutex> g(S->mu);
-            S->ralloc.release(r->off, r->len);
-            if (st != SK_OK || r->status == SK_ENOSUPPORT || r->status == SK_ENOMEM) {
-                if (st != SK_OK) r->status = SK_EDEVICE;
-                r->phase = 3;
-            } else {
-                r->phase = 2;
-                S->solve_q.push_back(r);
-                S->cv_solve.notify_one();
-            }
-            dirty = true;
+            if (ctx->h_ctl[k].state == ST_RUNNING) keep.push_back(S->active[k]);
+            else fin.push_back(k);
         }
-        if (dirty) {
+        if (!fin.empty()) {
+            st = retire_all(S, fin);
             std::lock_guard<std::mutex> g(S->mu);
+            for (int k : fin) {
+                Request *r = S->active[k];
+                S->ralloc.release(r->off, r->len);
+                if (st != SK_OK || r->status == SK_ENOSUPPORT || r->status == SK_ENOMEM) {
+                    if (st != SK_OK) r->status = SK_EDEVICE;
+                    r->phase = 3;
+                } else {
+                    r->phase = 2;
+                    S->solve_q.push_back(r);
+                    S->cv_solve.notify_one();
+                }
+            }
             S->active.swap(keep);
+            dirty = true;
         }
     }
 }
