@@ -155,8 +155,9 @@ def traffic_report(kernel, workload, fcsv, wcsv, cfcsv, cwcsv):
     cf = _counter_means(cfcsv, "FETCH_SIZE")["__amd_rocclr_copyBuffer"][0]
     cw = _counter_means(cwcsv, "WRITE_SIZE")["__amd_rocclr_copyBuffer"][0]
     fs, ws = copy_kib / cf, copy_kib / cw
-    f = _counter_means(fcsv, "FETCH_SIZE")["sk::" + kernel]
-    w = _counter_means(wcsv, "WRITE_SIZE")["sk::" + kernel]
+    kname = {"finalize": "sk::k_col_finalize"}.get(kernel, "sk::k_" + kernel)
+    f = _counter_means(fcsv, "FETCH_SIZE")[kname]
+    w = _counter_means(wcsv, "WRITE_SIZE")[kname]
     total = (f[0] * fs + w[0] * ws) * 1024.0
     print(f"kernel: {kernel}")
     print(f"workload: {workload}")

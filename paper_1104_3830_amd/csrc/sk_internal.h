@@ -70,9 +70,12 @@ struct Inst {
     int32_t fused;          // single-pass iteration (colpart holds kFusedSlots rows)
     int32_t fused_grid;
     int32_t ncolslots;      // rows of colpart in use: nseg (sweeps) or fused_grid (single pass)
-    int32_t nresslots;      // residual slots in use: row units (sweeps) or fused_grid
-    float *res_slots;       // per row unit (or workgroup): max |r_i - 1| of the current iterate
+    int32_t pad2;
+    // max |r_i - 1| of the current iterate, per row segment (log-domain
+    // sweeps), per row unit (stored-K sweeps) or per workgroup (single pass)
+    float *res_slots;
     float *drift_slots;     // stored K: per row unit max |log2 a_i|
+    float *rres;            // [n] |r_i - 1| from the log-domain row sweep
 };
 
 // Loads through a global-address-space pointer, so the compiler emits

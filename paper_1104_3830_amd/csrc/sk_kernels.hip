@@ -50,16 +50,6 @@ __device__ __forceinline__ double wave_max_d(double v) {
     return v;
 }
 
-// Unpacks 8 int16 from a 16-byte vector (v_cvt_f32_i32 with word select).
-__device__ __forceinline__ void unpack8(const int4 v, float (&w)[8]) {
-    w[0] = (float)(short)(v.x & 0xffff); w[1] = (float)(v.x >> 16);
-    w[2] = (float)(short)(v.y & 0xffff); w[3] = (float)(v.y >> 16);
-    w[4] = (float)(short)(v.z & 0xffff); w[5] = (float)(v.z >> 16);
-    w[6] = (float)(short)(v.w & 0xffff); w[7] = (float)(v.w >> 16);
-}
-
-constexpr float kSentF = -32768.0f;
-
 // Contiguous range of work units owned by this workgroup.
 __device__ __forceinline__ void unit_range(int nunits, int &u0, int &u1) {
     int per = (nunits + (int)gridDim.x - 1) / (int)gridDim.x;
@@ -136,30 +126,88 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_init(const Inst *__restri
     }
 }
 
+// ---------------------------------------------------------------- exp table
+// Every exponent the sweeps evaluate splits exactly into an integer part
+// E_ij = p w_ij + F_i + G_j and the fractions phi_i, gam_j:
+//   x_ij = exp(E_ij) * exp(phi_i) * exp(gam_j).
+// exp(E) for integer E is read from a table in LDS, correctly rounded to
+// float32; the fraction factors are one value per row and per column. Entries
+// with E <= kTabLo contribute exp(-88) < 2^-126 (dropped: a sum in the safe
+// range [2^-64, 2^64] of at most 16384 such terms changes by less than one
+// part in 2^40); E >= kTabHi reads +inf, which sends the row or column to the
+// exact max-shifted recompute. Integer arithmetic is exact: with p <= 2048
+// and |w| < 2^15, |4 E| < 2^31.
+constexpr int kTabLo = -88;
+constexpr int kTabHi = 80;
+constexpr int kTabN = kTabHi - kTabLo + 1;  // 169 entries
+constexpr int kTabMaxOff = 4 * (kTabN - 1);  // byte offset of the +inf entry
+
+__device__ __forceinline__ void fill_exp_table(float *tab) {
+    for (int k = threadIdx.x; k < kTabN; k += blockDim.x) {
+        float v;
+        if (k == 0) v = 0.f;
+        else if (k == kTabN - 1) v = INFINITY;
+        else v = (float)exp((double)(k + kTabLo));
+        tab[k] = v;
+    }
+}
+
+// Table read at a byte offset already clamped to [0, kTabMaxOff].
+__device__ __forceinline__ float tab_at(const float *tab, int off) {
+    return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(tab) + off);
+}
+
+// Byte offset of exp(E) with 4 E - 4 kTabLo = 4 p w + A + B (A, B prescaled).
+__device__ __forceinline__ int tab_off(int p4, int w, int A, int B) {
+    const int t = __mul24(p4, w) + A + B;
+    return min(max(t, 0), kTabMaxOff);
+}
+
+// Unpacks 8 int16 from a 16-byte vector as int32.
+__device__ __forceinline__ void unpack8i(const int4 v, int (&w)[8]) {
+    w[0] = (int)(short)(v.x & 0xffff); w[1] = v.x >> 16;
+    w[2] = (int)(short)(v.y & 0xffff); w[3] = v.y >> 16;
+    w[4] = (int)(short)(v.z & 0xffff); w[5] = v.z >> 16;
+    w[6] = (int)(short)(v.w & 0xffff); w[7] = v.w >> 16;
+}
+
+__device__ __forceinline__ int wave_max_i(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
 // ---------------------------------------------------------------- row sweep
-// One wavefront per row; column potentials (G_j as float, gam_j*log2 e)
-// staged once per workgroup in LDS; W read with coalesced 16-byte loads.
-// Sum over 8 consecutive columns q*8 .. q*8+7 of one 16-byte chunk.
+// One wavefront per row; per column (4 G_j, exp(gam_j)) staged once per
+// workgroup in LDS; W read with coalesced 16-byte loads. B = 4 (F_i - shift)
+// - 4 kTabLo carries the row's integer part and the shift.
+
+// Column data of the row sweep: a = 4 G_j, g = exp(gam_j).
+struct alignas(8) ColPot {
+    int a;
+    float g;
+};
+
 template <bool SENT>
-__device__ __forceinline__ float chunk8(const int4 v, int q, int n8, float pf, float Ff,
-                                        const float2 *__restrict__ pot, float shift) {
-    float w[8];
-    unpack8(v, w);
+__device__ __forceinline__ float chunk8(const int4 v, int q, int n8, int p4, int B,
+                                        const ColPot *__restrict__ cp,
+                                        const float *__restrict__ tab) {
+    int w[8];
+    unpack8i(v, w);
     float s = 0.f;
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-        const float2 gp = pot[c * n8 + q];
-        const float I = fmaf(w[c], pf, gp.x) + Ff;        // exact integer
-        float e = ex2(fmaf(I, kLog2e, gp.y) - shift);
-        if (SENT) e = (w[c] == kSentF) ? 0.f : e;
-        s += e;
+        const ColPot k = cp[c * n8 + q];
+        float e = tab_at(tab, tab_off(p4, w[c], k.a, B));
+        if (SENT) e = (w[c] == SK_SENTINEL) ? 0.f : e;
+        s = fmaf(e, k.g, s);
     }
     return s;
 }
 
 // Loads in flight per lane in the sweeps (build-time tuning knobs).
 #ifndef SK_ROW_UNROLL
-#define SK_ROW_UNROLL 4
+#define SK_ROW_UNROLL 2
 #endif
 #ifndef SK_COL_UNROLL
 #define SK_COL_UNROLL 2
@@ -168,9 +216,9 @@ __device__ __forceinline__ float chunk8(const int4 v, int q, int n8, float pf, f
 // Row partial sum for one lane: chunks lane*8 + k*512, SK_ROW_UNROLL 16-byte
 // loads in flight per lane.
 template <bool SENT>
-__device__ __forceinline__ float row_partial_v8(const int16_t *__restrict__ wr, int n, float pf,
-                                                float Ff, const float2 *__restrict__ pot, int lane,
-                                                float shift) {
+__device__ __forceinline__ float row_partial_v8(const int16_t *__restrict__ wr, int n, int p4,
+                                                int B, const ColPot *__restrict__ cp,
+                                                const float *__restrict__ tab, int lane) {
     constexpr int U = SK_ROW_UNROLL;
     const int n8 = n >> 3;
     float acc = 0.f;
@@ -181,117 +229,116 @@ __device__ __forceinline__ float row_partial_v8(const int16_t *__restrict__ wr, 
         for (int k = 0; k < U; ++k) v[k] = gload(reinterpret_cast<const int4 *>(wr + j0 + k * 512));
         const int q = j0 >> 3;
 #pragma unroll
-        for (int k = 0; k < U; ++k) acc += chunk8<SENT>(v[k], q + 64 * k, n8, pf, Ff, pot, shift);
+        for (int k = 0; k < U; ++k) acc += chunk8<SENT>(v[k], q + 64 * k, n8, p4, B, cp, tab);
     }
     for (; j0 < n; j0 += 512) {
         const int4 v = gload(reinterpret_cast<const int4 *>(wr + j0));
-        acc += chunk8<SENT>(v, j0 >> 3, n8, pf, Ff, pot, shift);
+        acc += chunk8<SENT>(v, j0 >> 3, n8, p4, B, cp, tab);
     }
     return acc;
 }
 
+// max_j of 4 (p w_ij + G_j) + B over the entries of the row (INT_MIN if none).
 template <bool SENT>
-__device__ __forceinline__ float row_max_v8(const int16_t *__restrict__ wr, int n, float pf,
-                                            float Ff, const float2 *__restrict__ pot, int lane) {
+__device__ __forceinline__ int row_max_v8(const int16_t *__restrict__ wr, int n, int p4, int B,
+                                          const ColPot *__restrict__ cp, int lane) {
     const int n8 = n >> 3;
-    float m = -INFINITY;
+    int m = INT_MIN;
     for (int j0 = lane * 8; j0 < n; j0 += 512) {
         const int4 v = gload(reinterpret_cast<const int4 *>(wr + j0));
-        float w[8];
-        unpack8(v, w);
+        int w[8];
+        unpack8i(v, w);
         const int q = j0 >> 3;
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
-            const float2 gp = pot[c * n8 + q];
-            const float I = fmaf(w[c], pf, gp.x) + Ff;
-            float y = fmaf(I, kLog2e, gp.y);
-            if (SENT) y = (w[c] == kSentF) ? -INFINITY : y;
-            m = fmaxf(m, y);
+            const int t = __mul24(p4, w[c]) + cp[c * n8 + q].a + B;
+            if (!SENT || w[c] != SK_SENTINEL) m = max(m, t);
         }
     }
     return m;
 }
 
 template <bool SENT>
-__device__ __forceinline__ float row_partial_v1(const int16_t *__restrict__ wr, int n, float pf,
-                                                float Ff, const float2 *__restrict__ pot, int lane,
-                                                float shift) {
+__device__ __forceinline__ float row_partial_v1(const int16_t *__restrict__ wr, int n, int p4,
+                                                int B, const ColPot *__restrict__ cp,
+                                                const float *__restrict__ tab, int lane) {
     float acc = 0.f;
     for (int j = lane; j < n; j += kWave) {
-        const float w = (float)gload(wr + j);
-        const float2 gp = pot[j];
-        const float I = fmaf(w, pf, gp.x) + Ff;
-        float e = ex2(fmaf(I, kLog2e, gp.y) - shift);
-        if (SENT) e = (w == kSentF) ? 0.f : e;
-        acc += e;
+        const int w = (int)gload(wr + j);
+        const ColPot k = cp[j];
+        float e = tab_at(tab, tab_off(p4, w, k.a, B));
+        if (SENT) e = (w == SK_SENTINEL) ? 0.f : e;
+        acc = fmaf(e, k.g, acc);
     }
     return acc;
 }
 
 template <bool SENT>
-__device__ __forceinline__ float row_max_v1(const int16_t *__restrict__ wr, int n, float pf,
-                                            float Ff, const float2 *__restrict__ pot, int lane) {
-    float m = -INFINITY;
+__device__ __forceinline__ int row_max_v1(const int16_t *__restrict__ wr, int n, int p4, int B,
+                                          const ColPot *__restrict__ cp, int lane) {
+    int m = INT_MIN;
     for (int j = lane; j < n; j += kWave) {
-        const float w = (float)gload(wr + j);
-        const float2 gp = pot[j];
-        const float I = fmaf(w, pf, gp.x) + Ff;
-        float y = fmaf(I, kLog2e, gp.y);
-        if (SENT) y = (w == kSentF) ? -INFINITY : y;
-        m = fmaxf(m, y);
+        const int w = (int)gload(wr + j);
+        const int t = __mul24(p4, w) + cp[j].a + B;
+        if (!SENT || w != SK_SENTINEL) m = max(m, t);
     }
     return m;
 }
 
 template <bool SENT, bool V8>
 __device__ __forceinline__ void row_step_one(const Inst &I, int row, int par, int lane,
-                                             const float2 *__restrict__ pot, float &resmax) {
+                                             const ColPot *__restrict__ cp,
+                                             const float *__restrict__ tab) {
     const int n = I.n;
     const int16_t *wr = I.W + (int64_t)row * I.pitch;
     const int Fi = I.F[par][row];
     const float phi = I.phi[par][row];
-    const float pf = (float)I.ctl->p;
-    const float Ff = (float)Fi;
-    float S = V8 ? row_partial_v8<SENT>(wr, n, pf, Ff, pot, lane, 0.f)
-                 : row_partial_v1<SENT>(wr, n, pf, Ff, pot, lane, 0.f);
+    const int p4 = 4 * I.ctl->p;
+    // S_i relative to the previous iterate: shift M = 0
+    int M = 0;
+    float S = V8 ? row_partial_v8<SENT>(wr, n, p4, 4 * (Fi - kTabLo), cp, tab, lane)
+                 : row_partial_v1<SENT>(wr, n, p4, 4 * (Fi - kTabLo), cp, tab, lane);
     S = wave_sum(S);
-    float l2S;  // log2 S_i
-    if (S >= kSafeLo && S <= kSafeHi) {
-        l2S = lg2(S);
-    } else {
-        // exact max-shift (Section 4.1.2): m = max_j of the exponent, then the sum
-        float m = V8 ? row_max_v8<SENT>(wr, n, pf, Ff, pot, lane)
-                     : row_max_v1<SENT>(wr, n, pf, Ff, pot, lane);
-        m = wave_max(m);
-        if (m == -INFINITY) {
+    if (!(S >= kSafeLo && S <= kSafeHi)) {
+        // exact max-shift (Section 4.1.2): M = max_j (p w_ij + F_i + G_j)
+        int m4 = V8 ? row_max_v8<SENT>(wr, n, p4, 4 * Fi, cp, lane)
+                    : row_max_v1<SENT>(wr, n, p4, 4 * Fi, cp, lane);
+        m4 = wave_max_i(m4);
+        if (m4 == INT_MIN) {
             if (lane == 0) atomicOr(&I.ctl->err, ERR_EMPTY_ROW);
-            l2S = 0.f;
+            S = 1.f;
         } else {
-            float S2 = V8 ? row_partial_v8<SENT>(wr, n, pf, Ff, pot, lane, m)
-                          : row_partial_v1<SENT>(wr, n, pf, Ff, pot, lane, m);
-            S2 = wave_sum(S2);
-            l2S = m + lg2(S2);
+            M = m4 >> 2;  // exact: m4 is a multiple of 4
+            S = V8 ? row_partial_v8<SENT>(wr, n, p4, 4 * (Fi - M - kTabLo), cp, tab, lane)
+                   : row_partial_v1<SENT>(wr, n, p4, 4 * (Fi - M - kTabLo), cp, tab, lane);
+            S = wave_sum(S);
         }
     }
     if (lane == 0) {
-        float phin = -l2S * kLn2;
+        // log u_i <- F_i - M - log S
+        const float l2S = lg2(S);
+        const float phin = -l2S * kLn2;
         const float k = rintf(phin);
-        I.F[par ^ 1][row] = Fi + (int)k;
+        I.F[par ^ 1][row] = Fi - M + (int)k;
         I.phi[par ^ 1][row] = phin - k;
-        // r_i = exp(phi_i) * S_i: row sum of the current iterate
-        const float r = ex2(fmaf(phi, kLog2e, l2S));
-        resmax = fmaxf(resmax, fabsf(r - 1.f));
+        // r_i = exp(phi_i + M) S: row sum of the current iterate
+        const float r = ex2(fmaf(phi + (float)M, kLog2e, l2S));
+        I.rres[row] = fabsf(r - 1.f);
     }
 }
 
+// Waves run their rows independently: the only barrier is the restaging of
+// the column data when the instance changes. The residual |r_i - 1| goes to
+// rres[i]; the column sweep reduces it per row segment.
 __global__ __launch_bounds__(kRowWaves * kWave) void k_row_sweep(const Inst *__restrict__ insts,
                                                                    const RowUnit *__restrict__ units,
                                                                    int nunits) {
-    extern __shared__ float2 lds_pot[];
-    __shared__ float wres[2][kRowWaves];
+    extern __shared__ ColPot lds_cp[];
+    __shared__ float tab[kTabN];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     int u0, u1;
     unit_range(nunits, u0, u1);
+    fill_exp_table(tab);
     int cur = -1;
     for (int u = u0; u < u1; ++u) {
         const RowUnit un = units[u];
@@ -304,33 +351,25 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_row_sweep(const Inst *__r
             __syncthreads();
             const int n8 = n >> 3;
             for (int j = threadIdx.x; j < n; j += blockDim.x) {
-                const float2 gp = make_float2((float)I.G[j], I.gam[j] * kLog2e);
-                lds_pot[I.vec8 ? swz8(j, n8) : j] = gp;
+                ColPot k;
+                k.a = 4 * I.G[j];
+                k.g = ex2(I.gam[j] * kLog2e);
+                lds_cp[I.vec8 ? swz8(j, n8) : j] = k;
             }
             __syncthreads();
             cur = un.inst;
         }
         const int row = un.row0 + wave;
-        float resmax = 0.f;
         if (row < n) {
             const int par = iter & 1;
             const bool sent = ctl->sent != 0u;
             if (I.vec8) {
-                if (sent) row_step_one<true, true>(I, row, par, lane, lds_pot, resmax);
-                else row_step_one<false, true>(I, row, par, lane, lds_pot, resmax);
+                if (sent) row_step_one<true, true>(I, row, par, lane, lds_cp, tab);
+                else row_step_one<false, true>(I, row, par, lane, lds_cp, tab);
             } else {
-                if (sent) row_step_one<true, false>(I, row, par, lane, lds_pot, resmax);
-                else row_step_one<false, false>(I, row, par, lane, lds_pot, resmax);
+                if (sent) row_step_one<true, false>(I, row, par, lane, lds_cp, tab);
+                else row_step_one<false, false>(I, row, par, lane, lds_cp, tab);
             }
-        }
-        // residual slot of this unit (no atomics: the finaliser reduces the slots)
-        const int b = (u - u0) & 1;
-        if (lane == 0) wres[b][wave] = resmax;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            float m = 0.f;
-            for (int w = 0; w < kRowWaves; ++w) m = fmaxf(m, wres[b][w]);
-            I.res_slots[un.row0 / kRowWaves] = m;
         }
     }
 }
@@ -338,41 +377,45 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_row_sweep(const Inst *__r
 // ---------------------------------------------------------------- column sweep
 // Workgroup = column tile x row segment. Lanes own columns (8 per lane with
 // 16-byte loads, coalesced along the row); waves split the segment's rows;
-// row potentials of the segment are staged in LDS; the four waves' partial
-// sums are combined through LDS in a fixed order and written to a fixed slot
-// colpart[seg][j]. The last workgroup to finish a tile sums its nseg slots in
-// segment order (deterministic) and updates G_j, gam_j.
+// per row (4 (F_i - kTabLo), exp(phi_i)) is staged in LDS; the four waves'
+// partial sums are combined through LDS in a fixed order and written to the
+// fixed slot colpart[seg][j], which the finalise kernel reduces in slot order.
 
 __device__ __forceinline__ bool stage_converged(const Inst &I, const Ctl *ctl) {
     const float res = __uint_as_float(ctl->res_bits);
     return ctl->iter >= 1 && res < I.tol;
 }
 
+// Row data of the column sweep: b = 4 (F_i - kTabLo), r = exp(phi_i).
+struct alignas(8) RowPot {
+    int b;
+    float r;
+};
+
 template <bool SENT, bool V8>
 __device__ __forceinline__ void col_partial(const Inst &I, int tile, int r0, int r1, int wave,
-                                            int lane, const float2 *__restrict__ rowpot,
-                                            float (&acc)[8]) {
+                                            int lane, const RowPot *__restrict__ rowpot,
+                                            const float *__restrict__ tab, float (&acc)[8]) {
     const int n = I.n;
-    const float pf = (float)I.ctl->p;
+    const int p4 = 4 * I.ctl->p;
 #pragma unroll
     for (int c = 0; c < 8; ++c) acc[c] = 0.f;
     if (V8) {
         const int c0 = tile * kColTile8 + lane * 8;
         if (c0 >= n) return;
-        float Gf[8];
+        int A[8];
 #pragma unroll
-        for (int c = 0; c < 8; ++c) Gf[c] = (float)I.G[c0 + c];
+        for (int c = 0; c < 8; ++c) A[c] = 4 * I.G[c0 + c];
         const int16_t *base = I.W + c0;
         const int64_t pitch = I.pitch;
-        auto body = [&](const int4 v, const float2 rp) {
-            float w[8];
-            unpack8(v, w);
+        auto body = [&](const int4 v, const RowPot rp) {
+            int w[8];
+            unpack8i(v, w);
 #pragma unroll
             for (int c = 0; c < 8; ++c) {
-                const float Iv = fmaf(w[c], pf, Gf[c]) + rp.x;
-                float e = ex2(fmaf(Iv, kLog2e, rp.y));
-                if (SENT) e = (w[c] == kSentF) ? 0.f : e;
-                acc[c] += e;
+                float e = tab_at(tab, tab_off(p4, w[c], A[c], rp.b));
+                if (SENT) e = (w[c] == SK_SENTINEL) ? 0.f : e;
+                acc[c] = fmaf(e, rp.r, acc[c]);
             }
         };
         int r = r0 + wave;
@@ -391,14 +434,13 @@ __device__ __forceinline__ void col_partial(const Inst &I, int tile, int r0, int
     } else {
         const int c0 = tile * kColTile1 + lane;
         if (c0 >= n) return;
-        const float Gf = (float)I.G[c0];
+        const int A = 4 * I.G[c0];
         for (int r = r0 + wave; r < r1; r += kColWaves) {
-            const float2 rp = rowpot[r - r0];
-            const float w = (float)gload(I.W + (int64_t)r * I.pitch + c0);
-            const float Iv = fmaf(w, pf, Gf) + rp.x;
-            float e = ex2(fmaf(Iv, kLog2e, rp.y));
-            if (SENT) e = (w == kSentF) ? 0.f : e;
-            acc[0] += e;
+            const RowPot rp = rowpot[r - r0];
+            const int w = (int)gload(I.W + (int64_t)r * I.pitch + c0);
+            float e = tab_at(tab, tab_off(p4, w, A, rp.b));
+            if (SENT) e = (w == SK_SENTINEL) ? 0.f : e;
+            acc[0] = fmaf(e, rp.r, acc[0]);
         }
     }
 }
@@ -407,10 +449,13 @@ __global__ __launch_bounds__(kColWaves * kWave) void k_col_sweep(const Inst *__r
                                                                    const ColUnit *__restrict__ units,
                                                                    int nunits) {
     __shared__ float red[kColWaves][kColTile8];
-    __shared__ float2 rowpot[kMaxSegRows];
+    __shared__ RowPot rowpot[kMaxSegRows];
+    __shared__ float tab[kTabN];
+    __shared__ float wmax[kColWaves];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     int u0, u1;
     unit_range(nunits, u0, u1);
+    fill_exp_table(tab);
     for (int u = u0; u < u1; ++u) {
         const ColUnit un = units[u];
         const Inst &I = insts[un.inst];
@@ -423,19 +468,36 @@ __global__ __launch_bounds__(kColWaves * kWave) void k_col_sweep(const Inst *__r
         const int ncols = min(tc, n - ctile0);
         const int r0 = un.seg * I.seg_rows, r1 = min(n, r0 + I.seg_rows);
         __syncthreads();
-        for (int r = r0 + (int)threadIdx.x; r < r1; r += blockDim.x)
-            rowpot[r - r0] = make_float2((float)I.F[npar][r], I.phi[npar][r] * kLog2e);
+        float rm = 0.f;
+        for (int r = r0 + (int)threadIdx.x; r < r1; r += blockDim.x) {
+            RowPot k;
+            k.b = 4 * (I.F[npar][r] - kTabLo);
+            k.r = ex2(I.phi[npar][r] * kLog2e);
+            rowpot[r - r0] = k;
+            if (un.tile == 0) rm = fmaxf(rm, I.rres[r]);
+        }
+        if (un.tile == 0) {
+            // residual slot of this row segment (read by the finalise kernel)
+            rm = wave_max(rm);
+            if (lane == 0) wmax[wave] = rm;
+        }
         __syncthreads();
+        if (un.tile == 0 && threadIdx.x == 0) {
+            float m = wmax[0];
+#pragma unroll
+            for (int w2 = 1; w2 < kColWaves; ++w2) m = fmaxf(m, wmax[w2]);
+            I.res_slots[un.seg] = m;
+        }
         float acc[8];
         const bool sent = ctl->sent != 0u;
         if (I.vec8) {
-            if (sent) col_partial<true, true>(I, un.tile, r0, r1, wave, lane, rowpot, acc);
-            else col_partial<false, true>(I, un.tile, r0, r1, wave, lane, rowpot, acc);
+            if (sent) col_partial<true, true>(I, un.tile, r0, r1, wave, lane, rowpot, tab, acc);
+            else col_partial<false, true>(I, un.tile, r0, r1, wave, lane, rowpot, tab, acc);
 #pragma unroll
             for (int c = 0; c < 8; ++c) red[wave][lane * 8 + c] = acc[c];
         } else {
-            if (sent) col_partial<true, false>(I, un.tile, r0, r1, wave, lane, rowpot, acc);
-            else col_partial<false, false>(I, un.tile, r0, r1, wave, lane, rowpot, acc);
+            if (sent) col_partial<true, false>(I, un.tile, r0, r1, wave, lane, rowpot, tab, acc);
+            else col_partial<false, false>(I, un.tile, r0, r1, wave, lane, rowpot, tab, acc);
             red[wave][lane] = acc[0];
         }
         __syncthreads();
@@ -477,9 +539,13 @@ __global__ __launch_bounds__(256) void k_col_finalize(const Inst *__restrict__ i
         const bool kpath = (mode & kFinStoredK) != 0;   // slots written by the stored-K kernels
         const bool onepass = (mode & kFinOnePass) != 0; // slots written by the single-pass kernel
         if (kpath && ctl->need_absorb) continue;
-        // residual (and drift) of this iteration's row step
+        // residual (and drift) of this iteration's row step: one slot per
+        // workgroup of the single pass, per row unit of the stored-K row
+        // sweep, per row segment of the log-domain sweeps
+        const int nres = onepass ? I.fused_grid
+                                 : (kpath ? (I.n + kRowWaves - 1) / kRowWaves : I.nseg);
         float m = 0.f, d = 0.f;
-        for (int q = t; q < I.nresslots; q += 256) {
+        for (int q = t; q < nres; q += 256) {
             m = fmaxf(m, I.res_slots[q]);
             if (kpath) d = fmaxf(d, I.drift_slots[q]);
         }
@@ -588,8 +654,9 @@ __device__ void end_stage(const Inst &I, Ctl *ctl, int par) {
 }
 
 __global__ __launch_bounds__(256) void k_iter_end(const Inst *__restrict__ insts) {
+    __shared__ int redi[256];
     __shared__ float red[256];
-    __shared__ float s_m;
+    __shared__ float tab[kTabN];
     const Inst &I = insts[blockIdx.x];
     Ctl *ctl = I.ctl;
     if (ctl->state != ST_RUNNING) return;
@@ -597,56 +664,55 @@ __global__ __launch_bounds__(256) void k_iter_end(const Inst *__restrict__ insts
     const bool conv = stage_converged(I, ctl);
     const int iter = ctl->iter;
     const int npar = (iter + 1) & 1;
-    const float pf = (float)ctl->p;
-    if (!conv) {
-        // exact two-pass recompute of columns whose sum left the safe range
-        const unsigned nres = ctl->rescue_cnt;
-        for (unsigned q = 0; q < nres; ++q) {
-            const int j = (int)I.rescue[q];
-            const float Gf = (float)I.G[j];
-            float m = -INFINITY;
-            for (int r = threadIdx.x; r < n; r += blockDim.x) {
-                const int16_t w = I.W[(int64_t)r * I.pitch + j];
-                if (w == SK_SENTINEL) continue;
-                const float Iv = fmaf((float)w, pf, Gf) + (float)I.F[npar][r];
-                m = fmaxf(m, fmaf(Iv, kLog2e, I.phi[npar][r] * kLog2e));
-            }
-            red[threadIdx.x] = m;
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                float mm = -INFINITY;
-                for (int t = 0; t < (int)blockDim.x; ++t) mm = fmaxf(mm, red[t]);
-                s_m = mm;
-            }
-            __syncthreads();
-            m = s_m;
-            float sacc = 0.f;
-            if (m != -INFINITY) {
-                for (int r = threadIdx.x; r < n; r += blockDim.x) {
-                    const int16_t w = I.W[(int64_t)r * I.pitch + j];
-                    if (w == SK_SENTINEL) continue;
-                    const float Iv = fmaf((float)w, pf, Gf) + (float)I.F[npar][r];
-                    sacc += ex2(fmaf(Iv, kLog2e, I.phi[npar][r] * kLog2e) - m);
-                }
-            }
-            __syncthreads();
-            red[threadIdx.x] = sacc;
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                if (m == -INFINITY) {
-                    atomicOr(&ctl->err, ERR_EMPTY_COL);
-                } else {
-                    float S = 0.f;
-                    for (int t = 0; t < (int)blockDim.x; ++t) S += red[t];
-                    // log v_j <- G_j - log T_j with log2 T_j = m + log2 S
-                    const double gn = (double)I.G[j] - (double)((m + lg2(S)) * kLn2);
-                    const double k = rint(gn);
-                    I.G[j] = (int32_t)k;
-                    I.gam[j] = (float)(gn - k);
-                }
-            }
+    const int p4 = 4 * ctl->p;
+    const unsigned nres = conv ? 0u : ctl->rescue_cnt;
+    if (nres > 0u) fill_exp_table(tab);
+    // exact max-shifted recompute (Section 4.1.2) of the columns whose sum
+    // left the safe range: M = max_i (p w_ij + F_i + G_j), then
+    // T_j = e^M sum_i exp(p w_ij + F_i + G_j - M) exp(phi_i)
+    for (unsigned q = 0; q < nres; ++q) {
+        const int j = (int)I.rescue[q];
+        const int A = 4 * I.G[j];
+        int m = INT_MIN;
+        for (int r = threadIdx.x; r < n; r += blockDim.x) {
+            const int w = (int)I.W[(int64_t)r * I.pitch + j];
+            if (w == SK_SENTINEL) continue;
+            m = max(m, __mul24(p4, w) + A + 4 * I.F[npar][r]);
+        }
+        __syncthreads();
+        redi[threadIdx.x] = m;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if ((int)threadIdx.x < o) redi[threadIdx.x] = max(redi[threadIdx.x], redi[threadIdx.x + o]);
             __syncthreads();
         }
+        const int m4 = redi[0];
+        const int M = m4 >> 2;  // exact: m4 is a multiple of 4 (unused when m4 == INT_MIN)
+        float sacc = 0.f;
+        if (m4 != INT_MIN) {
+            for (int r = threadIdx.x; r < n; r += blockDim.x) {
+                const int w = (int)I.W[(int64_t)r * I.pitch + j];
+                if (w == SK_SENTINEL) continue;
+                const float e = tab_at(tab, tab_off(p4, w, A, 4 * (I.F[npar][r] - M - kTabLo)));
+                sacc = fmaf(e, ex2(I.phi[npar][r] * kLog2e), sacc);
+            }
+        }
+        red[threadIdx.x] = sacc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            if (m4 == INT_MIN) {
+                atomicOr(&ctl->err, ERR_EMPTY_COL);
+            } else {
+                float S = 0.f;
+                for (int t = 0; t < (int)blockDim.x; ++t) S += red[t];
+                // log v_j <- G_j - M - log S
+                const float gn = -lg2(S) * kLn2;
+                const float k = rintf(gn);
+                I.G[j] = I.G[j] - M + (int)k;
+                I.gam[j] = gn - k;
+            }
+        }
+        __syncthreads();
     }
     __syncthreads();
     if (threadIdx.x == 0) {

@@ -53,6 +53,7 @@ size_t instance_bytes(int32_t n, int vec8, int storage, int fused) {
     b += align_up(sizeof(uint32_t) * n, 256);
     b += align_up(sizeof(Ctl), 256);
     b += align_up(sizeof(float) * std::max((n + kRowWaves - 1) / kRowWaves, kFusedSlots), 256) * 2;
+    b += align_up(sizeof(float) * n, 256);  // rres
     if (storage == SK_K_BF16 || storage == SK_K_F32) {
         const size_t es = storage == SK_K_BF16 ? 2 : 4;
         const size_t kp = (size_t)(n + 7) / 8 * 8;
@@ -332,10 +333,10 @@ bool sk::carve_instance(Bump &bump, const int16_t *W, int64_t pitch, int32_t nn,
     I.ctl = bump.take<Ctl>(1);
     const int nrows_units = (nn + kRowWaves - 1) / kRowWaves;
     I.ncolslots = I.fused ? I.fused_grid : t.nseg;
-    I.nresslots = I.fused ? I.fused_grid : nrows_units;
     I.res_slots = bump.take<float>(std::max(nrows_units, kFusedSlots));
     I.drift_slots = bump.take<float>(std::max(nrows_units, kFusedSlots));
-    if (!I.res_slots || !I.drift_slots) return false;
+    I.rres = bump.take<float>(nn);
+    if (!I.res_slots || !I.drift_slots || !I.rres) return false;
     if (!I.F[0] || !I.F[1] || !I.phi[0] || !I.phi[1] || !I.G || !I.gam || !I.colpart ||
         !I.rescue || !I.ctl)
         return false;

@@ -1,10 +1,13 @@
 // Served path: continuous batching of assignment solves on one GPU.
 //
-// sk_submit copies a request's W into pinned staging and queues it. A serving
+// sk_submit copies a request's W to the device at once when its footprint
+// (W plus the instance state) fits in the free part of the context arena and
+// no earlier request is waiting for space; otherwise into pinned host staging.
+// Copies run on a stream of their own, so they overlap the sweeps. A serving
 // thread repeats a tick:
-//   1. admit queued requests (FIFO) while their device footprint (W plus the
-//      instance state) fits in the free part of the context arena;
-//   2. copy the admitted W to the device and cold-start them;
+//   1. admit queued requests (FIFO) while their footprint fits; start the
+//      host-to-device copy of staged ones, and take in those whose copy is
+//      complete; cold-start the new instances;
 //   3. run a block of Sinkhorn iterations over every admitted instance at
 //      once (one row-sweep launch and one column-sweep launch per iteration
 //      cover all of them; each instance follows its own p ladder, tolerance
@@ -41,6 +44,8 @@ struct Request {
     bool in_ring = false;
     size_t off = 0, len = 0;     // device region in the arena
     Inst inst{};
+    bool loaded = false;         // W is in its device region
+    hipEvent_t ev = nullptr;     // completion of the host-to-device copy
     int phase = 0;               // 0 queued, 1 active, 2 solving, 3 done
     sk_status status = SK_OK;
     std::vector<int32_t> perm;
@@ -61,6 +66,8 @@ struct Server {
     bool stop = false;
     uint64_t next_id = 1;
     std::deque<Request *> queue;
+    std::deque<Request *> loading;  // admitted, copy in flight (serving thread only)
+    int staged_waiting = 0;         // queued requests whose W is still on the host
     std::vector<Request *> active;
     std::unordered_map<uint64_t, Request *> reqs;
     std::deque<Request *> solve_q;
@@ -68,6 +75,7 @@ struct Server {
     size_t tables_len = 0;
     Batch B;
     std::vector<RowUnit> init_units;
+    std::vector<int> fresh_idx;  // host source of d_fresh (kept until the tick syncs)
     RowUnit *d_init_units = nullptr;
     std::string error;
     int iters_per_tick = 16;
@@ -75,6 +83,7 @@ struct Server {
     size_t ring_bytes = 0;
     RangeAlloc ring_alloc;
     int *d_fresh = nullptr;      // indices of admitted instances (device)
+    hipStream_t copy_stream = nullptr;
 };
 
 static const size_t kRingBytes = size_t(512) << 20;
@@ -93,6 +102,20 @@ static const size_t kTablesBytes = size_t(64) << 20;
 
 static size_t footprint(int32_t n) {
     return align_up((size_t)n * n * 2, 256) + instance_bytes(n, (n % 8) == 0, SK_W_I16) + 4096;
+}
+
+// Carves the request's device region at offset `off` (W first, then the
+// instance state).
+static void place(Server *S, Request *r, size_t off) {
+    r->off = off;
+    Bump bump{S->ctx->arena + off, r->len};
+    int16_t *dW = bump.take<int16_t>((size_t)r->n * r->n);
+    carve_instance(bump, dW, r->n, r->n, &r->prm, r->inst);
+}
+
+static void drop_event(Request *r) {
+    if (r->ev) (void)hipEventDestroy(r->ev);
+    r->ev = nullptr;
 }
 
 static void solver_loop(Server *S) {
@@ -254,40 +277,68 @@ static void serve_loop(Server *S) {
     (void)hipSetDevice(ctx->device);
     bool dirty = false;
     for (;;) {
-        std::vector<Request *> fresh;
+        std::vector<Request *> fresh, to_copy;
         {
             std::unique_lock<std::mutex> g(S->mu);
             if (S->stop) break;
-            while (!S->queue.empty() && S->active.size() + fresh.size() < (size_t)kMaxBatch) {
+            while (!S->queue.empty() &&
+                   S->active.size() + S->loading.size() + fresh.size() + to_copy.size() <
+                       (size_t)kMaxBatch) {
                 Request *r = S->queue.front();
-                size_t off;
-                if (!S->ralloc.alloc(r->len, off)) break;
-                r->off = off;
-                Bump bump{ctx->arena + off, r->len};
-                int16_t *dW = bump.take<int16_t>((size_t)r->n * r->n);
-                carve_instance(bump, dW, r->n, r->n, &r->prm, r->inst);
+                if (!r->loaded) {
+                    size_t off;
+                    if (!S->ralloc.alloc(r->len, off)) break;
+                    place(S, r, off);
+                    --S->staged_waiting;
+                    to_copy.push_back(r);
+                } else {
+                    fresh.push_back(r);
+                }
                 r->phase = 1;
                 S->queue.pop_front();
-                fresh.push_back(r);
-            }
-            if (S->active.empty() && fresh.empty()) {
-                S->cv.wait_for(g, std::chrono::milliseconds(1));
-                continue;
             }
         }
-        sk_status st = SK_OK;
         hipError_t e = hipSuccess;
-        if (!fresh.empty()) {
-            for (Request *r : fresh)
-                if (e == hipSuccess)
-                    e = hipMemcpyAsync((void *)r->inst.W, r->staging, (size_t)r->n * r->n * 2,
-                                       hipMemcpyHostToDevice, ctx->stream);
+        for (Request *r : to_copy) {
+            if (e == hipSuccess)
+                e = hipMemcpyAsync((void *)r->inst.W, r->staging, (size_t)r->n * r->n * 2,
+                                   hipMemcpyHostToDevice, S->copy_stream);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&r->ev, hipEventDisableTiming);
+            if (e == hipSuccess) e = hipEventRecord(r->ev, S->copy_stream);
+            S->loading.push_back(r);
+        }
+        // take in the requests whose copy has completed, in admission order
+        while (e == hipSuccess && !S->loading.empty()) {
+            Request *r = S->loading.front();
+            const hipError_t q = hipEventQuery(r->ev);
+            if (q == hipErrorNotReady) break;
+            e = q;
+            drop_event(r);
+            {
+                std::lock_guard<std::mutex> g(S->mu);
+                release_staging(S, r);
+            }
+            fresh.push_back(r);
+            S->loading.pop_front();
+        }
+        if (e == hipSuccess && S->active.empty() && fresh.empty()) {
+            if (!S->loading.empty()) {
+                e = hipEventSynchronize(S->loading.front()->ev);
+            } else {
+                std::unique_lock<std::mutex> g(S->mu);
+                if (S->queue.empty() && !S->stop) S->cv.wait_for(g, std::chrono::milliseconds(1));
+            }
+            if (e == hipSuccess) continue;
+        }
+        sk_status st = SK_OK;
+        if (e == hipSuccess && !fresh.empty()) {
             const int base = (int)S->active.size();
             for (Request *r : fresh) S->active.push_back(r);
             st = rebuild(S);
             // cold start of the new instances only
             S->init_units.clear();
-            std::vector<int> idx;
+            std::vector<int> &idx = S->fresh_idx;
+            idx.clear();
             for (size_t q = 0; q < fresh.size(); ++q) {
                 const int k = base + (int)q;
                 idx.push_back(k);
@@ -309,12 +360,10 @@ static void serve_loop(Server *S) {
                     e = launch_init(S->B.d_insts, S->d_init_units, (int)chunk,
                                     (int)std::min<size_t>(chunk, (size_t)ctx->num_cus * 2), 1,
                                     ctx->stream);
-                if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+                // the unit table is reused by the next chunk's copy, which the
+                // stream orders after this launch; the host vector stays
+                // untouched until the tick's read-back synchronises
                 done += chunk;
-            }
-            {
-                std::lock_guard<std::mutex> g(S->mu);
-                for (Request *r : fresh) release_staging(S, r);
             }
             dirty = false;
         } else if (dirty) {
@@ -327,11 +376,19 @@ static void serve_loop(Server *S) {
         if (st != SK_OK || e != hipSuccess) {
             std::lock_guard<std::mutex> g(S->mu);
             S->error = e != hipSuccess ? hipGetErrorString(e) : ctx->err;
-            for (Request *r : S->active) {
+            for (auto *list : {&S->active, &fresh}) {
+                for (Request *r : *list) {
+                    r->status = SK_EDEVICE;
+                    r->phase = 3;
+                }
+                list->clear();
+            }
+            for (Request *r : S->loading) {
+                drop_event(r);
                 r->status = SK_EDEVICE;
                 r->phase = 3;
             }
-            S->active.clear();
+            S->loading.clear();
             break;
         }
         // retire finished instances
@@ -376,6 +433,12 @@ static Server *ensure_server(sk_ctx *ctx) {
     } else {
         S->ring = nullptr;
     }
+    if (hipSetDevice(ctx->device) != hipSuccess ||
+        hipStreamCreateWithFlags(&S->copy_stream, hipStreamNonBlocking) != hipSuccess) {
+        if (S->ring) (void)hipHostFree(S->ring);
+        delete S;
+        return nullptr;
+    }
     ctx->server = S;
     S->th = std::thread(serve_loop, S);
     for (int k = 0; k < 4; ++k) S->solvers.emplace_back(solver_loop, S);
@@ -394,10 +457,14 @@ void serve_stop(sk_ctx *ctx) {
     if (S->th.joinable()) S->th.join();
     for (auto &t : S->solvers)
         if (t.joinable()) t.join();
+    for (Request *r : S->loading) drop_event(r);
     for (auto &kv : S->reqs) {
         release_staging(S, kv.second);
+        drop_event(kv.second);
         delete kv.second;
     }
+    if (S->copy_stream) (void)hipStreamSynchronize(S->copy_stream);
+    if (S->copy_stream) (void)hipStreamDestroy(S->copy_stream);
     if (S->ring) (void)hipHostFree(S->ring);
     delete S;
     ctx->server = nullptr;
@@ -420,6 +487,7 @@ extern "C" sk_status sk_submit(sk_ctx *ctx, const int16_t *W_host, int32_t n, co
     if (!(params->threshold > 0.0)) return fail(ctx, SK_EINVAL, "threshold must be > 0");
     std::lock_guard<std::mutex> call(ctx->mu);
     Server *S = ensure_server(ctx);
+    if (!S) return fail(ctx, SK_EDEVICE, "could not start the serving thread");
     const size_t len = footprint(n);
     if (len + S->tables_len > ctx->arena_bytes)
         return fail(ctx, SK_ENOMEM, "n = %d can never fit in the arena", n);
@@ -428,33 +496,58 @@ extern "C" sk_status sk_submit(sk_ctx *ctx, const int16_t *W_host, int32_t n, co
     r->prm = *params;
     r->len = len;
     r->t_submit = std::chrono::steady_clock::now();
+    const size_t wbytes = (size_t)n * n * 2;
+    bool direct = false;
     {
         std::lock_guard<std::mutex> g(S->mu);
+        if (!S->error.empty()) {
+            delete r;
+            return fail(ctx, SK_EDEVICE, "serving thread stopped: %s", S->error.c_str());
+        }
+        if (S->queue.size() >= (size_t)kMaxBatch) {
+            delete r;
+            return SK_EAGAIN;
+        }
+        // straight to the device when it fits and nobody earlier is waiting
         size_t off;
-        if (S->ring && S->ring_alloc.alloc((size_t)n * n * 2, off)) {
+        if (S->staged_waiting == 0 && S->ralloc.alloc(len, off)) {
+            place(S, r, off);
+            direct = true;
+        } else if (S->ring && S->ring_alloc.alloc(wbytes, off)) {
             r->staging = (int16_t *)(S->ring + off);
             r->ring_off = off;
             r->in_ring = true;
         }
     }
-    if (!r->staging) r->staging = (int16_t *)malloc((size_t)n * n * 2);
-    if (!r->staging) {
-        delete r;
-        return fail(ctx, SK_ENOMEM, "host staging allocation failed");
+    if (direct) {
+        hipError_t e = hipSetDevice(ctx->device);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync((void *)r->inst.W, W_host, wbytes, hipMemcpyHostToDevice,
+                               S->copy_stream);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&r->ev, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(r->ev, S->copy_stream);
+        if (e == hipSuccess) e = hipEventSynchronize(r->ev);
+        drop_event(r);
+        if (e != hipSuccess) {
+            {
+                std::lock_guard<std::mutex> g(S->mu);
+                S->ralloc.release(r->off, r->len);
+            }
+            delete r;
+            return fail(ctx, SK_EDEVICE, "copy of W: %s", hipGetErrorString(e));
+        }
+        r->loaded = true;
+    } else {
+        if (!r->staging) r->staging = (int16_t *)malloc(wbytes);
+        if (!r->staging) {
+            delete r;
+            return fail(ctx, SK_ENOMEM, "host staging allocation failed");
+        }
+        memcpy(r->staging, W_host, wbytes);
     }
-    memcpy(r->staging, W_host, (size_t)n * n * 2);
     {
         std::lock_guard<std::mutex> g(S->mu);
-        if (!S->error.empty()) {
-            release_staging(S, r);
-            delete r;
-            return fail(ctx, SK_EDEVICE, "serving thread stopped: %s", S->error.c_str());
-        }
-        if (S->queue.size() >= (size_t)kMaxBatch) {
-            release_staging(S, r);
-            delete r;
-            return SK_EAGAIN;
-        }
+        if (!r->loaded) ++S->staged_waiting;
         r->id = S->next_id++;
         S->queue.push_back(r);
         S->reqs[r->id] = r;
