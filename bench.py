@@ -27,12 +27,12 @@ batched: 512 independent instances, n log-uniform on [32, 1024], weights
 uniform 0..1000; sk_scale_batch (one launch per sweep across all instances)
 against 512 sequential sk_scale calls with the same parameters.
 
-served: Poisson arrivals of planted instances with n log-uniform on
-[64, 8192], tolerance 1e-5; requests through sk_submit/sk_poll (continuous
+served: 1000 Poisson arrivals of planted instances with n log-uniform on
+[64, 8192], tolerance 1e-5, at offered loads of 0.5, 0.9 and 1.5 times the
+FIFO loop's measured capacity; requests through sk_submit/sk_poll (continuous
 batching) against a plain FIFO loop that solves one request at a time
-(scale, prune, exact solve) on the same GPU; solves/s and p50/p99 latency
-(completion minus arrival) for both, arrival rate set from the FIFO loop's
-measured capacity.
+(host-to-device copy, scale, prune, exact solve) on the same GPU; solves/s
+and p50/p99 latency (completion minus arrival) for both at each load.
 """
 from __future__ import annotations
 
@@ -71,9 +71,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
-    ap.add_argument("--served-requests", type=int, default=160)
-    ap.add_argument("--served-load", type=float, default=1.5,
-                    help="arrival rate as a multiple of the FIFO loop's capacity")
+    ap.add_argument("--served-requests", type=int, default=1000)
+    ap.add_argument("--served-loads", default="0.5,0.9,1.5",
+                    help="arrival rates as multiples of the FIFO loop's measured capacity")
     ap.add_argument("--fused", action="store_true",
                     help="single-pass iteration (one matrix read per iteration)")
     ap.add_argument("--trace-summary", metavar="CSV",
@@ -240,14 +240,14 @@ def batched_leg(sk, torch, seed=1):
                         for k, v in prof.items()}}
 
 
-def served_leg(sk, torch, n_requests, load, seed=2):
+def served_leg(sk, torch, n_requests, loads, seed=2):
     """Poisson arrivals; continuous batching vs a FIFO one-at-a-time loop."""
     import skgen
     # a pool of planted instances with log-uniform sizes; requests draw from it
     pool_n = skgen.sizes_loguniform(32, 64, 8192, seed)
     pool = [skgen.planted(int(n), seed * 100003 + k) for k, n in enumerate(pool_n)]
     pick = skgen.bounded(skgen.stream(seed, 99, n_requests), len(pool)).astype(np.int64)
-    reqs = [pool[int(k)] for k in pick]
+    reqs = [pool[int(k)][0] for k in pick]
     prm = sk.make_params([1, 2, 4, 8, 16, 32], tol=1e-5, max_iters=2000, check_every=32,
                          threshold=1e-4)
     fifo = sk.Context(0)
@@ -256,68 +256,73 @@ def served_leg(sk, torch, n_requests, load, seed=2):
         # a request arrives as host memory, like sk_submit's input
         return fifo.solve(torch.from_numpy(W).cuda(), prm)
 
-    for W, _ in pool[:4]:
-        fifo_one(W)  # warm-up
-    # FIFO capacity: back-to-back service time
+    for W, _ in pool[:4] + [max(pool, key=lambda e: e[0].shape[0])]:
+        fifo_one(W)  # warm-up (the largest instance sizes the arena once)
+    # FIFO capacity: back-to-back service time over the first 64 requests
+    m = min(64, n_requests)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in pick[: min(48, n_requests)]:
-        fifo_one(pool[int(k)][0])
+    for W in reqs[:m]:
+        fifo_one(W)
     torch.cuda.synchronize()
-    mu = min(48, n_requests) / (time.perf_counter() - t0)
-    lam = load * mu
-    arrivals = skgen.poisson_arrivals(lam, n_requests, seed)
-    # FIFO loop on the arrival trace (live)
-    lat_f = []
-    ok_f = 0
-    t_start = time.perf_counter()
-    for k, a in zip(pick, arrivals):
-        now = time.perf_counter() - t_start
-        if now < a:
-            time.sleep(a - now)
-        W = pool[int(k)][0]
-        out = fifo_one(W)
-        ok_f += out["weight"] == 1050 * W.shape[0]
-        lat_f.append(time.perf_counter() - t_start - a)
-    span_f = time.perf_counter() - t_start
-    fifo.close()
-    # served loop on the same trace
+    mu = m / (time.perf_counter() - t0)
+    q = lambda v, pc: round(float(np.percentile(np.asarray(v), pc)) * 1e3, 2)
+
+    def run_fifo(arrivals):
+        lat, ok = [], 0
+        t_start = time.perf_counter()
+        for W, a in zip(reqs, arrivals):
+            now = time.perf_counter() - t_start
+            if now < a:
+                time.sleep(a - now)
+            out = fifo_one(W)
+            ok += out["weight"] == 1050 * W.shape[0]
+            lat.append(time.perf_counter() - t_start - a)
+        return time.perf_counter() - t_start, lat, ok
+
     srv = sk.Context(0, arena_bytes=4 << 30)
-    # warm-up request
-    t = srv.submit(pool[0][0], prm)
+    t = srv.submit(pool[0][0], prm)  # warm-up request
     while srv.poll(t, pool[0][0].shape[0]) is None:
         time.sleep(0.0005)
-    pending = {}
-    lat_s = [None] * n_requests
-    ok_s = 0
-    t_start = time.perf_counter()
-    nxt = 0
-    while nxt < n_requests or pending:
-        now = time.perf_counter() - t_start
-        while nxt < n_requests and arrivals[nxt] <= now:
-            W, _ = reqs[nxt]
-            pending[srv.submit(W, prm)] = (nxt, W.shape[0])
-            nxt += 1
-        for tk in list(pending):
-            idx, n = pending[tk]
-            r = srv.poll(tk, n)
-            if r is not None:
-                lat_s[idx] = time.perf_counter() - t_start - arrivals[idx]
-                ok_s += r[2] == 1050 * n
-                del pending[tk]
-        time.sleep(0.0002)
-    span_s = time.perf_counter() - t_start
+
+    def run_served(arrivals):
+        pending = {}
+        lat = [None] * n_requests
+        ok = 0
+        t_start = time.perf_counter()
+        nxt = 0
+        while nxt < n_requests or pending:
+            now = time.perf_counter() - t_start
+            while nxt < n_requests and arrivals[nxt] <= now:
+                W = reqs[nxt]
+                pending[srv.submit(W, prm)] = (nxt, W.shape[0])
+                nxt += 1
+            for tk in list(pending):
+                idx, n = pending[tk]
+                r = srv.poll(tk, n)
+                if r is not None:
+                    lat[idx] = time.perf_counter() - t_start - arrivals[idx]
+                    ok += r[2] == 1050 * n
+                    del pending[tk]
+            time.sleep(0.0002)
+        return time.perf_counter() - t_start, lat, ok
+
+    per_load = []
+    for load in loads:
+        arrivals = skgen.poisson_arrivals(load * mu, n_requests, seed)
+        span_f, lat_f, ok_f = run_fifo(arrivals)
+        span_s, lat_s, ok_s = run_served(arrivals)
+        per_load.append({
+            "load": load, "arrival_rate_per_s": round(load * mu, 2),
+            "served": {"solves_per_s": round(n_requests / span_s, 2), "p50_ms": q(lat_s, 50),
+                       "p99_ms": q(lat_s, 99), "optimal": int(ok_s)},
+            "fifo": {"solves_per_s": round(n_requests / span_f, 2), "p50_ms": q(lat_f, 50),
+                     "p99_ms": q(lat_f, 99), "optimal": int(ok_f)},
+            "speedup_solves_per_s": round(span_f / span_s, 2)})
+    fifo.close()
     srv.close()
-    q = lambda v, p: float(np.percentile(np.asarray(v), p))
     return {"requests": n_requests, "n_range": [64, 8192], "pool_instances": len(pool),
-            "fifo_capacity_solves_per_s": round(mu, 2), "arrival_rate_per_s": round(lam, 2),
-            "served": {"solves_per_s": round(n_requests / span_s, 2),
-                       "p50_ms": round(q(lat_s, 50) * 1e3, 2), "p99_ms": round(q(lat_s, 99) * 1e3, 2),
-                       "optimal": ok_s},
-            "fifo": {"solves_per_s": round(n_requests / span_f, 2),
-                     "p50_ms": round(q(lat_f, 50) * 1e3, 2), "p99_ms": round(q(lat_f, 99) * 1e3, 2),
-                     "optimal": ok_f},
-            "speedup_solves_per_s": round(span_f / span_s, 2)}
+            "fifo_capacity_solves_per_s": round(mu, 2), "loads": per_load}
 
 
 def cpu_baseline(W, p, seconds):
@@ -445,7 +450,8 @@ def main():
     if not args.no_batched:
         out["batched"] = batched_leg(sk, torch)
     if not args.no_served:
-        out["served"] = served_leg(sk, torch, args.served_requests, args.served_load)
+        out["served"] = served_leg(sk, torch, args.served_requests,
+                                   [float(x) for x in args.served_loads.split(",")])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W, ladder[-1], args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -73,7 +73,8 @@ typedef enum {
  *                  exact iteration, so this only bounds wasted launches.
  *   threshold    : t of eq. matrixred, used by sk_prune (0 < t <= 1).
  *   storage      : see sk_storage.
- *   opt_ratio    : required gamma of eq. optratio (> 1), used by sk_submit.
+ *   opt_ratio    : required gamma of eq. optratio; >= 1 makes sk_solve stop at
+ *                  the first p that reaches it, < 1 evaluates the last p only.
  *   warm_start   : 0 = cold start (v = 1 for the first p); 1 = start from the
  *                  potentials passed in (their p is p_ladder[0]).
  *   fused        : 0 = a row-sweep launch and a column-sweep launch per
@@ -113,6 +114,12 @@ typedef struct {
     int64_t nnz_kept;          /* set by sk_prune */
     int32_t absorbs;           /* K recomputations (stored-K storages) */
     double seconds;
+    /* set by sk_solve (NaN / 0 elsewhere): */
+    double log_gamma;          /* log of the ratio gamma of eq. optratio: ub - w(B) */
+    double threshold_used;     /* threshold t of the returned reduced matrix B */
+    int32_t stages_evaluated;  /* stages whose B and gamma were formed */
+    int32_t optimal_proved;    /* 1 if ub - w(B) < 1: with integer weights no
+                                  permutation of A weighs more than w(B) */
 } sk_report;
 
 /* Potentials (scalings) of one instance, in device memory, 16*n bytes laid
@@ -183,6 +190,40 @@ sk_status sk_prune(sk_ctx *ctx, const int16_t *W, int32_t n, const void *potenti
  *   weight : host; sum_i w[i, perm(i)].
  * Returns SK_EINFEASIBLE if B has no perfect matching. Thread-safe. */
 sk_status sk_solve_reduced(const sk_csr *csr, int32_t *perm, int64_t *weight);
+
+/* The path of Algorithm alg:alg1 (Section 4.2) for one instance, natively:
+ * the continuation over params->p_ladder (as sk_scale), and at the end of a
+ * stage the FP64 certificate ub (Proposition prop:aoc), the reduced matrix B
+ * of eq. matrixred at t = params->threshold, an exact optimal assignment of B
+ * (as sk_solve_reduced) and log gamma = ub - w(B) (eq. optratio).
+ *   params->opt_ratio >= 1: every stage is evaluated; the call stops at the
+ *     first stage with gamma <= opt_ratio (the loop condition of the
+ *     algorithm, read as "raise p while gamma exceeds the ratio").
+ *   params->opt_ratio < 1: only the last stage is evaluated.
+ * When B has no perfect matching at the last stage, t is lowered tenfold, at
+ * most three times.
+ *   W          : DEVICE, n*n int16 row-major, caller-owned, read-only.
+ *   potentials : DEVICE, sk_potentials_bytes(n), caller-owned; read first
+ *                when params->warm_start; receives the scalings of the
+ *                returned stage.
+ *   perm       : HOST int32[n]; perm[i] = column assigned to row i.
+ *   weight     : HOST; w(B) = sum_i W[i][perm[i]], an optimal weight of B.
+ *   report     : HOST, may be NULL; work counters cover all stages run,
+ *                the other fields the returned stage.
+ * Any storage; the stored-K storages evaluate a stage after folding their
+ * scalings into the potentials. Needs an arena of
+ * sk_solve_arena_bytes(n, storage, kept), kept >= the entries B keeps
+ * (else SK_ENOMEM). Returns SK_OK when the
+ * ratio was reached (or, with opt_ratio < 1, B had a perfect matching);
+ * SK_ENOCONV when the ladder ended first (the stage with the smallest gamma
+ * is returned); SK_EINFEASIBLE when no B had a perfect matching;
+ * SK_ENOSUPPORT for an empty row or column of A. Blocks. */
+sk_status sk_solve(sk_ctx *ctx, const int16_t *W, int32_t n, const sk_params *params,
+                   void *potentials, int32_t *perm, int64_t *weight, sk_report *report);
+
+/* Device arena bytes sk_solve needs for this storage when B keeps at most
+ * max_kept entries. */
+size_t sk_solve_arena_bytes(int32_t n, int32_t storage, int64_t max_kept);
 
 /* Served path (continuous batching). sk_submit copies W (HOST, n*n int16)
  * into library-owned staging and queues the request; the context's serving

@@ -268,3 +268,57 @@ def solve(W, ladder, eps, max_iters, t):
     except Infeasible:
         perm, weight, log_gamma = None, None, None
     return Solution(p, ubar, vbar, iters, res, keep, int(keep.sum()), ub, perm, weight, log_gamma)
+
+
+def adaptive(W, ladder, eps, max_iters, t, opt_ratio):
+    """Algorithm alg:alg1 (Section 4.2) over a given ladder of p.
+
+    Per p, in order: Sinkhorn scaling of A^(p) carried over from the previous
+    p in the coordinates p^-1 log u, p^-1 log v (Section 4.1.2), the
+    certificate (Proposition prop:aoc), the reduced matrix (eq. matrixred),
+    an optimal assignment of it and log gamma = ub - w(B) (eq. optratio).
+    The loop is read as "raise p while gamma exceeds opt_ratio": it stops at
+    the first p with gamma <= opt_ratio; with opt_ratio < 1 only the last p is
+    evaluated. gamma is undefined when the reduced matrix has no perfect
+    matching; at the last p the threshold is then lowered tenfold, at most
+    three times. Returns (Solution of the returned p, status) with status
+    "ok", "ratio" (ladder ended first: the p with the smallest gamma is
+    returned) or "infeasible"; Solution.extra holds t and the number of
+    evaluated p."""
+    Bw = log_weights(W)
+    n = W.shape[0]
+    ubar, vbar = np.zeros(n), np.zeros(n)
+    evaluate_all = opt_ratio >= 1.0
+    best, evaluated, iters_all, res_all = None, 0, [], []
+    for k, p in enumerate(ladder):
+        ubar, vbar, it, res = sinkhorn(Bw, p, eps, max_iters, ubar, vbar)
+        iters_all.append(it)
+        res_all.append(res)
+        last = k + 1 == len(ladder)
+        if not (evaluate_all or last):
+            continue
+        ub = certificate(Bw, p, ubar, vbar)
+        tt = t
+        for tries in range(4):
+            keep = prune(Bw, p, ubar, vbar, tt)
+            try:
+                perm, weight = optimum_int(W, keep)
+                break
+            except Infeasible:
+                perm, weight = None, None
+                if not last or tries == 3:
+                    break
+                tt /= 10.0
+        evaluated += 1
+        if weight is not None:
+            lg = ub - weight
+            if best is None or lg < best.log_gamma:
+                best = Solution(float(p), ubar.copy(), vbar.copy(), list(iters_all), list(res_all),
+                                keep, int(keep.sum()), ub, perm, weight, lg, {"t": tt})
+            if not evaluate_all or best.log_gamma <= np.log(opt_ratio):
+                best.extra["evaluated"] = evaluated
+                return best, "ok"
+    if best is None:
+        return None, "infeasible"
+    best.extra["evaluated"] = evaluated
+    return best, "ratio"

@@ -26,7 +26,8 @@ SENTINEL = -32768
 
 EXPORTS = ["sk_potentials_bytes", "sk_arena_bytes", "sk_create", "sk_destroy", "sk_last_error",
            "sk_scale", "sk_prune", "sk_solve_reduced", "sk_submit", "sk_poll", "sk_scale_batch",
-           "sk_batch_arena_bytes", "sk_profile_enable", "sk_profile_read", "sk_set_tile_table"]
+           "sk_batch_arena_bytes", "sk_profile_enable", "sk_profile_read", "sk_set_tile_table",
+           "sk_solve", "sk_solve_arena_bytes"]
 TILE_TABLE = os.path.join(HERE, "tile_table_gfx950.json")
 
 
@@ -53,7 +54,9 @@ class Report(ctypes.Structure):
                 ("iters_total", ctypes.c_int64), ("iters_stage", ctypes.c_int64 * MAX_LADDER),
                 ("p_final", ctypes.c_int32), ("stages_capped", ctypes.c_int32),
                 ("nnz_kept", ctypes.c_int64), ("absorbs", ctypes.c_int32),
-                ("seconds", ctypes.c_double)]
+                ("seconds", ctypes.c_double), ("log_gamma", ctypes.c_double),
+                ("threshold_used", ctypes.c_double), ("stages_evaluated", ctypes.c_int32),
+                ("optimal_proved", ctypes.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "iters_stage"}
@@ -105,6 +108,11 @@ def lib():
         L.sk_prune.restype = ctypes.c_int
         L.sk_solve_reduced.argtypes = [ctypes.POINTER(CSR), ctypes.POINTER(i32), ctypes.POINTER(i64)]
         L.sk_solve_reduced.restype = ctypes.c_int
+        L.sk_solve.argtypes = [vp, vp, i32, ctypes.POINTER(Params), vp, ctypes.POINTER(i32),
+                               ctypes.POINTER(i64), ctypes.POINTER(Report)]
+        L.sk_solve.restype = ctypes.c_int
+        L.sk_solve_arena_bytes.argtypes = [i32, i32, i64]
+        L.sk_solve_arena_bytes.restype = sz
         L.sk_submit.argtypes = [vp, vp, i32, ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_uint64)]
         L.sk_submit.restype = ctypes.c_int
         L.sk_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(i32), ctypes.POINTER(i64),
@@ -139,7 +147,7 @@ def load_tile_table(path):
 
 
 def make_params(ladder, tol=1e-5, max_iters=20000, check_every=32, threshold=1e-4,
-                storage="i16", opt_ratio=2.0, warm_start=False, fused=False) -> Params:
+                storage="i16", opt_ratio=0.0, warm_start=False, fused=False) -> Params:
     p = Params()
     ladder = [int(x) for x in ladder]
     if not 1 <= len(ladder) <= MAX_LADDER:
@@ -345,19 +353,34 @@ class Context:
             return row_ptr, col[:nnz], w[:nnz]
         raise SkError(SK_ENOMEM, "sk_prune capacity")
 
-    def solve(self, W, params):
-        """The whole path for one instance: scale, prune, exact solve of the
-        reduced instance, certificate. Returns a dict."""
-        res = self.scale(W, params)
-        row_ptr, col, w = self.prune(W, res.potentials, params)
-        n = W.shape[0]
-        rp, cc, ww = row_ptr.cpu().numpy(), col.cpu().numpy(), w.cpu().numpy()
-        out = dict(status=res.status, report=res.report, nnz=int(rp[-1]), potentials=res.potentials)
-        try:
-            perm, weight = solve_reduced(rp, cc, ww, n)
-            out.update(perm=perm, weight=weight, log_gamma=res.report["ub"] - weight)
-        except SkError as e:
-            if e.status != SK_EINFEASIBLE:
-                raise
+    def solve(self, W, params, potentials=None, max_kept=None):
+        """The whole path for one instance through sk_solve: continuation in p,
+        certificate, reduced matrix, exact solve of it and log gamma; with
+        params.opt_ratio >= 1 the adaptive loop of Algorithm alg:alg1. Returns
+        a dict (status SK_OK or SK_ENOCONV; perm/weight None when no reduced
+        matrix had a perfect matching)."""
+        assert W.dtype == self.torch.int16 and W.is_cuda and W.is_contiguous()
+        n = int(W.shape[0])
+        kept = int(max_kept) if max_kept is not None else min(n * n, 64 * n + 4096)
+        pot = potentials if potentials is not None else self.new_potentials(n)
+        perm = np.empty(n, dtype=np.int32)
+        for attempt in range(2):
+            self.ensure_arena(lib().sk_solve_arena_bytes(n, params.storage, kept))
+            weight = ctypes.c_int64(0)
+            rep = Report()
+            st = lib().sk_solve(self._ptr, ctypes.c_void_p(W.data_ptr()), n, ctypes.byref(params),
+                                ctypes.c_void_p(pot.data_ptr()),
+                                perm.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                ctypes.byref(weight), ctypes.byref(rep))
+            if st == SK_ENOMEM and attempt == 0 and kept < n * n:
+                kept = n * n  # the reduced matrix kept more entries than budgeted
+                continue
+            break
+        self._check(st, "sk_solve", ok=(SK_OK, SK_ENOCONV, SK_EINFEASIBLE))
+        r = rep.as_dict()
+        out = dict(status=st, report=r, nnz=int(r["nnz_kept"]), potentials=pot)
+        if st == SK_EINFEASIBLE:
             out.update(perm=None, weight=None, log_gamma=None)
+        else:
+            out.update(perm=perm, weight=int(weight.value), log_gamma=r["log_gamma"])
         return out

@@ -2,19 +2,21 @@
 //
 // A workgroup of 1024 threads owns a contiguous block of rows and every
 // column; thread t owns the 8-column chunks t, t + 1024 (n <= 16384). For
-// each group of R rows it
-//   A. forms s_ij for its columns (I16: exp(p w_ij + F_i + G_j + gam_j) with
-//      the exact integer part; stored K: K_ij b_j), keeps them in registers and
-//      reduces the row sums S_i across the workgroup (the row step,
-//      eq. dad2: log u_i <- F_i - log S_i, resp. a_i <- 1 / S_i);
-//   B. adds s_ij / S_i into per-thread column accumulators: this is the
-//      column sum of the new row-stochastic iterate, since
-//      exp(p w_ij + log u_i(new) + log v_j) = s_ij / S_i (resp. K_ij a_i(new)
-//      = s_ij / (S_i b_j)).
-// The accumulators go to fixed slots colpart[workgroup][j]; a second kernel
-// adds the slots of each column in workgroup order (deterministic) and
+// each group of rows it
+//   A. forms the terms of its columns and reduces the row sums S_i across the
+//      workgroup (the row step, eq. dad2: log u_i <- F_i - log S_i, resp.
+//      a_i <- 1 / S_i);
+//   B. adds the terms divided by S_i into per-thread column accumulators: this
+//      is the column sum of the new row-stochastic iterate.
+// int16 W: the term is exp(E_ij) exp(gam_j) with the exact integer exponent
+// E_ij = p w_ij + F_i + G_j read from the LDS table; exp(gam_j) is constant
+// per column, so the accumulators hold sum_i exp(E_ij) / S_i and are scaled
+// by exp(gam_j) once at the end. Stored K: the term is K_ij b_j.
+// The accumulators go to fixed slots colpart[workgroup][j]; the finalise
+// kernel adds the slots of each column in workgroup order (deterministic) and
 // applies the column step (eq. dad3). The result equals a row sweep followed
 // by a column sweep, with half the matrix traffic.
+#include "sk_exptab.h"
 #include "sk_runtime.h"
 
 namespace sk {
@@ -268,6 +270,216 @@ __global__ __launch_bounds__(kFT) void k_fused(const Inst *__restrict__ insts, i
     }
 }
 
+// ---------------------------------------------------------------- int16 W
+// Rows of one group (kFR) are loaded one group ahead, so the loads of the next
+// group are in flight while this group is reduced. One barrier per group: the
+// per-wave row partials are double-buffered by group parity, and every lane
+// forms S_i from the 16 partials with the same butterfly (bitwise-equal in
+// all threads).
+__device__ __forceinline__ float sum16(float x) {
+    x += __shfl_xor(x, 1, kWave);
+    x += __shfl_xor(x, 2, kWave);
+    x += __shfl_xor(x, 4, kWave);
+    x += __shfl_xor(x, 8, kWave);
+    return x;
+}
+
+template <int CPT, int FR, bool SENT>
+__device__ __forceinline__ void fused_i16_body(const Inst &I, Ctl *ctl, const float *tab,
+                                               float (*red)[kFT / kWave][kFR], int *redm,
+                                               float *reds) {
+    const int n = I.n;
+    const int t = threadIdx.x, wave = t / kWave, lane = t % kWave;
+    const int par = ctl->iter & 1;
+    const int p4 = 4 * ctl->p;
+    const int per = (n + (int)gridDim.x - 1) / (int)gridDim.x;
+    const int r0 = blockIdx.x * per, r1 = min(n, r0 + per);
+    const int16_t *W = I.W;
+    const int64_t pitch = I.pitch;
+    int c0[CPT];
+    bool own[CPT];
+    int A[CPT][8];
+    float g[CPT][8], acc[CPT][8];
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+        c0[k] = (t + k * kFT) * 8;
+        own[k] = c0[k] < n;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            A[k][c] = own[k] ? 4 * I.G[c0[k] + c] : 0;
+            g[k][c] = own[k] ? fex2(I.gam[c0[k] + c] * kL2e) : 0.f;
+            acc[k][c] = 0.f;
+        }
+    }
+    float resmax = 0.f;
+    int4 nxt[FR][CPT];
+    auto load_group = [&](int rb) {
+#pragma unroll
+        for (int rr = 0; rr < FR; ++rr)
+#pragma unroll
+            for (int k = 0; k < CPT; ++k)
+                nxt[rr][k] = (rb + rr < r1 && own[k])
+                                 ? gload(reinterpret_cast<const int4 *>(W + (int64_t)(rb + rr) * pitch + c0[k]))
+                                 : make_int4(0, 0, 0, 0);
+    };
+    if (r0 < r1) load_group(r0);
+    int buf = 0;
+    for (int rb = r0; rb < r1; rb += FR) {
+        int4 cur[FR][CPT];
+#pragma unroll
+        for (int rr = 0; rr < FR; ++rr)
+#pragma unroll
+            for (int k = 0; k < CPT; ++k) cur[rr][k] = nxt[rr][k];
+        if (rb + FR < r1) load_group(rb + FR);
+        // A: exp(E_ij) per owned column and the row partials
+        float T[FR][CPT][8];
+        float part[FR];
+        int Fi[FR];
+#pragma unroll
+        for (int rr = 0; rr < FR; ++rr) {
+            const int row = rb + rr;
+            Fi[rr] = row < r1 ? I.F[par][row] : 0;
+            const int B = 4 * (Fi[rr] - kTabLo);
+            part[rr] = 0.f;
+#pragma unroll
+            for (int k = 0; k < CPT; ++k) {
+#pragma unroll
+                for (int c = 0; c < 8; ++c) T[rr][k][c] = 0.f;
+                if (row < r1 && own[k]) {
+                    int w[8];
+                    unpack8i(cur[rr][k], w);
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) {
+                        float e = tab_at(tab, tab_off(p4, w[c], A[k][c], B));
+                        if (SENT) e = (w[c] == SK_SENTINEL) ? 0.f : e;
+                        T[rr][k][c] = e;
+                        part[rr] = fmaf(e, g[k][c], part[rr]);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int rr = 0; rr < FR; ++rr) {
+            const float v = fwsum(part[rr]);
+            if (lane == 0) red[buf][wave][rr] = v;
+        }
+        __syncthreads();
+        float inv[FR];
+#pragma unroll
+        for (int rr = 0; rr < FR; ++rr) {
+            const int row = rb + rr;
+            const float S = sum16(red[buf][lane & 15][rr]);
+            inv[rr] = 0.f;
+            if (row >= r1) continue;  // uniform
+            if (S >= kLo && S <= kHi) {
+                inv[rr] = __builtin_amdgcn_rcpf(S);
+                if (t == 0) {
+                    // log u_i <- F_i - log S_i; r_i = exp(phi_i) S_i
+                    const float l2S = flg2(S);
+                    const float phin = -l2S * kLn2f;
+                    const float kk = rintf(phin);
+                    I.F[par ^ 1][row] = Fi[rr] + (int)kk;
+                    I.phi[par ^ 1][row] = phin - kk;
+                    const float r = fex2(fmaf(I.phi[par][row], kL2e, l2S));
+                    resmax = fmaxf(resmax, fabsf(r - 1.f));
+                }
+                continue;
+            }
+            // exact max shift (Section 4.1.2), uniform across the workgroup:
+            // M = max_j (p w_ij + F_i + G_j), then the sum with E - M
+            int m4 = INT_MIN;
+#pragma unroll
+            for (int k = 0; k < CPT; ++k) {
+                if (!own[k]) continue;
+                int w[8];
+                unpack8i(cur[rr][k], w);
+#pragma unroll
+                for (int c = 0; c < 8; ++c)
+                    if (!SENT || w[c] != SK_SENTINEL)
+                        m4 = max(m4, __mul24(p4, w[c]) + A[k][c] + 4 * Fi[rr]);
+            }
+            m4 = wave_max_i(m4);
+            if (lane == 0) redm[wave] = m4;
+            __syncthreads();
+            int mm = INT_MIN;
+            for (int w2 = 0; w2 < kFT / kWave; ++w2) mm = max(mm, redm[w2]);
+            const int M = mm >> 2;  // exact: a multiple of 4 (unused if mm == INT_MIN)
+            float s2 = 0.f;
+#pragma unroll
+            for (int k = 0; k < CPT; ++k) {
+#pragma unroll
+                for (int c = 0; c < 8; ++c) T[rr][k][c] = 0.f;
+                if (!own[k] || mm == INT_MIN) continue;
+                int w[8];
+                unpack8i(cur[rr][k], w);
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    float e = tab_at(tab, tab_off(p4, w[c], A[k][c], 4 * (Fi[rr] - M - kTabLo)));
+                    if (SENT) e = (w[c] == SK_SENTINEL) ? 0.f : e;
+                    T[rr][k][c] = e;
+                    s2 = fmaf(e, g[k][c], s2);
+                }
+            }
+            s2 = fwsum(s2);
+            if (lane == 0) reds[wave] = s2;
+            __syncthreads();
+            float S2 = 0.f;
+            for (int w2 = 0; w2 < kFT / kWave; ++w2) S2 += reds[w2];
+            if (mm == INT_MIN) {
+                if (t == 0) atomicOr(&ctl->err, ERR_EMPTY_ROW);
+            } else {
+                inv[rr] = __builtin_amdgcn_rcpf(S2);
+                if (t == 0) {
+                    const float l2S = flg2(S2);
+                    const float phin = -l2S * kLn2f;
+                    const float kk = rintf(phin);
+                    I.F[par ^ 1][row] = Fi[rr] - M + (int)kk;
+                    I.phi[par ^ 1][row] = phin - kk;
+                    const float r = fex2(fmaf(I.phi[par][row] + (float)M, kL2e, l2S));
+                    resmax = fmaxf(resmax, fabsf(r - 1.f));
+                }
+            }
+            __syncthreads();  // redm / reds are reused by the next such row
+        }
+        // B: column sums of the new row-stochastic iterate (times exp(-gam_j))
+#pragma unroll
+        for (int rr = 0; rr < FR; ++rr)
+#pragma unroll
+            for (int k = 0; k < CPT; ++k)
+#pragma unroll
+                for (int c = 0; c < 8; ++c) acc[k][c] = fmaf(T[rr][k][c], inv[rr], acc[k][c]);
+        buf ^= 1;
+    }
+    float *dst = I.colpart + (int64_t)blockIdx.x * n;
+#pragma unroll
+    for (int k = 0; k < CPT; ++k)
+        if (own[k]) {
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+                if (c0[k] + c < n) dst[c0[k] + c] = acc[k][c] * g[k][c];
+        }
+    // residual slot of this workgroup (thread 0 formed every row's residual)
+    if (t == 0) I.res_slots[blockIdx.x] = resmax;
+}
+
+// Rows per group: two with 8 owned columns per thread, one with 16 (register
+// budget of 128 VGPRs at 1024 threads).
+template <int CPT>
+__global__ __launch_bounds__(kFT) void k_fused_i16(const Inst *__restrict__ insts, int inst) {
+    constexpr int FR = CPT == 1 ? 2 : 1;
+    __shared__ float tab[kTabN];
+    __shared__ float red[2][kFT / kWave][kFR];
+    __shared__ int redm[kFT / kWave];
+    __shared__ float reds[kFT / kWave];
+    const Inst &I = insts[inst];
+    Ctl *ctl = I.ctl;
+    if (ctl->state != ST_RUNNING) return;
+    fill_exp_table(tab);
+    __syncthreads();
+    if (ctl->sent != 0u) fused_i16_body<CPT, FR, true>(I, ctl, tab, red, redm, reds);
+    else fused_i16_body<CPT, FR, false>(I, ctl, tab, red, redm, reds);
+}
+
 template <int ST>
 static hipError_t launch_fused_st(const Inst *d_insts, int inst, int n, int grid, hipStream_t st) {
     const int cpt = (n / 8 + kFT - 1) / kFT;
@@ -280,7 +492,13 @@ static hipError_t launch_fused_st(const Inst *d_insts, int inst, int n, int grid
 
 hipError_t launch_fused(const Inst *d_insts, int inst, int n, int grid, int storage,
                         hipStream_t st) {
-    if (storage == SK_W_I16) return launch_fused_st<SK_W_I16>(d_insts, inst, n, grid, st);
+    if (storage == SK_W_I16) {
+        if ((n / 8 + kFT - 1) / kFT <= 1)
+            hipLaunchKernelGGL(k_fused_i16<1>, dim3(grid), dim3(kFT), 0, st, d_insts, inst);
+        else
+            hipLaunchKernelGGL(k_fused_i16<2>, dim3(grid), dim3(kFT), 0, st, d_insts, inst);
+        return hipGetLastError();
+    }
     if (storage == SK_K_BF16) return launch_fused_st<SK_K_BF16>(d_insts, inst, n, grid, st);
     return launch_fused_st<SK_K_F32>(d_insts, inst, n, grid, st);
 }

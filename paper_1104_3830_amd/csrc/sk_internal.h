@@ -70,7 +70,7 @@ struct Inst {
     int32_t fused;          // single-pass iteration (colpart holds kFusedSlots rows)
     int32_t fused_grid;
     int32_t ncolslots;      // rows of colpart in use: nseg (sweeps) or fused_grid (single pass)
-    int32_t pad2;
+    int32_t pause;          // end every stage in ST_STAGE_END (the host advances p)
     // max |r_i - 1| of the current iterate, per row segment (log-domain
     // sweeps), per row unit (stored-K sweeps) or per workgroup (single pass)
     float *res_slots;

@@ -338,7 +338,8 @@ __global__ __launch_bounds__(256) void k_fold(const Inst *__restrict__ insts) {
     }
 }
 
-// Next p of the ladder (p^-1 log u, p^-1 log v held fixed), or done.
+// Next p of the ladder (p^-1 log u, p^-1 log v held fixed), or done; after a
+// pause at the end of a stage (stored K, or a host that evaluates each stage).
 __global__ __launch_bounds__(256) void k_advance(const Inst *__restrict__ insts) {
     const Inst &I = insts[blockIdx.x];
     Ctl *ctl = I.ctl;
@@ -363,7 +364,7 @@ __global__ __launch_bounds__(256) void k_advance(const Inst *__restrict__ insts)
             ctl->stage = s + 1;
             ctl->p = I.ladder[s + 1];
             ctl->iter = 0;
-            ctl->need_absorb = 1u;
+            ctl->need_absorb = I.storage != SK_W_I16 ? 1u : 0u;
             ctl->state = ST_RUNNING;
         }
     } else {
@@ -525,7 +526,7 @@ static sk_status request_absorb(sk_ctx *ctx, Batch &B) {
     return SK_OK;
 }
 
-sk_status run_single_k(sk_ctx *ctx, Batch &B, const sk_params *prm) {
+sk_status run_single_k(sk_ctx *ctx, Batch &B, const sk_params *prm, const StageHook *hook) {
     const int storage = prm->storage;
     const int check = std::max(1, prm->check_every);
     sk_status st;
@@ -562,6 +563,11 @@ sk_status run_single_k(sk_ctx *ctx, Batch &B, const sk_params *prm) {
                 ctx->k_res_cols = cr;
             }
             if ((st = fold(ctx, B)) != SK_OK) return st;
+            if (hook) {
+                bool stop = false;
+                if ((st = (*hook)(stop)) != SK_OK) return st;
+                if (stop) return SK_OK;
+            }
             KCHK(launch_advance(B.d_insts, B.count, ctx->stream));
             continue;
         }

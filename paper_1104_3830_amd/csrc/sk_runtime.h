@@ -2,6 +2,7 @@
 #pragma once
 
 #include <cstdarg>
+#include <functional>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -120,7 +121,27 @@ struct sk_ctx {
 namespace sk {
 
 sk_status fail(sk_ctx *ctx, sk_status st, const char *fmt, ...);
+
+// Returns SK_EDEVICE (with the HIP error text) from the enclosing function
+// when `expr` fails.
+#define HIPCHK(ctx, expr)                                                                   \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(ctx, SK_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));    \
+    } while (0)
+
+// Launch `call` between the profiler's begin/end events for kernel `id`.
+#define PROF(ctx, id, call)                         \
+    ([&]() {                                        \
+        (ctx)->prof.begin((ctx)->stream, (id));     \
+        hipError_t e__ = (call);                    \
+        (ctx)->prof.end((ctx)->stream);             \
+        return e__;                                 \
+    }())
 sk_status check_params(sk_ctx *ctx, const sk_params *p);
+sk_status check_range(sk_ctx *ctx, const sk_params *prm);  // p small enough for exact exponents
+sk_status status_of(const Ctl &c);  // SK_OK, SK_ENOCONV (a stage capped) or SK_ENOSUPPORT
 bool carve_instance(Bump &bump, const int16_t *W, int64_t pitch, int32_t n, const sk_params *prm,
                     Inst &I);
 sk_status finish_tables(sk_ctx *ctx, Bump &bump, Batch &B);
@@ -130,8 +151,15 @@ sk_status upload_batch(sk_ctx *ctx, Batch &B);
 sk_status start_batch(sk_ctx *ctx, Batch &B, const sk_params *prm, void *const *pot_in);
 sk_status read_ctl(sk_ctx *ctx, Batch &B);
 sk_status iterate_i16(sk_ctx *ctx, Batch &B);
-sk_status run_batch_i16(sk_ctx *ctx, Batch &B, const sk_params *prm);
-sk_status run_single_k(sk_ctx *ctx, Batch &B, const sk_params *prm);
+// Iterates until no instance is running (done, error, or paused at a stage
+// end); first_stage: the stage the instances start this call in (launch tags).
+sk_status run_batch_i16(sk_ctx *ctx, Batch &B, const sk_params *prm, int first_stage = 0);
+// Called at the end of every stage of the stored-K controller, after the
+// scalings are folded into the potentials and before p moves on; setting
+// `stop` ends the run there.
+using StageHook = std::function<sk_status(bool &stop)>;
+sk_status run_single_k(sk_ctx *ctx, Batch &B, const sk_params *prm,
+                       const StageHook *hook = nullptr);
 sk_status check_fp64(sk_ctx *ctx, Batch &B, int k, sk_report *rep);
 sk_status enqueue_check(sk_ctx *ctx, Batch &B, int k);  // writes B.d_checkout[k]
 void report_from_check(const double *out4, int p, sk_report *rep);

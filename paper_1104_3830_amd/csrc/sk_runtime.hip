@@ -153,14 +153,6 @@ Profiler::~Profiler() {
 
 using namespace sk;
 
-#define PROF(ctx, id, call)            \
-    ([&]() {                           \
-        (ctx)->prof.begin((ctx)->stream, (id)); \
-        hipError_t e__ = (call);       \
-        (ctx)->prof.end((ctx)->stream); \
-        return e__;                    \
-    }())
-
 sk_status sk_set_tile_table(const int32_t *n_max, const int32_t *seg_rows, int32_t count) {
     if (count < 0 || (count > 0 && (!n_max || !seg_rows))) return SK_EINVAL;
     std::vector<std::pair<int32_t, int32_t>> t;
@@ -278,13 +270,6 @@ sk_status sk::fail(sk_ctx *ctx, sk_status st, const char *fmt, ...) {
     ctx->err = buf;
     return st;
 }
-
-#define HIPCHK(ctx, expr)                                                                   \
-    do {                                                                                    \
-        hipError_t e_ = (expr);                                                             \
-        if (e_ != hipSuccess)                                                               \
-            return fail(ctx, SK_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));    \
-    } while (0)
 
 sk_status sk::check_params(sk_ctx *ctx, const sk_params *p) {
     if (!p) return fail(ctx, SK_EINVAL, "params is NULL");
@@ -480,7 +465,7 @@ sk_status sk::iterate_i16(sk_ctx *ctx, Batch &B) {
 // With timing on, launches are tagged afterwards: a triple (row, column,
 // end) either did an iteration, or only detected that a stage had converged
 // (its column sweep does no sums), or came after every instance finished.
-sk_status sk::run_batch_i16(sk_ctx *ctx, Batch &B, const sk_params *prm) {
+sk_status sk::run_batch_i16(sk_ctx *ctx, Batch &B, const sk_params *prm, int first_stage) {
     const int check = std::max(1, prm->check_every);
     const int64_t bound = (prm->max_iters_per_stage + 1) * prm->n_p + 1;
     const size_t pstart = ctx->prof.pending.size();
@@ -506,10 +491,10 @@ sk_status sk::run_batch_i16(sk_ctx *ctx, Batch &B, const sk_params *prm) {
         for (int k = 0; k < B.count; ++k) {
             const Ctl &c = ctx->h_ctl[k];
             int64_t t = 0;
-            for (int s = 0; s <= std::min(c.stage, prm->n_p - 1); ++s) {
+            for (int s = first_stage; s <= std::min(c.stage, prm->n_p - 1); ++s) {
                 t += c.stage_iters[s];
                 const bool conv = c.stage_iters[s] < prm->max_iters_per_stage &&
-                                  (s < c.stage || c.state == ST_DONE);
+                                  (s < c.stage || c.state == ST_DONE || c.state == ST_STAGE_END);
                 if (conv) {
                     if (B.count == 1) detect.push_back(t);
                     t += 1;
@@ -597,7 +582,7 @@ sk_status sk::copy_potentials_out(sk_ctx *ctx, Batch &B, int k, void *pot) {
     return SK_OK;
 }
 
-static sk_status status_of(const Ctl &c) {
+sk_status sk::status_of(const Ctl &c) {
     if (c.err & (ERR_EMPTY_ROW | ERR_EMPTY_COL)) return SK_ENOSUPPORT;
     if (c.capped) return SK_ENOCONV;
     return SK_OK;
@@ -607,7 +592,7 @@ static sk_status status_of(const Ctl &c) {
 // valid weights are in [-16384, 16383], so p <= 128 guarantees |p w| <= 2^21.
 // Larger p is accepted when the weights are small enough; the input scan
 // would be needed to prove it, so the bound here is on p alone.
-static sk_status check_range(sk_ctx *ctx, const sk_params *prm) {
+sk_status sk::check_range(sk_ctx *ctx, const sk_params *prm) {
     int pmax = 0;
     for (int s = 0; s < prm->n_p; ++s) pmax = std::max(pmax, prm->p_ladder[s]);
     if ((int64_t)pmax * 16384 > ((int64_t)1 << 25))

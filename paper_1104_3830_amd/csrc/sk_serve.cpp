@@ -136,6 +136,15 @@ static void solver_loop(Server *S) {
             std::lock_guard<std::mutex> g(S->mu);
             r->weight = weight;
             if (st != SK_OK) r->status = st;
+            r->rep.stages_evaluated = 1;
+            r->rep.threshold_used = r->prm.threshold;
+            if (st == SK_OK) {
+                // log gamma = ub - w(B) (eq. optratio); integer weights: < 1 proves optimality
+                r->rep.log_gamma = r->rep.ub - (double)weight;
+                r->rep.optimal_proved = r->rep.log_gamma < 1.0 - 1e-9 ? 1 : 0;
+            } else {
+                r->rep.log_gamma = NAN;
+            }
             r->rep.seconds =
                 std::chrono::duration<double>(std::chrono::steady_clock::now() - r->t_submit).count();
             r->rp.clear();

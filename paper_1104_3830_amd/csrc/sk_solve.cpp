@@ -1,0 +1,239 @@
+// The whole path for one instance, with the adaptive loop of Algorithm
+// alg:alg1 (Section 4.2): continuation in p; at the end of each stage the FP64
+// certificate (Proposition prop:aoc), the reduced matrix B (eq. matrixred),
+// an exact optimal assignment of B on the host and the ratio gamma
+// (eq. optratio); it stops at the first stage whose gamma is within the
+// required ratio.
+//
+// When every stage is evaluated, the device stage controller pauses at each
+// stage end (Inst::pause); the host evaluates the stage and either stops or
+// moves to the next p with p^-1 log u and p^-1 log v held fixed.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "sk_runtime.h"
+
+namespace sk {
+namespace {
+
+struct StageResult {
+    bool feasible = false;
+    int p = 0;
+    double t = 0;
+    double log_gamma = INFINITY;
+    int64_t weight = 0;
+    int64_t nnz = 0;
+    std::vector<int32_t> perm;
+    sk_report rep{};
+};
+
+// B at threshold t from the committed potentials of instance 0, its CSR on
+// the host, and an exact optimum of B (feasible = B has a perfect matching).
+sk_status reduce_and_solve(sk_ctx *ctx, Batch &B, Bump rest, double t, StageResult &r) {
+    const Inst &I = B.h_insts[0];
+    const int n = I.n;
+    int64_t *d_rp = rest.take<int64_t>((size_t)n + 1);
+    if (!d_rp) return fail(ctx, SK_ENOMEM, "arena too small for the reduced matrix (row pointers)");
+    const double logt = std::log(t);
+    const int nunits = (int)B.h_rows.size();
+    const size_t lds = sizeof(double) * (size_t)n;
+    HIPCHK(ctx, PROF(ctx, KID_PRUNE_COUNT, launch_prune_count(B.d_insts, B.d_rows, nunits, B.row_grid,
+                                                             logt, B.d_counts, lds, ctx->stream)));
+    HIPCHK(ctx, PROF(ctx, KID_SCAN, launch_scan(B.d_counts, d_rp, n, ctx->stream, B.d_nnz)));
+    HIPCHK(ctx, hipMemcpyAsync(ctx->h_nnz, B.d_nnz, sizeof(int64_t), hipMemcpyDeviceToHost,
+                               ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    const int64_t nnz = ctx->h_nnz[0];
+    std::vector<int64_t> rp((size_t)n + 1);
+    std::vector<int32_t> col((size_t)nnz);
+    std::vector<int16_t> w((size_t)nnz);
+    if (nnz > 0) {
+        int32_t *d_col = rest.take<int32_t>((size_t)nnz);
+        int16_t *d_w = rest.take<int16_t>((size_t)nnz);
+        if (!d_col || !d_w)
+            return fail(ctx, SK_ENOMEM, "the reduced matrix keeps %lld entries; the arena cannot hold them",
+                        (long long)nnz);
+        HIPCHK(ctx, PROF(ctx, KID_PRUNE_FILL, launch_prune_fill(B.d_insts, B.d_rows, nunits, B.row_grid,
+                                                               logt, d_rp, d_col, d_w, lds, ctx->stream)));
+        HIPCHK(ctx, hipMemcpyAsync(col.data(), d_col, sizeof(int32_t) * (size_t)nnz,
+                                   hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(ctx, hipMemcpyAsync(w.data(), d_w, sizeof(int16_t) * (size_t)nnz, hipMemcpyDeviceToHost,
+                                   ctx->stream));
+    }
+    HIPCHK(ctx, hipMemcpyAsync(rp.data(), d_rp, sizeof(int64_t) * ((size_t)n + 1),
+                               hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    sk_csr csr{n, nnz, rp.data(), col.data(), w.data()};
+    r.perm.assign((size_t)n, -1);
+    r.t = t;
+    r.nnz = nnz;
+    const sk_status s = sk_solve_reduced(&csr, r.perm.data(), &r.weight);
+    if (s == SK_EINFEASIBLE) {
+        r.feasible = false;
+        return SK_OK;
+    }
+    if (s != SK_OK) return fail(ctx, s, "exact solve of the reduced matrix rejected its CSR");
+    r.feasible = true;
+    return SK_OK;
+}
+
+}  // namespace
+}  // namespace sk
+
+using namespace sk;
+
+size_t sk_solve_arena_bytes(int32_t n, int32_t storage, int64_t max_kept) {
+    if (n < 1 || n > kMaxN || max_kept < 0) return 0;
+    return sk_arena_bytes(n, storage) + align_up(sizeof(int64_t) * ((size_t)n + 1), 256) +
+           align_up(sizeof(int32_t) * (size_t)max_kept, 256) +
+           align_up(sizeof(int16_t) * (size_t)max_kept, 256) + 1024;
+}
+
+extern "C" sk_status sk_solve(sk_ctx *ctx, const int16_t *W, int32_t n, const sk_params *params,
+                              void *potentials, int32_t *perm, int64_t *weight, sk_report *report) {
+    if (!ctx) return SK_EINVAL;
+    const auto t0 = std::chrono::steady_clock::now();
+    std::lock_guard<std::mutex> g(ctx->mu);
+    if (serving(ctx)) return fail(ctx, SK_EINVAL, "context is serving; blocking calls are disabled");
+    ctx->absorbs = 0;
+    sk_status st = check_params(ctx, params);
+    if (st != SK_OK) return st;
+    if (!W || !potentials || !perm || !weight) return fail(ctx, SK_EINVAL, "null argument");
+    if (n < 1 || n > kMaxN) return fail(ctx, SK_EINVAL, "n = %d outside [1, %d]", n, kMaxN);
+    if (!(params->threshold > 0.0)) return fail(ctx, SK_EINVAL, "threshold must be > 0");
+    if (params->fused && params->storage == SK_W_I16 && (n % 8 != 0 || (uintptr_t)W % 16 != 0))
+        return fail(ctx, SK_EINVAL, "the single-pass iteration over int16 W needs n %% 8 == 0");
+    if ((st = check_range(ctx, params)) != SK_OK) return st;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    Bump bump{ctx->arena, ctx->arena_bytes};
+    Batch &B = ctx->scratch_batch;
+    int64_t pitch = n;
+    const int16_t *Ws[1] = {W};
+    // gamma <= opt_ratio is the stopping rule (reading of Algorithm alg:alg1);
+    // opt_ratio < 1 asks for one evaluation, at the last p, and the log-domain
+    // device controller then runs the whole ladder without pausing
+    const bool adaptive = params->opt_ratio >= 1.0;
+    const double log_ratio = adaptive ? std::log(params->opt_ratio) : 0.0;
+    const bool kpath = params->storage != SK_W_I16;
+    if ((st = plan_batch(ctx, bump, 1, Ws, &pitch, &n, params, B)) != SK_OK) return st;
+    B.h_insts[0].pause = (adaptive && !kpath) ? 1 : 0;
+    if ((st = upload_batch(ctx, B)) != SK_OK) return st;
+    void *pots[1] = {potentials};
+    if ((st = start_batch(ctx, B, params, pots)) != SK_OK) return st;
+    StageResult best;
+    bool have_best = false, reached = false;
+    int evaluated = 0;
+
+    // the end of one stage: certificate, B, exact optimum of B, gamma
+    auto evaluate = [&](const Ctl &c, bool last, bool &stop) -> sk_status {
+        stop = false;
+        if (!(adaptive || last)) return SK_OK;
+        StageResult r;
+        r.p = c.p;
+        fill_report(c, &r.rep);
+        sk_status s2 = check_fp64(ctx, B, 0, &r.rep);
+        if (s2 != SK_OK) return s2;
+        // a B with no perfect matching at the last p: lower t tenfold, at most three times
+        double t = params->threshold;
+        for (int tries = 0;; ++tries) {
+            if ((s2 = reduce_and_solve(ctx, B, bump, t, r)) != SK_OK) return s2;
+            if (r.feasible || !last || tries == 3) break;
+            t /= 10.0;
+        }
+        ++evaluated;
+        if (r.feasible) {
+            r.log_gamma = r.rep.ub - (double)r.weight;
+            if (!have_best || r.log_gamma < best.log_gamma) {
+                if ((s2 = copy_potentials_out(ctx, B, 0, potentials)) != SK_OK) return s2;
+                best = std::move(r);
+                have_best = true;
+            }
+            if (!adaptive || best.log_gamma <= log_ratio) {
+                reached = true;
+                stop = true;
+            }
+        }
+        return SK_OK;
+    };
+
+    if (kpath) {
+        // stored K: the controller pauses at every stage end anyway
+        const StageHook hook = [&](bool &stop) {
+            const Ctl &c = ctx->h_ctl[0];
+            return evaluate(c, c.stage + 1 >= params->n_p, stop);
+        };
+        if ((st = run_single_k(ctx, B, params, &hook)) != SK_OK) return st;
+        if ((st = read_ctl(ctx, B)) != SK_OK) return st;
+    } else {
+        int stage = 0;
+        for (;;) {
+            if ((st = run_batch_i16(ctx, B, params, stage)) != SK_OK) return st;
+            const Ctl c = ctx->h_ctl[0];
+            if (c.state == ST_ERROR) break;
+            if (c.state != ST_STAGE_END && c.state != ST_DONE)
+                return fail(ctx, SK_EDEVICE, "stage controller ended in state %d", c.state);
+            stage = c.stage;
+            const bool last = c.state == ST_DONE || stage + 1 >= params->n_p;
+            bool stop = false;
+            if ((st = evaluate(c, last, stop)) != SK_OK) return st;
+            if (stop || last) break;
+            HIPCHK(ctx, launch_advance(B.d_insts, 1, ctx->stream));
+            stage += 1;
+        }
+    }
+    const Ctl c = ctx->h_ctl[0];
+    if (c.state == ST_ERROR) {
+        if (report) {
+            memset(report, 0, sizeof *report);
+            fill_report(c, report);
+            report->log_gamma = NAN;
+            report->threshold_used = NAN;
+        }
+        return fail(ctx, status_of(c), "a row or column of A has no entry");
+    }
+    if (!have_best) {
+        if ((st = copy_potentials_out(ctx, B, 0, potentials)) != SK_OK) return st;
+    }
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    sk_report rep;
+    memset(&rep, 0, sizeof rep);
+    fill_report(c, &rep);  // work done over all stages run
+    rep.absorbs = ctx->absorbs;
+    if (have_best) {
+        rep.residual_fp64 = best.rep.residual_fp64;
+        rep.col_residual_fp64 = best.rep.col_residual_fp64;
+        rep.residual_exact_fp64 = best.rep.residual_exact_fp64;
+        rep.col_residual_exact_fp64 = best.rep.col_residual_exact_fp64;
+        if (kpath && best.p == params->p_ladder[params->n_p - 1] && !std::isnan(ctx->k_res_rows)) {
+            // the matrix the stored-K sweeps balance, K a b (before folding)
+            rep.residual_fp64 = ctx->k_res_rows;
+            rep.col_residual_fp64 = ctx->k_res_cols;
+        }
+        rep.ub = best.rep.ub;
+        rep.residual_fp32 = best.rep.residual_fp32;
+        rep.p_final = best.p;
+        rep.nnz_kept = best.nnz;
+        rep.log_gamma = best.log_gamma;
+        rep.threshold_used = best.t;
+        // integer weights: every permutation of A weighs at most ub, so
+        // ub - w(B) < 1 leaves no room for a better one
+        rep.optimal_proved = best.log_gamma < 1.0 - 1e-9 ? 1 : 0;
+        memcpy(perm, best.perm.data(), sizeof(int32_t) * (size_t)n);
+        *weight = best.weight;
+    } else {
+        rep.log_gamma = NAN;
+        rep.threshold_used = NAN;
+    }
+    rep.stages_evaluated = evaluated;
+    rep.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (report) *report = rep;
+    if (!have_best)
+        return fail(ctx, SK_EINFEASIBLE, "no reduced matrix had a perfect matching (last t = %g)",
+                    params->threshold * 1e-3);
+    if (!reached)
+        return fail(ctx, SK_ENOCONV, "gamma = exp(%g) above opt_ratio %g after the last p",
+                    best.log_gamma, params->opt_ratio);
+    return SK_OK;
+}

@@ -34,6 +34,7 @@ TAG_DIAG = 4
 TAG_SIZES = 5
 TAG_ARRIVALS = 6
 TAG_OFFDIAG = 7
+TAG_POINTS = 8
 
 
 def _mix(z: np.ndarray) -> np.ndarray:
@@ -148,3 +149,22 @@ def planted_batch(count: int, lo: int, hi: int, seed: int):
     """A ragged batch of planted instances: list of (W, sigma)."""
     ns = sizes_loguniform(count, lo, hi, seed)
     return [planted(int(n), seed * 100003 + k) for k, n in enumerate(ns)]
+
+
+def euclidean_points(n: int, seed: int):
+    """2n points uniform in the unit cube of R^3: (x, y), each of shape (n, 3)."""
+    u = unit(stream(seed, TAG_POINTS, 6 * n)).reshape(2, n, 3)
+    return u[0], u[1]
+
+
+def euclidean(n: int, seed: int, scale: int = 1000, chunk_rows: int = 1024):
+    """Euclidean random assignment workload: a_ij = exp(-d(x_i, y_j)) for the
+    points of euclidean_points. The int16 log-weights are the distances
+    quantised at 1/scale: w_ij = -round(scale * d(x_i, y_j)) (d <= sqrt 3, so
+    |w| <= 1733 at scale 1000). Returns (W, x, y)."""
+    x, y = euclidean_points(n, seed)
+    W = np.empty((n, n), dtype=np.int16)
+    for r in range(0, n, chunk_rows):
+        d = np.sqrt(((x[r:r + chunk_rows, None, :] - y[None, :, :]) ** 2).sum(axis=2))
+        W[r:r + chunk_rows] = -np.rint(scale * d).astype(np.int16)
+    return W, x, y

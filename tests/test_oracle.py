@@ -351,3 +351,58 @@ def test_solve_planted_and_dominant():
     sol = oracle.solve(Wd, [1, 2, 4, 8, 16, 32], 1e-5, 5000, 1e-4)
     assert np.array_equal(sol.perm, np.arange(128))
     assert sol.nnz == 128   # only the permutation survives
+
+
+# ---------------------------------------------------------------- Algorithm alg:alg1
+
+def test_adaptive_planted_closed_form():
+    """Planted optimum (weight 1050 n, permutation sigma) at whatever p the
+    loop returns; gamma >= 1 always (ub >= w_opt(A) >= w_opt(B))."""
+    n = 24
+    W, sigma = skgen.planted(n, 5)
+    for ratio in (0.0, 1.5, 1e300):
+        s, status = oracle.adaptive(W, [1, 2, 4, 8, 16], 1e-9, 5000, 1e-4, ratio)
+        assert status == "ok"
+        assert s.weight == 1050 * n and (s.perm == sigma).all()
+        assert s.log_gamma >= -1e-9
+
+
+def test_adaptive_certified_weight_is_brute_force_optimum():
+    """Whenever log gamma < 1 the returned weight is the optimum of A over all
+    n! permutations (integer weights), checked by enumeration."""
+    for seed in range(6):
+        W = skgen.uniform_weights(6, 0, 12, seed=seed)
+        s, status = oracle.adaptive(W, [1, 2, 4, 8, 16, 32], 1e-10, 20000, 1e-4, math.e)
+        assert status in ("ok", "ratio")
+        best = max(int(W[np.arange(6), list(q)].astype(np.int64).sum())
+                   for q in itertools.permutations(range(6)))
+        assert s.log_gamma >= -1e-9 and s.ub >= best - 1e-9
+        if s.log_gamma < 1.0:
+            assert s.weight == best
+
+
+def test_adaptive_stopping_rule():
+    """A huge ratio stops at the first stage with a perfect matching; a ratio
+    below 1 evaluates the last stage only; a ratio never reached returns the
+    stage with the smallest gamma."""
+    W = skgen.uniform_weights(64, 0, 100, seed=1)
+    lad = [1, 2, 4, 8]
+    s, status = oracle.adaptive(W, lad, 1e-6, 3000, 1e-4, 1e300)
+    assert status == "ok" and s.p == 1.0 and s.extra["evaluated"] == 1
+    s, status = oracle.adaptive(W, lad, 1e-6, 3000, 1e-4, 0.0)
+    assert status == "ok" and s.p == 8.0 and s.extra["evaluated"] == 1
+    s, status = oracle.adaptive(W, lad, 1e-6, 3000, 1e-4, 1.0 + 1e-12)
+    assert status == "ratio" and s.extra["evaluated"] == 4
+    gammas = [oracle.adaptive(W, lad[: k + 1], 1e-6, 3000, 1e-4, 0.0)[0].log_gamma
+              for k in range(4)]
+    assert s.log_gamma == min(gammas)
+
+
+def test_adaptive_lowers_threshold_at_last_stage():
+    """t = 0.99 leaves no perfect matching at p = 1; the loop lowers t tenfold
+    until the reduced matrix has one, and the weight is then the optimum."""
+    W = skgen.uniform_weights(64, 0, 100, seed=4)
+    s, status = oracle.adaptive(W, [1], 1e-9, 5000, 0.99, 0.0)
+    assert status == "ok" and s.extra["t"] < 0.99
+    assert s.extra["t"] == pytest.approx(0.99 * 10.0 ** round(math.log10(s.extra["t"] / 0.99)))
+    assert s.weight == oracle.optimum_int(W)[1]
