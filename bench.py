@@ -27,6 +27,10 @@ batched: 512 independent instances, n log-uniform on [32, 1024], weights
 uniform 0..1000; sk_scale_batch (one launch per sweep across all instances)
 against 512 sequential sk_scale calls with the same parameters.
 
+euclidean: the Euclidean random assignment workload at n = 1000 (2n points
+uniform in the unit cube, a_ij = exp(-d), distances quantised at 1/1000)
+through sk_solve with opt_ratio e: gamma, p, iterations, kept entries.
+
 served: 1000 Poisson arrivals of planted instances with n log-uniform on
 [64, 8192], tolerance 1e-5, at offered loads of 0.5, 0.9 and 1.5 times the
 FIFO loop's measured capacity; requests through sk_submit/sk_poll (continuous
@@ -71,6 +75,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-euclidean", action="store_true")
     ap.add_argument("--served-requests", type=int, default=1000)
     ap.add_argument("--served-loads", default="0.5,0.9,1.5",
                     help="arrival rates as multiples of the FIFO loop's measured capacity")
@@ -325,6 +330,28 @@ def served_leg(sk, torch, n_requests, loads, seed=2):
             "fifo_capacity_solves_per_s": round(mu, 2), "loads": per_load}
 
 
+def euclidean_leg(sk, torch, n=1000, seed=0):
+    """The Euclidean random assignment workload at the paper's size: 2n points
+    uniform in the unit cube, a_ij = exp(-d), distances quantised at 1/1000,
+    through sk_solve (Algorithm 1 with opt_ratio e)."""
+    import math
+    import skgen
+    W, _, _ = skgen.euclidean(n, seed)
+    prm = sk.make_params([1], tol=1e-5, max_iters=20000, threshold=1e-4, opt_ratio=math.e)
+    ctx = sk.Context(0)
+    Wd = torch.from_numpy(W).cuda()
+    ctx.solve(Wd, prm)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = ctx.solve(Wd, prm)
+    el = time.perf_counter() - t0
+    r = out["report"]
+    ctx.close()
+    return {"n": n, "p": r["p_final"], "gamma": round(math.exp(r["log_gamma"]), 4),
+            "iterations": r["iters_total"], "kept_percent": round(100.0 * r["nnz_kept"] / n / n, 3),
+            "optimal_proved": bool(r["optimal_proved"]), "seconds": round(el, 4)}
+
+
 def cpu_baseline(W, p, seconds):
     """The oracle's Sinkhorn at the same n and p, timed on the host cores."""
     import oracle
@@ -449,6 +476,8 @@ def main():
     del Wd
     if not args.no_batched:
         out["batched"] = batched_leg(sk, torch)
+    if not args.no_euclidean:
+        out["euclidean"] = euclidean_leg(sk, torch)
     if not args.no_served:
         out["served"] = served_leg(sk, torch, args.served_requests,
                                    [float(x) for x in args.served_loads.split(",")])

@@ -271,23 +271,45 @@ __global__ __launch_bounds__(kFT) void k_fused(const Inst *__restrict__ insts, i
 }
 
 // ---------------------------------------------------------------- int16 W
-// Rows of one group (kFR) are loaded one group ahead, so the loads of the next
-// group are in flight while this group is reduced. One barrier per group: the
-// per-wave row partials are double-buffered by group parity, and every lane
-// forms S_i from the 16 partials with the same butterfly (bitwise-equal in
-// all threads).
-__device__ __forceinline__ float sum16(float x) {
-    x += __shfl_xor(x, 1, kWave);
-    x += __shfl_xor(x, 2, kWave);
-    x += __shfl_xor(x, 4, kWave);
-    x += __shfl_xor(x, 8, kWave);
+// Sums across lanes with DPP moves in a fixed order (deterministic, no LDS
+// round trip): after dpp_sum16 every lane of a 16-lane row holds the row's
+// sum, bitwise equal in all of them (each step adds two equal-shaped partial
+// sums, and float addition is commutative); dpp_wave_sum leaves the
+// wavefront's total in lane 63.
+template <int CTRL, int ROWMASK = 0xf>
+__device__ __forceinline__ float dppf(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROWMASK, 0xf, false));
+}
+__device__ __forceinline__ float dpp_sum16(float x) {
+    x += dppf<0xB1>(x);   // quad_perm [1,0,3,2]
+    x += dppf<0x4E>(x);   // quad_perm [2,3,0,1]
+    x += dppf<0x141>(x);  // row_half_mirror
+    x += dppf<0x140>(x);  // row_mirror
     return x;
 }
+__device__ __forceinline__ float dpp_wave_sum(float x) {
+    x = dpp_sum16(x);
+    x += dppf<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
+    x += dppf<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+}
 
+__device__ __forceinline__ int gld(const int32_t *p) { return *(const SK_GLOBAL int32_t *)p; }
+__device__ __forceinline__ float gld(const float *p) { return *(const SK_GLOBAL float *)p; }
+__device__ __forceinline__ void gst(int32_t *p, int v) { *(SK_GLOBAL int32_t *)p = v; }
+__device__ __forceinline__ void gst(float *p, float v) { *(SK_GLOBAL float *)p = v; }
+
+// Rows of a group (FR) are loaded one group ahead into the other of two
+// register buffers, so the next group's loads are in flight while this one is
+// reduced. One barrier per group: the per-wave row partials are
+// double-buffered by group parity and every lane forms S_i from the 16
+// partials with dpp_sum16. The scalar work of row i (its new potentials and
+// residual) is done by lane 0 of wave (i - r0) mod 16, so no single wave falls
+// behind at every barrier.
 template <int CPT, int FR, bool SENT>
 __device__ __forceinline__ void fused_i16_body(const Inst &I, Ctl *ctl, const float *tab,
                                                float (*red)[kFT / kWave][kFR], int *redm,
-                                               float *reds) {
+                                               float *reds, float *wres, float *gl) {
     const int n = I.n;
     const int t = threadIdx.x, wave = t / kWave, lane = t % kWave;
     const int par = ctl->iter & 1;
@@ -296,41 +318,40 @@ __device__ __forceinline__ void fused_i16_body(const Inst &I, Ctl *ctl, const fl
     const int r0 = blockIdx.x * per, r1 = min(n, r0 + per);
     const int16_t *W = I.W;
     const int64_t pitch = I.pitch;
+    const int32_t *Fp = I.F[par];
+    int32_t *Fn = I.F[par ^ 1];
+    const float *phip = I.phi[par];
+    float *phin_p = I.phi[par ^ 1];
     int c0[CPT];
     bool own[CPT];
+    // per owned column: 4 G_j in registers, exp(gam_j) in LDS at
+    // gl[(k * 8 + c) * kFT + t] (each lane reads consecutive words)
     int A[CPT][8];
-    float g[CPT][8], acc[CPT][8];
+    float acc[CPT][8];
 #pragma unroll
     for (int k = 0; k < CPT; ++k) {
         c0[k] = (t + k * kFT) * 8;
         own[k] = c0[k] < n;
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
-            A[k][c] = own[k] ? 4 * I.G[c0[k] + c] : 0;
-            g[k][c] = own[k] ? fex2(I.gam[c0[k] + c] * kL2e) : 0.f;
+            A[k][c] = own[k] ? 4 * gld(I.G + c0[k] + c) : 0;
+            gl[(k * 8 + c) * kFT + t] = own[k] ? fex2(gld(I.gam + c0[k] + c) * kL2e) : 0.f;
             acc[k][c] = 0.f;
         }
     }
     float resmax = 0.f;
-    int4 nxt[FR][CPT];
-    auto load_group = [&](int rb) {
+    int4 ba[FR][CPT], bb[FR][CPT];
+    auto load_group = [&](int4 (&buf)[FR][CPT], int rb) {
 #pragma unroll
         for (int rr = 0; rr < FR; ++rr)
 #pragma unroll
             for (int k = 0; k < CPT; ++k)
-                nxt[rr][k] = (rb + rr < r1 && own[k])
+                buf[rr][k] = (rb + rr < r1 && own[k])
                                  ? gload(reinterpret_cast<const int4 *>(W + (int64_t)(rb + rr) * pitch + c0[k]))
                                  : make_int4(0, 0, 0, 0);
     };
-    if (r0 < r1) load_group(r0);
-    int buf = 0;
-    for (int rb = r0; rb < r1; rb += FR) {
-        int4 cur[FR][CPT];
-#pragma unroll
-        for (int rr = 0; rr < FR; ++rr)
-#pragma unroll
-            for (int k = 0; k < CPT; ++k) cur[rr][k] = nxt[rr][k];
-        if (rb + FR < r1) load_group(rb + FR);
+    int parity = 0;
+    auto process = [&](const int4 (&cur)[FR][CPT], int rb) {
         // A: exp(E_ij) per owned column and the row partials
         float T[FR][CPT][8];
         float part[FR];
@@ -338,13 +359,12 @@ __device__ __forceinline__ void fused_i16_body(const Inst &I, Ctl *ctl, const fl
 #pragma unroll
         for (int rr = 0; rr < FR; ++rr) {
             const int row = rb + rr;
-            Fi[rr] = row < r1 ? I.F[par][row] : 0;
+            Fi[rr] = row < r1 ? gld(Fp + row) : 0;
             const int B = 4 * (Fi[rr] - kTabLo);
             part[rr] = 0.f;
 #pragma unroll
             for (int k = 0; k < CPT; ++k) {
-#pragma unroll
-                for (int c = 0; c < 8; ++c) T[rr][k][c] = 0.f;
+                // T of rows past r1 or of columns past n is never read
                 if (row < r1 && own[k]) {
                     int w[8];
                     unpack8i(cur[rr][k], w);
@@ -353,34 +373,35 @@ __device__ __forceinline__ void fused_i16_body(const Inst &I, Ctl *ctl, const fl
                         float e = tab_at(tab, tab_off(p4, w[c], A[k][c], B));
                         if (SENT) e = (w[c] == SK_SENTINEL) ? 0.f : e;
                         T[rr][k][c] = e;
-                        part[rr] = fmaf(e, g[k][c], part[rr]);
+                        part[rr] = fmaf(e, gl[(k * 8 + c) * kFT + t], part[rr]);
                     }
                 }
             }
         }
 #pragma unroll
         for (int rr = 0; rr < FR; ++rr) {
-            const float v = fwsum(part[rr]);
-            if (lane == 0) red[buf][wave][rr] = v;
+            const float v = dpp_wave_sum(part[rr]);
+            if (lane == 0) red[parity][wave][rr] = v;
         }
         __syncthreads();
         float inv[FR];
 #pragma unroll
         for (int rr = 0; rr < FR; ++rr) {
             const int row = rb + rr;
-            const float S = sum16(red[buf][lane & 15][rr]);
+            const float S = dpp_sum16(red[parity][lane & 15][rr]);
             inv[rr] = 0.f;
             if (row >= r1) continue;  // uniform
+            const bool writer = t == ((row - r0) & 15) * kWave;
             if (S >= kLo && S <= kHi) {
                 inv[rr] = __builtin_amdgcn_rcpf(S);
-                if (t == 0) {
+                if (writer) {
                     // log u_i <- F_i - log S_i; r_i = exp(phi_i) S_i
                     const float l2S = flg2(S);
                     const float phin = -l2S * kLn2f;
                     const float kk = rintf(phin);
-                    I.F[par ^ 1][row] = Fi[rr] + (int)kk;
-                    I.phi[par ^ 1][row] = phin - kk;
-                    const float r = fex2(fmaf(I.phi[par][row], kL2e, l2S));
+                    gst(Fn + row, Fi[rr] + (int)kk);
+                    gst(phin_p + row, phin - kk);
+                    const float r = fex2(fmaf(gld(phip + row), kL2e, l2S));
                     resmax = fmaxf(resmax, fabsf(r - 1.f));
                 }
                 continue;
@@ -407,20 +428,20 @@ __device__ __forceinline__ void fused_i16_body(const Inst &I, Ctl *ctl, const fl
             float s2 = 0.f;
 #pragma unroll
             for (int k = 0; k < CPT; ++k) {
-#pragma unroll
-                for (int c = 0; c < 8; ++c) T[rr][k][c] = 0.f;
-                if (!own[k] || mm == INT_MIN) continue;
+                if (!own[k]) continue;
                 int w[8];
                 unpack8i(cur[rr][k], w);
 #pragma unroll
                 for (int c = 0; c < 8; ++c) {
-                    float e = tab_at(tab, tab_off(p4, w[c], A[k][c], 4 * (Fi[rr] - M - kTabLo)));
+                    float e = mm == INT_MIN
+                                  ? 0.f
+                                  : tab_at(tab, tab_off(p4, w[c], A[k][c], 4 * (Fi[rr] - M - kTabLo)));
                     if (SENT) e = (w[c] == SK_SENTINEL) ? 0.f : e;
                     T[rr][k][c] = e;
-                    s2 = fmaf(e, g[k][c], s2);
+                    s2 = fmaf(e, gl[(k * 8 + c) * kFT + t], s2);
                 }
             }
-            s2 = fwsum(s2);
+            s2 = dpp_wave_sum(s2);
             if (lane == 0) reds[wave] = s2;
             __syncthreads();
             float S2 = 0.f;
@@ -429,13 +450,13 @@ __device__ __forceinline__ void fused_i16_body(const Inst &I, Ctl *ctl, const fl
                 if (t == 0) atomicOr(&ctl->err, ERR_EMPTY_ROW);
             } else {
                 inv[rr] = __builtin_amdgcn_rcpf(S2);
-                if (t == 0) {
+                if (writer) {
                     const float l2S = flg2(S2);
                     const float phin = -l2S * kLn2f;
                     const float kk = rintf(phin);
-                    I.F[par ^ 1][row] = Fi[rr] - M + (int)kk;
-                    I.phi[par ^ 1][row] = phin - kk;
-                    const float r = fex2(fmaf(I.phi[par][row] + (float)M, kL2e, l2S));
+                    gst(Fn + row, Fi[rr] - M + (int)kk);
+                    gst(phin_p + row, phin - kk);
+                    const float r = fex2(fmaf(gld(phip + row) + (float)M, kL2e, l2S));
                     resmax = fmaxf(resmax, fabsf(r - 1.f));
                 }
             }
@@ -443,12 +464,24 @@ __device__ __forceinline__ void fused_i16_body(const Inst &I, Ctl *ctl, const fl
         }
         // B: column sums of the new row-stochastic iterate (times exp(-gam_j))
 #pragma unroll
-        for (int rr = 0; rr < FR; ++rr)
+        for (int rr = 0; rr < FR; ++rr) {
+            if (rb + rr >= r1) continue;  // uniform
 #pragma unroll
             for (int k = 0; k < CPT; ++k)
+                if (own[k]) {
 #pragma unroll
-                for (int c = 0; c < 8; ++c) acc[k][c] = fmaf(T[rr][k][c], inv[rr], acc[k][c]);
-        buf ^= 1;
+                    for (int c = 0; c < 8; ++c) acc[k][c] = fmaf(T[rr][k][c], inv[rr], acc[k][c]);
+                }
+        }
+        parity ^= 1;
+    };
+    if (r0 < r1) load_group(ba, r0);
+    for (int rb = r0; rb < r1; rb += 2 * FR) {
+        if (rb + FR < r1) load_group(bb, rb + FR);
+        process(ba, rb);
+        if (rb + FR >= r1) break;
+        if (rb + 2 * FR < r1) load_group(ba, rb + 2 * FR);
+        process(bb, rb + FR);
     }
     float *dst = I.colpart + (int64_t)blockIdx.x * n;
 #pragma unroll
@@ -456,10 +489,17 @@ __device__ __forceinline__ void fused_i16_body(const Inst &I, Ctl *ctl, const fl
         if (own[k]) {
 #pragma unroll
             for (int c = 0; c < 8; ++c)
-                if (c0[k] + c < n) dst[c0[k] + c] = acc[k][c] * g[k][c];
+                if (c0[k] + c < n) gst(dst + c0[k] + c, acc[k][c] * gl[(k * 8 + c) * kFT + t]);
         }
-    // residual slot of this workgroup (thread 0 formed every row's residual)
-    if (t == 0) I.res_slots[blockIdx.x] = resmax;
+    // residual slot of this workgroup: lane 0 of every wave formed the
+    // residuals of its rows
+    if (lane == 0) wres[wave] = resmax;
+    __syncthreads();
+    if (t == 0) {
+        float m = 0.f;
+        for (int w2 = 0; w2 < kFT / kWave; ++w2) m = fmaxf(m, wres[w2]);
+        I.res_slots[blockIdx.x] = m;
+    }
 }
 
 // Rows per group: two with 8 owned columns per thread, one with 16 (register
@@ -471,13 +511,15 @@ __global__ __launch_bounds__(kFT) void k_fused_i16(const Inst *__restrict__ inst
     __shared__ float red[2][kFT / kWave][kFR];
     __shared__ int redm[kFT / kWave];
     __shared__ float reds[kFT / kWave];
+    __shared__ float wres[kFT / kWave];
+    __shared__ float gl[CPT * 8 * kFT];
     const Inst &I = insts[inst];
     Ctl *ctl = I.ctl;
     if (ctl->state != ST_RUNNING) return;
     fill_exp_table(tab);
     __syncthreads();
-    if (ctl->sent != 0u) fused_i16_body<CPT, FR, true>(I, ctl, tab, red, redm, reds);
-    else fused_i16_body<CPT, FR, false>(I, ctl, tab, red, redm, reds);
+    if (ctl->sent != 0u) fused_i16_body<CPT, FR, true>(I, ctl, tab, red, redm, reds, wres, gl);
+    else fused_i16_body<CPT, FR, false>(I, ctl, tab, red, redm, reds, wres, gl);
 }
 
 template <int ST>

@@ -1,9 +1,10 @@
 """GPU parity: libsk (HIP, through the C ABI) against the FP64 oracle.
 
-Tolerances. The sweeps form p*w_ij + F_i + G_j exactly and round only the
-fractions (|.| <= 1/2), the exp2/log2 hardware approximations (~1 ulp) and
-the FP32 accumulation of a row or column (<= n terms, accumulated 8 at a time
-per lane then across 64 lanes). Per sweep this gives a relative error on a
+Tolerances. The sweeps form the integer exponent p*w_ij + F_i + G_j exactly,
+read exp of it from a correctly rounded table (0.5 ulp), multiply by the
+fraction factors exp(phi_i) or exp(gam_j) (hardware exp2 of a value below 1
+in magnitude, ~1 ulp), and accumulate a row or column in FP32 (<= n terms, 8
+at a time per lane, then across lanes and fixed slots). Per sweep this gives a relative error on a
 row or column sum of a few 1e-7 (far below 1e-5 even with n = 16384 terms
 in the worst case of ~2.4e-6), hence an error in log u_i or log v_j of a few
 1e-7 per step. Over k iterations of a contraction these errors stay bounded by

@@ -134,3 +134,25 @@ def test_planted_4096_full_path(ctx):
     assert out["weight"] == 1050 * n  # closed form of the planted optimum
     assert (out["perm"] == sigma).all()
     assert out["report"]["optimal_proved"] == 1
+
+
+def test_euclidean_workload(ctx):
+    """Euclidean random assignment (2n points in the unit cube, a_ij =
+    exp(-d(x_i, y_j))) with distances quantised at 1/1000: same optimal
+    weight and proof as the oracle; the permutation's real total distance is
+    within n / 1000 of the real-valued optimum (each quantised weight is off
+    by at most 1/2000)."""
+    from scipy.optimize import linear_sum_assignment
+    n = 256
+    W, x, y = skgen.euclidean(n, 0)
+    ladder, tol, cap, t = [1], 1e-5, 20000, 1e-4
+    want, status = oracle.adaptive(W, ladder, tol, cap, t, math.e)
+    assert status == "ok"
+    prm = sk.make_params(ladder, tol=tol, max_iters=cap, threshold=t, opt_ratio=math.e)
+    out = ctx.solve(dev(W), prm)
+    assert out["status"] == sk.SK_OK
+    assert out["weight"] == want.weight == oracle.optimum_int(W)[1]
+    assert out["report"]["optimal_proved"] == 1
+    d = np.sqrt(((x[:, None, :] - y[None, :, :]) ** 2).sum(axis=2))
+    r, c = linear_sum_assignment(d)
+    assert d[np.arange(n), out["perm"]].sum() - d[r, c].sum() <= n / 1000.0
