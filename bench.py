@@ -28,8 +28,9 @@ uniform 0..1000; sk_scale_batch (one launch per sweep across all instances)
 against 512 sequential sk_scale calls with the same parameters.
 
 euclidean: the Euclidean random assignment workload at n = 1000 (2n points
-uniform in the unit cube, a_ij = exp(-d), distances quantised at 1/1000)
-through sk_solve with opt_ratio e: gamma, p, iterations, kept entries.
+uniform in the unit cube, a_ij = exp(-d), distances quantised at 1/100)
+through sk_solve with the paper's required ratio 2: gamma (paper's units),
+p, iterations, kept entries.
 
 served: 1000 Poisson arrivals of planted instances with n log-uniform on
 [64, 8192], tolerance 1e-5, at offered loads of 0.5, 0.9 and 1.5 times the
@@ -330,14 +331,18 @@ def served_leg(sk, torch, n_requests, loads, seed=2):
             "fifo_capacity_solves_per_s": round(mu, 2), "loads": per_load}
 
 
-def euclidean_leg(sk, torch, n=1000, seed=0):
+def euclidean_leg(sk, torch, n=1000, seed=0, scale=100):
     """The Euclidean random assignment workload at the paper's size: 2n points
-    uniform in the unit cube, a_ij = exp(-d), distances quantised at 1/1000,
-    through sk_solve (Algorithm 1 with opt_ratio e)."""
+    uniform in the unit cube, a_ij = exp(-d), log-weights -d quantised at
+    1/scale (so W = scale log a and p = 1 here is the paper's prescaled
+    p = w_max - w_min), through sk_solve with the paper's required ratio 2
+    (2^scale in these units) over the ladder 1, 2. gamma is reported in the
+    paper's units, exp(log gamma / scale)."""
     import math
     import skgen
-    W, _, _ = skgen.euclidean(n, seed)
-    prm = sk.make_params([1], tol=1e-5, max_iters=20000, threshold=1e-4, opt_ratio=math.e)
+    W, _, _ = skgen.euclidean(n, seed, scale=scale)
+    prm = sk.make_params([1, 2], tol=1e-5, max_iters=20000, threshold=1e-4,
+                         opt_ratio=2.0 ** scale)
     ctx = sk.Context(0)
     Wd = torch.from_numpy(W).cuda()
     ctx.solve(Wd, prm)  # warm-up
@@ -347,9 +352,11 @@ def euclidean_leg(sk, torch, n=1000, seed=0):
     el = time.perf_counter() - t0
     r = out["report"]
     ctx.close()
-    return {"n": n, "p": r["p_final"], "gamma": round(math.exp(r["log_gamma"]), 4),
+    wr = int(W.max()) - int(W.min())
+    return {"n": n, "scale": scale, "p": r["p_final"], "p_prescaled": r["p_final"] * wr,
+            "gamma": round(math.exp(r["log_gamma"] / scale), 4),
             "iterations": r["iters_total"], "kept_percent": round(100.0 * r["nnz_kept"] / n / n, 3),
-            "optimal_proved": bool(r["optimal_proved"]), "seconds": round(el, 4)}
+            "status": out["status"], "seconds": round(el, 4)}
 
 
 def cpu_baseline(W, p, seconds):

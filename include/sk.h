@@ -82,7 +82,16 @@ typedef enum {
  *                  launch per iteration that forms the row sums and the new
  *                  column sums from one read of the matrix (single instance,
  *                  n % 8 == 0 for int16 W). Both give the same iterates up to
- *                  FP32 summation order. */
+ *                  FP32 summation order.
+ *   deform_a     : 0 = continuation over the ladder (stages at fixed p).
+ *                  > 0 = the deformed Sinkhorn iteration (Section 3.2,
+ *                  schedule p_m = a log(m + 1) of Theorem
+ *                  logconvergencepositive): one stage in which iteration m
+ *                  (from 1) runs at p_m = round(deform_a * ln(m + 1)) kept in
+ *                  [p_ladder[0], p_ladder[n_p - 1]], with u and v carried
+ *                  unscaled from one p to the next; it stops at the first
+ *                  iterate computed at the last p whose residual is below
+ *                  tol, or at max_iters_per_stage. int16 W only. */
 typedef struct {
     int32_t p_ladder[SK_MAX_LADDER];
     int32_t n_p;
@@ -94,6 +103,7 @@ typedef struct {
     double opt_ratio;
     int32_t warm_start;
     int32_t fused;
+    double deform_a;
 } sk_params;
 
 /* Per-run report. Residuals are max_i |r_i - 1| (rows) and max_j |c_j - 1|

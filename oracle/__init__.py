@@ -23,6 +23,7 @@ Every function cites the passage it follows; parity status of each part:
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 from dataclasses import dataclass, field
 
@@ -322,3 +323,118 @@ def adaptive(W, ladder, eps, max_iters, t, opt_ratio):
         return None, "infeasible"
     best.extra["evaluated"] = evaluated
     return best, "ratio"
+
+
+def deformed_p(a, p_min, p_max, m):
+    """p of iteration m (from 1) of the deformed iteration: the schedule
+    p_m = a log(m + 1) of Theorem logconvergencepositive, rounded to an
+    integer (half to even) and kept in [p_min, p_max]."""
+    return int(min(p_max, max(p_min, round(a * math.log(m + 1)))))
+
+
+def deformed(B, a, p_min, p_max, eps, max_iters):
+    """Deformed Sinkhorn iteration (Section 3.2): v_0 = 1 and, for m = 1, 2, ...,
+    u_m = I(A^(p_m) v_{m-1}), v_m = I(A^(p_m)T u_m) with u and v carried as they
+    are from one p to the next (no rescaling). Stops after iteration m when
+    p_m = p_max and the column-stochastic iterate W_m has max_i |r_i - 1| < eps
+    at that p, or after max_iters iterations.
+    Returns (log u, log v, iterations, p of the last iteration, residual)."""
+    n = B.shape[0]
+    logu, logv = np.zeros(n), np.zeros(n)
+    res = math.inf
+    m = 0
+    while m < max_iters:
+        m += 1
+        p = deformed_p(a, p_min, p_max, m)
+        logu = p * row_step(B, p, logv / p)
+        logv = p * col_step(B, p, logu / p)
+        if p == p_max:
+            res = row_residual(B, p, logu / p, logv / p)
+            if res < eps:
+                break
+    return logu, logv, m, deformed_p(a, p_min, p_max, m), res
+
+
+def newton(B, p, tol, max_products, ubar=None, vbar=None, lo=0.1, hi=3.0, eta_max=0.1,
+           g=0.9):
+    """Newton iteration for the diagonal scaling of A^(p) (Section 5.2, the
+    method of Knight and Ruiz cited there).
+
+    X = diag(u) A^(p) diag(v) for the starting scalings (u = v = 1 unless
+    given) and S = [[0, X], [X^T, 0]] (the symmetric embedding of a
+    nonsymmetric matrix). Find x > 0 with x o (S x) = 1. A Newton step for
+    x o (S x) - 1 = 0, written multiplicatively as x <- x o y, solves
+    (D(x) S D(x) + D(v)) y = 1 + v, v = x o (S x), by conjugate gradients
+    preconditioned with D(v) and started at y = 1 (residual 1 - v); the matrix
+    is symmetric positive semidefinite and the system consistent when A has
+    support. A CG step that would take y to or past lo (or hi) is cut at that
+    bound and ends the inner solve. The inner solve stops once the
+    preconditioned residual falls below max(eta^2 |1 - v|^2, tol^2), with the
+    forcing term eta updated after every outer step from the ratio of
+    successive residuals (at most eta_max, at least tol / (2 |1 - v|)). The
+    outer loop stops when |1 - v|_2 <= tol or after max_products products
+    with S. Returns (ubar, vbar, outer steps, products with S, max |row or
+    column sum - 1| of the result)."""
+    n = B.shape[0]
+    ubar = np.zeros(n) if ubar is None else np.array(ubar, dtype=np.float64)
+    vbar = np.zeros(n) if vbar is None else np.array(vbar, dtype=np.float64)
+    X = scaled_matrix(B, p, ubar, vbar)
+
+    def Sx(z):
+        return np.concatenate([X @ z[n:], X.T @ z[:n]])
+
+    rt = tol * tol
+    x = np.ones(2 * n)
+    v = x * Sx(x)
+    r = 1.0 - v
+    rout = float(r @ r)
+    rold = rout
+    products, outer, eta = 1, 0, eta_max
+    while rout > rt and products < max_products:
+        outer += 1
+        y = np.ones(2 * n)
+        inner_tol = max(eta * eta * rout, rt)
+        rho, rho_prev = rout, 1.0
+        d = z = None
+        while rho > inner_tol and products < max_products:
+            if d is None:
+                z = r / v
+                rho = float(r @ z)
+                d = z.copy()
+            else:
+                d = z + (rho / rho_prev) * d
+            w = x * Sx(x * d) + v * d
+            products += 1
+            alpha = rho / float(d @ w)
+            step = alpha * d
+            ynew = y + step
+            if ynew.min() <= lo:
+                neg = step < 0
+                y = y + ((lo - y[neg]) / step[neg]).min() * step
+                break
+            if ynew.max() >= hi:
+                over = ynew > hi
+                y = y + ((hi - y[over]) / step[over]).min() * step
+                break
+            y = ynew
+            r = r - alpha * w
+            rho_prev = rho
+            z = r / v
+            rho = float(r @ z)
+        x = x * y
+        v = x * Sx(x)
+        products += 1
+        r = 1.0 - v
+        rout = float(r @ r)
+        # forcing term for the next inner solve
+        ratio, rold = rout / rold, rout
+        eta_prev = eta
+        eta = g * ratio
+        if g * eta_prev * eta_prev > 0.1:
+            eta = max(eta, g * eta_prev * eta_prev)
+        eta = max(min(eta, eta_max), 0.5 * tol / max(math.sqrt(rout), 1e-300))
+    rows, cols = x[:n], x[n:]
+    ub = ubar + np.log(rows) / p
+    vb = vbar + np.log(cols) / p
+    rs, cs = sums(B, p, ub, vb)
+    return ub, vb, outer, products, max(np.abs(rs - 1).max(), np.abs(cs - 1).max())

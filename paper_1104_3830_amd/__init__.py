@@ -43,7 +43,8 @@ class Params(ctypes.Structure):
                 ("tol", ctypes.c_double), ("max_iters_per_stage", ctypes.c_int64),
                 ("check_every", ctypes.c_int32), ("threshold", ctypes.c_double),
                 ("storage", ctypes.c_int32), ("opt_ratio", ctypes.c_double),
-                ("warm_start", ctypes.c_int32), ("fused", ctypes.c_int32)]
+                ("warm_start", ctypes.c_int32), ("fused", ctypes.c_int32),
+                ("deform_a", ctypes.c_double)]
 
 
 class Report(ctypes.Structure):
@@ -147,7 +148,8 @@ def load_tile_table(path):
 
 
 def make_params(ladder, tol=1e-5, max_iters=20000, check_every=32, threshold=1e-4,
-                storage="i16", opt_ratio=0.0, warm_start=False, fused=False) -> Params:
+                storage="i16", opt_ratio=0.0, warm_start=False, fused=False,
+                deform_a=0.0) -> Params:
     p = Params()
     ladder = [int(x) for x in ladder]
     if not 1 <= len(ladder) <= MAX_LADDER:
@@ -163,6 +165,7 @@ def make_params(ladder, tol=1e-5, max_iters=20000, check_every=32, threshold=1e-
     p.opt_ratio = float(opt_ratio)
     p.warm_start = 1 if warm_start else 0
     p.fused = 1 if fused else 0
+    p.deform_a = float(deform_a)
     return p
 
 

@@ -68,6 +68,7 @@ struct Inst {
     int32_t storage;
     int32_t kpitch;
     int32_t fused;          // single-pass iteration (colpart holds kFusedSlots rows)
+    double deform_a;        // > 0: deformed iteration, p_m = round(a ln(m + 1)) in [ladder[0], ladder[n_p - 1]]
     int32_t fused_grid;
     int32_t ncolslots;      // rows of colpart in use: nseg (sweeps) or fused_grid (single pass)
     int32_t pause;          // end every stage in ST_STAGE_END (the host advances p)
@@ -77,6 +78,13 @@ struct Inst {
     float *drift_slots;     // stored K: per row unit max |log2 a_i|
     float *rres;            // [n] |r_i - 1| from the log-domain row sweep
 };
+
+// p of iteration m (from 1) of the deformed iteration.
+__device__ __forceinline__ int deform_p(const Inst &I, int64_t m) {
+    const double v = rint(I.deform_a * log((double)(m + 1)));
+    const double lo = (double)I.ladder[0], hi = (double)I.ladder[I.n_p - 1];
+    return (int)fmin(hi, fmax(lo, v));
+}
 
 // Loads through a global-address-space pointer, so the compiler emits
 // global_load (counted by vmcnt only) instead of flat_load (also counted by

@@ -119,7 +119,7 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_init(const Inst *__restri
             if (mx == SK_SENTINEL) atomicOr(&I.ctl->err, ERR_EMPTY_ROW);
             if (sent) atomicOr(&I.ctl->sent, 1u);
             if (cold) {
-                I.F[0][row] = (mx == SK_SENTINEL) ? 0 : -I.ladder[0] * mx;
+                I.F[0][row] = (mx == SK_SENTINEL) ? 0 : -I.ctl->p * mx;
                 I.phi[0][row] = 0.f;
             }
         }
@@ -159,7 +159,22 @@ __device__ __forceinline__ float chunk8(const int4 v, int q, int n8, int p4, int
 #define SK_ROW_UNROLL 2
 #endif
 #ifndef SK_COL_UNROLL
-#define SK_COL_UNROLL 2
+#define SK_COL_UNROLL 1
+#endif
+// Two rows per wave in the row sweep (build-time switch) and the chunks in
+// flight per row when it does.
+#ifndef SK_ROW_PAIR
+#define SK_ROW_PAIR 0
+#endif
+#ifndef SK_PAIR_UNROLL
+#define SK_PAIR_UNROLL 1
+#endif
+// Software pipelining of the sweeps' loads (build-time switch).
+#ifndef SK_ROW_PIPE
+#define SK_ROW_PIPE 0
+#endif
+#ifndef SK_COL_PIPE
+#define SK_COL_PIPE 1
 #endif
 
 // Row partial sum for one lane: chunks lane*8 + k*512, SK_ROW_UNROLL 16-byte
@@ -172,6 +187,35 @@ __device__ __forceinline__ float row_partial_v8(const int16_t *__restrict__ wr, 
     const int n8 = n >> 3;
     float acc = 0.f;
     int j0 = lane * 8;
+#if SK_ROW_PIPE
+    // two register buffers (see the column sweep); chunks are still added in order
+    auto ld = [&](int4 (&v)[U], int jj) {
+#pragma unroll
+        for (int k = 0; k < U; ++k) v[k] = gload(reinterpret_cast<const int4 *>(wr + jj + k * 512));
+    };
+    auto use = [&](const int4 (&v)[U], int jj) {
+#pragma unroll
+        for (int k = 0; k < U; ++k) acc += chunk8<SENT>(v[k], (jj >> 3) + 64 * k, n8, p4, B, cp, tab);
+    };
+    if (j0 + (U - 1) * 512 < n) {
+        int4 va[U], vb[U];
+        ld(va, j0);
+        for (;;) {
+            const int j2 = j0 + U * 512;
+            const bool more = j2 + (U - 1) * 512 < n;
+            if (more) ld(vb, j2);
+            use(va, j0);
+            j0 = j2;
+            if (!more) break;
+            const int j3 = j0 + U * 512;
+            const bool more2 = j3 + (U - 1) * 512 < n;
+            if (more2) ld(va, j3);
+            use(vb, j0);
+            j0 = j3;
+            if (!more2) break;
+        }
+    }
+#else
     for (; j0 + (U - 1) * 512 < n; j0 += U * 512) {
         int4 v[U];
 #pragma unroll
@@ -180,6 +224,7 @@ __device__ __forceinline__ float row_partial_v8(const int16_t *__restrict__ wr, 
 #pragma unroll
         for (int k = 0; k < U; ++k) acc += chunk8<SENT>(v[k], q + 64 * k, n8, p4, B, cp, tab);
     }
+#endif
     for (; j0 < n; j0 += 512) {
         const int4 v = gload(reinterpret_cast<const int4 *>(wr + j0));
         acc += chunk8<SENT>(v, j0 >> 3, n8, p4, B, cp, tab);
@@ -234,20 +279,17 @@ __device__ __forceinline__ int row_max_v1(const int16_t *__restrict__ wr, int n,
     return m;
 }
 
+// Completes the row step of `row` from its sum S relative to the previous
+// iterate (shift 0): the exact max-shifted recompute if S left the safe
+// range, then the new potentials and the residual.
 template <bool SENT, bool V8>
-__device__ __forceinline__ void row_step_one(const Inst &I, int row, int par, int lane,
-                                             const ColPot *__restrict__ cp,
-                                             const float *__restrict__ tab) {
+__device__ __forceinline__ void row_finish(const Inst &I, int row, int par, int lane, int Fi,
+                                           float S, const ColPot *__restrict__ cp,
+                                           const float *__restrict__ tab) {
     const int n = I.n;
     const int16_t *wr = I.W + (int64_t)row * I.pitch;
-    const int Fi = I.F[par][row];
-    const float phi = I.phi[par][row];
     const int p4 = 4 * I.ctl->p;
-    // S_i relative to the previous iterate: shift M = 0
     int M = 0;
-    float S = V8 ? row_partial_v8<SENT>(wr, n, p4, 4 * (Fi - kTabLo), cp, tab, lane)
-                 : row_partial_v1<SENT>(wr, n, p4, 4 * (Fi - kTabLo), cp, tab, lane);
-    S = wave_sum(S);
     if (!(S >= kSafeLo && S <= kSafeHi)) {
         // exact max-shift (Section 4.1.2): M = max_j (p w_ij + F_i + G_j)
         int m4 = V8 ? row_max_v8<SENT>(wr, n, p4, 4 * Fi, cp, lane)
@@ -265,6 +307,7 @@ __device__ __forceinline__ void row_step_one(const Inst &I, int row, int par, in
     }
     if (lane == 0) {
         // log u_i <- F_i - M - log S
+        const float phi = I.phi[par][row];
         const float l2S = lg2(S);
         const float phin = -l2S * kLn2;
         const float k = rintf(phin);
@@ -274,6 +317,100 @@ __device__ __forceinline__ void row_step_one(const Inst &I, int row, int par, in
         const float r = ex2(fmaf(phi + (float)M, kLog2e, l2S));
         I.rres[row] = fabsf(r - 1.f);
     }
+}
+
+template <bool SENT, bool V8>
+__device__ __forceinline__ void row_step_one(const Inst &I, int row, int par, int lane,
+                                             const ColPot *__restrict__ cp,
+                                             const float *__restrict__ tab) {
+    const int n = I.n;
+    const int16_t *wr = I.W + (int64_t)row * I.pitch;
+    const int Fi = I.F[par][row];
+    const int p4 = 4 * I.ctl->p;
+    float S = V8 ? row_partial_v8<SENT>(wr, n, p4, 4 * (Fi - kTabLo), cp, tab, lane)
+                 : row_partial_v1<SENT>(wr, n, p4, 4 * (Fi - kTabLo), cp, tab, lane);
+    S = wave_sum(S);
+    row_finish<SENT, V8>(I, row, par, lane, Fi, S, cp, tab);
+}
+
+// Two rows in one pass over the columns: each column's (4 G_j, exp(gam_j))
+// is read from LDS once for both rows. Each row's chunks are added in the
+// same order as in row_partial_v8, so a row's sum does not depend on whether
+// it is paired.
+template <bool SENT>
+__device__ __forceinline__ void chunk8x2(const int4 v0, const int4 v1, int q, int n8, int p4,
+                                         int B0, int B1, const ColPot *__restrict__ cp,
+                                         const float *__restrict__ tab, float &s0, float &s1) {
+    int w0[8], w1[8];
+    unpack8i(v0, w0);
+    unpack8i(v1, w1);
+    s0 = 0.f;
+    s1 = 0.f;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const ColPot k = cp[c * n8 + q];
+        float e0 = tab_at(tab, tab_off(p4, w0[c], k.a, B0));
+        float e1 = tab_at(tab, tab_off(p4, w1[c], k.a, B1));
+        if (SENT) {
+            e0 = (w0[c] == SK_SENTINEL) ? 0.f : e0;
+            e1 = (w1[c] == SK_SENTINEL) ? 0.f : e1;
+        }
+        s0 = fmaf(e0, k.g, s0);
+        s1 = fmaf(e1, k.g, s1);
+    }
+}
+
+template <bool SENT>
+__device__ __forceinline__ void row_partial2_v8(const int16_t *__restrict__ wr0,
+                                                const int16_t *__restrict__ wr1, int n, int p4,
+                                                int B0, int B1, const ColPot *__restrict__ cp,
+                                                const float *__restrict__ tab, int lane,
+                                                float &acc0, float &acc1) {
+    constexpr int U = SK_PAIR_UNROLL;
+    const int n8 = n >> 3;
+    acc0 = 0.f;
+    acc1 = 0.f;
+    int j0 = lane * 8;
+    for (; j0 + (U - 1) * 512 < n; j0 += U * 512) {
+        int4 v0[U], v1[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            v0[k] = gload(reinterpret_cast<const int4 *>(wr0 + j0 + k * 512));
+            v1[k] = gload(reinterpret_cast<const int4 *>(wr1 + j0 + k * 512));
+        }
+        const int q = j0 >> 3;
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            float s0, s1;
+            chunk8x2<SENT>(v0[k], v1[k], q + 64 * k, n8, p4, B0, B1, cp, tab, s0, s1);
+            acc0 += s0;
+            acc1 += s1;
+        }
+    }
+    for (; j0 < n; j0 += 512) {
+        float s0, s1;
+        chunk8x2<SENT>(gload(reinterpret_cast<const int4 *>(wr0 + j0)),
+                       gload(reinterpret_cast<const int4 *>(wr1 + j0)), j0 >> 3, n8, p4, B0, B1, cp,
+                       tab, s0, s1);
+        acc0 += s0;
+        acc1 += s1;
+    }
+}
+
+template <bool SENT>
+__device__ __forceinline__ void row_step_pair(const Inst &I, int ra, int rb, int par, int lane,
+                                              const ColPot *__restrict__ cp,
+                                              const float *__restrict__ tab) {
+    const int n = I.n;
+    const int Fa = I.F[par][ra], Fb = I.F[par][rb];
+    const int p4 = 4 * I.ctl->p;
+    float Sa, Sb;
+    row_partial2_v8<SENT>(I.W + (int64_t)ra * I.pitch, I.W + (int64_t)rb * I.pitch, n, p4,
+                          4 * (Fa - kTabLo), 4 * (Fb - kTabLo), cp, tab, lane, Sa, Sb);
+    Sa = wave_sum(Sa);
+    Sb = wave_sum(Sb);
+    row_finish<SENT, true>(I, ra, par, lane, Fa, Sa, cp, tab);
+    row_finish<SENT, true>(I, rb, par, lane, Fb, Sb, cp, tab);
 }
 
 // Waves run their rows independently: the only barrier is the restaging of
@@ -289,11 +426,14 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_row_sweep(const Inst *__r
     unit_range(nunits, u0, u1);
     fill_exp_table(tab);
     int cur = -1;
-    for (int u = u0; u < u1; ++u) {
+    for (int u = u0; u < u1;) {
         const RowUnit un = units[u];
         const Inst &I = insts[un.inst];
         Ctl *ctl = I.ctl;
-        if (ctl->state != ST_RUNNING) continue;
+        if (ctl->state != ST_RUNNING) {
+            ++u;
+            continue;
+        }
         const int n = I.n;
         const int iter = ctl->iter;
         if (un.inst != cur) {
@@ -308,18 +448,25 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_row_sweep(const Inst *__r
             __syncthreads();
             cur = un.inst;
         }
-        const int row = un.row0 + wave;
-        if (row < n) {
-            const int par = iter & 1;
-            const bool sent = ctl->sent != 0u;
+        const int par = iter & 1;
+        const bool sent = ctl->sent != 0u;
+        const int ra = un.row0 + wave;
+        // the next unit of the same instance is done in the same pass
+        const bool pair = SK_ROW_PAIR && I.vec8 && u + 1 < u1 && units[u + 1].inst == un.inst;
+        const int rb = pair ? units[u + 1].row0 + wave : n;
+        if (rb < n) {
+            if (sent) row_step_pair<true>(I, ra, rb, par, lane, lds_cp, tab);
+            else row_step_pair<false>(I, ra, rb, par, lane, lds_cp, tab);
+        } else if (ra < n) {
             if (I.vec8) {
-                if (sent) row_step_one<true, true>(I, row, par, lane, lds_cp, tab);
-                else row_step_one<false, true>(I, row, par, lane, lds_cp, tab);
+                if (sent) row_step_one<true, true>(I, ra, par, lane, lds_cp, tab);
+                else row_step_one<false, true>(I, ra, par, lane, lds_cp, tab);
             } else {
-                if (sent) row_step_one<true, false>(I, row, par, lane, lds_cp, tab);
-                else row_step_one<false, false>(I, row, par, lane, lds_cp, tab);
+                if (sent) row_step_one<true, false>(I, ra, par, lane, lds_cp, tab);
+                else row_step_one<false, false>(I, ra, par, lane, lds_cp, tab);
             }
         }
+        u += pair ? 2 : 1;
     }
 }
 
@@ -330,9 +477,16 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_row_sweep(const Inst *__r
 // partial sums are combined through LDS in a fixed order and written to the
 // fixed slot colpart[seg][j], which the finalise kernel reduces in slot order.
 
+// The deformed iteration may stop only at an iterate computed at the last p
+// (its residual is then measured at that p too: the schedule stays there).
+__device__ __forceinline__ bool deform_settled(const Inst &I, const Ctl *ctl) {
+    if (I.deform_a <= 0.0) return true;
+    return deform_p(I, ctl->iter) == I.ladder[I.n_p - 1];
+}
+
 __device__ __forceinline__ bool stage_converged(const Inst &I, const Ctl *ctl) {
     const float res = __uint_as_float(ctl->res_bits);
-    return ctl->iter >= 1 && res < I.tol;
+    return ctl->iter >= 1 && res < I.tol && deform_settled(I, ctl);
 }
 
 // Row data of the column sweep: b = 4 (F_i - kTabLo), r = exp(phi_i).
@@ -370,6 +524,38 @@ __device__ __forceinline__ void col_partial(const Inst &I, int tile, int r0, int
         int r = r0 + wave;
         constexpr int S = kColWaves;
         constexpr int U = SK_COL_UNROLL;
+#if SK_COL_PIPE
+        // two register buffers: the next U rows are requested before the
+        // current U are used, so loads stay in flight during the arithmetic
+        // (rows are still added in order)
+        auto ld = [&](int4 (&v)[U], int rr) {
+#pragma unroll
+            for (int k = 0; k < U; ++k)
+                v[k] = gload(reinterpret_cast<const int4 *>(base + (int64_t)(rr + k * S) * pitch));
+        };
+        auto use = [&](const int4 (&v)[U], int rr) {
+#pragma unroll
+            for (int k = 0; k < U; ++k) body(v[k], rowpot[rr + k * S - r0]);
+        };
+        if (r + (U - 1) * S < r1) {
+            int4 va[U], vb[U];
+            ld(va, r);
+            for (;;) {
+                const int r2 = r + U * S;
+                const bool more = r2 + (U - 1) * S < r1;
+                if (more) ld(vb, r2);
+                use(va, r);
+                r = r2;
+                if (!more) break;
+                const int r3 = r + U * S;
+                const bool more2 = r3 + (U - 1) * S < r1;
+                if (more2) ld(va, r3);
+                use(vb, r);
+                r = r3;
+                if (!more2) break;
+            }
+        }
+#else
         for (; r + (U - 1) * S < r1; r += U * S) {
             int4 v[U];
 #pragma unroll
@@ -378,6 +564,7 @@ __device__ __forceinline__ void col_partial(const Inst &I, int tile, int r0, int
 #pragma unroll
             for (int k = 0; k < U; ++k) body(v[k], rowpot[r + k * S - r0]);
         }
+#endif
         for (; r < r1; r += S) body(gload(reinterpret_cast<const int4 *>(base + (int64_t)r * pitch)),
                                     rowpot[r - r0]);
     } else {
@@ -510,7 +697,7 @@ __global__ __launch_bounds__(256) void k_col_finalize(const Inst *__restrict__ i
             __syncthreads();
         }
         const float res = rmax[0];
-        const bool conv = ctl->iter >= 1 && res < I.tol;
+        const bool conv = ctl->iter >= 1 && res < I.tol && deform_settled(I, ctl);
         if (un.group == 0 && t == 0) {
             ctl->res_bits = __float_as_uint(res);
             if (kpath && dmax[0] > 0.f) atomicMax(&ctl->drift_bits, __float_as_uint(dmax[0]));
@@ -595,6 +782,12 @@ __device__ void stage_advance(const Inst &I, Ctl *ctl, int par) {
 // next p and recompute K; so does an instance whose host evaluates every
 // stage (certificate, reduced matrix, ratio) before raising p.
 __device__ void end_stage(const Inst &I, Ctl *ctl, int par) {
+    if (I.deform_a > 0.0) {
+        // the deformed iteration is a single stage
+        __syncthreads();
+        if (threadIdx.x == 0) ctl->state = ST_DONE;
+        return;
+    }
     if (I.storage == SK_W_I16 && !I.pause) {
         stage_advance(I, ctl, par);
     } else {
@@ -691,6 +884,9 @@ __global__ __launch_bounds__(256) void k_iter_end(const Inst *__restrict__ insts
     if ((int64_t)(iter + 1) >= I.max_iters) {
         if (threadIdx.x == 0) ctl->capped += 1;
         end_stage(I, ctl, npar);
+    } else if (I.deform_a > 0.0 && threadIdx.x == 0) {
+        // deformed iteration: the next iteration's p, potentials unscaled
+        ctl->p = deform_p(I, iter + 2);
     }
 }
 
@@ -1014,7 +1210,7 @@ __global__ __launch_bounds__(256) void k_reset_ctl(const Inst *__restrict__ inst
             Ctl c;
             memset(&c, 0, sizeof c);
             c.state = ST_RUNNING;
-            c.p = I.ladder[0];
+            c.p = I.deform_a > 0.0 ? deform_p(I, 1) : I.ladder[0];
             c.last_res = INFINITY;
             *I.ctl = c;
         }

@@ -281,6 +281,10 @@ sk_status sk::check_params(sk_ctx *ctx, const sk_params *p) {
     if (!(p->tol >= 0.0)) return fail(ctx, SK_EINVAL, "tol must be >= 0");
     if (p->max_iters_per_stage < 1) return fail(ctx, SK_EINVAL, "max_iters_per_stage must be >= 1");
     if (p->storage < SK_W_I16 || p->storage > SK_K_F32) return fail(ctx, SK_EINVAL, "bad storage");
+    if (!(p->deform_a >= 0.0) || p->deform_a > 1e6)
+        return fail(ctx, SK_EINVAL, "deform_a must be in [0, 1e6]");
+    if (p->deform_a > 0.0 && p->storage != SK_W_I16)
+        return fail(ctx, SK_EINVAL, "the deformed iteration sweeps int16 W");
     return SK_OK;
 }
 
@@ -305,6 +309,7 @@ bool sk::carve_instance(Bump &bump, const int16_t *W, int64_t pitch, int32_t nn,
     I.max_iters = prm->max_iters_per_stage;
     I.storage = prm->storage;
     I.fused = prm->fused ? 1 : 0;
+    I.deform_a = prm->deform_a > 0.0 ? prm->deform_a : 0.0;
     I.fused_grid = std::min(kFusedSlots, std::max(1, nn / 2));
     for (int b = 0; b < 2; ++b) {
         I.F[b] = bump.take<int32_t>(nn);

@@ -349,3 +349,40 @@ def test_fused_cold_start_exact_shift(ctx):
     Lg, Lo = logx(B, p, ub_g, vb_g), logx(B, p, ub_o, vb_o)
     sig = Lo > np.log(1e-6)
     assert np.abs(Lg - Lo)[sig].max() < 1e-4
+
+
+# ---------------------------------------------------------------- deformed iteration
+
+@pytest.mark.parametrize("n,a,pmax,iters", [(257, 2.0, 8, 40), (1024, 3.0, 16, 60), (64, 4.0, 32, 300)])
+def test_deformed_fixed_iterations_match_oracle(ctx, n, a, pmax, iters):
+    """Deformed iteration (p_m = round(a ln(m + 1)) in [1, pmax], u and v carried
+    unscaled), exactly `iters` iterations: X from the GPU potentials matches
+    the oracle's entry by entry, at the same final p."""
+    W = skgen.uniform_weights(n, 0, 100, seed=n + 11)
+    B = oracle.log_weights(W)
+    prm = sk.make_params([1, pmax], tol=0.0, max_iters=iters, check_every=16, deform_a=a)
+    res = ctx.scale(dev(W), prm)
+    assert res.status == sk.SK_ENOCONV
+    assert res.report["iters_total"] == iters
+    lu_o, lv_o, m, p, _ = oracle.deformed(B, a, 1, pmax, 0.0, iters)
+    assert m == iters and res.report["p_final"] == p
+    lu, lv = sk.split_potentials(res.potentials, n)
+    Xg = p * B + lu[:, None] + lv[None, :]
+    Xo = p * B + lu_o[:, None] + lv_o[None, :]
+    big = Xo > np.log(1e-6)
+    assert np.abs(Xg - Xo)[big].max() < 1e-4
+
+
+def test_deformed_planted_solve(ctx):
+    """Deformed iteration to p = 16 on a planted instance: the stopping
+    iteration is the oracle's, and the reduced matrix gives the planted
+    optimum (closed form 1050 n)."""
+    n = 1024
+    W, sigma = skgen.planted(n, seed=5)
+    B = oracle.log_weights(W)
+    prm = sk.make_params([1, 16], tol=1e-6, max_iters=5000, threshold=1e-4, deform_a=3.0)
+    out = ctx.solve(dev(W), prm)
+    _, _, m, p, res = oracle.deformed(B, 3.0, 1, 16, 1e-6, 5000)
+    assert out["status"] == sk.SK_OK and out["report"]["p_final"] == p == 16
+    assert out["report"]["iters_total"] == m
+    assert out["weight"] == 1050 * n and (out["perm"] == sigma).all()

@@ -406,3 +406,121 @@ def test_adaptive_lowers_threshold_at_last_stage():
     assert status == "ok" and s.extra["t"] < 0.99
     assert s.extra["t"] == pytest.approx(0.99 * 10.0 ** round(math.log10(s.extra["t"] / 0.99)))
     assert s.weight == oracle.optimum_int(W)[1]
+
+
+# ---------------------------------------------------------------- deformed iteration
+
+def test_deformed_constant_p_reproduces_worked_example():
+    """With p_m held at 10 the deformed iteration is Sinkhorn iteration on
+    A^(10): it stops at the same iteration (106) with the matrix printed in
+    Section 2.3, to within half a unit of its 7th decimal."""
+    fx = fixtures.load("example_3x3.txt")
+    B = oracle.log_of(fx["A"])
+    lu, lv, m, p, res = oracle.deformed(B, 1.0, 10, 10, 1e-4, 10**6)
+    X = np.exp(p * B + lu[:, None] + lv[None, :])
+    assert (m, p) == (106, 10) and res < 1e-4
+    assert np.abs(X - fx["X"]).max() <= 5e-8
+
+
+def _deformed_state(B, a, pmin, pmax, m):
+    lu, lv, m2, p, _ = oracle.deformed(B, a, pmin, pmax, 0.0, m)
+    assert m2 == m and p == oracle.deformed_p(a, pmin, pmax, m)
+    return lu, lv
+
+
+def test_deformed_hadamard_identity():
+    """Section 3.2, proposition on the iterates: with W_m = diag(u_m) A^(p_m)
+    diag(v_m) and Z_m = diag(u_{m+1}) A^(p_{m+1}) diag(v_m),
+    Z_m = ROWS(W_m o A^(p_{m+1} - p_m)), checked across steps where p changes."""
+    rng = np.random.default_rng(3)
+    A = rng.uniform(0.05, 1.0, size=(5, 5))
+    B = oracle.log_of(A)
+    a, pmin, pmax = 2.0, 1, 9
+    changed = 0
+    for m in range(1, 14):
+        pm, pm1 = (oracle.deformed_p(a, pmin, pmax, k) for k in (m, m + 1))
+        changed += pm1 != pm
+        lu_m, lv_m = _deformed_state(B, a, pmin, pmax, m)
+        lu_n, _ = _deformed_state(B, a, pmin, pmax, m + 1)
+        Wm = np.exp(pm * B + lu_m[:, None] + lv_m[None, :])
+        Zm = np.exp(pm1 * B + lu_n[:, None] + lv_m[None, :])
+        H = Wm * A ** (pm1 - pm)
+        assert np.abs(Zm - H / H.sum(axis=1, keepdims=True)).max() < 1e-12
+        assert np.abs(Zm.sum(axis=1) - 1).max() < 1e-12  # Z_m is row-stochastic
+    assert changed >= 3
+
+
+def test_deformed_permutation_ratio():
+    """Section 3.2: for permutations sigma, pi of A,
+    w_sigma(Z_m) / w_pi(Z_m) = (w_sigma(A) / w_pi(A))^(p_{m+1}), by enumeration
+    of all permutations of a 4 x 4 matrix."""
+    rng = np.random.default_rng(5)
+    A = rng.uniform(0.1, 1.0, size=(4, 4))
+    B = oracle.log_of(A)
+    a, pmin, pmax = 3.0, 1, 12
+    perms = list(itertools.permutations(range(4)))
+    for m in (1, 4, 9):
+        pm1 = oracle.deformed_p(a, pmin, pmax, m + 1)
+        _, lv_m = _deformed_state(B, a, pmin, pmax, m)
+        lu_n, _ = _deformed_state(B, a, pmin, pmax, m + 1)
+        logZ = pm1 * B + lu_n[:, None] + lv_m[None, :]
+        s0 = perms[0]
+        for q in perms[1:]:
+            lhs = sum(logZ[i, q[i]] - logZ[i, s0[i]] for i in range(4))
+            rhs = pm1 * sum(B[i, q[i]] - B[i, s0[i]] for i in range(4))
+            assert abs(lhs - rhs) < 1e-10
+
+
+def test_deformed_planted_converges_to_permutation():
+    """Theorem optimalassign: the limit's support is the optimal permutation
+    (planted, unique); its weight is the closed form 1050 n."""
+    n = 32
+    W, sigma = skgen.planted(n, 3)
+    B = oracle.log_weights(W)
+    lu, lv, m, p, res = oracle.deformed(B, 3.0, 1, 16, 1e-9, 5000)
+    X = np.exp(p * B + lu[:, None] + lv[None, :])
+    assert p == 16 and res < 1e-9
+    assert np.abs(X[np.arange(n), sigma] - 1.0).max() < 1e-6
+    perm, weight = oracle.optimum_int(W, X >= 1e-4)
+    assert weight == 1050 * n and (perm == sigma).all()
+
+
+# ---------------------------------------------------------------- Newton scaling
+
+def test_newton_2x2_closed_form():
+    """X(p) of a positive 2 x 2 matrix is [[t, 1 - t], [1 - t, t]] with
+    t / (1 - t) = (a d / (b c))^(p/2); the Newton iteration reaches it."""
+    A = np.array([[3.0, 1.0], [0.5, 2.0]])
+    B = oracle.log_of(A)
+    for p in (1.0, 3.0):
+        ub, vb, outer, prods, res = oracle.newton(B, p, 1e-13, 1000)
+        X = oracle.scaled_matrix(B, p, ub, vb)
+        t = 1.0 / (1.0 + (A[0, 1] * A[1, 0] / (A[0, 0] * A[1, 1])) ** (p / 2))
+        assert np.abs(X - np.array([[t, 1 - t], [1 - t, t]])).max() < 1e-12
+        assert res < 1e-12
+
+
+def test_newton_worked_example():
+    """Section 2.3's 3 x 3 matrix at p = 10: the Newton limit is the printed
+    1e-4-bistochastic iterate to within 1e-4, and a bistochastic matrix to
+    1e-12."""
+    fx = fixtures.load("example_3x3.txt")
+    B = oracle.log_of(fx["A"])
+    ub, vb, outer, prods, res = oracle.newton(B, fx["p"], 1e-13, 5000)
+    X = oracle.scaled_matrix(B, fx["p"], ub, vb)
+    assert res < 1e-12
+    assert np.abs(X - fx["X"]).max() < 1e-4
+
+
+def test_newton_equals_sinkhorn_limit():
+    """X(p) is unique (Section 2.1): Newton and a converged Sinkhorn
+    iteration give the same matrix; Newton needs far fewer products with A."""
+    W = skgen.uniform_weights(64, 0, 100, seed=2)
+    B = oracle.log_weights(W)
+    ub0 = -B.max(axis=1)
+    ub, vb, outer, prods, res = oracle.newton(B, 1.0, 1e-11, 5000, ubar=ub0)
+    us, vs, m, r2 = oracle.sinkhorn(B, 1.0, 1e-13, 200000, ub0, None)
+    assert res < 1e-10 and r2 < 1e-13
+    Xn, Xs = oracle.scaled_matrix(B, 1.0, ub, vb), oracle.scaled_matrix(B, 1.0, us, vs)
+    assert np.abs(Xn - Xs).max() < 1e-10
+    assert prods < m / 4
