@@ -80,6 +80,8 @@ def parse():
     ap.add_argument("--served-requests", type=int, default=1000)
     ap.add_argument("--served-loads", default="0.5,0.9,1.5",
                     help="arrival rates as multiples of the FIFO loop's measured capacity")
+    ap.add_argument("--method", default="sinkhorn", choices=["sinkhorn", "newton"],
+                    help="scaling iteration of the sweep leg")
     ap.add_argument("--fused", action="store_true",
                     help="single-pass iteration (one matrix read per iteration)")
     ap.add_argument("--trace-summary", metavar="CSV",
@@ -411,7 +413,8 @@ def main():
     W = skgen.uniform_weights(n, 0, 1000, seed=args.seed)
     Wd = torch.from_numpy(W).cuda()
     prm = sk.make_params(ladder, tol=args.tol, max_iters=args.cap, check_every=32,
-                         threshold=args.threshold, storage=args.storage, fused=args.fused)
+                         threshold=args.threshold, storage=args.storage, fused=args.fused,
+                         method=args.method)
     ctx = sk.Context(0)
     torch.cuda.synchronize()
 
@@ -452,7 +455,9 @@ def main():
     dom = max(full.items(), key=lambda kv: kv[1][1])
     dom_name, (dom_launches, dom_ms) = dom
     avg_s = dom_ms / dom_launches / 1e3
-    per_launch = n * n * es if dom_name in SWEEP_KERNELS[args.storage] else None
+    # a Newton product with S = [[0, X], [X^T, 0]] reads the matrix twice
+    per_launch = (n * n * es if dom_name in SWEEP_KERNELS[args.storage]
+                  else 2 * n * n * es if dom_name == "nt_product" else None)
     achieved = per_launch / avg_s / 1e9 if per_launch else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1) if achieved else None,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -470,9 +475,10 @@ def main():
         "config": {"workload": f"dense n={n}, int16 w uniform 0..1000 (seed {args.seed}), "
                                f"ladder {ladder}, tol {args.tol}, {args.cap} iterations/stage cap, "
                                f"t={args.threshold}, storage {args.storage}"
-                               f"{', single-pass iteration' if args.fused else ''}; scale+recheck+"
+                               f"{', single-pass iteration' if args.fused else ''}"
+                               f"{', Newton scaling' if args.method == 'newton' else ''}; scale+recheck+"
                                f"prune+exact solve per step", "n": n, "storage": args.storage,
-                   "fused": bool(args.fused)},
+                   "fused": bool(args.fused), "method": args.method},
         "iters_per_step": iters // args.steps, "iters_per_s": round(iters / el, 1),
         "matrix_reads_per_iter": reads,
         "nnz_kept": nnz, "weight": weight, "log_gamma": lg,

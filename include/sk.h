@@ -91,7 +91,14 @@ typedef enum {
  *                  [p_ladder[0], p_ladder[n_p - 1]], with u and v carried
  *                  unscaled from one p to the next; it stops at the first
  *                  iterate computed at the last p whose residual is below
- *                  tol, or at max_iters_per_stage. int16 W only. */
+ *                  tol, or at max_iters_per_stage. int16 W only.
+ *   method       : SK_SINKHORN (0) = Sinkhorn iteration; SK_NEWTON (1) =
+ *                  Newton iteration (Section 5.2, the Knight-Ruiz method):
+ *                  at each p, x o (S x) = 1 for S = [[0, X], [X^T, 0]] with
+ *                  conjugate-gradient inner solves, until max_i |1 - (x o S
+ *                  x)_i| <= tol; max_iters_per_stage then bounds the products
+ *                  with S per stage (reported as iterations). One int16
+ *                  instance, not fused, not deformed. */
 typedef struct {
     int32_t p_ladder[SK_MAX_LADDER];
     int32_t n_p;
@@ -104,7 +111,10 @@ typedef struct {
     int32_t warm_start;
     int32_t fused;
     double deform_a;
+    int32_t method;
 } sk_params;
+
+enum { SK_SINKHORN = 0, SK_NEWTON = 1 };
 
 /* Per-run report. Residuals are max_i |r_i - 1| (rows) and max_j |c_j - 1|
  * (columns) of the returned iterate. "Balanced matrix" is the matrix the

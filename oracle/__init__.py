@@ -372,8 +372,8 @@ def newton(B, p, tol, max_products, ubar=None, vbar=None, lo=0.1, hi=3.0, eta_ma
     preconditioned residual falls below max(eta^2 |1 - v|^2, tol^2), with the
     forcing term eta updated after every outer step from the ratio of
     successive residuals (at most eta_max, at least tol / (2 |1 - v|)). The
-    outer loop stops when |1 - v|_2 <= tol or after max_products products
-    with S. Returns (ubar, vbar, outer steps, products with S, max |row or
+    outer loop stops when max_i |1 - v_i| <= tol or after max_products
+    products with S. Returns (ubar, vbar, outer steps, products with S, max |row or
     column sum - 1| of the result)."""
     n = B.shape[0]
     ubar = np.zeros(n) if ubar is None else np.array(ubar, dtype=np.float64)
@@ -390,7 +390,7 @@ def newton(B, p, tol, max_products, ubar=None, vbar=None, lo=0.1, hi=3.0, eta_ma
     rout = float(r @ r)
     rold = rout
     products, outer, eta = 1, 0, eta_max
-    while rout > rt and products < max_products:
+    while np.abs(r).max() > tol and products < max_products:
         outer += 1
         y = np.ones(2 * n)
         inner_tol = max(eta * eta * rout, rt)

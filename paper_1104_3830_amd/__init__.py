@@ -44,7 +44,7 @@ class Params(ctypes.Structure):
                 ("check_every", ctypes.c_int32), ("threshold", ctypes.c_double),
                 ("storage", ctypes.c_int32), ("opt_ratio", ctypes.c_double),
                 ("warm_start", ctypes.c_int32), ("fused", ctypes.c_int32),
-                ("deform_a", ctypes.c_double)]
+                ("deform_a", ctypes.c_double), ("method", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):
@@ -149,7 +149,7 @@ def load_tile_table(path):
 
 def make_params(ladder, tol=1e-5, max_iters=20000, check_every=32, threshold=1e-4,
                 storage="i16", opt_ratio=0.0, warm_start=False, fused=False,
-                deform_a=0.0) -> Params:
+                deform_a=0.0, method="sinkhorn") -> Params:
     p = Params()
     ladder = [int(x) for x in ladder]
     if not 1 <= len(ladder) <= MAX_LADDER:
@@ -166,6 +166,7 @@ def make_params(ladder, tol=1e-5, max_iters=20000, check_every=32, threshold=1e-
     p.warm_start = 1 if warm_start else 0
     p.fused = 1 if fused else 0
     p.deform_a = float(deform_a)
+    p.method = {"sinkhorn": 0, "newton": 1}[method] if isinstance(method, str) else int(method)
     return p
 
 

@@ -18,7 +18,7 @@ constexpr int kMaxSegRows = 1024;
 constexpr int kFusedSlots = 256;  // workgroups (and column-partial slots) of the fused kernel
 
 enum : int32_t { ST_RUNNING = 0, ST_DONE = 1, ST_ERROR = 2, ST_STAGE_END = 3 };
-enum : uint32_t { ERR_EMPTY_ROW = 1u, ERR_EMPTY_COL = 2u, ERR_RANGE = 4u };
+enum : uint32_t { ERR_EMPTY_ROW = 1u, ERR_EMPTY_COL = 2u, ERR_RANGE = 4u, ERR_NEWTON = 8u };
 
 // Per-instance control block, device memory. Written by the kernels only at
 // the places documented on each field; read by the host between launches.
@@ -102,6 +102,24 @@ __device__ __forceinline__ float4 gload(const float4 *p) {
 }
 __device__ __forceinline__ int16_t gload(const int16_t *p) { return *(const SK_GLOBAL int16_t *)p; }
 
+// Newton scaling (Knight-Ruiz) of one instance: state of the device-side
+// outer/inner (conjugate gradient) iteration on the 2n-vectors of the
+// symmetric embedding S = [[0, X], [X^T, 0]].
+enum : int32_t { NT_OUTER = 0, NT_INNER = 1 };
+enum : int32_t { NT_RUN = 0, NT_CONVERGED = 1, NT_CAPPED = 2, NT_FAILED = 3 };
+struct NtCtl {
+    int32_t mode;          // NT_OUTER: sd = S x;  NT_INNER: sd = S (x o d)
+    int32_t done;          // NT_RUN / NT_CONVERGED / NT_CAPPED / NT_FAILED
+    int32_t first;         // the next NT_OUTER is the initial one
+    int32_t pad;
+    int64_t products, outer, max_products;
+    double rout, rold, rho, rho_prev, eta, inner_tol, resinf;
+    double tol, lo, hi, eta_max, g;
+};
+struct NtVec {
+    float *q, *sd, *x, *v, *r, *z, *d, *y, *w;  // [2n] each
+};
+
 struct RowUnit { int32_t inst, row0; };
 struct ColUnit { int32_t inst, tile, seg, pad; };
 struct FinUnit { int32_t inst, group; };  // 64 columns of one instance
@@ -114,6 +132,12 @@ hipError_t launch_row_sweep(const Inst *d_insts, const RowUnit *d_units, int nun
                             size_t lds_bytes, hipStream_t st);
 hipError_t launch_col_sweep(const Inst *d_insts, const ColUnit *d_units, int nunits, int grid,
                             hipStream_t st);
+hipError_t launch_nt_product(const Inst *d_insts, const RowUnit *d_rows, int nrows, int row_grid,
+                             size_t row_lds, const ColUnit *d_cols, int ncols, int col_grid,
+                             const NtCtl *nt, NtVec vec, int n, hipStream_t st);
+hipError_t launch_nt_step(const Inst *d_insts, NtCtl *nt, NtVec vec, int n, hipStream_t st);
+hipError_t launch_nt_fold(const Inst *d_insts, const NtCtl *nt, NtVec vec, int n, int last,
+                          hipStream_t st);
 hipError_t launch_iter_end(const Inst *d_insts, int count, hipStream_t st);
 enum : int { kFinOnePass = 1, kFinStoredK = 2 };
 hipError_t launch_col_finalize(const Inst *d_insts, const FinUnit *d_units, int nunits, int grid,

@@ -1217,6 +1217,325 @@ __global__ __launch_bounds__(256) void k_reset_ctl(const Inst *__restrict__ inst
     }
 }
 
+// ---------------------------------------------------------------- Newton scaling
+// Products with S = [[0, X], [X^T, 0]] for X = diag(u) A^(p) diag(v) at the
+// instance's potentials (fixed during a Newton solve): sd[i] = (X q_c)_i and
+// sd[n + j] = (X^T q_r)_j for q = (q_r, q_c), each term formed as in the
+// sweeps, exp(E_ij) exp(phi_i) exp(gam_j). One instance (index 0).
+__global__ __launch_bounds__(kRowWaves * kWave) void k_nt_rows(const Inst *__restrict__ insts,
+                                                                 const RowUnit *__restrict__ units,
+                                                                 int nunits,
+                                                                 const NtCtl *__restrict__ nt,
+                                                                 const float *__restrict__ q,
+                                                                 float *__restrict__ sd) {
+    extern __shared__ ColPot lds_cp[];
+    __shared__ float tab[kTabN];
+    if (nt->done != NT_RUN) return;
+    const Inst &I = insts[0];
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int n = I.n, n8 = n >> 3;
+    const int par = I.ctl->iter & 1;
+    const int p4 = 4 * I.ctl->p;
+    const bool sent = I.ctl->sent != 0u;
+    int u0, u1;
+    unit_range(nunits, u0, u1);
+    fill_exp_table(tab);
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        ColPot k;
+        k.a = 4 * I.G[j];
+        k.g = ex2(I.gam[j] * kLog2e) * q[n + j];
+        lds_cp[I.vec8 ? swz8(j, n8) : j] = k;
+    }
+    __syncthreads();
+    for (int u = u0; u < u1; ++u) {
+        const int row = units[u].row0 + wave;
+        if (row >= n) continue;
+        const int16_t *wr = I.W + (int64_t)row * I.pitch;
+        const int B = 4 * (I.F[par][row] - kTabLo);
+        float S;
+        if (I.vec8) S = sent ? row_partial_v8<true>(wr, n, p4, B, lds_cp, tab, lane)
+                             : row_partial_v8<false>(wr, n, p4, B, lds_cp, tab, lane);
+        else S = sent ? row_partial_v1<true>(wr, n, p4, B, lds_cp, tab, lane)
+                      : row_partial_v1<false>(wr, n, p4, B, lds_cp, tab, lane);
+        S = wave_sum(S);
+        if (lane == 0) sd[row] = ex2(I.phi[par][row] * kLog2e) * S;
+    }
+}
+
+__global__ __launch_bounds__(kColWaves * kWave) void k_nt_cols(const Inst *__restrict__ insts,
+                                                                 const ColUnit *__restrict__ units,
+                                                                 int nunits,
+                                                                 const NtCtl *__restrict__ nt,
+                                                                 const float *__restrict__ q) {
+    __shared__ float red[kColWaves][kColTile8];
+    __shared__ RowPot rowpot[kMaxSegRows];
+    __shared__ float tab[kTabN];
+    if (nt->done != NT_RUN) return;
+    const Inst &I = insts[0];
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int n = I.n;
+    const int par = I.ctl->iter & 1;
+    const bool sent = I.ctl->sent != 0u;
+    int u0, u1;
+    unit_range(nunits, u0, u1);
+    fill_exp_table(tab);
+    for (int u = u0; u < u1; ++u) {
+        const ColUnit un = units[u];
+        const int tc = I.tile_cols;
+        const int ctile0 = un.tile * tc;
+        const int ncols = min(tc, n - ctile0);
+        const int r0 = un.seg * I.seg_rows, r1 = min(n, r0 + I.seg_rows);
+        __syncthreads();
+        for (int r = r0 + (int)threadIdx.x; r < r1; r += blockDim.x) {
+            RowPot k;
+            k.b = 4 * (I.F[par][r] - kTabLo);
+            k.r = ex2(I.phi[par][r] * kLog2e) * q[r];
+            rowpot[r - r0] = k;
+        }
+        __syncthreads();
+        float acc[8];
+        if (I.vec8) {
+            if (sent) col_partial<true, true>(I, un.tile, r0, r1, wave, lane, rowpot, tab, acc);
+            else col_partial<false, true>(I, un.tile, r0, r1, wave, lane, rowpot, tab, acc);
+#pragma unroll
+            for (int c = 0; c < 8; ++c) red[wave][lane * 8 + c] = acc[c];
+        } else {
+            if (sent) col_partial<true, false>(I, un.tile, r0, r1, wave, lane, rowpot, tab, acc);
+            else col_partial<false, false>(I, un.tile, r0, r1, wave, lane, rowpot, tab, acc);
+            red[wave][lane] = acc[0];
+        }
+        __syncthreads();
+        float *dst = I.colpart + (int64_t)un.seg * n + ctile0;
+        for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
+            float v = red[0][c];
+#pragma unroll
+            for (int w2 = 1; w2 < kColWaves; ++w2) v += red[w2][c];
+            dst[c] = v;
+        }
+    }
+}
+
+// sd[n + j] = exp(gam_j) * sum of the column's slots in segment order.
+__global__ __launch_bounds__(256) void k_nt_cols_sum(const Inst *__restrict__ insts,
+                                                     const NtCtl *__restrict__ nt,
+                                                     float *__restrict__ sd) {
+    if (nt->done != NT_RUN) return;
+    const Inst &I = insts[0];
+    const int n = I.n;
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+        float v = 0.f;
+        for (int s = 0; s < I.nseg; ++s) v += I.colpart[(int64_t)s * n + j];
+        sd[n + j] = ex2(I.gam[j] * kLog2e) * v;
+    }
+}
+
+// Block reductions for the 1024-thread step kernel (fixed order).
+__device__ double nt_sum(double v, double *sh) {
+    v = wave_sum_d(v);
+    const int wave = threadIdx.x / kWave;
+    __syncthreads();
+    if (threadIdx.x % kWave == 0) sh[wave] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int w2 = 0; w2 < (int)blockDim.x / kWave; ++w2) t += sh[w2];
+    return t;
+}
+__device__ float nt_max(float v, double *sh) {
+    v = wave_max(v);
+    const int wave = threadIdx.x / kWave;
+    __syncthreads();
+    if (threadIdx.x % kWave == 0) sh[wave] = (double)v;
+    __syncthreads();
+    float t = -INFINITY;
+    for (int w2 = 0; w2 < (int)blockDim.x / kWave; ++w2) t = fmaxf(t, (float)sh[w2]);
+    return t;
+}
+__device__ float nt_min(float v, double *sh) { return -nt_max(-v, sh); }
+
+// One step of the Newton / conjugate-gradient iteration, after the product
+// sd of the vector q it asked for (one workgroup):
+//   NT_OUTER (sd = S x): v = x o S x, r = 1 - v; stop if max |r_i| <= tol;
+//     update the forcing term eta; start an inner solve of
+//     (D(x) S D(x) + D(v)) y = 1 + v at y = 1 with the preconditioner D(v).
+//   NT_INNER (sd = S (x o d)): w = x o sd + v o d, the CG step on y; a step
+//     that takes y to or past lo (hi) is cut at that bound and ends the
+//     solve, as does a preconditioned residual below the inner tolerance;
+//     then x <- x o y and the next product is S x.
+__global__ __launch_bounds__(1024) void k_nt_step(const Inst *__restrict__ insts, NtCtl *nt,
+                                                  NtVec V) {
+    __shared__ double sh[1024 / kWave];
+    __shared__ NtCtl c;
+    if (threadIdx.x == 0) c = *nt;
+    __syncthreads();
+    if (c.done != NT_RUN) return;
+    const int n2 = 2 * insts[0].n;
+    const int t = threadIdx.x, T = blockDim.x;
+    bool start_inner = false, end_inner = false;
+    if (c.mode == NT_OUTER) {
+        double rr = 0.0;
+        float rinf = 0.f;
+        for (int i = t; i < n2; i += T) {
+            const float v = V.x[i] * V.sd[i];
+            const float r = 1.f - v;
+            V.v[i] = v;
+            V.r[i] = r;
+            rr += (double)r * r;
+            rinf = fmaxf(rinf, fabsf(r));
+        }
+        const double rout = nt_sum(rr, sh);
+        const float resinf = nt_max(rinf, sh);
+        __syncthreads();
+        if (t == 0) {
+            c.products += 1;
+            if (!c.first) {
+                const double ratio = rout / c.rold;
+                const double eta_prev = c.eta;
+                double eta = c.g * ratio;
+                if (c.g * eta_prev * eta_prev > 0.1) eta = fmax(eta, c.g * eta_prev * eta_prev);
+                c.eta = fmax(fmin(eta, c.eta_max), 0.5 * c.tol / fmax(sqrt(rout), 1e-300));
+            }
+            c.first = 0;
+            c.rold = rout;
+            c.rout = rout;
+            c.resinf = resinf;
+            if (resinf <= c.tol) c.done = NT_CONVERGED;
+            else if (!(rout < INFINITY)) c.done = NT_FAILED;
+            else if (c.products >= c.max_products) c.done = NT_CAPPED;
+            c.inner_tol = fmax(c.eta * c.eta * rout, c.tol * c.tol);
+        }
+        __syncthreads();
+        start_inner = c.done == NT_RUN;
+    } else {
+        double dw = 0.0;
+        for (int i = t; i < n2; i += T) {
+            const float w = V.x[i] * V.sd[i] + V.v[i] * V.d[i];
+            V.w[i] = w;
+            dw += (double)V.d[i] * w;
+        }
+        const double dsum = nt_sum(dw, sh);
+        const float alpha = (float)(c.rho / dsum);
+        float mn = INFINITY, mx = -INFINITY;
+        for (int i = t; i < n2; i += T) {
+            const float yn = V.y[i] + alpha * V.d[i];
+            mn = fminf(mn, yn);
+            mx = fmaxf(mx, yn);
+        }
+        mn = nt_min(mn, sh);
+        mx = nt_max(mx, sh);
+        const float lo = (float)c.lo, hi = (float)c.hi;
+        if (!(dsum > 0.0) || !(mn == mn)) {
+            if (t == 0) c.done = NT_FAILED;
+        } else if (mn <= lo || mx >= hi) {
+            // cut the step at the bound it reaches first
+            float gm = INFINITY;
+            for (int i = t; i < n2; i += T) {
+                const float st = alpha * V.d[i];
+                if (mn <= lo) {
+                    if (st < 0.f) gm = fminf(gm, (lo - V.y[i]) / st);
+                } else if (V.y[i] + st > hi) {
+                    gm = fminf(gm, (hi - V.y[i]) / st);
+                }
+            }
+            gm = nt_min(gm, sh);
+            if (!(gm < INFINITY)) gm = 1.f;  // reached the bound exactly: the full step
+            for (int i = t; i < n2; i += T) V.y[i] += gm * alpha * V.d[i];
+            end_inner = true;
+        } else {
+            double rz = 0.0;
+            for (int i = t; i < n2; i += T) {
+                V.y[i] += alpha * V.d[i];
+                const float r = V.r[i] - alpha * V.w[i];
+                const float z = r / V.v[i];
+                V.r[i] = r;
+                V.z[i] = z;
+                rz += (double)r * z;
+            }
+            const double rho = nt_sum(rz, sh);
+            __syncthreads();
+            if (t == 0) {
+                c.rho_prev = c.rho;
+                c.rho = rho;
+            }
+            __syncthreads();
+            end_inner = !(c.rho > c.inner_tol) || c.products + 1 >= c.max_products;
+            if (!end_inner) {
+                const float beta = (float)(c.rho / c.rho_prev);
+                for (int i = t; i < n2; i += T) {
+                    const float d = V.z[i] + beta * V.d[i];
+                    V.d[i] = d;
+                    V.q[i] = V.x[i] * d;
+                }
+            }
+        }
+        if (t == 0) c.products += 1;
+    }
+    __syncthreads();
+    if (c.done != NT_RUN) {
+        if (t == 0) *nt = c;
+        return;
+    }
+    if (start_inner) {
+        // y = 1, z = r / v, d = z, rho = r . z; next product S (x o d)
+        double rz = 0.0;
+        for (int i = t; i < n2; i += T) {
+            const float z = V.r[i] / V.v[i];
+            V.y[i] = 1.f;
+            V.z[i] = z;
+            V.d[i] = z;
+            V.q[i] = V.x[i] * z;
+            rz += (double)V.r[i] * z;
+        }
+        const double rho = nt_sum(rz, sh);
+        if (t == 0) {
+            c.rho = rho;
+            c.mode = NT_INNER;
+        }
+    } else if (end_inner) {
+        for (int i = t; i < n2; i += T) {
+            const float x = V.x[i] * V.y[i];
+            V.x[i] = x;
+            V.q[i] = x;
+        }
+        if (t == 0) {
+            c.mode = NT_OUTER;
+            c.outer += 1;
+        }
+    }
+    __syncthreads();
+    if (t == 0) *nt = c;
+}
+
+// Folds the Newton scalings into the potentials: log u_i += log x_i,
+// log v_j += log x_{n+j} (FP64, re-split into integer and fraction), and
+// ends the stage for the host.
+__global__ __launch_bounds__(256) void k_nt_fold(const Inst *__restrict__ insts,
+                                                 const NtCtl *__restrict__ nt,
+                                                 const float *__restrict__ x, int last) {
+    const Inst &I = insts[0];
+    Ctl *ctl = I.ctl;
+    const int n = I.n;
+    const int par = ctl->iter & 1;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const double f = (double)I.F[par][i] + (double)I.phi[par][i] + log((double)x[i]);
+        const double k = rint(f);
+        I.F[par][i] = (int32_t)k;
+        I.phi[par][i] = (float)(f - k);
+        const double g = (double)I.G[i] + (double)I.gam[i] + log((double)x[n + i]);
+        const double kg = rint(g);
+        I.G[i] = (int32_t)kg;
+        I.gam[i] = (float)(g - kg);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const NtCtl c = *nt;
+        ctl->stage_iters[ctl->stage] = c.products;
+        ctl->iters_total += c.products;
+        ctl->last_res = (float)c.resinf;
+        if (c.done == NT_CAPPED) ctl->capped += 1;
+        if (c.done == NT_FAILED) ctl->err |= ERR_NEWTON;
+        ctl->state = c.done == NT_FAILED ? ST_ERROR : (last ? ST_DONE : ST_STAGE_END);
+    }
+}
+
 // ---------------------------------------------------------------- launchers
 hipError_t launch_gather_ctl(const Inst *d_insts, int count, Ctl *out, hipStream_t st) {
     const int words = count * (int)(sizeof(Ctl) / sizeof(uint32_t));
@@ -1249,6 +1568,27 @@ hipError_t launch_col_sweep(const Inst *d_insts, const ColUnit *d_units, int nun
 hipError_t launch_col_finalize(const Inst *d_insts, const FinUnit *d_units, int nunits, int grid,
                                int mode, hipStream_t st) {
     hipLaunchKernelGGL(k_col_finalize, dim3(grid), dim3(256), 0, st, d_insts, d_units, nunits, mode);
+    return hipGetLastError();
+}
+hipError_t launch_nt_product(const Inst *d_insts, const RowUnit *d_rows, int nrows, int row_grid,
+                             size_t row_lds, const ColUnit *d_cols, int ncols, int col_grid,
+                             const NtCtl *nt, NtVec vec, int n, hipStream_t st) {
+    hipLaunchKernelGGL(k_nt_rows, dim3(row_grid), dim3(kRowWaves * kWave), row_lds, st, d_insts,
+                       d_rows, nrows, nt, vec.q, vec.sd);
+    hipLaunchKernelGGL(k_nt_cols, dim3(col_grid), dim3(kColWaves * kWave), 0, st, d_insts, d_cols,
+                       ncols, nt, vec.q);
+    hipLaunchKernelGGL(k_nt_cols_sum, dim3((n + 255) / 256), dim3(256), 0, st, d_insts, nt, vec.sd);
+    return hipGetLastError();
+}
+hipError_t launch_nt_step(const Inst *d_insts, NtCtl *nt, NtVec vec, int n, hipStream_t st) {
+    (void)n;
+    hipLaunchKernelGGL(k_nt_step, dim3(1), dim3(1024), 0, st, d_insts, nt, vec);
+    return hipGetLastError();
+}
+hipError_t launch_nt_fold(const Inst *d_insts, const NtCtl *nt, NtVec vec, int n, int last,
+                          hipStream_t st) {
+    hipLaunchKernelGGL(k_nt_fold, dim3((n + 255) / 256), dim3(256), 0, st, d_insts, nt, vec.x,
+                       last);
     return hipGetLastError();
 }
 hipError_t launch_iter_end(const Inst *d_insts, int count, hipStream_t st) {
@@ -1296,6 +1636,9 @@ hipError_t set_kernel_attributes() {
     const int lds = (int)(kMaxN * sizeof(double));
     hipError_t e;
     if ((e = hipFuncSetAttribute((const void *)k_row_sweep, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 lds)) != hipSuccess)
+        return e;
+    if ((e = hipFuncSetAttribute((const void *)k_nt_rows, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  lds)) != hipSuccess)
         return e;
     if ((e = hipFuncSetAttribute((const void *)k_check_rows,

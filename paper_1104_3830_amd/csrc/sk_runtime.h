@@ -66,7 +66,8 @@ enum KernelId {
     KID_ROW_DETECT, KID_COL_DETECT, KID_ITER_END_DETECT, KID_ROW_IDLE, KID_COL_IDLE,
     KID_ITER_END_IDLE, KID_ROW_K_DETECT, KID_COL_K_DETECT, KID_ROW_K_IDLE, KID_COL_K_IDLE,
     KID_FUSED, KID_FINALIZE, KID_FUSED_DETECT, KID_FINALIZE_DETECT, KID_FUSED_IDLE,
-    KID_FINALIZE_IDLE, KID_COUNT
+    KID_FINALIZE_IDLE, KID_NT_PRODUCT, KID_NT_STEP, KID_NT_PRODUCT_IDLE, KID_NT_STEP_IDLE,
+    KID_COUNT
 };
 extern const char *kKernelNames[KID_COUNT];
 
@@ -160,6 +161,14 @@ sk_status run_batch_i16(sk_ctx *ctx, Batch &B, const sk_params *prm, int first_s
 using StageHook = std::function<sk_status(bool &stop)>;
 sk_status run_single_k(sk_ctx *ctx, Batch &B, const sk_params *prm,
                        const StageHook *hook = nullptr);
+// Newton scaling stage by stage (one int16 instance); its vectors come from
+// `bump` (the arena after the batch plan).
+sk_status run_newton_i16(sk_ctx *ctx, Batch &B, const sk_params *prm, Bump &bump,
+                         const StageHook *hook = nullptr);
+// Arena bytes of the Newton vectors and state for size n.
+inline size_t newton_bytes(int32_t n) {
+    return 9 * align_up(sizeof(float) * 2 * (size_t)n, 256) + 1024;
+}
 sk_status check_fp64(sk_ctx *ctx, Batch &B, int k, sk_report *rep);
 sk_status enqueue_check(sk_ctx *ctx, Batch &B, int k);  // writes B.d_checkout[k]
 void report_from_check(const double *out4, int p, sk_report *rep);

@@ -96,7 +96,8 @@ const char *kKernelNames[KID_COUNT] = {"init", "row_sweep", "col_sweep", "iter_e
                                        "iter_end:idle", "row_sweep_k:detect", "col_sweep_k:detect",
                                        "row_sweep_k:idle", "col_sweep_k:idle", "fused",
                                        "finalize", "fused:detect", "finalize:detect",
-                                       "fused:idle", "finalize:idle"};
+                                       "fused:idle", "finalize:idle", "nt_product", "nt_step",
+                                       "nt_product:idle", "nt_step:idle"};
 
 hipEvent_t Profiler::take() {
     if (!pool.empty()) {
@@ -202,7 +203,8 @@ size_t sk_potentials_bytes(int32_t n) { return n > 0 ? (size_t)16 * n : 0; }
 
 size_t sk_arena_bytes(int32_t n, int32_t storage) {
     if (n <= 0) return 0;
-    return instance_bytes(n, (n % 8) == 0, storage, 1) + shared_bytes(1, &n) + 4096;
+    return instance_bytes(n, (n % 8) == 0, storage, 1) + shared_bytes(1, &n) + newton_bytes(n) +
+           4096;
 }
 
 size_t sk_batch_arena_bytes(int32_t count, const int32_t *n, int32_t storage) {
@@ -285,6 +287,9 @@ sk_status sk::check_params(sk_ctx *ctx, const sk_params *p) {
         return fail(ctx, SK_EINVAL, "deform_a must be in [0, 1e6]");
     if (p->deform_a > 0.0 && p->storage != SK_W_I16)
         return fail(ctx, SK_EINVAL, "the deformed iteration sweeps int16 W");
+    if (p->method != SK_SINKHORN && p->method != SK_NEWTON) return fail(ctx, SK_EINVAL, "bad method");
+    if (p->method == SK_NEWTON && (p->storage != SK_W_I16 || p->fused || p->deform_a > 0.0))
+        return fail(ctx, SK_EINVAL, "Newton scaling runs on int16 W, two-pass, undeformed");
     return SK_OK;
 }
 
@@ -589,6 +594,7 @@ sk_status sk::copy_potentials_out(sk_ctx *ctx, Batch &B, int k, void *pot) {
 
 sk_status sk::status_of(const Ctl &c) {
     if (c.err & (ERR_EMPTY_ROW | ERR_EMPTY_COL)) return SK_ENOSUPPORT;
+    if (c.err & ERR_NEWTON) return SK_EDEVICE;
     if (c.capped) return SK_ENOCONV;
     return SK_OK;
 }
@@ -632,7 +638,11 @@ sk_status sk::scale_impl(sk_ctx *ctx, int count, const int16_t *const *W, const 
     if ((st = plan_batch(ctx, bump, count, W, pitch.data(), n, prm, B)) != SK_OK) return st;
     if ((st = upload_batch(ctx, B)) != SK_OK) return st;
     if ((st = start_batch(ctx, B, prm, pot)) != SK_OK) return st;
-    if (prm->storage == SK_W_I16) {
+    if (prm->method == SK_NEWTON) {
+        if (count != 1) return fail(ctx, SK_EINVAL, "Newton scaling is single-instance");
+        if ((st = run_newton_i16(ctx, B, prm, bump)) != SK_OK) return st;
+        if ((st = read_ctl(ctx, B)) != SK_OK) return st;
+    } else if (prm->storage == SK_W_I16) {
         if ((st = run_batch_i16(ctx, B, prm)) != SK_OK) return st;
     } else {
         if ((st = run_single_k(ctx, B, prm)) != SK_OK) return st;
@@ -667,7 +677,7 @@ sk_status sk::scale_impl(sk_ctx *ctx, int count, const int16_t *const *W, const 
         rep.seconds = 0;
         if (reports) reports[k] = rep;
         sk_status sk = status_of(c);
-        if (sk == SK_ENOSUPPORT) result = SK_ENOSUPPORT;
+        if (sk == SK_ENOSUPPORT || sk == SK_EDEVICE) result = sk;
         else if (sk == SK_ENOCONV && result == SK_OK) result = SK_ENOCONV;
     }
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
@@ -676,6 +686,7 @@ sk_status sk::scale_impl(sk_ctx *ctx, int count, const int16_t *const *W, const 
     if (reports)
         for (int k = 0; k < count; ++k) reports[k].seconds = secs;
     if (result == SK_ENOSUPPORT) fail(ctx, result, "a row or column of A has no entry");
+    else if (result == SK_EDEVICE) fail(ctx, result, "Newton scaling broke down");
     else if (result == SK_ENOCONV) fail(ctx, result, "a stage hit max_iters_per_stage");
     return result;
 }

@@ -118,7 +118,7 @@ extern "C" sk_status sk_solve(sk_ctx *ctx, const int16_t *W, int32_t n, const sk
     const double log_ratio = adaptive ? std::log(params->opt_ratio) : 0.0;
     const bool kpath = params->storage != SK_W_I16;
     if ((st = plan_batch(ctx, bump, 1, Ws, &pitch, &n, params, B)) != SK_OK) return st;
-    B.h_insts[0].pause = (adaptive && !kpath) ? 1 : 0;
+    B.h_insts[0].pause = (adaptive && !kpath && params->method == SK_SINKHORN) ? 1 : 0;
     if ((st = upload_batch(ctx, B)) != SK_OK) return st;
     void *pots[1] = {potentials};
     if ((st = start_batch(ctx, B, params, pots)) != SK_OK) return st;
@@ -158,7 +158,15 @@ extern "C" sk_status sk_solve(sk_ctx *ctx, const int16_t *W, int32_t n, const sk
         return SK_OK;
     };
 
-    if (kpath) {
+    if (params->method == SK_NEWTON) {
+        // Newton scaling ends every stage on the host anyway
+        const StageHook hook = [&](bool &stop) {
+            const Ctl &c = ctx->h_ctl[0];
+            return evaluate(c, c.stage + 1 >= params->n_p, stop);
+        };
+        if ((st = run_newton_i16(ctx, B, params, bump, &hook)) != SK_OK) return st;
+        if ((st = read_ctl(ctx, B)) != SK_OK) return st;
+    } else if (kpath) {
         // stored K: the controller pauses at every stage end anyway
         const StageHook hook = [&](bool &stop) {
             const Ctl &c = ctx->h_ctl[0];
@@ -184,13 +192,14 @@ extern "C" sk_status sk_solve(sk_ctx *ctx, const int16_t *W, int32_t n, const sk
         }
     }
     const Ctl c = ctx->h_ctl[0];
-    if (c.state == ST_ERROR) {
+    if (c.state == ST_ERROR || (c.err & (ERR_EMPTY_ROW | ERR_EMPTY_COL))) {
         if (report) {
             memset(report, 0, sizeof *report);
             fill_report(c, report);
             report->log_gamma = NAN;
             report->threshold_used = NAN;
         }
+        if (c.err & ERR_NEWTON) return fail(ctx, SK_EDEVICE, "Newton scaling broke down");
         return fail(ctx, status_of(c), "a row or column of A has no entry");
     }
     if (!have_best) {
