@@ -118,7 +118,9 @@ struct NtCtl {
 };
 struct NtVec {
     float *q, *sd, *x, *v, *r, *z, *d, *y, *w;  // [2n] each
+    double *parts;  // [kNtPhases + 1][kNtMaxGroups][4] per-workgroup partial reductions
 };
+constexpr int kNtPhases = 4, kNtMaxGroups = 64, kNtThreads = 256;
 
 struct RowUnit { int32_t inst, row0; };
 struct ColUnit { int32_t inst, tile, seg, pad; };
@@ -135,6 +137,7 @@ hipError_t launch_col_sweep(const Inst *d_insts, const ColUnit *d_units, int nun
 hipError_t launch_nt_product(const Inst *d_insts, const RowUnit *d_rows, int nrows, int row_grid,
                              size_t row_lds, const ColUnit *d_cols, int ncols, int col_grid,
                              const NtCtl *nt, NtVec vec, int n, hipStream_t st);
+// nt: two control blocks (double-buffered by phase parity; nt[1] is current).
 hipError_t launch_nt_step(const Inst *d_insts, NtCtl *nt, NtVec vec, int n, hipStream_t st);
 hipError_t launch_nt_fold(const Inst *d_insts, const NtCtl *nt, NtVec vec, int n, int last,
                           hipStream_t st);

@@ -1329,8 +1329,8 @@ __global__ __launch_bounds__(256) void k_nt_cols_sum(const Inst *__restrict__ in
     }
 }
 
-// Block reductions for the 1024-thread step kernel (fixed order).
-__device__ double nt_sum(double v, double *sh) {
+// Block reductions of the phase kernels (fixed order).
+__device__ double nt_bsum(double v, double *sh) {
     v = wave_sum_d(v);
     const int wave = threadIdx.x / kWave;
     __syncthreads();
@@ -1340,109 +1340,173 @@ __device__ double nt_sum(double v, double *sh) {
     for (int w2 = 0; w2 < (int)blockDim.x / kWave; ++w2) t += sh[w2];
     return t;
 }
-__device__ float nt_max(float v, double *sh) {
-    v = wave_max(v);
+__device__ double nt_bmax(double v, double *sh) {
+    v = wave_max_d(v);
     const int wave = threadIdx.x / kWave;
     __syncthreads();
-    if (threadIdx.x % kWave == 0) sh[wave] = (double)v;
+    if (threadIdx.x % kWave == 0) sh[wave] = v;
     __syncthreads();
-    float t = -INFINITY;
-    for (int w2 = 0; w2 < (int)blockDim.x / kWave; ++w2) t = fmaxf(t, (float)sh[w2]);
+    double t = -INFINITY;
+    for (int w2 = 0; w2 < (int)blockDim.x / kWave; ++w2) t = fmax(t, sh[w2]);
     return t;
 }
-__device__ float nt_min(float v, double *sh) { return -nt_max(-v, sh); }
+// Reductions over the workgroups' partials of a phase: thread g loads the
+// partial of workgroup g and the block reduces them in a fixed tree, the same
+// in every workgroup, so all of them see the same scalars. Called by every
+// thread of the block.
+__device__ double nt_gsum(const double *part, int slot, double *sh) {
+    const int g = threadIdx.x;
+    return nt_bsum(g < (int)gridDim.x ? part[g * 4 + slot] : 0.0, sh);
+}
+__device__ double nt_gmax(const double *part, int slot, double *sh) {
+    const int g = threadIdx.x;
+    return nt_bmax(g < (int)gridDim.x ? part[g * 4 + slot] : -INFINITY, sh);
+}
+__device__ double nt_gmin(const double *part, int slot, double *sh) {
+    return -nt_bmax(threadIdx.x < gridDim.x ? -part[threadIdx.x * 4 + slot] : -INFINITY, sh);
+}
 
-// One step of the Newton / conjugate-gradient iteration, after the product
-// sd of the vector q it asked for (one workgroup):
-//   NT_OUTER (sd = S x): v = x o S x, r = 1 - v; stop if max |r_i| <= tol;
-//     update the forcing term eta; start an inner solve of
-//     (D(x) S D(x) + D(v)) y = 1 + v at y = 1 with the preconditioner D(v).
-//   NT_INNER (sd = S (x o d)): w = x o sd + v o d, the CG step on y; a step
-//     that takes y to or past lo (hi) is cut at that bound and ends the
-//     solve, as does a preconditioned residual below the inner tolerance;
-//     then x <- x o y and the next product is S x.
-__global__ __launch_bounds__(1024) void k_nt_step(const Inst *__restrict__ insts, NtCtl *nt,
-                                                  NtVec V) {
-    __shared__ double sh[1024 / kWave];
-    __shared__ NtCtl c;
-    if (threadIdx.x == 0) c = *nt;
-    __syncthreads();
-    if (c.done != NT_RUN) return;
+// One phase of a step of the Newton / conjugate-gradient iteration, after
+// the product sd of the vector q it asked for. Four phases per step, each a
+// grid-wide pass over the 2n-vectors that ends in per-workgroup partials;
+// the next phase reduces them in a fixed order. Workgroup 0 alone writes
+// the control block, which later phases (next launches) read.
+//   NT_OUTER (sd = S x): 1. v = x o S x, r = 1 - v, |r|_2^2, max |r_i|;
+//     2. stop if max |r_i| <= tol; forcing term eta; start an inner solve
+//     of (D(x) S D(x) + D(v)) y = 1 + v at y = 1 with the preconditioner
+//     D(v): z = r / v, d = z, q = x o d, r . z;  3. rho;  4. next product
+//     S q (the mode changes only in phase 4, for every step).
+//   NT_INNER (sd = S (x o d)): 1. w = x o sd + v o d, d . w;  2. alpha,
+//     the extremes of y + alpha d;  3. a step that takes y to or past lo
+//     (hi) is cut at that bound (its factor reduced here), else the CG
+//     update of y, r, z and r . z;  4. cut: y += gamma alpha d and the
+//     inner solve ends; else rho, and the solve ends below the inner
+//     tolerance (x <- x o y, next product S x) or continues with
+//     d = z + beta d (next product S (x o d)).
+__device__ void nt_phase_body(const Inst *__restrict__ insts, const NtCtl &c, NtCtl &u, NtVec V,
+                              int phase, double *sh) {
     const int n2 = 2 * insts[0].n;
-    const int t = threadIdx.x, T = blockDim.x;
-    bool start_inner = false, end_inner = false;
+    const int G = gridDim.x, gid = blockIdx.x, t = threadIdx.x;
+    const int i0 = gid * kNtThreads + t, stride = G * kNtThreads;
+    const double *prev = V.parts + (size_t)(phase - 1) * kNtMaxGroups * 4;
+    double *mine = V.parts + (size_t)phase * kNtMaxGroups * 4 + gid * 4;
+    const float lo = (float)c.lo, hi = (float)c.hi;
     if (c.mode == NT_OUTER) {
-        double rr = 0.0;
-        float rinf = 0.f;
-        for (int i = t; i < n2; i += T) {
-            const float v = V.x[i] * V.sd[i];
-            const float r = 1.f - v;
-            V.v[i] = v;
-            V.r[i] = r;
-            rr += (double)r * r;
-            rinf = fmaxf(rinf, fabsf(r));
-        }
-        const double rout = nt_sum(rr, sh);
-        const float resinf = nt_max(rinf, sh);
-        __syncthreads();
-        if (t == 0) {
-            c.products += 1;
-            if (!c.first) {
-                const double ratio = rout / c.rold;
-                const double eta_prev = c.eta;
-                double eta = c.g * ratio;
-                if (c.g * eta_prev * eta_prev > 0.1) eta = fmax(eta, c.g * eta_prev * eta_prev);
-                c.eta = fmax(fmin(eta, c.eta_max), 0.5 * c.tol / fmax(sqrt(rout), 1e-300));
+        if (phase == 1) {
+            double rr = 0.0, rinf = 0.0;
+            for (int i = i0; i < n2; i += stride) {
+                const float v = V.x[i] * V.sd[i];
+                const float r = 1.f - v;
+                V.v[i] = v;
+                V.r[i] = r;
+                rr += (double)r * r;
+                rinf = fmax(rinf, (double)fabsf(r));
             }
-            c.first = 0;
-            c.rold = rout;
-            c.rout = rout;
-            c.resinf = resinf;
-            if (resinf <= c.tol) c.done = NT_CONVERGED;
-            else if (!(rout < INFINITY)) c.done = NT_FAILED;
-            else if (c.products >= c.max_products) c.done = NT_CAPPED;
-            c.inner_tol = fmax(c.eta * c.eta * rout, c.tol * c.tol);
+            rr = nt_bsum(rr, sh);
+            rinf = nt_bmax(rinf, sh);
+            if (t == 0) {
+                mine[0] = rr;
+                mine[1] = rinf;
+            }
+        } else if (phase == 2) {
+            const double rout = nt_gsum(prev, 0, sh), resinf = nt_gmax(prev, 1, sh);
+            const int64_t products = c.products + 1;
+            double eta = c.eta;
+            if (!c.first) {
+                const double eta_prev = c.eta;
+                eta = c.g * (rout / c.rold);
+                if (c.g * eta_prev * eta_prev > 0.1) eta = fmax(eta, c.g * eta_prev * eta_prev);
+                eta = fmax(fmin(eta, c.eta_max), 0.5 * c.tol / fmax(sqrt(rout), 1e-300));
+            }
+            int done = NT_RUN;
+            if (resinf <= c.tol) done = NT_CONVERGED;
+            else if (!(rout < INFINITY)) done = NT_FAILED;
+            else if (products >= c.max_products) done = NT_CAPPED;
+            u.products = products;
+            u.eta = eta;
+            u.first = 0;
+            u.rold = rout;
+            u.rout = rout;
+            u.resinf = resinf;
+            u.done = done;
+            u.inner_tol = fmax(eta * eta * rout, c.tol * c.tol);
+            if (done != NT_RUN) return;
+            double rz = 0.0;
+            for (int i = i0; i < n2; i += stride) {
+                const float z = V.r[i] / V.v[i];
+                V.y[i] = 1.f;
+                V.z[i] = z;
+                V.d[i] = z;
+                V.q[i] = V.x[i] * z;
+                rz += (double)V.r[i] * z;
+            }
+            rz = nt_bsum(rz, sh);
+            if (t == 0) mine[0] = rz;
+        } else if (phase == 3) {
+            u.rho = nt_gsum(prev, 0, sh);
+        } else {
+            // the mode changes only in the last phase of a step
+            u.mode = NT_INNER;
         }
-        __syncthreads();
-        start_inner = c.done == NT_RUN;
-    } else {
+        return;
+    }
+    // NT_INNER
+    const double *p1 = V.parts + (size_t)1 * kNtMaxGroups * 4;
+    const double *p2 = V.parts + (size_t)2 * kNtMaxGroups * 4;
+    const double *p3 = V.parts + (size_t)3 * kNtMaxGroups * 4;
+    if (phase == 1) {
         double dw = 0.0;
-        for (int i = t; i < n2; i += T) {
+        for (int i = i0; i < n2; i += stride) {
             const float w = V.x[i] * V.sd[i] + V.v[i] * V.d[i];
             V.w[i] = w;
             dw += (double)V.d[i] * w;
         }
-        const double dsum = nt_sum(dw, sh);
-        const float alpha = (float)(c.rho / dsum);
-        float mn = INFINITY, mx = -INFINITY;
-        for (int i = t; i < n2; i += T) {
+        dw = nt_bsum(dw, sh);
+        if (t == 0) mine[0] = dw;
+        return;
+    }
+    const double dsum = nt_gsum(p1, 0, sh);
+    const float alpha = (float)(c.rho / dsum);
+    if (phase == 2) {
+        double mn = INFINITY, mx = -INFINITY;
+        for (int i = i0; i < n2; i += stride) {
             const float yn = V.y[i] + alpha * V.d[i];
-            mn = fminf(mn, yn);
-            mx = fmaxf(mx, yn);
+            mn = fmin(mn, (double)yn);
+            mx = fmax(mx, (double)yn);
         }
-        mn = nt_min(mn, sh);
-        mx = nt_max(mx, sh);
-        const float lo = (float)c.lo, hi = (float)c.hi;
-        if (!(dsum > 0.0) || !(mn == mn)) {
-            if (t == 0) c.done = NT_FAILED;
-        } else if (mn <= lo || mx >= hi) {
-            // cut the step at the bound it reaches first
-            float gm = INFINITY;
-            for (int i = t; i < n2; i += T) {
+        mn = -nt_bmax(-mn, sh);
+        mx = nt_bmax(mx, sh);
+        if (t == 0) {
+            mine[0] = mn;
+            mine[1] = mx;
+        }
+        return;
+    }
+    const double gmn = nt_gmin(p2, 0, sh);
+    const double gmx = nt_gmax(p2, 1, sh);
+    const bool failed = !(dsum > 0.0) || !(gmn == gmn);
+    const bool cut = !failed && ((float)gmn <= lo || (float)gmx >= hi);
+    if (phase == 3) {
+        if (failed) {
+            u.done = NT_FAILED;
+            return;
+        }
+        if (cut) {
+            // the step's largest fraction that keeps y inside (lo, hi)
+            double gm = INFINITY;
+            for (int i = i0; i < n2; i += stride) {
                 const float st = alpha * V.d[i];
-                if (mn <= lo) {
-                    if (st < 0.f) gm = fminf(gm, (lo - V.y[i]) / st);
+                if ((float)gmn <= lo) {
+                    if (st < 0.f) gm = fmin(gm, (double)((lo - V.y[i]) / st));
                 } else if (V.y[i] + st > hi) {
-                    gm = fminf(gm, (hi - V.y[i]) / st);
+                    gm = fmin(gm, (double)((hi - V.y[i]) / st));
                 }
             }
-            gm = nt_min(gm, sh);
-            if (!(gm < INFINITY)) gm = 1.f;  // reached the bound exactly: the full step
-            for (int i = t; i < n2; i += T) V.y[i] += gm * alpha * V.d[i];
-            end_inner = true;
+            gm = -nt_bmax(-gm, sh);
+            if (t == 0) mine[0] = gm;
         } else {
             double rz = 0.0;
-            for (int i = t; i < n2; i += T) {
+            for (int i = i0; i < n2; i += stride) {
                 V.y[i] += alpha * V.d[i];
                 const float r = V.r[i] - alpha * V.w[i];
                 const float z = r / V.v[i];
@@ -1450,59 +1514,62 @@ __global__ __launch_bounds__(1024) void k_nt_step(const Inst *__restrict__ insts
                 V.z[i] = z;
                 rz += (double)r * z;
             }
-            const double rho = nt_sum(rz, sh);
-            __syncthreads();
-            if (t == 0) {
-                c.rho_prev = c.rho;
-                c.rho = rho;
-            }
-            __syncthreads();
-            end_inner = !(c.rho > c.inner_tol) || c.products + 1 >= c.max_products;
-            if (!end_inner) {
-                const float beta = (float)(c.rho / c.rho_prev);
-                for (int i = t; i < n2; i += T) {
-                    const float d = V.z[i] + beta * V.d[i];
-                    V.d[i] = d;
-                    V.q[i] = V.x[i] * d;
-                }
-            }
+            rz = nt_bsum(rz, sh);
+            if (t == 0) mine[0] = rz;
         }
-        if (t == 0) c.products += 1;
-    }
-    __syncthreads();
-    if (c.done != NT_RUN) {
-        if (t == 0) *nt = c;
         return;
     }
-    if (start_inner) {
-        // y = 1, z = r / v, d = z, rho = r . z; next product S (x o d)
-        double rz = 0.0;
-        for (int i = t; i < n2; i += T) {
-            const float z = V.r[i] / V.v[i];
-            V.y[i] = 1.f;
-            V.z[i] = z;
-            V.d[i] = z;
-            V.q[i] = V.x[i] * z;
-            rz += (double)V.r[i] * z;
+    // phase 4
+    if (cut) {
+        const double gm = nt_gmin(p3, 0, sh);
+        const float f = gm < INFINITY ? (float)gm : 1.f;  // reached the bound exactly: full step
+        for (int i = i0; i < n2; i += stride) {
+            const float x = V.x[i] * (V.y[i] + f * alpha * V.d[i]);
+            V.x[i] = x;
+            V.q[i] = x;
         }
-        const double rho = nt_sum(rz, sh);
-        if (t == 0) {
-            c.rho = rho;
-            c.mode = NT_INNER;
-        }
-    } else if (end_inner) {
-        for (int i = t; i < n2; i += T) {
+        u.products = c.products + 1;
+        u.mode = NT_OUTER;
+        u.outer = c.outer + 1;
+        return;
+    }
+    const double rho = nt_gsum(p3, 0, sh);
+    const bool end = !(rho > c.inner_tol) || c.products + 1 >= c.max_products;
+    if (end) {
+        for (int i = i0; i < n2; i += stride) {
             const float x = V.x[i] * V.y[i];
             V.x[i] = x;
             V.q[i] = x;
         }
-        if (t == 0) {
-            c.mode = NT_OUTER;
-            c.outer += 1;
+    } else {
+        const float beta = (float)(rho / c.rho);
+        for (int i = i0; i < n2; i += stride) {
+            const float d = V.z[i] + beta * V.d[i];
+            V.d[i] = d;
+            V.q[i] = V.x[i] * d;
         }
     }
-    __syncthreads();
-    if (t == 0) *nt = c;
+    u.products = c.products + 1;
+    u.rho_prev = c.rho;
+    u.rho = rho;
+    if (end) {
+        u.mode = NT_OUTER;
+        u.outer = c.outer + 1;
+    }
+}
+
+// The control block is double-buffered by phase parity: a phase reads
+// nt[phase & 1] and workgroup 0 writes the whole updated state to the other
+// copy, so no workgroup of a launch can see a state written in that launch.
+// After phase 4 (and for the product kernels and the host) the current state
+// is nt[1].
+__global__ __launch_bounds__(kNtThreads) void k_nt_phase(const Inst *__restrict__ insts, NtCtl *nt,
+                                                         NtVec V, int phase) {
+    __shared__ double sh[kNtThreads / kWave];
+    const NtCtl c = nt[phase & 1];
+    NtCtl u = c;
+    if (c.done == NT_RUN) nt_phase_body(insts, c, u, V, phase, sh);
+    if (blockIdx.x == 0 && threadIdx.x == 0) nt[(phase + 1) & 1] = u;
 }
 
 // Folds the Newton scalings into the potentials: log u_i += log x_i,
@@ -1573,21 +1640,23 @@ hipError_t launch_col_finalize(const Inst *d_insts, const FinUnit *d_units, int 
 hipError_t launch_nt_product(const Inst *d_insts, const RowUnit *d_rows, int nrows, int row_grid,
                              size_t row_lds, const ColUnit *d_cols, int ncols, int col_grid,
                              const NtCtl *nt, NtVec vec, int n, hipStream_t st) {
+    const NtCtl *cur = nt + 1;  // the state after the last completed step
     hipLaunchKernelGGL(k_nt_rows, dim3(row_grid), dim3(kRowWaves * kWave), row_lds, st, d_insts,
-                       d_rows, nrows, nt, vec.q, vec.sd);
+                       d_rows, nrows, cur, vec.q, vec.sd);
     hipLaunchKernelGGL(k_nt_cols, dim3(col_grid), dim3(kColWaves * kWave), 0, st, d_insts, d_cols,
-                       ncols, nt, vec.q);
-    hipLaunchKernelGGL(k_nt_cols_sum, dim3((n + 255) / 256), dim3(256), 0, st, d_insts, nt, vec.sd);
+                       ncols, cur, vec.q);
+    hipLaunchKernelGGL(k_nt_cols_sum, dim3((n + 255) / 256), dim3(256), 0, st, d_insts, cur, vec.sd);
     return hipGetLastError();
 }
 hipError_t launch_nt_step(const Inst *d_insts, NtCtl *nt, NtVec vec, int n, hipStream_t st) {
-    (void)n;
-    hipLaunchKernelGGL(k_nt_step, dim3(1), dim3(1024), 0, st, d_insts, nt, vec);
+    const int groups = std::max(1, std::min(kNtMaxGroups, (2 * n + 2 * kNtThreads - 1) / (2 * kNtThreads)));
+    for (int ph = 1; ph <= kNtPhases; ++ph)
+        hipLaunchKernelGGL(k_nt_phase, dim3(groups), dim3(kNtThreads), 0, st, d_insts, nt, vec, ph);
     return hipGetLastError();
 }
 hipError_t launch_nt_fold(const Inst *d_insts, const NtCtl *nt, NtVec vec, int n, int last,
                           hipStream_t st) {
-    hipLaunchKernelGGL(k_nt_fold, dim3((n + 255) / 256), dim3(256), 0, st, d_insts, nt, vec.x,
+    hipLaunchKernelGGL(k_nt_fold, dim3((n + 255) / 256), dim3(256), 0, st, d_insts, nt + 1, vec.x,
                        last);
     return hipGetLastError();
 }

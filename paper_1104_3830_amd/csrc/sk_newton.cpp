@@ -3,9 +3,9 @@
 // x o (S x) = 1 for the symmetric embedding S = [[0, X], [X^T, 0]] of the
 // matrix X scaled by the stage's starting potentials, by Newton steps whose
 // linear systems are solved by preconditioned conjugate gradients; the
-// iteration runs on the device (product kernels + a one-workgroup step
-// kernel holding the state) and the host only launches blocks of steps and
-// reads the control block. The scalings found are folded into the
+// iteration runs on the device (product kernels + four short phase kernels
+// per step, the state in a device control block) and the host only launches
+// blocks of steps and reads the control block. The scalings found are folded into the
 // potentials, then p moves on with p^-1 log u and p^-1 log v held fixed.
 #include <vector>
 
@@ -18,13 +18,14 @@ sk_status run_newton_i16(sk_ctx *ctx, Batch &B, const sk_params *prm, Bump &bump
     const Inst &I = B.h_insts[0];
     const int n = I.n;
     const size_t n2 = 2 * (size_t)n;
-    NtCtl *d_nt = bump.take<NtCtl>(1);
+    NtCtl *d_nt = bump.take<NtCtl>(2);  // double-buffered by phase parity; [1] is current
     NtVec V{};
     float **vecs[] = {&V.q, &V.sd, &V.x, &V.v, &V.r, &V.z, &V.d, &V.y, &V.w};
     for (float **p : vecs) *p = bump.take<float>(n2);
     for (float **p : vecs)
         if (!*p) return fail(ctx, SK_ENOMEM, "arena too small for the Newton vectors");
-    if (!d_nt) return fail(ctx, SK_ENOMEM, "arena too small for the Newton state");
+    V.parts = bump.take<double>((size_t)(kNtPhases + 1) * kNtMaxGroups * 4);
+    if (!d_nt || !V.parts) return fail(ctx, SK_ENOMEM, "arena too small for the Newton state");
     const std::vector<float> ones(n2, 1.f);
     const int check = std::max(1, prm->check_every);
     const int64_t bound = prm->max_iters_per_stage / check + 16;
@@ -44,7 +45,8 @@ sk_status run_newton_i16(sk_ctx *ctx, Batch &B, const sk_params *prm, Bump &bump
         init.eta_max = 0.1;
         init.g = 0.9;
         init.eta = 0.1;
-        HIPCHK(ctx, hipMemcpyAsync(d_nt, &init, sizeof init, hipMemcpyHostToDevice, ctx->stream));
+        const NtCtl init2[2] = {init, init};
+        HIPCHK(ctx, hipMemcpyAsync(d_nt, init2, sizeof init2, hipMemcpyHostToDevice, ctx->stream));
         HIPCHK(ctx, hipMemcpyAsync(V.x, ones.data(), sizeof(float) * n2, hipMemcpyHostToDevice,
                                    ctx->stream));
         HIPCHK(ctx, hipMemcpyAsync(V.q, ones.data(), sizeof(float) * n2, hipMemcpyHostToDevice,
@@ -60,7 +62,7 @@ sk_status run_newton_i16(sk_ctx *ctx, Batch &B, const sk_params *prm, Bump &bump
                                                    ctx->stream)));
                 HIPCHK(ctx, PROF(ctx, KID_NT_STEP, launch_nt_step(B.d_insts, d_nt, V, n, ctx->stream)));
             }
-            HIPCHK(ctx, hipMemcpyAsync(&h, d_nt, sizeof h, hipMemcpyDeviceToHost, ctx->stream));
+            HIPCHK(ctx, hipMemcpyAsync(&h, d_nt + 1, sizeof h, hipMemcpyDeviceToHost, ctx->stream));
             HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
             if (h.done != NT_RUN) break;
             if (rounds > bound) return fail(ctx, SK_EDEVICE, "Newton controller did not terminate");

@@ -167,7 +167,8 @@ sk_status run_newton_i16(sk_ctx *ctx, Batch &B, const sk_params *prm, Bump &bump
                          const StageHook *hook = nullptr);
 // Arena bytes of the Newton vectors and state for size n.
 inline size_t newton_bytes(int32_t n) {
-    return 9 * align_up(sizeof(float) * 2 * (size_t)n, 256) + 1024;
+    return 9 * align_up(sizeof(float) * 2 * (size_t)n, 256) +
+           align_up(sizeof(double) * (kNtPhases + 1) * kNtMaxGroups * 4, 256) + 1024;
 }
 sk_status check_fp64(sk_ctx *ctx, Batch &B, int k, sk_report *rep);
 sk_status enqueue_check(sk_ctx *ctx, Batch &B, int k);  // writes B.d_checkout[k]
