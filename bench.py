@@ -2,10 +2,11 @@
 
 One step = one pass of the whole path over one synthetic instance (n = 16384,
 int16 log-weights uniform on 0..1000, seed 0; input resident in HBM before the
-timed region): continuation over the p ladder 1, 2, 4, 8, 16, 32 (tolerance
-1e-5, a fixed per-stage iteration budget), FP64 recheck and certificate,
-reduction at t = 1e-4 to CSR, copy of the CSR to the host, exact solve of the
-reduced instance, and the gamma decision.
+timed region), one sk_solve call: continuation over the p ladder 1, 2, 4, 8,
+16, 32 (tolerance 1e-5, a fixed per-stage iteration budget), FP64 recheck and
+certificate, reduction at t = 1e-4 to CSR, copy of the CSR to the host, exact
+solve of the reduced instance, and the gamma decision. phases_ms times the
+same path once more in its separate calls.
 
 value = algorithmic sweep bytes of the step (n^2 * element bytes per sweep,
 two sweeps per iteration) / wall time of the step, i.e. whole-job throughput of
@@ -419,15 +420,26 @@ def main():
     torch.cuda.synchronize()
 
     def step():
+        # the whole path in one library call (sk_solve)
+        out = ctx.solve(Wd, prm)
+        return out["report"], out["nnz"], out["weight"], out["log_gamma"]
+
+    def phases():
+        """One untimed pass through the same path in its separate calls,
+        with the time of each (milliseconds)."""
+        t = [time.perf_counter()]
         res = ctx.scale(Wd, prm)
+        torch.cuda.synchronize()
+        t.append(time.perf_counter())
         row_ptr, col, w = ctx.prune(Wd, res.potentials, prm)
+        torch.cuda.synchronize()
+        t.append(time.perf_counter())
         rp, cc, ww = row_ptr.cpu().numpy(), col.cpu().numpy(), w.cpu().numpy()
-        try:
-            perm, weight = sk.solve_reduced(rp, cc, ww, n)
-            lg = res.report["ub"] - weight
-        except sk.SkError:
-            weight, lg = None, None
-        return res.report, int(rp[-1]), weight, lg
+        t.append(time.perf_counter())
+        sk.solve_reduced(rp, cc, ww, n)
+        t.append(time.perf_counter())
+        names = ["scale_and_recheck", "prune", "csr_to_host", "exact_solve_host"]
+        return {k: round((t[i + 1] - t[i]) * 1e3, 3) for i, k in enumerate(names)}
 
     for _ in range(args.warmup):
         step()
@@ -443,6 +455,7 @@ def main():
     el = time.perf_counter() - t0
     prof = ctx.profile_read()
     ctx.profile(False)
+    phase_ms = phases()
 
     es = ELEM_BYTES[args.storage]
     # matrix reads per iteration: two sweeps, or one single-pass launch
@@ -483,6 +496,7 @@ def main():
         "matrix_reads_per_iter": reads,
         "nnz_kept": nnz, "weight": weight, "log_gamma": lg,
         "residual_fp64": rep["residual_fp64"],
+        "phases_ms": phase_ms,
         "roofline": roofline, "kernels": kernels,
     }
     ctx.close()

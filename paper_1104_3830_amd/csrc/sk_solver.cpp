@@ -36,20 +36,21 @@ extern "C" sk_status sk_solve_reduced(const sk_csr *csr, int32_t *perm, int64_t 
     const int32_t *col = csr->col;
     const int16_t *w = csr->w;
     if (rp[0] != 0 || rp[n] != csr->nnz) return SK_EINVAL;
-    for (int i = 0; i < n; ++i) {
+    for (int i = 0; i < n; ++i)
         if (rp[i + 1] < rp[i]) return SK_EINVAL;
-        if (rp[i + 1] == rp[i]) return SK_EINFEASIBLE;  // empty row
-    }
-    for (int64_t e = 0; e < csr->nnz; ++e)
-        if (col[e] < 0 || col[e] >= n || w[e] == SK_SENTINEL) return SK_EINVAL;
 
     const int64_t INF = std::numeric_limits<int64_t>::max() / 4;
     std::vector<int64_t> u(n), v(n, 0);
     std::vector<int32_t> row_of(n, -1), col_of(n, -1);
     // u_i = min_j c_ij makes every reduced cost non-negative with v = 0
+    // (and the entries are checked on the way)
     for (int i = 0; i < n; ++i) {
+        if (rp[i + 1] == rp[i]) return SK_EINFEASIBLE;  // empty row
         int64_t m = INF;
-        for (int64_t e = rp[i]; e < rp[i + 1]; ++e) m = std::min<int64_t>(m, -(int64_t)w[e]);
+        for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+            if (col[e] < 0 || col[e] >= n || w[e] == SK_SENTINEL) return SK_EINVAL;
+            m = std::min<int64_t>(m, -(int64_t)w[e]);
+        }
         u[i] = m;
     }
     // column reduction: v_j = min over edges into j of c_ij - u_i keeps every
@@ -63,15 +64,36 @@ extern "C" sk_status sk_solve_reduced(const sk_csr *csr, int32_t *perm, int64_t 
     for (int j = 0; j < n; ++j)
         if (v[j] == INF) return SK_EINFEASIBLE;  // empty column
     // maximum matching on the tight edges (reduced cost 0), Hopcroft-Karp
+    // from a greedy start (each row takes its first free tight column)
     {
-        std::vector<int64_t> tp(n + 1, 0);
-        std::vector<int32_t> tc;
-        tc.reserve((size_t)csr->nnz / 4 + n);
-        for (int i = 0; i < n; ++i) {
+        int64_t ntight = 0;
+        for (int i = 0; i < n; ++i)
             for (int64_t e = rp[i]; e < rp[i + 1]; ++e)
-                if (-(int64_t)w[e] - u[i] - v[col[e]] == 0) tc.push_back(col[e]);
-            tp[i + 1] = (int64_t)tc.size();
+                ntight += (-(int64_t)w[e] - u[i] - v[col[e]] == 0);
+        // when every edge is tight (the usual case for a reduced matrix B)
+        // the matching runs on B's own arrays
+        std::vector<int64_t> tpv;
+        std::vector<int32_t> tcv;
+        const int64_t *tp = rp;
+        const int32_t *tc = col;
+        if (ntight != csr->nnz) {
+            tpv.assign(n + 1, 0);
+            tcv.reserve((size_t)ntight);
+            for (int i = 0; i < n; ++i) {
+                for (int64_t e = rp[i]; e < rp[i + 1]; ++e)
+                    if (-(int64_t)w[e] - u[i] - v[col[e]] == 0) tcv.push_back(col[e]);
+                tpv[i + 1] = (int64_t)tcv.size();
+            }
+            tp = tpv.data();
+            tc = tcv.data();
         }
+        for (int i = 0; i < n; ++i)
+            for (int64_t e = tp[i]; e < tp[i + 1]; ++e)
+                if (row_of[tc[e]] < 0) {
+                    row_of[tc[e]] = i;
+                    col_of[i] = tc[e];
+                    break;
+                }
         const int NIL = std::numeric_limits<int>::max();
         std::vector<int> dist(n), q(n), stack;
         std::vector<int64_t> it(n);
