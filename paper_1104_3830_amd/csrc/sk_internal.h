@@ -23,7 +23,7 @@ enum : uint32_t { ERR_EMPTY_ROW = 1u, ERR_EMPTY_COL = 2u, ERR_RANGE = 4u, ERR_NE
 // Per-instance control block, device memory. Written by the kernels only at
 // the places documented on each field; read by the host between launches.
 struct Ctl {
-    uint32_t res_bits;      // max_i |r_i - 1| of the current iterate (float bits); row sweep atomicMax
+    uint32_t res_bits;      // max_i |r_i - 1| of the current iterate (float bits), from the finalise
     uint32_t rescue_cnt;    // columns whose sum left the safe range in the last column sweep
     uint32_t err;           // ERR_* flags
     uint32_t sent;          // 1: W holds the sentinel (set by the input scan)
@@ -77,7 +77,13 @@ struct Inst {
     float *res_slots;
     float *drift_slots;     // stored K: per row unit max |log2 a_i|
     float *rres;            // [n] |r_i - 1| from the log-domain row sweep
+    // max |r_i - 1| of the log-domain row sweep spread over kRowResSlots
+    // words kRowResStride apart (float bits, atomicMax by each wave; zero
+    // between iterations); the column sweep reduces them
+    uint32_t *rowres;
 };
+constexpr int kRowResSlots = 64;    // = kWave: one wave reduces them
+constexpr int kRowResStride = 32;   // one 128-byte line per slot
 
 // p of iteration m (from 1) of the deformed iteration.
 __device__ __forceinline__ int deform_p(const Inst &I, int64_t m) {
@@ -146,9 +152,10 @@ enum : int { kFinOnePass = 1, kFinStoredK = 2 };
 hipError_t launch_col_finalize(const Inst *d_insts, const FinUnit *d_units, int nunits, int grid,
                                int mode, hipStream_t st);
 hipError_t launch_check_rows(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
-                             double *rsum, double *rmax, size_t lds_bytes, hipStream_t st);
-hipError_t launch_check_cols(const Inst *d_insts, int inst, int n, int nseg, double *part,
-                             double *csum, hipStream_t st);
+                             double *rsum, double *rmax, double logt, int64_t *counts,
+                             int32_t *hint, size_t lds_bytes, hipStream_t st);
+hipError_t launch_check_cols(const Inst *d_insts, int inst, int n, int nseg, int vec8,
+                             double *part, double *csum, hipStream_t st);
 hipError_t launch_prune_count(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
                               double logt, int64_t *counts, size_t lds_bytes, hipStream_t st);
 hipError_t launch_scan(const int64_t *counts, int64_t *row_ptr, int n, hipStream_t st,

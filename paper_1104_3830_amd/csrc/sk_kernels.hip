@@ -283,9 +283,9 @@ __device__ __forceinline__ int row_max_v1(const int16_t *__restrict__ wr, int n,
 // iterate (shift 0): the exact max-shifted recompute if S left the safe
 // range, then the new potentials and the residual.
 template <bool SENT, bool V8>
-__device__ __forceinline__ void row_finish(const Inst &I, int row, int par, int lane, int Fi,
-                                           float S, const ColPot *__restrict__ cp,
-                                           const float *__restrict__ tab) {
+__device__ __forceinline__ float row_finish(const Inst &I, int row, int par, int lane, int Fi,
+                                            float S, const ColPot *__restrict__ cp,
+                                            const float *__restrict__ tab) {
     const int n = I.n;
     const int16_t *wr = I.W + (int64_t)row * I.pitch;
     const int p4 = 4 * I.ctl->p;
@@ -315,12 +315,15 @@ __device__ __forceinline__ void row_finish(const Inst &I, int row, int par, int 
         I.phi[par ^ 1][row] = phin - k;
         // r_i = exp(phi_i + M) S: row sum of the current iterate
         const float r = ex2(fmaf(phi + (float)M, kLog2e, l2S));
-        I.rres[row] = fabsf(r - 1.f);
+        const float res = fabsf(r - 1.f);
+        I.rres[row] = res;
+        return res;
     }
+    return 0.f;
 }
 
 template <bool SENT, bool V8>
-__device__ __forceinline__ void row_step_one(const Inst &I, int row, int par, int lane,
+__device__ __forceinline__ float row_step_one(const Inst &I, int row, int par, int lane,
                                              const ColPot *__restrict__ cp,
                                              const float *__restrict__ tab) {
     const int n = I.n;
@@ -330,7 +333,7 @@ __device__ __forceinline__ void row_step_one(const Inst &I, int row, int par, in
     float S = V8 ? row_partial_v8<SENT>(wr, n, p4, 4 * (Fi - kTabLo), cp, tab, lane)
                  : row_partial_v1<SENT>(wr, n, p4, 4 * (Fi - kTabLo), cp, tab, lane);
     S = wave_sum(S);
-    row_finish<SENT, V8>(I, row, par, lane, Fi, S, cp, tab);
+    return row_finish<SENT, V8>(I, row, par, lane, Fi, S, cp, tab);
 }
 
 // Two rows in one pass over the columns: each column's (4 G_j, exp(gam_j))
@@ -398,7 +401,7 @@ __device__ __forceinline__ void row_partial2_v8(const int16_t *__restrict__ wr0,
 }
 
 template <bool SENT>
-__device__ __forceinline__ void row_step_pair(const Inst &I, int ra, int rb, int par, int lane,
+__device__ __forceinline__ float row_step_pair(const Inst &I, int ra, int rb, int par, int lane,
                                               const ColPot *__restrict__ cp,
                                               const float *__restrict__ tab) {
     const int n = I.n;
@@ -409,13 +412,17 @@ __device__ __forceinline__ void row_step_pair(const Inst &I, int ra, int rb, int
                           4 * (Fa - kTabLo), 4 * (Fb - kTabLo), cp, tab, lane, Sa, Sb);
     Sa = wave_sum(Sa);
     Sb = wave_sum(Sb);
-    row_finish<SENT, true>(I, ra, par, lane, Fa, Sa, cp, tab);
-    row_finish<SENT, true>(I, rb, par, lane, Fb, Sb, cp, tab);
+    const float ea = row_finish<SENT, true>(I, ra, par, lane, Fa, Sa, cp, tab);
+    const float eb = row_finish<SENT, true>(I, rb, par, lane, Fb, Sb, cp, tab);
+    return fmaxf(ea, eb);
 }
 
 // Waves run their rows independently: the only barrier is the restaging of
 // the column data when the instance changes. The residual |r_i - 1| goes to
-// rres[i]; the column sweep reduces it per row segment.
+// rres[i] (the column sweep reduces it per row segment for the finalise) and
+// each wave's maximum to one of the instance's rowres slots (an exact
+// maximum, so the column sweep's reduction of the slots equals the
+// finalise's value; it uses it to skip a detection pass).
 __global__ __launch_bounds__(kRowWaves * kWave) void k_row_sweep(const Inst *__restrict__ insts,
                                                                    const RowUnit *__restrict__ units,
                                                                    int nunits) {
@@ -424,8 +431,21 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_row_sweep(const Inst *__r
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     int u0, u1;
     unit_range(nunits, u0, u1);
+    __shared__ unsigned wg_res, wg_done;
+    if (threadIdx.x == 0) {
+        wg_res = 0u;
+        wg_done = 0u;
+    }
     fill_exp_table(tab);
+    __syncthreads();
     int cur = -1;
+    float wres = 0.f;  // this wave's residual maximum for instance `cur` (lane 0)
+    const int slot = (int)((blockIdx.x * kRowWaves + wave) % kRowResSlots) * kRowResStride;
+    auto flush = [&]() {
+        if (cur >= 0 && lane == 0 && wres > 0.f)
+            atomicMax(&insts[cur].rowres[slot], __float_as_uint(wres));
+        wres = 0.f;
+    };
     for (int u = u0; u < u1;) {
         const RowUnit un = units[u];
         const Inst &I = insts[un.inst];
@@ -437,6 +457,7 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_row_sweep(const Inst *__r
         const int n = I.n;
         const int iter = ctl->iter;
         if (un.inst != cur) {
+            flush();
             __syncthreads();
             const int n8 = n >> 3;
             for (int j = threadIdx.x; j < n; j += blockDim.x) {
@@ -454,19 +475,33 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_row_sweep(const Inst *__r
         // the next unit of the same instance is done in the same pass
         const bool pair = SK_ROW_PAIR && I.vec8 && u + 1 < u1 && units[u + 1].inst == un.inst;
         const int rb = pair ? units[u + 1].row0 + wave : n;
+        float e = 0.f;
         if (rb < n) {
-            if (sent) row_step_pair<true>(I, ra, rb, par, lane, lds_cp, tab);
-            else row_step_pair<false>(I, ra, rb, par, lane, lds_cp, tab);
+            e = sent ? row_step_pair<true>(I, ra, rb, par, lane, lds_cp, tab)
+                     : row_step_pair<false>(I, ra, rb, par, lane, lds_cp, tab);
         } else if (ra < n) {
             if (I.vec8) {
-                if (sent) row_step_one<true, true>(I, ra, par, lane, lds_cp, tab);
-                else row_step_one<false, true>(I, ra, par, lane, lds_cp, tab);
+                e = sent ? row_step_one<true, true>(I, ra, par, lane, lds_cp, tab)
+                         : row_step_one<false, true>(I, ra, par, lane, lds_cp, tab);
             } else {
-                if (sent) row_step_one<true, false>(I, ra, par, lane, lds_cp, tab);
-                else row_step_one<false, false>(I, ra, par, lane, lds_cp, tab);
+                e = sent ? row_step_one<true, false>(I, ra, par, lane, lds_cp, tab)
+                         : row_step_one<false, false>(I, ra, par, lane, lds_cp, tab);
             }
         }
+        wres = fmaxf(wres, e);
         u += pair ? 2 : 1;
+    }
+    // every wave ends on the same instance: the waves' maxima meet in LDS and
+    // the last wave to finish sends the workgroup's to the slot
+    if (lane == 0) {
+        if (wres > 0.f) atomicMax(&wg_res, __float_as_uint(wres));
+        __threadfence_block();
+        const unsigned k = atomicAdd(&wg_done, 1u);
+        if (k == kRowWaves - 1) {
+            __threadfence_block();
+            const unsigned m = atomicMax(&wg_res, 0u);  // read after every wave's update
+            if (cur >= 0 && m > 0u) atomicMax(&insts[cur].rowres[slot], m);
+        }
     }
 }
 
@@ -588,6 +623,7 @@ __global__ __launch_bounds__(kColWaves * kWave) void k_col_sweep(const Inst *__r
     __shared__ RowPot rowpot[kMaxSegRows];
     __shared__ float tab[kTabN];
     __shared__ float wmax[kColWaves];
+    __shared__ float rowres_max;
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     int u0, u1;
     unit_range(nunits, u0, u1);
@@ -617,6 +653,11 @@ __global__ __launch_bounds__(kColWaves * kWave) void k_col_sweep(const Inst *__r
             rm = wave_max(rm);
             if (lane == 0) wmax[wave] = rm;
         }
+        if (wave == 0) {
+            // the row sweep's residual (see k_row_sweep)
+            const float rr = wave_max(__uint_as_float(I.rowres[lane * kRowResStride]));
+            if (lane == 0) rowres_max = rr;
+        }
         __syncthreads();
         if (un.tile == 0 && threadIdx.x == 0) {
             float m = wmax[0];
@@ -624,6 +665,9 @@ __global__ __launch_bounds__(kColWaves * kWave) void k_col_sweep(const Inst *__r
             for (int w2 = 1; w2 < kColWaves; ++w2) m = fmaxf(m, wmax[w2]);
             I.res_slots[un.seg] = m;
         }
+        // the row sweep measured a converged iterate: the finalise will end
+        // the stage without a column step, so no column sums are needed
+        if (ctl->iter >= 1 && rowres_max < I.tol && deform_settled(I, ctl)) continue;
         float acc[8];
         const bool sent = ctl->sent != 0u;
         if (I.vec8) {
@@ -796,9 +840,13 @@ __device__ void end_stage(const Inst &I, Ctl *ctl, int par) {
     }
 }
 
-__global__ __launch_bounds__(256) void k_iter_end(const Inst *__restrict__ insts) {
-    __shared__ int redi[256];
-    __shared__ float red[256];
+// One workgroup of kIterEndThreads per instance (the FP64 rescaling of all
+// potentials at a stage change is spread over all of them).
+constexpr int kIterEndThreads = 1024;
+
+__global__ __launch_bounds__(kIterEndThreads) void k_iter_end(const Inst *__restrict__ insts) {
+    __shared__ int redi[kIterEndThreads];
+    __shared__ float red[kIterEndThreads];
     __shared__ float tab[kTabN];
     const Inst &I = insts[blockIdx.x];
     Ctl *ctl = I.ctl;
@@ -825,7 +873,7 @@ __global__ __launch_bounds__(256) void k_iter_end(const Inst *__restrict__ insts
         __syncthreads();
         redi[threadIdx.x] = m;
         __syncthreads();
-        for (int o = 128; o > 0; o >>= 1) {
+        for (int o = kIterEndThreads / 2; o > 0; o >>= 1) {
             if ((int)threadIdx.x < o) redi[threadIdx.x] = max(redi[threadIdx.x], redi[threadIdx.x + o]);
             __syncthreads();
         }
@@ -857,6 +905,7 @@ __global__ __launch_bounds__(256) void k_iter_end(const Inst *__restrict__ insts
         }
         __syncthreads();
     }
+    for (int q = threadIdx.x; q < kRowResSlots; q += blockDim.x) I.rowres[q * kRowResStride] = 0u;
     __syncthreads();
     if (threadIdx.x == 0) {
         ctl->rescue_cnt = 0u;
@@ -909,10 +958,14 @@ __device__ __forceinline__ double logv_at(const Inst &I, const double *lv, int j
     return lv[I.vec8 ? swz8(j, I.n >> 3) : j];
 }
 
+// With counts != nullptr it also counts the entries with log x_ij >= logt
+// (the row lengths of B for the scan) and stores in hint[i] the first column
+// of the row's largest x_ij (a starting matching for the exact solve).
 __global__ __launch_bounds__(kRowWaves * kWave) void k_check_rows(const Inst *__restrict__ insts,
                                                                     const RowUnit *__restrict__ units,
                                                                     int nunits, double *rsum,
-                                                                    double *rmax) {
+                                                                    double *rmax, double logt,
+                                                                    int64_t *counts, int32_t *hint) {
     extern __shared__ double lv[];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     int u0, u1;
@@ -934,18 +987,38 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_check_rows(const Inst *__
         const double f = (double)I.F[par][row] + (double)I.phi[par][row];
         const int16_t *wr = I.W + (int64_t)row * I.pitch;
         double s = 0.0, m = -INFINITY;
+        int jm = -1, cnt = 0;
         visit_row(I, wr, lane, [&](int j, int w) {
             if (w == SK_SENTINEL) return;
-            const double t = p * (double)w + logv_at(I, lv, j);
+            const double pw = p * (double)w, lvj = logv_at(I, lv, j);
+            const double t = pw + lvj;
             const double lx = t + f;
             if (lx > kNegligibleLog) s += exp(lx);
-            m = fmax(m, t);
+            // the kept test in the exact arithmetic order of the fill kernel
+            cnt += (pw + f + lvj >= logt);
+            if (t > m) {  // a lane visits its columns in increasing order
+                m = t;
+                jm = j;
+            }
         });
         s = wave_sum_d(s);
-        m = wave_max_d(m);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const double m2 = __shfl_xor(m, o, kWave);
+            const int j2 = __shfl_xor(jm, o, kWave);
+            if (m2 > m || (m2 == m && (unsigned)j2 < (unsigned)jm)) {
+                m = m2;
+                jm = j2;
+            }
+            cnt += __shfl_xor(cnt, o, kWave);
+        }
         if (lane == 0) {
             rsum[row] = s;
             rmax[row] = m;
+            if (counts) {
+                counts[row] = cnt;
+                hint[row] = jm;
+            }
         }
     }
 }
@@ -984,6 +1057,82 @@ __global__ __launch_bounds__(256) void k_check_cols_sum(const Inst *__restrict__
     double s = 0.0;
     for (int seg = 0; seg < I.nseg; ++seg) s += part[(int64_t)seg * n + j];
     csum[j] = s;
+}
+
+// The same slots from 8 columns per lane (16-byte loads along each row) with
+// the segment's rows split over four waves and the waves' sums added in a
+// fixed order. The exact integer part E = p w_ij + F_i + G_j decides first:
+// |phi_i|, |gam_j| <= 1/2, so E < kCheckSkip gives log x_ij < kNegligibleLog.
+constexpr int kCheckSkip = -50;
+
+__device__ __forceinline__ void check_cols_add8(const int4 v, int p, int2 rf, const int (&G)[8],
+                                                const double (&gm)[8], double (&s)[8]) {
+    int w[8];
+    unpack8i(v, w);
+    const double ph = (double)__int_as_float(rf.y);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int E = p * w[c] + rf.x + G[c];
+        if (w[c] != SK_SENTINEL && E >= kCheckSkip) {
+            const double lx = (double)E + (ph + gm[c]);
+            if (lx > kNegligibleLog) s[c] += exp(lx);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kColWaves * kWave) void k_check_cols_part8(const Inst *__restrict__ insts,
+                                                                        int inst, double *part) {
+    __shared__ double red[kColWaves][kColTile8];
+    __shared__ int2 rowf[kMaxSegRows];
+    const Inst &I = insts[inst];
+    const int n = I.n;
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int ctile0 = blockIdx.x * kColTile8;
+    const int seg = blockIdx.y;
+    const int r0 = seg * I.seg_rows, r1 = min(n, r0 + I.seg_rows);
+    const int par = I.ctl->iter & 1;
+    const int p = I.ctl->p;
+    for (int r = r0 + (int)threadIdx.x; r < r1; r += blockDim.x)
+        rowf[r - r0] = make_int2(I.F[par][r], __float_as_int(I.phi[par][r]));
+    __syncthreads();
+    const int j0 = ctile0 + lane * 8;
+    double s[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) s[c] = 0.0;
+    if (j0 < n) {  // n % 8 == 0: all 8 columns exist
+        int G[8];
+        double gm[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            G[c] = I.G[j0 + c];
+            gm[c] = (double)I.gam[j0 + c];
+        }
+        const int16_t *w0 = I.W + j0;
+        int r = r0 + wave;
+        for (; r + 3 * kColWaves < r1; r += 4 * kColWaves) {
+            int4 v[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                v[k] = gload(reinterpret_cast<const int4 *>(w0 + (int64_t)(r + k * kColWaves) * I.pitch));
+#pragma unroll
+            for (int k = 0; k < 4; ++k) check_cols_add8(v[k], p, rowf[r + k * kColWaves - r0], G, gm, s);
+        }
+        for (; r < r1; r += kColWaves) {
+            const int4 v = gload(reinterpret_cast<const int4 *>(w0 + (int64_t)r * I.pitch));
+            check_cols_add8(v, p, rowf[r - r0], G, gm, s);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) red[wave][lane * 8 + c] = s[c];
+    __syncthreads();
+    double *dst = part + (int64_t)seg * n + ctile0;
+    const int ncols = min(kColTile8, n - ctile0);
+    for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
+        double t = red[0][c];
+#pragma unroll
+        for (int w2 = 1; w2 < kColWaves; ++w2) t += red[w2][c];
+        dst[c] = t;
+    }
 }
 
 // Reduces the FP64 check of one instance to four numbers, in a fixed order:
@@ -1206,6 +1355,7 @@ __global__ __launch_bounds__(256) void k_reset_ctl(const Inst *__restrict__ inst
                                                    int m) {
     for (int q = blockIdx.x; q < m; q += gridDim.x) {
         const Inst &I = insts[idx ? idx[q] : q];
+        for (int q = threadIdx.x; q < kRowResSlots; q += blockDim.x) I.rowres[q * kRowResStride] = 0u;
         if (threadIdx.x == 0) {
             Ctl c;
             memset(&c, 0, sizeof c);
@@ -1661,13 +1811,14 @@ hipError_t launch_nt_fold(const Inst *d_insts, const NtCtl *nt, NtVec vec, int n
     return hipGetLastError();
 }
 hipError_t launch_iter_end(const Inst *d_insts, int count, hipStream_t st) {
-    hipLaunchKernelGGL(k_iter_end, dim3(count), dim3(256), 0, st, d_insts);
+    hipLaunchKernelGGL(k_iter_end, dim3(count), dim3(kIterEndThreads), 0, st, d_insts);
     return hipGetLastError();
 }
 hipError_t launch_check_rows(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
-                             double *rsum, double *rmax, size_t lds_bytes, hipStream_t st) {
+                             double *rsum, double *rmax, double logt, int64_t *counts,
+                             int32_t *hint, size_t lds_bytes, hipStream_t st) {
     hipLaunchKernelGGL(k_check_rows, dim3(grid), dim3(kRowWaves * kWave), lds_bytes, st, d_insts, d_units,
-                       nunits, rsum, rmax);
+                       nunits, rsum, rmax, logt, counts, hint);
     return hipGetLastError();
 }
 hipError_t launch_check_reduce(const Inst *d_insts, int inst, const double *rsum,
@@ -1675,10 +1826,14 @@ hipError_t launch_check_reduce(const Inst *d_insts, int inst, const double *rsum
     hipLaunchKernelGGL(k_check_reduce, dim3(1), dim3(256), 0, st, d_insts, inst, rsum, rmax, csum, out);
     return hipGetLastError();
 }
-hipError_t launch_check_cols(const Inst *d_insts, int inst, int n, int nseg, double *part,
-                             double *csum, hipStream_t st) {
-    hipLaunchKernelGGL(k_check_cols_part, dim3((n + 255) / 256, nseg), dim3(256), 0, st, d_insts,
-                       inst, part);
+hipError_t launch_check_cols(const Inst *d_insts, int inst, int n, int nseg, int vec8,
+                             double *part, double *csum, hipStream_t st) {
+    if (vec8)
+        hipLaunchKernelGGL(k_check_cols_part8, dim3((n + kColTile8 - 1) / kColTile8, nseg),
+                           dim3(kColWaves * kWave), 0, st, d_insts, inst, part);
+    else
+        hipLaunchKernelGGL(k_check_cols_part, dim3((n + 255) / 256, nseg), dim3(256), 0, st, d_insts,
+                           inst, part);
     hipLaunchKernelGGL(k_check_cols_sum, dim3((n + 255) / 256), dim3(256), 0, st, d_insts, inst,
                        part, csum);
     return hipGetLastError();

@@ -598,22 +598,22 @@ sk_status run_single_k(sk_ctx *ctx, Batch &B, const sk_params *prm, const StageH
                 ctx->prof.end(ctx->stream);
 
             } else {
-                ctx->prof.begin(ctx->stream, KID_ROW_K);
+                // the two sweeps share the stamp between them
+                Profiler &pf = ctx->prof;
+                const int s0 = pf.stamp(ctx->stream);
                 KCHK(launch_row_sweep_k(B.d_insts, B.d_rows, (int)B.h_rows.size(), B.row_grid_k,
                                         B.row_lds_k, storage, ctx->stream));
-                ctx->prof.end(ctx->stream);
-                ctx->prof.begin(ctx->stream, KID_COL_K);
+                const int s1 = pf.stamp(ctx->stream);
                 KCHK(launch_col_sweep_k(B.d_insts, B.d_cols, (int)B.h_cols.size(), B.col_grid,
                                         storage, ctx->stream));
-                ctx->prof.end(ctx->stream);
+                const int s2 = pf.stamp(ctx->stream);
+                pf.add(KID_ROW_K, s0, s1);
+                pf.add(KID_COL_K, s1, s2);
             }
-            ctx->prof.begin(ctx->stream, KID_FINALIZE);
+            // finalise and end of iteration: short, not stamped
             KCHK(launch_col_finalize(B.d_insts, B.d_fins, (int)B.h_fins.size(), B.fin_grid,
                                      kFinStoredK | (I0.fused ? kFinOnePass : 0), ctx->stream));
-            ctx->prof.end(ctx->stream);
-            ctx->prof.begin(ctx->stream, KID_ITER_END);
             KCHK(launch_iter_end(B.d_insts, B.count, ctx->stream));
-            ctx->prof.end(ctx->stream);
         }
         if (ctx->prof.on) {
             if ((st = read_ctl(ctx, B)) != SK_OK) return st;

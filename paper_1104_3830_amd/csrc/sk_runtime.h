@@ -71,14 +71,20 @@ enum KernelId {
 };
 extern const char *kKernelNames[KID_COUNT];
 
-// HIP-event timing of launches on the context stream.
+// HIP-event timing of launches on the context stream. Each recorded event
+// is a stamp; a timed launch is the interval between two stamps, and
+// back-to-back launches share the stamp between them (each stamp is a
+// timestamp packet in the stream, so fewer stamps cost the stream less).
 struct Profiler {
     bool on = false;
-    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+    std::vector<hipEvent_t> stamps;
+    std::vector<std::pair<int, std::pair<int, int>>> pending;  // (kernel id, (stamp, stamp))
     std::vector<hipEvent_t> pool;
     int64_t launches[KID_COUNT] = {};
     double total_ms[KID_COUNT] = {};
     hipEvent_t take();
+    int stamp(hipStream_t st);                // index of a new stamp, -1 when off
+    void add(int id, int from, int to);       // launch `id` ran between two stamps
     void begin(hipStream_t st, int id);
     void end(hipStream_t st);
     void drain();   // call after the stream is synchronised
@@ -96,7 +102,7 @@ struct Profiler {
     }
     ~Profiler();
     int cur_id = -1;
-    hipEvent_t cur_start = nullptr;
+    int cur_start = -1;
 };
 
 }  // namespace sk
@@ -170,8 +176,21 @@ inline size_t newton_bytes(int32_t n) {
     return 9 * align_up(sizeof(float) * 2 * (size_t)n, 256) +
            align_up(sizeof(double) * (kNtPhases + 1) * kNtMaxGroups * 4, 256) + 1024;
 }
+// Extra outputs of the FP64 row check: per row the number of entries with
+// log x_ij >= logt (device int64[n]) and the first column of the largest x_ij
+// (device int32[n]).
+struct CheckCounts {
+    double logt;
+    int64_t *counts;
+    int32_t *hint;
+};
+// sk_solve_reduced with a column per row to try first in the greedy start
+// of the matching (nullptr: none).
+sk_status solve_reduced_seeded(const sk_csr *csr, const int32_t *hint, int32_t *perm,
+                               int64_t *weight);
 sk_status check_fp64(sk_ctx *ctx, Batch &B, int k, sk_report *rep);
-sk_status enqueue_check(sk_ctx *ctx, Batch &B, int k);  // writes B.d_checkout[k]
+// writes B.d_checkout[k] (and the counts when cc != nullptr)
+sk_status enqueue_check(sk_ctx *ctx, Batch &B, int k, const CheckCounts *cc = nullptr);
 void report_from_check(const double *out4, int p, sk_report *rep);
 void fill_report(const Ctl &c, sk_report *rep);
 sk_status copy_potentials_out(sk_ctx *ctx, Batch &B, int k, void *pot);

@@ -54,6 +54,7 @@ size_t instance_bytes(int32_t n, int vec8, int storage, int fused) {
     b += align_up(sizeof(Ctl), 256);
     b += align_up(sizeof(float) * std::max((n + kRowWaves - 1) / kRowWaves, kFusedSlots), 256) * 2;
     b += align_up(sizeof(float) * n, 256);  // rres
+    b += align_up(sizeof(uint32_t) * kRowResSlots * kRowResStride, 256);  // rowres
     if (storage == SK_K_BF16 || storage == SK_K_F32) {
         const size_t es = storage == SK_K_BF16 ? 2 : 4;
         const size_t kp = (size_t)(n + 7) / 8 * 8;
@@ -109,31 +110,42 @@ hipEvent_t Profiler::take() {
     if (hipEventCreate(&e) != hipSuccess) return nullptr;
     return e;
 }
+int Profiler::stamp(hipStream_t st) {
+    if (!on) return -1;
+    hipEvent_t e = take();
+    if (!e) return -1;
+    if (hipEventRecord(e, st) != hipSuccess) {
+        pool.push_back(e);
+        return -1;
+    }
+    stamps.push_back(e);
+    return (int)stamps.size() - 1;
+}
+void Profiler::add(int id, int from, int to) {
+    if (from >= 0 && to >= 0) pending.push_back({id, {from, to}});
+}
 void Profiler::begin(hipStream_t st, int id) {
     if (!on) return;
     cur_id = id;
-    cur_start = take();
-    if (cur_start) (void)hipEventRecord(cur_start, st);
+    cur_start = stamp(st);
 }
 void Profiler::end(hipStream_t st) {
-    if (!on || !cur_start) return;
-    hipEvent_t e = take();
-    if (!e) return;
-    (void)hipEventRecord(e, st);
-    pending.push_back({cur_id, {cur_start, e}});
-    cur_start = nullptr;
+    if (!on || cur_start < 0) return;
+    add(cur_id, cur_start, stamp(st));
+    cur_start = -1;
 }
 void Profiler::drain() {
     for (auto &p : pending) {
         float ms = 0.f;
-        if (hipEventElapsedTime(&ms, p.second.first, p.second.second) == hipSuccess) {
+        if (hipEventElapsedTime(&ms, stamps[p.second.first], stamps[p.second.second]) == hipSuccess) {
             launches[p.first] += 1;
             total_ms[p.first] += ms;
         }
-        pool.push_back(p.second.first);
-        pool.push_back(p.second.second);
     }
+    for (hipEvent_t e : stamps) pool.push_back(e);
+    stamps.clear();
     pending.clear();
+    cur_start = -1;
 }
 void Profiler::reset() {
     drain();
@@ -143,10 +155,7 @@ void Profiler::reset() {
     }
 }
 Profiler::~Profiler() {
-    for (auto &p : pending) {
-        (void)hipEventDestroy(p.second.first);
-        (void)hipEventDestroy(p.second.second);
-    }
+    for (auto e : stamps) (void)hipEventDestroy(e);
     for (auto e : pool) (void)hipEventDestroy(e);
 }
 
@@ -331,7 +340,8 @@ bool sk::carve_instance(Bump &bump, const int16_t *W, int64_t pitch, int32_t nn,
     I.res_slots = bump.take<float>(std::max(nrows_units, kFusedSlots));
     I.drift_slots = bump.take<float>(std::max(nrows_units, kFusedSlots));
     I.rres = bump.take<float>(nn);
-    if (!I.res_slots || !I.drift_slots || !I.rres) return false;
+    I.rowres = bump.take<uint32_t>((size_t)kRowResSlots * kRowResStride);
+    if (!I.res_slots || !I.drift_slots || !I.rres || !I.rowres) return false;
     if (!I.F[0] || !I.F[1] || !I.phi[0] || !I.phi[1] || !I.G || !I.gam || !I.colpart ||
         !I.rescue || !I.ctl)
         return false;
@@ -455,19 +465,26 @@ sk_status sk::iterate_i16(sk_ctx *ctx, Batch &B) {
         const Inst &I = B.h_insts[0];
         HIPCHK(ctx, PROF(ctx, KID_FUSED, launch_fused(B.d_insts, 0, I.n, I.fused_grid, SK_W_I16,
                                                       ctx->stream)));
-        HIPCHK(ctx, PROF(ctx, KID_FINALIZE, launch_col_finalize(B.d_insts, B.d_fins,
-                                                                (int)B.h_fins.size(), B.fin_grid,
-                                                                kFinOnePass, ctx->stream)));
-        HIPCHK(ctx, PROF(ctx, KID_ITER_END, launch_iter_end(B.d_insts, B.count, ctx->stream)));
+        HIPCHK(ctx, launch_col_finalize(B.d_insts, B.d_fins, (int)B.h_fins.size(), B.fin_grid,
+                                        kFinOnePass, ctx->stream));
+        HIPCHK(ctx, launch_iter_end(B.d_insts, B.count, ctx->stream));
         return SK_OK;
     }
-    HIPCHK(ctx, PROF(ctx, KID_ROW, launch_row_sweep(B.d_insts, B.d_rows, (int)B.h_rows.size(), B.row_grid, B.row_lds,
-                                 ctx->stream)));
-    HIPCHK(ctx, PROF(ctx, KID_COL, launch_col_sweep(B.d_insts, B.d_cols, (int)B.h_cols.size(), B.col_grid,
-                                 ctx->stream)));
-    HIPCHK(ctx, PROF(ctx, KID_FINALIZE, launch_col_finalize(B.d_insts, B.d_fins, (int)B.h_fins.size(),
-                                                            B.fin_grid, 0, ctx->stream)));
-    HIPCHK(ctx, PROF(ctx, KID_ITER_END, launch_iter_end(B.d_insts, B.count, ctx->stream)));
+    // timed: the two sweeps, with one stamp between them; the short
+    // finalise and end-of-iteration launches are not stamped
+    Profiler &pf = ctx->prof;
+    const int s0 = pf.stamp(ctx->stream);
+    HIPCHK(ctx, launch_row_sweep(B.d_insts, B.d_rows, (int)B.h_rows.size(), B.row_grid, B.row_lds,
+                                 ctx->stream));
+    const int s1 = pf.stamp(ctx->stream);
+    HIPCHK(ctx, launch_col_sweep(B.d_insts, B.d_cols, (int)B.h_cols.size(), B.col_grid,
+                                 ctx->stream));
+    const int s2 = pf.stamp(ctx->stream);
+    pf.add(KID_ROW, s0, s1);
+    pf.add(KID_COL, s1, s2);
+    HIPCHK(ctx, launch_col_finalize(B.d_insts, B.d_fins, (int)B.h_fins.size(), B.fin_grid, 0,
+                                    ctx->stream));
+    HIPCHK(ctx, launch_iter_end(B.d_insts, B.count, ctx->stream));
     return SK_OK;
 }
 
@@ -532,18 +549,20 @@ sk_status sk::run_batch_i16(sk_ctx *ctx, Batch &B, const sk_params *prm, int fir
 
 // FP64 recheck of instance k (enqueued): row and column sums of the balanced
 // matrix and the certificate terms, reduced on the device into B.d_checkout[k].
-sk_status sk::enqueue_check(sk_ctx *ctx, Batch &B, int k) {
+sk_status sk::enqueue_check(sk_ctx *ctx, Batch &B, int k, const CheckCounts *cc) {
     const Inst &I = B.h_insts[k];
     const int nn = I.n;
     size_t first = 0;
     while (first < B.h_rows.size() && B.h_rows[first].inst != k) ++first;
     const int nunits = (nn + kRowWaves - 1) / kRowWaves;
     const int grid = std::min(nunits, ctx->num_cus * 2);
-    HIPCHK(ctx, PROF(ctx, KID_CHECK_ROWS, launch_check_rows(B.d_insts, B.d_rows + first, nunits, grid,
-                                                            B.d_rsum, B.d_rmax,
-                                                            sizeof(double) * (size_t)nn, ctx->stream)));
-    HIPCHK(ctx, PROF(ctx, KID_CHECK_COLS, launch_check_cols(B.d_insts, k, nn, I.nseg, B.d_cpart,
-                                                            B.d_csum, ctx->stream)));
+    HIPCHK(ctx, PROF(ctx, KID_CHECK_ROWS,
+                     launch_check_rows(B.d_insts, B.d_rows + first, nunits, grid, B.d_rsum,
+                                       B.d_rmax, cc ? cc->logt : 0.0, cc ? cc->counts : nullptr,
+                                       cc ? cc->hint : nullptr, sizeof(double) * (size_t)nn,
+                                       ctx->stream)));
+    HIPCHK(ctx, PROF(ctx, KID_CHECK_COLS, launch_check_cols(B.d_insts, k, nn, I.nseg, I.vec8,
+                                                            B.d_cpart, B.d_csum, ctx->stream)));
     HIPCHK(ctx, launch_check_reduce(B.d_insts, k, B.d_rsum, B.d_rmax, B.d_csum,
                                     B.d_checkout + 4 * (size_t)k, ctx->stream));
     return SK_OK;

@@ -31,27 +31,32 @@ struct StageResult {
 
 // B at threshold t from the committed potentials of instance 0, its CSR on
 // the host, and an exact optimum of B (feasible = B has a perfect matching).
-sk_status reduce_and_solve(sk_ctx *ctx, Batch &B, Bump rest, double t, StageResult &r) {
+// With counted, the row lengths of B are already in B.d_counts, their scan in
+// d_rp and the entry count in ctx->h_nnz[0] (the FP64 check made them).
+// d_hint: per row the column of its largest x_ij, the start of the matching.
+sk_status reduce_and_solve(sk_ctx *ctx, Batch &B, Bump &rest, int64_t *d_rp, const int32_t *d_hint,
+                           double t, bool counted, StageResult &r) {
     const Inst &I = B.h_insts[0];
     const int n = I.n;
-    int64_t *d_rp = rest.take<int64_t>((size_t)n + 1);
-    if (!d_rp) return fail(ctx, SK_ENOMEM, "arena too small for the reduced matrix (row pointers)");
     const double logt = std::log(t);
     const int nunits = (int)B.h_rows.size();
     const size_t lds = sizeof(double) * (size_t)n;
-    HIPCHK(ctx, PROF(ctx, KID_PRUNE_COUNT, launch_prune_count(B.d_insts, B.d_rows, nunits, B.row_grid,
-                                                             logt, B.d_counts, lds, ctx->stream)));
-    HIPCHK(ctx, PROF(ctx, KID_SCAN, launch_scan(B.d_counts, d_rp, n, ctx->stream, B.d_nnz)));
-    HIPCHK(ctx, hipMemcpyAsync(ctx->h_nnz, B.d_nnz, sizeof(int64_t), hipMemcpyDeviceToHost,
-                               ctx->stream));
-    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if (!counted) {
+        HIPCHK(ctx, PROF(ctx, KID_PRUNE_COUNT, launch_prune_count(B.d_insts, B.d_rows, nunits, B.row_grid,
+                                                                 logt, B.d_counts, lds, ctx->stream)));
+        HIPCHK(ctx, PROF(ctx, KID_SCAN, launch_scan(B.d_counts, d_rp, n, ctx->stream, B.d_nnz)));
+        HIPCHK(ctx, hipMemcpyAsync(ctx->h_nnz, B.d_nnz, sizeof(int64_t), hipMemcpyDeviceToHost,
+                                   ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    }
     const int64_t nnz = ctx->h_nnz[0];
     std::vector<int64_t> rp((size_t)n + 1);
-    std::vector<int32_t> col((size_t)nnz);
+    std::vector<int32_t> col((size_t)nnz), hint((size_t)n);
     std::vector<int16_t> w((size_t)nnz);
     if (nnz > 0) {
-        int32_t *d_col = rest.take<int32_t>((size_t)nnz);
-        int16_t *d_w = rest.take<int16_t>((size_t)nnz);
+        Bump tmp = rest;  // the entries are scratch until copied out
+        int32_t *d_col = tmp.take<int32_t>((size_t)nnz);
+        int16_t *d_w = tmp.take<int16_t>((size_t)nnz);
         if (!d_col || !d_w)
             return fail(ctx, SK_ENOMEM, "the reduced matrix keeps %lld entries; the arena cannot hold them",
                         (long long)nnz);
@@ -64,12 +69,14 @@ sk_status reduce_and_solve(sk_ctx *ctx, Batch &B, Bump rest, double t, StageResu
     }
     HIPCHK(ctx, hipMemcpyAsync(rp.data(), d_rp, sizeof(int64_t) * ((size_t)n + 1),
                                hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(hint.data(), d_hint, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost,
+                               ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     sk_csr csr{n, nnz, rp.data(), col.data(), w.data()};
     r.perm.assign((size_t)n, -1);
     r.t = t;
     r.nnz = nnz;
-    const sk_status s = sk_solve_reduced(&csr, r.perm.data(), &r.weight);
+    const sk_status s = solve_reduced_seeded(&csr, hint.data(), r.perm.data(), &r.weight);
     if (s == SK_EINFEASIBLE) {
         r.feasible = false;
         return SK_OK;
@@ -87,6 +94,7 @@ using namespace sk;
 size_t sk_solve_arena_bytes(int32_t n, int32_t storage, int64_t max_kept) {
     if (n < 1 || n > kMaxN || max_kept < 0) return 0;
     return sk_arena_bytes(n, storage) + align_up(sizeof(int64_t) * ((size_t)n + 1), 256) +
+           align_up(sizeof(int32_t) * (size_t)n, 256) +
            align_up(sizeof(int32_t) * (size_t)max_kept, 256) +
            align_up(sizeof(int16_t) * (size_t)max_kept, 256) + 1024;
 }
@@ -133,12 +141,27 @@ extern "C" sk_status sk_solve(sk_ctx *ctx, const int16_t *W, int32_t n, const sk
         StageResult r;
         r.p = c.p;
         fill_report(c, &r.rep);
-        sk_status s2 = check_fp64(ctx, B, 0, &r.rep);
-        if (s2 != SK_OK) return s2;
-        // a B with no perfect matching at the last p: lower t tenfold, at most three times
+        Bump rest = bump;
+        int64_t *d_rp = rest.take<int64_t>((size_t)n + 1);
+        int32_t *d_hint = rest.take<int32_t>((size_t)n);
+        if (!d_rp || !d_hint)
+            return fail(ctx, SK_ENOMEM, "arena too small for the reduced matrix (row pointers)");
+        // FP64 certificate, row lengths of B at t and their scan: one sync
         double t = params->threshold;
+        const CheckCounts cc{std::log(t), B.d_counts, d_hint};
+        sk_status s2 = enqueue_check(ctx, B, 0, &cc);
+        if (s2 != SK_OK) return s2;
+        HIPCHK(ctx, PROF(ctx, KID_SCAN, launch_scan(B.d_counts, d_rp, n, ctx->stream, B.d_nnz)));
+        HIPCHK(ctx, hipMemcpyAsync(ctx->h_checkout, B.d_checkout, 4 * sizeof(double),
+                                   hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(ctx, hipMemcpyAsync(ctx->h_nnz, B.d_nnz, sizeof(int64_t), hipMemcpyDeviceToHost,
+                                   ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        report_from_check(ctx->h_checkout, c.p, &r.rep);
+        // a B with no perfect matching at the last p: lower t tenfold, at most three times
         for (int tries = 0;; ++tries) {
-            if ((s2 = reduce_and_solve(ctx, B, bump, t, r)) != SK_OK) return s2;
+            if ((s2 = reduce_and_solve(ctx, B, rest, d_rp, d_hint, t, tries == 0, r)) != SK_OK)
+                return s2;
             if (r.feasible || !last || tries == 3) break;
             t /= 10.0;
         }

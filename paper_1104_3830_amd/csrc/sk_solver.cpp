@@ -24,7 +24,19 @@ struct HeapItem {
 
 }  // namespace
 
+namespace sk {
+sk_status solve_reduced_seeded(const sk_csr *csr, const int32_t *hint, int32_t *perm,
+                               int64_t *weight);
+}
+
 extern "C" sk_status sk_solve_reduced(const sk_csr *csr, int32_t *perm, int64_t *weight) {
+    return sk::solve_reduced_seeded(csr, nullptr, perm, weight);
+}
+
+// hint (optional, n entries): a column per row to try first when the greedy
+// start of the matching is built; any values are accepted.
+sk_status sk::solve_reduced_seeded(const sk_csr *csr, const int32_t *hint, int32_t *perm,
+                                   int64_t *weight) {
     if (!csr || !perm || !weight || csr->n < 0) return SK_EINVAL;
     const int n = csr->n;
     if (n == 0) {
@@ -64,7 +76,8 @@ extern "C" sk_status sk_solve_reduced(const sk_csr *csr, int32_t *perm, int64_t 
     for (int j = 0; j < n; ++j)
         if (v[j] == INF) return SK_EINFEASIBLE;  // empty column
     // maximum matching on the tight edges (reduced cost 0), Hopcroft-Karp
-    // from a greedy start (each row takes its first free tight column)
+    // from a greedy start: each row takes its hinted column if that edge is
+    // tight and the column still free, else its first free tight column
     {
         int64_t ntight = 0;
         for (int i = 0; i < n; ++i)
@@ -87,13 +100,26 @@ extern "C" sk_status sk_solve_reduced(const sk_csr *csr, int32_t *perm, int64_t 
             tp = tpv.data();
             tc = tcv.data();
         }
-        for (int i = 0; i < n; ++i)
+        if (hint)
+            for (int i = 0; i < n; ++i) {
+                const int32_t h = hint[i];
+                if (h < 0 || h >= n || row_of[h] >= 0) continue;
+                for (int64_t e = tp[i]; e < tp[i + 1]; ++e)
+                    if (tc[e] == h) {
+                        row_of[h] = i;
+                        col_of[i] = h;
+                        break;
+                    }
+            }
+        for (int i = 0; i < n; ++i) {
+            if (col_of[i] >= 0) continue;
             for (int64_t e = tp[i]; e < tp[i + 1]; ++e)
                 if (row_of[tc[e]] < 0) {
                     row_of[tc[e]] = i;
                     col_of[i] = tc[e];
                     break;
                 }
+        }
         const int NIL = std::numeric_limits<int>::max();
         std::vector<int> dist(n), q(n), stack;
         std::vector<int64_t> it(n);
@@ -109,13 +135,17 @@ extern "C" sk_status sk_solve_reduced(const sk_csr *csr, int32_t *perm, int64_t 
                     dist[i] = NIL;
                 }
             }
+            // layers up to the first one that reaches a free column
             bool found = false;
+            int limit = NIL;
             while (qh < qt) {
                 const int i = q[qh++];
+                if (dist[i] > limit) break;
                 for (int64_t e = tp[i]; e < tp[i + 1]; ++e) {
                     const int i2 = row_of[tc[e]];
                     if (i2 < 0) {
                         found = true;
+                        limit = dist[i];
                     } else if (dist[i2] == NIL) {
                         dist[i2] = dist[i] + 1;
                         q[qt++] = i2;
