@@ -62,21 +62,36 @@ __device__ __forceinline__ void unit_range(int nunits, int &u0, int &u1) {
 // read 64 consecutive entries for each c (no bank conflicts).
 __device__ __forceinline__ int swz8(int j, int n8) { return (j & 7) * n8 + (j >> 3); }
 
+// 16-byte loads in flight per lane in the single-wave row passes (input
+// scan, FP64 row check, kept counts, CSR fill).
+constexpr int kVisitLoads = 4;
+
 // Visits the entries of one row: lane-strided 8-wide chunks with 16-byte
 // loads when the instance allows it, single entries otherwise. f(j, w).
+
 template <class Fn>
 __device__ __forceinline__ void visit_row(const Inst &I, const int16_t *wr, int lane, Fn f) {
     const int n = I.n;
     if (I.vec8) {
-        for (int j0 = lane * 8; j0 < n; j0 += 512) {
-            const int4 v = gload(reinterpret_cast<const int4 *>(wr + j0));
+        // kVisitLoads 16-byte loads in flight per lane, then their entries in order
+        constexpr int U = kVisitLoads;
+        auto use = [&](const int4 v, int j0) {
             const int q[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 f(j0 + 2 * c, (int)(short)(q[c] & 0xffff));
                 f(j0 + 2 * c + 1, q[c] >> 16);
             }
+        };
+        int j0 = lane * 8;
+        for (; j0 + (U - 1) * 512 < n; j0 += U * 512) {
+            int4 v[U];
+#pragma unroll
+            for (int k = 0; k < U; ++k) v[k] = gload(reinterpret_cast<const int4 *>(wr + j0 + k * 512));
+#pragma unroll
+            for (int k = 0; k < U; ++k) use(v[k], j0 + k * 512);
         }
+        for (; j0 < n; j0 += 512) use(gload(reinterpret_cast<const int4 *>(wr + j0)), j0);
     } else {
         for (int j = lane; j < n; j += kWave) f(j, (int)gload(wr + j));
     }
@@ -947,15 +962,29 @@ __global__ __launch_bounds__(kIterEndThreads) void k_iter_end(const Inst *__rest
 // FP64 ulp of the sum); their exp is not evaluated.
 constexpr double kNegligibleLog = -46.0;
 
-// Stages log v_j = G_j + gam_j (FP64) for the instance in LDS; swizzled like
-// the row sweep when 8-wide chunks are used.
-__device__ __forceinline__ void stage_logv(const Inst &I, double *lv) {
+// An entry whose exact integer exponent E = p w_ij + F_i + G_j is below
+// kCheckSkip has log x_ij < kNegligibleLog: |phi_i|, |gam_j| <= 1/2.
+constexpr int kCheckSkip = -50;
+
+// Integer bound below which no entry can reach log x_ij >= logt (same
+// argument: log x_ij <= E + 1).
+__device__ __forceinline__ int kept_skip(double logt) {
+    return (int)fmax(fmin(floor(logt), 1073741824.0), -1073741824.0) - 2;
+}
+
+// Stages the column potentials (G_j, bits of gam_j) for the instance in LDS;
+// swizzled like the row sweep when 8-wide chunks are used. log v_j in FP64 is
+// (double)G_j + (double)gam_j.
+__device__ __forceinline__ void stage_gq(const Inst &I, int2 *gq) {
     const int n = I.n, n8 = n >> 3;
     for (int j = threadIdx.x; j < n; j += blockDim.x)
-        lv[I.vec8 ? swz8(j, n8) : j] = (double)I.G[j] + (double)I.gam[j];
+        gq[I.vec8 ? swz8(j, n8) : j] = make_int2(I.G[j], __float_as_int(I.gam[j]));
 }
-__device__ __forceinline__ double logv_at(const Inst &I, const double *lv, int j) {
-    return lv[I.vec8 ? swz8(j, I.n >> 3) : j];
+__device__ __forceinline__ int2 gq_at(const Inst &I, const int2 *gq, int j) {
+    return gq[I.vec8 ? swz8(j, I.n >> 3) : j];
+}
+__device__ __forceinline__ double logv_of(int2 q) {
+    return (double)q.x + (double)__int_as_float(q.y);
 }
 
 // With counts != nullptr it also counts the entries with log x_ij >= logt
@@ -966,31 +995,34 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_check_rows(const Inst *__
                                                                     int nunits, double *rsum,
                                                                     double *rmax, double logt,
                                                                     int64_t *counts, int32_t *hint) {
-    extern __shared__ double lv[];
+    extern __shared__ int2 gq[];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     int u0, u1;
     unit_range(nunits, u0, u1);
+    const int eskip = counts ? min(kCheckSkip, kept_skip(logt)) : kCheckSkip;
     int cur = -1;
     for (int u = u0; u < u1; ++u) {
         const RowUnit un = units[u];
         const Inst &I = insts[un.inst];
         if (un.inst != cur) {
             __syncthreads();
-            stage_logv(I, lv);
+            stage_gq(I, gq);
             __syncthreads();
             cur = un.inst;
         }
         const int n = I.n, row = un.row0 + wave;
         if (row >= n) continue;
         const int par = I.ctl->iter & 1;
-        const double p = (double)I.ctl->p;
-        const double f = (double)I.F[par][row] + (double)I.phi[par][row];
+        const int pi = I.ctl->p, Fi = I.F[par][row];
+        const double p = (double)pi;
+        const double f = (double)Fi + (double)I.phi[par][row];
         const int16_t *wr = I.W + (int64_t)row * I.pitch;
         double s = 0.0, m = -INFINITY;
         int jm = -1, cnt = 0;
-        visit_row(I, wr, lane, [&](int j, int w) {
-            if (w == SK_SENTINEL) return;
-            const double pw = p * (double)w, lvj = logv_at(I, lv, j);
+        int Kb = INT_MIN / 2;  // integer part p w + G_j of this lane's largest t so far
+        // one entry in FP64 (t = p w_ij + log v_j, log x_ij = t + log u_i)
+        auto exact = [&](int j, int w, int2 q, int K) {
+            const double pw = p * (double)w, lvj = logv_of(q);
             const double t = pw + lvj;
             const double lx = t + f;
             if (lx > kNegligibleLog) s += exp(lx);
@@ -999,8 +1031,51 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_check_rows(const Inst *__
             if (t > m) {  // a lane visits its columns in increasing order
                 m = t;
                 jm = j;
+                Kb = K;
             }
-        });
+        };
+        // exact integer tests first: an entry that is negligible, below the
+        // threshold and below this lane's maximum (t <= K + 1/2 and the
+        // maximum is >= Kb - 1/2) changes nothing. Kb only grows, so testing
+        // a chunk against the Kb it started with is conservative.
+        if (I.vec8) {
+            const int n8 = n >> 3;
+            constexpr int U = kVisitLoads;
+            for (int j0 = lane * 8; j0 < n; j0 += U * 512) {
+                int4 v[U];
+#pragma unroll
+                for (int k = 0; k < U; ++k)
+                    v[k] = j0 + k * 512 < n ? gload(reinterpret_cast<const int4 *>(wr + j0 + k * 512))
+                                            : make_int4(0, 0, 0, 0);
+#pragma unroll
+                for (int k = 0; k < U; ++k) {
+                    const int jj = j0 + k * 512;
+                    if (jj >= n) break;
+                    int w[8];
+                    unpack8i(v[k], w);
+                    int K[8];
+                    unsigned flag = 0;
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) {
+                        K[c] = pi * w[c] + gq[c * n8 + (jj >> 3)].x;
+                        if (w[c] != SK_SENTINEL && (K[c] + Fi >= eskip || K[c] >= Kb - 1)) flag |= 1u << c;
+                    }
+                    if (flag) {
+#pragma unroll
+                        for (int c = 0; c < 8; ++c)
+                            if (flag & (1u << c)) exact(jj + c, w[c], gq[c * n8 + (jj >> 3)], K[c]);
+                    }
+                }
+            }
+        } else {
+            visit_row(I, wr, lane, [&](int j, int w) {
+                if (w == SK_SENTINEL) return;
+                const int2 q = gq_at(I, gq, j);
+                const int K = pi * w + q.x;
+                if (K + Fi < eskip && K < Kb - 1) return;
+                exact(j, w, q, K);
+            });
+        }
         s = wave_sum_d(s);
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
@@ -1061,9 +1136,8 @@ __global__ __launch_bounds__(256) void k_check_cols_sum(const Inst *__restrict__
 
 // The same slots from 8 columns per lane (16-byte loads along each row) with
 // the segment's rows split over four waves and the waves' sums added in a
-// fixed order. The exact integer part E = p w_ij + F_i + G_j decides first:
-// |phi_i|, |gam_j| <= 1/2, so E < kCheckSkip gives log x_ij < kNegligibleLog.
-constexpr int kCheckSkip = -50;
+// fixed order. The exact integer part E = p w_ij + F_i + G_j decides first
+// (E < kCheckSkip: negligible).
 
 __device__ __forceinline__ void check_cols_add8(const int4 v, int p, int2 rf, const int (&G)[8],
                                                 const double (&gm)[8], double (&s)[8]) {
@@ -1178,30 +1252,34 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_prune_count(const Inst *_
                                                                      const RowUnit *__restrict__ units,
                                                                      int nunits, double logt,
                                                                      int64_t *counts) {
-    extern __shared__ double lv[];
+    extern __shared__ int2 gq[];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     int u0, u1;
     unit_range(nunits, u0, u1);
+    const int eskip = kept_skip(logt);
     int cur = -1;
     for (int u = u0; u < u1; ++u) {
         const RowUnit un = units[u];
         const Inst &I = insts[un.inst];
         if (un.inst != cur) {
             __syncthreads();
-            stage_logv(I, lv);
+            stage_gq(I, gq);
             __syncthreads();
             cur = un.inst;
         }
         const int n = I.n, row = un.row0 + wave;
         if (row >= n) continue;
         const int par = I.ctl->iter & 1;
-        const double p = (double)I.ctl->p;
-        const double f = (double)I.F[par][row] + (double)I.phi[par][row];
+        const int pi = I.ctl->p, Fi = I.F[par][row];
+        const double p = (double)pi;
+        const double f = (double)Fi + (double)I.phi[par][row];
         const int16_t *wr = I.W + (int64_t)row * I.pitch;
         int cnt = 0;
         visit_row(I, wr, lane, [&](int j, int w) {
             if (w == SK_SENTINEL) return;
-            const double lx = p * (double)w + f + logv_at(I, lv, j);
+            const int2 q = gq_at(I, gq, j);
+            if (pi * w + q.x + Fi < eskip) return;  // cannot reach t
+            const double lx = p * (double)w + f + logv_of(q);
             cnt += (lx >= logt);
         });
 #pragma unroll
@@ -1248,49 +1326,72 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_prune_fill(const Inst *__
                                                                     const int64_t *__restrict__ row_ptr,
                                                                     int32_t *__restrict__ col,
                                                                     int16_t *__restrict__ wout) {
-    extern __shared__ double lv[];
+    extern __shared__ int2 gq[];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     int u0, u1;
     unit_range(nunits, u0, u1);
+    const int eskip = kept_skip(logt);
     int cur = -1;
     for (int u = u0; u < u1; ++u) {
         const RowUnit un = units[u];
         const Inst &I = insts[un.inst];
         if (un.inst != cur) {
             __syncthreads();
-            stage_logv(I, lv);
+            stage_gq(I, gq);
             __syncthreads();
             cur = un.inst;
         }
         const int n = I.n, row = un.row0 + wave;
         if (row >= n) continue;
         const int par = I.ctl->iter & 1;
-        const double p = (double)I.ctl->p;
-        const double f = (double)I.F[par][row] + (double)I.phi[par][row];
+        const int pi = I.ctl->p, Fi = I.F[par][row];
+        const double p = (double)pi;
+        const double f = (double)Fi + (double)I.phi[par][row];
         const int16_t *wr = I.W + (int64_t)row * I.pitch;
         int64_t pos = row_ptr[row];
         if (I.vec8) {
             // each lane tests 8 consecutive columns; kept entries are placed
             // by a wave prefix sum of the per-lane counts (column order kept)
+            constexpr int U = kVisitLoads;
+            int4 vb[U];
             for (int j0b = 0; j0b < n; j0b += 512) {
                 const int j0 = j0b + lane * 8;
+                const int slot = (j0b / 512) % U;
+                if (slot == 0) {
+                    // the next U chunks of this lane, loaded together
+#pragma unroll
+                    for (int k = 0; k < U; ++k)
+                        vb[k] = j0 + k * 512 < n ? gload(reinterpret_cast<const int4 *>(wr + j0 + k * 512))
+                                                 : make_int4(0, 0, 0, 0);
+                }
                 int wv[8];
                 unsigned keep = 0;
                 if (j0 < n) {
-                    const int4 v = gload(reinterpret_cast<const int4 *>(wr + j0));
+                    int4 v = vb[0];
+#pragma unroll
+                    for (int k = 1; k < U; ++k)
+                        if (slot == k) v = vb[k];
                     const int q[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
                     for (int c = 0; c < 4; ++c) {
                         wv[2 * c] = (int)(short)(q[c] & 0xffff);
                         wv[2 * c + 1] = q[c] >> 16;
                     }
+                    // exact integer test first (below eskip an entry cannot
+                    // reach t), then FP64 for the few that can
+                    const int base = j0 >> 3, n8 = n >> 3;
+                    unsigned cand = 0;
 #pragma unroll
-                    for (int c = 0; c < 8; ++c) {
-                        const int j = j0 + c;
-                        if (wv[c] != SK_SENTINEL) {
-                            const double lx = p * (double)wv[c] + f + logv_at(I, lv, j);
-                            if (lx >= logt) keep |= 1u << c;
-                        }
+                    for (int c = 0; c < 8; ++c)
+                        if (wv[c] != SK_SENTINEL && pi * wv[c] + gq[c * n8 + base].x + Fi >= eskip)
+                            cand |= 1u << c;
+                    if (cand) {
+#pragma unroll
+                        for (int c = 0; c < 8; ++c)
+                            if (cand & (1u << c)) {
+                                const double lx = p * (double)wv[c] + f + logv_of(gq[c * n8 + base]);
+                                if (lx >= logt) keep |= 1u << c;
+                            }
                     }
                 }
                 const int cnt = __popc(keep);
@@ -1320,8 +1421,11 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_prune_fill(const Inst *__
             if (j < n) {
                 w = wr[j];
                 if (w != SK_SENTINEL) {
-                    const double lx = p * (double)w + f + logv_at(I, lv, j);
-                    keep = lx >= logt;
+                    const int2 q = gq_at(I, gq, j);
+                    if (pi * w + q.x + Fi >= eskip) {
+                        const double lx = p * (double)w + f + logv_of(q);
+                        keep = lx >= logt;
+                    }
                 }
             }
             const uint64_t mask = __ballot(keep);

@@ -586,12 +586,20 @@ sk_status run_single_k(sk_ctx *ctx, Batch &B, const sk_params *prm, const StageH
             continue;
         }
         // a block of K iterations; afterwards the launches past the point
-        // where the stage ended are tagged (detection / idle)
+        // where the stage ended are tagged (detection / idle). The stage's
+        // first block is sized by the previous stage's iterations, later ones
+        // are short, so few launches run after the stage has ended.
         const size_t pstart = ctx->prof.pending.size();
         const int64_t it0 = c.iters_total;
         const int stage0 = c.stage;
         const Inst &I0 = B.h_insts[0];
-        for (int k = 0; k < check; ++k) {
+        const int64_t done = c.stage_iters[c.stage];
+        int blk = std::min(check, 8);
+        if (done <= 1)
+            blk = c.stage == 0 ? check
+                               : (int)std::min<int64_t>(
+                                     check, std::max<int64_t>(4, c.stage_iters[c.stage - 1] + 2 - done));
+        for (int k = 0; k < blk; ++k) {
             if (I0.fused) {
                 ctx->prof.begin(ctx->stream, KID_FUSED);
                 KCHK(launch_fused(B.d_insts, 0, I0.n, I0.fused_grid, storage, ctx->stream));

@@ -497,18 +497,37 @@ sk_status sk::run_batch_i16(sk_ctx *ctx, Batch &B, const sk_params *prm, int fir
     const int64_t bound = (prm->max_iters_per_stage + 1) * prm->n_p + 1;
     const size_t pstart = ctx->prof.pending.size();
     int64_t launched = 0;
+    // Launch blocks are check_every iterations long until the end is near:
+    // once every running instance is in its last stage (or, for an instance
+    // paused at each stage end, after the first block of the stage) they are
+    // at most kTailBlock long, so fewer launches run after the end. The first
+    // block of a paused stage is sized by the previous stage's iterations.
+    constexpr int kTailBlock = 8;
+    int blk = check;
+    if (B.count == 1 && B.h_insts[0].pause && first_stage > 0)
+        blk = (int)std::min<int64_t>(check, std::max<int64_t>(
+                                                4, ctx->h_ctl[0].stage_iters[first_stage - 1] + 2));
     for (;;) {
-        for (int k = 0; k < check; ++k) {
+        for (int k = 0; k < blk; ++k) {
             sk_status s = iterate_i16(ctx, B);
             if (s != SK_OK) return s;
         }
-        launched += check;
+        launched += blk;
         sk_status s = read_ctl(ctx, B);
         if (s != SK_OK) return s;
-        bool running = false;
-        for (int k = 0; k < B.count; ++k) running |= ctx->h_ctl[k].state == ST_RUNNING;
+        bool running = false, tail = true;
+        for (int k = 0; k < B.count; ++k) {
+            const Ctl &c = ctx->h_ctl[k];
+            if (c.state != ST_RUNNING) continue;
+            running = true;
+            const Inst &I = B.h_insts[k];
+            // (the deformed iteration is one long stage: full blocks)
+            const bool last = I.deform_a <= 0.0 && c.stage + 1 >= I.n_p;
+            tail &= last || I.pause;
+        }
         if (!running) break;
         if (launched > bound) return fail(ctx, SK_EDEVICE, "stage controller did not terminate");
+        blk = tail ? std::min(check, kTailBlock) : check;
     }
     if (ctx->prof.on) {
         // triple index of each convergence detection, and the number of
