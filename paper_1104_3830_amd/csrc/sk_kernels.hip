@@ -299,7 +299,7 @@ __device__ __forceinline__ int row_max_v1(const int16_t *__restrict__ wr, int n,
 // range, then the new potentials and the residual.
 template <bool SENT, bool V8>
 __device__ __forceinline__ float row_finish(const Inst &I, int row, int par, int lane, int Fi,
-                                            float S, const ColPot *__restrict__ cp,
+                                            float phi, float S, const ColPot *__restrict__ cp,
                                             const float *__restrict__ tab) {
     const int n = I.n;
     const int16_t *wr = I.W + (int64_t)row * I.pitch;
@@ -322,7 +322,6 @@ __device__ __forceinline__ float row_finish(const Inst &I, int row, int par, int
     }
     if (lane == 0) {
         // log u_i <- F_i - M - log S
-        const float phi = I.phi[par][row];
         const float l2S = lg2(S);
         const float phin = -l2S * kLn2;
         const float k = rintf(phin);
@@ -344,11 +343,13 @@ __device__ __forceinline__ float row_step_one(const Inst &I, int row, int par, i
     const int n = I.n;
     const int16_t *wr = I.W + (int64_t)row * I.pitch;
     const int Fi = I.F[par][row];
+    // loaded with F_i so that the end of the row does not wait for it
+    const float phi = I.phi[par][row];
     const int p4 = 4 * I.ctl->p;
     float S = V8 ? row_partial_v8<SENT>(wr, n, p4, 4 * (Fi - kTabLo), cp, tab, lane)
                  : row_partial_v1<SENT>(wr, n, p4, 4 * (Fi - kTabLo), cp, tab, lane);
     S = wave_sum(S);
-    return row_finish<SENT, V8>(I, row, par, lane, Fi, S, cp, tab);
+    return row_finish<SENT, V8>(I, row, par, lane, Fi, phi, S, cp, tab);
 }
 
 // Two rows in one pass over the columns: each column's (4 G_j, exp(gam_j))
@@ -427,8 +428,8 @@ __device__ __forceinline__ float row_step_pair(const Inst &I, int ra, int rb, in
                           4 * (Fa - kTabLo), 4 * (Fb - kTabLo), cp, tab, lane, Sa, Sb);
     Sa = wave_sum(Sa);
     Sb = wave_sum(Sb);
-    const float ea = row_finish<SENT, true>(I, ra, par, lane, Fa, Sa, cp, tab);
-    const float eb = row_finish<SENT, true>(I, rb, par, lane, Fb, Sb, cp, tab);
+    const float ea = row_finish<SENT, true>(I, ra, par, lane, Fa, I.phi[par][ra], Sa, cp, tab);
+    const float eb = row_finish<SENT, true>(I, rb, par, lane, Fb, I.phi[par][rb], Sb, cp, tab);
     return fmaxf(ea, eb);
 }
 
