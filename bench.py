@@ -304,15 +304,19 @@ def served_leg(sk, torch, n_requests, loads, seed=2):
             now = time.perf_counter() - t_start
             while nxt < n_requests and arrivals[nxt] <= now:
                 W = reqs[nxt]
-                pending[srv.submit(W, prm)] = (nxt, W.shape[0])
+                try:
+                    pending[srv.submit(W, prm)] = (nxt, W.shape[0])
+                except sk.SkError as e:
+                    if e.status != sk.SK_EAGAIN:
+                        raise
+                    break  # queue full: poll, then submit again
                 nxt += 1
-            for tk in list(pending):
-                idx, n = pending[tk]
+            # finished requests from the completion queue, then collected
+            for tk in srv.completed():
+                idx, n = pending.pop(tk)
                 r = srv.poll(tk, n)
-                if r is not None:
-                    lat[idx] = time.perf_counter() - t_start - arrivals[idx]
-                    ok += r[2] == 1050 * n
-                    del pending[tk]
+                lat[idx] = time.perf_counter() - t_start - arrivals[idx]
+                ok += r[2] == 1050 * n
             time.sleep(0.0002)
         return time.perf_counter() - t_start, lat, ok
 
@@ -328,10 +332,19 @@ def served_leg(sk, torch, n_requests, loads, seed=2):
             "fifo": {"solves_per_s": round(n_requests / span_f, 2), "p50_ms": q(lat_f, 50),
                      "p99_ms": q(lat_f, 99), "optimal": int(ok_f)},
             "speedup_solves_per_s": round(span_f / span_s, 2)})
+    # saturation: every request arrives at time 0 (peak solves/s of each)
+    zero = np.zeros(n_requests)
+    span_f, _, ok_f = run_fifo(zero)
+    span_s, _, ok_s = run_served(zero)
+    saturated = {"served_solves_per_s": round(n_requests / span_s, 2),
+                 "fifo_solves_per_s": round(n_requests / span_f, 2),
+                 "speedup_solves_per_s": round(span_f / span_s, 2),
+                 "optimal": [int(ok_s), int(ok_f)]}
     fifo.close()
     srv.close()
     return {"requests": n_requests, "n_range": [64, 8192], "pool_instances": len(pool),
-            "fifo_capacity_solves_per_s": round(mu, 2), "loads": per_load}
+            "fifo_capacity_solves_per_s": round(mu, 2), "loads": per_load,
+            "saturated": saturated}
 
 
 def euclidean_leg(sk, torch, n=1000, seed=0, scale=100):

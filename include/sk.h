@@ -250,9 +250,19 @@ size_t sk_solve_arena_bytes(int32_t n, int32_t storage, int64_t max_kept);
  * thread admits queued requests when their device footprint fits in the
  * arena, sweeps all admitted instances together, and on convergence prunes,
  * solves the reduced instance and checks the certificate. *ticket receives
- * an id for sk_poll. Returns SK_EAGAIN if the queue is full. */
+ * an id for sk_poll. The caller's buffer may be reused when the call
+ * returns. Returns SK_EAGAIN when the queue is full or no staging memory is
+ * free (a pinned ring of 512 MiB; poll finished requests, then submit again). */
 sk_status sk_submit(sk_ctx *ctx, const int16_t *W_host, int32_t n, const sk_params *params,
                     uint64_t *ticket);
+
+/* Completion queue of the served path, for callers that hold many tickets:
+ * moves up to `max` tickets of finished, not yet collected requests (in the
+ * order they finished) into `tickets` (host uint64[max], caller-owned) and
+ * returns how many; collect each with sk_poll. 0 when none is pending or no
+ * request was submitted; -1 on a null context or bad arguments. A ticket
+ * finished but not listed (the list keeps the last 65536) stays pollable. */
+int32_t sk_completed(sk_ctx *ctx, uint64_t *tickets, int32_t max);
 
 /* Non-blocking. Returns SK_EAGAIN while the request runs; otherwise its final
  * status, with perm (host int32[n]), weight and report (may be NULL) filled,

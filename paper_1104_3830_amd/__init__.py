@@ -25,7 +25,7 @@ MAX_LADDER = 32
 SENTINEL = -32768
 
 EXPORTS = ["sk_potentials_bytes", "sk_arena_bytes", "sk_create", "sk_destroy", "sk_last_error",
-           "sk_scale", "sk_prune", "sk_solve_reduced", "sk_submit", "sk_poll", "sk_scale_batch",
+           "sk_scale", "sk_prune", "sk_solve_reduced", "sk_submit", "sk_poll", "sk_completed", "sk_scale_batch",
            "sk_batch_arena_bytes", "sk_profile_enable", "sk_profile_read", "sk_set_tile_table",
            "sk_solve", "sk_solve_arena_bytes"]
 TILE_TABLE = os.path.join(HERE, "tile_table_gfx950.json")
@@ -107,6 +107,8 @@ def lib():
         L.sk_scale_batch.restype = ctypes.c_int
         L.sk_prune.argtypes = [vp, vp, i32, vp, ctypes.POINTER(Params), ctypes.POINTER(CSR)]
         L.sk_prune.restype = ctypes.c_int
+        L.sk_completed.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64), i32]
+        L.sk_completed.restype = i32
         L.sk_solve_reduced.argtypes = [ctypes.POINTER(CSR), ctypes.POINTER(i32), ctypes.POINTER(i64)]
         L.sk_solve_reduced.restype = ctypes.c_int
         L.sk_solve.argtypes = [vp, vp, i32, ctypes.POINTER(Params), vp, ctypes.POINTER(i32),
@@ -320,6 +322,14 @@ class Context:
                              ctypes.byref(t))
         self._check(st, "sk_submit")
         return t.value
+
+    def completed(self, max_tickets=1024):
+        """Tickets of finished requests not collected yet (sk_completed)."""
+        buf = (ctypes.c_uint64 * max_tickets)()
+        k = lib().sk_completed(self._ptr, buf, max_tickets)
+        if k < 0:
+            raise SkError(SK_EINVAL, "sk_completed")
+        return [int(buf[i]) for i in range(k)]
 
     def poll(self, ticket, n):
         """None while the request runs, else (status, perm, weight, report)."""

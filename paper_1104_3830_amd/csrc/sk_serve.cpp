@@ -19,6 +19,7 @@
 // Every per-instance computation depends only on that instance (work units,
 // tile plan and reduction order are functions of n), so a request's result is
 // the same alone and in any mix.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
@@ -45,6 +46,7 @@ struct Request {
     size_t off = 0, len = 0;     // device region in the arena
     Inst inst{};
     bool loaded = false;         // W is in its device region
+    bool copying = false;        // placed, and its copy from the ring is in flight (ev)
     hipEvent_t ev = nullptr;     // completion of the host-to-device copy
     int phase = 0;               // 0 queued, 1 active, 2 solving, 3 done
     sk_status status = SK_OK;
@@ -70,6 +72,7 @@ struct Server {
     int staged_waiting = 0;         // queued requests whose W is still on the host
     std::vector<Request *> active;
     std::unordered_map<uint64_t, Request *> reqs;
+    std::deque<uint64_t> done_ids;  // finished requests in completion order (sk_completed)
     std::deque<Request *> solve_q;
     RangeAlloc ralloc;
     size_t tables_len = 0;
@@ -100,6 +103,29 @@ static void release_staging(Server *S, Request *r) {
 
 static const size_t kTablesBytes = size_t(64) << 20;
 
+// Host copy of a submitted W into staging: one thread per kCopyChunk bytes,
+// at most kCopyThreads (a single thread copies at about 25-30 GB/s).
+static const size_t kCopyChunk = size_t(8) << 20;
+static const int kCopyThreads = 4;
+
+static void stage_copy(void *dst, const void *src, size_t bytes) {
+    const int nt = (int)std::min<size_t>(kCopyThreads, std::max<size_t>(1, bytes / kCopyChunk));
+    if (nt <= 1) {
+        memcpy(dst, src, bytes);
+        return;
+    }
+    const size_t part = (bytes / nt + 63) / 64 * 64;
+    std::vector<std::thread> th;
+    th.reserve(nt - 1);
+    for (int k = 1; k < nt; ++k) {
+        const size_t a = std::min(bytes, part * k), b = std::min(bytes, part * (k + 1));
+        if (a < b)
+            th.emplace_back([=] { memcpy((char *)dst + a, (const char *)src + a, b - a); });
+    }
+    memcpy(dst, src, std::min(bytes, part));
+    for (auto &t : th) t.join();
+}
+
 static size_t footprint(int32_t n) {
     return align_up((size_t)n * n * 2, 256) + instance_bytes(n, (n % 8) == 0, SK_W_I16) + 4096;
 }
@@ -111,6 +137,15 @@ static void place(Server *S, Request *r, size_t off) {
     Bump bump{S->ctx->arena + off, r->len};
     int16_t *dW = bump.take<int16_t>((size_t)r->n * r->n);
     carve_instance(bump, dW, r->n, r->n, &r->prm, r->inst);
+}
+
+// Marks r finished (caller holds S->mu) and records it for sk_completed; the
+// record keeps at most kMaxDoneIds entries (older tickets stay pollable).
+static const size_t kMaxDoneIds = size_t(1) << 16;
+static void mark_done(Server *S, Request *r) {
+    r->phase = 3;
+    S->done_ids.push_back(r->id);
+    if (S->done_ids.size() > kMaxDoneIds) S->done_ids.pop_front();
 }
 
 static void drop_event(Request *r) {
@@ -153,7 +188,7 @@ static void solver_loop(Server *S) {
             r->col.shrink_to_fit();
             r->w.clear();
             r->w.shrink_to_fit();
-            r->phase = 3;
+            mark_done(S, r);
         }
     }
 }
@@ -286,6 +321,8 @@ static void serve_loop(Server *S) {
     (void)hipSetDevice(ctx->device);
     bool dirty = false;
     for (;;) {
+        // to_copy: admitted in queue order, each either with its copy already
+        // in flight (placed at submission) or to be copied from staging now
         std::vector<Request *> fresh, to_copy;
         {
             std::unique_lock<std::mutex> g(S->mu);
@@ -294,7 +331,9 @@ static void serve_loop(Server *S) {
                    S->active.size() + S->loading.size() + fresh.size() + to_copy.size() <
                        (size_t)kMaxBatch) {
                 Request *r = S->queue.front();
-                if (!r->loaded) {
+                if (r->copying) {
+                    to_copy.push_back(r);
+                } else if (!r->loaded) {
                     size_t off;
                     if (!S->ralloc.alloc(r->len, off)) break;
                     place(S, r, off);
@@ -309,11 +348,13 @@ static void serve_loop(Server *S) {
         }
         hipError_t e = hipSuccess;
         for (Request *r : to_copy) {
-            if (e == hipSuccess)
-                e = hipMemcpyAsync((void *)r->inst.W, r->staging, (size_t)r->n * r->n * 2,
-                                   hipMemcpyHostToDevice, S->copy_stream);
-            if (e == hipSuccess) e = hipEventCreateWithFlags(&r->ev, hipEventDisableTiming);
-            if (e == hipSuccess) e = hipEventRecord(r->ev, S->copy_stream);
+            if (!r->copying) {
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync((void *)r->inst.W, r->staging, (size_t)r->n * r->n * 2,
+                                       hipMemcpyHostToDevice, S->copy_stream);
+                if (e == hipSuccess) e = hipEventCreateWithFlags(&r->ev, hipEventDisableTiming);
+                if (e == hipSuccess) e = hipEventRecord(r->ev, S->copy_stream);
+            }
             S->loading.push_back(r);
         }
         // take in the requests whose copy has completed, in admission order
@@ -388,14 +429,14 @@ static void serve_loop(Server *S) {
             for (auto *list : {&S->active, &fresh}) {
                 for (Request *r : *list) {
                     r->status = SK_EDEVICE;
-                    r->phase = 3;
+                    mark_done(S, r);
                 }
                 list->clear();
             }
             for (Request *r : S->loading) {
                 drop_event(r);
                 r->status = SK_EDEVICE;
-                r->phase = 3;
+                mark_done(S, r);
             }
             S->loading.clear();
             break;
@@ -415,7 +456,7 @@ static void serve_loop(Server *S) {
                 S->ralloc.release(r->off, r->len);
                 if (st != SK_OK || r->status == SK_ENOSUPPORT || r->status == SK_ENOMEM) {
                     if (st != SK_OK) r->status = SK_EDEVICE;
-                    r->phase = 3;
+                    mark_done(S, r);
                 } else {
                     r->phase = 2;
                     S->solve_q.push_back(r);
@@ -506,7 +547,13 @@ extern "C" sk_status sk_submit(sk_ctx *ctx, const int16_t *W_host, int32_t n, co
     r->len = len;
     r->t_submit = std::chrono::steady_clock::now();
     const size_t wbytes = (size_t)n * n * 2;
-    bool direct = false;
+    // W goes to the pinned ring when it has room (a parallel host copy; the
+    // caller's buffer is free when this returns) and from there to the device
+    // by an asynchronous copy started here if the device region is free too;
+    // without ring room it is copied straight to a free device region
+    // (waiting for the copy); with neither the call returns SK_EAGAIN (heap
+    // staging only when the pinned ring could not be allocated)
+    bool placed = false;
     {
         std::lock_guard<std::mutex> g(S->mu);
         if (!S->error.empty()) {
@@ -517,18 +564,41 @@ extern "C" sk_status sk_submit(sk_ctx *ctx, const int16_t *W_host, int32_t n, co
             delete r;
             return SK_EAGAIN;
         }
-        // straight to the device when it fits and nobody earlier is waiting
         size_t off;
-        if (S->staged_waiting == 0 && S->ralloc.alloc(len, off)) {
-            place(S, r, off);
-            direct = true;
-        } else if (S->ring && S->ring_alloc.alloc(wbytes, off)) {
+        if (S->ring && S->ring_alloc.alloc(wbytes, off)) {
             r->staging = (int16_t *)(S->ring + off);
             r->ring_off = off;
             r->in_ring = true;
         }
+        // a device region now only when nobody earlier is waiting for one
+        if (S->staged_waiting == 0 && S->ralloc.alloc(len, off)) {
+            place(S, r, off);
+            placed = true;
+        }
     }
-    if (direct) {
+    auto undo = [&](const char *what, hipError_t e) {
+        drop_event(r);
+        {
+            std::lock_guard<std::mutex> g(S->mu);
+            if (placed) S->ralloc.release(r->off, r->len);
+            release_staging(S, r);
+        }
+        delete r;
+        return fail(ctx, SK_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+    };
+    if (r->in_ring) {
+        stage_copy(r->staging, W_host, wbytes);
+        if (placed) {
+            hipError_t e = hipSetDevice(ctx->device);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync((void *)r->inst.W, r->staging, wbytes, hipMemcpyHostToDevice,
+                                   S->copy_stream);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&r->ev, hipEventDisableTiming);
+            if (e == hipSuccess) e = hipEventRecord(r->ev, S->copy_stream);
+            if (e != hipSuccess) return undo("copy of W", e);
+            r->copying = true;
+        }
+    } else if (placed) {
         hipError_t e = hipSetDevice(ctx->device);
         if (e == hipSuccess)
             e = hipMemcpyAsync((void *)r->inst.W, W_host, wbytes, hipMemcpyHostToDevice,
@@ -536,27 +606,26 @@ extern "C" sk_status sk_submit(sk_ctx *ctx, const int16_t *W_host, int32_t n, co
         if (e == hipSuccess) e = hipEventCreateWithFlags(&r->ev, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventRecord(r->ev, S->copy_stream);
         if (e == hipSuccess) e = hipEventSynchronize(r->ev);
+        if (e != hipSuccess) return undo("copy of W", e);
         drop_event(r);
-        if (e != hipSuccess) {
-            {
-                std::lock_guard<std::mutex> g(S->mu);
-                S->ralloc.release(r->off, r->len);
-            }
-            delete r;
-            return fail(ctx, SK_EDEVICE, "copy of W: %s", hipGetErrorString(e));
-        }
         r->loaded = true;
+    } else if (S->ring) {
+        // neither ring room nor a free device region: the caller polls and
+        // submits again (heap staging would later need a pageable copy that
+        // stalls the serving thread)
+        delete r;
+        return SK_EAGAIN;
     } else {
-        if (!r->staging) r->staging = (int16_t *)malloc(wbytes);
+        r->staging = (int16_t *)malloc(wbytes);
         if (!r->staging) {
             delete r;
             return fail(ctx, SK_ENOMEM, "host staging allocation failed");
         }
-        memcpy(r->staging, W_host, wbytes);
+        stage_copy(r->staging, W_host, wbytes);
     }
     {
         std::lock_guard<std::mutex> g(S->mu);
-        if (!r->loaded) ++S->staged_waiting;
+        if (!r->loaded && !r->copying) ++S->staged_waiting;
         r->id = S->next_id++;
         S->queue.push_back(r);
         S->reqs[r->id] = r;
@@ -586,4 +655,18 @@ extern "C" sk_status sk_poll(sk_ctx *ctx, uint64_t ticket, int32_t *perm, int64_
     const sk_status st = r->status;
     delete r;
     return st;
+}
+
+extern "C" int32_t sk_completed(sk_ctx *ctx, uint64_t *tickets, int32_t max) {
+    if (!ctx || max < 0 || (max > 0 && !tickets)) return -1;
+    Server *S = ctx->server;
+    if (!S) return 0;
+    std::lock_guard<std::mutex> g(S->mu);
+    int32_t k = 0;
+    while (k < max && !S->done_ids.empty()) {
+        const uint64_t id = S->done_ids.front();
+        S->done_ids.pop_front();
+        if (S->reqs.count(id)) tickets[k++] = id;  // not collected yet
+    }
+    return k;
 }
