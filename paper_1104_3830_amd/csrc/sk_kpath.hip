@@ -637,9 +637,7 @@ sk_status run_single_k(sk_ctx *ctx, Batch &B, const sk_params *prm, const StageH
             };
             ctx->prof.retag(pstart, KID_ROW_K, tag(KID_ROW_K_DETECT, KID_ROW_K_IDLE));
             ctx->prof.retag(pstart, KID_COL_K, tag(KID_COL_K_DETECT, KID_COL_K_IDLE));
-            ctx->prof.retag(pstart, KID_ITER_END, tag(KID_ITER_END_DETECT, KID_ITER_END_IDLE));
             ctx->prof.retag(pstart, KID_FUSED, tag(KID_FUSED_DETECT, KID_FUSED_IDLE));
-            ctx->prof.retag(pstart, KID_FINALIZE, tag(KID_FINALIZE_DETECT, KID_FINALIZE_IDLE));
         }
     }
     return SK_OK;

@@ -60,13 +60,16 @@ struct Bump {
 };
 struct Server;
 
+// Timed launch classes (the short finalise and end-of-iteration launches of
+// an iteration are not timed). *_DETECT: a launch that only detected the end
+// of a stage; *_IDLE: a launch after every instance finished.
 enum KernelId {
-    KID_INIT, KID_ROW, KID_COL, KID_ITER_END, KID_CHECK_ROWS, KID_CHECK_COLS, KID_PRUNE_COUNT,
+    KID_INIT, KID_ROW, KID_COL, KID_CHECK_ROWS, KID_CHECK_COLS, KID_PRUNE_COUNT,
     KID_SCAN, KID_PRUNE_FILL, KID_ABSORB, KID_ROW_K, KID_COL_K, KID_FOLD_K,
-    KID_ROW_DETECT, KID_COL_DETECT, KID_ITER_END_DETECT, KID_ROW_IDLE, KID_COL_IDLE,
-    KID_ITER_END_IDLE, KID_ROW_K_DETECT, KID_COL_K_DETECT, KID_ROW_K_IDLE, KID_COL_K_IDLE,
-    KID_FUSED, KID_FINALIZE, KID_FUSED_DETECT, KID_FINALIZE_DETECT, KID_FUSED_IDLE,
-    KID_FINALIZE_IDLE, KID_NT_PRODUCT, KID_NT_STEP, KID_NT_PRODUCT_IDLE, KID_NT_STEP_IDLE,
+    KID_ROW_DETECT, KID_COL_DETECT, KID_ROW_IDLE, KID_COL_IDLE,
+    KID_ROW_K_DETECT, KID_COL_K_DETECT, KID_ROW_K_IDLE, KID_COL_K_IDLE,
+    KID_FUSED, KID_FUSED_DETECT, KID_FUSED_IDLE,
+    KID_NT_PRODUCT, KID_NT_STEP, KID_NT_PRODUCT_IDLE, KID_NT_STEP_IDLE,
     KID_COUNT
 };
 extern const char *kKernelNames[KID_COUNT];

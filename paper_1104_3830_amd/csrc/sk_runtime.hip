@@ -89,16 +89,15 @@ size_t shared_bytes(int32_t count, const int32_t *n) {
 
 
 
-const char *kKernelNames[KID_COUNT] = {"init", "row_sweep", "col_sweep", "iter_end",
-                                       "check_rows", "check_cols", "prune_count", "scan",
-                                       "prune_fill", "absorb", "row_sweep_k", "col_sweep_k",
-                                       "fold_k", "row_sweep:detect", "col_sweep:detect",
-                                       "iter_end:detect", "row_sweep:idle", "col_sweep:idle",
-                                       "iter_end:idle", "row_sweep_k:detect", "col_sweep_k:detect",
-                                       "row_sweep_k:idle", "col_sweep_k:idle", "fused",
-                                       "finalize", "fused:detect", "finalize:detect",
-                                       "fused:idle", "finalize:idle", "nt_product", "nt_step",
-                                       "nt_product:idle", "nt_step:idle"};
+const char *kKernelNames[KID_COUNT] = {"init", "row_sweep", "col_sweep", "check_rows",
+                                       "check_cols", "prune_count", "scan", "prune_fill",
+                                       "absorb", "row_sweep_k", "col_sweep_k", "fold_k",
+                                       "row_sweep:detect", "col_sweep:detect", "row_sweep:idle",
+                                       "col_sweep:idle", "row_sweep_k:detect",
+                                       "col_sweep_k:detect", "row_sweep_k:idle",
+                                       "col_sweep_k:idle", "fused", "fused:detect", "fused:idle",
+                                       "nt_product", "nt_step", "nt_product:idle",
+                                       "nt_step:idle"};
 
 hipEvent_t Profiler::take() {
     if (!pool.empty()) {
@@ -559,9 +558,7 @@ sk_status sk::run_batch_i16(sk_ctx *ctx, Batch &B, const sk_params *prm, int fir
         };
         ctx->prof.retag(pstart, KID_ROW, tagger(KID_ROW_DETECT, KID_ROW_IDLE));
         ctx->prof.retag(pstart, KID_COL, tagger(KID_COL_DETECT, KID_COL_IDLE));
-        ctx->prof.retag(pstart, KID_ITER_END, tagger(KID_ITER_END_DETECT, KID_ITER_END_IDLE));
         ctx->prof.retag(pstart, KID_FUSED, tagger(KID_FUSED_DETECT, KID_FUSED_IDLE));
-        ctx->prof.retag(pstart, KID_FINALIZE, tagger(KID_FINALIZE_DETECT, KID_FINALIZE_IDLE));
     }
     return SK_OK;
 }
