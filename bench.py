@@ -141,13 +141,21 @@ def source_hash():
     return h.hexdigest()
 
 
+def _kernel_key(name):
+    """'void sk::k_row_sweep<true>(...)' -> 'sk::k_row_sweep'."""
+    import re
+    k = name.split("(")[0]
+    k = re.sub(r"<[^<>]*>$", "", k)
+    return k[5:] if k.startswith("void ") else k
+
+
 def _counter_means(path, counter):
     import csv
     per = {}
     for r in csv.DictReader(open(path)):
         if r["Counter_Name"] != counter:
             continue
-        k = r["Kernel_Name"].split("(")[0]
+        k = _kernel_key(r["Kernel_Name"])
         per.setdefault(k, {}).setdefault(r["Dispatch_Id"], 0.0)
         per[k][r["Dispatch_Id"]] += float(r["Counter_Value"])
     out = {}

@@ -42,16 +42,16 @@ __device__ __forceinline__ float fwmax(float v) {
 }
 
 // 8 values of one chunk as floats: int16 w (I16) or K (BF16 / F32).
-template <int ST>
+template <int ST, bool NT>
 __device__ __forceinline__ void fload(const void *base, int64_t off, float (&x)[8]) {
     if (ST == SK_W_I16) {
-        const int4 v = gload(reinterpret_cast<const int4 *>(reinterpret_cast<const int16_t *>(base) + off));
+        const int4 v = gload<NT>(reinterpret_cast<const int4 *>(reinterpret_cast<const int16_t *>(base) + off));
         x[0] = (float)(short)(v.x & 0xffff); x[1] = (float)(v.x >> 16);
         x[2] = (float)(short)(v.y & 0xffff); x[3] = (float)(v.y >> 16);
         x[4] = (float)(short)(v.z & 0xffff); x[5] = (float)(v.z >> 16);
         x[6] = (float)(short)(v.w & 0xffff); x[7] = (float)(v.w >> 16);
     } else if (ST == SK_K_BF16) {
-        const int4 v = gload(reinterpret_cast<const int4 *>(reinterpret_cast<const uint16_t *>(base) + off));
+        const int4 v = gload<NT>(reinterpret_cast<const int4 *>(reinterpret_cast<const uint16_t *>(base) + off));
         const uint32_t q[4] = {(uint32_t)v.x, (uint32_t)v.y, (uint32_t)v.z, (uint32_t)v.w};
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -60,13 +60,13 @@ __device__ __forceinline__ void fload(const void *base, int64_t off, float (&x)[
         }
     } else {
         const float4 *p = reinterpret_cast<const float4 *>(reinterpret_cast<const float *>(base) + off);
-        const float4 a = gload(p), b = gload(p + 1);
+        const float4 a = gload<NT>(p), b = gload<NT>(p + 1);
         x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
         x[4] = b.x; x[5] = b.y; x[6] = b.z; x[7] = b.w;
     }
 }
 
-template <int ST, int CPT>
+template <int ST, int CPT, bool NT>
 __global__ __launch_bounds__(kFT) void k_fused(const Inst *__restrict__ insts, int inst) {
     __shared__ float red[kFT / kWave][kFR];
     __shared__ float rowinv[kFR];
@@ -123,7 +123,7 @@ __global__ __launch_bounds__(kFT) void k_fused(const Inst *__restrict__ insts, i
                 for (int c = 0; c < 8; ++c) s[rr][k][c] = 0.f;
                 if (row < r1 && own[k]) {
                     float x[8];
-                    fload<ST>(base, (int64_t)row * pitch + c0[k], x);
+                    fload<ST, NT>(base, (int64_t)row * pitch + c0[k], x);
 #pragma unroll
                     for (int c = 0; c < 8; ++c) {
                         float e;
@@ -189,7 +189,7 @@ __global__ __launch_bounds__(kFT) void k_fused(const Inst *__restrict__ insts, i
                 for (int k = 0; k < CPT; ++k) {
                     if (!own[k]) continue;
                     float x[8];
-                    fload<ST>(base, (int64_t)row * pitch + c0[k], x);
+                    fload<ST, NT>(base, (int64_t)row * pitch + c0[k], x);
 #pragma unroll
                     for (int c = 0; c < 8; ++c) {
                         const float Iv = fmaf(x[c], pf, gx[k][c]) + Ff[rr];
@@ -306,7 +306,7 @@ __device__ __forceinline__ void gst(float *p, float v) { *(SK_GLOBAL float *)p =
 // partials with dpp_sum16. The scalar work of row i (its new potentials and
 // residual) is done by lane 0 of wave (i - r0) mod 16, so no single wave falls
 // behind at every barrier.
-template <int CPT, int FR, bool SENT>
+template <int CPT, int FR, bool SENT, bool NT>
 __device__ __forceinline__ void fused_i16_body(const Inst &I, Ctl *ctl, const float *tab,
                                                float (*red)[kFT / kWave][kFR], int *redm,
                                                float *reds, float *wres, float *gl) {
@@ -347,7 +347,7 @@ __device__ __forceinline__ void fused_i16_body(const Inst &I, Ctl *ctl, const fl
 #pragma unroll
             for (int k = 0; k < CPT; ++k)
                 buf[rr][k] = (rb + rr < r1 && own[k])
-                                 ? gload(reinterpret_cast<const int4 *>(W + (int64_t)(rb + rr) * pitch + c0[k]))
+                                 ? gload<NT>(reinterpret_cast<const int4 *>(W + (int64_t)(rb + rr) * pitch + c0[k]))
                                  : make_int4(0, 0, 0, 0);
     };
     int parity = 0;
@@ -504,7 +504,7 @@ __device__ __forceinline__ void fused_i16_body(const Inst &I, Ctl *ctl, const fl
 
 // Rows per group: two with 8 owned columns per thread, one with 16 (register
 // budget of 128 VGPRs at 1024 threads).
-template <int CPT>
+template <int CPT, bool NT>
 __global__ __launch_bounds__(kFT) void k_fused_i16(const Inst *__restrict__ insts, int inst) {
     constexpr int FR = CPT == 1 ? 2 : 1;
     __shared__ float tab[kTabN];
@@ -518,31 +518,38 @@ __global__ __launch_bounds__(kFT) void k_fused_i16(const Inst *__restrict__ inst
     if (ctl->state != ST_RUNNING) return;
     fill_exp_table(tab);
     __syncthreads();
-    if (ctl->sent != 0u) fused_i16_body<CPT, FR, true>(I, ctl, tab, red, redm, reds, wres, gl);
-    else fused_i16_body<CPT, FR, false>(I, ctl, tab, red, redm, reds, wres, gl);
+    if (ctl->sent != 0u) fused_i16_body<CPT, FR, true, NT>(I, ctl, tab, red, redm, reds, wres, gl);
+    else fused_i16_body<CPT, FR, false, NT>(I, ctl, tab, red, redm, reds, wres, gl);
 }
 
-template <int ST>
+template <int ST, bool NT>
 static hipError_t launch_fused_st(const Inst *d_insts, int inst, int n, int grid, hipStream_t st) {
     const int cpt = (n / 8 + kFT - 1) / kFT;
     if (cpt <= 1)
-        hipLaunchKernelGGL((k_fused<ST, 1>), dim3(grid), dim3(kFT), 0, st, d_insts, inst);
+        hipLaunchKernelGGL((k_fused<ST, 1, NT>), dim3(grid), dim3(kFT), 0, st, d_insts, inst);
     else
-        hipLaunchKernelGGL((k_fused<ST, 2>), dim3(grid), dim3(kFT), 0, st, d_insts, inst);
+        hipLaunchKernelGGL((k_fused<ST, 2, NT>), dim3(grid), dim3(kFT), 0, st, d_insts, inst);
     return hipGetLastError();
 }
 
-hipError_t launch_fused(const Inst *d_insts, int inst, int n, int grid, int storage,
-                        hipStream_t st) {
+template <bool NT>
+static hipError_t launch_fused_nt(const Inst *d_insts, int inst, int n, int grid, int storage,
+                                  hipStream_t st) {
     if (storage == SK_W_I16) {
         if ((n / 8 + kFT - 1) / kFT <= 1)
-            hipLaunchKernelGGL(k_fused_i16<1>, dim3(grid), dim3(kFT), 0, st, d_insts, inst);
+            hipLaunchKernelGGL((k_fused_i16<1, NT>), dim3(grid), dim3(kFT), 0, st, d_insts, inst);
         else
-            hipLaunchKernelGGL(k_fused_i16<2>, dim3(grid), dim3(kFT), 0, st, d_insts, inst);
+            hipLaunchKernelGGL((k_fused_i16<2, NT>), dim3(grid), dim3(kFT), 0, st, d_insts, inst);
         return hipGetLastError();
     }
-    if (storage == SK_K_BF16) return launch_fused_st<SK_K_BF16>(d_insts, inst, n, grid, st);
-    return launch_fused_st<SK_K_F32>(d_insts, inst, n, grid, st);
+    if (storage == SK_K_BF16) return launch_fused_st<SK_K_BF16, NT>(d_insts, inst, n, grid, st);
+    return launch_fused_st<SK_K_F32, NT>(d_insts, inst, n, grid, st);
+}
+
+hipError_t launch_fused(const Inst *d_insts, int inst, int n, int grid, int storage, int nt_loads,
+                        hipStream_t st) {
+    return nt_loads ? launch_fused_nt<true>(d_insts, inst, n, grid, storage, st)
+                    : launch_fused_nt<false>(d_insts, inst, n, grid, storage, st);
 }
 
 }  // namespace sk

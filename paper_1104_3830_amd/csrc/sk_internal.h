@@ -45,6 +45,7 @@ struct Inst {
     int64_t pitch;
     int32_t n;
     int32_t vec8;           // 1: n % 8 == 0 and rows 16-byte aligned -> 8-wide loads
+    int32_t nt;             // 1: sweeps launched with non-temporal matrix loads (batch > kNtBytes)
     int32_t nseg;           // row segments of the column sweep
     int32_t seg_rows;
     int32_t ntiles;         // column tiles of the column sweep
@@ -98,15 +99,36 @@ __device__ __forceinline__ int deform_p(const Inst &I, int64_t m) {
 typedef int sk_gi4 __attribute__((ext_vector_type(4)));
 typedef float sk_gf4 __attribute__((ext_vector_type(4)));
 #define SK_GLOBAL __attribute__((address_space(1)))
+// Matrix loads (W or K). With NT they carry the non-temporal hint: when the
+// batch's matrices exceed the last-level cache a pass reads each entry once,
+// and keeping the stream out of the caches' normal replacement made the
+// n = 16384 sweeps 4-6% faster; a batch that fits (re-read every iteration
+// from the cache) is slower with it. NT is a template parameter of the sweep
+// kernels (the hint is an instruction bit; a run-time choice between two
+// otherwise identical loads is merged by the compiler), chosen at launch from
+// Inst::nt.
+template <bool NT>
 __device__ __forceinline__ int4 gload(const int4 *p) {
-    const sk_gi4 v = *(const SK_GLOBAL sk_gi4 *)p;
+    sk_gi4 v;
+    if constexpr (NT) v = __builtin_nontemporal_load((const SK_GLOBAL sk_gi4 *)p);
+    else v = *(const SK_GLOBAL sk_gi4 *)p;
     return make_int4(v.x, v.y, v.z, v.w);
 }
+template <bool NT>
 __device__ __forceinline__ float4 gload(const float4 *p) {
-    const sk_gf4 v = *(const SK_GLOBAL sk_gf4 *)p;
+    sk_gf4 v;
+    if constexpr (NT) v = __builtin_nontemporal_load((const SK_GLOBAL sk_gf4 *)p);
+    else v = *(const SK_GLOBAL sk_gf4 *)p;
     return make_float4(v.x, v.y, v.z, v.w);
 }
-__device__ __forceinline__ int16_t gload(const int16_t *p) { return *(const SK_GLOBAL int16_t *)p; }
+template <bool NT>
+__device__ __forceinline__ int16_t gload(const int16_t *p) {
+    if constexpr (NT) return __builtin_nontemporal_load((const SK_GLOBAL int16_t *)p);
+    else return *(const SK_GLOBAL int16_t *)p;
+}
+// Matrix bytes of a batch above which its loads take the non-temporal hint
+// (three quarters of MI355X's 256 MiB last-level cache).
+constexpr size_t kNtBytes = size_t(192) << 20;
 
 // Newton scaling (Knight-Ruiz) of one instance: state of the device-side
 // outer/inner (conjugate gradient) iteration on the 2n-vectors of the
@@ -137,12 +159,12 @@ constexpr int kFinCols = 64;
 hipError_t launch_init(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid, int cold,
                        hipStream_t st);
 hipError_t launch_row_sweep(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
-                            size_t lds_bytes, hipStream_t st);
+                            size_t lds_bytes, int nt_loads, hipStream_t st);
 hipError_t launch_col_sweep(const Inst *d_insts, const ColUnit *d_units, int nunits, int grid,
-                            hipStream_t st);
+                            int nt_loads, hipStream_t st);
 hipError_t launch_nt_product(const Inst *d_insts, const RowUnit *d_rows, int nrows, int row_grid,
                              size_t row_lds, const ColUnit *d_cols, int ncols, int col_grid,
-                             const NtCtl *nt, NtVec vec, int n, hipStream_t st);
+                             const NtCtl *nt, NtVec vec, int n, int nt_loads, hipStream_t st);
 // nt: two control blocks (double-buffered by phase parity; nt[1] is current).
 hipError_t launch_nt_step(const Inst *d_insts, NtCtl *nt, NtVec vec, int n, hipStream_t st);
 hipError_t launch_nt_fold(const Inst *d_insts, const NtCtl *nt, NtVec vec, int n, int last,
@@ -168,15 +190,17 @@ hipError_t launch_prune_fill(const Inst *d_insts, const RowUnit *d_units, int nu
 hipError_t launch_absorb(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
                          size_t lds_bytes, int storage, hipStream_t st);
 hipError_t launch_row_sweep_k(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
-                              size_t lds_bytes, int storage, hipStream_t st);
+                              size_t lds_bytes, int storage, int nt_loads,
+                              hipStream_t st);
 hipError_t launch_col_sweep_k(const Inst *d_insts, const ColUnit *d_units, int nunits, int grid,
-                              int storage, hipStream_t st);
+                              int storage, int nt_loads,
+                              hipStream_t st);
 hipError_t launch_fold_k(const Inst *d_insts, int count, hipStream_t st);
 hipError_t launch_advance(const Inst *d_insts, int count, hipStream_t st);
 hipError_t launch_check_k(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid, int inst,
                           int n, int nseg, int storage, double *rsum, double *part, double *csum,
                           hipStream_t st);
-hipError_t launch_fused(const Inst *d_insts, int inst, int n, int grid, int storage,
+hipError_t launch_fused(const Inst *d_insts, int inst, int n, int grid, int storage, int nt_loads,
                         hipStream_t st);
 hipError_t launch_gather_ctl(const Inst *d_insts, int count, Ctl *out, hipStream_t st);
 hipError_t launch_reset_ctl(const Inst *d_insts, const int *idx, int m, hipStream_t st);

@@ -87,13 +87,13 @@ __device__ __forceinline__ void visit_row(const Inst &I, const int16_t *wr, int 
         for (; j0 + (U - 1) * 512 < n; j0 += U * 512) {
             int4 v[U];
 #pragma unroll
-            for (int k = 0; k < U; ++k) v[k] = gload(reinterpret_cast<const int4 *>(wr + j0 + k * 512));
+            for (int k = 0; k < U; ++k) v[k] = gload<false>(reinterpret_cast<const int4 *>(wr + j0 + k * 512));
 #pragma unroll
             for (int k = 0; k < U; ++k) use(v[k], j0 + k * 512);
         }
-        for (; j0 < n; j0 += 512) use(gload(reinterpret_cast<const int4 *>(wr + j0)), j0);
+        for (; j0 < n; j0 += 512) use(gload<false>(reinterpret_cast<const int4 *>(wr + j0)), j0);
     } else {
-        for (int j = lane; j < n; j += kWave) f(j, (int)gload(wr + j));
+        for (int j = lane; j < n; j += kWave) f(j, (int)gload<false>(wr + j));
     }
 }
 
@@ -194,7 +194,7 @@ __device__ __forceinline__ float chunk8(const int4 v, int q, int n8, int p4, int
 
 // Row partial sum for one lane: chunks lane*8 + k*512, SK_ROW_UNROLL 16-byte
 // loads in flight per lane.
-template <bool SENT>
+template <bool SENT, bool NT>
 __device__ __forceinline__ float row_partial_v8(const int16_t *__restrict__ wr, int n, int p4,
                                                 int B, const ColPot *__restrict__ cp,
                                                 const float *__restrict__ tab, int lane) {
@@ -206,7 +206,7 @@ __device__ __forceinline__ float row_partial_v8(const int16_t *__restrict__ wr, 
     // two register buffers (see the column sweep); chunks are still added in order
     auto ld = [&](int4 (&v)[U], int jj) {
 #pragma unroll
-        for (int k = 0; k < U; ++k) v[k] = gload(reinterpret_cast<const int4 *>(wr + jj + k * 512));
+        for (int k = 0; k < U; ++k) v[k] = gload<NT>(reinterpret_cast<const int4 *>(wr + jj + k * 512));
     };
     auto use = [&](const int4 (&v)[U], int jj) {
 #pragma unroll
@@ -234,27 +234,27 @@ __device__ __forceinline__ float row_partial_v8(const int16_t *__restrict__ wr, 
     for (; j0 + (U - 1) * 512 < n; j0 += U * 512) {
         int4 v[U];
 #pragma unroll
-        for (int k = 0; k < U; ++k) v[k] = gload(reinterpret_cast<const int4 *>(wr + j0 + k * 512));
+        for (int k = 0; k < U; ++k) v[k] = gload<NT>(reinterpret_cast<const int4 *>(wr + j0 + k * 512));
         const int q = j0 >> 3;
 #pragma unroll
         for (int k = 0; k < U; ++k) acc += chunk8<SENT>(v[k], q + 64 * k, n8, p4, B, cp, tab);
     }
 #endif
     for (; j0 < n; j0 += 512) {
-        const int4 v = gload(reinterpret_cast<const int4 *>(wr + j0));
+        const int4 v = gload<NT>(reinterpret_cast<const int4 *>(wr + j0));
         acc += chunk8<SENT>(v, j0 >> 3, n8, p4, B, cp, tab);
     }
     return acc;
 }
 
 // max_j of 4 (p w_ij + G_j) + B over the entries of the row (INT_MIN if none).
-template <bool SENT>
+template <bool SENT, bool NT>
 __device__ __forceinline__ int row_max_v8(const int16_t *__restrict__ wr, int n, int p4, int B,
                                           const ColPot *__restrict__ cp, int lane) {
     const int n8 = n >> 3;
     int m = INT_MIN;
     for (int j0 = lane * 8; j0 < n; j0 += 512) {
-        const int4 v = gload(reinterpret_cast<const int4 *>(wr + j0));
+        const int4 v = gload<NT>(reinterpret_cast<const int4 *>(wr + j0));
         int w[8];
         unpack8i(v, w);
         const int q = j0 >> 3;
@@ -267,13 +267,13 @@ __device__ __forceinline__ int row_max_v8(const int16_t *__restrict__ wr, int n,
     return m;
 }
 
-template <bool SENT>
+template <bool SENT, bool NT>
 __device__ __forceinline__ float row_partial_v1(const int16_t *__restrict__ wr, int n, int p4,
                                                 int B, const ColPot *__restrict__ cp,
                                                 const float *__restrict__ tab, int lane) {
     float acc = 0.f;
     for (int j = lane; j < n; j += kWave) {
-        const int w = (int)gload(wr + j);
+        const int w = (int)gload<NT>(wr + j);
         const ColPot k = cp[j];
         float e = tab_at(tab, tab_off(p4, w, k.a, B));
         if (SENT) e = (w == SK_SENTINEL) ? 0.f : e;
@@ -282,12 +282,12 @@ __device__ __forceinline__ float row_partial_v1(const int16_t *__restrict__ wr, 
     return acc;
 }
 
-template <bool SENT>
+template <bool SENT, bool NT>
 __device__ __forceinline__ int row_max_v1(const int16_t *__restrict__ wr, int n, int p4, int B,
                                           const ColPot *__restrict__ cp, int lane) {
     int m = INT_MIN;
     for (int j = lane; j < n; j += kWave) {
-        const int w = (int)gload(wr + j);
+        const int w = (int)gload<NT>(wr + j);
         const int t = __mul24(p4, w) + cp[j].a + B;
         if (!SENT || w != SK_SENTINEL) m = max(m, t);
     }
@@ -297,7 +297,7 @@ __device__ __forceinline__ int row_max_v1(const int16_t *__restrict__ wr, int n,
 // Completes the row step of `row` from its sum S relative to the previous
 // iterate (shift 0): the exact max-shifted recompute if S left the safe
 // range, then the new potentials and the residual.
-template <bool SENT, bool V8>
+template <bool SENT, bool V8, bool NT>
 __device__ __forceinline__ float row_finish(const Inst &I, int row, int par, int lane, int Fi,
                                             float phi, float S, const ColPot *__restrict__ cp,
                                             const float *__restrict__ tab) {
@@ -307,16 +307,16 @@ __device__ __forceinline__ float row_finish(const Inst &I, int row, int par, int
     int M = 0;
     if (!(S >= kSafeLo && S <= kSafeHi)) {
         // exact max-shift (Section 4.1.2): M = max_j (p w_ij + F_i + G_j)
-        int m4 = V8 ? row_max_v8<SENT>(wr, n, p4, 4 * Fi, cp, lane)
-                    : row_max_v1<SENT>(wr, n, p4, 4 * Fi, cp, lane);
+        int m4 = V8 ? row_max_v8<SENT, NT>(wr, n, p4, 4 * Fi, cp, lane)
+                    : row_max_v1<SENT, NT>(wr, n, p4, 4 * Fi, cp, lane);
         m4 = wave_max_i(m4);
         if (m4 == INT_MIN) {
             if (lane == 0) atomicOr(&I.ctl->err, ERR_EMPTY_ROW);
             S = 1.f;
         } else {
             M = m4 >> 2;  // exact: m4 is a multiple of 4
-            S = V8 ? row_partial_v8<SENT>(wr, n, p4, 4 * (Fi - M - kTabLo), cp, tab, lane)
-                   : row_partial_v1<SENT>(wr, n, p4, 4 * (Fi - M - kTabLo), cp, tab, lane);
+            S = V8 ? row_partial_v8<SENT, NT>(wr, n, p4, 4 * (Fi - M - kTabLo), cp, tab, lane)
+                   : row_partial_v1<SENT, NT>(wr, n, p4, 4 * (Fi - M - kTabLo), cp, tab, lane);
             S = wave_sum(S);
         }
     }
@@ -336,7 +336,7 @@ __device__ __forceinline__ float row_finish(const Inst &I, int row, int par, int
     return 0.f;
 }
 
-template <bool SENT, bool V8>
+template <bool SENT, bool V8, bool NT>
 __device__ __forceinline__ float row_step_one(const Inst &I, int row, int par, int lane,
                                              const ColPot *__restrict__ cp,
                                              const float *__restrict__ tab) {
@@ -346,10 +346,10 @@ __device__ __forceinline__ float row_step_one(const Inst &I, int row, int par, i
     // loaded with F_i so that the end of the row does not wait for it
     const float phi = I.phi[par][row];
     const int p4 = 4 * I.ctl->p;
-    float S = V8 ? row_partial_v8<SENT>(wr, n, p4, 4 * (Fi - kTabLo), cp, tab, lane)
-                 : row_partial_v1<SENT>(wr, n, p4, 4 * (Fi - kTabLo), cp, tab, lane);
+    float S = V8 ? row_partial_v8<SENT, NT>(wr, n, p4, 4 * (Fi - kTabLo), cp, tab, lane)
+                 : row_partial_v1<SENT, NT>(wr, n, p4, 4 * (Fi - kTabLo), cp, tab, lane);
     S = wave_sum(S);
-    return row_finish<SENT, V8>(I, row, par, lane, Fi, phi, S, cp, tab);
+    return row_finish<SENT, V8, NT>(I, row, par, lane, Fi, phi, S, cp, tab);
 }
 
 // Two rows in one pass over the columns: each column's (4 G_j, exp(gam_j))
@@ -379,7 +379,7 @@ __device__ __forceinline__ void chunk8x2(const int4 v0, const int4 v1, int q, in
     }
 }
 
-template <bool SENT>
+template <bool SENT, bool NT>
 __device__ __forceinline__ void row_partial2_v8(const int16_t *__restrict__ wr0,
                                                 const int16_t *__restrict__ wr1, int n, int p4,
                                                 int B0, int B1, const ColPot *__restrict__ cp,
@@ -394,8 +394,8 @@ __device__ __forceinline__ void row_partial2_v8(const int16_t *__restrict__ wr0,
         int4 v0[U], v1[U];
 #pragma unroll
         for (int k = 0; k < U; ++k) {
-            v0[k] = gload(reinterpret_cast<const int4 *>(wr0 + j0 + k * 512));
-            v1[k] = gload(reinterpret_cast<const int4 *>(wr1 + j0 + k * 512));
+            v0[k] = gload<NT>(reinterpret_cast<const int4 *>(wr0 + j0 + k * 512));
+            v1[k] = gload<NT>(reinterpret_cast<const int4 *>(wr1 + j0 + k * 512));
         }
         const int q = j0 >> 3;
 #pragma unroll
@@ -408,15 +408,15 @@ __device__ __forceinline__ void row_partial2_v8(const int16_t *__restrict__ wr0,
     }
     for (; j0 < n; j0 += 512) {
         float s0, s1;
-        chunk8x2<SENT>(gload(reinterpret_cast<const int4 *>(wr0 + j0)),
-                       gload(reinterpret_cast<const int4 *>(wr1 + j0)), j0 >> 3, n8, p4, B0, B1, cp,
+        chunk8x2<SENT>(gload<NT>(reinterpret_cast<const int4 *>(wr0 + j0)),
+                       gload<NT>(reinterpret_cast<const int4 *>(wr1 + j0)), j0 >> 3, n8, p4, B0, B1, cp,
                        tab, s0, s1);
         acc0 += s0;
         acc1 += s1;
     }
 }
 
-template <bool SENT>
+template <bool SENT, bool NT>
 __device__ __forceinline__ float row_step_pair(const Inst &I, int ra, int rb, int par, int lane,
                                               const ColPot *__restrict__ cp,
                                               const float *__restrict__ tab) {
@@ -424,12 +424,12 @@ __device__ __forceinline__ float row_step_pair(const Inst &I, int ra, int rb, in
     const int Fa = I.F[par][ra], Fb = I.F[par][rb];
     const int p4 = 4 * I.ctl->p;
     float Sa, Sb;
-    row_partial2_v8<SENT>(I.W + (int64_t)ra * I.pitch, I.W + (int64_t)rb * I.pitch, n, p4,
+    row_partial2_v8<SENT, NT>(I.W + (int64_t)ra * I.pitch, I.W + (int64_t)rb * I.pitch, n, p4,
                           4 * (Fa - kTabLo), 4 * (Fb - kTabLo), cp, tab, lane, Sa, Sb);
     Sa = wave_sum(Sa);
     Sb = wave_sum(Sb);
-    const float ea = row_finish<SENT, true>(I, ra, par, lane, Fa, I.phi[par][ra], Sa, cp, tab);
-    const float eb = row_finish<SENT, true>(I, rb, par, lane, Fb, I.phi[par][rb], Sb, cp, tab);
+    const float ea = row_finish<SENT, true, NT>(I, ra, par, lane, Fa, I.phi[par][ra], Sa, cp, tab);
+    const float eb = row_finish<SENT, true, NT>(I, rb, par, lane, Fb, I.phi[par][rb], Sb, cp, tab);
     return fmaxf(ea, eb);
 }
 
@@ -439,6 +439,7 @@ __device__ __forceinline__ float row_step_pair(const Inst &I, int ra, int rb, in
 // each wave's maximum to one of the instance's rowres slots (an exact
 // maximum, so the column sweep's reduction of the slots equals the
 // finalise's value; it uses it to skip a detection pass).
+template <bool NT>
 __global__ __launch_bounds__(kRowWaves * kWave) void k_row_sweep(const Inst *__restrict__ insts,
                                                                    const RowUnit *__restrict__ units,
                                                                    int nunits) {
@@ -493,15 +494,15 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_row_sweep(const Inst *__r
         const int rb = pair ? units[u + 1].row0 + wave : n;
         float e = 0.f;
         if (rb < n) {
-            e = sent ? row_step_pair<true>(I, ra, rb, par, lane, lds_cp, tab)
-                     : row_step_pair<false>(I, ra, rb, par, lane, lds_cp, tab);
+            e = sent ? row_step_pair<true, NT>(I, ra, rb, par, lane, lds_cp, tab)
+                     : row_step_pair<false, NT>(I, ra, rb, par, lane, lds_cp, tab);
         } else if (ra < n) {
             if (I.vec8) {
-                e = sent ? row_step_one<true, true>(I, ra, par, lane, lds_cp, tab)
-                         : row_step_one<false, true>(I, ra, par, lane, lds_cp, tab);
+                e = sent ? row_step_one<true, true, NT>(I, ra, par, lane, lds_cp, tab)
+                         : row_step_one<false, true, NT>(I, ra, par, lane, lds_cp, tab);
             } else {
-                e = sent ? row_step_one<true, false>(I, ra, par, lane, lds_cp, tab)
-                         : row_step_one<false, false>(I, ra, par, lane, lds_cp, tab);
+                e = sent ? row_step_one<true, false, NT>(I, ra, par, lane, lds_cp, tab)
+                         : row_step_one<false, false, NT>(I, ra, par, lane, lds_cp, tab);
             }
         }
         wres = fmaxf(wres, e);
@@ -546,7 +547,7 @@ struct alignas(8) RowPot {
     float r;
 };
 
-template <bool SENT, bool V8>
+template <bool SENT, bool V8, bool NT>
 __device__ __forceinline__ void col_partial(const Inst &I, int tile, int r0, int r1, int wave,
                                             int lane, const RowPot *__restrict__ rowpot,
                                             const float *__restrict__ tab, float (&acc)[8]) {
@@ -582,7 +583,7 @@ __device__ __forceinline__ void col_partial(const Inst &I, int tile, int r0, int
         auto ld = [&](int4 (&v)[U], int rr) {
 #pragma unroll
             for (int k = 0; k < U; ++k)
-                v[k] = gload(reinterpret_cast<const int4 *>(base + (int64_t)(rr + k * S) * pitch));
+                v[k] = gload<NT>(reinterpret_cast<const int4 *>(base + (int64_t)(rr + k * S) * pitch));
         };
         auto use = [&](const int4 (&v)[U], int rr) {
 #pragma unroll
@@ -611,12 +612,12 @@ __device__ __forceinline__ void col_partial(const Inst &I, int tile, int r0, int
             int4 v[U];
 #pragma unroll
             for (int k = 0; k < U; ++k)
-                v[k] = gload(reinterpret_cast<const int4 *>(base + (int64_t)(r + k * S) * pitch));
+                v[k] = gload<NT>(reinterpret_cast<const int4 *>(base + (int64_t)(r + k * S) * pitch));
 #pragma unroll
             for (int k = 0; k < U; ++k) body(v[k], rowpot[r + k * S - r0]);
         }
 #endif
-        for (; r < r1; r += S) body(gload(reinterpret_cast<const int4 *>(base + (int64_t)r * pitch)),
+        for (; r < r1; r += S) body(gload<NT>(reinterpret_cast<const int4 *>(base + (int64_t)r * pitch)),
                                     rowpot[r - r0]);
     } else {
         const int c0 = tile * kColTile1 + lane;
@@ -624,7 +625,7 @@ __device__ __forceinline__ void col_partial(const Inst &I, int tile, int r0, int
         const int A = 4 * I.G[c0];
         for (int r = r0 + wave; r < r1; r += kColWaves) {
             const RowPot rp = rowpot[r - r0];
-            const int w = (int)gload(I.W + (int64_t)r * I.pitch + c0);
+            const int w = (int)gload<NT>(I.W + (int64_t)r * I.pitch + c0);
             float e = tab_at(tab, tab_off(p4, w, A, rp.b));
             if (SENT) e = (w == SK_SENTINEL) ? 0.f : e;
             acc[0] = fmaf(e, rp.r, acc[0]);
@@ -632,6 +633,7 @@ __device__ __forceinline__ void col_partial(const Inst &I, int tile, int r0, int
     }
 }
 
+template <bool NT>
 __global__ __launch_bounds__(kColWaves * kWave) void k_col_sweep(const Inst *__restrict__ insts,
                                                                    const ColUnit *__restrict__ units,
                                                                    int nunits) {
@@ -687,13 +689,13 @@ __global__ __launch_bounds__(kColWaves * kWave) void k_col_sweep(const Inst *__r
         float acc[8];
         const bool sent = ctl->sent != 0u;
         if (I.vec8) {
-            if (sent) col_partial<true, true>(I, un.tile, r0, r1, wave, lane, rowpot, tab, acc);
-            else col_partial<false, true>(I, un.tile, r0, r1, wave, lane, rowpot, tab, acc);
+            if (sent) col_partial<true, true, NT>(I, un.tile, r0, r1, wave, lane, rowpot, tab, acc);
+            else col_partial<false, true, NT>(I, un.tile, r0, r1, wave, lane, rowpot, tab, acc);
 #pragma unroll
             for (int c = 0; c < 8; ++c) red[wave][lane * 8 + c] = acc[c];
         } else {
-            if (sent) col_partial<true, false>(I, un.tile, r0, r1, wave, lane, rowpot, tab, acc);
-            else col_partial<false, false>(I, un.tile, r0, r1, wave, lane, rowpot, tab, acc);
+            if (sent) col_partial<true, false, NT>(I, un.tile, r0, r1, wave, lane, rowpot, tab, acc);
+            else col_partial<false, false, NT>(I, un.tile, r0, r1, wave, lane, rowpot, tab, acc);
             red[wave][lane] = acc[0];
         }
         __syncthreads();
@@ -1046,7 +1048,7 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_check_rows(const Inst *__
                 int4 v[U];
 #pragma unroll
                 for (int k = 0; k < U; ++k)
-                    v[k] = j0 + k * 512 < n ? gload(reinterpret_cast<const int4 *>(wr + j0 + k * 512))
+                    v[k] = j0 + k * 512 < n ? gload<false>(reinterpret_cast<const int4 *>(wr + j0 + k * 512))
                                             : make_int4(0, 0, 0, 0);
 #pragma unroll
                 for (int k = 0; k < U; ++k) {
@@ -1188,12 +1190,12 @@ __global__ __launch_bounds__(kColWaves * kWave) void k_check_cols_part8(const In
             int4 v[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k)
-                v[k] = gload(reinterpret_cast<const int4 *>(w0 + (int64_t)(r + k * kColWaves) * I.pitch));
+                v[k] = gload<false>(reinterpret_cast<const int4 *>(w0 + (int64_t)(r + k * kColWaves) * I.pitch));
 #pragma unroll
             for (int k = 0; k < 4; ++k) check_cols_add8(v[k], p, rowf[r + k * kColWaves - r0], G, gm, s);
         }
         for (; r < r1; r += kColWaves) {
-            const int4 v = gload(reinterpret_cast<const int4 *>(w0 + (int64_t)r * I.pitch));
+            const int4 v = gload<false>(reinterpret_cast<const int4 *>(w0 + (int64_t)r * I.pitch));
             check_cols_add8(v, p, rowf[r - r0], G, gm, s);
         }
     }
@@ -1362,7 +1364,7 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_prune_fill(const Inst *__
                     // the next U chunks of this lane, loaded together
 #pragma unroll
                     for (int k = 0; k < U; ++k)
-                        vb[k] = j0 + k * 512 < n ? gload(reinterpret_cast<const int4 *>(wr + j0 + k * 512))
+                        vb[k] = j0 + k * 512 < n ? gload<false>(reinterpret_cast<const int4 *>(wr + j0 + k * 512))
                                                  : make_int4(0, 0, 0, 0);
                 }
                 int wv[8];
@@ -1477,6 +1479,7 @@ __global__ __launch_bounds__(256) void k_reset_ctl(const Inst *__restrict__ inst
 // instance's potentials (fixed during a Newton solve): sd[i] = (X q_c)_i and
 // sd[n + j] = (X^T q_r)_j for q = (q_r, q_c), each term formed as in the
 // sweeps, exp(E_ij) exp(phi_i) exp(gam_j). One instance (index 0).
+template <bool NT>
 __global__ __launch_bounds__(kRowWaves * kWave) void k_nt_rows(const Inst *__restrict__ insts,
                                                                  const RowUnit *__restrict__ units,
                                                                  int nunits,
@@ -1508,15 +1511,16 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_nt_rows(const Inst *__res
         const int16_t *wr = I.W + (int64_t)row * I.pitch;
         const int B = 4 * (I.F[par][row] - kTabLo);
         float S;
-        if (I.vec8) S = sent ? row_partial_v8<true>(wr, n, p4, B, lds_cp, tab, lane)
-                             : row_partial_v8<false>(wr, n, p4, B, lds_cp, tab, lane);
-        else S = sent ? row_partial_v1<true>(wr, n, p4, B, lds_cp, tab, lane)
-                      : row_partial_v1<false>(wr, n, p4, B, lds_cp, tab, lane);
+        if (I.vec8) S = sent ? row_partial_v8<true, NT>(wr, n, p4, B, lds_cp, tab, lane)
+                             : row_partial_v8<false, NT>(wr, n, p4, B, lds_cp, tab, lane);
+        else S = sent ? row_partial_v1<true, NT>(wr, n, p4, B, lds_cp, tab, lane)
+                      : row_partial_v1<false, NT>(wr, n, p4, B, lds_cp, tab, lane);
         S = wave_sum(S);
         if (lane == 0) sd[row] = ex2(I.phi[par][row] * kLog2e) * S;
     }
 }
 
+template <bool NT>
 __global__ __launch_bounds__(kColWaves * kWave) void k_nt_cols(const Inst *__restrict__ insts,
                                                                  const ColUnit *__restrict__ units,
                                                                  int nunits,
@@ -1550,13 +1554,13 @@ __global__ __launch_bounds__(kColWaves * kWave) void k_nt_cols(const Inst *__res
         __syncthreads();
         float acc[8];
         if (I.vec8) {
-            if (sent) col_partial<true, true>(I, un.tile, r0, r1, wave, lane, rowpot, tab, acc);
-            else col_partial<false, true>(I, un.tile, r0, r1, wave, lane, rowpot, tab, acc);
+            if (sent) col_partial<true, true, NT>(I, un.tile, r0, r1, wave, lane, rowpot, tab, acc);
+            else col_partial<false, true, NT>(I, un.tile, r0, r1, wave, lane, rowpot, tab, acc);
 #pragma unroll
             for (int c = 0; c < 8; ++c) red[wave][lane * 8 + c] = acc[c];
         } else {
-            if (sent) col_partial<true, false>(I, un.tile, r0, r1, wave, lane, rowpot, tab, acc);
-            else col_partial<false, false>(I, un.tile, r0, r1, wave, lane, rowpot, tab, acc);
+            if (sent) col_partial<true, false, NT>(I, un.tile, r0, r1, wave, lane, rowpot, tab, acc);
+            else col_partial<false, false, NT>(I, un.tile, r0, r1, wave, lane, rowpot, tab, acc);
             red[wave][lane] = acc[0];
         }
         __syncthreads();
@@ -1876,15 +1880,23 @@ hipError_t launch_init(const Inst *d_insts, const RowUnit *d_units, int nunits, 
     return hipGetLastError();
 }
 hipError_t launch_row_sweep(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
-                            size_t lds_bytes, hipStream_t st) {
-    hipLaunchKernelGGL(k_row_sweep, dim3(grid), dim3(kRowWaves * kWave), lds_bytes, st, d_insts,
-                       d_units, nunits);
+                            size_t lds_bytes, int nt_loads, hipStream_t st) {
+    if (nt_loads)
+        hipLaunchKernelGGL(k_row_sweep<true>, dim3(grid), dim3(kRowWaves * kWave), lds_bytes, st,
+                           d_insts, d_units, nunits);
+    else
+        hipLaunchKernelGGL(k_row_sweep<false>, dim3(grid), dim3(kRowWaves * kWave), lds_bytes, st,
+                           d_insts, d_units, nunits);
     return hipGetLastError();
 }
 hipError_t launch_col_sweep(const Inst *d_insts, const ColUnit *d_units, int nunits, int grid,
-                            hipStream_t st) {
-    hipLaunchKernelGGL(k_col_sweep, dim3(grid), dim3(kColWaves * kWave), 0, st, d_insts, d_units,
-                       nunits);
+                            int nt_loads, hipStream_t st) {
+    if (nt_loads)
+        hipLaunchKernelGGL(k_col_sweep<true>, dim3(grid), dim3(kColWaves * kWave), 0, st, d_insts,
+                           d_units, nunits);
+    else
+        hipLaunchKernelGGL(k_col_sweep<false>, dim3(grid), dim3(kColWaves * kWave), 0, st, d_insts,
+                           d_units, nunits);
     return hipGetLastError();
 }
 hipError_t launch_col_finalize(const Inst *d_insts, const FinUnit *d_units, int nunits, int grid,
@@ -1894,12 +1906,19 @@ hipError_t launch_col_finalize(const Inst *d_insts, const FinUnit *d_units, int 
 }
 hipError_t launch_nt_product(const Inst *d_insts, const RowUnit *d_rows, int nrows, int row_grid,
                              size_t row_lds, const ColUnit *d_cols, int ncols, int col_grid,
-                             const NtCtl *nt, NtVec vec, int n, hipStream_t st) {
+                             const NtCtl *nt, NtVec vec, int n, int nt_loads, hipStream_t st) {
     const NtCtl *cur = nt + 1;  // the state after the last completed step
-    hipLaunchKernelGGL(k_nt_rows, dim3(row_grid), dim3(kRowWaves * kWave), row_lds, st, d_insts,
-                       d_rows, nrows, cur, vec.q, vec.sd);
-    hipLaunchKernelGGL(k_nt_cols, dim3(col_grid), dim3(kColWaves * kWave), 0, st, d_insts, d_cols,
-                       ncols, cur, vec.q);
+    if (nt_loads) {
+        hipLaunchKernelGGL(k_nt_rows<true>, dim3(row_grid), dim3(kRowWaves * kWave), row_lds, st,
+                           d_insts, d_rows, nrows, cur, vec.q, vec.sd);
+        hipLaunchKernelGGL(k_nt_cols<true>, dim3(col_grid), dim3(kColWaves * kWave), 0, st, d_insts,
+                           d_cols, ncols, cur, vec.q);
+    } else {
+        hipLaunchKernelGGL(k_nt_rows<false>, dim3(row_grid), dim3(kRowWaves * kWave), row_lds, st,
+                           d_insts, d_rows, nrows, cur, vec.q, vec.sd);
+        hipLaunchKernelGGL(k_nt_cols<false>, dim3(col_grid), dim3(kColWaves * kWave), 0, st, d_insts,
+                           d_cols, ncols, cur, vec.q);
+    }
     hipLaunchKernelGGL(k_nt_cols_sum, dim3((n + 255) / 256), dim3(256), 0, st, d_insts, cur, vec.sd);
     return hipGetLastError();
 }
@@ -1964,12 +1983,10 @@ hipError_t launch_prune_fill(const Inst *d_insts, const RowUnit *d_units, int nu
 hipError_t set_kernel_attributes() {
     const int lds = (int)(kMaxN * sizeof(double));
     hipError_t e;
-    if ((e = hipFuncSetAttribute((const void *)k_row_sweep, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 lds)) != hipSuccess)
-        return e;
-    if ((e = hipFuncSetAttribute((const void *)k_nt_rows, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 lds)) != hipSuccess)
-        return e;
+    for (const void *f : {(const void *)k_row_sweep<true>, (const void *)k_row_sweep<false>,
+                          (const void *)k_nt_rows<true>, (const void *)k_nt_rows<false>})
+        if ((e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds)) != hipSuccess)
+            return e;
     if ((e = hipFuncSetAttribute((const void *)k_check_rows,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds)) != hipSuccess)
         return e;

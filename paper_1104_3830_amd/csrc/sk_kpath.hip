@@ -51,10 +51,10 @@ __device__ __forceinline__ uint32_t bf16_rne(float x) {
 }
 
 // Loads 8 consecutive K values starting at a multiple of 8.
-template <int ST>
+template <int ST, bool NT>
 __device__ __forceinline__ void load8(const void *K, int64_t off, float (&k)[8]) {
     if (ST == SK_K_BF16) {
-        const int4 v = gload(reinterpret_cast<const int4 *>(reinterpret_cast<const uint16_t *>(K) + off));
+        const int4 v = gload<NT>(reinterpret_cast<const int4 *>(reinterpret_cast<const uint16_t *>(K) + off));
         const uint32_t x[4] = {(uint32_t)v.x, (uint32_t)v.y, (uint32_t)v.z, (uint32_t)v.w};
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -63,7 +63,7 @@ __device__ __forceinline__ void load8(const void *K, int64_t off, float (&k)[8])
         }
     } else {
         const float4 *p = reinterpret_cast<const float4 *>(reinterpret_cast<const float *>(K) + off);
-        const float4 a = gload(p), b = gload(p + 1);
+        const float4 a = gload<NT>(p), b = gload<NT>(p + 1);
         k[0] = a.x; k[1] = a.y; k[2] = a.z; k[3] = a.w;
         k[4] = b.x; k[5] = b.y; k[6] = b.z; k[7] = b.w;
     }
@@ -109,7 +109,7 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_absorb(const Inst *__rest
             // 8 columns per lane: one 16-byte load of W, one 16/32-byte store of K
             const int n8 = n >> 3;
             for (int j0 = lane * 8; j0 < n; j0 += 512) {
-                const int4 v = gload(reinterpret_cast<const int4 *>(wr + j0));
+                const int4 v = gload<false>(reinterpret_cast<const int4 *>(wr + j0));
                 const int q[4] = {v.x, v.y, v.z, v.w};
                 float k[8];
 #pragma unroll
@@ -172,7 +172,7 @@ __global__ __launch_bounds__(256) void k_absorb_done(const Inst *__restrict__ in
 }
 
 // ---------------------------------------------------------------- K row sweep
-template <int ST>
+template <int ST, bool NT>
 __global__ __launch_bounds__(kRowWaves * kWave) void k_row_sweep_k(const Inst *__restrict__ insts,
                                                                    const RowUnit *__restrict__ units,
                                                                    int nunits) {
@@ -203,10 +203,10 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_row_sweep_k(const Inst *_
             int j0 = lane * 8;
             for (; j0 + 3 * 512 < kp; j0 += 4 * 512) {
                 float k0[8], k1[8], k2[8], k3[8];
-                load8<ST>(I.K, rbase + j0, k0);
-                load8<ST>(I.K, rbase + j0 + 512, k1);
-                load8<ST>(I.K, rbase + j0 + 1024, k2);
-                load8<ST>(I.K, rbase + j0 + 1536, k3);
+                load8<ST, NT>(I.K, rbase + j0, k0);
+                load8<ST, NT>(I.K, rbase + j0 + 512, k1);
+                load8<ST, NT>(I.K, rbase + j0 + 1024, k2);
+                load8<ST, NT>(I.K, rbase + j0 + 1536, k3);
                 const int q = j0 >> 3;
                 float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
 #pragma unroll
@@ -220,7 +220,7 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_row_sweep_k(const Inst *_
             }
             for (; j0 < kp; j0 += 512) {
                 float k[8];
-                load8<ST>(I.K, rbase + j0, k);
+                load8<ST, NT>(I.K, rbase + j0, k);
                 const int q = j0 >> 3;
                 float s = 0.f;
 #pragma unroll
@@ -255,7 +255,7 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_row_sweep_k(const Inst *_
 }
 
 // ---------------------------------------------------------------- K column sweep
-template <int ST>
+template <int ST, bool NT>
 __global__ __launch_bounds__(kColWaves * kWave) void k_col_sweep_k(const Inst *__restrict__ insts,
                                                                    const ColUnit *__restrict__ units,
                                                                    int nunits) {
@@ -286,10 +286,10 @@ __global__ __launch_bounds__(kColWaves * kWave) void k_col_sweep_k(const Inst *_
             int r = r0 + wave;
             for (; r + 3 * S < r1; r += 4 * S) {
                 float k0[8], k1[8], k2[8], k3[8];
-                load8<ST>(I.K, (int64_t)r * kp + c0, k0);
-                load8<ST>(I.K, (int64_t)(r + S) * kp + c0, k1);
-                load8<ST>(I.K, (int64_t)(r + 2 * S) * kp + c0, k2);
-                load8<ST>(I.K, (int64_t)(r + 3 * S) * kp + c0, k3);
+                load8<ST, NT>(I.K, (int64_t)r * kp + c0, k0);
+                load8<ST, NT>(I.K, (int64_t)(r + S) * kp + c0, k1);
+                load8<ST, NT>(I.K, (int64_t)(r + 2 * S) * kp + c0, k2);
+                load8<ST, NT>(I.K, (int64_t)(r + 3 * S) * kp + c0, k3);
                 const float a0 = ash[r - r0], a1 = ash[r + S - r0];
                 const float a2 = ash[r + 2 * S - r0], a3 = ash[r + 3 * S - r0];
 #pragma unroll
@@ -298,7 +298,7 @@ __global__ __launch_bounds__(kColWaves * kWave) void k_col_sweep_k(const Inst *_
             }
             for (; r < r1; r += S) {
                 float k[8];
-                load8<ST>(I.K, (int64_t)r * kp + c0, k);
+                load8<ST, NT>(I.K, (int64_t)r * kp + c0, k);
                 const float ar = ash[r - r0];
 #pragma unroll
                 for (int c = 0; c < 8; ++c) acc[c] = fmaf(k[c], ar, acc[c]);
@@ -442,25 +442,33 @@ hipError_t launch_absorb(const Inst *d_insts, const RowUnit *d_units, int nunits
                            d_insts, d_units, nunits);
     return hipGetLastError();
 }
-hipError_t launch_row_sweep_k(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
-                              size_t lds_bytes, int storage, hipStream_t st) {
-    if (storage == SK_K_BF16)
-        hipLaunchKernelGGL(k_row_sweep_k<SK_K_BF16>, dim3(grid), dim3(kRowWaves * kWave), lds_bytes,
-                           st, d_insts, d_units, nunits);
+template <int ST, bool NT>
+static hipError_t launch_sweeps_k(bool rows, const Inst *d_insts, const void *d_units, int nunits,
+                                  int grid, size_t lds_bytes, hipStream_t st) {
+    if (rows)
+        hipLaunchKernelGGL((k_row_sweep_k<ST, NT>), dim3(grid), dim3(kRowWaves * kWave), lds_bytes,
+                           st, d_insts, (const RowUnit *)d_units, nunits);
     else
-        hipLaunchKernelGGL(k_row_sweep_k<SK_K_F32>, dim3(grid), dim3(kRowWaves * kWave), lds_bytes,
-                           st, d_insts, d_units, nunits);
+        hipLaunchKernelGGL((k_col_sweep_k<ST, NT>), dim3(grid), dim3(kColWaves * kWave), 0, st,
+                           d_insts, (const ColUnit *)d_units, nunits);
     return hipGetLastError();
 }
-hipError_t launch_col_sweep_k(const Inst *d_insts, const ColUnit *d_units, int nunits, int grid,
-                              int storage, hipStream_t st) {
+static hipError_t launch_sweep_k(bool rows, const Inst *d_insts, const void *d_units, int nunits,
+                                 int grid, size_t lds_bytes, int storage, int nt_loads,
+                                 hipStream_t st) {
     if (storage == SK_K_BF16)
-        hipLaunchKernelGGL(k_col_sweep_k<SK_K_BF16>, dim3(grid), dim3(kColWaves * kWave), 0, st,
-                           d_insts, d_units, nunits);
-    else
-        hipLaunchKernelGGL(k_col_sweep_k<SK_K_F32>, dim3(grid), dim3(kColWaves * kWave), 0, st,
-                           d_insts, d_units, nunits);
-    return hipGetLastError();
+        return nt_loads ? launch_sweeps_k<SK_K_BF16, true>(rows, d_insts, d_units, nunits, grid, lds_bytes, st)
+                        : launch_sweeps_k<SK_K_BF16, false>(rows, d_insts, d_units, nunits, grid, lds_bytes, st);
+    return nt_loads ? launch_sweeps_k<SK_K_F32, true>(rows, d_insts, d_units, nunits, grid, lds_bytes, st)
+                    : launch_sweeps_k<SK_K_F32, false>(rows, d_insts, d_units, nunits, grid, lds_bytes, st);
+}
+hipError_t launch_row_sweep_k(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
+                              size_t lds_bytes, int storage, int nt_loads, hipStream_t st) {
+    return launch_sweep_k(true, d_insts, d_units, nunits, grid, lds_bytes, storage, nt_loads, st);
+}
+hipError_t launch_col_sweep_k(const Inst *d_insts, const ColUnit *d_units, int nunits, int grid,
+                              int storage, int nt_loads, hipStream_t st) {
+    return launch_sweep_k(false, d_insts, d_units, nunits, grid, 0, storage, nt_loads, st);
 }
 hipError_t launch_fold_k(const Inst *d_insts, int count, hipStream_t st) {
     hipLaunchKernelGGL(k_fold, dim3(count), dim3(256), 0, st, d_insts);
@@ -602,7 +610,7 @@ sk_status run_single_k(sk_ctx *ctx, Batch &B, const sk_params *prm, const StageH
         for (int k = 0; k < blk; ++k) {
             if (I0.fused) {
                 ctx->prof.begin(ctx->stream, KID_FUSED);
-                KCHK(launch_fused(B.d_insts, 0, I0.n, I0.fused_grid, storage, ctx->stream));
+                KCHK(launch_fused(B.d_insts, 0, I0.n, I0.fused_grid, storage, I0.nt, ctx->stream));
                 ctx->prof.end(ctx->stream);
 
             } else {
@@ -610,10 +618,10 @@ sk_status run_single_k(sk_ctx *ctx, Batch &B, const sk_params *prm, const StageH
                 Profiler &pf = ctx->prof;
                 const int s0 = pf.stamp(ctx->stream);
                 KCHK(launch_row_sweep_k(B.d_insts, B.d_rows, (int)B.h_rows.size(), B.row_grid_k,
-                                        B.row_lds_k, storage, ctx->stream));
+                                        B.row_lds_k, storage, I0.nt, ctx->stream));
                 const int s1 = pf.stamp(ctx->stream);
                 KCHK(launch_col_sweep_k(B.d_insts, B.d_cols, (int)B.h_cols.size(), B.col_grid,
-                                        storage, ctx->stream));
+                                        storage, I0.nt, ctx->stream));
                 const int s2 = pf.stamp(ctx->stream);
                 pf.add(KID_ROW_K, s0, s1);
                 pf.add(KID_COL_K, s1, s2);
@@ -652,11 +660,14 @@ hipError_t set_k_attributes() {
     if ((e = hipFuncSetAttribute((const void *)k_absorb<SK_K_F32>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds)) != hipSuccess)
         return e;
-    if ((e = hipFuncSetAttribute((const void *)k_row_sweep_k<SK_K_BF16>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds / 2)) != hipSuccess)
-        return e;
-    return hipFuncSetAttribute((const void *)k_row_sweep_k<SK_K_F32>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, lds / 2);
+    for (const void *f : {(const void *)k_row_sweep_k<SK_K_BF16, true>,
+                          (const void *)k_row_sweep_k<SK_K_BF16, false>,
+                          (const void *)k_row_sweep_k<SK_K_F32, true>,
+                          (const void *)k_row_sweep_k<SK_K_F32, false>})
+        if ((e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds / 2)) !=
+            hipSuccess)
+            return e;
+    return hipSuccess;
 }
 
 }  // namespace sk

@@ -59,7 +59,7 @@ sk_status run_newton_i16(sk_ctx *ctx, Batch &B, const sk_params *prm, Bump &bump
                                  launch_nt_product(B.d_insts, B.d_rows, (int)B.h_rows.size(),
                                                    B.row_grid, B.row_lds, B.d_cols,
                                                    (int)B.h_cols.size(), B.col_grid, d_nt, V, n,
-                                                   ctx->stream)));
+                                                   B.h_insts[0].nt, ctx->stream)));
                 HIPCHK(ctx, PROF(ctx, KID_NT_STEP, launch_nt_step(B.d_insts, d_nt, V, n, ctx->stream)));
             }
             HIPCHK(ctx, hipMemcpyAsync(&h, d_nt + 1, sizeof h, hipMemcpyDeviceToHost, ctx->stream));

@@ -359,6 +359,14 @@ bool sk::carve_instance(Bump &bump, const int16_t *W, int64_t pitch, int32_t nn,
 // Work-unit tables, shared scratch and launch grids for the instances in B.h_insts.
 sk_status sk::finish_tables(sk_ctx *ctx, Bump &bump, Batch &B) {
     B.count = (int)B.h_insts.size();
+    // matrix loads take the non-temporal hint only when the batch's matrices
+    // cannot stay in the last-level cache between passes
+    size_t mbytes = 0;
+    for (const Inst &I : B.h_insts) {
+        const size_t es = I.storage == SK_K_F32 ? 4 : 2;
+        mbytes += es * (size_t)I.n * (size_t)(I.storage == SK_W_I16 ? I.pitch : (I.n + 7) / 8 * 8);
+    }
+    for (Inst &I : B.h_insts) I.nt = mbytes > kNtBytes ? 1 : 0;
     B.h_rows.clear();
     B.h_cols.clear();
     B.h_fins.clear();
@@ -463,7 +471,7 @@ sk_status sk::iterate_i16(sk_ctx *ctx, Batch &B) {
     if (B.count == 1 && B.h_insts[0].fused) {
         const Inst &I = B.h_insts[0];
         HIPCHK(ctx, PROF(ctx, KID_FUSED, launch_fused(B.d_insts, 0, I.n, I.fused_grid, SK_W_I16,
-                                                      ctx->stream)));
+                                                      I.nt, ctx->stream)));
         HIPCHK(ctx, launch_col_finalize(B.d_insts, B.d_fins, (int)B.h_fins.size(), B.fin_grid,
                                         kFinOnePass, ctx->stream));
         HIPCHK(ctx, launch_iter_end(B.d_insts, B.count, ctx->stream));
@@ -473,10 +481,11 @@ sk_status sk::iterate_i16(sk_ctx *ctx, Batch &B) {
     // finalise and end-of-iteration launches are not stamped
     Profiler &pf = ctx->prof;
     const int s0 = pf.stamp(ctx->stream);
+    const int nt = B.count > 0 ? B.h_insts[0].nt : 0;  // the same for the whole batch
     HIPCHK(ctx, launch_row_sweep(B.d_insts, B.d_rows, (int)B.h_rows.size(), B.row_grid, B.row_lds,
-                                 ctx->stream));
+                                 nt, ctx->stream));
     const int s1 = pf.stamp(ctx->stream);
-    HIPCHK(ctx, launch_col_sweep(B.d_insts, B.d_cols, (int)B.h_cols.size(), B.col_grid,
+    HIPCHK(ctx, launch_col_sweep(B.d_insts, B.d_cols, (int)B.h_cols.size(), B.col_grid, nt,
                                  ctx->stream));
     const int s2 = pf.stamp(ctx->stream);
     pf.add(KID_ROW, s0, s1);
