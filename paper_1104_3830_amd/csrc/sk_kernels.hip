@@ -1022,9 +1022,9 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_check_rows(const Inst *__
         const int16_t *wr = I.W + (int64_t)row * I.pitch;
         double s = 0.0, m = -INFINITY;
         int jm = -1, cnt = 0;
-        int Kb = INT_MIN / 2;  // integer part p w + G_j of this lane's largest t so far
+        int Emax = INT_MIN;  // this lane's largest exact exponent E = p w + F_i + G_j
         // one entry in FP64 (t = p w_ij + log v_j, log x_ij = t + log u_i)
-        auto exact = [&](int j, int w, int2 q, int K) {
+        auto exact = [&](int j, int w, int2 q) {
             const double pw = p * (double)w, lvj = logv_of(q);
             const double t = pw + lvj;
             const double lx = t + f;
@@ -1034,13 +1034,14 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_check_rows(const Inst *__
             if (t > m) {  // a lane visits its columns in increasing order
                 m = t;
                 jm = j;
-                Kb = K;
             }
         };
-        // exact integer tests first: an entry that is negligible, below the
-        // threshold and below this lane's maximum (t <= K + 1/2 and the
-        // maximum is >= Kb - 1/2) changes nothing. Kb only grows, so testing
-        // a chunk against the Kb it started with is conservative.
+        // Pass 1 takes in FP64 only the entries with E >= eskip (the others
+        // are negligible and below the threshold). The row maximum of t is at
+        // an entry with E >= E* - 1 (E* the largest E; |phi_i|, |gam_j| <=
+        // 1/2): when E* - 1 >= eskip pass 1 has seen it; otherwise (every
+        // entry negligible) pass 2 looks at the entries with E in [E* - 1,
+        // eskip).
         if (I.vec8) {
             const int n8 = n >> 3;
             constexpr int U = kVisitLoads;
@@ -1056,17 +1057,19 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_check_rows(const Inst *__
                     if (jj >= n) break;
                     int w[8];
                     unpack8i(v[k], w);
-                    int K[8];
                     unsigned flag = 0;
 #pragma unroll
                     for (int c = 0; c < 8; ++c) {
-                        K[c] = pi * w[c] + gq[c * n8 + (jj >> 3)].x;
-                        if (w[c] != SK_SENTINEL && (K[c] + Fi >= eskip || K[c] >= Kb - 1)) flag |= 1u << c;
+                        const int E = pi * w[c] + gq[c * n8 + (jj >> 3)].x + Fi;
+                        if (w[c] != SK_SENTINEL) {
+                            Emax = max(Emax, E);
+                            if (E >= eskip) flag |= 1u << c;
+                        }
                     }
                     if (flag) {
 #pragma unroll
                         for (int c = 0; c < 8; ++c)
-                            if (flag & (1u << c)) exact(jj + c, w[c], gq[c * n8 + (jj >> 3)], K[c]);
+                            if (flag & (1u << c)) exact(jj + c, w[c], gq[c * n8 + (jj >> 3)]);
                     }
                 }
             }
@@ -1074,9 +1077,23 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_check_rows(const Inst *__
             visit_row(I, wr, lane, [&](int j, int w) {
                 if (w == SK_SENTINEL) return;
                 const int2 q = gq_at(I, gq, j);
-                const int K = pi * w + q.x;
-                if (K + Fi < eskip && K < Kb - 1) return;
-                exact(j, w, q, K);
+                const int E = pi * w + q.x + Fi;
+                Emax = max(Emax, E);
+                if (E >= eskip) exact(j, w, q);
+            });
+        }
+        const int Es = wave_max_i(Emax);
+        if (Es != INT_MIN && Es - 1 < eskip) {
+            visit_row(I, wr, lane, [&](int j, int w) {
+                if (w == SK_SENTINEL) return;
+                const int2 q = gq_at(I, gq, j);
+                const int E = pi * w + q.x + Fi;
+                if (E < Es - 1 || E >= eskip) return;
+                const double t = p * (double)w + logv_of(q);
+                if (t > m || (t == m && j < jm)) {
+                    m = t;
+                    jm = j;
+                }
             });
         }
         s = wave_sum_d(s);
