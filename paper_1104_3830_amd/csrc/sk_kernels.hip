@@ -1371,66 +1371,63 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_prune_fill(const Inst *__
         int64_t pos = row_ptr[row];
         if (I.vec8) {
             // each lane tests 8 consecutive columns; kept entries are placed
-            // by a wave prefix sum of the per-lane counts (column order kept)
+            // by a wave prefix sum of the per-lane counts (column order kept),
+            // skipped for the chunks where no lane keeps an entry
             constexpr int U = kVisitLoads;
-            int4 vb[U];
-            for (int j0b = 0; j0b < n; j0b += 512) {
-                const int j0 = j0b + lane * 8;
-                const int slot = (j0b / 512) % U;
-                if (slot == 0) {
-                    // the next U chunks of this lane, loaded together
+            const int n8 = n >> 3;
+            for (int jb0 = 0; jb0 < n; jb0 += U * 512) {
+                int4 vb[U];
 #pragma unroll
-                    for (int k = 0; k < U; ++k)
-                        vb[k] = j0 + k * 512 < n ? gload<false>(reinterpret_cast<const int4 *>(wr + j0 + k * 512))
-                                                 : make_int4(0, 0, 0, 0);
+                for (int k = 0; k < U; ++k) {
+                    const int j0 = jb0 + k * 512 + lane * 8;
+                    vb[k] = j0 < n ? gload<false>(reinterpret_cast<const int4 *>(wr + j0))
+                                   : make_int4(0, 0, 0, 0);
                 }
-                int wv[8];
-                unsigned keep = 0;
-                if (j0 < n) {
-                    int4 v = vb[0];
 #pragma unroll
-                    for (int k = 1; k < U; ++k)
-                        if (slot == k) v = vb[k];
-                    const int q[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-                        wv[2 * c] = (int)(short)(q[c] & 0xffff);
-                        wv[2 * c + 1] = q[c] >> 16;
-                    }
-                    // exact integer test first (below eskip an entry cannot
-                    // reach t), then FP64 for the few that can
-                    const int base = j0 >> 3, n8 = n >> 3;
-                    unsigned cand = 0;
-#pragma unroll
-                    for (int c = 0; c < 8; ++c)
-                        if (wv[c] != SK_SENTINEL && pi * wv[c] + gq[c * n8 + base].x + Fi >= eskip)
-                            cand |= 1u << c;
-                    if (cand) {
+                for (int k = 0; k < U; ++k) {
+                    const int jb = jb0 + k * 512;
+                    if (jb >= n) break;
+                    const int j0 = jb + lane * 8;
+                    int wv[8];
+                    unsigned keep = 0;
+                    if (j0 < n) {
+                        unpack8i(vb[k], wv);
+                        // exact integer test first (below eskip an entry
+                        // cannot reach t), then FP64 for the few that can
+                        const int base = j0 >> 3;
+                        unsigned cand = 0;
 #pragma unroll
                         for (int c = 0; c < 8; ++c)
-                            if (cand & (1u << c)) {
-                                const double lx = p * (double)wv[c] + f + logv_of(gq[c * n8 + base]);
-                                if (lx >= logt) keep |= 1u << c;
-                            }
-                    }
-                }
-                const int cnt = __popc(keep);
-                int incl = cnt;
+                            if (wv[c] != SK_SENTINEL && pi * wv[c] + gq[c * n8 + base].x + Fi >= eskip)
+                                cand |= 1u << c;
+                        if (cand) {
 #pragma unroll
-                for (int o = 1; o < kWave; o <<= 1) {
-                    const int y = __shfl_up(incl, o, kWave);
-                    if (lane >= o) incl += y;
-                }
-                const int total = __shfl(incl, kWave - 1, kWave);
-                int64_t q = pos + (incl - cnt);
-#pragma unroll
-                for (int c = 0; c < 8; ++c)
-                    if (keep & (1u << c)) {
-                        col[q] = j0 + c;
-                        wout[q] = (int16_t)wv[c];
-                        ++q;
+                            for (int c = 0; c < 8; ++c)
+                                if (cand & (1u << c)) {
+                                    const double lx = p * (double)wv[c] + f + logv_of(gq[c * n8 + base]);
+                                    if (lx >= logt) keep |= 1u << c;
+                                }
+                        }
                     }
-                pos += total;
+                    if (__ballot(keep != 0u) == 0ull) continue;  // nothing kept in this chunk
+                    const int cnt = __popc(keep);
+                    int incl = cnt;
+#pragma unroll
+                    for (int o = 1; o < kWave; o <<= 1) {
+                        const int y = __shfl_up(incl, o, kWave);
+                        if (lane >= o) incl += y;
+                    }
+                    const int total = __shfl(incl, kWave - 1, kWave);
+                    int64_t q = pos + (incl - cnt);
+#pragma unroll
+                    for (int c = 0; c < 8; ++c)
+                        if (keep & (1u << c)) {
+                            col[q] = j0 + c;
+                            wout[q] = (int16_t)wv[c];
+                            ++q;
+                        }
+                    pos += total;
+                }
             }
             continue;
         }
