@@ -291,11 +291,15 @@ size_t sk_batch_arena_bytes(int32_t count, const int32_t *n, int32_t storage);
  * thread-safe with running calls. count = 0 restores the built-in rule. */
 sk_status sk_set_tile_table(const int32_t *n_max, const int32_t *seg_rows, int32_t count);
 
-/* Kernel timing (measurement aid, off by default). While enabled, every
- * kernel the context launches is bracketed by HIP events on the context's
- * stream; durations accumulate per kernel name until the next enable.
- * sk_profile_read fills up to `max` entries (host array) and returns how many
- * kernels were seen. */
+/* Kernel timing (measurement aid, off by default). While enabled, the
+ * context's kernels are timed with HIP events on its stream: the two sweeps
+ * of an iteration share the event between them, the short per-iteration
+ * finalise and end-of-iteration launches are not timed, and the other
+ * kernels are bracketed one by one; durations accumulate per kernel name
+ * (launches that only detected a stage end or came after every instance
+ * finished are counted under "<name>:detect" and "<name>:idle") until the
+ * next enable. sk_profile_read fills up to `max` entries (host array) and
+ * returns how many kernels were seen. */
 typedef struct {
     char name[32];
     int64_t launches;
