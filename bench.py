@@ -231,7 +231,9 @@ def batched_leg(sk, torch, seed=1):
           for k, n in enumerate(ns)]
     prm = sk.make_params([1, 2, 4, 8, 16, 32], tol=1e-5, max_iters=500, check_every=32)
     ctx = sk.Context(0)
-    ctx.scale_batch(Ws[:8], prm)  # warm-up
+    # warm-up over the whole batch (2 iterations per stage): the arena is
+    # sized and touched before the timed run
+    ctx.scale_batch(Ws, sk.make_params([1, 2, 4, 8, 16, 32], tol=1e-5, max_iters=2, check_every=2))
     torch.cuda.synchronize()
     ctx.profile(True)
     t0 = time.perf_counter()

@@ -161,7 +161,9 @@ typedef struct {
 } sk_csr;
 
 /* Device memory a context needs to scale one instance of size n with the
- * given storage (the arena passed to sk_create must be at least this). */
+ * given storage (the arena passed to sk_create must be at least this). When
+ * n is not a multiple of 8 this includes the library's copy of W at a row
+ * pitch of n rounded up to 8 (so that every size takes 16-byte loads). */
 size_t sk_arena_bytes(int32_t n, int32_t storage);
 
 /* Creates a context on `device`, launching on `hip_stream` (a hipStream_t;
@@ -279,7 +281,8 @@ sk_status sk_scale_batch(sk_ctx *ctx, int32_t count, const int16_t *const *W,
                          const int32_t *n, const sk_params *params, void *const *potentials,
                          sk_report *reports);
 
-/* Device arena bytes sk_scale_batch needs for these sizes. */
+/* Device arena bytes sk_scale_batch needs for these sizes (with the padded
+ * copy of each W whose n is not a multiple of 8, as for sk_arena_bytes). */
 size_t sk_batch_arena_bytes(int32_t count, const int32_t *n, int32_t storage);
 
 /* Tile-shape table (process-wide). The column sweep splits the rows of an

@@ -249,6 +249,10 @@ class Context:
         if st != SK_OK:
             raise SkError(st, "sk_create")
         self._ptr = ptr
+        if getattr(self, "_profiling", False):
+            # a larger arena means a new library context: timing stays on
+            # (launches timed before the regrow are not carried over)
+            self._check(lib().sk_profile_enable(self._ptr, 1), "sk_profile_enable")
 
     def ensure_arena(self, nbytes):
         if self.arena is None or self.arena.numel() < nbytes:
@@ -276,6 +280,7 @@ class Context:
     def profile(self, enable=True):
         """Turns HIP-event timing of every launch on/off (and resets it)."""
         self._check(lib().sk_profile_enable(self._ptr, 1 if enable else 0), "sk_profile_enable")
+        self._profiling = bool(enable)
 
     def profile_read(self):
         """{kernel name: (launches, total milliseconds)} since the last enable."""

@@ -17,6 +17,18 @@ constexpr int kMaxN = 16384;     // row sweep stages all column potentials in LD
 constexpr int kMaxSegRows = 1024;
 constexpr int kFusedSlots = 256;  // workgroups (and column-partial slots) of the fused kernel
 
+// Column count of the 8-wide layout: n rounded up to a multiple of 8.
+__host__ __device__ constexpr int pad8(int n) { return (n + 7) & ~7; }
+// Padding columns j in [n, pad8(n)) of the 8-wide kernels take these column
+// potentials. With |4 p w| <= 2^28 (p <= 2048, int16 w) and row terms
+// |B| = |4 (F_i - kTabLo)| < 2^29 (the potentials stay within a few p times
+// the weight range, below 2^26), 4 p w + kPadExp4 + B lies in (-2^31, 0), so
+// the exp-table read clamps to its zero entry and the column adds exactly 0;
+// kPadG puts the exact exponent far below every skip bound of the FP64 check
+// (which also masks these columns explicitly).
+constexpr int kPadExp4 = -(1 << 30);
+constexpr int kPadG = -(1 << 28);
+
 enum : int32_t { ST_RUNNING = 0, ST_DONE = 1, ST_ERROR = 2, ST_STAGE_END = 3 };
 enum : uint32_t { ERR_EMPTY_ROW = 1u, ERR_EMPTY_COL = 2u, ERR_RANGE = 4u, ERR_NEWTON = 8u };
 
@@ -44,7 +56,9 @@ struct Inst {
     const int16_t *W;       // n x n log-weights, row pitch `pitch` elements
     int64_t pitch;
     int32_t n;
-    int32_t vec8;           // 1: n % 8 == 0 and rows 16-byte aligned -> 8-wide loads
+    // 1: rows 16-byte aligned with pitch >= pad8(n) -> 8-wide loads over
+    // pad8(n) columns; columns n..pad8(n)-1 are padding (any values)
+    int32_t vec8;
     int32_t nt;             // 1: sweeps launched with non-temporal matrix loads (batch > kNtBytes)
     int32_t nseg;           // row segments of the column sweep
     int32_t seg_rows;
@@ -82,6 +96,10 @@ struct Inst {
     // words kRowResStride apart (float bits, atomicMax by each wave; zero
     // between iterations); the column sweep reduces them
     uint32_t *rowres;
+    // the caller's W when W is the library's padded copy (n % 8 != 0),
+    // else nullptr; copied once per batch before the input scan
+    const int16_t *Wsrc;
+    int64_t src_pitch;
 };
 constexpr int kRowResSlots = 64;    // = kWave: one wave reduces them
 constexpr int kRowResStride = 32;   // one 128-byte line per slot
@@ -158,6 +176,8 @@ constexpr int kFinCols = 64;
 // Kernel launchers (sk_kernels.hip). All enqueue on `st`.
 hipError_t launch_init(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid, int cold,
                        hipStream_t st);
+hipError_t launch_pad_copy(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
+                           hipStream_t st);
 hipError_t launch_row_sweep(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
                             size_t lds_bytes, int nt_loads, hipStream_t st);
 hipError_t launch_col_sweep(const Inst *d_insts, const ColUnit *d_units, int nunits, int grid,

@@ -62,12 +62,23 @@ __device__ __forceinline__ void unit_range(int nunits, int &u0, int &u1) {
 // read 64 consecutive entries for each c (no bank conflicts).
 __device__ __forceinline__ int swz8(int j, int n8) { return (j & 7) * n8 + (j >> 3); }
 
+// In a row's last 8-wide chunk (columns jj..jj+7 with jj + 8 > n) the padding
+// columns are marked absent, so the sentinel tests that follow skip them.
+__device__ __forceinline__ void mask_pad8(int (&w)[8], int jj, int n) {
+    if (jj + 8 > n) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+            if (jj + c >= n) w[c] = SK_SENTINEL;
+    }
+}
+
 // 16-byte loads in flight per lane in the single-wave row passes (input
 // scan, FP64 row check, kept counts, CSR fill).
 constexpr int kVisitLoads = 4;
 
 // Visits the entries of one row: lane-strided 8-wide chunks with 16-byte
-// loads when the instance allows it, single entries otherwise. f(j, w).
+// loads when the instance allows it, single entries otherwise. f(j, w); the
+// padding columns j >= n of the 8-wide layout are passed as SK_SENTINEL.
 
 template <class Fn>
 __device__ __forceinline__ void visit_row(const Inst &I, const int16_t *wr, int lane, Fn f) {
@@ -76,12 +87,11 @@ __device__ __forceinline__ void visit_row(const Inst &I, const int16_t *wr, int 
         // kVisitLoads 16-byte loads in flight per lane, then their entries in order
         constexpr int U = kVisitLoads;
         auto use = [&](const int4 v, int j0) {
-            const int q[4] = {v.x, v.y, v.z, v.w};
+            int w[8];
+            unpack8i(v, w);
+            mask_pad8(w, j0, n);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                f(j0 + 2 * c, (int)(short)(q[c] & 0xffff));
-                f(j0 + 2 * c + 1, q[c] >> 16);
-            }
+            for (int c = 0; c < 8; ++c) f(j0 + c, w[c]);
         };
         int j0 = lane * 8;
         for (; j0 + (U - 1) * 512 < n; j0 += U * 512) {
@@ -94,6 +104,34 @@ __device__ __forceinline__ void visit_row(const Inst &I, const int16_t *wr, int 
         for (; j0 < n; j0 += 512) use(gload<false>(reinterpret_cast<const int4 *>(wr + j0)), j0);
     } else {
         for (int j = lane; j < n; j += kWave) f(j, (int)gload<false>(wr + j));
+    }
+}
+
+// ---------------------------------------------------------------- padded copy
+// Copies the caller's W into the library's 8-wide layout (pitch pad8(n),
+// columns n.. set to 0) for the instances that have one (Wsrc != nullptr):
+// one wave per row, each lane writing 16-byte aligned chunks of 8 columns.
+__global__ __launch_bounds__(kRowWaves * kWave) void k_pad_copy(const Inst *__restrict__ insts,
+                                                                  const RowUnit *__restrict__ units,
+                                                                  int nunits) {
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    int u0, u1;
+    unit_range(nunits, u0, u1);
+    for (int u = u0; u < u1; ++u) {
+        const RowUnit un = units[u];
+        const Inst &I = insts[un.inst];
+        const int n = I.n, row = un.row0 + wave;
+        if (!I.Wsrc || row >= n) continue;
+        const uint16_t *src = reinterpret_cast<const uint16_t *>(I.Wsrc) + (int64_t)row * I.src_pitch;
+        int16_t *dst = const_cast<int16_t *>(I.W) + (int64_t)row * I.pitch;
+        for (int j0 = lane * 8; j0 < n; j0 += 512) {
+            unsigned h[8];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) h[c] = j0 + c < n ? (unsigned)src[j0 + c] : 0u;
+            *reinterpret_cast<int4 *>(dst + j0) =
+                make_int4((int)(h[0] | (h[1] << 16)), (int)(h[2] | (h[3] << 16)),
+                          (int)(h[4] | (h[5] << 16)), (int)(h[6] | (h[7] << 16)));
+        }
     }
 }
 
@@ -121,8 +159,8 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_init(const Inst *__restri
         const int16_t *wr = I.W + (int64_t)row * I.pitch;
         int mx = -32768;
         int sent = 0;
-        visit_row(I, wr, lane, [&](int, int w) {
-            sent |= (w == SK_SENTINEL);
+        visit_row(I, wr, lane, [&](int j, int w) {
+            sent |= (w == SK_SENTINEL) & (j < n);  // not the padding columns
             mx = max(mx, w);
         });
 #pragma unroll
@@ -199,7 +237,7 @@ __device__ __forceinline__ float row_partial_v8(const int16_t *__restrict__ wr, 
                                                 int B, const ColPot *__restrict__ cp,
                                                 const float *__restrict__ tab, int lane) {
     constexpr int U = SK_ROW_UNROLL;
-    const int n8 = n >> 3;
+    const int n8 = pad8(n) >> 3;
     float acc = 0.f;
     int j0 = lane * 8;
 #if SK_ROW_PIPE
@@ -251,7 +289,7 @@ __device__ __forceinline__ float row_partial_v8(const int16_t *__restrict__ wr, 
 template <bool SENT, bool NT>
 __device__ __forceinline__ int row_max_v8(const int16_t *__restrict__ wr, int n, int p4, int B,
                                           const ColPot *__restrict__ cp, int lane) {
-    const int n8 = n >> 3;
+    const int n8 = pad8(n) >> 3;
     int m = INT_MIN;
     for (int j0 = lane * 8; j0 < n; j0 += 512) {
         const int4 v = gload<NT>(reinterpret_cast<const int4 *>(wr + j0));
@@ -261,7 +299,7 @@ __device__ __forceinline__ int row_max_v8(const int16_t *__restrict__ wr, int n,
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
             const int t = __mul24(p4, w[c]) + cp[c * n8 + q].a + B;
-            if (!SENT || w[c] != SK_SENTINEL) m = max(m, t);
+            if ((!SENT || w[c] != SK_SENTINEL) && j0 + c < n) m = max(m, t);
         }
     }
     return m;
@@ -386,7 +424,7 @@ __device__ __forceinline__ void row_partial2_v8(const int16_t *__restrict__ wr0,
                                                 const float *__restrict__ tab, int lane,
                                                 float &acc0, float &acc1) {
     constexpr int U = SK_PAIR_UNROLL;
-    const int n8 = n >> 3;
+    const int n8 = pad8(n) >> 3;
     acc0 = 0.f;
     acc1 = 0.f;
     int j0 = lane * 8;
@@ -433,6 +471,19 @@ __device__ __forceinline__ float row_step_pair(const Inst &I, int ra, int rb, in
     return fmaxf(ea, eb);
 }
 
+// Column potentials of the padding columns n..pad8(n)-1 of the 8-wide layout
+// (a separate loop, so that the staging of the real columns keeps its loads
+// unconditional and in flight together).
+__device__ __forceinline__ void stage_pad_cols(const Inst &I, ColPot *cp, int n8) {
+    if (!I.vec8) return;
+    for (int j = I.n + (int)threadIdx.x; j < 8 * n8; j += blockDim.x) {
+        ColPot k;
+        k.a = kPadExp4;
+        k.g = 0.f;
+        cp[swz8(j, n8)] = k;
+    }
+}
+
 // Waves run their rows independently: the only barrier is the restaging of
 // the column data when the instance changes. The residual |r_i - 1| goes to
 // rres[i] (the column sweep reduces it per row segment for the finalise) and
@@ -476,13 +527,14 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_row_sweep(const Inst *__r
         if (un.inst != cur) {
             flush();
             __syncthreads();
-            const int n8 = n >> 3;
+            const int n8 = pad8(n) >> 3;
             for (int j = threadIdx.x; j < n; j += blockDim.x) {
                 ColPot k;
                 k.a = 4 * I.G[j];
                 k.g = ex2(I.gam[j] * kLog2e);
                 lds_cp[I.vec8 ? swz8(j, n8) : j] = k;
             }
+            stage_pad_cols(I, lds_cp, n8);
             __syncthreads();
             cur = un.inst;
         }
@@ -558,9 +610,16 @@ __device__ __forceinline__ void col_partial(const Inst &I, int tile, int r0, int
     if (V8) {
         const int c0 = tile * kColTile8 + lane * 8;
         if (c0 >= n) return;
-        int A[8];
+        int A[8];  // padding columns (c0 + c >= n) add exactly 0 and are not written
+        if (c0 + 8 <= n) {
+            const int4 g0 = *reinterpret_cast<const int4 *>(I.G + c0);
+            const int4 g1 = *reinterpret_cast<const int4 *>(I.G + c0 + 4);
+            A[0] = 4 * g0.x; A[1] = 4 * g0.y; A[2] = 4 * g0.z; A[3] = 4 * g0.w;
+            A[4] = 4 * g1.x; A[5] = 4 * g1.y; A[6] = 4 * g1.z; A[7] = 4 * g1.w;
+        } else {
 #pragma unroll
-        for (int c = 0; c < 8; ++c) A[c] = 4 * I.G[c0 + c];
+            for (int c = 0; c < 8; ++c) A[c] = c0 + c < n ? 4 * I.G[c0 + c] : kPadExp4;
+        }
         const int16_t *base = I.W + c0;
         const int64_t pitch = I.pitch;
         auto body = [&](const int4 v, const RowPot rp) {
@@ -979,12 +1038,14 @@ __device__ __forceinline__ int kept_skip(double logt) {
 // swizzled like the row sweep when 8-wide chunks are used. log v_j in FP64 is
 // (double)G_j + (double)gam_j.
 __device__ __forceinline__ void stage_gq(const Inst &I, int2 *gq) {
-    const int n = I.n, n8 = n >> 3;
+    const int n = I.n, n8 = pad8(n) >> 3;
     for (int j = threadIdx.x; j < n; j += blockDim.x)
         gq[I.vec8 ? swz8(j, n8) : j] = make_int2(I.G[j], __float_as_int(I.gam[j]));
+    if (I.vec8)
+        for (int j = n + (int)threadIdx.x; j < 8 * n8; j += blockDim.x) gq[swz8(j, n8)] = make_int2(kPadG, 0);
 }
 __device__ __forceinline__ int2 gq_at(const Inst &I, const int2 *gq, int j) {
-    return gq[I.vec8 ? swz8(j, I.n >> 3) : j];
+    return gq[I.vec8 ? swz8(j, pad8(I.n) >> 3) : j];
 }
 __device__ __forceinline__ double logv_of(int2 q) {
     return (double)q.x + (double)__int_as_float(q.y);
@@ -1043,7 +1104,7 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_check_rows(const Inst *__
         // entry negligible) pass 2 looks at the entries with E in [E* - 1,
         // eskip).
         if (I.vec8) {
-            const int n8 = n >> 3;
+            const int n8 = pad8(n) >> 3;
             constexpr int U = kVisitLoads;
             for (int j0 = lane * 8; j0 < n; j0 += U * 512) {
                 int4 v[U];
@@ -1057,6 +1118,7 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_check_rows(const Inst *__
                     if (jj >= n) break;
                     int w[8];
                     unpack8i(v[k], w);
+                    mask_pad8(w, jj, n);
                     unsigned flag = 0;
 #pragma unroll
                     for (int c = 0; c < 8; ++c) {
@@ -1193,13 +1255,22 @@ __global__ __launch_bounds__(kColWaves * kWave) void k_check_cols_part8(const In
     double s[8];
 #pragma unroll
     for (int c = 0; c < 8; ++c) s[c] = 0.0;
-    if (j0 < n) {  // n % 8 == 0: all 8 columns exist
+    if (j0 < n) {
+        // padding columns (j0 + c >= n) fall below kCheckSkip and are not written
         int G[8];
         double gm[8];
+        if (j0 + 8 <= n) {
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            G[c] = I.G[j0 + c];
-            gm[c] = (double)I.gam[j0 + c];
+            for (int c = 0; c < 8; ++c) {
+                G[c] = I.G[j0 + c];
+                gm[c] = (double)I.gam[j0 + c];
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                G[c] = j0 + c < n ? I.G[j0 + c] : kPadG;
+                gm[c] = j0 + c < n ? (double)I.gam[j0 + c] : 0.0;
+            }
         }
         const int16_t *w0 = I.W + j0;
         int r = r0 + wave;
@@ -1374,7 +1445,7 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_prune_fill(const Inst *__
             // by a wave prefix sum of the per-lane counts (column order kept),
             // skipped for the chunks where no lane keeps an entry
             constexpr int U = kVisitLoads;
-            const int n8 = n >> 3;
+            const int n8 = pad8(n) >> 3;
             for (int jb0 = 0; jb0 < n; jb0 += U * 512) {
                 int4 vb[U];
 #pragma unroll
@@ -1392,6 +1463,7 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_prune_fill(const Inst *__
                     unsigned keep = 0;
                     if (j0 < n) {
                         unpack8i(vb[k], wv);
+                        mask_pad8(wv, j0, n);
                         // exact integer test first (below eskip an entry
                         // cannot reach t), then FP64 for the few that can
                         const int base = j0 >> 3;
@@ -1505,7 +1577,7 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_nt_rows(const Inst *__res
     if (nt->done != NT_RUN) return;
     const Inst &I = insts[0];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int n = I.n, n8 = n >> 3;
+    const int n = I.n, n8 = pad8(n) >> 3;
     const int par = I.ctl->iter & 1;
     const int p4 = 4 * I.ctl->p;
     const bool sent = I.ctl->sent != 0u;
@@ -1518,6 +1590,7 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_nt_rows(const Inst *__res
         k.g = ex2(I.gam[j] * kLog2e) * q[n + j];
         lds_cp[I.vec8 ? swz8(j, n8) : j] = k;
     }
+    stage_pad_cols(I, lds_cp, n8);
     __syncthreads();
     for (int u = u0; u < u1; ++u) {
         const int row = units[u].row0 + wave;
@@ -1891,6 +1964,12 @@ hipError_t launch_init(const Inst *d_insts, const RowUnit *d_units, int nunits, 
                        hipStream_t st) {
     hipLaunchKernelGGL(k_init, dim3(grid), dim3(kRowWaves * kWave), 0, st, d_insts, d_units,
                        nunits, cold);
+    return hipGetLastError();
+}
+hipError_t launch_pad_copy(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
+                           hipStream_t st) {
+    hipLaunchKernelGGL(k_pad_copy, dim3(grid), dim3(kRowWaves * kWave), 0, st, d_insts, d_units,
+                       nunits);
     return hipGetLastError();
 }
 hipError_t launch_row_sweep(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,

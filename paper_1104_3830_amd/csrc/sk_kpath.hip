@@ -92,9 +92,12 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_absorb(const Inst *__rest
         const int n = I.n, kp = I.kpitch;
         if (un.inst != cur) {
             __syncthreads();
-            const int n8 = n >> 3;
+            const int n8 = pad8(n) >> 3;
             for (int j = threadIdx.x; j < n; j += blockDim.x)
                 pot[I.vec8 ? kswz(j, n8) : j] = make_float2((float)I.G[j], I.gam[j] * kLog2eK);
+            if (I.vec8)  // padding columns (their K entries are set to 0 below)
+                for (int j = n + (int)threadIdx.x; j < 8 * n8; j += blockDim.x)
+                    pot[kswz(j, n8)] = make_float2(0.f, 0.f);
             __syncthreads();
             cur = un.inst;
         }
@@ -106,8 +109,9 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_absorb(const Inst *__rest
         const float ph = I.phi[par][row] * kLog2eK;
         const int16_t *wr = I.W + (int64_t)row * I.pitch;
         if (I.vec8) {
-            // 8 columns per lane: one 16-byte load of W, one 16/32-byte store of K
-            const int n8 = n >> 3;
+            // 8 columns per lane: one 16-byte load of W, one 16/32-byte store of
+            // K (K's padding columns, j >= n, get 0 as in the 1-wide branch)
+            const int n8 = pad8(n) >> 3;
             for (int j0 = lane * 8; j0 < n; j0 += 512) {
                 const int4 v = gload<false>(reinterpret_cast<const int4 *>(wr + j0));
                 const int q[4] = {v.x, v.y, v.z, v.w};
@@ -118,7 +122,7 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_absorb(const Inst *__rest
                     const float2 gp = pot[c * n8 + (j0 >> 3)];
                     const float Iv = fmaf((float)w, pf, gp.x) + Ff;
                     const float e = fminf(kex2(fmaf(Iv, kLog2eK, gp.y) + ph), kKHi);
-                    k[c] = (w == SK_SENTINEL) ? 0.f : e;
+                    k[c] = (w == SK_SENTINEL || j0 + c >= n) ? 0.f : e;
                 }
                 if (ST == SK_K_BF16) {
                     uint32_t o[4];

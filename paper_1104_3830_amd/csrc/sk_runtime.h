@@ -19,6 +19,9 @@ struct TilePlan {
 TilePlan plan_tiles(int32_t n, int vec8);
 size_t instance_bytes(int32_t n, int vec8, int storage, int fused = 0);
 size_t shared_bytes(int32_t count, const int32_t *n);
+size_t pad_copy_bytes(int32_t n);
+// LDS of the kernels that stage (G_j, gam_j) per column (FP64 check, pruning)
+inline size_t gq_lds_bytes(int32_t n) { return 8 * (size_t)pad8(n); }
 
 // A set of instances swept together, with its device tables.
 struct Batch {
@@ -70,6 +73,7 @@ enum KernelId {
     KID_ROW_K_DETECT, KID_COL_K_DETECT, KID_ROW_K_IDLE, KID_COL_K_IDLE,
     KID_FUSED, KID_FUSED_DETECT, KID_FUSED_IDLE,
     KID_NT_PRODUCT, KID_NT_STEP, KID_NT_PRODUCT_IDLE, KID_NT_STEP_IDLE,
+    KID_PAD_COPY,
     KID_COUNT
 };
 extern const char *kKernelNames[KID_COUNT];

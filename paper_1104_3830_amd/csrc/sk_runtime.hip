@@ -64,13 +64,20 @@ size_t instance_bytes(int32_t n, int vec8, int storage, int fused) {
     return b;
 }
 
+// The library's 8-wide copy of a W whose n is not a multiple of 8.
+size_t pad_copy_bytes(int32_t n) {
+    return (n % 8) ? align_up(sizeof(int16_t) * (size_t)n * (size_t)pad8(n), 256) : 0;
+}
+
 size_t shared_bytes(int32_t count, const int32_t *n) {
     int64_t rows = 0, cols = 0, nmax = 0, cpart = 0, fins = 0;
     for (int k = 0; k < count; ++k) {
-        TilePlan t = plan_tiles(n[k], (n[k] % 8) == 0);
+        // an instance takes the 8-wide plan unless its W is misaligned
+        // (then the 1-wide plan: no more slots, more column units)
+        TilePlan t = plan_tiles(n[k], 1), t1 = plan_tiles(n[k], 0);
         cpart = std::max<int64_t>(cpart, (int64_t)t.nseg * n[k]);
         rows += (n[k] + kRowWaves - 1) / kRowWaves;
-        cols += (int64_t)t.ntiles * t.nseg;
+        cols += std::max<int64_t>((int64_t)t.ntiles * t.nseg, (int64_t)t1.ntiles * t1.nseg);
         fins += (n[k] + kFinCols - 1) / kFinCols;
         nmax = std::max<int64_t>(nmax, n[k]);
     }
@@ -97,7 +104,7 @@ const char *kKernelNames[KID_COUNT] = {"init", "row_sweep", "col_sweep", "check_
                                        "col_sweep_k:detect", "row_sweep_k:idle",
                                        "col_sweep_k:idle", "fused", "fused:detect", "fused:idle",
                                        "nt_product", "nt_step", "nt_product:idle",
-                                       "nt_step:idle"};
+                                       "nt_step:idle", "pad_copy"};
 
 hipEvent_t Profiler::take() {
     if (!pool.empty()) {
@@ -211,14 +218,14 @@ size_t sk_potentials_bytes(int32_t n) { return n > 0 ? (size_t)16 * n : 0; }
 
 size_t sk_arena_bytes(int32_t n, int32_t storage) {
     if (n <= 0) return 0;
-    return instance_bytes(n, (n % 8) == 0, storage, 1) + shared_bytes(1, &n) + newton_bytes(n) +
-           4096;
+    return instance_bytes(n, 1, storage, 1) + pad_copy_bytes(n) + shared_bytes(1, &n) +
+           newton_bytes(n) + 4096;
 }
 
 size_t sk_batch_arena_bytes(int32_t count, const int32_t *n, int32_t storage) {
     if (count <= 0 || !n) return 0;
     size_t b = shared_bytes(count, n) + 4096;
-    for (int k = 0; k < count; ++k) b += instance_bytes(n[k], (n[k] % 8) == 0, storage);
+    for (int k = 0; k < count; ++k) b += instance_bytes(n[k], 1, storage) + pad_copy_bytes(n[k]);
     return b;
 }
 
@@ -310,7 +317,20 @@ bool sk::carve_instance(Bump &bump, const int16_t *W, int64_t pitch, int32_t nn,
     I.W = W;
     I.pitch = pitch;
     I.n = nn;
-    I.vec8 = (nn % 8 == 0) && (pitch % 8 == 0) && ((uintptr_t)W % 16 == 0);
+    // 8-wide loads read whole aligned 16-byte chunks up to column pad8(n):
+    // inside each row when pitch >= pad8(n), and for the last row inside the
+    // aligned chunk that holds its last entry
+    I.vec8 = (pitch % 8 == 0) && (pitch >= pad8(nn)) && ((uintptr_t)W % 16 == 0);
+    if (!I.vec8 && nn % 8 != 0) {
+        // the library's padded copy (filled by k_pad_copy before the input scan)
+        int16_t *cp = bump.take<int16_t>((size_t)nn * pad8(nn));
+        if (!cp) return false;
+        I.Wsrc = W;
+        I.src_pitch = pitch;
+        I.W = cp;
+        I.pitch = pad8(nn);
+        I.vec8 = 1;
+    }
     TilePlan t = plan_tiles(nn, I.vec8);
     I.nseg = t.nseg;
     I.seg_rows = t.seg_rows;
@@ -396,8 +416,8 @@ sk_status sk::finish_tables(sk_ctx *ctx, Bump &bump, Batch &B) {
     if (!B.d_insts || !B.d_rows || !B.d_cols || !B.d_fins || !B.d_rsum || !B.d_rmax || !B.d_csum ||
         !B.d_counts || !B.d_cpart || !B.d_ctl_all || !B.d_checkout || !B.d_nnz)
         return fail(ctx, SK_ENOMEM, "arena too small for the batch tables");
-    // grids: row sweep stages n columns of potentials (8 B each) in LDS
-    const size_t lds = sizeof(float2) * (size_t)B.nmax;
+    // grids: row sweep stages pad8(n) columns of potentials (8 B each) in LDS
+    const size_t lds = sizeof(float2) * (size_t)pad8(B.nmax);
     const int per_cu = lds <= 32768 ? 2 : 1;
     B.row_lds = lds;
     B.row_lds_k = sizeof(float) * (size_t)((B.nmax + 7) / 8 * 8);
@@ -428,6 +448,11 @@ sk_status sk::upload_batch(sk_ctx *ctx, Batch &B) {
                                hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(ctx, hipMemcpyAsync(B.d_fins, B.h_fins.data(), sizeof(FinUnit) * B.h_fins.size(),
                                hipMemcpyHostToDevice, ctx->stream));
+    bool pads = false;
+    for (const Inst &I : B.h_insts) pads |= I.Wsrc != nullptr;
+    if (pads)
+        HIPCHK(ctx, PROF(ctx, KID_PAD_COPY, launch_pad_copy(B.d_insts, B.d_rows, (int)B.h_rows.size(),
+                                                            B.row_grid, ctx->stream)));
     return SK_OK;
 }
 
@@ -584,7 +609,7 @@ sk_status sk::enqueue_check(sk_ctx *ctx, Batch &B, int k, const CheckCounts *cc)
     HIPCHK(ctx, PROF(ctx, KID_CHECK_ROWS,
                      launch_check_rows(B.d_insts, B.d_rows + first, nunits, grid, B.d_rsum,
                                        B.d_rmax, cc ? cc->logt : 0.0, cc ? cc->counts : nullptr,
-                                       cc ? cc->hint : nullptr, sizeof(double) * (size_t)nn,
+                                       cc ? cc->hint : nullptr, gq_lds_bytes(nn),
                                        ctx->stream)));
     HIPCHK(ctx, PROF(ctx, KID_CHECK_COLS, launch_check_cols(B.d_insts, k, nn, I.nseg, I.vec8,
                                                             B.d_cpart, B.d_csum, ctx->stream)));
@@ -791,7 +816,7 @@ sk_status sk_prune(sk_ctx *ctx, const int16_t *W, int32_t n, const void *potenti
     const double logt = std::log(params->threshold);
     const int nunits = (int)B.h_rows.size();
     HIPCHK(ctx, PROF(ctx, KID_PRUNE_COUNT, launch_prune_count(B.d_insts, B.d_rows, nunits, B.row_grid, logt, B.d_counts,
-                                   sizeof(double) * (size_t)n, ctx->stream)));
+                                   gq_lds_bytes(n), ctx->stream)));
     HIPCHK(ctx, PROF(ctx, KID_SCAN, launch_scan(B.d_counts, csr->row_ptr, n, ctx->stream)));
     int64_t total = 0;
     HIPCHK(ctx, hipMemcpyAsync(&total, csr->row_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost,
@@ -805,7 +830,7 @@ sk_status sk_prune(sk_ctx *ctx, const int16_t *W, int32_t n, const void *potenti
     if (total > 0) {
         if (!csr->col || !csr->w) return fail(ctx, SK_EINVAL, "null col/w buffers");
         HIPCHK(ctx, PROF(ctx, KID_PRUNE_FILL, launch_prune_fill(B.d_insts, B.d_rows, nunits, B.row_grid, logt, csr->row_ptr,
-                                      csr->col, csr->w, sizeof(double) * (size_t)n, ctx->stream)));
+                                      csr->col, csr->w, gq_lds_bytes(n), ctx->stream)));
     }
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     return SK_OK;

@@ -91,10 +91,14 @@ struct Server {
 
 static const size_t kRingBytes = size_t(512) << 20;
 
+// Staged and device layout of a request's W: rows pad8(n) entries apart, so
+// the kernels take 8-wide loads for every n.
+static size_t wbytes_of(int32_t n) { return sizeof(int16_t) * (size_t)n * (size_t)pad8(n); }
+
 static void release_staging(Server *S, Request *r) {
     if (!r->staging) return;
     if (r->in_ring) {
-        S->ring_alloc.release(r->ring_off, (size_t)r->n * r->n * 2);
+        S->ring_alloc.release(r->ring_off, wbytes_of(r->n));
     } else {
         free(r->staging);
     }
@@ -126,8 +130,34 @@ static void stage_copy(void *dst, const void *src, size_t bytes) {
     for (auto &t : th) t.join();
 }
 
+// The caller's dense n x n W into that layout (padding columns set to 0),
+// rows split over at most kCopyThreads threads as in stage_copy.
+static void stage_rows(int16_t *dst, const int16_t *src, int32_t n) {
+    const int32_t P = pad8(n);
+    if (P == n) {
+        stage_copy(dst, src, wbytes_of(n));
+        return;
+    }
+    auto rows = [=](int32_t r0, int32_t r1) {
+        for (int32_t r = r0; r < r1; ++r) {
+            memcpy(dst + (size_t)r * P, src + (size_t)r * n, sizeof(int16_t) * n);
+            memset(dst + (size_t)r * P + n, 0, sizeof(int16_t) * (P - n));
+        }
+    };
+    const int nt = (int)std::min<size_t>(kCopyThreads, std::max<size_t>(1, wbytes_of(n) / kCopyChunk));
+    const int32_t per = (n + nt - 1) / nt;
+    std::vector<std::thread> th;
+    th.reserve(nt - 1);
+    for (int k = 1; k < nt; ++k) {
+        const int32_t a = std::min(n, per * k), b = std::min(n, per * (k + 1));
+        if (a < b) th.emplace_back(rows, a, b);
+    }
+    rows(0, std::min(n, per));
+    for (auto &t : th) t.join();
+}
+
 static size_t footprint(int32_t n) {
-    return align_up((size_t)n * n * 2, 256) + instance_bytes(n, (n % 8) == 0, SK_W_I16) + 4096;
+    return align_up(wbytes_of(n), 256) + instance_bytes(n, 1, SK_W_I16) + 4096;
 }
 
 // Carves the request's device region at offset `off` (W first, then the
@@ -135,8 +165,8 @@ static size_t footprint(int32_t n) {
 static void place(Server *S, Request *r, size_t off) {
     r->off = off;
     Bump bump{S->ctx->arena + off, r->len};
-    int16_t *dW = bump.take<int16_t>((size_t)r->n * r->n);
-    carve_instance(bump, dW, r->n, r->n, &r->prm, r->inst);
+    int16_t *dW = bump.take<int16_t>((size_t)r->n * pad8(r->n));
+    carve_instance(bump, dW, pad8(r->n), r->n, &r->prm, r->inst);
 }
 
 // Marks r finished (caller holds S->mu) and records it for sk_completed; the
@@ -248,7 +278,7 @@ static sk_status retire_all(Server *S, const std::vector<int> &fin) {
         const double logt = std::log(r->prm.threshold);
         int64_t *d_rp = (int64_t *)(ctx->arena + rp_off[q]);
         e = launch_prune_count(B.d_insts, B.d_rows + first, nunits, grid, logt, B.d_counts,
-                               sizeof(double) * (size_t)r->n, ctx->stream);
+                               gq_lds_bytes(r->n), ctx->stream);
         if (e == hipSuccess) e = launch_scan(B.d_counts, d_rp, r->n, ctx->stream, B.d_nnz + k);
     }
     if (st == SK_OK && e == hipSuccess)
@@ -290,7 +320,7 @@ static sk_status retire_all(Server *S, const std::vector<int> &fin) {
             const int grid = std::min(nunits, ctx->num_cus * 2);
             e = launch_prune_fill(B.d_insts, B.d_rows + first, nunits, grid,
                                   std::log(r->prm.threshold), d_rp, d_col, d_w,
-                                  sizeof(double) * (size_t)r->n, ctx->stream);
+                                  gq_lds_bytes(r->n), ctx->stream);
             r->col.resize(nnz);
             r->w.resize(nnz);
             if (e == hipSuccess)
@@ -350,7 +380,7 @@ static void serve_loop(Server *S) {
         for (Request *r : to_copy) {
             if (!r->copying) {
                 if (e == hipSuccess)
-                    e = hipMemcpyAsync((void *)r->inst.W, r->staging, (size_t)r->n * r->n * 2,
+                    e = hipMemcpyAsync((void *)r->inst.W, r->staging, wbytes_of(r->n),
                                        hipMemcpyHostToDevice, S->copy_stream);
                 if (e == hipSuccess) e = hipEventCreateWithFlags(&r->ev, hipEventDisableTiming);
                 if (e == hipSuccess) e = hipEventRecord(r->ev, S->copy_stream);
@@ -546,7 +576,7 @@ extern "C" sk_status sk_submit(sk_ctx *ctx, const int16_t *W_host, int32_t n, co
     r->prm = *params;
     r->len = len;
     r->t_submit = std::chrono::steady_clock::now();
-    const size_t wbytes = (size_t)n * n * 2;
+    const size_t wbytes = wbytes_of(n);
     // W goes to the pinned ring when it has room (a parallel host copy; the
     // caller's buffer is free when this returns) and from there to the device
     // by an asynchronous copy started here if the device region is free too;
@@ -587,7 +617,7 @@ extern "C" sk_status sk_submit(sk_ctx *ctx, const int16_t *W_host, int32_t n, co
         return fail(ctx, SK_EDEVICE, "%s: %s", what, hipGetErrorString(e));
     };
     if (r->in_ring) {
-        stage_copy(r->staging, W_host, wbytes);
+        stage_rows(r->staging, W_host, n);
         if (placed) {
             hipError_t e = hipSetDevice(ctx->device);
             if (e == hipSuccess)
@@ -601,8 +631,9 @@ extern "C" sk_status sk_submit(sk_ctx *ctx, const int16_t *W_host, int32_t n, co
     } else if (placed) {
         hipError_t e = hipSetDevice(ctx->device);
         if (e == hipSuccess)
-            e = hipMemcpyAsync((void *)r->inst.W, W_host, wbytes, hipMemcpyHostToDevice,
-                               S->copy_stream);
+            e = hipMemcpy2DAsync((void *)r->inst.W, sizeof(int16_t) * pad8(n), W_host,
+                                 sizeof(int16_t) * n, sizeof(int16_t) * n, n,
+                                 hipMemcpyHostToDevice, S->copy_stream);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&r->ev, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventRecord(r->ev, S->copy_stream);
         if (e == hipSuccess) e = hipEventSynchronize(r->ev);
@@ -621,7 +652,7 @@ extern "C" sk_status sk_submit(sk_ctx *ctx, const int16_t *W_host, int32_t n, co
             delete r;
             return fail(ctx, SK_ENOMEM, "host staging allocation failed");
         }
-        stage_copy(r->staging, W_host, wbytes);
+        stage_rows(r->staging, W_host, n);
     }
     {
         std::lock_guard<std::mutex> g(S->mu);

@@ -40,7 +40,7 @@ sk_status reduce_and_solve(sk_ctx *ctx, Batch &B, Bump &rest, int64_t *d_rp, con
     const int n = I.n;
     const double logt = std::log(t);
     const int nunits = (int)B.h_rows.size();
-    const size_t lds = sizeof(double) * (size_t)n;
+    const size_t lds = gq_lds_bytes(n);
     if (!counted) {
         HIPCHK(ctx, PROF(ctx, KID_PRUNE_COUNT, launch_prune_count(B.d_insts, B.d_rows, nunits, B.row_grid,
                                                                  logt, B.d_counts, lds, ctx->stream)));

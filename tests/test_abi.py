@@ -123,3 +123,18 @@ def test_solve_reduced_errors():
     perm, weight = sk.solve_reduced(np.array([0], np.int64), np.array([], np.int32),
                                     np.array([], np.int16), 0)
     assert weight == 0
+
+
+def test_arena_sizes_include_the_padded_copy():
+    """A W whose n is not a multiple of 8 is copied into the library's 8-wide
+    layout (pitch rounded up to 8): the arena sizes grow by that copy, and
+    only for such n."""
+    L = sk.lib()
+    copy = 2 * 1001 * 1008
+    assert L.sk_arena_bytes(1001, 0) - L.sk_arena_bytes(1000, 0) >= copy
+    assert L.sk_arena_bytes(1008, 0) - L.sk_arena_bytes(1000, 0) < copy // 4
+    one = lambda n: L.sk_batch_arena_bytes(1, (ctypes.c_int32 * 1)(n), 0)
+    assert one(1001) - one(1000) >= copy
+    assert one(1008) - one(1000) < copy // 4
+    two = L.sk_batch_arena_bytes(2, (ctypes.c_int32 * 2)(1001, 37), 0)
+    assert two - L.sk_batch_arena_bytes(2, (ctypes.c_int32 * 2)(1000, 40), 0) >= copy + 2 * 37 * 40

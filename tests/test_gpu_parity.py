@@ -67,12 +67,13 @@ def test_fixed_iterations_match_oracle(ctx, n, p, iters):
     assert np.abs(np.exp(Lg) - np.exp(Lo)).max() < 1e-5
 
 
-@pytest.mark.parametrize("n", [512, 16384])
+@pytest.mark.parametrize("n", [512, 4099, 16383, 16384])
 def test_single_step_sampled_full_size(ctx, n):
     """One full iteration from a warm start at p = 32 (w uniform on 0..1000):
     log u of sampled rows equals the oracle's row step on the starting v, and
     log v of sampled columns equals the oracle's column step on the GPU's new
-    u. At n = 16384 this is the benchmark's configuration."""
+    u. At n = 16384 this is the benchmark's configuration; 4099 and 16383 run
+    on the library's padded 8-wide copy (ragged last chunk and column tile)."""
     p = 32
     W = skgen.uniform_weights(n, 0, 1000, seed=3)
     Wd = dev(W)
@@ -82,8 +83,8 @@ def test_single_step_sampled_full_size(ctx, n):
     res = ctx.scale(Wd, sk.make_params([p], tol=0.0, max_iters=1, warm_start=True), potentials=pot1)
     ub1, vb1 = bars(res.potentials, n, p)
     rng = np.random.default_rng(0)
-    rows = np.sort(rng.choice(n, 64, replace=False))
-    cols = np.sort(rng.choice(n, 64, replace=False))
+    rows = np.sort(np.r_[rng.choice(n - 8, 60, replace=False), np.arange(n - 4, n)])
+    cols = np.sort(np.r_[rng.choice(n - 8, 60, replace=False), np.arange(n - 4, n)])
     u_or = oracle.row_step(oracle.log_weights(W[rows]), p, vb0)
     v_or = oracle.col_step(oracle.log_weights(np.ascontiguousarray(W[:, cols])), p, ub1)
     # potentials are compared in log u = p * ubar units (absolute)
@@ -129,10 +130,11 @@ def test_config_planted_n4096(ctx):
     assert out["log_gamma"] < 1.0
 
 
-def test_config_dominant_sparse(ctx):
+@pytest.mark.parametrize("n", [2048, 2045])
+def test_config_dominant_sparse(ctx, n):
     """Diagonally dominant 5% pattern (sentinel elsewhere): the identity is the
-    unique optimum; the reduced matrix keeps exactly the diagonal."""
-    n = 2048
+    unique optimum; the reduced matrix keeps exactly the diagonal (n = 2045:
+    sentinels and the padding columns of the 8-wide copy together)."""
     W = skgen.dominant(n, seed=5)
     prm = sk.make_params([1, 2, 4, 8, 16, 32], tol=1e-5, max_iters=5000, check_every=64,
                          threshold=1e-4)
@@ -225,13 +227,16 @@ def test_n1_and_n2(ctx):
     assert abs(X[0, 0] - R / (1 + R)) < 1e-6
 
 
-def test_empty_row_and_column_report_no_support(ctx):
-    W = skgen.uniform_weights(16, 0, 10, seed=1)
+@pytest.mark.parametrize("n", [16, 13])
+def test_empty_row_and_column_report_no_support(ctx, n):
+    """An all-sentinel row or column has no support (n = 13: the padding
+    columns of the 8-wide copy must not count as entries of the row)."""
+    W = skgen.uniform_weights(n, 0, 10, seed=1)
     W[3, :] = sk.SENTINEL
     with pytest.raises(sk.SkError) as e:
         ctx.scale(dev(W), sk.make_params([1, 2], tol=1e-6, max_iters=50))
     assert e.value.status == sk.SK_ENOSUPPORT
-    W = skgen.uniform_weights(16, 0, 10, seed=1)
+    W = skgen.uniform_weights(n, 0, 10, seed=1)
     W[:, 5] = sk.SENTINEL
     with pytest.raises(sk.SkError) as e:
         ctx.scale(dev(W), sk.make_params([1, 2], tol=1e-6, max_iters=50))
