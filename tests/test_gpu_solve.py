@@ -125,6 +125,26 @@ def test_dominant_instance_proves_optimality(ctx):
     assert out["report"]["optimal_proved"] == 1
 
 
+def test_dominant_full_size_recovers_identity(ctx):
+    """The diagonally dominant 5% pattern at n = 16384 (sentinel-heavy, the
+    largest size): the unique optimum is the identity (every diagonal weight
+    exceeds every off-diagonal one), with the closed-form weight; the reduced
+    matrix keeps the diagonal only and the certificate proves optimality."""
+    n = 16384
+    W = skgen.dominant(n, seed=5)
+    diag = int(np.diag(W).astype(np.int64).sum())
+    Wd = dev(W)
+    del W
+    prm = sk.make_params([1, 2, 4, 8, 16, 32], tol=1e-5, max_iters=60, check_every=32,
+                         threshold=1e-4)
+    out = ctx.solve(Wd, prm)
+    assert out["status"] in (sk.SK_OK, sk.SK_ENOCONV)
+    assert out["weight"] == diag
+    assert (out["perm"] == np.arange(n)).all()
+    assert out["nnz"] == n
+    assert out["report"]["optimal_proved"] == 1
+
+
 def test_planted_4096_full_path(ctx):
     n = 4096
     W, sigma = skgen.planted(n, seed=2)
