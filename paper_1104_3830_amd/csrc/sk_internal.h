@@ -15,6 +15,7 @@ constexpr int kColTile8 = 512;   // columns per column tile, 8-wide vector loads
 constexpr int kColTile1 = 64;    // columns per column tile, scalar loads
 constexpr int kMaxN = 16384;     // row sweep stages all column potentials in LDS
 constexpr int kMaxSegRows = 1024;
+constexpr int kShortRowN = 2048;  // batches up to this n take the short-row row sweep
 constexpr int kFusedSlots = 256;  // workgroups (and column-partial slots) of the fused kernel
 
 // Column count of the 8-wide layout: n rounded up to a multiple of 8.
@@ -178,8 +179,13 @@ hipError_t launch_init(const Inst *d_insts, const RowUnit *d_units, int nunits, 
                        hipStream_t st);
 hipError_t launch_pad_copy(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
                            hipStream_t st);
+// short_rows: every instance of the batch has n <= kShortRowN (the row
+// sweep compiled for two workgroups per CU, sk_rowshort.hip)
 hipError_t launch_row_sweep(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
-                            size_t lds_bytes, int nt_loads, hipStream_t st);
+                            size_t lds_bytes, int nt_loads, int short_rows, hipStream_t st);
+hipError_t launch_row_sweep_short(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
+                                  size_t lds_bytes, int nt_loads, hipStream_t st);
+hipError_t set_row_sweep_short_attributes();
 hipError_t launch_col_sweep(const Inst *d_insts, const ColUnit *d_units, int nunits, int grid,
                             int nt_loads, hipStream_t st);
 hipError_t launch_nt_product(const Inst *d_insts, const RowUnit *d_rows, int nrows, int row_grid,

@@ -1,0 +1,463 @@
+// Device helpers shared by the HIP kernels, and the log-domain row sweep.
+// The row sweep is a template on the waves per SIMD it is compiled for; each
+// instantiation lives in a translation unit of its own (sk_kernels.hip: long
+// rows; sk_rowshort.hip: batches of short rows), so that neither changes the
+// other's code.
+#pragma once
+
+#include "sk_exptab.h"
+
+namespace sk {
+
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kLn2 = 0.6931471805599453f;
+constexpr float kSafeLo = 5.421010862427522e-20f;  // 2^-64
+constexpr float kSafeHi = 1.8446744073709552e19f;  // 2^64
+
+__device__ __forceinline__ float ex2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float lg2(float x) { return __builtin_amdgcn_logf(x); }
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+__device__ __forceinline__ double wave_max_d(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+// Contiguous range of work units owned by this workgroup.
+__device__ __forceinline__ void unit_range(int nunits, int &u0, int &u1) {
+    int per = (nunits + (int)gridDim.x - 1) / (int)gridDim.x;
+    u0 = (int)blockIdx.x * per;
+    u1 = min(nunits, u0 + per);
+}
+
+// LDS position of column j for 8-wide lanes: lane l owns columns
+// l*8 + k*512 + c; storing column j at (j%8)*(n/8) + j/8 makes the 64 lanes
+// read 64 consecutive entries for each c (no bank conflicts).
+__device__ __forceinline__ int swz8(int j, int n8) { return (j & 7) * n8 + (j >> 3); }
+
+// In a row's last 8-wide chunk (columns jj..jj+7 with jj + 8 > n) the padding
+// columns are marked absent, so the sentinel tests that follow skip them.
+__device__ __forceinline__ void mask_pad8(int (&w)[8], int jj, int n) {
+    if (jj + 8 > n) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+            if (jj + c >= n) w[c] = SK_SENTINEL;
+    }
+}
+
+// ---------------------------------------------------------------- row sweep
+// One wavefront per row; per column (4 G_j, exp(gam_j)) staged once per
+// workgroup in LDS; W read with coalesced 16-byte loads. B = 4 (F_i - shift)
+// - 4 kTabLo carries the row's integer part and the shift.
+
+// Column data of the row sweep: a = 4 G_j, g = exp(gam_j).
+struct alignas(8) ColPot {
+    int a;
+    float g;
+};
+
+template <bool SENT>
+__device__ __forceinline__ float chunk8(const int4 v, int q, int n8, int p4, int B,
+                                        const ColPot *__restrict__ cp,
+                                        const float *__restrict__ tab) {
+    int w[8];
+    unpack8i(v, w);
+    float s = 0.f;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const ColPot k = cp[c * n8 + q];
+        float e = tab_at(tab, tab_off(p4, w[c], k.a, B));
+        if (SENT) e = (w[c] == SK_SENTINEL) ? 0.f : e;
+        s = fmaf(e, k.g, s);
+    }
+    return s;
+}
+
+// Loads in flight per lane in the sweeps (build-time tuning knobs).
+#ifndef SK_ROW_UNROLL
+#define SK_ROW_UNROLL 2
+#endif
+#ifndef SK_COL_UNROLL
+#define SK_COL_UNROLL 1
+#endif
+// Two rows per wave in the row sweep (build-time switch) and the chunks in
+// flight per row when it does.
+#ifndef SK_ROW_PAIR
+#define SK_ROW_PAIR 0
+#endif
+#ifndef SK_PAIR_UNROLL
+#define SK_PAIR_UNROLL 1
+#endif
+// Software pipelining of the sweeps' loads (build-time switch).
+#ifndef SK_ROW_PIPE
+#define SK_ROW_PIPE 0
+#endif
+#ifndef SK_COL_PIPE
+#define SK_COL_PIPE 1
+#endif
+
+// Row partial sum for one lane: chunks lane*8 + k*512, SK_ROW_UNROLL 16-byte
+// loads in flight per lane.
+template <bool SENT, bool NT>
+__device__ __forceinline__ float row_partial_v8(const int16_t *__restrict__ wr, int n, int p4,
+                                                int B, const ColPot *__restrict__ cp,
+                                                const float *__restrict__ tab, int lane) {
+    constexpr int U = SK_ROW_UNROLL;
+    const int n8 = pad8(n) >> 3;
+    float acc = 0.f;
+    int j0 = lane * 8;
+#if SK_ROW_PIPE
+    // two register buffers (see the column sweep); chunks are still added in order
+    auto ld = [&](int4 (&v)[U], int jj) {
+#pragma unroll
+        for (int k = 0; k < U; ++k) v[k] = gload<NT>(reinterpret_cast<const int4 *>(wr + jj + k * 512));
+    };
+    auto use = [&](const int4 (&v)[U], int jj) {
+#pragma unroll
+        for (int k = 0; k < U; ++k) acc += chunk8<SENT>(v[k], (jj >> 3) + 64 * k, n8, p4, B, cp, tab);
+    };
+    if (j0 + (U - 1) * 512 < n) {
+        int4 va[U], vb[U];
+        ld(va, j0);
+        for (;;) {
+            const int j2 = j0 + U * 512;
+            const bool more = j2 + (U - 1) * 512 < n;
+            if (more) ld(vb, j2);
+            use(va, j0);
+            j0 = j2;
+            if (!more) break;
+            const int j3 = j0 + U * 512;
+            const bool more2 = j3 + (U - 1) * 512 < n;
+            if (more2) ld(va, j3);
+            use(vb, j0);
+            j0 = j3;
+            if (!more2) break;
+        }
+    }
+#else
+    for (; j0 + (U - 1) * 512 < n; j0 += U * 512) {
+        int4 v[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) v[k] = gload<NT>(reinterpret_cast<const int4 *>(wr + j0 + k * 512));
+        const int q = j0 >> 3;
+#pragma unroll
+        for (int k = 0; k < U; ++k) acc += chunk8<SENT>(v[k], q + 64 * k, n8, p4, B, cp, tab);
+    }
+#endif
+    for (; j0 < n; j0 += 512) {
+        const int4 v = gload<NT>(reinterpret_cast<const int4 *>(wr + j0));
+        acc += chunk8<SENT>(v, j0 >> 3, n8, p4, B, cp, tab);
+    }
+    return acc;
+}
+
+// max_j of 4 (p w_ij + G_j) + B over the entries of the row (INT_MIN if none).
+template <bool SENT, bool NT>
+__device__ __forceinline__ int row_max_v8(const int16_t *__restrict__ wr, int n, int p4, int B,
+                                          const ColPot *__restrict__ cp, int lane) {
+    const int n8 = pad8(n) >> 3;
+    int m = INT_MIN;
+    for (int j0 = lane * 8; j0 < n; j0 += 512) {
+        const int4 v = gload<NT>(reinterpret_cast<const int4 *>(wr + j0));
+        int w[8];
+        unpack8i(v, w);
+        const int q = j0 >> 3;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int t = __mul24(p4, w[c]) + cp[c * n8 + q].a + B;
+            if ((!SENT || w[c] != SK_SENTINEL) && j0 + c < n) m = max(m, t);
+        }
+    }
+    return m;
+}
+
+template <bool SENT, bool NT>
+__device__ __forceinline__ float row_partial_v1(const int16_t *__restrict__ wr, int n, int p4,
+                                                int B, const ColPot *__restrict__ cp,
+                                                const float *__restrict__ tab, int lane) {
+    float acc = 0.f;
+    for (int j = lane; j < n; j += kWave) {
+        const int w = (int)gload<NT>(wr + j);
+        const ColPot k = cp[j];
+        float e = tab_at(tab, tab_off(p4, w, k.a, B));
+        if (SENT) e = (w == SK_SENTINEL) ? 0.f : e;
+        acc = fmaf(e, k.g, acc);
+    }
+    return acc;
+}
+
+template <bool SENT, bool NT>
+__device__ __forceinline__ int row_max_v1(const int16_t *__restrict__ wr, int n, int p4, int B,
+                                          const ColPot *__restrict__ cp, int lane) {
+    int m = INT_MIN;
+    for (int j = lane; j < n; j += kWave) {
+        const int w = (int)gload<NT>(wr + j);
+        const int t = __mul24(p4, w) + cp[j].a + B;
+        if (!SENT || w != SK_SENTINEL) m = max(m, t);
+    }
+    return m;
+}
+
+// Completes the row step of `row` from its sum S relative to the previous
+// iterate (shift 0): the exact max-shifted recompute if S left the safe
+// range, then the new potentials and the residual.
+template <bool SENT, bool V8, bool NT>
+__device__ __forceinline__ float row_finish(const Inst &I, int row, int par, int lane, int Fi,
+                                            float phi, float S, const ColPot *__restrict__ cp,
+                                            const float *__restrict__ tab) {
+    const int n = I.n;
+    const int16_t *wr = I.W + (int64_t)row * I.pitch;
+    const int p4 = 4 * I.ctl->p;
+    int M = 0;
+    if (!(S >= kSafeLo && S <= kSafeHi)) {
+        // exact max-shift (Section 4.1.2): M = max_j (p w_ij + F_i + G_j)
+        int m4 = V8 ? row_max_v8<SENT, NT>(wr, n, p4, 4 * Fi, cp, lane)
+                    : row_max_v1<SENT, NT>(wr, n, p4, 4 * Fi, cp, lane);
+        m4 = wave_max_i(m4);
+        if (m4 == INT_MIN) {
+            if (lane == 0) atomicOr(&I.ctl->err, ERR_EMPTY_ROW);
+            S = 1.f;
+        } else {
+            M = m4 >> 2;  // exact: m4 is a multiple of 4
+            S = V8 ? row_partial_v8<SENT, NT>(wr, n, p4, 4 * (Fi - M - kTabLo), cp, tab, lane)
+                   : row_partial_v1<SENT, NT>(wr, n, p4, 4 * (Fi - M - kTabLo), cp, tab, lane);
+            S = wave_sum(S);
+        }
+    }
+    if (lane == 0) {
+        // log u_i <- F_i - M - log S
+        const float l2S = lg2(S);
+        const float phin = -l2S * kLn2;
+        const float k = rintf(phin);
+        I.F[par ^ 1][row] = Fi - M + (int)k;
+        I.phi[par ^ 1][row] = phin - k;
+        // r_i = exp(phi_i + M) S: row sum of the current iterate
+        const float r = ex2(fmaf(phi + (float)M, kLog2e, l2S));
+        const float res = fabsf(r - 1.f);
+        I.rres[row] = res;
+        return res;
+    }
+    return 0.f;
+}
+
+template <bool SENT, bool V8, bool NT>
+__device__ __forceinline__ float row_step_one(const Inst &I, int row, int par, int lane,
+                                             const ColPot *__restrict__ cp,
+                                             const float *__restrict__ tab) {
+    const int n = I.n;
+    const int16_t *wr = I.W + (int64_t)row * I.pitch;
+    const int Fi = I.F[par][row];
+    // loaded with F_i so that the end of the row does not wait for it
+    const float phi = I.phi[par][row];
+    const int p4 = 4 * I.ctl->p;
+    float S = V8 ? row_partial_v8<SENT, NT>(wr, n, p4, 4 * (Fi - kTabLo), cp, tab, lane)
+                 : row_partial_v1<SENT, NT>(wr, n, p4, 4 * (Fi - kTabLo), cp, tab, lane);
+    S = wave_sum(S);
+    return row_finish<SENT, V8, NT>(I, row, par, lane, Fi, phi, S, cp, tab);
+}
+
+// Two rows in one pass over the columns: each column's (4 G_j, exp(gam_j))
+// is read from LDS once for both rows. Each row's chunks are added in the
+// same order as in row_partial_v8, so a row's sum does not depend on whether
+// it is paired.
+template <bool SENT>
+__device__ __forceinline__ void chunk8x2(const int4 v0, const int4 v1, int q, int n8, int p4,
+                                         int B0, int B1, const ColPot *__restrict__ cp,
+                                         const float *__restrict__ tab, float &s0, float &s1) {
+    int w0[8], w1[8];
+    unpack8i(v0, w0);
+    unpack8i(v1, w1);
+    s0 = 0.f;
+    s1 = 0.f;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const ColPot k = cp[c * n8 + q];
+        float e0 = tab_at(tab, tab_off(p4, w0[c], k.a, B0));
+        float e1 = tab_at(tab, tab_off(p4, w1[c], k.a, B1));
+        if (SENT) {
+            e0 = (w0[c] == SK_SENTINEL) ? 0.f : e0;
+            e1 = (w1[c] == SK_SENTINEL) ? 0.f : e1;
+        }
+        s0 = fmaf(e0, k.g, s0);
+        s1 = fmaf(e1, k.g, s1);
+    }
+}
+
+template <bool SENT, bool NT>
+__device__ __forceinline__ void row_partial2_v8(const int16_t *__restrict__ wr0,
+                                                const int16_t *__restrict__ wr1, int n, int p4,
+                                                int B0, int B1, const ColPot *__restrict__ cp,
+                                                const float *__restrict__ tab, int lane,
+                                                float &acc0, float &acc1) {
+    constexpr int U = SK_PAIR_UNROLL;
+    const int n8 = pad8(n) >> 3;
+    acc0 = 0.f;
+    acc1 = 0.f;
+    int j0 = lane * 8;
+    for (; j0 + (U - 1) * 512 < n; j0 += U * 512) {
+        int4 v0[U], v1[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            v0[k] = gload<NT>(reinterpret_cast<const int4 *>(wr0 + j0 + k * 512));
+            v1[k] = gload<NT>(reinterpret_cast<const int4 *>(wr1 + j0 + k * 512));
+        }
+        const int q = j0 >> 3;
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            float s0, s1;
+            chunk8x2<SENT>(v0[k], v1[k], q + 64 * k, n8, p4, B0, B1, cp, tab, s0, s1);
+            acc0 += s0;
+            acc1 += s1;
+        }
+    }
+    for (; j0 < n; j0 += 512) {
+        float s0, s1;
+        chunk8x2<SENT>(gload<NT>(reinterpret_cast<const int4 *>(wr0 + j0)),
+                       gload<NT>(reinterpret_cast<const int4 *>(wr1 + j0)), j0 >> 3, n8, p4, B0, B1, cp,
+                       tab, s0, s1);
+        acc0 += s0;
+        acc1 += s1;
+    }
+}
+
+template <bool SENT, bool NT>
+__device__ __forceinline__ float row_step_pair(const Inst &I, int ra, int rb, int par, int lane,
+                                              const ColPot *__restrict__ cp,
+                                              const float *__restrict__ tab) {
+    const int n = I.n;
+    const int Fa = I.F[par][ra], Fb = I.F[par][rb];
+    const int p4 = 4 * I.ctl->p;
+    float Sa, Sb;
+    row_partial2_v8<SENT, NT>(I.W + (int64_t)ra * I.pitch, I.W + (int64_t)rb * I.pitch, n, p4,
+                          4 * (Fa - kTabLo), 4 * (Fb - kTabLo), cp, tab, lane, Sa, Sb);
+    Sa = wave_sum(Sa);
+    Sb = wave_sum(Sb);
+    const float ea = row_finish<SENT, true, NT>(I, ra, par, lane, Fa, I.phi[par][ra], Sa, cp, tab);
+    const float eb = row_finish<SENT, true, NT>(I, rb, par, lane, Fb, I.phi[par][rb], Sb, cp, tab);
+    return fmaxf(ea, eb);
+}
+
+// Column potentials of the padding columns n..pad8(n)-1 of the 8-wide layout
+// (a separate loop, so that the staging of the real columns keeps its loads
+// unconditional and in flight together).
+__device__ __forceinline__ void stage_pad_cols(const Inst &I, ColPot *cp, int n8) {
+    if (!I.vec8) return;
+    for (int j = I.n + (int)threadIdx.x; j < 8 * n8; j += blockDim.x) {
+        ColPot k;
+        k.a = kPadExp4;
+        k.g = 0.f;
+        cp[swz8(j, n8)] = k;
+    }
+}
+
+// Waves run their rows independently: the only barrier is the restaging of
+// the column data when the instance changes. The residual |r_i - 1| goes to
+// rres[i] (the column sweep reduces it per row segment for the finalise) and
+// each wave's maximum to one of the instance's rowres slots (an exact
+// maximum, so the column sweep's reduction of the slots equals the
+// finalise's value; it uses it to skip a detection pass).
+// MINW is the waves per SIMD the kernel is compiled for: 1 for long rows
+// (registers hold loads in flight), 8 for batches of short rows (n <=
+// kShortRowN; two workgroups per CU, at most 64 VGPRs). A short row is one or
+// two passes of loads, so a wave's time goes to waiting for them, and twice
+// the resident waves hide twice the latency.
+template <bool NT, int MINW>
+__global__ __launch_bounds__(kRowWaves * kWave, MINW) void k_row_sweep(const Inst *__restrict__ insts,
+                                                                   const RowUnit *__restrict__ units,
+                                                                   int nunits) {
+    extern __shared__ ColPot lds_cp[];
+    __shared__ float tab[kTabN];
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    int u0, u1;
+    unit_range(nunits, u0, u1);
+    __shared__ unsigned wg_res, wg_done;
+    if (threadIdx.x == 0) {
+        wg_res = 0u;
+        wg_done = 0u;
+    }
+    fill_exp_table(tab);
+    __syncthreads();
+    int cur = -1;
+    float wres = 0.f;  // this wave's residual maximum for instance `cur` (lane 0)
+    const int slot = (int)((blockIdx.x * kRowWaves + wave) % kRowResSlots) * kRowResStride;
+    auto flush = [&]() {
+        if (cur >= 0 && lane == 0 && wres > 0.f)
+            atomicMax(&insts[cur].rowres[slot], __float_as_uint(wres));
+        wres = 0.f;
+    };
+    for (int u = u0; u < u1;) {
+        const RowUnit un = units[u];
+        const Inst &I = insts[un.inst];
+        Ctl *ctl = I.ctl;
+        if (ctl->state != ST_RUNNING) {
+            ++u;
+            continue;
+        }
+        const int n = I.n;
+        const int iter = ctl->iter;
+        if (un.inst != cur) {
+            flush();
+            __syncthreads();
+            const int n8 = pad8(n) >> 3;
+            for (int j = threadIdx.x; j < n; j += blockDim.x) {
+                ColPot k;
+                k.a = 4 * I.G[j];
+                k.g = ex2(I.gam[j] * kLog2e);
+                lds_cp[I.vec8 ? swz8(j, n8) : j] = k;
+            }
+            stage_pad_cols(I, lds_cp, n8);
+            __syncthreads();
+            cur = un.inst;
+        }
+        const int par = iter & 1;
+        const bool sent = ctl->sent != 0u;
+        const int ra = un.row0 + wave;
+        // the next unit of the same instance is done in the same pass
+        const bool pair = SK_ROW_PAIR && I.vec8 && u + 1 < u1 && units[u + 1].inst == un.inst;
+        const int rb = pair ? units[u + 1].row0 + wave : n;
+        float e = 0.f;
+        if (rb < n) {
+            e = sent ? row_step_pair<true, NT>(I, ra, rb, par, lane, lds_cp, tab)
+                     : row_step_pair<false, NT>(I, ra, rb, par, lane, lds_cp, tab);
+        } else if (ra < n) {
+            if (I.vec8) {
+                e = sent ? row_step_one<true, true, NT>(I, ra, par, lane, lds_cp, tab)
+                         : row_step_one<false, true, NT>(I, ra, par, lane, lds_cp, tab);
+            } else {
+                e = sent ? row_step_one<true, false, NT>(I, ra, par, lane, lds_cp, tab)
+                         : row_step_one<false, false, NT>(I, ra, par, lane, lds_cp, tab);
+            }
+        }
+        wres = fmaxf(wres, e);
+        u += pair ? 2 : 1;
+    }
+    // every wave ends on the same instance: the waves' maxima meet in LDS and
+    // the last wave to finish sends the workgroup's to the slot
+    if (lane == 0) {
+        if (wres > 0.f) atomicMax(&wg_res, __float_as_uint(wres));
+        __threadfence_block();
+        const unsigned k = atomicAdd(&wg_done, 1u);
+        if (k == kRowWaves - 1) {
+            __threadfence_block();
+            const unsigned m = atomicMax(&wg_res, 0u);  // read after every wave's update
+            if (cur >= 0 && m > 0u) atomicMax(&insts[cur].rowres[slot], m);
+        }
+    }
+}
+
+}  // namespace sk

@@ -508,7 +508,7 @@ sk_status sk::iterate_i16(sk_ctx *ctx, Batch &B) {
     const int s0 = pf.stamp(ctx->stream);
     const int nt = B.count > 0 ? B.h_insts[0].nt : 0;  // the same for the whole batch
     HIPCHK(ctx, launch_row_sweep(B.d_insts, B.d_rows, (int)B.h_rows.size(), B.row_grid, B.row_lds,
-                                 nt, ctx->stream));
+                                 nt, B.nmax <= kShortRowN, ctx->stream));
     const int s1 = pf.stamp(ctx->stream);
     HIPCHK(ctx, launch_col_sweep(B.d_insts, B.d_cols, (int)B.h_cols.size(), B.col_grid, nt,
                                  ctx->stream));
