@@ -46,8 +46,8 @@ __device__ __forceinline__ void unit_range(int nunits, int &u0, int &u1) {
 }
 
 // LDS position of column j for 8-wide lanes: lane l owns columns
-// l*8 + k*512 + c; storing column j at (j%8)*(n/8) + j/8 makes the 64 lanes
-// read 64 consecutive entries for each c (no bank conflicts).
+// l*8 + k*512 + c; storing column j at (j%8)*n8 + j/8, n8 = pad8(n)/8, makes
+// the 64 lanes read 64 consecutive entries for each c (no bank conflicts).
 __device__ __forceinline__ int swz8(int j, int n8) { return (j & 7) * n8 + (j >> 3); }
 
 // In a row's last 8-wide chunk (columns jj..jj+7 with jj + 8 > n) the padding

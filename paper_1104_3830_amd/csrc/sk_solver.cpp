@@ -10,11 +10,17 @@
 #include <cstring>
 #include <limits>
 #include <queue>
+#include <thread>
 #include <vector>
 
 #include "../../include/sk.h"
 
 namespace {
+
+// The row and column reductions of an instance with at least kParallelNnz
+// entries run on up to kReduceThreads host threads.
+constexpr int64_t kParallelNnz = int64_t(1) << 17;
+constexpr unsigned kReduceThreads = 4;
 
 struct HeapItem {
     int64_t d;
@@ -52,71 +58,96 @@ sk_status sk::solve_reduced_seeded(const sk_csr *csr, const int32_t *hint, int32
         if (rp[i + 1] < rp[i]) return SK_EINVAL;
 
     const int64_t INF = std::numeric_limits<int64_t>::max() / 4;
-    std::vector<int64_t> u(n), v(n, 0);
+    std::vector<int64_t> u(n), v(n, INF);
     std::vector<int32_t> row_of(n, -1), col_of(n, -1);
-    // u_i = min_j c_ij makes every reduced cost non-negative with v = 0
-    // (and the entries are checked on the way)
-    for (int i = 0; i < n; ++i) {
-        if (rp[i + 1] == rp[i]) return SK_EINFEASIBLE;  // empty row
-        int64_t m = INF;
-        for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
-            if (col[e] < 0 || col[e] >= n || w[e] == SK_SENTINEL) return SK_EINVAL;
-            m = std::min<int64_t>(m, -(int64_t)w[e]);
+    std::vector<int64_t> mpos(n, -1);  // CSR position of row i's matched edge
+    // u_i = min_j c_ij makes every reduced cost non-negative with v = 0; the
+    // column reduction v_j = min over edges into j of c_ij - u_i keeps them
+    // non-negative and makes more edges tight. Both in one pass over the rows
+    // (a row's second loop finds it in cache), the entries checked on the way;
+    // large instances split the rows over a few threads, each with its own
+    // column minima (merged after), and report the first bad row in row order.
+    struct Part {
+        int r0, r1;
+        std::vector<int64_t> vmin;
+        int bad_row = -1;
+        sk_status bad = SK_OK;
+    };
+    auto reduce_rows = [&](Part &P, int64_t *vmin) {
+        for (int i = P.r0; i < P.r1; ++i) {
+            const int64_t e0 = rp[i], e1 = rp[i + 1];
+            if (e1 == e0) {  // empty row
+                P.bad_row = i;
+                P.bad = SK_EINFEASIBLE;
+                return;
+            }
+            int64_t m = INF;
+            for (int64_t e = e0; e < e1; ++e) {
+                if (col[e] < 0 || col[e] >= n || w[e] == SK_SENTINEL) {
+                    P.bad_row = i;
+                    P.bad = SK_EINVAL;
+                    return;
+                }
+                m = std::min<int64_t>(m, -(int64_t)w[e]);
+            }
+            u[i] = m;
+            for (int64_t e = e0; e < e1; ++e) {
+                const int j = col[e];
+                vmin[j] = std::min<int64_t>(vmin[j], -(int64_t)w[e] - m);
+            }
         }
-        u[i] = m;
+    };
+    {
+        const unsigned hc = std::thread::hardware_concurrency();
+        const int T = csr->nnz >= kParallelNnz && hc >= 2 ? (int)std::min<unsigned>(kReduceThreads, hc) : 1;
+        std::vector<Part> parts(T);
+        for (int t = 0; t < T; ++t) {
+            // rows split so that each part holds about nnz / T entries
+            const int64_t lo = csr->nnz * t / T, hi = csr->nnz * (t + 1) / T;
+            parts[t].r0 = t == 0 ? 0 : (int)(std::lower_bound(rp, rp + n, lo) - rp);
+            parts[t].r1 = t == T - 1 ? n : (int)(std::lower_bound(rp, rp + n, hi) - rp);
+            if (t > 0) parts[t].vmin.assign(n, INF);
+        }
+        std::vector<std::thread> th;
+        for (int t = 1; t < T; ++t) th.emplace_back([&, t] { reduce_rows(parts[t], parts[t].vmin.data()); });
+        reduce_rows(parts[0], v.data());
+        for (auto &x : th) x.join();
+        for (const Part &P : parts)
+            if (P.bad != SK_OK) return P.bad;  // parts are in row order
+        for (int t = 1; t < T; ++t)
+            for (int j = 0; j < n; ++j) v[j] = std::min(v[j], parts[t].vmin[j]);
     }
-    // column reduction: v_j = min over edges into j of c_ij - u_i keeps every
-    // reduced cost non-negative and makes more edges tight
-    for (int j = 0; j < n; ++j) v[j] = INF;
-    for (int i = 0; i < n; ++i)
-        for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
-            const int j = col[e];
-            v[j] = std::min<int64_t>(v[j], -(int64_t)w[e] - u[i]);
-        }
     for (int j = 0; j < n; ++j)
         if (v[j] == INF) return SK_EINFEASIBLE;  // empty column
-    // maximum matching on the tight edges (reduced cost 0), Hopcroft-Karp
-    // from a greedy start: each row takes its hinted column if that edge is
-    // tight and the column still free, else its first free tight column
+    // maximum matching on the tight edges (reduced cost 0), tested where an
+    // edge is looked at: Hopcroft-Karp from a greedy start, in which each row
+    // takes its hinted column if that edge is tight and the column still
+    // free, else its first free tight column
+    auto tight = [&](int i, int64_t e) { return -(int64_t)w[e] - u[i] - v[col[e]] == 0; };
     {
-        int64_t ntight = 0;
-        for (int i = 0; i < n; ++i)
-            for (int64_t e = rp[i]; e < rp[i + 1]; ++e)
-                ntight += (-(int64_t)w[e] - u[i] - v[col[e]] == 0);
-        // when every edge is tight (the usual case for a reduced matrix B)
-        // the matching runs on B's own arrays
-        std::vector<int64_t> tpv;
-        std::vector<int32_t> tcv;
         const int64_t *tp = rp;
         const int32_t *tc = col;
-        if (ntight != csr->nnz) {
-            tpv.assign(n + 1, 0);
-            tcv.reserve((size_t)ntight);
-            for (int i = 0; i < n; ++i) {
-                for (int64_t e = rp[i]; e < rp[i + 1]; ++e)
-                    if (-(int64_t)w[e] - u[i] - v[col[e]] == 0) tcv.push_back(col[e]);
-                tpv[i + 1] = (int64_t)tcv.size();
-            }
-            tp = tpv.data();
-            tc = tcv.data();
-        }
         if (hint)
             for (int i = 0; i < n; ++i) {
                 const int32_t h = hint[i];
                 if (h < 0 || h >= n || row_of[h] >= 0) continue;
                 for (int64_t e = tp[i]; e < tp[i + 1]; ++e)
                     if (tc[e] == h) {
-                        row_of[h] = i;
-                        col_of[i] = h;
+                        if (tight(i, e)) {
+                            row_of[h] = i;
+                            col_of[i] = h;
+                            mpos[i] = e;
+                        }
                         break;
                     }
             }
         for (int i = 0; i < n; ++i) {
             if (col_of[i] >= 0) continue;
             for (int64_t e = tp[i]; e < tp[i + 1]; ++e)
-                if (row_of[tc[e]] < 0) {
+                if (row_of[tc[e]] < 0 && tight(i, e)) {
                     row_of[tc[e]] = i;
                     col_of[i] = tc[e];
+                    mpos[i] = e;
                     break;
                 }
         }
@@ -142,6 +173,7 @@ sk_status sk::solve_reduced_seeded(const sk_csr *csr, const int32_t *hint, int32
                 const int i = q[qh++];
                 if (dist[i] > limit) break;
                 for (int64_t e = tp[i]; e < tp[i + 1]; ++e) {
+                    if (!tight(i, e)) continue;
                     const int i2 = row_of[tc[e]];
                     if (i2 < 0) {
                         found = true;
@@ -166,6 +198,10 @@ sk_status sk::solve_reduced_seeded(const sk_csr *csr, const int32_t *hint, int32
                         stack.pop_back();
                         continue;
                     }
+                    if (!tight(i, it[i])) {
+                        ++it[i];
+                        continue;
+                    }
                     const int j = tc[it[i]];
                     const int i2 = row_of[j];
                     if (i2 < 0) {
@@ -173,6 +209,7 @@ sk_status sk::solve_reduced_seeded(const sk_csr *csr, const int32_t *hint, int32
                             const int jj = tc[it[r]];
                             col_of[r] = jj;
                             row_of[jj] = r;
+                            mpos[r] = it[r];
                         }
                         for (int r : stack) dist[r] = NIL;  // used this phase
                         stack.clear();
@@ -190,6 +227,7 @@ sk_status sk::solve_reduced_seeded(const sk_csr *csr, const int32_t *hint, int32
 
     std::vector<int64_t> dist(n, INF);
     std::vector<int32_t> pred(n, -1);  // row from which column j was reached
+    std::vector<int64_t> pred_e(n, -1);  // and the CSR position of that edge
     std::vector<char> done(n, 0);
     std::vector<int32_t> touched, finalized;
     touched.reserve(n);
@@ -214,6 +252,7 @@ sk_status sk::solve_reduced_seeded(const sk_csr *csr, const int32_t *hint, int32
             if (d < dist[j]) {
                 dist[j] = d;
                 pred[j] = s;
+                pred_e[j] = e;
                 heap.push({d, j});
             }
         }
@@ -240,6 +279,7 @@ sk_status sk::solve_reduced_seeded(const sk_csr *csr, const int32_t *hint, int32
                 if (nd < dist[k]) {
                     dist[k] = nd;
                     pred[k] = i;
+                    pred_e[k] = e;
                     heap.push({nd, k});
                 }
             }
@@ -261,23 +301,18 @@ sk_status sk::solve_reduced_seeded(const sk_csr *csr, const int32_t *hint, int32
             const int prev = col_of[i];
             row_of[j] = i;
             col_of[i] = j;
+            mpos[i] = pred_e[j];
             if (i == s) break;
             j = prev;
         }
     }
+    // the weight from the matched edges themselves
     int64_t total = 0;
     for (int i = 0; i < n; ++i) {
+        const int64_t e = mpos[i];
+        if (e < rp[i] || e >= rp[i + 1] || col[e] != col_of[i]) return SK_EINVAL;
         perm[i] = col_of[i];
-        int64_t wi = 0;
-        bool found = false;
-        for (int64_t e = rp[i]; e < rp[i + 1]; ++e)
-            if (col[e] == col_of[i]) {
-                wi = w[e];
-                found = true;
-                break;
-            }
-        if (!found) return SK_EINVAL;
-        total += wi;
+        total += w[e];
     }
     *weight = total;
     return SK_OK;

@@ -104,6 +104,53 @@ def test_solve_reduced_vs_oracle_hungarian():
         assert mask[np.arange(n), perm].all()
 
 
+def test_solve_reduced_large_split_over_threads():
+    """An instance with more than 2^17 entries: the reductions run on several
+    host threads. The optimum equals the oracle's; an empty row or a bad
+    column index late in the rows is still reported (the first bad row in row
+    order decides the status)."""
+    rng = np.random.default_rng(11)
+    n = 1500
+    w = rng.integers(0, 1001, (n, n))
+    mask = rng.random((n, n)) < 0.07
+    mask[np.arange(n), rng.permutation(n)] = True
+    rp, cols, ww = _csr(mask, w)
+    assert rp[-1] >= 1 << 17
+    perm, weight = sk.solve_reduced(rp, cols, ww, n)
+    _, w_or = oracle.hungarian(w, mask)
+    assert weight == w_or
+    assert sorted(perm) == list(range(n)) and mask[np.arange(n), perm].all()
+    bad = cols.copy()
+    bad[rp[n - 3]] = n + 5  # a column index out of range in one of the last rows
+    with pytest.raises(sk.SkError) as e:
+        sk.solve_reduced(rp, bad, ww, n)
+    assert e.value.status == sk.SK_EINVAL
+    m2 = mask.copy()
+    m2[n - 2, :] = False  # an empty row late in the rows, before the bad index
+    rp2, cols2, ww2 = _csr(m2, w)
+    bad2 = cols2.copy()
+    bad2[rp2[n - 1]] = -1
+    with pytest.raises(sk.SkError) as e:
+        sk.solve_reduced(rp2, bad2, ww2, n)
+    assert e.value.status == sk.SK_EINFEASIBLE
+    # the two faults in different threads' rows: the earlier row decides
+    m3 = mask.copy()
+    m3[10, :] = False
+    rp3, cols3, ww3 = _csr(m3, w)
+    bad3 = cols3.copy()
+    bad3[rp3[n - 1]] = n
+    with pytest.raises(sk.SkError) as e:
+        sk.solve_reduced(rp3, bad3, ww3, n)
+    assert e.value.status == sk.SK_EINFEASIBLE
+    m4 = mask.copy()
+    m4[n - 1, :] = False
+    rp4, cols4, ww4 = _csr(m4, w)
+    cols4[rp4[10]] = n
+    with pytest.raises(sk.SkError) as e:
+        sk.solve_reduced(rp4, cols4, ww4, n)
+    assert e.value.status == sk.SK_EINVAL
+
+
 def test_solve_reduced_errors():
     # empty row
     rp = np.array([0, 1, 1], dtype=np.int64)

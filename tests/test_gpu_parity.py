@@ -205,6 +205,22 @@ def test_batch_equals_single_bitwise(ctx):
         assert single.report["iters_stage"] == b.report["iters_stage"]
 
 
+def test_row_sweep_instantiations_agree_bitwise(ctx):
+    """A batch whose largest n is at most 2048 runs the row sweep compiled for
+    short rows; with a larger instance in the batch every instance takes the
+    long-row one. The two are the same arithmetic in the same order, so an
+    instance's potentials are bitwise the same either way."""
+    ns = [37, 300, 1000]
+    Ws = [skgen.uniform_weights(n, 0, 1000, seed=70 + k) for k, n in enumerate(ns)]
+    big = skgen.uniform_weights(2100, 0, 1000, seed=79)
+    prm = sk.make_params([1, 2, 4, 8, 16, 32], tol=1e-5, max_iters=300, check_every=16)
+    mixed = ctx.scale_batch([dev(W) for W in Ws] + [dev(big)], prm)
+    for W, b in zip(Ws, mixed):
+        alone = ctx.scale(dev(W), prm)
+        assert torch.equal(alone.potentials, b.potentials)
+        assert alone.report["iters_stage"] == b.report["iters_stage"]
+
+
 def test_repeat_runs_bitwise(ctx):
     W = skgen.uniform_weights(1024, 0, 1000, seed=1)
     prm = sk.make_params([4, 8], tol=1e-5, max_iters=300)
