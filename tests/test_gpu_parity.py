@@ -319,6 +319,63 @@ def test_stored_k_path(ctx, storage, n):
     assert np.abs(Xk - Xr).max() < (2e-2 if storage == "bf16" else 1e-4)
 
 
+@pytest.mark.parametrize("storage,tol", [("bf16", 3e-3), ("f32", 2e-5)])
+def test_stored_k_step_sampled_full_size(ctx, storage, tol):
+    """Stored K at n = 16384 (w uniform on 0..1000, p = 32): from a warm start
+    a stage's first iteration is the exact log-domain one and its second runs
+    on K. The second iteration's log u on sampled rows equals the oracle's row
+    step on the oracle's first-iteration v, and its log v on sampled columns
+    the oracle's column step on the GPU's new u, within the rounding of K
+    (BF16: 2^-9 relative per entry, so at most ~2e-3 on a log sum; FP32:
+    2^-24 per entry plus the FP32 sums)."""
+    n, p = 16384, 32
+    W = skgen.uniform_weights(n, 0, 1000, seed=3)
+    Wd = dev(W)
+    warm = ctx.scale(Wd, sk.make_params([p], tol=0.0, max_iters=20, check_every=20))
+    ub0, vb0 = bars(warm.potentials, n, p)
+    res = ctx.scale(Wd, sk.make_params([p], tol=0.0, max_iters=2, warm_start=True, storage=storage),
+                    potentials=warm.potentials.clone())
+    assert res.report["iters_total"] == 2
+    ub2, vb2 = bars(res.potentials, n, p)
+    # the oracle's first iteration from the same start, in blocks of rows / columns
+    blk = 2048
+    ub1 = np.concatenate([oracle.row_step(oracle.log_weights(W[r:r + blk]), p, vb0)
+                          for r in range(0, n, blk)])
+    vb1 = np.concatenate([oracle.col_step(oracle.log_weights(np.ascontiguousarray(W[:, c:c + blk])), p, ub1)
+                          for c in range(0, n, blk)])
+    rng = np.random.default_rng(1)
+    rows = np.sort(rng.choice(n, 64, replace=False))
+    cols = np.sort(rng.choice(n, 64, replace=False))
+    u_or = oracle.row_step(oracle.log_weights(W[rows]), p, vb1)
+    v_or = oracle.col_step(oracle.log_weights(np.ascontiguousarray(W[:, cols])), p, ub2)
+    assert np.abs(p * (ub2[rows] - u_or)).max() < tol
+    assert np.abs(p * (vb2[cols] - v_or)).max() < tol
+
+
+def test_batched_full_size_sampled_parity(ctx):
+    """The batched workload at its full size (512 instances, n log-uniform on
+    [32, 1024], w uniform on 0..1000), a fixed 20 iterations at p = 4 in one
+    batch: sampled instances (the smallest, the largest and four others) give
+    the oracle's iterate entry by entry."""
+    ns = skgen.sizes_loguniform(512, 32, 1024, 1)
+    Ws = [skgen.uniform_weights(int(n), 0, 1000, seed=100003 + k) for k, n in enumerate(ns)]
+    p, iters = 4, 20
+    res = ctx.scale_batch([dev(W) for W in Ws], sk.make_params([p], tol=0.0, max_iters=iters,
+                                                              check_every=iters))
+    rng = np.random.default_rng(5)
+    pick = sorted({int(np.argmin(ns)), int(np.argmax(ns)), *rng.choice(512, 4, replace=False).tolist()})
+    for k in pick:
+        n = int(ns[k])
+        assert res[k].report["iters_total"] == iters
+        B = oracle.log_weights(Ws[k])
+        ub_g, vb_g = bars(res[k].potentials, n, p)
+        ub_o, vb_o, m, _ = oracle.sinkhorn(B, p, 0.0, iters)
+        assert m == iters
+        Lg, Lo = logx(B, p, ub_g, vb_g), logx(B, p, ub_o, vb_o)
+        sig = Lo > np.log(1e-6)
+        assert np.abs(Lg - Lo)[sig].max() < 1e-4, (k, n)
+
+
 # ---------------------------------------------------------------- single-pass iteration
 
 @pytest.mark.parametrize("n,p,iters", [(64, 1, 50), (1024, 8, 25), (2048, 32, 10)])

@@ -135,3 +135,22 @@ def test_completion_queue_lists_each_finished_request_once():
     res = wait_all(srv, tickets, [4096] * len(tickets))
     srv.close()
     assert all(r[2] == 1050 * 4096 for r in res)
+
+
+def test_served_largest_request_with_small_ones():
+    """The served workload's largest size, n = 8192 (planted, w uniform on
+    0..1000 with w_i sigma(i) = 1050), submitted with small requests: every
+    request returns its unique optimum sigma with the closed-form weight
+    1050 n."""
+    ns = [8192, 64, 257, 1000]
+    insts = [skgen.planted(n, seed=700 + k) for k, n in enumerate(ns)]
+    prm = sk.make_params(LADDER, tol=1e-5, max_iters=2000, check_every=32, threshold=1e-4)
+    need = sum(int(sk.lib().sk_arena_bytes(n, 0)) + 2 * n * ((n + 7) // 8 * 8) for n in ns)
+    srv = sk.Context(0, arena_bytes=need + (96 << 20))
+    tickets = [srv.submit(W, prm) for W, _ in insts]
+    res = wait_all(srv, tickets, ns)
+    for (W, sigma), n, (st, perm, weight, rep) in zip(insts, ns, res):
+        assert st == sk.SK_OK, (n, st)
+        assert weight == 1050 * n
+        assert np.array_equal(perm, sigma)
+    srv.close()
