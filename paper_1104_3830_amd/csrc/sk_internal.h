@@ -1,6 +1,7 @@
 // Internal data structures shared by the HIP kernels and the host runtime.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -174,7 +175,20 @@ struct ColUnit { int32_t inst, tile, seg, pad; };
 struct FinUnit { int32_t inst, group; };  // 64 columns of one instance
 constexpr int kFinCols = 64;
 
-// Kernel launchers (sk_kernels.hip). All enqueue on `st`.
+// Launches `kernel` on `st`. With a non-null `stop` the launch itself
+// records the event at the kernel's end (the dispatch carries the timestamp),
+// so no separate marker packet enters the stream.
+template <class F, class... Args>
+inline void launch_stamped(F kernel, dim3 grid, dim3 block, size_t lds, hipStream_t st,
+                           hipEvent_t stop, Args... args) {
+    if (stop)
+        hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)lds, st, nullptr, stop, 0u, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, lds, st, args...);
+}
+
+// Kernel launchers (sk_kernels.hip). All enqueue on `st`; `stop` (optional)
+// is recorded at the end of the launch (launch_stamped).
 hipError_t launch_init(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid, int cold,
                        hipStream_t st);
 hipError_t launch_pad_copy(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
@@ -182,12 +196,14 @@ hipError_t launch_pad_copy(const Inst *d_insts, const RowUnit *d_units, int nuni
 // short_rows: every instance of the batch has n <= kShortRowN (the row
 // sweep compiled for two workgroups per CU, sk_rowshort.hip)
 hipError_t launch_row_sweep(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
-                            size_t lds_bytes, int nt_loads, int short_rows, hipStream_t st);
+                            size_t lds_bytes, int nt_loads, int short_rows, hipStream_t st,
+                            hipEvent_t stop = nullptr);
 hipError_t launch_row_sweep_short(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
-                                  size_t lds_bytes, int nt_loads, hipStream_t st);
+                                  size_t lds_bytes, int nt_loads, hipStream_t st,
+                                  hipEvent_t stop = nullptr);
 hipError_t set_row_sweep_short_attributes();
 hipError_t launch_col_sweep(const Inst *d_insts, const ColUnit *d_units, int nunits, int grid,
-                            int nt_loads, hipStream_t st);
+                            int nt_loads, hipStream_t st, hipEvent_t stop = nullptr);
 hipError_t launch_nt_product(const Inst *d_insts, const RowUnit *d_rows, int nrows, int row_grid,
                              size_t row_lds, const ColUnit *d_cols, int ncols, int col_grid,
                              const NtCtl *nt, NtVec vec, int n, int nt_loads, hipStream_t st);
@@ -195,7 +211,8 @@ hipError_t launch_nt_product(const Inst *d_insts, const RowUnit *d_rows, int nro
 hipError_t launch_nt_step(const Inst *d_insts, NtCtl *nt, NtVec vec, int n, hipStream_t st);
 hipError_t launch_nt_fold(const Inst *d_insts, const NtCtl *nt, NtVec vec, int n, int last,
                           hipStream_t st);
-hipError_t launch_iter_end(const Inst *d_insts, int count, hipStream_t st);
+hipError_t launch_iter_end(const Inst *d_insts, int count, hipStream_t st,
+                           hipEvent_t stop = nullptr);
 enum : int { kFinOnePass = 1, kFinStoredK = 2 };
 hipError_t launch_col_finalize(const Inst *d_insts, const FinUnit *d_units, int nunits, int grid,
                                int mode, hipStream_t st);

@@ -1527,24 +1527,26 @@ hipError_t launch_pad_copy(const Inst *d_insts, const RowUnit *d_units, int nuni
     return hipGetLastError();
 }
 hipError_t launch_row_sweep(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
-                            size_t lds_bytes, int nt_loads, int short_rows, hipStream_t st) {
-    if (short_rows) return launch_row_sweep_short(d_insts, d_units, nunits, grid, lds_bytes, nt_loads, st);
+                            size_t lds_bytes, int nt_loads, int short_rows, hipStream_t st,
+                            hipEvent_t stop) {
+    if (short_rows)
+        return launch_row_sweep_short(d_insts, d_units, nunits, grid, lds_bytes, nt_loads, st, stop);
     if (nt_loads)
-        hipLaunchKernelGGL((k_row_sweep<true, 1>), dim3(grid), dim3(kRowWaves * kWave), lds_bytes, st,
-                           d_insts, d_units, nunits);
+        launch_stamped(k_row_sweep<true, 1>, dim3(grid), dim3(kRowWaves * kWave), lds_bytes, st, stop,
+                       d_insts, d_units, nunits);
     else
-        hipLaunchKernelGGL((k_row_sweep<false, 1>), dim3(grid), dim3(kRowWaves * kWave), lds_bytes, st,
-                           d_insts, d_units, nunits);
+        launch_stamped(k_row_sweep<false, 1>, dim3(grid), dim3(kRowWaves * kWave), lds_bytes, st, stop,
+                       d_insts, d_units, nunits);
     return hipGetLastError();
 }
 hipError_t launch_col_sweep(const Inst *d_insts, const ColUnit *d_units, int nunits, int grid,
-                            int nt_loads, hipStream_t st) {
+                            int nt_loads, hipStream_t st, hipEvent_t stop) {
     if (nt_loads)
-        hipLaunchKernelGGL(k_col_sweep<true>, dim3(grid), dim3(kColWaves * kWave), 0, st, d_insts,
-                           d_units, nunits);
+        launch_stamped(k_col_sweep<true>, dim3(grid), dim3(kColWaves * kWave), 0, st, stop, d_insts,
+                       d_units, nunits);
     else
-        hipLaunchKernelGGL(k_col_sweep<false>, dim3(grid), dim3(kColWaves * kWave), 0, st, d_insts,
-                           d_units, nunits);
+        launch_stamped(k_col_sweep<false>, dim3(grid), dim3(kColWaves * kWave), 0, st, stop, d_insts,
+                       d_units, nunits);
     return hipGetLastError();
 }
 hipError_t launch_col_finalize(const Inst *d_insts, const FinUnit *d_units, int nunits, int grid,
@@ -1582,8 +1584,8 @@ hipError_t launch_nt_fold(const Inst *d_insts, const NtCtl *nt, NtVec vec, int n
                        last);
     return hipGetLastError();
 }
-hipError_t launch_iter_end(const Inst *d_insts, int count, hipStream_t st) {
-    hipLaunchKernelGGL(k_iter_end, dim3(count), dim3(kIterEndThreads), 0, st, d_insts);
+hipError_t launch_iter_end(const Inst *d_insts, int count, hipStream_t st, hipEvent_t stop) {
+    launch_stamped(k_iter_end, dim3(count), dim3(kIterEndThreads), 0, st, stop, d_insts);
     return hipGetLastError();
 }
 hipError_t launch_check_rows(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,

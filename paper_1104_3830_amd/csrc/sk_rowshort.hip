@@ -7,13 +7,13 @@
 namespace sk {
 
 hipError_t launch_row_sweep_short(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
-                                  size_t lds_bytes, int nt_loads, hipStream_t st) {
+                                  size_t lds_bytes, int nt_loads, hipStream_t st, hipEvent_t stop) {
     if (nt_loads)
-        hipLaunchKernelGGL((k_row_sweep<true, 8>), dim3(grid), dim3(kRowWaves * kWave), lds_bytes, st,
-                           d_insts, d_units, nunits);
+        launch_stamped(k_row_sweep<true, 8>, dim3(grid), dim3(kRowWaves * kWave), lds_bytes, st, stop,
+                       d_insts, d_units, nunits);
     else
-        hipLaunchKernelGGL((k_row_sweep<false, 8>), dim3(grid), dim3(kRowWaves * kWave), lds_bytes, st,
-                           d_insts, d_units, nunits);
+        launch_stamped(k_row_sweep<false, 8>, dim3(grid), dim3(kRowWaves * kWave), lds_bytes, st, stop,
+                       d_insts, d_units, nunits);
     return hipGetLastError();
 }
 

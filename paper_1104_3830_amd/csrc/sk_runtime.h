@@ -78,10 +78,14 @@ enum KernelId {
 };
 extern const char *kKernelNames[KID_COUNT];
 
-// HIP-event timing of launches on the context stream. Each recorded event
-// is a stamp; a timed launch is the interval between two stamps, and
-// back-to-back launches share the stamp between them (each stamp is a
-// timestamp packet in the stream, so fewer stamps cost the stream less).
+// HIP-event timing of launches on the context stream. Each event is a
+// stamp; a timed launch is the interval between two stamps, and back-to-back
+// launches share the stamp between them. A stamp is either a marker packet
+// in the stream (stamp()) or an event that a launch records at its own end
+// (kernel_stamp(), passed to launch_stamped): the latter adds no packet, so it
+// costs the stream less and a launch timed from the previous launch's end
+// stamp to its own is timed without any marker latency. Events are created
+// without the system-scope fence (they time launches and order nothing).
 struct Profiler {
     bool on = false;
     std::vector<hipEvent_t> stamps;
@@ -90,7 +94,10 @@ struct Profiler {
     int64_t launches[KID_COUNT] = {};
     double total_ms[KID_COUNT] = {};
     hipEvent_t take();
-    int stamp(hipStream_t st);                // index of a new stamp, -1 when off
+    int stamp(hipStream_t st);                // index of a new marker stamp, -1 when off
+    // An event for a launch to record at its end (nullptr when off); its
+    // stamp index goes to *idx (-1 when off).
+    hipEvent_t kernel_stamp(int *idx);
     void add(int id, int from, int to);       // launch `id` ran between two stamps
     void begin(hipStream_t st, int id);
     void end(hipStream_t st);
@@ -110,6 +117,7 @@ struct Profiler {
     ~Profiler();
     int cur_id = -1;
     int cur_start = -1;
+    int iter_end_stamp = -1;  // end stamp of the last end-of-iteration launch
 };
 
 }  // namespace sk
@@ -125,6 +133,8 @@ struct sk_ctx {
     sk::Ctl *h_ctl = nullptr;      // pinned readback of control blocks
     double *h_checkout = nullptr;  // pinned readback of reduced checks [kMaxBatch][4]
     int64_t *h_nnz = nullptr;      // pinned readback of kept counts [kMaxBatch]
+    char *h_csr = nullptr;         // pinned host copy of sk_solve's reduced matrix (grown on demand)
+    size_t h_csr_bytes = 0;
     sk::Batch scratch_batch;
     int absorbs = 0;
     double k_res_rows = 0, k_res_cols = 0;
@@ -164,7 +174,9 @@ sk_status plan_batch(sk_ctx *ctx, Bump &bump, int count, const int16_t *const *W
 sk_status upload_batch(sk_ctx *ctx, Batch &B);
 sk_status start_batch(sk_ctx *ctx, Batch &B, const sk_params *prm, void *const *pot_in);
 sk_status read_ctl(sk_ctx *ctx, Batch &B);
-sk_status iterate_i16(sk_ctx *ctx, Batch &B);
+// chained: the previous launch on the stream is the end-of-iteration launch
+// of the previous call (timing then starts from that launch's end stamp).
+sk_status iterate_i16(sk_ctx *ctx, Batch &B, bool chained = false);
 // Iterates until no instance is running (done, error, or paused at a stage
 // end); first_stage: the stage the instances start this call in (launch tags).
 sk_status run_batch_i16(sk_ctx *ctx, Batch &B, const sk_params *prm, int first_stage = 0);

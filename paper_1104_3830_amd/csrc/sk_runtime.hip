@@ -113,7 +113,16 @@ hipEvent_t Profiler::take() {
         return e;
     }
     hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
+    return e;
+}
+hipEvent_t Profiler::kernel_stamp(int *idx) {
+    *idx = -1;
+    if (!on) return nullptr;
+    hipEvent_t e = take();
+    if (!e) return nullptr;
+    stamps.push_back(e);
+    *idx = (int)stamps.size() - 1;
     return e;
 }
 int Profiler::stamp(hipStream_t st) {
@@ -152,6 +161,7 @@ void Profiler::drain() {
     stamps.clear();
     pending.clear();
     cur_start = -1;
+    iter_end_stamp = -1;
 }
 void Profiler::reset() {
     drain();
@@ -272,6 +282,7 @@ sk_status sk_destroy(sk_ctx *ctx) {
     if (ctx->h_ctl) (void)hipHostFree(ctx->h_ctl);
     if (ctx->h_checkout) (void)hipHostFree(ctx->h_checkout);
     if (ctx->h_nnz) (void)hipHostFree(ctx->h_nnz);
+    if (ctx->h_csr) (void)hipHostFree(ctx->h_csr);
     delete ctx;
     return SK_OK;
 }
@@ -492,7 +503,8 @@ sk_status sk::read_ctl(sk_ctx *ctx, Batch &B) {
 }
 
 // One Sinkhorn iteration over every running instance of the batch.
-sk_status sk::iterate_i16(sk_ctx *ctx, Batch &B) {
+sk_status sk::iterate_i16(sk_ctx *ctx, Batch &B, bool chained) {
+    Profiler &pf = ctx->prof;
     if (B.count == 1 && B.h_insts[0].fused) {
         const Inst &I = B.h_insts[0];
         HIPCHK(ctx, PROF(ctx, KID_FUSED, launch_fused(B.d_insts, 0, I.n, I.fused_grid, SK_W_I16,
@@ -500,24 +512,29 @@ sk_status sk::iterate_i16(sk_ctx *ctx, Batch &B) {
         HIPCHK(ctx, launch_col_finalize(B.d_insts, B.d_fins, (int)B.h_fins.size(), B.fin_grid,
                                         kFinOnePass, ctx->stream));
         HIPCHK(ctx, launch_iter_end(B.d_insts, B.count, ctx->stream));
+        pf.iter_end_stamp = -1;
         return SK_OK;
     }
-    // timed: the two sweeps, with one stamp between them; the short
-    // finalise and end-of-iteration launches are not stamped
-    Profiler &pf = ctx->prof;
-    const int s0 = pf.stamp(ctx->stream);
+    // timed: the two sweeps. Each sweep and the end-of-iteration launch
+    // record their own end stamps; the row sweep is timed from the previous
+    // iteration's end stamp when this call follows it directly, else from a
+    // marker. The short finalise launch between is not stamped.
+    const int s0 = chained && pf.iter_end_stamp >= 0 ? pf.iter_end_stamp : pf.stamp(ctx->stream);
     const int nt = B.count > 0 ? B.h_insts[0].nt : 0;  // the same for the whole batch
+    int s1, s2, s3;
+    hipEvent_t e1 = pf.kernel_stamp(&s1);
     HIPCHK(ctx, launch_row_sweep(B.d_insts, B.d_rows, (int)B.h_rows.size(), B.row_grid, B.row_lds,
-                                 nt, B.nmax <= kShortRowN, ctx->stream));
-    const int s1 = pf.stamp(ctx->stream);
+                                 nt, B.nmax <= kShortRowN, ctx->stream, e1));
+    hipEvent_t e2 = pf.kernel_stamp(&s2);
     HIPCHK(ctx, launch_col_sweep(B.d_insts, B.d_cols, (int)B.h_cols.size(), B.col_grid, nt,
-                                 ctx->stream));
-    const int s2 = pf.stamp(ctx->stream);
+                                 ctx->stream, e2));
     pf.add(KID_ROW, s0, s1);
     pf.add(KID_COL, s1, s2);
     HIPCHK(ctx, launch_col_finalize(B.d_insts, B.d_fins, (int)B.h_fins.size(), B.fin_grid, 0,
                                     ctx->stream));
-    HIPCHK(ctx, launch_iter_end(B.d_insts, B.count, ctx->stream));
+    hipEvent_t e3 = pf.kernel_stamp(&s3);
+    HIPCHK(ctx, launch_iter_end(B.d_insts, B.count, ctx->stream, e3));
+    pf.iter_end_stamp = s3;
     return SK_OK;
 }
 
@@ -542,7 +559,7 @@ sk_status sk::run_batch_i16(sk_ctx *ctx, Batch &B, const sk_params *prm, int fir
                                                 4, ctx->h_ctl[0].stage_iters[first_stage - 1] + 2));
     for (;;) {
         for (int k = 0; k < blk; ++k) {
-            sk_status s = iterate_i16(ctx, B);
+            sk_status s = iterate_i16(ctx, B, k > 0);
             if (s != SK_OK) return s;
         }
         launched += blk;

@@ -50,9 +50,24 @@ sk_status reduce_and_solve(sk_ctx *ctx, Batch &B, Bump &rest, int64_t *d_rp, con
         HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     }
     const int64_t nnz = ctx->h_nnz[0];
-    std::vector<int64_t> rp((size_t)n + 1);
-    std::vector<int32_t> col((size_t)nnz), hint((size_t)n);
-    std::vector<int16_t> w((size_t)nnz);
+    // the host copy goes to pinned memory kept by the context: one DMA per
+    // array, and no fresh pages to fault in on every call
+    const size_t o_hint = align_up(sizeof(int64_t) * ((size_t)n + 1), 256);
+    const size_t o_col = o_hint + align_up(sizeof(int32_t) * (size_t)n, 256);
+    const size_t o_w = o_col + align_up(sizeof(int32_t) * (size_t)nnz, 256);
+    const size_t need = o_w + align_up(sizeof(int16_t) * (size_t)nnz, 256);
+    if (need > ctx->h_csr_bytes) {
+        if (ctx->h_csr) HIPCHK(ctx, hipHostFree(ctx->h_csr));
+        ctx->h_csr = nullptr;
+        ctx->h_csr_bytes = 0;
+        const size_t bytes = std::max(need, need / 2 * 3);  // room to grow
+        HIPCHK(ctx, hipHostMalloc((void **)&ctx->h_csr, bytes, hipHostMallocDefault));
+        ctx->h_csr_bytes = bytes;
+    }
+    int64_t *rp = reinterpret_cast<int64_t *>(ctx->h_csr);
+    int32_t *hint = reinterpret_cast<int32_t *>(ctx->h_csr + o_hint);
+    int32_t *col = reinterpret_cast<int32_t *>(ctx->h_csr + o_col);
+    int16_t *w = reinterpret_cast<int16_t *>(ctx->h_csr + o_w);
     if (nnz > 0) {
         Bump tmp = rest;  // the entries are scratch until copied out
         int32_t *d_col = tmp.take<int32_t>((size_t)nnz);
@@ -62,21 +77,21 @@ sk_status reduce_and_solve(sk_ctx *ctx, Batch &B, Bump &rest, int64_t *d_rp, con
                         (long long)nnz);
         HIPCHK(ctx, PROF(ctx, KID_PRUNE_FILL, launch_prune_fill(B.d_insts, B.d_rows, nunits, B.row_grid,
                                                                logt, d_rp, d_col, d_w, lds, ctx->stream)));
-        HIPCHK(ctx, hipMemcpyAsync(col.data(), d_col, sizeof(int32_t) * (size_t)nnz,
+        HIPCHK(ctx, hipMemcpyAsync(col, d_col, sizeof(int32_t) * (size_t)nnz,
                                    hipMemcpyDeviceToHost, ctx->stream));
-        HIPCHK(ctx, hipMemcpyAsync(w.data(), d_w, sizeof(int16_t) * (size_t)nnz, hipMemcpyDeviceToHost,
+        HIPCHK(ctx, hipMemcpyAsync(w, d_w, sizeof(int16_t) * (size_t)nnz, hipMemcpyDeviceToHost,
                                    ctx->stream));
     }
-    HIPCHK(ctx, hipMemcpyAsync(rp.data(), d_rp, sizeof(int64_t) * ((size_t)n + 1),
+    HIPCHK(ctx, hipMemcpyAsync(rp, d_rp, sizeof(int64_t) * ((size_t)n + 1),
                                hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(ctx, hipMemcpyAsync(hint.data(), d_hint, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost,
+    HIPCHK(ctx, hipMemcpyAsync(hint, d_hint, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost,
                                ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-    sk_csr csr{n, nnz, rp.data(), col.data(), w.data()};
+    sk_csr csr{n, nnz, rp, col, w};
     r.perm.assign((size_t)n, -1);
     r.t = t;
     r.nnz = nnz;
-    const sk_status s = solve_reduced_seeded(&csr, hint.data(), r.perm.data(), &r.weight);
+    const sk_status s = solve_reduced_seeded(&csr, hint, r.perm.data(), &r.weight);
     if (s == SK_EINFEASIBLE) {
         r.feasible = false;
         return SK_OK;
