@@ -355,6 +355,50 @@ __device__ __forceinline__ float row_step_pair(const Inst &I, int ra, int rb, in
 // Column potentials of the padding columns n..pad8(n)-1 of the 8-wide layout
 // (a separate loop, so that the staging of the real columns keeps its loads
 // unconditional and in flight together).
+// Stages (4 G_j, exp(gam_j)) of every column of I into LDS (swizzled for the
+// 8-wide loads when I.vec8). Each thread takes 16 consecutive columns and
+// issues all of their loads before it uses any, so the staging costs one
+// memory round trip per thread rather than one per column; the columns past
+// the last full group of 16 (all of them when the vectors are not 16-byte
+// aligned) go one per thread. Every value is the one the per-column form
+// computes.
+__device__ __forceinline__ void stage_col_pots(const Inst &I, ColPot *cp, int n8) {
+    const int n = I.n;
+    const int t = (int)threadIdx.x, nt = (int)blockDim.x;
+    int tail = 0;
+    if (((reinterpret_cast<uintptr_t>(I.G) | reinterpret_cast<uintptr_t>(I.gam)) & 15) == 0) {
+        for (int j0 = 16 * t; j0 + 16 <= n; j0 += 16 * nt) {
+            int4 g[4];
+            float4 m[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                g[k] = *reinterpret_cast<const int4 *>(I.G + j0 + 4 * k);
+                m[k] = *reinterpret_cast<const float4 *>(I.gam + j0 + 4 * k);
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int gk[4] = {g[k].x, g[k].y, g[k].z, g[k].w};
+                const float mk[4] = {m[k].x, m[k].y, m[k].z, m[k].w};
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int j = j0 + 4 * k + c;
+                    ColPot v;
+                    v.a = 4 * gk[c];
+                    v.g = ex2(mk[c] * kLog2e);
+                    cp[I.vec8 ? swz8(j, n8) : j] = v;
+                }
+            }
+        }
+        tail = n & ~15;
+    }
+    for (int j = tail + t; j < n; j += nt) {
+        ColPot v;
+        v.a = 4 * I.G[j];
+        v.g = ex2(I.gam[j] * kLog2e);
+        cp[I.vec8 ? swz8(j, n8) : j] = v;
+    }
+}
+
 __device__ __forceinline__ void stage_pad_cols(const Inst &I, ColPot *cp, int n8) {
     if (!I.vec8) return;
     for (int j = I.n + (int)threadIdx.x; j < 8 * n8; j += blockDim.x) {
@@ -414,12 +458,7 @@ __global__ __launch_bounds__(kRowWaves * kWave, MINW) void k_row_sweep(const Ins
             flush();
             __syncthreads();
             const int n8 = pad8(n) >> 3;
-            for (int j = threadIdx.x; j < n; j += blockDim.x) {
-                ColPot k;
-                k.a = 4 * I.G[j];
-                k.g = ex2(I.gam[j] * kLog2e);
-                lds_cp[I.vec8 ? swz8(j, n8) : j] = k;
-            }
+            stage_col_pots(I, lds_cp, n8);
             stage_pad_cols(I, lds_cp, n8);
             __syncthreads();
             cur = un.inst;
