@@ -151,6 +151,52 @@ sk_status sk::solve_reduced_seeded(const sk_csr *csr, const int32_t *hint, int32
                     break;
                 }
         }
+        // Free rows one at a time: a breadth-first search over alternating
+        // tight paths that stops at the first free column it reaches, then
+        // flips that path. On sparse instances the paths are short and each
+        // search looks at few edges; the searches share a budget of edge
+        // visits, and whatever is still free when it runs out (or has no
+        // tight augmenting path) goes to Hopcroft-Karp below, which keeps
+        // the worst case at O(m sqrt(n)) plus the budget.
+        {
+            std::vector<int32_t> seen(n, -1);  // free row whose search reached column j
+            std::vector<int32_t> via_row(n);   // row from which column j was reached
+            std::vector<int64_t> via_e(n);     // and the CSR position of that edge
+            std::vector<int32_t> fq;
+            fq.reserve(n);
+            int64_t budget = 4 * (csr->nnz + n);
+            for (int s = 0; s < n && budget > 0; ++s) {
+                if (col_of[s] >= 0) continue;
+                fq.clear();
+                fq.push_back(s);
+                int found = -1;
+                for (size_t h = 0; h < fq.size() && found < 0; ++h) {
+                    const int i = fq[h];
+                    budget -= tp[i + 1] - tp[i];
+                    for (int64_t e = tp[i]; e < tp[i + 1]; ++e) {
+                        const int j = tc[e];
+                        if (seen[j] == s || !tight(i, e)) continue;
+                        seen[j] = s;
+                        via_row[j] = i;
+                        via_e[j] = e;
+                        if (row_of[j] < 0) {
+                            found = j;
+                            break;
+                        }
+                        fq.push_back(row_of[j]);
+                    }
+                }
+                for (int j = found; j >= 0;) {  // flip the path back to s
+                    const int i = via_row[j];
+                    const int prev = col_of[i];
+                    row_of[j] = i;
+                    col_of[i] = j;
+                    mpos[i] = via_e[j];
+                    if (i == s) break;
+                    j = prev;
+                }
+            }
+        }
         const int NIL = std::numeric_limits<int>::max();
         std::vector<int> dist(n), q(n), stack;
         std::vector<int64_t> it(n);

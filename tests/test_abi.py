@@ -185,3 +185,54 @@ def test_arena_sizes_include_the_padded_copy():
     assert one(1008) - one(1000) < copy // 4
     two = L.sk_batch_arena_bytes(2, (ctypes.c_int32 * 2)(1001, 37), 0)
     assert two - L.sk_batch_arena_bytes(2, (ctypes.c_int32 * 2)(1000, 40), 0) >= copy + 2 * 37 * 40
+
+
+def _budget_instance():
+    """Row block A (1200 rows) complete onto 600 columns at weight 100, each
+    A row also reaching a column of its own at weight 0; 600 rows B each
+    reaching the own columns of two A rows at weight 50. After the row and
+    column reductions the tight edges are A x (600 columns) and the B edges,
+    so 600 A rows are left free and every search from one of them visits the
+    whole A block without finding a free column."""
+    k = 1200
+    n = k + k // 2
+    w = np.zeros((n, n), np.int64)
+    mask = np.zeros((n, n), bool)
+    mask[:k, : k // 2] = True
+    w[:k, : k // 2] = 100
+    own = k // 2 + np.arange(k)
+    mask[np.arange(k), own] = True
+    for t in range(k // 2):
+        for c in (own[2 * t], own[2 * t + 1]):
+            mask[k + t, c] = True
+            w[k + t, c] = 50
+    return n, w, mask
+
+
+def test_solve_reduced_when_searches_exhaust_their_budget():
+    """Single-row augmenting searches that fail on the tight graph use up
+    their shared budget; the rest of the matching goes to Hopcroft-Karp and
+    the shortest-path augmentations, and the optimum is still exact
+    (600*100 + 600*50)."""
+    n, w, mask = _budget_instance()
+    rp, cols, ww = _csr(mask, w)
+    perm, weight = sk.solve_reduced(rp, cols, ww, n)
+    _, w_or = oracle.hungarian(w, mask)
+    assert weight == w_or == 600 * 100 + 600 * 50
+    assert sorted(perm) == list(range(n)) and mask[np.arange(n), perm].all()
+
+
+def test_solve_reduced_all_tight_random_graph():
+    """Every entry has the same weight, so every edge is tight and the
+    matching is found by the augmenting searches alone: a random graph of 8
+    entries per row plus a planted permutation (a perfect matching exists)."""
+    rng = np.random.default_rng(5)
+    n = 4000
+    mask = np.zeros((n, n), bool)
+    mask[np.repeat(np.arange(n), 8), rng.integers(0, n, 8 * n)] = True
+    mask[np.arange(n), rng.permutation(n)] = True
+    w = np.full((n, n), 1000, np.int64)
+    rp, cols, ww = _csr(mask, w)
+    perm, weight = sk.solve_reduced(rp, cols, ww, n)
+    assert weight == 1000 * n
+    assert sorted(perm) == list(range(n)) and mask[np.arange(n), perm].all()
