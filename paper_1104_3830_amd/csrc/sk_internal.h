@@ -195,12 +195,14 @@ hipError_t launch_pad_copy(const Inst *d_insts, const RowUnit *d_units, int nuni
                            hipStream_t st);
 // short_rows: every instance of the batch has n <= kShortRowN (the row
 // sweep compiled for two workgroups per CU, sk_rowshort.hip)
-hipError_t launch_row_sweep(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
-                            size_t lds_bytes, int nt_loads, int short_rows, hipStream_t st,
-                            hipEvent_t stop = nullptr);
-hipError_t launch_row_sweep_short(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
-                                  size_t lds_bytes, int nt_loads, hipStream_t st,
-                                  hipEvent_t stop = nullptr);
+// bounds (device, grid + 1 entries, or nullptr for an even split by count):
+// workgroup b sweeps the units [bounds[b], bounds[b + 1]).
+hipError_t launch_row_sweep(const Inst *d_insts, const RowUnit *d_units, int nunits,
+                            const int32_t *bounds, int grid, size_t lds_bytes, int nt_loads,
+                            int short_rows, hipStream_t st, hipEvent_t stop = nullptr);
+hipError_t launch_row_sweep_short(const Inst *d_insts, const RowUnit *d_units, int nunits,
+                                  const int32_t *bounds, int grid, size_t lds_bytes, int nt_loads,
+                                  hipStream_t st, hipEvent_t stop = nullptr);
 hipError_t set_row_sweep_short_attributes();
 hipError_t launch_col_sweep(const Inst *d_insts, const ColUnit *d_units, int nunits, int grid,
                             int nt_loads, hipStream_t st, hipEvent_t stop = nullptr);

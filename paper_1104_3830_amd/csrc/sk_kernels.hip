@@ -1526,17 +1526,18 @@ hipError_t launch_pad_copy(const Inst *d_insts, const RowUnit *d_units, int nuni
                        nunits);
     return hipGetLastError();
 }
-hipError_t launch_row_sweep(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
-                            size_t lds_bytes, int nt_loads, int short_rows, hipStream_t st,
-                            hipEvent_t stop) {
+hipError_t launch_row_sweep(const Inst *d_insts, const RowUnit *d_units, int nunits,
+                            const int32_t *bounds, int grid, size_t lds_bytes, int nt_loads,
+                            int short_rows, hipStream_t st, hipEvent_t stop) {
     if (short_rows)
-        return launch_row_sweep_short(d_insts, d_units, nunits, grid, lds_bytes, nt_loads, st, stop);
+        return launch_row_sweep_short(d_insts, d_units, nunits, bounds, grid, lds_bytes, nt_loads, st,
+                                      stop);
     if (nt_loads)
         launch_stamped(k_row_sweep<true, 1>, dim3(grid), dim3(kRowWaves * kWave), lds_bytes, st, stop,
-                       d_insts, d_units, nunits);
+                       d_insts, d_units, nunits, bounds);
     else
         launch_stamped(k_row_sweep<false, 1>, dim3(grid), dim3(kRowWaves * kWave), lds_bytes, st, stop,
-                       d_insts, d_units, nunits);
+                       d_insts, d_units, nunits, bounds);
     return hipGetLastError();
 }
 hipError_t launch_col_sweep(const Inst *d_insts, const ColUnit *d_units, int nunits, int grid,

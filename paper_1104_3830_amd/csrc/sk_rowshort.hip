@@ -6,14 +6,15 @@
 
 namespace sk {
 
-hipError_t launch_row_sweep_short(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
-                                  size_t lds_bytes, int nt_loads, hipStream_t st, hipEvent_t stop) {
+hipError_t launch_row_sweep_short(const Inst *d_insts, const RowUnit *d_units, int nunits,
+                                  const int32_t *bounds, int grid, size_t lds_bytes, int nt_loads,
+                                  hipStream_t st, hipEvent_t stop) {
     if (nt_loads)
         launch_stamped(k_row_sweep<true, 8>, dim3(grid), dim3(kRowWaves * kWave), lds_bytes, st, stop,
-                       d_insts, d_units, nunits);
+                       d_insts, d_units, nunits, bounds);
     else
         launch_stamped(k_row_sweep<false, 8>, dim3(grid), dim3(kRowWaves * kWave), lds_bytes, st, stop,
-                       d_insts, d_units, nunits);
+                       d_insts, d_units, nunits, bounds);
     return hipGetLastError();
 }
 

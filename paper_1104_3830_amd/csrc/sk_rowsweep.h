@@ -356,17 +356,20 @@ __device__ __forceinline__ float row_step_pair(const Inst &I, int ra, int rb, in
 // (a separate loop, so that the staging of the real columns keeps its loads
 // unconditional and in flight together).
 // Stages (4 G_j, exp(gam_j)) of every column of I into LDS (swizzled for the
-// 8-wide loads when I.vec8). Each thread takes 16 consecutive columns and
+// 8-wide loads when I.vec8). With WIDE, each thread takes 16 consecutive columns and
 // issues all of their loads before it uses any, so the staging costs one
 // memory round trip per thread rather than one per column; the columns past
 // the last full group of 16 (all of them when the vectors are not 16-byte
 // aligned) go one per thread. Every value is the one the per-column form
 // computes.
+// WIDE: the 16-column groups are compiled in (the long-row build; the
+// short-row build, at 64 registers, stages one column per thread).
+template <bool WIDE>
 __device__ __forceinline__ void stage_col_pots(const Inst &I, ColPot *cp, int n8) {
     const int n = I.n;
     const int t = (int)threadIdx.x, nt = (int)blockDim.x;
     int tail = 0;
-    if (((reinterpret_cast<uintptr_t>(I.G) | reinterpret_cast<uintptr_t>(I.gam)) & 15) == 0) {
+    if (WIDE && ((reinterpret_cast<uintptr_t>(I.G) | reinterpret_cast<uintptr_t>(I.gam)) & 15) == 0) {
         for (int j0 = 16 * t; j0 + 16 <= n; j0 += 16 * nt) {
             int4 g[4];
             float4 m[4];
@@ -423,12 +426,20 @@ __device__ __forceinline__ void stage_pad_cols(const Inst &I, ColPot *cp, int n8
 template <bool NT, int MINW>
 __global__ __launch_bounds__(kRowWaves * kWave, MINW) void k_row_sweep(const Inst *__restrict__ insts,
                                                                    const RowUnit *__restrict__ units,
-                                                                   int nunits) {
+                                                                   int nunits,
+                                                                   const int32_t *__restrict__ bounds) {
     extern __shared__ ColPot lds_cp[];
     __shared__ float tab[kTabN];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    // the workgroup's units: [bounds[b], bounds[b + 1]) (a split by cost
+    // planned on the host), or an even split by count without bounds
     int u0, u1;
-    unit_range(nunits, u0, u1);
+    if (bounds) {
+        u0 = bounds[blockIdx.x];
+        u1 = bounds[blockIdx.x + 1];
+    } else {
+        unit_range(nunits, u0, u1);
+    }
     __shared__ unsigned wg_res, wg_done;
     if (threadIdx.x == 0) {
         wg_res = 0u;
@@ -458,7 +469,7 @@ __global__ __launch_bounds__(kRowWaves * kWave, MINW) void k_row_sweep(const Ins
             flush();
             __syncthreads();
             const int n8 = pad8(n) >> 3;
-            stage_col_pots(I, lds_cp, n8);
+            stage_col_pots<MINW == 1>(I, lds_cp, n8);
             stage_pad_cols(I, lds_cp, n8);
             __syncthreads();
             cur = un.inst;

@@ -33,6 +33,8 @@ struct Batch {
     std::vector<FinUnit> h_fins;
     Inst *d_insts = nullptr;
     RowUnit *d_rows = nullptr;
+    std::vector<int32_t> h_row_bounds;  // row sweep: units of workgroup b are [b], [b + 1]
+    int32_t *d_row_bounds = nullptr;
     ColUnit *d_cols = nullptr;
     FinUnit *d_fins = nullptr;
     double *d_rsum = nullptr, *d_rmax = nullptr, *d_csum = nullptr;

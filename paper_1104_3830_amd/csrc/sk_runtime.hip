@@ -13,6 +13,18 @@
 #include "sk_internal.h"
 #include "sk_runtime.h"
 
+// Cost model of the row-sweep split (build-time tuning knobs; see
+// finish_tables).
+#ifndef SK_BAL_RT_COLS
+#define SK_BAL_RT_COLS 512
+#endif
+#ifndef SK_BAL_UNIT
+#define SK_BAL_UNIT 0
+#endif
+#ifndef SK_BAL_STAGE
+#define SK_BAL_STAGE 0
+#endif
+
 namespace sk {
 
 // ---------------------------------------------------------------- planning
@@ -435,6 +447,38 @@ sk_status sk::finish_tables(sk_ctx *ctx, Bump &bump, Batch &B) {
     B.row_grid = (int)std::max<size_t>(1, std::min<size_t>(B.h_rows.size(), (size_t)ctx->num_cus * per_cu));
     const int per_cu_k = B.row_lds_k <= 65536 ? 2 : 1;
     B.row_grid_k = (int)std::max<size_t>(1, std::min<size_t>(B.h_rows.size(), (size_t)ctx->num_cus * per_cu_k));
+    // Row-sweep ranges: contiguous runs of row units of about equal cost, so
+    // that a batch of mixed sizes does not wait on the workgroups that drew
+    // the large instances (an even split by count ran the 512-instance batch
+    // of n in [32, 1024] 24% slower). Costs in hundredths of a step: a unit
+    // (one row per wave) takes one step per SK_BAL_RT_COLS columns of its
+    // rows (one 16-byte load per lane covers 512) plus SK_BAL_UNIT, and the
+    // first unit of an instance also SK_BAL_STAGE for the staging of the
+    // instance's column data; the defaults were chosen by timing that batch.
+    // Integer costs: equal units split exactly evenly.
+    {
+        const size_t nu = B.h_rows.size();
+        const int g = B.row_grid;
+        std::vector<int64_t> cost(nu);
+        int64_t total = 0;
+        for (size_t q = 0; q < nu; ++q) {
+            const int64_t nn = B.h_insts[B.h_rows[q].inst].n;
+            int64_t c = 100 * ((nn + SK_BAL_RT_COLS - 1) / SK_BAL_RT_COLS) + SK_BAL_UNIT;
+            if (q == 0 || B.h_rows[q - 1].inst != B.h_rows[q].inst) c += SK_BAL_STAGE;
+            cost[q] = c;
+            total += c;
+        }
+        B.h_row_bounds.assign((size_t)g + 1, (int32_t)nu);
+        B.h_row_bounds[0] = 0;
+        int b = 0;
+        int64_t acc = 0;
+        for (size_t q = 0; q < nu && b + 1 < g; ++q) {
+            acc += cost[q];
+            while (b + 1 < g && acc * g >= total * (b + 1)) B.h_row_bounds[++b] = (int32_t)(q + 1);
+        }
+        B.d_row_bounds = bump.take<int32_t>((size_t)g + 1);
+        if (!B.d_row_bounds) return fail(ctx, SK_ENOMEM, "arena too small for the batch tables");
+    }
     B.col_grid = (int)std::max<size_t>(1, std::min<size_t>(B.h_cols.size(), (size_t)ctx->num_cus * 8));
     B.fin_grid = (int)std::max<size_t>(1, std::min<size_t>(B.h_fins.size(), (size_t)ctx->num_cus * 4));
     return SK_OK;
@@ -455,6 +499,9 @@ sk_status sk::upload_batch(sk_ctx *ctx, Batch &B) {
                                hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(ctx, hipMemcpyAsync(B.d_rows, B.h_rows.data(), sizeof(RowUnit) * B.h_rows.size(),
                                hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(B.d_row_bounds, B.h_row_bounds.data(),
+                               sizeof(int32_t) * B.h_row_bounds.size(), hipMemcpyHostToDevice,
+                               ctx->stream));
     HIPCHK(ctx, hipMemcpyAsync(B.d_cols, B.h_cols.data(), sizeof(ColUnit) * B.h_cols.size(),
                                hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(ctx, hipMemcpyAsync(B.d_fins, B.h_fins.data(), sizeof(FinUnit) * B.h_fins.size(),
@@ -523,8 +570,8 @@ sk_status sk::iterate_i16(sk_ctx *ctx, Batch &B, bool chained) {
     const int nt = B.count > 0 ? B.h_insts[0].nt : 0;  // the same for the whole batch
     int s1, s2, s3;
     hipEvent_t e1 = pf.kernel_stamp(&s1);
-    HIPCHK(ctx, launch_row_sweep(B.d_insts, B.d_rows, (int)B.h_rows.size(), B.row_grid, B.row_lds,
-                                 nt, B.nmax <= kShortRowN, ctx->stream, e1));
+    HIPCHK(ctx, launch_row_sweep(B.d_insts, B.d_rows, (int)B.h_rows.size(), B.d_row_bounds,
+                                 B.row_grid, B.row_lds, nt, B.nmax <= kShortRowN, ctx->stream, e1));
     hipEvent_t e2 = pf.kernel_stamp(&s2);
     HIPCHK(ctx, launch_col_sweep(B.d_insts, B.d_cols, (int)B.h_cols.size(), B.col_grid, nt,
                                  ctx->stream, e2));
