@@ -393,7 +393,7 @@ def euclidean_leg(sk, torch, n=1000, seed=0, scale=100):
             "status": out["status"], "seconds": round(el, 4)}
 
 
-def dominant_leg(sk, torch, prm, n=16384, seed=5, solves=3):
+def dominant_leg(sk, torch, prm, n=16384, seed=5, solves=8):
     """Diagonally dominant 5% pattern at n = 16384 (sentinel-heavy input)."""
     import skgen
     W = skgen.dominant(n, seed)
