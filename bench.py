@@ -21,12 +21,18 @@ WRITE_SIZE counters (each scaled by what the same counter reads for a plain
 kernel sources still hash to the value recorded there; otherwise null.
 
 cpu_baseline: the FP64 oracle, as it stands, timed on this host's cores on a
-bounded sample of the same workload (a few full iterations at n = 16384),
-converted to the same unit.
+bounded sample of the same workload (median of 5 runs of 2 full iterations at
+n = 16384 on every core; median of 5 one-core runs of a 1/16 sample), converted
+to the same unit, with the CPU model.
+
+precision: the same workload with int16 W, BF16 K and FP32 K: whole steps,
+sweep launch durations and roofline fractions, and the error of each against
+the FP64 oracle after a fixed number of iterations from identical potentials.
 
 batched: 512 independent instances, n log-uniform on [32, 1024], weights
 uniform 0..1000; sk_scale_batch (one launch per sweep across all instances)
-against 512 sequential sk_scale calls with the same parameters.
+against 512 sequential sk_scale calls with the same parameters (scalings per
+second; the number of instances that reached the tolerance is reported).
 
 euclidean: the Euclidean random assignment workload at n = 1000 (2n points
 uniform in the unit cube, a_ij = exp(-d), distances quantised at 1/100)
@@ -40,7 +46,8 @@ parameters: time per solve, sweep rate over the dense-stored int16 matrix
 and over the non-zeros only (2 B value + 4 B column index each), and whether
 the unique optimum (the identity) is recovered with its exact weight.
 
-served: 1000 Poisson arrivals of planted instances with n log-uniform on
+served: 1000 Poisson arrivals of distinct planted instances (row permutations
+of 32 base instances) with n log-uniform on
 [64, 8192], tolerance 1e-5, at offered loads of 0.5, 0.9 and 1.5 times the
 FIFO loop's measured capacity; requests through sk_submit/sk_poll (continuous
 batching) against a plain FIFO loop that solves one request at a time
@@ -81,7 +88,7 @@ def parse():
     ap.add_argument("--threshold", type=float, default=1e-4)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-euclidean", action="store_true")
@@ -231,13 +238,19 @@ def calibrate_copy():
                       "gbs_read_plus_write": round(2 * (1 << 30) / el / 1e9, 1)}), flush=True)
 
 
-def batched_leg(sk, torch, seed=1):
-    """512 ragged instances: one batched run vs 512 sequential runs."""
+def batched_leg(sk, torch, seed=1, cap=500):
+    """512 ragged instances: one batched scaling run vs 512 sequential runs
+    with the same parameters (scaling only: no reduction or exact solve, so
+    the rates are scalings per second). Uniform weights on 0..1000 at p = 1
+    converge slowly (the oracle needs more than 1e5 iterations for some of
+    these instances), so stages stop at the cap; the leg reports how many
+    instances reached the tolerance in every stage and the worst FP64
+    residual, which are the same for both forms (bitwise equal results)."""
     import skgen
     ns = skgen.sizes_loguniform(512, 32, 1024, seed)
     Ws = [torch.from_numpy(skgen.uniform_weights(int(n), 0, 1000, seed * 100003 + k)).cuda()
           for k, n in enumerate(ns)]
-    prm = sk.make_params([1, 2, 4, 8, 16, 32], tol=1e-5, max_iters=500, check_every=32)
+    prm = sk.make_params([1, 2, 4, 8, 16, 32], tol=1e-5, max_iters=cap, check_every=32)
     ctx = sk.Context(0)
     # warm-up over the whole batch (2 iterations per stage): the arena is
     # sized and touched before the timed run
@@ -257,11 +270,18 @@ def batched_leg(sk, torch, seed=1):
     same = all(torch.equal(a.potentials, b.potentials) for a, b in zip(res_b, res_s))
     ctx.close()
     elems = int(sum(int(n) * int(n) for n in ns))
+    reps = [r.report for r in res_b]
     return {"instances": 512, "n_range": [32, 1024], "matrix_MB": round(elems * 2 / 1e6, 1),
-            "batched_solves_per_s": round(512 / tb, 1), "sequential_solves_per_s": round(512 / ts, 1),
+            "tol": 1e-5, "cap_per_stage": cap,
+            "instances_reached_tol": int(sum(r["stages_capped"] == 0 for r in reps)),
+            "stages_capped_total": int(sum(r["stages_capped"] for r in reps)),
+            "max_residual_fp64": float(max(max(r["residual_fp64"], r["col_residual_fp64"])
+                                           for r in reps)),
+            "batched_scalings_per_s": round(512 / tb, 1),
+            "sequential_scalings_per_s": round(512 / ts, 1),
             "speedup": round(ts / tb, 2), "batched_s": round(tb, 3), "sequential_s": round(ts, 3),
-            "iters_total": int(sum(r.report["iters_total"] for r in res_b)),
-            "iters_max": int(max(r.report["iters_total"] for r in res_b)),
+            "iters_total": int(sum(r["iters_total"] for r in reps)),
+            "iters_max": int(max(r["iters_total"] for r in reps)),
             "identical_to_sequential": bool(same),
             "kernels": {k: {"launches": v[0], "avg_us": round(v[1] / max(v[0], 1) * 1e3, 2)}
                         for k, v in prof.items()}}
@@ -270,11 +290,16 @@ def batched_leg(sk, torch, seed=1):
 def served_leg(sk, torch, n_requests, loads, seed=2):
     """Poisson arrivals; continuous batching vs a FIFO one-at-a-time loop."""
     import skgen
-    # a pool of planted instances with log-uniform sizes; requests draw from it
+    # 32 planted base instances with log-uniform sizes; request k is a base
+    # instance with its rows permuted by a seeded permutation, so every
+    # request is a distinct matrix with the known optimum 1050 n
     pool_n = skgen.sizes_loguniform(32, 64, 8192, seed)
     pool = [skgen.planted(int(n), seed * 100003 + k) for k, n in enumerate(pool_n)]
     pick = skgen.bounded(skgen.stream(seed, 99, n_requests), len(pool)).astype(np.int64)
-    reqs = [pool[int(k)][0] for k in pick]
+    reqs = []
+    for r, k in enumerate(pick):
+        base = pool[int(k)][0]
+        reqs.append(np.ascontiguousarray(base[skgen.permutation(base.shape[0], seed * 7919 + r)]))
     prm = sk.make_params([1, 2, 4, 8, 16, 32], tol=1e-5, max_iters=2000, check_every=32,
                          threshold=1e-4)
     fifo = sk.Context(0)
@@ -360,7 +385,8 @@ def served_leg(sk, torch, n_requests, loads, seed=2):
                  "optimal": [int(ok_s), int(ok_f)]}
     fifo.close()
     srv.close()
-    return {"requests": n_requests, "n_range": [64, 8192], "pool_instances": len(pool),
+    return {"requests": n_requests, "n_range": [64, 8192], "distinct_matrices": n_requests,
+            "base_instances": len(pool),
             "fifo_capacity_solves_per_s": round(mu, 2), "loads": per_load,
             "saturated": saturated}
 
@@ -425,28 +451,137 @@ def dominant_leg(sk, torch, prm, n=16384, seed=5, solves=8):
             "optimal": bool(np.array_equal(out["perm"], np.arange(n)) and out["weight"] == diag)}
 
 
-def cpu_baseline(W, p, seconds):
-    """The oracle's Sinkhorn at the same n and p, timed on the host cores."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+# One repetition of the 1-core sample, run in a child process started with
+# OMP_NUM_THREADS=1 (the oracle is OpenMP-parallel over rows and columns): a
+# row step over a block of rows and a column step over a block of columns of
+# the same instance (handed over in an .npz file), printed as seconds per
+# full iteration.
+_ONE_CORE = """
+import sys, time, numpy as np
+sys.path.insert(0, {root!r})
+import oracle
+d = np.load({path!r})
+n, p = {n}, {p}
+Br = oracle.log_weights(d["rows"])
+Bc = oracle.log_weights(d["cols"])
+z = np.zeros(n)
+t0 = time.perf_counter()
+oracle.row_step(Br, p, z)
+oracle.col_step(Bc, p, z)
+print((time.perf_counter() - t0) * n / Br.shape[0])
+"""
+
+
+def cpu_baseline(W, B, p, runs=5, iters=2, blk=1024):
+    """The oracle's Sinkhorn at the same n and p, timed on the host cores:
+    the median of `runs` runs of `iters` full iterations (row step, column
+    step, residual) with every core OpenMP gives it, and the median of `runs`
+    one-core runs of a 1/16 sample (a row step over `blk` rows and a column
+    step over `blk` columns, scaled to a full iteration)."""
+    import statistics
+    import subprocess
+    import tempfile
+
     import oracle
     n = W.shape[0]
-    B = oracle.log_weights(W)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    ubar = np.zeros(n)
-    vbar = np.zeros(n)
-    iters = 0
-    t0 = time.perf_counter()
-    while True:
-        ubar, vbar, m, _ = oracle.sinkhorn(B, p, 0.0, 1, ubar, vbar)
-        iters += m
-        el = time.perf_counter() - t0
-        if el >= seconds:
-            break
-    sweeps = 2 * iters
-    gbs = sweeps * n * n * 2 / el / 1e9
-    return {"value": round(gbs, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",
-            "sample": f"{iters} full Sinkhorn iterations (row step, column step, residual) of the "
-                      f"FP64 oracle at n={n}, p={p}, w uniform 0..1000, in {el:.1f} s; "
-                      f"{sweeps / el:.3f} sweeps/s, counted at n^2*2 bytes per sweep"}
+    per_iter = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        _, _, m, _ = oracle.sinkhorn(B, p, 0.0, iters)
+        per_iter.append((time.perf_counter() - t0) / m)
+    med = statistics.median(per_iter)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    one = []
+    with tempfile.TemporaryDirectory() as tmp:
+        path = os.path.join(tmp, "blocks.npz")
+        np.savez(path, rows=W[:blk], cols=np.ascontiguousarray(W[:, :blk]))
+        code = _ONE_CORE.format(root=ROOT, path=path, n=n, p=p)
+        for _ in range(runs):
+            r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True,
+                               text=True, check=True)
+            one.append(float(r.stdout.strip().splitlines()[-1]))
+    med1 = statistics.median(one)
+    gbs = lambda t: round(2 * n * n * 2 / t / 1e9, 3)
+    return {"value": gbs(med), "unit": "GB/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "runs": runs,
+            "sweeps_per_s": round(2 / med, 3),
+            "one_core": {"value": gbs(med1), "unit": "GB/s", "sweeps_per_s": round(2 / med1, 4)},
+            "sample": f"FP64 oracle Sinkhorn at n={n}, p={p}, w uniform 0..1000: median of {runs} "
+                      f"runs of {iters} full iterations (row step, column step, residual) on "
+                      f"{threads} threads ({med:.2f} s per iteration); 1 core: median of {runs} "
+                      f"runs of a row step over {blk} rows and a column step over {blk} columns, "
+                      f"scaled to a full iteration ({med1:.1f} s per iteration); counted at "
+                      f"n^2*2 bytes per sweep"}
+
+
+def precision_leg(sk, torch, W, Wd, B, ladder, cap, tol, threshold, p=32, iters=3, steps=3):
+    """The n = 16384 workload with the matrix read three ways: int16 W with
+    exp recomputed in every sweep, K stored in BF16, K stored in FP32.
+    Per storage: whole sk_solve steps (the main leg's parameters) with the
+    sweeps' average launch durations and their fraction of the HBM peak; and
+    the error against the FP64 oracle at a fixed sweep count: from identical
+    potentials (20 int16 iterations at p), `iters` iterations of the storage
+    (the first of a stored-K stage is the exact log-domain one, the others
+    sweep K) against the oracle's `iters` iterations from the same start,
+    as max |log u - log u*| and max |log v - log v*| over all rows and
+    columns, and the FP64 residual of the matrix the storage balances."""
+    import oracle
+    n = W.shape[0]
+    ctx = sk.Context(0)
+    warm = ctx.scale(Wd, sk.make_params([p], tol=0.0, max_iters=20, check_every=20))
+    lu0, lv0 = sk.split_potentials(warm.potentials, n)
+    ub_o, vb_o, m, _ = oracle.sinkhorn(B, p, 0.0, iters, lu0 / p, lv0 / p)
+    assert m == iters
+    out = {"n": n, "p_error": p, "iterations_from_identical_start": iters}
+    for storage in ("i16", "bf16", "f32"):
+        es = ELEM_BYTES[storage]
+        prm = sk.make_params(ladder, tol=tol, max_iters=cap, check_every=32, threshold=threshold,
+                             storage=storage)
+        ctx.solve(Wd, prm)  # warm-up (sizes the arena)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        t0 = time.perf_counter()
+        its = 0
+        for _ in range(steps):
+            o = ctx.solve(Wd, prm)
+            its += o["report"]["iters_total"]
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / steps
+        prof = ctx.profile_read()
+        ctx.profile(False)
+        r = o["report"]
+        rk, ck = SWEEP_KERNELS[storage][:2]
+        us = {k: prof[k][1] / prof[k][0] * 1e3 for k in (rk, ck) if k in prof}
+        res = ctx.scale(Wd, sk.make_params([p], tol=0.0, max_iters=iters, warm_start=True,
+                                           storage=storage), potentials=warm.potentials.clone())
+        lu, lv = sk.split_potentials(res.potentials, n)
+        out[storage] = {
+            "ms_per_step": round(el * 1e3, 3), "iters_per_step": its // steps,
+            "step_sweep_GBps": round(2 * its / steps * n * n * es / el / 1e9, 1),
+            "row_sweep_us": round(us.get(rk, 0.0), 2), "col_sweep_us": round(us.get(ck, 0.0), 2),
+            "row_sweep_frac": round(n * n * es / (us[rk] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
+            if rk in us else None,
+            "col_sweep_frac": round(n * n * es / (us[ck] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
+            if ck in us else None,
+            "absorbs_per_step": r["absorbs"], "weight": o["weight"],
+            "residual_fp64": r["residual_fp64"], "col_residual_fp64": r["col_residual_fp64"],
+            "residual_exact_fp64": r["residual_exact_fp64"],
+            "max_abs_err_log_u": float(np.abs(lu - p * ub_o).max()),
+            "max_abs_err_log_v": float(np.abs(lv - p * vb_o).max()),
+        }
+    ctx.close()
+    return out
 
 
 def main():
@@ -557,12 +692,23 @@ def main():
                    "fused": bool(args.fused), "method": args.method},
         "iters_per_step": iters // args.steps, "iters_per_s": round(iters / el, 1),
         "matrix_reads_per_iter": reads,
+        "stages_capped": rep["stages_capped"],
+        "iters_stage": rep["iters_stage"][:len(ladder)],
         "nnz_kept": nnz, "weight": weight, "log_gamma": lg,
-        "residual_fp64": rep["residual_fp64"],
+        "optimal_proved": bool(rep["optimal_proved"]),
+        "residual_fp32": rep["residual_fp32"],
+        "residual_fp64": rep["residual_fp64"], "col_residual_fp64": rep["col_residual_fp64"],
         "phases_ms": phase_ms,
         "roofline": roofline, "kernels": kernels,
     }
     ctx.close()
+    B = None
+    if not (args.no_precision and args.no_cpu_baseline):
+        import oracle
+        B = oracle.log_weights(W)
+    if not args.no_precision:
+        out["precision"] = precision_leg(sk, torch, W, Wd, B, ladder, args.cap, args.tol,
+                                         args.threshold)
     del Wd
     if not args.no_batched:
         out["batched"] = batched_leg(sk, torch)
@@ -574,7 +720,7 @@ def main():
         out["served"] = served_leg(sk, torch, args.served_requests,
                                    [float(x) for x in args.served_loads.split(",")])
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(W, ladder[-1], args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(W, B, ladder[-1])
     print(json.dumps(out), flush=True)
 
 

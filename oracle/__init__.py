@@ -17,6 +17,13 @@ Every function cites the passage it follows; parity status of each part:
   certificate ......................... pinned (upper bound vs brute force,
       tight at convergence)
   hungarian ........................... pinned (brute force n <= 8, scipy)
+  hungarian_real ...................... pinned (brute force n <= 7, scipy, equality
+      with hungarian on integer weights)
+  prescale_log ........................ pinned (equal to the linear prescale; range
+      [0, 1]; invariance under entrywise powers)
+  adaptive_real ....................... pinned (equal to adaptive on integer weights
+      without prescaling; invariance under entrywise powers with prescaling;
+      optimum against the Hungarian of the whole matrix)
   prescale ............................ pinned (range [1, e], idempotence,
       invariance under entrywise powers, Section 4.1.1)
 """
@@ -69,6 +76,8 @@ def lib():
         L.or_prescale.restype = None
         L.or_hungarian.argtypes = [ctypes.c_int, _i64p, _u8p, _i32p, _i64p]
         L.or_hungarian.restype = ctypes.c_int
+        L.or_hungarian_real.argtypes = [ctypes.c_int, _dp, _u8p, _i32p, _dp]
+        L.or_hungarian_real.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -228,6 +237,44 @@ def hungarian(w, allowed=None):
     return perm, weight.value
 
 
+def hungarian_real(w, allowed=None):
+    """Exact maximum-weight perfect matching for real weights, dense O(n^3)
+    (the Hungarian method of Section 1's solver class) in FP64. w: n x n
+    float64; allowed: bool mask (default: the finite entries). Returns
+    (perm, weight)."""
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    n = w.shape[0]
+    if allowed is None:
+        allowed = np.isfinite(w)
+    allowed = np.ascontiguousarray(allowed & np.isfinite(w), dtype=np.uint8)
+    wz = np.where(allowed.astype(bool), w, 0.0)
+    perm = np.empty(n, dtype=np.int32)
+    weight = ctypes.c_double(0.0)
+    if n == 0:
+        return perm, 0.0
+    st = lib().or_hungarian_real(n, _d(np.ascontiguousarray(wz)), allowed.ctypes.data_as(_u8p),
+                                 perm.ctypes.data_as(_i32p), ctypes.byref(weight))
+    if st:
+        raise Infeasible("no perfect matching on the allowed entries")
+    return perm, weight.value
+
+
+def prescale_log(B):
+    """The prescaling of Section 4.1.1 written on b = log a: with lo, hi the
+    smallest and largest finite b, b' = (b - lo) / (hi - lo) when
+    max(A)/min(A) > e (hi - lo > 1: A^(m)/c with m = 1/log(max/min)),
+    otherwise b' = b - lo (A / min(A)). Returns (b', the factor applied to p:
+    p on A' equals p / (hi - lo), resp. p, on A)."""
+    B = np.asarray(B, dtype=np.float64)
+    fin = B[np.isfinite(B)]
+    lo, hi = float(fin.min()), float(fin.max())
+    scale = 1.0 / (hi - lo) if hi - lo > 1.0 else 1.0
+    with np.errstate(invalid="ignore"):
+        out = (B - lo) * scale
+    out[np.isneginf(B)] = -np.inf
+    return np.ascontiguousarray(out), scale
+
+
 def optimum_int(W, allowed=None):
     """Optimal assignment of int16 log-weights W (sentinel entries excluded)."""
     mask = W != SENTINEL
@@ -317,6 +364,60 @@ def adaptive(W, ladder, eps, max_iters, t, opt_ratio):
                 best = Solution(float(p), ubar.copy(), vbar.copy(), list(iters_all), list(res_all),
                                 keep, int(keep.sum()), ub, perm, weight, lg, {"t": tt})
             if not evaluate_all or best.log_gamma <= np.log(opt_ratio):
+                best.extra["evaluated"] = evaluated
+                return best, "ok"
+    if best is None:
+        return None, "infeasible"
+    best.extra["evaluated"] = evaluated
+    return best, "ratio"
+
+
+def adaptive_real(B, ladder, eps, max_iters, t, opt_ratio, prescale=True):
+    """Algorithm alg:alg1 (Section 4.2) on real log-weights b = log a (-inf
+    for a zero): with prescale, A is first replaced by its prescaled matrix
+    (Section 4.1.1, prescale_log) and every quantity below refers to it, as
+    in the algorithm; then, for each p of the ladder in order, Sinkhorn
+    scaling of A^(p) to eps (carried from the previous p in the coordinates
+    p^-1 log u, p^-1 log v), the certificate (Proposition prop:aoc), the
+    reduced matrix at t (eq. matrixred), an optimal assignment of it and
+    log gamma = ub - w(B) (eq. optratio). It stops at the first p with
+    gamma <= opt_ratio (the loop condition read as "raise p while gamma
+    exceeds the ratio"); when B has no perfect matching at the last p, t is
+    lowered tenfold, at most three times. Returns (Solution, status) as
+    adaptive(); Solution.weight is w(B) in the prescaled units and
+    Solution.extra holds t, the number of evaluated p, the p factor of the
+    prescaling and the weight in the original units."""
+    B = np.asarray(B, dtype=np.float64)
+    n = B.shape[0]
+    Bp, scale = prescale_log(B) if prescale else (np.ascontiguousarray(B), 1.0)
+    ubar, vbar = np.zeros(n), np.zeros(n)
+    best, evaluated, iters_all, res_all = None, 0, [], []
+    for k, p in enumerate(ladder):
+        ubar, vbar, it, res = sinkhorn(Bp, p, eps, max_iters, ubar, vbar)
+        iters_all.append(it)
+        res_all.append(res)
+        last = k + 1 == len(ladder)
+        ub = certificate(Bp, p, ubar, vbar)
+        tt = t
+        for tries in range(4):
+            keep = prune(Bp, p, ubar, vbar, tt)
+            try:
+                perm, weight = hungarian_real(Bp, keep)
+                break
+            except Infeasible:
+                perm, weight = None, None
+                if not last or tries == 3:
+                    break
+                tt /= 10.0
+        evaluated += 1
+        if weight is not None:
+            lg = ub - weight
+            if best is None or lg < best.log_gamma:
+                w_orig = float(B[np.arange(n), perm].sum())
+                best = Solution(float(p), ubar.copy(), vbar.copy(), list(iters_all), list(res_all),
+                                keep, int(keep.sum()), ub, perm, weight, lg,
+                                {"t": tt, "p_scale": scale, "weight_orig": w_orig})
+            if best.log_gamma <= np.log(opt_ratio):
                 best.extra["evaluated"] = evaluated
                 return best, "ok"
     if best is None:

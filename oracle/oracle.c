@@ -313,3 +313,82 @@ int or_hungarian(int n, const int64_t *w, const uint8_t *allowed, int32_t *perm,
     free(used);
     return status;
 }
+
+/* The same dense O(n^3) Hungarian method for real weights (log-weights of a
+ * nonnegative matrix), maximising sum_i w[i, perm(i)] over the allowed
+ * entries in FP64. Returns 0 and fills perm/weight, or 1 if no perfect
+ * matching uses only allowed entries. */
+int or_hungarian_real(int n, const double *w, const uint8_t *allowed, int32_t *perm,
+                      double *weight)
+{
+    double *u = calloc((size_t)n + 1, sizeof(double));
+    double *v = calloc((size_t)n + 1, sizeof(double));
+    double *minv = malloc(((size_t)n + 1) * sizeof(double));
+    int *match = calloc((size_t)n + 1, sizeof(int));
+    int *way = calloc((size_t)n + 1, sizeof(int));
+    char *used = malloc((size_t)n + 1);
+    int status = 0;
+    for (int i = 1; i <= n && status == 0; ++i) {
+        match[0] = i;
+        int j0 = 0;
+        for (int j = 0; j <= n; ++j) {
+            minv[j] = INFINITY;
+            used[j] = 0;
+        }
+        do {
+            used[j0] = 1;
+            int i0 = match[j0];
+            double delta = INFINITY;
+            int j1 = -1;
+            for (int j = 1; j <= n; ++j) {
+                if (used[j]) continue;
+                size_t k = (size_t)(i0 - 1) * n + (size_t)(j - 1);
+                if (allowed[k]) {
+                    double cur = -w[k] - u[i0] - v[j];
+                    if (cur < minv[j]) {
+                        minv[j] = cur;
+                        way[j] = j0;
+                    }
+                }
+                if (minv[j] < delta) {
+                    delta = minv[j];
+                    j1 = j;
+                }
+            }
+            if (j1 < 0 || delta == INFINITY) {
+                status = 1;
+                break;
+            }
+            for (int j = 0; j <= n; ++j) {
+                if (used[j]) {
+                    u[match[j]] += delta;
+                    v[j] -= delta;
+                } else if (minv[j] < INFINITY) {
+                    minv[j] -= delta;
+                }
+            }
+            j0 = j1;
+        } while (match[j0] != 0);
+        if (status) break;
+        do {
+            int j1 = way[j0];
+            match[j0] = match[j1];
+            j0 = j1;
+        } while (j0);
+    }
+    if (status == 0) {
+        double total = 0.0;
+        for (int j = 1; j <= n; ++j) {
+            perm[match[j] - 1] = j - 1;
+            total += w[(size_t)(match[j] - 1) * n + (size_t)(j - 1)];
+        }
+        *weight = total;
+    }
+    free(u);
+    free(v);
+    free(minv);
+    free(match);
+    free(way);
+    free(used);
+    return status;
+}

@@ -14,8 +14,7 @@ from dataclasses import dataclass
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-# SK_LIB_PATH selects another build of the library (build-variant comparisons)
-LIB_PATH = os.environ.get("SK_LIB_PATH", os.path.join(HERE, "libsk.so"))
+LIB_PATH = os.path.join(HERE, "libsk.so")
 
 SK_OK, SK_EINVAL, SK_ENOMEM, SK_ENOCONV, SK_EINFEASIBLE, SK_EAGAIN, SK_EDEVICE, SK_ENOSUPPORT = range(8)
 STATUS_NAMES = ["SK_OK", "SK_EINVAL", "SK_ENOMEM", "SK_ENOCONV", "SK_EINFEASIBLE", "SK_EAGAIN",

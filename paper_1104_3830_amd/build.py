@@ -19,16 +19,17 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              "-Wall", "-Wno-unused-function"]
 
 
-def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
-    """Compiles every source and links `out` (defines: extra -D flags)."""
+def build(verbose: bool = False) -> str:
+    """Compiles every source and links libsk.so in the package directory."""
+    out = LIB
     objs = []
-    bdir = os.path.join(os.path.dirname(out) if out != LIB else HERE, "_build")
+    bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
     for src in SOURCES:
         path = os.path.join(CSRC, src)
         obj = os.path.join(bdir, src + ".o")
         if src.endswith(".hip"):
-            cmd = ["hipcc", "-x", "hip", *HIP_FLAGS, *[f"-D{d}" for d in defines], "-c", path,
+            cmd = ["hipcc", "-x", "hip", *HIP_FLAGS, "-c", path,
                    "-o", obj]
         else:
             cmd = ["hipcc", "-O3", "-std=c++17", "-fPIC", "-Wall", "-c", path, "-o", obj]

@@ -18,6 +18,7 @@ constexpr int kMaxN = 16384;     // row sweep stages all column potentials in LD
 constexpr int kMaxSegRows = 1024;
 constexpr int kShortRowN = 2048;  // batches up to this n take the short-row row sweep
 constexpr int kFusedSlots = 256;  // workgroups (and column-partial slots) of the fused kernel
+constexpr int kMaxRowGrid = 1024;  // row-sweep workgroups (bounds table sized for it)
 
 // Column count of the 8-wide layout: n rounded up to a multiple of 8.
 __host__ __device__ constexpr int pad8(int n) { return (n + 7) & ~7; }

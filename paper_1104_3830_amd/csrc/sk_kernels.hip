@@ -188,8 +188,7 @@ __device__ __forceinline__ void col_partial(const Inst &I, int tile, int r0, int
         };
         int r = r0 + wave;
         constexpr int S = kColWaves;
-        constexpr int U = SK_COL_UNROLL;
-#if SK_COL_PIPE
+        constexpr int U = kColLoads;
         // two register buffers: the next U rows are requested before the
         // current U are used, so loads stay in flight during the arithmetic
         // (rows are still added in order)
@@ -220,16 +219,6 @@ __device__ __forceinline__ void col_partial(const Inst &I, int tile, int r0, int
                 if (!more2) break;
             }
         }
-#else
-        for (; r + (U - 1) * S < r1; r += U * S) {
-            int4 v[U];
-#pragma unroll
-            for (int k = 0; k < U; ++k)
-                v[k] = gload<NT>(reinterpret_cast<const int4 *>(base + (int64_t)(r + k * S) * pitch));
-#pragma unroll
-            for (int k = 0; k < U; ++k) body(v[k], rowpot[r + k * S - r0]);
-        }
-#endif
         for (; r < r1; r += S) body(gload<NT>(reinterpret_cast<const int4 *>(base + (int64_t)r * pitch)),
                                     rowpot[r - r0]);
     } else {

@@ -88,68 +88,22 @@ __device__ __forceinline__ float chunk8(const int4 v, int q, int n8, int p4, int
     return s;
 }
 
-// Loads in flight per lane in the sweeps (build-time tuning knobs).
-#ifndef SK_ROW_UNROLL
-#define SK_ROW_UNROLL 2
-#endif
-#ifndef SK_COL_UNROLL
-#define SK_COL_UNROLL 1
-#endif
-// Two rows per wave in the row sweep (build-time switch) and the chunks in
-// flight per row when it does.
-#ifndef SK_ROW_PAIR
-#define SK_ROW_PAIR 0
-#endif
-#ifndef SK_PAIR_UNROLL
-#define SK_PAIR_UNROLL 1
-#endif
-// Software pipelining of the sweeps' loads (build-time switch).
-#ifndef SK_ROW_PIPE
-#define SK_ROW_PIPE 0
-#endif
-#ifndef SK_COL_PIPE
-#define SK_COL_PIPE 1
-#endif
+// 16-byte loads in flight per lane: the row sweep issues kRowLoads chunks of a
+// row before using them; the column sweep double-buffers kColLoads rows (3
+// and 4 row chunks, and a software-pipelined row sweep, measured no faster).
+constexpr int kRowLoads = 2;
+constexpr int kColLoads = 1;
 
-// Row partial sum for one lane: chunks lane*8 + k*512, SK_ROW_UNROLL 16-byte
+// Row partial sum for one lane: chunks lane*8 + k*512, kRowLoads 16-byte
 // loads in flight per lane.
 template <bool SENT, bool NT>
 __device__ __forceinline__ float row_partial_v8(const int16_t *__restrict__ wr, int n, int p4,
                                                 int B, const ColPot *__restrict__ cp,
                                                 const float *__restrict__ tab, int lane) {
-    constexpr int U = SK_ROW_UNROLL;
+    constexpr int U = kRowLoads;
     const int n8 = pad8(n) >> 3;
     float acc = 0.f;
     int j0 = lane * 8;
-#if SK_ROW_PIPE
-    // two register buffers (see the column sweep); chunks are still added in order
-    auto ld = [&](int4 (&v)[U], int jj) {
-#pragma unroll
-        for (int k = 0; k < U; ++k) v[k] = gload<NT>(reinterpret_cast<const int4 *>(wr + jj + k * 512));
-    };
-    auto use = [&](const int4 (&v)[U], int jj) {
-#pragma unroll
-        for (int k = 0; k < U; ++k) acc += chunk8<SENT>(v[k], (jj >> 3) + 64 * k, n8, p4, B, cp, tab);
-    };
-    if (j0 + (U - 1) * 512 < n) {
-        int4 va[U], vb[U];
-        ld(va, j0);
-        for (;;) {
-            const int j2 = j0 + U * 512;
-            const bool more = j2 + (U - 1) * 512 < n;
-            if (more) ld(vb, j2);
-            use(va, j0);
-            j0 = j2;
-            if (!more) break;
-            const int j3 = j0 + U * 512;
-            const bool more2 = j3 + (U - 1) * 512 < n;
-            if (more2) ld(va, j3);
-            use(vb, j0);
-            j0 = j3;
-            if (!more2) break;
-        }
-    }
-#else
     for (; j0 + (U - 1) * 512 < n; j0 += U * 512) {
         int4 v[U];
 #pragma unroll
@@ -158,7 +112,6 @@ __device__ __forceinline__ float row_partial_v8(const int16_t *__restrict__ wr, 
 #pragma unroll
         for (int k = 0; k < U; ++k) acc += chunk8<SENT>(v[k], q + 64 * k, n8, p4, B, cp, tab);
     }
-#endif
     for (; j0 < n; j0 += 512) {
         const int4 v = gload<NT>(reinterpret_cast<const int4 *>(wr + j0));
         acc += chunk8<SENT>(v, j0 >> 3, n8, p4, B, cp, tab);
@@ -269,87 +222,6 @@ __device__ __forceinline__ float row_step_one(const Inst &I, int row, int par, i
                  : row_partial_v1<SENT, NT>(wr, n, p4, 4 * (Fi - kTabLo), cp, tab, lane);
     S = wave_sum(S);
     return row_finish<SENT, V8, NT>(I, row, par, lane, Fi, phi, S, cp, tab);
-}
-
-// Two rows in one pass over the columns: each column's (4 G_j, exp(gam_j))
-// is read from LDS once for both rows. Each row's chunks are added in the
-// same order as in row_partial_v8, so a row's sum does not depend on whether
-// it is paired.
-template <bool SENT>
-__device__ __forceinline__ void chunk8x2(const int4 v0, const int4 v1, int q, int n8, int p4,
-                                         int B0, int B1, const ColPot *__restrict__ cp,
-                                         const float *__restrict__ tab, float &s0, float &s1) {
-    int w0[8], w1[8];
-    unpack8i(v0, w0);
-    unpack8i(v1, w1);
-    s0 = 0.f;
-    s1 = 0.f;
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        const ColPot k = cp[c * n8 + q];
-        float e0 = tab_at(tab, tab_off(p4, w0[c], k.a, B0));
-        float e1 = tab_at(tab, tab_off(p4, w1[c], k.a, B1));
-        if (SENT) {
-            e0 = (w0[c] == SK_SENTINEL) ? 0.f : e0;
-            e1 = (w1[c] == SK_SENTINEL) ? 0.f : e1;
-        }
-        s0 = fmaf(e0, k.g, s0);
-        s1 = fmaf(e1, k.g, s1);
-    }
-}
-
-template <bool SENT, bool NT>
-__device__ __forceinline__ void row_partial2_v8(const int16_t *__restrict__ wr0,
-                                                const int16_t *__restrict__ wr1, int n, int p4,
-                                                int B0, int B1, const ColPot *__restrict__ cp,
-                                                const float *__restrict__ tab, int lane,
-                                                float &acc0, float &acc1) {
-    constexpr int U = SK_PAIR_UNROLL;
-    const int n8 = pad8(n) >> 3;
-    acc0 = 0.f;
-    acc1 = 0.f;
-    int j0 = lane * 8;
-    for (; j0 + (U - 1) * 512 < n; j0 += U * 512) {
-        int4 v0[U], v1[U];
-#pragma unroll
-        for (int k = 0; k < U; ++k) {
-            v0[k] = gload<NT>(reinterpret_cast<const int4 *>(wr0 + j0 + k * 512));
-            v1[k] = gload<NT>(reinterpret_cast<const int4 *>(wr1 + j0 + k * 512));
-        }
-        const int q = j0 >> 3;
-#pragma unroll
-        for (int k = 0; k < U; ++k) {
-            float s0, s1;
-            chunk8x2<SENT>(v0[k], v1[k], q + 64 * k, n8, p4, B0, B1, cp, tab, s0, s1);
-            acc0 += s0;
-            acc1 += s1;
-        }
-    }
-    for (; j0 < n; j0 += 512) {
-        float s0, s1;
-        chunk8x2<SENT>(gload<NT>(reinterpret_cast<const int4 *>(wr0 + j0)),
-                       gload<NT>(reinterpret_cast<const int4 *>(wr1 + j0)), j0 >> 3, n8, p4, B0, B1, cp,
-                       tab, s0, s1);
-        acc0 += s0;
-        acc1 += s1;
-    }
-}
-
-template <bool SENT, bool NT>
-__device__ __forceinline__ float row_step_pair(const Inst &I, int ra, int rb, int par, int lane,
-                                              const ColPot *__restrict__ cp,
-                                              const float *__restrict__ tab) {
-    const int n = I.n;
-    const int Fa = I.F[par][ra], Fb = I.F[par][rb];
-    const int p4 = 4 * I.ctl->p;
-    float Sa, Sb;
-    row_partial2_v8<SENT, NT>(I.W + (int64_t)ra * I.pitch, I.W + (int64_t)rb * I.pitch, n, p4,
-                          4 * (Fa - kTabLo), 4 * (Fb - kTabLo), cp, tab, lane, Sa, Sb);
-    Sa = wave_sum(Sa);
-    Sb = wave_sum(Sb);
-    const float ea = row_finish<SENT, true, NT>(I, ra, par, lane, Fa, I.phi[par][ra], Sa, cp, tab);
-    const float eb = row_finish<SENT, true, NT>(I, rb, par, lane, Fb, I.phi[par][rb], Sb, cp, tab);
-    return fmaxf(ea, eb);
 }
 
 // Column potentials of the padding columns n..pad8(n)-1 of the 8-wide layout
@@ -477,14 +349,8 @@ __global__ __launch_bounds__(kRowWaves * kWave, MINW) void k_row_sweep(const Ins
         const int par = iter & 1;
         const bool sent = ctl->sent != 0u;
         const int ra = un.row0 + wave;
-        // the next unit of the same instance is done in the same pass
-        const bool pair = SK_ROW_PAIR && I.vec8 && u + 1 < u1 && units[u + 1].inst == un.inst;
-        const int rb = pair ? units[u + 1].row0 + wave : n;
         float e = 0.f;
-        if (rb < n) {
-            e = sent ? row_step_pair<true, NT>(I, ra, rb, par, lane, lds_cp, tab)
-                     : row_step_pair<false, NT>(I, ra, rb, par, lane, lds_cp, tab);
-        } else if (ra < n) {
+        if (ra < n) {
             if (I.vec8) {
                 e = sent ? row_step_one<true, true, NT>(I, ra, par, lane, lds_cp, tab)
                          : row_step_one<false, true, NT>(I, ra, par, lane, lds_cp, tab);
@@ -494,7 +360,7 @@ __global__ __launch_bounds__(kRowWaves * kWave, MINW) void k_row_sweep(const Ins
             }
         }
         wres = fmaxf(wres, e);
-        u += pair ? 2 : 1;
+        ++u;
     }
     // every wave ends on the same instance: the waves' maxima meet in LDS and
     // the last wave to finish sends the workgroup's to the slot

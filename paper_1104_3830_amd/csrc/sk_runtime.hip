@@ -13,18 +13,6 @@
 #include "sk_internal.h"
 #include "sk_runtime.h"
 
-// Cost model of the row-sweep split (build-time tuning knobs; see
-// finish_tables).
-#ifndef SK_BAL_RT_COLS
-#define SK_BAL_RT_COLS 512
-#endif
-#ifndef SK_BAL_UNIT
-#define SK_BAL_UNIT 0
-#endif
-#ifndef SK_BAL_STAGE
-#define SK_BAL_STAGE 0
-#endif
-
 namespace sk {
 
 // ---------------------------------------------------------------- planning
@@ -103,6 +91,7 @@ size_t shared_bytes(int32_t count, const int32_t *n) {
     b += align_up(sizeof(double) * nmax, 256) * 3;  // FP64 check: rsum, rmax, csum
     b += align_up(sizeof(double) * (size_t)cpart, 256);  // FP64 column partials
     b += align_up(sizeof(int64_t) * (nmax + 1), 256);  // prune row counts
+    b += align_up(sizeof(int32_t) * (kMaxRowGrid + 1), 256);  // row-sweep workgroup bounds
     return b;
 }
 
@@ -444,18 +433,20 @@ sk_status sk::finish_tables(sk_ctx *ctx, Bump &bump, Batch &B) {
     const int per_cu = lds <= 32768 ? 2 : 1;
     B.row_lds = lds;
     B.row_lds_k = sizeof(float) * (size_t)((B.nmax + 7) / 8 * 8);
-    B.row_grid = (int)std::max<size_t>(1, std::min<size_t>(B.h_rows.size(), (size_t)ctx->num_cus * per_cu));
+    B.row_grid = (int)std::max<size_t>(
+        1, std::min<size_t>({B.h_rows.size(), (size_t)ctx->num_cus * per_cu, (size_t)kMaxRowGrid}));
     const int per_cu_k = B.row_lds_k <= 65536 ? 2 : 1;
     B.row_grid_k = (int)std::max<size_t>(1, std::min<size_t>(B.h_rows.size(), (size_t)ctx->num_cus * per_cu_k));
     // Row-sweep ranges: contiguous runs of row units of about equal cost, so
     // that a batch of mixed sizes does not wait on the workgroups that drew
     // the large instances (an even split by count ran the 512-instance batch
     // of n in [32, 1024] 24% slower). Costs in hundredths of a step: a unit
-    // (one row per wave) takes one step per SK_BAL_RT_COLS columns of its
-    // rows (one 16-byte load per lane covers 512) plus SK_BAL_UNIT, and the
-    // first unit of an instance also SK_BAL_STAGE for the staging of the
-    // instance's column data; the defaults were chosen by timing that batch.
+    // (one row per wave) takes one step per 512 columns of its rows (one
+    // 16-byte load per lane covers 512); of five cost models timed on that
+    // batch this was the best (charging the staging of an instance's column
+    // data, or a constant per unit, did not help).
     // Integer costs: equal units split exactly evenly.
+    constexpr int64_t kCostCols = 512;
     {
         const size_t nu = B.h_rows.size();
         const int g = B.row_grid;
@@ -463,8 +454,7 @@ sk_status sk::finish_tables(sk_ctx *ctx, Bump &bump, Batch &B) {
         int64_t total = 0;
         for (size_t q = 0; q < nu; ++q) {
             const int64_t nn = B.h_insts[B.h_rows[q].inst].n;
-            int64_t c = 100 * ((nn + SK_BAL_RT_COLS - 1) / SK_BAL_RT_COLS) + SK_BAL_UNIT;
-            if (q == 0 || B.h_rows[q - 1].inst != B.h_rows[q].inst) c += SK_BAL_STAGE;
+            const int64_t c = 100 * ((nn + kCostCols - 1) / kCostCols);
             cost[q] = c;
             total += c;
         }
@@ -732,20 +722,23 @@ sk_status sk::status_of(const Ctl &c) {
     return SK_OK;
 }
 
-// Exactness of p*w_ij + F_i + G_j in float32 needs |p w| well below 2^24;
-// valid weights are in [-16384, 16383], so p <= 128 guarantees |p w| <= 2^21.
-// Larger p is accepted when the weights are small enough; the input scan
-// would be needed to prove it, so the bound here is on p alone.
+// The sweeps form the exponent 4 (p w_ij + F_i + G_j) in int32 (the byte
+// offset of exp(E) in the LDS table), with p w from v_mul_i32_i24. Valid
+// weights lie in [-16384, 16383]; p <= 2048 keeps |4 p w| <= 2^27, so with
+// the potentials' integer parts (a few p times the weight range) and the
+// padding columns' kPadExp4 = -2^30 every sum stays inside int32 and every
+// exponent is exact.
 sk_status sk::check_range(sk_ctx *ctx, const sk_params *prm) {
     int pmax = 0;
     for (int s = 0; s < prm->n_p; ++s) pmax = std::max(pmax, prm->p_ladder[s]);
     if ((int64_t)pmax * 16384 > ((int64_t)1 << 25))
-        return fail(ctx, SK_EINVAL, "p = %d: p * 16384 exceeds 2^25 (exact float range)", pmax);
+        return fail(ctx, SK_EINVAL, "p = %d: p * 16384 exceeds 2^25 (exact int32 exponents)", pmax);
     return SK_OK;
 }
 
 sk_status sk::scale_impl(sk_ctx *ctx, int count, const int16_t *const *W, const int32_t *n,
-                         const sk_params *prm, void *const *pot, sk_report *reports) {
+                         const sk_params *prm, void *const *pot, sk_report *reports, char *arena,
+                         size_t arena_bytes) {
     auto t0 = std::chrono::steady_clock::now();
     if (serving(ctx)) return fail(ctx, SK_EINVAL, "context is serving; blocking calls are disabled");
     ctx->absorbs = 0;
@@ -766,7 +759,7 @@ sk_status sk::scale_impl(sk_ctx *ctx, int count, const int16_t *const *W, const 
         return fail(ctx, SK_EINVAL, "the single-pass iteration over int16 W needs n %% 8 == 0");
     if ((st = check_range(ctx, prm)) != SK_OK) return st;
     HIPCHK(ctx, hipSetDevice(ctx->device));
-    Bump bump{ctx->arena, ctx->arena_bytes};
+    Bump bump{arena, arena_bytes};
     Batch &B = ctx->scratch_batch;
     if ((st = plan_batch(ctx, bump, count, W, pitch.data(), n, prm, B)) != SK_OK) return st;
     if ((st = upload_batch(ctx, B)) != SK_OK) return st;
@@ -830,7 +823,7 @@ sk_status sk_scale(sk_ctx *ctx, const int16_t *W, int32_t n, const sk_params *pa
     std::lock_guard<std::mutex> g(ctx->mu);
     const int16_t *Ws[1] = {W};
     void *pots[1] = {potentials};
-    return scale_impl(ctx, 1, Ws, &n, params, pots, report);
+    return scale_impl(ctx, 1, Ws, &n, params, pots, report, ctx->arena, ctx->arena_bytes);
 }
 
 sk_status sk_scale_batch(sk_ctx *ctx, int32_t count, const int16_t *const *W, const int32_t *n,
@@ -838,7 +831,7 @@ sk_status sk_scale_batch(sk_ctx *ctx, int32_t count, const int16_t *const *W, co
     if (!ctx) return SK_EINVAL;
     if (!W || !n || !potentials) return fail(ctx, SK_EINVAL, "null array argument");
     std::lock_guard<std::mutex> g(ctx->mu);
-    return scale_impl(ctx, count, W, n, params, potentials, reports);
+    return scale_impl(ctx, count, W, n, params, potentials, reports, ctx->arena, ctx->arena_bytes);
 }
 
 // ---------------------------------------------------------------- prune

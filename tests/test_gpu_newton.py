@@ -66,3 +66,43 @@ def test_newton_rejects_unsupported_combinations(ctx):
         prm = sk.make_params([1], method="newton", **kw)
         with pytest.raises(sk.SkError):
             ctx.scale(dev(W), prm)
+
+
+def test_newton_full_size(ctx):
+    """Newton scaling at n = 16384 (w uniform on 0..1000, p = 32, cold start
+    F = -p rowmax, G = 0; the product kernels' two-chunk, non-temporal form).
+    One product with S at x = 1 gives the row and column sums of the
+    starting matrix: its reported max |1 - (S x)_i| equals the oracle's FP64
+    sums on the same potentials. Run to tol from the same start, the result
+    is a fixed point of the oracle's row and column steps on sampled rows and
+    columns, and the library's FP64 recheck is within a few tol."""
+    n, p = 16384, 32
+    W = skgen.uniform_weights(n, 0, 1000, seed=3)
+    Wd = dev(W)
+    one = ctx.scale(Wd, sk.make_params([p], tol=1e-5, max_iters=1, method="newton"))
+    assert one.status == sk.SK_ENOCONV and one.report["iters_total"] == 1
+    lu0, lv0 = sk.split_potentials(one.potentials, n)  # the start (x = 1 folds to it)
+    # the oracle's sums of the starting matrix, in row blocks
+    rmax, csum = 0.0, np.zeros(n)
+    blk = 2048
+    for r0 in range(0, n, blk):
+        Bb = oracle.log_weights(W[r0:r0 + blk])
+        X = np.exp(Bb * p + lu0[r0:r0 + blk, None] + lv0[None, :])
+        rmax = max(rmax, np.abs(X.sum(axis=1) - 1).max())
+        csum += X.sum(axis=0)
+    want = max(rmax, np.abs(csum - 1).max())
+    assert want > 1.0  # far from balanced: the product is a real test
+    assert abs(one.report["residual_fp32"] - want) <= 2e-6 * want
+    res = ctx.scale(Wd, sk.make_params([p], tol=1e-5, max_iters=2000, check_every=8,
+                                       method="newton"))
+    assert res.status == sk.SK_OK
+    r = res.report
+    assert r["residual_fp64"] < 5e-5 and r["col_residual_fp64"] < 5e-5
+    lu, lv = sk.split_potentials(res.potentials, n)
+    rng = np.random.default_rng(2)
+    rows = np.sort(rng.choice(n, 64, replace=False))
+    cols = np.sort(rng.choice(n, 64, replace=False))
+    u_or = p * oracle.row_step(oracle.log_weights(W[rows]), p, lv / p)
+    v_or = p * oracle.col_step(oracle.log_weights(np.ascontiguousarray(W[:, cols])), p, lu / p)
+    assert np.abs(lu[rows] - u_or).max() < 1e-4
+    assert np.abs(lv[cols] - v_or).max() < 1e-4

@@ -55,21 +55,27 @@ def test_served_results_equal_alone_and_in_the_mix():
 
 def test_served_admission_with_small_arena():
     """An arena that holds about one instance at a time still serves every
-    request (admission waits for memory to free up)."""
+    request (admission waits for memory to free up), and each result is
+    bitwise the one the instance gives alone and the planted optimum."""
     ns = [512, 512, 400, 512]
-    insts = [skgen.uniform_weights(n, 0, 1000, seed=20 + k) for k, n in enumerate(ns)]
-    prm = sk.make_params(LADDER, tol=1e-5, max_iters=300, threshold=1e-4)
+    insts = [skgen.planted(n, seed=20 + k) for k, n in enumerate(ns)]
+    prm = sk.make_params(LADDER, tol=1e-5, max_iters=2000, threshold=1e-4)
+    alone = sk.Context(0)
+    ref = [alone.solve(torch.from_numpy(W).cuda(), prm) for W, _ in insts]
+    alone.close()
     need = int(sk.lib().sk_arena_bytes(512, 0)) + 512 * 512 * 2
-    srv = sk.Context(0, arena_bytes=(64 << 20) * 4 // 4 + 2 * need)
-    tickets = [srv.submit(W, prm) for W in insts]
+    srv = sk.Context(0, arena_bytes=(64 << 20) + 2 * need)
+    tickets = [srv.submit(W, prm) for W, _ in insts]
     res = wait_all(srv, tickets, ns)
     srv.close()
-    for W, (st, perm, weight, rep) in zip(insts, res):
-        assert st in (sk.SK_OK, sk.SK_ENOCONV, sk.SK_EINFEASIBLE)
-        if st != sk.SK_EINFEASIBLE:
-            _, w_opt = oracle.optimum_int(W)
-            assert weight <= w_opt
-            assert rep["ub"] >= w_opt - 1e-6
+    for (W, sigma), r, (st, perm, weight, rep) in zip(insts, ref, res):
+        n = W.shape[0]
+        assert st == sk.SK_OK == r["status"]
+        assert weight == r["weight"] == 1050 * n == oracle.optimum_int(W)[1]
+        assert np.array_equal(perm, sigma) and np.array_equal(perm, r["perm"])
+        assert rep["ub"] == r["report"]["ub"]
+        assert rep["iters_stage"] == r["report"]["iters_stage"]
+        assert rep["residual_fp64"] == r["report"]["residual_fp64"]
 
 
 def test_served_bad_request_does_not_block_others():

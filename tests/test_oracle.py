@@ -524,3 +524,93 @@ def test_newton_equals_sinkhorn_limit():
     Xn, Xs = oracle.scaled_matrix(B, 1.0, ub, vb), oracle.scaled_matrix(B, 1.0, us, vs)
     assert np.abs(Xn - Xs).max() < 1e-10
     assert prods < m / 4
+
+
+# ---------------------------------------------------------------- real log-weights
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 7])
+def test_hungarian_real_vs_brute_force(n):
+    rng = np.random.default_rng(100 + n)
+    for trial in range(6):
+        w = rng.standard_normal((n, n)) * 3.0
+        allowed = rng.random((n, n)) < (0.5 if trial % 2 else 1.0)
+        b = np.where(allowed, w, -np.inf)
+        best, winners = brute.all_optima(b)
+        if best == -math.inf:
+            with pytest.raises(oracle.Infeasible):
+                oracle.hungarian_real(b)
+            continue
+        perm, weight = oracle.hungarian_real(b)
+        assert weight == pytest.approx(best, abs=1e-12)
+        assert tuple(perm) in winners
+
+
+def test_hungarian_real_vs_scipy_and_integer_solver():
+    from scipy.optimize import linear_sum_assignment
+    rng = np.random.default_rng(8)
+    for n in (30, 120, 301):
+        w = -rng.uniform(0.0, 1.7, (n, n))
+        perm, weight = oracle.hungarian_real(w)
+        r, c = linear_sum_assignment(w, maximize=True)
+        assert weight == pytest.approx(w[r, c].sum(), abs=1e-9)
+        assert sorted(perm) == list(range(n))
+        wi = rng.integers(0, 1001, (n, n))
+        assert oracle.hungarian_real(wi.astype(float))[1] == oracle.hungarian(wi)[1]
+
+
+def test_prescale_log_matches_linear_prescale():
+    """Section 4.1.1 on log-weights equals the linear prescaling (pinned
+    above) entry by entry, maps the finite entries onto [0, 1] when
+    max/min > e, and is invariant under entrywise powers A^(q)."""
+    rng = np.random.default_rng(3)
+    A = rng.uniform(0.01, 5.0, (7, 7))
+    A[2, 4] = 0.0
+    B = oracle.log_of(A)
+    Bp, scale = oracle.prescale_log(B)
+    assert scale == pytest.approx(1.0 / (np.log(A[A > 0].max()) - np.log(A[A > 0].min())))
+    assert np.allclose(np.exp(Bp), oracle.prescale(A), atol=1e-13)
+    fin = Bp[np.isfinite(Bp)]
+    assert fin.min() == 0.0 and fin.max() == pytest.approx(1.0, abs=1e-15)
+    for q in (2.0, 7.5):
+        assert np.allclose(oracle.prescale_log(q * B)[0], Bp, atol=1e-13)
+    C = rng.uniform(1.0, 2.0, (4, 4))
+    Cp, s2 = oracle.prescale_log(np.log(C))
+    assert s2 == 1.0 and np.allclose(np.exp(Cp), C / C.min())
+
+
+def test_adaptive_real_equals_integer_loop_without_prescaling():
+    """On integer weights with prescaling off, the real-weight loop takes the
+    same decisions as the integer one (same p, t, weight and log gamma)."""
+    W = skgen.uniform_weights(48, 0, 100, seed=2)
+    lad = [1, 2, 4, 8]
+    for ratio in (0.0, math.e, 1.0 + 1e-12):
+        a, sa = oracle.adaptive(W, lad, 1e-7, 5000, 1e-4, ratio if ratio >= 1 else 1e300)
+        b, sb = oracle.adaptive_real(oracle.log_weights(W), lad, 1e-7, 5000, 1e-4,
+                                     ratio if ratio >= 1 else 1e300, prescale=False)
+        assert sa == sb and a.p == b.p and a.extra["t"] == b.extra["t"]
+        assert a.weight == b.weight and a.log_gamma == pytest.approx(b.log_gamma, abs=1e-9)
+        assert np.array_equal(a.perm, b.perm)
+
+
+def test_adaptive_real_paper_defaults_power_invariance_and_optimum():
+    """Algorithm alg:alg1 with the paper's defaults (p0 = 100, p += 50 on the
+    prescaled matrix, eps = t = 1/n, required ratio 2) on a Euclidean random
+    assignment instance (real log-weights -d): the result does not change
+    when A is replaced by an entrywise power A^(q) (the prescaled matrix is
+    the same, Section 4.1.1); gamma >= 1; and when gamma is within the ratio
+    the reduced matrix's optimum is within log gamma of the optimum of the
+    whole matrix, in the prescaled units."""
+    n = 40
+    x, y = skgen.euclidean_points(n, 3)
+    B = -np.sqrt(((x[:, None, :] - y[None, :, :]) ** 2).sum(axis=2))
+    lad = [100 + 50 * k for k in range(8)]
+    s, st = oracle.adaptive_real(B, lad, 1.0 / n, 20000, 1.0 / n, 2.0)
+    s3, st3 = oracle.adaptive_real(3.0 * B, lad, 1.0 / n, 20000, 1.0 / n, 2.0)
+    assert st == st3 and s.p == s3.p and np.array_equal(s.perm, s3.perm)
+    assert s.log_gamma == pytest.approx(s3.log_gamma, abs=1e-9)
+    assert s.log_gamma >= -1e-9
+    Bp, scale = oracle.prescale_log(B)
+    _, w_all = oracle.hungarian_real(Bp)
+    assert s.weight <= w_all + 1e-12
+    assert w_all - s.weight <= s.log_gamma + 1e-9
+    assert s.extra["weight_orig"] == pytest.approx(B[np.arange(n), s.perm].sum())
