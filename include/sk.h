@@ -243,6 +243,27 @@ sk_status sk_solve_reduced(const sk_csr *csr, int32_t *perm, int64_t *weight);
 sk_status sk_solve(sk_ctx *ctx, const int16_t *W, int32_t n, const sk_params *params,
                    void *potentials, int32_t *perm, int64_t *weight, sk_report *report);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): sk_scale
+ * with its working memory taken from a static device array of the library
+ * instead of the context's arena. The array (SK_STATIC_SCRATCH_BYTES, on each
+ * GPU the library runs on) is resolved by sk_create and held until the
+ * process ends; this call allocates nothing. The caller still passes W and
+ * the potentials (as for sk_scale) and may pass a context created with no
+ * arena (arena_dev_ptr NULL).
+ *   Limit: instances whose working memory (sk_arena_bytes(n, storage))
+ *   exceeds SK_STATIC_SCRATCH_BYTES are rejected with SK_ENOMEM before any
+ *   work is queued: int16 W up to n = 16384 when n is a multiple of 8 (else
+ *   the library's padded copy of W must fit too: n <= 5423), stored BF16 K
+ *   up to n = 5416, stored FP32 K up to n = 3920 (n a multiple of 8).
+ *   Every call on a GPU shares that GPU's array and leaves its contents
+ *   behind (each call initialises what it reads): calls that overlap on one
+ *   GPU, from any contexts or threads, race and must be serialised by the
+ *   caller. Same arguments, statuses and results as sk_scale. */
+#define SK_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+sk_status sk_scale_static(sk_ctx *ctx, const int16_t *W, int32_t n, const sk_params *params,
+                          void *potentials, sk_report *report);
+
 /* Device arena bytes sk_solve needs for this storage when B keeps at most
  * max_kept entries. */
 size_t sk_solve_arena_bytes(int32_t n, int32_t storage, int64_t max_kept);

@@ -26,7 +26,7 @@ SENTINEL = -32768
 EXPORTS = ["sk_potentials_bytes", "sk_arena_bytes", "sk_create", "sk_destroy", "sk_last_error",
            "sk_scale", "sk_prune", "sk_solve_reduced", "sk_submit", "sk_poll", "sk_completed", "sk_scale_batch",
            "sk_batch_arena_bytes", "sk_profile_enable", "sk_profile_read", "sk_set_tile_table",
-           "sk_solve", "sk_solve_arena_bytes"]
+           "sk_solve", "sk_solve_arena_bytes", "sk_scale_static"]
 TILE_TABLE = os.path.join(HERE, "tile_table_gfx950.json")
 
 
@@ -100,6 +100,9 @@ def lib():
         L.sk_last_error.restype = ctypes.c_char_p
         L.sk_scale.argtypes = [vp, vp, i32, ctypes.POINTER(Params), vp, ctypes.POINTER(Report)]
         L.sk_scale.restype = ctypes.c_int
+        L.sk_scale_static.argtypes = [vp, vp, i32, ctypes.POINTER(Params), vp,
+                                      ctypes.POINTER(Report)]
+        L.sk_scale_static.restype = ctypes.c_int
         L.sk_scale_batch.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(i32),
                                      ctypes.POINTER(Params), ctypes.POINTER(vp),
                                      ctypes.POINTER(Report)]
@@ -302,6 +305,19 @@ class Context:
         st = lib().sk_scale(self._ptr, ctypes.c_void_p(W.data_ptr()), n, ctypes.byref(params),
                             ctypes.c_void_p(pot.data_ptr()), ctypes.byref(rep))
         self._check(st, "sk_scale", ok=(SK_OK, SK_ENOCONV))
+        return Result(st, rep.as_dict(), pot)
+
+    def scale_static(self, W, params, potentials=None):
+        """As scale(), through sk_scale_static: the library's static device
+        scratch instead of the context's arena (no device allocation)."""
+        assert W.dtype == self.torch.int16 and W.is_cuda and W.is_contiguous()
+        n = W.shape[0]
+        pot = potentials if potentials is not None else self.new_potentials(n)
+        rep = Report()
+        st = lib().sk_scale_static(self._ptr, ctypes.c_void_p(W.data_ptr()), n,
+                                   ctypes.byref(params), ctypes.c_void_p(pot.data_ptr()),
+                                   ctypes.byref(rep))
+        self._check(st, "sk_scale_static", ok=(SK_OK, SK_ENOCONV))
         return Result(st, rep.as_dict(), pot)
 
     def scale_batch(self, Ws, params, potentials=None):

@@ -216,10 +216,13 @@ void report_from_check(const double *out4, int p, sk_report *rep);
 void fill_report(const Ctl &c, sk_report *rep);
 sk_status copy_potentials_out(sk_ctx *ctx, Batch &B, int k, void *pot);
 // Scales `count` instances with their working memory carved from
-// [arena, arena + arena_bytes).
+// [arena, arena + arena_bytes) (the context's arena, or the static scratch).
 sk_status scale_impl(sk_ctx *ctx, int count, const int16_t *const *W, const int32_t *n,
                      const sk_params *prm, void *const *pot, sk_report *reports, char *arena,
                      size_t arena_bytes);
+// Resolves the device address of the static scratch on `device` (the current
+// device), once per device; sk_create calls it.
+hipError_t static_scratch_init(int device);
 void serve_stop(sk_ctx *ctx);
 bool serving(const sk_ctx *ctx);
 hipError_t set_k_attributes();

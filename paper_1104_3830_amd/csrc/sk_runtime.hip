@@ -247,6 +247,8 @@ sk_status sk_create(sk_ctx **out, int device, void *hip_stream, void *arena_dev_
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return SK_EDEVICE;
     if (hipSetDevice(device) != hipSuccess) return SK_EDEVICE;
+    // the static scratch of sk_scale_static: its address on this device
+    if (static_scratch_init(device) != hipSuccess) return SK_EDEVICE;
     {
         std::lock_guard<std::mutex> g(g_attr_mu);
         if (!g_attr_done) {
