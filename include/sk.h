@@ -98,7 +98,14 @@ typedef enum {
  *                  conjugate-gradient inner solves, until max_i |1 - (x o S
  *                  x)_i| <= tol; max_iters_per_stage then bounds the products
  *                  with S per stage (reported as iterations). One int16
- *                  instance, not fused, not deformed. */
+ *                  instance, not fused, not deformed.
+ *   prescale     : real-valued entry points only (0 elsewhere). 1 = p acts on
+ *                  the prescaled matrix of Section 4.1.1 (the one Algorithm
+ *                  alg:alg1 scales): with w_min, w_max the smallest and
+ *                  largest finite log-weights, p on A' = A^(m)/c equals
+ *                  p / (w_max - w_min) on A when w_max - w_min > 1 (max/min
+ *                  > e), else p (A' = A / min(A)); gamma (eq. optratio) is
+ *                  then the prescaled matrix's. 0 = p acts on A. */
 typedef struct {
     int32_t p_ladder[SK_MAX_LADDER];
     int32_t n_p;
@@ -112,6 +119,7 @@ typedef struct {
     int32_t fused;
     double deform_a;
     int32_t method;
+    int32_t prescale;
 } sk_params;
 
 enum { SK_SINKHORN = 0, SK_NEWTON = 1 };
@@ -140,6 +148,8 @@ typedef struct {
     int32_t stages_evaluated;  /* stages whose B and gamma were formed */
     int32_t optimal_proved;    /* 1 if ub - w(B) < 1: with integer weights no
                                   permutation of A weighs more than w(B) */
+    double p_scale;            /* the stage's p is p_final * p_scale (1 unless
+                                  the real-valued path prescales) */
 } sk_report;
 
 /* Potentials (scalings) of one instance, in device memory, 16*n bytes laid
@@ -263,6 +273,51 @@ sk_status sk_solve(sk_ctx *ctx, const int16_t *W, int32_t n, const sk_params *pa
 #define SK_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
 sk_status sk_scale_static(sk_ctx *ctx, const int16_t *W, int32_t n, const sk_params *params,
                           void *potentials, sk_report *report);
+
+/* Real-valued log-weights (Section 5's Euclidean random assignment, and
+ * Algorithm alg:alg1 with its own p schedule on the prescaled matrix,
+ * Section 4.1.1). W is float32 log A, row-major, pitch n, with -INFINITY for
+ * a_ij = 0 (NaN and +inf are rejected). p = p_ladder[k] * (prescale ?
+ * 1 / (w_max - w_min) : 1) need not be an integer. Each term
+ * exp(p (w_ij - w_max) + log u_i + log v_j) has its exponent formed in FP64
+ * and split exactly into a power of two and a fraction in [-1/2, 1/2] whose
+ * exp2 is taken in FP32 (about 2 FP32 ulp per term); row and column sums
+ * accumulate in FP32, the recheck and certificate in FP64. The potentials
+ * have the int16 path's layout, for the shifted weights: x_ij =
+ * exp(p (w_ij - w_max) + log u_i + log v_j), w_max the largest finite w.
+ * params: storage SK_W_I16 (the sweeps read W), not fused, not deformed,
+ * Sinkhorn; ub and weights are in the units of W. One instance per call.
+ * Errors as for sk_scale / sk_solve; SK_EINVAL for a NaN or +inf weight. */
+typedef struct {
+    int32_t n;
+    int64_t nnz;
+    int64_t *row_ptr;
+    int32_t *col;
+    float *w;
+} sk_csr_real;
+
+/* Device arena bytes sk_scale_real / sk_solve_real need at size n when the
+ * reduced matrix keeps at most max_kept entries (0 for sk_scale_real). */
+size_t sk_real_arena_bytes(int32_t n, int64_t max_kept);
+
+/* sk_scale for real-valued log-weights. W: DEVICE float[n*n]. */
+sk_status sk_scale_real(sk_ctx *ctx, const float *W, int32_t n, const sk_params *params,
+                        void *potentials, sk_report *report);
+
+/* sk_solve for real-valued log-weights (Algorithm alg:alg1 with
+ * opt_ratio >= 1): per stage the FP64 certificate, the reduced matrix at t,
+ * an exact optimum of it on the host (sk_solve_reduced_real) and log gamma =
+ * s (ub - w(B)) with s = p_scale when params->prescale (the prescaled
+ * matrix's gamma), else 1. *weight = w(B) = sum_i W[i][perm[i]] in FP64.
+ * optimal_proved stays 0 (no integrality). */
+sk_status sk_solve_real(sk_ctx *ctx, const float *W, int32_t n, const sk_params *params,
+                        void *potentials, int32_t *perm, double *weight, sk_report *report);
+
+/* Exact maximum-weight perfect matching of a real-weight reduced instance
+ * (HOST buffers), by shortest augmenting paths (Dijkstra with potentials) in
+ * FP64: optimal up to the rounding of the sums. SK_EINFEASIBLE without a
+ * perfect matching. Thread-safe. */
+sk_status sk_solve_reduced_real(const sk_csr_real *csr, int32_t *perm, double *weight);
 
 /* Device arena bytes sk_solve needs for this storage when B keeps at most
  * max_kept entries. */

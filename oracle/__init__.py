@@ -386,12 +386,13 @@ def adaptive_real(B, ladder, eps, max_iters, t, opt_ratio, prescale=True):
     lowered tenfold, at most three times. Returns (Solution, status) as
     adaptive(); Solution.weight is w(B) in the prescaled units and
     Solution.extra holds t, the number of evaluated p, the p factor of the
-    prescaling and the weight in the original units."""
+    prescaling, the weight in the original units and (p, log gamma) of every
+    evaluated p."""
     B = np.asarray(B, dtype=np.float64)
     n = B.shape[0]
     Bp, scale = prescale_log(B) if prescale else (np.ascontiguousarray(B), 1.0)
     ubar, vbar = np.zeros(n), np.zeros(n)
-    best, evaluated, iters_all, res_all = None, 0, [], []
+    best, evaluated, iters_all, res_all, gammas = None, 0, [], [], []
     for k, p in enumerate(ladder):
         ubar, vbar, it, res = sinkhorn(Bp, p, eps, max_iters, ubar, vbar)
         iters_all.append(it)
@@ -410,6 +411,7 @@ def adaptive_real(B, ladder, eps, max_iters, t, opt_ratio, prescale=True):
                     break
                 tt /= 10.0
         evaluated += 1
+        gammas.append((float(p), ub - weight if weight is not None else math.inf))
         if weight is not None:
             lg = ub - weight
             if best is None or lg < best.log_gamma:
@@ -419,10 +421,12 @@ def adaptive_real(B, ladder, eps, max_iters, t, opt_ratio, prescale=True):
                                 {"t": tt, "p_scale": scale, "weight_orig": w_orig})
             if best.log_gamma <= np.log(opt_ratio):
                 best.extra["evaluated"] = evaluated
+                best.extra["gammas"] = gammas
                 return best, "ok"
     if best is None:
         return None, "infeasible"
     best.extra["evaluated"] = evaluated
+    best.extra["gammas"] = gammas
     return best, "ratio"
 
 

@@ -26,7 +26,8 @@ SENTINEL = -32768
 EXPORTS = ["sk_potentials_bytes", "sk_arena_bytes", "sk_create", "sk_destroy", "sk_last_error",
            "sk_scale", "sk_prune", "sk_solve_reduced", "sk_submit", "sk_poll", "sk_completed", "sk_scale_batch",
            "sk_batch_arena_bytes", "sk_profile_enable", "sk_profile_read", "sk_set_tile_table",
-           "sk_solve", "sk_solve_arena_bytes", "sk_scale_static"]
+           "sk_solve", "sk_solve_arena_bytes", "sk_scale_static", "sk_real_arena_bytes",
+           "sk_scale_real", "sk_solve_real", "sk_solve_reduced_real"]
 TILE_TABLE = os.path.join(HERE, "tile_table_gfx950.json")
 
 
@@ -43,7 +44,8 @@ class Params(ctypes.Structure):
                 ("check_every", ctypes.c_int32), ("threshold", ctypes.c_double),
                 ("storage", ctypes.c_int32), ("opt_ratio", ctypes.c_double),
                 ("warm_start", ctypes.c_int32), ("fused", ctypes.c_int32),
-                ("deform_a", ctypes.c_double), ("method", ctypes.c_int32)]
+                ("deform_a", ctypes.c_double), ("method", ctypes.c_int32),
+                ("prescale", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):
@@ -56,7 +58,7 @@ class Report(ctypes.Structure):
                 ("nnz_kept", ctypes.c_int64), ("absorbs", ctypes.c_int32),
                 ("seconds", ctypes.c_double), ("log_gamma", ctypes.c_double),
                 ("threshold_used", ctypes.c_double), ("stages_evaluated", ctypes.c_int32),
-                ("optimal_proved", ctypes.c_int32)]
+                ("optimal_proved", ctypes.c_int32), ("p_scale", ctypes.c_double)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "iters_stage"}
@@ -72,6 +74,9 @@ class KernelStat(ctypes.Structure):
 class CSR(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int64),
                 ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("w", ctypes.c_void_p)]
+
+
+CSRReal = CSR  # same layout; w points to float32
 
 
 _lib = None
@@ -103,6 +108,16 @@ def lib():
         L.sk_scale_static.argtypes = [vp, vp, i32, ctypes.POINTER(Params), vp,
                                       ctypes.POINTER(Report)]
         L.sk_scale_static.restype = ctypes.c_int
+        L.sk_real_arena_bytes.argtypes = [i32, i64]
+        L.sk_real_arena_bytes.restype = sz
+        L.sk_scale_real.argtypes = [vp, vp, i32, ctypes.POINTER(Params), vp, ctypes.POINTER(Report)]
+        L.sk_scale_real.restype = ctypes.c_int
+        L.sk_solve_real.argtypes = [vp, vp, i32, ctypes.POINTER(Params), vp, ctypes.POINTER(i32),
+                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(Report)]
+        L.sk_solve_real.restype = ctypes.c_int
+        L.sk_solve_reduced_real.argtypes = [ctypes.POINTER(CSRReal), ctypes.POINTER(i32),
+                                            ctypes.POINTER(ctypes.c_double)]
+        L.sk_solve_reduced_real.restype = ctypes.c_int
         L.sk_scale_batch.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(i32),
                                      ctypes.POINTER(Params), ctypes.POINTER(vp),
                                      ctypes.POINTER(Report)]
@@ -153,7 +168,7 @@ def load_tile_table(path):
 
 def make_params(ladder, tol=1e-5, max_iters=20000, check_every=32, threshold=1e-4,
                 storage="i16", opt_ratio=0.0, warm_start=False, fused=False,
-                deform_a=0.0, method="sinkhorn") -> Params:
+                deform_a=0.0, method="sinkhorn", prescale=False) -> Params:
     p = Params()
     ladder = [int(x) for x in ladder]
     if not 1 <= len(ladder) <= MAX_LADDER:
@@ -171,7 +186,18 @@ def make_params(ladder, tol=1e-5, max_iters=20000, check_every=32, threshold=1e-
     p.fused = 1 if fused else 0
     p.deform_a = float(deform_a)
     p.method = {"sinkhorn": 0, "newton": 1}[method] if isinstance(method, str) else int(method)
+    p.prescale = 1 if prescale else 0
     return p
+
+
+def paper_params(n, ladder=None, opt_ratio=2.0, max_iters=100000, check_every=32) -> Params:
+    """Algorithm alg:alg1's defaults (Section 4.2): p0 = 100 raised by 50 per
+    round on the prescaled matrix (Section 4.1.1), eps = t = 1/n; the
+    experiments' required ratio is about 2. The ladder holds the 32 rounds
+    p = 100, 150, ..., 1650 unless given."""
+    lad = ladder if ladder is not None else [100 + 50 * k for k in range(MAX_LADDER)]
+    return make_params(lad, tol=1.0 / n, max_iters=max_iters, check_every=check_every,
+                       threshold=1.0 / n, opt_ratio=opt_ratio, prescale=True)
 
 
 def potentials_bytes(n):
@@ -215,6 +241,25 @@ def solve_reduced(row_ptr, col, w, n):
                                 ctypes.byref(weight))
     if st != SK_OK:
         raise SkError(st, "sk_solve_reduced")
+    return perm, weight.value
+
+
+def solve_reduced_real(row_ptr, col, w, n):
+    """Exact max-weight perfect matching of a host CSR instance with real
+    (float32) weights. Returns (perm, weight); raises SkError(SK_EINFEASIBLE)
+    without a matching."""
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    csr = CSRReal(int(n), int(row_ptr[-1]) if len(row_ptr) else 0, row_ptr.ctypes.data,
+                  col.ctypes.data if col.size else None, w.ctypes.data if w.size else None)
+    perm = np.empty(int(n), dtype=np.int32)
+    weight = ctypes.c_double(0.0)
+    st = lib().sk_solve_reduced_real(ctypes.byref(csr),
+                                     perm.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                     ctypes.byref(weight))
+    if st != SK_OK:
+        raise SkError(st, "sk_solve_reduced_real")
     return perm, weight.value
 
 
@@ -319,6 +364,44 @@ class Context:
                                    ctypes.byref(rep))
         self._check(st, "sk_scale_static", ok=(SK_OK, SK_ENOCONV))
         return Result(st, rep.as_dict(), pot)
+
+    def scale_real(self, W, params, potentials=None):
+        """Real-valued log-weights: W float32 CUDA tensor (n, n), -inf for a
+        zero entry. Returns Result; status SK_OK or SK_ENOCONV."""
+        assert W.dtype == self.torch.float32 and W.is_cuda and W.is_contiguous()
+        n = int(W.shape[0])
+        self.ensure_arena(lib().sk_real_arena_bytes(n, 0))
+        pot = potentials if potentials is not None else self.new_potentials(n)
+        rep = Report()
+        st = lib().sk_scale_real(self._ptr, ctypes.c_void_p(W.data_ptr()), n, ctypes.byref(params),
+                                 ctypes.c_void_p(pot.data_ptr()), ctypes.byref(rep))
+        self._check(st, "sk_scale_real", ok=(SK_OK, SK_ENOCONV))
+        return Result(st, rep.as_dict(), pot)
+
+    def solve_real(self, W, params, potentials=None, max_kept=None):
+        """Algorithm alg:alg1 on real-valued log-weights through sk_solve_real
+        (see paper_params for the paper's defaults). Returns a dict as
+        solve(); weight is a float."""
+        assert W.dtype == self.torch.float32 and W.is_cuda and W.is_contiguous()
+        n = int(W.shape[0])
+        kept = int(max_kept) if max_kept is not None else n * n
+        pot = potentials if potentials is not None else self.new_potentials(n)
+        perm = np.empty(n, dtype=np.int32)
+        self.ensure_arena(lib().sk_real_arena_bytes(n, kept))
+        weight = ctypes.c_double(0.0)
+        rep = Report()
+        st = lib().sk_solve_real(self._ptr, ctypes.c_void_p(W.data_ptr()), n, ctypes.byref(params),
+                                 ctypes.c_void_p(pot.data_ptr()),
+                                 perm.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                 ctypes.byref(weight), ctypes.byref(rep))
+        self._check(st, "sk_solve_real", ok=(SK_OK, SK_ENOCONV, SK_EINFEASIBLE))
+        r = rep.as_dict()
+        out = dict(status=st, report=r, nnz=int(r["nnz_kept"]), potentials=pot)
+        if st == SK_EINFEASIBLE:
+            out.update(perm=None, weight=None, log_gamma=None)
+        else:
+            out.update(perm=perm, weight=float(weight.value), log_gamma=r["log_gamma"])
+        return out
 
     def scale_batch(self, Ws, params, potentials=None):
         """Ws: list of int16 CUDA tensors. Returns list of Result (shared status)."""

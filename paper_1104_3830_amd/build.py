@@ -9,9 +9,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsk.so")
 SOURCES = ["sk_kernels.hip", "sk_rowshort.hip", "sk_fused.hip", "sk_runtime.hip", "sk_kpath.hip",
-           "sk_static.hip",
+           "sk_static.hip", "sk_real.hip",
            "sk_solver.cpp",
-           "sk_serve.cpp", "sk_solve.cpp", "sk_newton.cpp"]
+           "sk_serve.cpp", "sk_solve.cpp", "sk_newton.cpp", "sk_realhost.cpp"]
 ARCH = os.environ.get("SK_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are kept out of the generated code.

@@ -19,6 +19,7 @@ constexpr int kMaxSegRows = 1024;
 constexpr int kShortRowN = 2048;  // batches up to this n take the short-row row sweep
 constexpr int kFusedSlots = 256;  // workgroups (and column-partial slots) of the fused kernel
 constexpr int kMaxRowGrid = 1024;  // row-sweep workgroups (bounds table sized for it)
+constexpr int kRealTile = 256;     // columns per column tile of the real-weight sweeps
 
 // Column count of the 8-wide layout: n rounded up to a multiple of 8.
 __host__ __device__ constexpr int pad8(int n) { return (n + 7) & ~7; }
@@ -103,6 +104,17 @@ struct Inst {
     // else nullptr; copied once per batch before the input scan
     const int16_t *Wsrc;
     int64_t src_pitch;
+    // real-valued log-weights (sk_scale_real / sk_solve_real): n x n float32,
+    // row pitch `pitch` elements, -inf for a_ij = 0; nullptr for int16 W.
+    // The sweeps use w_ij - wref (wref = the largest finite weight; a common
+    // shift of the log-weights leaves X(p) unchanged), so the potentials stay
+    // within a few p times the weight range.
+    const float *Wr;
+    float wref;
+    int32_t pad2;
+    // p of the current stage is ctl->p * pscale: 1 for int16 W; with the
+    // prescaling of Section 4.1.1, 1 / (w_max - w_min) when that exceeds 1
+    double pscale;
 };
 constexpr int kRowResSlots = 64;    // = kWave: one wave reduces them
 constexpr int kRowResStride = 32;   // one 128-byte line per slot
@@ -249,6 +261,23 @@ hipError_t launch_check_k(const Inst *d_insts, const RowUnit *d_units, int nunit
 hipError_t launch_fused(const Inst *d_insts, int inst, int n, int grid, int storage, int nt_loads,
                         hipStream_t st);
 hipError_t launch_gather_ctl(const Inst *d_insts, int count, Ctl *out, hipStream_t st);
+// real-valued log-weights (sk_real.hip)
+hipError_t launch_real_minmax(const float *W, int n, int64_t pitch, int grid, float *part,
+                              hipStream_t st);
+hipError_t launch_init_real(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid, int cold,
+                            hipStream_t st);
+hipError_t launch_row_sweep_real(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
+                                 size_t lds_bytes, int nt_loads, int vec4, hipStream_t st,
+                                 hipEvent_t stop = nullptr);
+hipError_t launch_col_sweep_real(const Inst *d_insts, const ColUnit *d_units, int nunits, int grid,
+                                 int nt_loads, int vec4, hipStream_t st, hipEvent_t stop = nullptr);
+hipError_t launch_check_real(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid, int inst,
+                             int n, int nseg, double *rsum, double *rmax, double logt, int64_t *counts,
+                             int32_t *hint, double *part, double *csum, hipStream_t st);
+hipError_t launch_prune_fill_real(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
+                                  double logt, const int64_t *row_ptr, int32_t *col, float *w, int n,
+                                  hipStream_t st);
+hipError_t set_real_attributes();
 hipError_t launch_reset_ctl(const Inst *d_insts, const int *idx, int m, hipStream_t st);
 hipError_t set_kernel_attributes();
 

@@ -17,6 +17,7 @@
 //                                        r_i = exp(phi_i) S_i.
 #include <algorithm>
 
+#include "sk_real.h"
 #include "sk_rowsweep.h"
 
 namespace sk {
@@ -476,7 +477,13 @@ __global__ __launch_bounds__(kIterEndThreads) void k_iter_end(const Inst *__rest
     const int iter = ctl->iter;
     const int npar = (iter + 1) & 1;
     const int p4 = 4 * ctl->p;
-    const unsigned nres = conv ? 0u : ctl->rescue_cnt;
+    unsigned nres = conv ? 0u : ctl->rescue_cnt;
+    if (I.Wr) {
+        // real-valued log-weights: the same recompute with FP64 exponents
+        __shared__ double redd[kIterEndThreads];
+        for (unsigned q = 0; q < nres; ++q) real_rescue_column(I, ctl, (int)I.rescue[q], npar, redd);
+        nres = 0u;
+    }
     if (nres > 0u) fill_exp_table(tab);
     // exact max-shifted recompute (Section 4.1.2) of the columns whose sum
     // left the safe range: M = max_i (p w_ij + F_i + G_j), then

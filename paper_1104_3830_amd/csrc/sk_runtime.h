@@ -165,11 +165,14 @@ sk_status fail(sk_ctx *ctx, sk_status st, const char *fmt, ...);
         (ctx)->prof.end((ctx)->stream);             \
         return e__;                                 \
     }())
-sk_status check_params(sk_ctx *ctx, const sk_params *p);
+// real: the parameters of a real-valued entry point (prescale allowed; two
+// sweeps, Sinkhorn, W read directly)
+sk_status check_params(sk_ctx *ctx, const sk_params *p, bool real = false);
 sk_status check_range(sk_ctx *ctx, const sk_params *prm);  // p small enough for exact exponents
 sk_status status_of(const Ctl &c);  // SK_OK, SK_ENOCONV (a stage capped) or SK_ENOSUPPORT
+// Wr != nullptr: a real-valued instance (W unused; Wr read with pitch `pitch`).
 bool carve_instance(Bump &bump, const int16_t *W, int64_t pitch, int32_t n, const sk_params *prm,
-                    Inst &I);
+                    Inst &I, const float *Wr = nullptr);
 sk_status finish_tables(sk_ctx *ctx, Bump &bump, Batch &B);
 sk_status plan_batch(sk_ctx *ctx, Bump &bump, int count, const int16_t *const *W,
                      const int64_t *pitch, const int32_t *n, const sk_params *prm, Batch &B);
@@ -212,7 +215,9 @@ sk_status solve_reduced_seeded(const sk_csr *csr, const int32_t *hint, int32_t *
 sk_status check_fp64(sk_ctx *ctx, Batch &B, int k, sk_report *rep);
 // writes B.d_checkout[k] (and the counts when cc != nullptr)
 sk_status enqueue_check(sk_ctx *ctx, Batch &B, int k, const CheckCounts *cc = nullptr);
-void report_from_check(const double *out4, int p, sk_report *rep);
+// p: the stage's p (ctl.p * pscale); wref: the common shift of a real-valued
+// instance's log-weights (0 for int16 W), added back to the certificate.
+void report_from_check(const double *out4, double p, sk_report *rep, int n = 0, double wref = 0.0);
 void fill_report(const Ctl &c, sk_report *rep);
 sk_status copy_potentials_out(sk_ctx *ctx, Batch &B, int k, void *pot);
 // Scales `count` instances with their working memory carved from

@@ -254,6 +254,7 @@ sk_status sk_create(sk_ctx **out, int device, void *hip_stream, void *arena_dev_
         if (!g_attr_done) {
             if (set_kernel_attributes() != hipSuccess) return SK_EDEVICE;
             if (set_k_attributes() != hipSuccess) return SK_EDEVICE;
+            if (set_real_attributes() != hipSuccess) return SK_EDEVICE;
             g_attr_done = true;
         }
     }
@@ -302,7 +303,7 @@ sk_status sk::fail(sk_ctx *ctx, sk_status st, const char *fmt, ...) {
     return st;
 }
 
-sk_status sk::check_params(sk_ctx *ctx, const sk_params *p) {
+sk_status sk::check_params(sk_ctx *ctx, const sk_params *p, bool real) {
     if (!p) return fail(ctx, SK_EINVAL, "params is NULL");
     if (p->n_p < 1 || p->n_p > SK_MAX_LADDER)
         return fail(ctx, SK_EINVAL, "n_p must be in [1, %d]", SK_MAX_LADDER);
@@ -319,6 +320,13 @@ sk_status sk::check_params(sk_ctx *ctx, const sk_params *p) {
     if (p->method != SK_SINKHORN && p->method != SK_NEWTON) return fail(ctx, SK_EINVAL, "bad method");
     if (p->method == SK_NEWTON && (p->storage != SK_W_I16 || p->fused || p->deform_a > 0.0))
         return fail(ctx, SK_EINVAL, "Newton scaling runs on int16 W, two-pass, undeformed");
+    if (p->prescale != 0 && p->prescale != 1) return fail(ctx, SK_EINVAL, "prescale must be 0 or 1");
+    if (!real && p->prescale)
+        return fail(ctx, SK_EINVAL, "prescaling needs real-valued weights (sk_scale_real / sk_solve_real)");
+    if (real && (p->storage != SK_W_I16 || p->fused || p->deform_a > 0.0 || p->method != SK_SINKHORN))
+        return fail(ctx, SK_EINVAL,
+                    "real-valued weights run the two-sweep Sinkhorn iteration on W (storage 0, not fused, "
+                    "not deformed)");
     return SK_OK;
 }
 
@@ -326,16 +334,23 @@ sk_status sk::check_params(sk_ctx *ctx, const sk_params *p) {
 
 // Fills the descriptor of one instance and carves its buffers from `bump`.
 bool sk::carve_instance(Bump &bump, const int16_t *W, int64_t pitch, int32_t nn,
-                        const sk_params *prm, Inst &I) {
+                        const sk_params *prm, Inst &I, const float *Wr) {
     I = Inst{};
     I.W = W;
     I.pitch = pitch;
     I.n = nn;
+    I.pscale = 1.0;
     // 8-wide loads read whole aligned 16-byte chunks up to column pad8(n):
     // inside each row when pitch >= pad8(n), and for the last row inside the
     // aligned chunk that holds its last entry
     I.vec8 = (pitch % 8 == 0) && (pitch >= pad8(nn)) && ((uintptr_t)W % 16 == 0);
-    if (!I.vec8 && nn % 8 != 0) {
+    if (Wr) {
+        // real-valued: 16-byte loads of 4 floats when every row is whole
+        // 16-byte chunks
+        I.W = nullptr;
+        I.Wr = Wr;
+        I.vec8 = (nn % 4 == 0) && (pitch % 4 == 0) && ((uintptr_t)Wr % 16 == 0);
+    } else if (!I.vec8 && nn % 8 != 0) {
         // the library's padded copy (filled by k_pad_copy before the input scan)
         int16_t *cp = bump.take<int16_t>((size_t)nn * pad8(nn));
         if (!cp) return false;
@@ -345,7 +360,11 @@ bool sk::carve_instance(Bump &bump, const int16_t *W, int64_t pitch, int32_t nn,
         I.pitch = pad8(nn);
         I.vec8 = 1;
     }
-    TilePlan t = plan_tiles(nn, I.vec8);
+    TilePlan t = plan_tiles(nn, Wr ? 1 : I.vec8);
+    if (Wr) {
+        t.tile_cols = kRealTile;
+        t.ntiles = (nn + kRealTile - 1) / kRealTile;
+    }
     I.nseg = t.nseg;
     I.seg_rows = t.seg_rows;
     I.ntiles = t.ntiles;
@@ -397,7 +416,7 @@ sk_status sk::finish_tables(sk_ctx *ctx, Bump &bump, Batch &B) {
     // cannot stay in the last-level cache between passes
     size_t mbytes = 0;
     for (const Inst &I : B.h_insts) {
-        const size_t es = I.storage == SK_K_F32 ? 4 : 2;
+        const size_t es = (I.storage == SK_K_F32 || I.Wr) ? 4 : 2;
         mbytes += es * (size_t)I.n * (size_t)(I.storage == SK_W_I16 ? I.pitch : (I.n + 7) / 8 * 8);
     }
     for (Inst &I : B.h_insts) I.nt = mbytes > kNtBytes ? 1 : 0;
@@ -523,8 +542,12 @@ sk_status sk::start_batch(sk_ctx *ctx, Batch &B, const sk_params *prm, void *con
                                        hipMemcpyDeviceToDevice, ctx->stream));
         }
     }
-    HIPCHK(ctx, PROF(ctx, KID_INIT, launch_init(B.d_insts, B.d_rows, (int)B.h_rows.size(), B.row_grid,
-                            prm->warm_start ? 0 : 1, ctx->stream)));
+    if (B.h_insts[0].Wr)
+        HIPCHK(ctx, PROF(ctx, KID_INIT, launch_init_real(B.d_insts, B.d_rows, (int)B.h_rows.size(),
+                                                         B.row_grid, prm->warm_start ? 0 : 1, ctx->stream)));
+    else
+        HIPCHK(ctx, PROF(ctx, KID_INIT, launch_init(B.d_insts, B.d_rows, (int)B.h_rows.size(), B.row_grid,
+                                                    prm->warm_start ? 0 : 1, ctx->stream)));
     return SK_OK;
 }
 
@@ -562,11 +585,20 @@ sk_status sk::iterate_i16(sk_ctx *ctx, Batch &B, bool chained) {
     const int nt = B.count > 0 ? B.h_insts[0].nt : 0;  // the same for the whole batch
     int s1, s2, s3;
     hipEvent_t e1 = pf.kernel_stamp(&s1);
-    HIPCHK(ctx, launch_row_sweep(B.d_insts, B.d_rows, (int)B.h_rows.size(), B.d_row_bounds,
-                                 B.row_grid, B.row_lds, nt, B.nmax <= kShortRowN, ctx->stream, e1));
+    const Inst &I0 = B.h_insts[0];
+    if (I0.Wr)
+        HIPCHK(ctx, launch_row_sweep_real(B.d_insts, B.d_rows, (int)B.h_rows.size(), B.row_grid,
+                                          B.row_lds, nt, I0.vec8, ctx->stream, e1));
+    else
+        HIPCHK(ctx, launch_row_sweep(B.d_insts, B.d_rows, (int)B.h_rows.size(), B.d_row_bounds,
+                                     B.row_grid, B.row_lds, nt, B.nmax <= kShortRowN, ctx->stream, e1));
     hipEvent_t e2 = pf.kernel_stamp(&s2);
-    HIPCHK(ctx, launch_col_sweep(B.d_insts, B.d_cols, (int)B.h_cols.size(), B.col_grid, nt,
-                                 ctx->stream, e2));
+    if (I0.Wr)
+        HIPCHK(ctx, launch_col_sweep_real(B.d_insts, B.d_cols, (int)B.h_cols.size(), B.col_grid, nt,
+                                          I0.vec8, ctx->stream, e2));
+    else
+        HIPCHK(ctx, launch_col_sweep(B.d_insts, B.d_cols, (int)B.h_cols.size(), B.col_grid, nt,
+                                     ctx->stream, e2));
     pf.add(KID_ROW, s0, s1);
     pf.add(KID_COL, s1, s2);
     HIPCHK(ctx, launch_col_finalize(B.d_insts, B.d_fins, (int)B.h_fins.size(), B.fin_grid, 0,
@@ -662,6 +694,16 @@ sk_status sk::enqueue_check(sk_ctx *ctx, Batch &B, int k, const CheckCounts *cc)
     while (first < B.h_rows.size() && B.h_rows[first].inst != k) ++first;
     const int nunits = (nn + kRowWaves - 1) / kRowWaves;
     const int grid = std::min(nunits, ctx->num_cus * 2);
+    if (I.Wr) {
+        HIPCHK(ctx, PROF(ctx, KID_CHECK_ROWS,
+                         launch_check_real(B.d_insts, B.d_rows + first, nunits, grid, k, nn, I.nseg,
+                                           B.d_rsum, B.d_rmax, cc ? cc->logt : 0.0,
+                                           cc ? cc->counts : nullptr, cc ? cc->hint : nullptr,
+                                           B.d_cpart, B.d_csum, ctx->stream)));
+        HIPCHK(ctx, launch_check_reduce(B.d_insts, k, B.d_rsum, B.d_rmax, B.d_csum,
+                                        B.d_checkout + 4 * (size_t)k, ctx->stream));
+        return SK_OK;
+    }
     HIPCHK(ctx, PROF(ctx, KID_CHECK_ROWS,
                      launch_check_rows(B.d_insts, B.d_rows + first, nunits, grid, B.d_rsum,
                                        B.d_rmax, cc ? cc->logt : 0.0, cc ? cc->counts : nullptr,
@@ -676,12 +718,12 @@ sk_status sk::enqueue_check(sk_ctx *ctx, Batch &B, int k, const CheckCounts *cc)
 
 // Proposition prop:aoc with log d_r = log u, log d_c = log v: log u cancels,
 // UB = p^-1 (sum_i max_j (p w_ij + log v_j) - sum_j log v_j).
-void sk::report_from_check(const double *o, int p, sk_report *rep) {
+void sk::report_from_check(const double *o, double p, sk_report *rep, int n, double wref) {
     rep->residual_fp64 = o[0];
     rep->col_residual_fp64 = o[1];
     rep->residual_exact_fp64 = o[0];
     rep->col_residual_exact_fp64 = o[1];
-    rep->ub = (o[2] - o[3]) / (double)p;
+    rep->ub = (o[2] - o[3]) / p + (double)n * wref;
 }
 
 sk_status sk::check_fp64(sk_ctx *ctx, Batch &B, int k, sk_report *rep) {

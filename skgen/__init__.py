@@ -35,6 +35,7 @@ TAG_SIZES = 5
 TAG_ARRIVALS = 6
 TAG_OFFDIAG = 7
 TAG_POINTS = 8
+TAG_REAL = 9
 
 
 def _mix(z: np.ndarray) -> np.ndarray:
@@ -168,3 +169,26 @@ def euclidean(n: int, seed: int, scale: int = 1000, chunk_rows: int = 1024):
         d = np.sqrt(((x[r:r + chunk_rows, None, :] - y[None, :, :]) ** 2).sum(axis=2))
         W[r:r + chunk_rows] = -np.rint(scale * d).astype(np.int16)
     return W, x, y
+
+
+def euclidean_real(n: int, seed: int, chunk_rows: int = 1024):
+    """The Euclidean random assignment workload with real log-weights:
+    w_ij = -d(x_i, y_j) as float32 (a_ij = exp(-d)), no quantisation.
+    Returns (W, x, y)."""
+    x, y = euclidean_points(n, seed)
+    W = np.empty((n, n), dtype=np.float32)
+    for r in range(0, n, chunk_rows):
+        d = np.sqrt(((x[r:r + chunk_rows, None, :] - y[None, :, :]) ** 2).sum(axis=2))
+        W[r:r + chunk_rows] = (-d).astype(np.float32)
+    return W
+
+
+def uniform_real(n: int, seed: int, chunk_rows: int = 1024):
+    """A matrix with entries uniform on (0, 1] given by its log-weights
+    w_ij = log a_ij (float32), the random matrix of Section 5's experiments."""
+    W = np.empty((n, n), dtype=np.float32)
+    for r in range(0, n, chunk_rows):
+        rows = min(chunk_rows, n - r)
+        u = unit(stream(seed, TAG_REAL, rows * n, offset=r * n)).reshape(rows, n)
+        W[r:r + rows] = np.log1p(-u).astype(np.float32)
+    return W

@@ -43,6 +43,8 @@ int main(void) {{
   printf("%zu %zu %zu %zu %zu\\n", offsetof(sk_params, tol), offsetof(sk_params, storage),
          offsetof(sk_params, warm_start), offsetof(sk_params, fused), offsetof(sk_report, seconds));
   printf("%zu %zu\\n", offsetof(sk_report, nnz_kept), offsetof(sk_csr, w));
+  printf("%zu %zu %zu %zu\\n", offsetof(sk_params, prescale), offsetof(sk_report, p_scale),
+         sizeof(sk_csr_real), offsetof(sk_csr_real, w));
   return 0;
 }}''')
     exe = tmp_path / "layout"
@@ -51,7 +53,9 @@ int main(void) {{
     got = [int(x) for x in out]
     want = [ctypes.sizeof(sk.Params), ctypes.sizeof(sk.Report), ctypes.sizeof(sk.CSR),
             sk.Params.tol.offset, sk.Params.storage.offset, sk.Params.warm_start.offset,
-            sk.Params.fused.offset, sk.Report.seconds.offset, sk.Report.nnz_kept.offset, sk.CSR.w.offset]
+            sk.Params.fused.offset, sk.Report.seconds.offset, sk.Report.nnz_kept.offset, sk.CSR.w.offset,
+            sk.Params.prescale.offset, sk.Report.p_scale.offset, ctypes.sizeof(sk.CSRReal),
+            sk.CSRReal.w.offset]
     assert got == want
 
 
@@ -236,3 +240,67 @@ def test_solve_reduced_all_tight_random_graph():
     perm, weight = sk.solve_reduced(rp, cols, ww, n)
     assert weight == 1000 * n
     assert sorted(perm) == list(range(n)) and mask[np.arange(n), perm].all()
+
+
+# ---------------------------------------------------------------- real-weight exact solve
+
+def _csr_of(b):
+    """CSR (row_ptr, col, w float32) of the finite entries of b."""
+    n = b.shape[0]
+    rp, cols, ws = [0], [], []
+    for i in range(n):
+        js = np.nonzero(np.isfinite(b[i]))[0]
+        cols.extend(js.tolist())
+        ws.extend(b[i, js].tolist())
+        rp.append(len(cols))
+    return (np.array(rp, dtype=np.int64), np.array(cols, dtype=np.int32),
+            np.array(ws, dtype=np.float32))
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 7, 8])
+def test_real_solver_vs_brute_force(n):
+    rng = np.random.default_rng(200 + n)
+    for trial in range(8):
+        w = (rng.standard_normal((n, n)) * 2.0).astype(np.float32).astype(np.float64)
+        keep = rng.random((n, n)) < (0.45 if trial % 2 else 1.0)
+        b = np.where(keep, w, -np.inf)
+        best, _ = brute.all_optima(b)
+        rp, col, ww = _csr_of(b)
+        if best == -math.inf:
+            with pytest.raises(sk.SkError) as e:
+                sk.solve_reduced_real(rp, col, ww, n)
+            assert e.value.status == sk.SK_EINFEASIBLE
+            continue
+        perm, weight = sk.solve_reduced_real(rp, col, ww, n)
+        assert sorted(perm.tolist()) == list(range(n))
+        assert np.isfinite(b[np.arange(n), perm]).all()
+        assert weight == pytest.approx(best, abs=1e-9)
+        assert weight == pytest.approx(b[np.arange(n), perm].sum(), abs=1e-9)
+
+
+def test_real_solver_vs_oracle_on_sparse_instances():
+    """Sparse random instances (about 8 entries per row plus a hidden perfect
+    matching, so one exists) against the oracle's dense real Hungarian."""
+    rng = np.random.default_rng(5)
+    for n in (50, 300, 1000):
+        w = -rng.uniform(0.0, 1.73, (n, n)).astype(np.float32).astype(np.float64)
+        keep = rng.random((n, n)) < 8.0 / n
+        keep[np.arange(n), rng.permutation(n)] = True
+        b = np.where(keep, w, -np.inf)
+        rp, col, ww = _csr_of(b)
+        perm, weight = sk.solve_reduced_real(rp, col, ww, n)
+        _, w_or = oracle.hungarian_real(b)
+        assert weight == pytest.approx(w_or, abs=1e-7)
+        assert np.isfinite(b[np.arange(n), perm]).all()
+
+
+def test_real_solver_rejects_bad_csr():
+    rp = np.array([0, 1, 2], dtype=np.int64)
+    col = np.array([0, 5], dtype=np.int32)  # column out of range
+    with pytest.raises(sk.SkError) as e:
+        sk.solve_reduced_real(rp, col, np.array([1.0, 2.0], dtype=np.float32), 2)
+    assert e.value.status == sk.SK_EINVAL
+    col = np.array([0, 0], dtype=np.int32)  # both rows on column 0
+    with pytest.raises(sk.SkError) as e:
+        sk.solve_reduced_real(rp, col, np.array([1.0, 2.0], dtype=np.float32), 2)
+    assert e.value.status == sk.SK_EINFEASIBLE

@@ -1,0 +1,192 @@
+"""GPU parity of the real-valued log-weight path (sk_scale_real, sk_solve_real)
+against the FP64 oracle.
+
+The GPU forms each term's exponent in FP64 and takes exp2 of its fraction in
+FP32 (about 2 ulp per term), sums in FP32, so per sweep a row or column sum
+carries a relative error of a few 1e-7, as in the int16 path: the same
+tolerances apply (1e-4 on log x for entries >= 1e-6 after fixed iteration
+counts, 2e-6 ln n on log potentials after one step). The GPU sweeps the
+weights shifted by their largest finite value wref (X(p) does not change), so
+its potentials map to the oracle's as ubar = log u / p - wref, vbar = log v / p.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1104_3830_amd as sk
+import skgen
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = sk.Context(0)
+    yield c
+    c.close()
+
+
+def dev(W):
+    return torch.from_numpy(np.ascontiguousarray(W, dtype=np.float32)).cuda()
+
+
+def bars(res, W, n):
+    """(p, ubar, vbar) in the oracle's convention from a GPU result."""
+    r = res.report if hasattr(res, "report") else res["report"]
+    pot = res.potentials if hasattr(res, "potentials") else res["potentials"]
+    p = r["p_final"] * r["p_scale"]
+    lu, lv = sk.split_potentials(pot, n)
+    wref = float(W[np.isfinite(W)].max())
+    return p, lu / p - wref, lv / p
+
+
+def holes(n, seed):
+    """log U(0,1] weights with about 30% of the entries -inf (a zero), the
+    diagonal kept so that every row and column has support."""
+    W = skgen.uniform_real(n, seed)
+    drop = skgen.unit(skgen.stream(seed, 77, n * n)).reshape(n, n) < 0.3
+    drop[np.arange(n), np.arange(n)] = False
+    W[drop] = -np.inf
+    return W
+
+
+def stops_clear(Bp, ladder, tol, cap, margin=1e-6):
+    """Per stage of the oracle's continuation on Bp, whether its stop is clear
+    of the tolerance band (residual at the stop below tol - margin, the one
+    before above tol + margin), where FP32 takes the same decision."""
+    n = Bp.shape[0]
+    ub, vb = np.zeros(n), np.zeros(n)
+    out = []
+    for p in ladder:
+        ub1, vb1, m, res = oracle.sinkhorn(Bp, p, tol, cap, ub, vb)
+        ok = res < tol - margin
+        if m > 1:
+            ok = ok and oracle.sinkhorn(Bp, p, 0.0, m - 1, ub, vb)[3] > tol + margin
+        out.append(ok)
+        ub, vb = ub1, vb1
+    return out
+
+
+WORKLOADS = {"rand": lambda n, s: skgen.uniform_real(n, s),
+             "euclid": lambda n, s: skgen.euclidean_real(n, s),
+             "holes": holes}
+
+
+@pytest.mark.parametrize("kind,n,P,iters", [("rand", 64, 25, 30), ("euclid", 257, 100, 40),
+                                            ("rand", 1000, 150, 25), ("holes", 300, 60, 20),
+                                            ("euclid", 1001, 200, 15)])
+def test_real_fixed_iterations_match_oracle(ctx, kind, n, P, iters):
+    """Cold start, one stage at the prescaled p (a non-integer p on W), exactly
+    `iters` iterations: X from the GPU potentials matches the oracle's
+    iterate on the same W entry by entry (n = 257 and 1001: one column per
+    load; the others four)."""
+    W = WORKLOADS[kind](n, 3)
+    B = W.astype(np.float64)
+    prm = sk.make_params([P], tol=0.0, max_iters=iters, check_every=16, prescale=True)
+    res = ctx.scale_real(dev(W), prm)
+    assert res.status == sk.SK_ENOCONV and res.report["iters_total"] == iters
+    p, ub_g, vb_g = bars(res, W, n)
+    _, scale = oracle.prescale_log(B)
+    assert res.report["p_scale"] == pytest.approx(scale, rel=1e-12)
+    ub_o, vb_o, m, _ = oracle.sinkhorn(B, p, 0.0, iters)
+    assert m == iters
+    with np.errstate(invalid="ignore"):
+        Lg = p * (B + ub_g[:, None] + vb_g[None, :])
+        Lo = p * (B + ub_o[:, None] + vb_o[None, :])
+    sig = np.isfinite(Lo) & (Lo > np.log(1e-6))
+    assert np.abs(Lg - Lo)[sig].max() < 1e-4
+    Xg = oracle.scaled_matrix(B, p, ub_g, vb_g)
+    Xo = oracle.scaled_matrix(B, p, ub_o, vb_o)
+    assert np.abs(Xg - Xo).max() < 1e-5
+
+
+@pytest.mark.parametrize("n", [16384, 4097])
+def test_real_single_step_sampled_full_size(ctx, n):
+    """One iteration from a warm start at the prescaled p = 200 on log U(0,1]
+    weights: log u of sampled rows equals the oracle's row step on the
+    starting v, log v of sampled columns the oracle's column step on the
+    GPU's new u (n = 16384: 1 GiB of float32 weights, non-temporal loads;
+    4097: one column per load)."""
+    W = skgen.uniform_real(n, 5)
+    Wd = dev(W)
+    warm = ctx.scale_real(Wd, sk.make_params([200], tol=0.0, max_iters=20, check_every=20, prescale=True))
+    p, ub0, vb0 = bars(warm, W, n)
+    res = ctx.scale_real(Wd, sk.make_params([200], tol=0.0, max_iters=1, warm_start=True, prescale=True),
+                         potentials=warm.potentials.clone())
+    assert res.report["iters_total"] == 1
+    _, ub1, vb1 = bars(res, W, n)
+    rng = np.random.default_rng(0)
+    rows = np.sort(np.r_[rng.choice(n - 8, 60, replace=False), np.arange(n - 4, n)])
+    cols = np.sort(np.r_[rng.choice(n - 8, 60, replace=False), np.arange(n - 4, n)])
+    u_or = oracle.row_step(W[rows].astype(np.float64), p, vb0)
+    v_or = oracle.col_step(np.ascontiguousarray(W[:, cols]).astype(np.float64), p, ub1)
+    assert np.abs(p * (ub1[rows] - u_or)).max() < 2e-6 * np.log(n)
+    assert np.abs(p * (vb1[cols] - v_or)).max() < 2e-6 * np.log(n)
+
+
+@pytest.mark.parametrize("kind,n", [("rand", 1000), ("euclid", 1000), ("holes", 400)])
+def test_real_algorithm1_paper_defaults(ctx, kind, n):
+    """Algorithm alg:alg1 with the paper's defaults (p0 = 100, +50 per round on
+    the prescaled matrix, eps = t = 1/n, required ratio 2) through
+    sk_solve_real against the oracle's Algorithm alg:alg1 on the same
+    weights: the same rounds evaluated (every stage's gamma checked clear of
+    the ratio), the same iterations per round (a round whose oracle stop
+    lies within the FP32 error of the tolerance, as the Euclidean p = 200
+    round does at 1.6e-7 below it, may stop one iteration apart), the same
+    optimal permutation of the reduced matrix with its weight, gamma and the
+    kept entries."""
+    W = WORKLOADS[kind](n, 0)
+    B = W.astype(np.float64)
+    lad = [100 + 50 * k for k in range(8)]
+    want, status = oracle.adaptive_real(B, lad, 1.0 / n, 100000, 1.0 / n, 2.0)
+    assert status == "ok"
+    assert all(abs(g - math.log(2.0)) > 0.01 for _, g in want.extra["gammas"])
+    clear = stops_clear(oracle.prescale_log(B)[0], lad[:len(want.iters)], 1.0 / n, 100000)
+    out = ctx.solve_real(dev(W), sk.paper_params(n, ladder=lad, max_iters=100000))
+    r = out["report"]
+    assert out["status"] == sk.SK_OK
+    assert r["p_final"] == want.p and r["stages_evaluated"] == want.extra["evaluated"]
+    for got, it, ok in zip(r["iters_stage"], want.iters, clear):
+        assert got == it if ok else abs(got - it) <= 1, (r["iters_stage"], want.iters, clear)
+    assert np.array_equal(out["perm"], want.perm)
+    assert out["weight"] == pytest.approx(want.extra["weight_orig"], abs=1e-9 * n)
+    assert out["log_gamma"] == pytest.approx(want.log_gamma, abs=1e-3)
+    assert abs(out["nnz"] - want.nnz) <= max(2, 0.002 * want.nnz)
+    assert r["p_scale"] == pytest.approx(want.extra["p_scale"], rel=1e-12)
+
+
+def test_real_prescaled_result_invariant_under_powers(ctx):
+    """Section 4.1.1: the prescaled matrix of A^(q) is that of A, so Algorithm
+    alg:alg1 returns the same permutation, p and gamma for W and q W."""
+    n = 500
+    W = skgen.euclidean_real(n, 4)
+    prm = sk.paper_params(n, ladder=[100 + 50 * k for k in range(8)], max_iters=100000)
+    a = ctx.solve_real(dev(W), prm)
+    b = ctx.solve_real(dev(3.0 * W), prm)
+    assert a["status"] == b["status"] == sk.SK_OK
+    assert np.array_equal(a["perm"], b["perm"])
+    assert a["report"]["p_final"] == b["report"]["p_final"]
+    assert a["log_gamma"] == pytest.approx(b["log_gamma"], abs=1e-4)
+    assert b["weight"] == pytest.approx(3.0 * a["weight"], rel=1e-6)
+
+
+def test_real_errors(ctx):
+    n = 32
+    W = skgen.uniform_real(n, 1)
+    bad = W.copy()
+    bad[3, 4] = np.nan
+    with pytest.raises(sk.SkError) as e:
+        ctx.scale_real(dev(bad), sk.make_params([100], prescale=True))
+    assert e.value.status == sk.SK_EINVAL
+    empty = W.copy()
+    empty[5, :] = -np.inf
+    with pytest.raises(sk.SkError) as e:
+        ctx.scale_real(dev(empty), sk.make_params([100], tol=1e-6, max_iters=50, prescale=True))
+    assert e.value.status == sk.SK_ENOSUPPORT
+    with pytest.raises(sk.SkError) as e:
+        ctx.scale_real(dev(W), sk.make_params([100], storage="bf16"))
+    assert e.value.status == sk.SK_EINVAL
