@@ -25,6 +25,9 @@ bounded sample of the same workload (median of 5 runs of 2 full iterations at
 n = 16384 on every core; median of 5 one-core runs of a 1/16 sample), converted
 to the same unit, with the CPU model.
 
+single_pass: the main leg's step through the single-pass iteration (one
+matrix read per iteration), with the single-pass kernel's launch duration.
+
 precision: the same workload with int16 W, BF16 K and FP32 K: whole steps,
 sweep launch durations and roofline fractions, and the error of each against
 the FP64 oracle after a fixed number of iterations from identical potentials.
@@ -34,10 +37,13 @@ uniform 0..1000; sk_scale_batch (one launch per sweep across all instances)
 against 512 sequential sk_scale calls with the same parameters (scalings per
 second; the number of instances that reached the tolerance is reported).
 
-euclidean: the Euclidean random assignment workload at n = 1000 (2n points
-uniform in the unit cube, a_ij = exp(-d), distances quantised at 1/100)
-through sk_solve with the paper's required ratio 2: gamma (paper's units),
-p, iterations, kept entries.
+algorithm1: Algorithm 1 with the paper's defaults (p0 = 100, +50 per round on
+the prescaled matrix, eps = t = 1/n, required ratio 2) on real-valued
+log-weights at n = 1000: the random matrix (entries uniform on (0, 1]) and
+the Euclidean random assignment matrix (2n points uniform in the unit cube,
+a_ij = exp(-d), not quantised), through sk_solve_real: gamma, p, iterations,
+kept entries beside Table 1's rows (context); and the real-valued sweeps'
+launch durations at n = 16384.
 
 dominant: the diagonally dominant 5% pattern at n = 16384 (w_ii uniform
 800..1000, off-diagonal entries present with probability 0.05 with values
@@ -89,9 +95,11 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
+    ap.add_argument("--precision-steps", type=int, default=3)
+    ap.add_argument("--no-single-pass", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
-    ap.add_argument("--no-euclidean", action="store_true")
+    ap.add_argument("--no-algorithm1", action="store_true")
     ap.add_argument("--no-dominant", action="store_true")
     ap.add_argument("--served-requests", type=int, default=1000)
     ap.add_argument("--served-loads", default="0.5,0.9,1.5",
@@ -111,6 +119,10 @@ def parse():
                              "COPY_WRITE_CSV"),
                     help="only write the HBM traffic summary of one kernel from two --pmc runs of "
                          "the benchmark and two of --calibrate-copy")
+    ap.add_argument("--traffic-table", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV",
+                                                         "COPY_WRITE_CSV"),
+                    help="only print, per kernel instantiation, the HBM bytes per launch (FETCH_SIZE + "
+                         "WRITE_SIZE scaled by the copy calibration) over launches that did work")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (the reference "
                          "kernel for scaling HBM byte counters)")
@@ -204,6 +216,45 @@ def traffic_report(kernel, workload, fcsv, wcsv, cfcsv, cwcsv):
     print(f"bytes_per_launch: {total:.0f}")
 
 
+def _counter_means_full(path, counter):
+    """As _counter_means, keyed by the full kernel name with its template
+    arguments (instantiations apart)."""
+    import csv
+    per = {}
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] != counter:
+            continue
+        k = r["Kernel_Name"].split("(")[0]
+        k = k[5:] if k.startswith("void ") else k
+        per.setdefault(k, {}).setdefault(r["Dispatch_Id"], 0.0)
+        per[k][r["Dispatch_Id"]] += float(r["Counter_Value"])
+    out = {}
+    for k, d in per.items():
+        v = list(d.values())
+        hi = max(v) if v else 0.0
+        work = [x for x in v if x > 0.01 * hi]
+        out[k] = (sum(work) / len(work) if work else 0.0, len(work), len(v))
+    return out
+
+
+def traffic_table(fcsv, wcsv, cfcsv, cwcsv):
+    copy_kib = (1 << 30) / 1024.0
+    cf = _counter_means(cfcsv, "FETCH_SIZE")["__amd_rocclr_copyBuffer"][0]
+    cw = _counter_means(cwcsv, "WRITE_SIZE")["__amd_rocclr_copyBuffer"][0]
+    fs, ws = copy_kib / cf, copy_kib / cw
+    f = _counter_means_full(fcsv, "FETCH_SIZE")
+    w = _counter_means_full(wcsv, "WRITE_SIZE")
+    print(f"source_sha256: {source_hash()}")
+    print(f"copy calibration: 1 GiB copy reads {cf:.1f} KiB (fetch x {fs:.4f}), writes {cw:.1f} KiB "
+          f"(write x {ws:.4f})")
+    print("| kernel | working launches | fetch MB/launch | write MB/launch | HBM MB/launch |")
+    print("|---|---|---|---|---|")
+    for k in sorted(f, key=lambda k: -f[k][0]):
+        fb = f[k][0] * fs * 1024.0
+        wb = w.get(k, (0.0, 0, 0))[0] * ws * 1024.0
+        print(f"| {k} | {f[k][1]} of {f[k][2]} | {fb / 1e6:.1f} | {wb / 1e6:.1f} | {(fb + wb) / 1e6:.1f} |")
+
+
 def committed_traffic(kernel, storage, n):
     """HBM bytes per launch from profiles/, or None if the sources changed since."""
     path = os.path.join(ROOT, "profiles", f"hbm_traffic_{kernel}_{storage}_n{n}.txt")
@@ -238,18 +289,21 @@ def calibrate_copy():
                       "gbs_read_plus_write": round(2 * (1 << 30) / el / 1e9, 1)}), flush=True)
 
 
-def batched_leg(sk, torch, seed=1, cap=500):
+def batched_leg(sk, torch, seed=1, cap=500, planted=False):
     """512 ragged instances: one batched scaling run vs 512 sequential runs
     with the same parameters (scaling only: no reduction or exact solve, so
     the rates are scalings per second). Uniform weights on 0..1000 at p = 1
     converge slowly (the oracle needs more than 1e5 iterations for some of
     these instances), so stages stop at the cap; the leg reports how many
     instances reached the tolerance in every stage and the worst FP64
-    residual, which are the same for both forms (bitwise equal results)."""
+    residual, which are the same for both forms (bitwise equal results).
+    planted: the same sizes with a planted optimum (w_i sigma(i) = 1050),
+    which every instance scales to the tolerance."""
     import skgen
     ns = skgen.sizes_loguniform(512, 32, 1024, seed)
-    Ws = [torch.from_numpy(skgen.uniform_weights(int(n), 0, 1000, seed * 100003 + k)).cuda()
-          for k, n in enumerate(ns)]
+    gen = ((lambda n, s: skgen.planted(n, s)[0]) if planted
+           else (lambda n, s: skgen.uniform_weights(n, 0, 1000, s)))
+    Ws = [torch.from_numpy(gen(int(n), seed * 100003 + k)).cuda() for k, n in enumerate(ns)]
     prm = sk.make_params([1, 2, 4, 8, 16, 32], tol=1e-5, max_iters=cap, check_every=32)
     ctx = sk.Context(0)
     # warm-up over the whole batch (2 iterations per stage): the arena is
@@ -272,6 +326,7 @@ def batched_leg(sk, torch, seed=1, cap=500):
     elems = int(sum(int(n) * int(n) for n in ns))
     reps = [r.report for r in res_b]
     return {"instances": 512, "n_range": [32, 1024], "matrix_MB": round(elems * 2 / 1e6, 1),
+            "weights": "planted (w_i sigma(i) = 1050)" if planted else "uniform 0..1000",
             "tol": 1e-5, "cap_per_stage": cap,
             "instances_reached_tol": int(sum(r["stages_capped"] == 0 for r in reps)),
             "stages_capped_total": int(sum(r["stages_capped"] for r in reps)),
@@ -391,32 +446,67 @@ def served_leg(sk, torch, n_requests, loads, seed=2):
             "saturated": saturated}
 
 
-def euclidean_leg(sk, torch, n=1000, seed=0, scale=100):
-    """The Euclidean random assignment workload at the paper's size: 2n points
-    uniform in the unit cube, a_ij = exp(-d), log-weights -d quantised at
-    1/scale (so W = scale log a and p = 1 here is the paper's prescaled
-    p = w_max - w_min), through sk_solve with the paper's required ratio 2
-    (2^scale in these units) over the ladder 1, 2. gamma is reported in the
-    paper's units, exp(log gamma / scale)."""
+def table1_rows():
+    """Table 1 of the paper (Section 5.1) from the committed context fixture:
+    {name: (gamma, p, iterations, kept %)}."""
+    out = {}
+    path = os.path.join(ROOT, "tests", "golden", "table1_sinkhorn.txt")
+    for line in open(path):
+        parts = line.split()
+        if len(parts) == 5 and not line.startswith("#"):
+            out[parts[0]] = tuple(float(x) for x in parts[1:])
+    return out
+
+
+def algorithm1_leg(sk, torch, n=1000, seed=0, sweep_n=16384, sweep_iters=20):
+    """Algorithm alg:alg1 with the paper's defaults (p0 = 100, +50 per round on
+    the prescaled matrix, eps = t = 1/n, required ratio 2) on real-valued
+    log-weights at the paper's n = 1000: the random matrix (entries uniform
+    on (0, 1]) and the Euclidean random assignment matrix (-d, not
+    quantised), through sk_solve_real: gamma, p, iterations, kept entries and
+    time per solve, beside Table 1's rand and euclidean rows (another
+    machine, MATLAB, other random draws: context only). Also the real-valued
+    sweeps at n = sweep_n (float32 W, 4 bytes per element): average launch
+    durations over sweep_iters iterations at the prescaled p = 200."""
     import math
     import skgen
-    W, _, _ = skgen.euclidean(n, seed, scale=scale)
-    prm = sk.make_params([1, 2], tol=1e-5, max_iters=20000, threshold=1e-4,
-                         opt_ratio=2.0 ** scale)
+    ref = table1_rows()
     ctx = sk.Context(0)
+    out = {"n": n, "defaults": "p0=100, +50 per round (prescaled), eps=t=1/n, opt_ratio=2"}
+    for name, W in (("rand", skgen.uniform_real(n, seed)), ("euclidean", skgen.euclidean_real(n, seed))):
+        Wd = torch.from_numpy(W).cuda()
+        prm = sk.paper_params(n)
+        ctx.solve_real(Wd, prm)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        o = ctx.solve_real(Wd, prm)
+        el = time.perf_counter() - t0
+        r = o["report"]
+        g, pp, it, kept = ref[name]
+        out[name] = {"gamma": round(math.exp(o["log_gamma"]), 4), "p": r["p_final"],
+                     "p_on_W": r["p_final"] * r["p_scale"], "iterations": r["iters_total"],
+                     "iters_per_round": r["iters_stage"][:r["stages_evaluated"]],
+                     "kept_percent": round(100.0 * o["nnz"] / n / n, 3), "status": o["status"],
+                     "ms_per_solve": round(el * 1e3, 2), "weight": o["weight"],
+                     "table1": {"gamma": g, "p": int(pp), "iterations": int(it), "kept_percent": kept}}
+    W = skgen.uniform_real(sweep_n, seed)
     Wd = torch.from_numpy(W).cuda()
-    ctx.solve(Wd, prm)  # warm-up
+    del W
+    prm = sk.make_params([200], tol=0.0, max_iters=sweep_iters, check_every=sweep_iters, prescale=True)
+    ctx.scale_real(Wd, prm)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    out = ctx.solve(Wd, prm)
-    el = time.perf_counter() - t0
-    r = out["report"]
+    ctx.profile(True)
+    ctx.scale_real(Wd, prm)
+    prof = ctx.profile_read()
+    ctx.profile(False)
     ctx.close()
-    wr = int(W.max()) - int(W.min())
-    return {"n": n, "scale": scale, "p": r["p_final"], "p_prescaled": r["p_final"] * wr,
-            "gamma": round(math.exp(r["log_gamma"] / scale), 4),
-            "iterations": r["iters_total"], "kept_percent": round(100.0 * r["nnz_kept"] / n / n, 3),
-            "status": out["status"], "seconds": round(el, 4)}
+    us = {k: prof[k][1] / prof[k][0] * 1e3 for k in ("row_sweep", "col_sweep") if k in prof}
+    bytes_sweep = sweep_n * sweep_n * 4
+    out["sweeps"] = {"n": sweep_n, "element_bytes": 4, "iterations": sweep_iters,
+                     **{f"{k}_us": round(v, 2) for k, v in us.items()},
+                     **{f"{k}_frac": round(bytes_sweep / (v * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
+                        for k, v in us.items()}}
+    return out
 
 
 def dominant_leg(sk, torch, prm, n=16384, seed=5, solves=8):
@@ -525,6 +615,34 @@ def cpu_baseline(W, B, p, runs=5, iters=2, blk=1024):
                       f"n^2*2 bytes per sweep"}
 
 
+def single_pass_leg(sk, torch, Wd, ladder, cap, tol, threshold, steps=3):
+    """The main leg's step through the single-pass iteration (one read of the
+    matrix per iteration instead of two): step time and the single-pass
+    kernel's average launch duration against one matrix read."""
+    n = int(Wd.shape[0])
+    prm = sk.make_params(ladder, tol=tol, max_iters=cap, check_every=32, threshold=threshold, fused=True)
+    ctx = sk.Context(0)
+    ctx.solve(Wd, prm)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    its = 0
+    for _ in range(steps):
+        o = ctx.solve(Wd, prm)
+        its += o["report"]["iters_total"]
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    ctx.close()
+    us = prof["fused"][1] / prof["fused"][0] * 1e3 if "fused" in prof else None
+    return {"n": n, "ms_per_step": round(el * 1e3, 3), "iters_per_step": its // steps,
+            "weight": o["weight"], "stages_capped": o["report"]["stages_capped"],
+            "kernel_us": round(us, 2) if us else None,
+            "frac": round(n * n * 2 / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4) if us else None,
+            "matrix_reads_per_iter": 1}
+
+
 def precision_leg(sk, torch, W, Wd, B, ladder, cap, tol, threshold, p=32, iters=3, steps=3):
     """The n = 16384 workload with the matrix read three ways: int16 W with
     exp recomputed in every sweep, K stored in BF16, K stored in FP32.
@@ -597,6 +715,9 @@ def main():
         return
     if args.traffic_report:
         traffic_report(*args.traffic_report)
+        return
+    if args.traffic_table:
+        traffic_table(*args.traffic_table)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
@@ -708,12 +829,16 @@ def main():
         B = oracle.log_weights(W)
     if not args.no_precision:
         out["precision"] = precision_leg(sk, torch, W, Wd, B, ladder, args.cap, args.tol,
-                                         args.threshold)
+                                         args.threshold, steps=args.precision_steps)
+    if not args.no_single_pass and not args.fused:
+        out["single_pass"] = single_pass_leg(sk, torch, Wd, ladder, args.cap, args.tol, args.threshold,
+                                             steps=args.precision_steps)
     del Wd
     if not args.no_batched:
         out["batched"] = batched_leg(sk, torch)
-    if not args.no_euclidean:
-        out["euclidean"] = euclidean_leg(sk, torch)
+        out["batched_planted"] = batched_leg(sk, torch, planted=True)
+    if not args.no_algorithm1:
+        out["algorithm1"] = algorithm1_leg(sk, torch)
     if not args.no_dominant:
         out["dominant"] = dominant_leg(sk, torch, prm)
     if not args.no_served:

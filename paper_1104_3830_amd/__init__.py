@@ -80,6 +80,7 @@ CSRReal = CSR  # same layout; w points to float32
 
 
 _lib = None
+loaded_tile_table = []  # (n_max, seg_rows) entries the binding passed to sk_set_tile_table
 
 
 def lib():
@@ -152,11 +153,13 @@ def lib():
 
 def set_tile_table(entries):
     """entries: list of (n_max, seg_rows), n_max ascending; [] = built-in rule."""
+    global loaded_tile_table
     nm = (ctypes.c_int32 * max(len(entries), 1))(*[int(a) for a, _ in entries])
     sr = (ctypes.c_int32 * max(len(entries), 1))(*[int(b) for _, b in entries])
     st = lib().sk_set_tile_table(nm, sr, len(entries))
     if st != SK_OK:
         raise SkError(st, "sk_set_tile_table")
+    loaded_tile_table = [(int(a), int(b)) for a, b in entries]
 
 
 def load_tile_table(path):

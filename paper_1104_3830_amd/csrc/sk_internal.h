@@ -100,6 +100,9 @@ struct Inst {
     // words kRowResStride apart (float bits, atomicMax by each wave; zero
     // between iterations); the column sweep reduces them
     uint32_t *rowres;
+    // residual / drift slots the stored-K row sweep writes (one per workgroup)
+    int32_t kres_slots;
+    int32_t pad3;
     // the caller's W when W is the library's padded copy (n % 8 != 0),
     // else nullptr; copied once per batch before the input scan
     const int16_t *Wsrc;

@@ -341,10 +341,9 @@ __global__ __launch_bounds__(256) void k_col_finalize(const Inst *__restrict__ i
         const bool onepass = (mode & kFinOnePass) != 0; // slots written by the single-pass kernel
         if (kpath && ctl->need_absorb) continue;
         // residual (and drift) of this iteration's row step: one slot per
-        // workgroup of the single pass, per row unit of the stored-K row
-        // sweep, per row segment of the log-domain sweeps
-        const int nres = onepass ? I.fused_grid
-                                 : (kpath ? (I.n + kRowWaves - 1) / kRowWaves : I.nseg);
+        // workgroup of the single pass and of the stored-K row sweep, per
+        // row segment of the log-domain sweeps
+        const int nres = onepass ? I.fused_grid : (kpath ? I.kres_slots : I.nseg);
         float m = 0.f, d = 0.f;
         for (int q = t; q < nres; q += 256) {
             m = fmaxf(m, I.res_slots[q]);

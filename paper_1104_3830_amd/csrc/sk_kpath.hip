@@ -181,11 +181,15 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_row_sweep_k(const Inst *_
                                                                    const RowUnit *__restrict__ units,
                                                                    int nunits) {
     extern __shared__ float bsh[];
-    __shared__ float wres[2][kRowWaves], wdrift[2][kRowWaves];
+    __shared__ float wres[kRowWaves], wdrift[kRowWaves];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     int u0, u1;
     krange(nunits, u0, u1);
     int cur = -1;
+    // each wave's running maxima over its rows (lane 0); the workgroup's go to
+    // its residual and drift slots at the end, so the waves run their rows
+    // without a barrier
+    float resmax = 0.f, drift = 0.f;
     for (int u = u0; u < u1; ++u) {
         const RowUnit un = units[u];
         const Inst &I = insts[un.inst];
@@ -199,28 +203,24 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_row_sweep_k(const Inst *_
             cur = un.inst;
         }
         const int row = un.row0 + wave;
-        float resmax = 0.f, drift = 0.f;
         if (row < n) {
             const int par = ctl->iter & 1;
             float acc = 0.f;
             const int64_t rbase = (int64_t)row * kp;
             int j0 = lane * 8;
-            for (; j0 + 3 * 512 < kp; j0 += 4 * 512) {
-                float k0[8], k1[8], k2[8], k3[8];
+            // two 16-byte loads in flight per lane (as the int16 row sweep)
+            for (; j0 + 512 < kp; j0 += 2 * 512) {
+                float k0[8], k1[8];
                 load8<ST, NT>(I.K, rbase + j0, k0);
                 load8<ST, NT>(I.K, rbase + j0 + 512, k1);
-                load8<ST, NT>(I.K, rbase + j0 + 1024, k2);
-                load8<ST, NT>(I.K, rbase + j0 + 1536, k3);
                 const int q = j0 >> 3;
-                float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+                float s0 = 0.f, s1 = 0.f;
 #pragma unroll
                 for (int c = 0; c < 8; ++c) {
                     s0 = fmaf(k0[c], bsh[c * n8 + q], s0);
                     s1 = fmaf(k1[c], bsh[c * n8 + q + 64], s1);
-                    s2 = fmaf(k2[c], bsh[c * n8 + q + 128], s2);
-                    s3 = fmaf(k3[c], bsh[c * n8 + q + 192], s3);
                 }
-                acc += (s0 + s1) + (s2 + s3);
+                acc += s0 + s1;
             }
             for (; j0 < kp; j0 += 512) {
                 float k[8];
@@ -236,25 +236,27 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_row_sweep_k(const Inst *_
                 const float aold = I.a[par][row];
                 const float anew = 1.f / fminf(fmaxf(S, kKLo), kKHi);
                 I.a[par ^ 1][row] = anew;
-                resmax = fabsf(aold * S - 1.f);
-                drift = fabsf(klg2(anew));
+                resmax = fmaxf(resmax, fabsf(aold * S - 1.f));
+                drift = fmaxf(drift, fabsf(klg2(anew)));
             }
         }
-        const int b = (u - u0) & 1;
-        if (lane == 0) {
-            wres[b][wave] = resmax;
-            wdrift[b][wave] = drift;
+    }
+    // stored K is single-instance: every workgroup writes its slot of
+    // instance 0 (0 when it had no row), the finalise reduces kres_slots of them
+    if (lane == 0) {
+        wres[wave] = resmax;
+        wdrift[wave] = drift;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float m = 0.f, d = 0.f;
+        for (int w = 0; w < kRowWaves; ++w) {
+            m = fmaxf(m, wres[w]);
+            d = fmaxf(d, wdrift[w]);
         }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            float m = 0.f, d = 0.f;
-            for (int w = 0; w < kRowWaves; ++w) {
-                m = fmaxf(m, wres[b][w]);
-                d = fmaxf(d, wdrift[b][w]);
-            }
-            I.res_slots[un.row0 / kRowWaves] = m;
-            I.drift_slots[un.row0 / kRowWaves] = d;
-        }
+        const Inst &I = insts[0];
+        I.res_slots[blockIdx.x] = m;
+        I.drift_slots[blockIdx.x] = d;
     }
 }
 

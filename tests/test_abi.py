@@ -304,3 +304,19 @@ def test_real_solver_rejects_bad_csr():
     with pytest.raises(sk.SkError) as e:
         sk.solve_reduced_real(rp, col, np.array([1.0, 2.0], dtype=np.float32), 2)
     assert e.value.status == sk.SK_EINFEASIBLE
+
+
+def test_tuned_tile_table_is_valid_and_loaded():
+    """The autotuner's committed table (column-sweep segment heights per size
+    bucket) is well formed, accepted by sk_set_tile_table and loaded by the
+    binding at import."""
+    import json
+    if not os.path.exists(sk.TILE_TABLE):
+        pytest.skip("no tuned table committed")
+    tab = json.load(open(sk.TILE_TABLE))
+    ent = [(e["n_max"], e["seg_rows"]) for e in tab["entries"]]
+    assert ent and all(a < b for (a, _), (b, _) in zip(ent, ent[1:]))
+    assert all(16 <= s <= 1024 and s % 16 == 0 for _, s in ent)
+    sk.lib()
+    if not os.environ.get("SK_NO_TILE_TABLE"):
+        assert sk.loaded_tile_table == ent

@@ -255,7 +255,12 @@ def test_prune_matches_oracle_on_same_potentials(ctx, n):
 # ---------------------------------------------------------------- batch, determinism
 
 def test_batch_equals_single_bitwise(ctx):
-    """Per-instance results do not depend on what else is in the batch."""
+    """Per-instance results do not depend on what else is in the batch (under
+    the tuned tile table when one is committed: the shape is a function of n
+    only)."""
+    import os
+    if os.path.exists(sk.TILE_TABLE) and not os.environ.get("SK_NO_TILE_TABLE"):
+        assert sk.loaded_tile_table, "the committed tile table was not loaded"
     ns = [37, 64, 130, 256, 512, 1000]
     Ws = [skgen.uniform_weights(n, 0, 1000, seed=90 + k) for k, n in enumerate(ns)]
     prm = sk.make_params([1, 2, 4, 8, 16, 32], tol=1e-5, max_iters=400, check_every=16)
