@@ -142,18 +142,24 @@ def trace_summary(path):
 
 
 def counter_summary(path):
+    """Per kernel instantiation, the mean of every counter over its full-work
+    dispatches: those whose SQ_INSTS_VALU (else the first counter) is at
+    least half the kernel's largest, so launches that only detected a
+    stage's end or skipped a finished instance are left out."""
     import csv
     per = {}
     for r in csv.DictReader(open(path)):
-        key = (r["Kernel_Name"].split("(")[0], r["Counter_Name"])
-        per.setdefault(key, {}).setdefault(r["Dispatch_Id"], 0.0)
-        per[key][r["Dispatch_Id"]] += float(r["Counter_Value"])
-    for (k, c), d in sorted(per.items()):
-        v = list(d.values())
-        hi = max(v) if v else 0.0
-        work = [x for x in v if x > 0.01 * hi]
-        print(f"{k} {c} dispatches={len(v)} working={len(work)} "
-              f"mean_working={(sum(work) / len(work) if work else 0):.1f}")
+        k = r["Kernel_Name"].split("(")[0]
+        d = per.setdefault(k, {}).setdefault(r["Dispatch_Id"], {})
+        d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    for k, disp in sorted(per.items()):
+        names = sorted({c for d in disp.values() for c in d})
+        ref = "SQ_INSTS_VALU" if "SQ_INSTS_VALU" in names else names[0]
+        hi = max(d.get(ref, 0.0) for d in disp.values())
+        full = [d for d in disp.values() if d.get(ref, 0.0) >= 0.5 * hi]
+        means = {c: sum(d.get(c, 0.0) for d in full) / len(full) for c in names}
+        cells = " ".join(f"{c}={means[c]:.4g}" for c in names)
+        print(f"{k} | dispatches={len(disp)} full_work={len(full)} | {cells}")
 
 
 def source_hash():
