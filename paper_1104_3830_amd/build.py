@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsk.so")
 SOURCES = ["sk_kernels.hip", "sk_rowshort.hip", "sk_fused.hip", "sk_runtime.hip", "sk_kpath.hip",
            "sk_static.hip", "sk_real.hip",
-           "sk_solver.cpp",
+           "sk_solver.cpp", "sk_solver_real.cpp",
            "sk_serve.cpp", "sk_solve.cpp", "sk_newton.cpp", "sk_realhost.cpp"]
 ARCH = os.environ.get("SK_OFFLOAD_ARCH", "gfx950")
 

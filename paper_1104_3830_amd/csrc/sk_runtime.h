@@ -7,6 +7,7 @@
 #include <string>
 #include <vector>
 
+#include "sk_hostsolve.h"
 #include "sk_internal.h"
 
 namespace sk {
@@ -208,10 +209,6 @@ struct CheckCounts {
     int64_t *counts;
     int32_t *hint;
 };
-// sk_solve_reduced with a column per row to try first in the greedy start
-// of the matching (nullptr: none).
-sk_status solve_reduced_seeded(const sk_csr *csr, const int32_t *hint, int32_t *perm,
-                               int64_t *weight);
 sk_status check_fp64(sk_ctx *ctx, Batch &B, int k, sk_report *rep);
 // writes B.d_checkout[k] (and the counts when cc != nullptr)
 sk_status enqueue_check(sk_ctx *ctx, Batch &B, int k, const CheckCounts *cc = nullptr);

@@ -5,9 +5,9 @@
 // no earlier request is waiting for space; otherwise into pinned host staging.
 // Copies run on a stream of their own, so they overlap the sweeps. A serving
 // thread repeats a tick:
-//   1. admit queued requests (FIFO) while their footprint fits; start the
-//      host-to-device copy of staged ones, and take in those whose copy is
-//      complete; cold-start the new instances;
+//   1. admit queued requests (FIFO) while their footprint fits (the policy
+//      is in sk_sched.h); start the host-to-device copy of staged ones, and
+//      take in those whose copy is complete; cold-start the new instances;
 //   3. run a block of Sinkhorn iterations over every admitted instance at
 //      once (one row-sweep launch and one column-sweep launch per iteration
 //      cover all of them; each instance follows its own p ladder, tolerance
@@ -33,6 +33,7 @@
 
 #include "sk_alloc.h"
 #include "sk_runtime.h"
+#include "sk_sched.h"
 
 namespace sk {
 
@@ -357,24 +358,9 @@ static void serve_loop(Server *S) {
         {
             std::unique_lock<std::mutex> g(S->mu);
             if (S->stop) break;
-            while (!S->queue.empty() &&
-                   S->active.size() + S->loading.size() + fresh.size() + to_copy.size() <
-                       (size_t)kMaxBatch) {
-                Request *r = S->queue.front();
-                if (r->copying) {
-                    to_copy.push_back(r);
-                } else if (!r->loaded) {
-                    size_t off;
-                    if (!S->ralloc.alloc(r->len, off)) break;
-                    place(S, r, off);
-                    --S->staged_waiting;
-                    to_copy.push_back(r);
-                } else {
-                    fresh.push_back(r);
-                }
-                r->phase = 1;
-                S->queue.pop_front();
-            }
+            admit_fifo(S->queue, S->active.size() + S->loading.size(), (size_t)kMaxBatch, S->ralloc,
+                       S->staged_waiting, fresh, to_copy,
+                       [S](Request *r, size_t off) { place(S, r, off); });
         }
         hipError_t e = hipSuccess;
         for (Request *r : to_copy) {
@@ -582,7 +568,8 @@ extern "C" sk_status sk_submit(sk_ctx *ctx, const int16_t *W_host, int32_t n, co
     // by an asynchronous copy started here if the device region is free too;
     // without ring room it is copied straight to a free device region
     // (waiting for the copy); with neither the call returns SK_EAGAIN (heap
-    // staging only when the pinned ring could not be allocated)
+    // staging only when the pinned ring could not be allocated); the
+    // decision is plan_entry's (sk_sched.h)
     bool placed = false;
     {
         std::lock_guard<std::mutex> g(S->mu);
@@ -590,19 +577,19 @@ extern "C" sk_status sk_submit(sk_ctx *ctx, const int16_t *W_host, int32_t n, co
             delete r;
             return fail(ctx, SK_EDEVICE, "serving thread stopped: %s", S->error.c_str());
         }
-        if (S->queue.size() >= (size_t)kMaxBatch) {
+        const EntryPlan ep = plan_entry(S->ring ? &S->ring_alloc : nullptr, S->ralloc, S->queue.size(),
+                                        (size_t)kMaxBatch, S->staged_waiting, wbytes, len);
+        if (ep.kind == Entry::Again) {
             delete r;
             return SK_EAGAIN;
         }
-        size_t off;
-        if (S->ring && S->ring_alloc.alloc(wbytes, off)) {
-            r->staging = (int16_t *)(S->ring + off);
-            r->ring_off = off;
+        if (ep.kind == Entry::RingAndDevice || ep.kind == Entry::RingOnly) {
+            r->staging = (int16_t *)(S->ring + ep.ring_off);
+            r->ring_off = ep.ring_off;
             r->in_ring = true;
         }
-        // a device region now only when nobody earlier is waiting for one
-        if (S->staged_waiting == 0 && S->ralloc.alloc(len, off)) {
-            place(S, r, off);
+        if (ep.kind == Entry::RingAndDevice || ep.kind == Entry::DeviceOnly) {
+            place(S, r, ep.dev_off);
             placed = true;
         }
     }
@@ -640,13 +627,10 @@ extern "C" sk_status sk_submit(sk_ctx *ctx, const int16_t *W_host, int32_t n, co
         if (e != hipSuccess) return undo("copy of W", e);
         drop_event(r);
         r->loaded = true;
-    } else if (S->ring) {
-        // neither ring room nor a free device region: the caller polls and
-        // submits again (heap staging would later need a pageable copy that
-        // stalls the serving thread)
-        delete r;
-        return SK_EAGAIN;
     } else {
+        // no ring at all (with a ring, neither ring room nor a free region was
+        // refused above: heap staging would later need a pageable copy that
+        // stalls the serving thread)
         r->staging = (int16_t *)malloc(wbytes);
         if (!r->staging) {
             delete r;

@@ -13,7 +13,7 @@
 #include <thread>
 #include <vector>
 
-#include "../../include/sk.h"
+#include "sk_hostsolve.h"
 
 namespace {
 
@@ -29,11 +29,6 @@ struct HeapItem {
 };
 
 }  // namespace
-
-namespace sk {
-sk_status solve_reduced_seeded(const sk_csr *csr, const int32_t *hint, int32_t *perm,
-                               int64_t *weight);
-}
 
 extern "C" sk_status sk_solve_reduced(const sk_csr *csr, int32_t *perm, int64_t *weight) {
     return sk::solve_reduced_seeded(csr, nullptr, perm, weight);

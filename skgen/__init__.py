@@ -174,7 +174,7 @@ def euclidean(n: int, seed: int, scale: int = 1000, chunk_rows: int = 1024):
 def euclidean_real(n: int, seed: int, chunk_rows: int = 1024):
     """The Euclidean random assignment workload with real log-weights:
     w_ij = -d(x_i, y_j) as float32 (a_ij = exp(-d)), no quantisation.
-    Returns (W, x, y)."""
+    Returns W (the points are euclidean_points(n, seed))."""
     x, y = euclidean_points(n, seed)
     W = np.empty((n, n), dtype=np.float32)
     for r in range(0, n, chunk_rows):
