@@ -624,29 +624,38 @@ def cpu_baseline(W, B, p, runs=5, iters=2, blk=1024):
 def single_pass_leg(sk, torch, Wd, ladder, cap, tol, threshold, steps=3):
     """The main leg's step through the single-pass iteration (one read of the
     matrix per iteration instead of two): step time and the single-pass
-    kernel's average launch duration against one matrix read."""
+    kernel's average launch duration against one matrix read, for int16 W
+    and for the stored BF16 and FP32 K (whose steps include the absorb pass
+    of every stage)."""
     n = int(Wd.shape[0])
-    prm = sk.make_params(ladder, tol=tol, max_iters=cap, check_every=32, threshold=threshold, fused=True)
+    out = {"n": n, "matrix_reads_per_iter": 1}
     ctx = sk.Context(0)
-    ctx.solve(Wd, prm)
-    torch.cuda.synchronize()
-    ctx.profile(True)
-    t0 = time.perf_counter()
-    its = 0
-    for _ in range(steps):
-        o = ctx.solve(Wd, prm)
-        its += o["report"]["iters_total"]
-    torch.cuda.synchronize()
-    el = (time.perf_counter() - t0) / steps
-    prof = ctx.profile_read()
-    ctx.profile(False)
+    for st, eb in (("i16", 2), ("bf16", 2), ("f32", 4)):
+        prm = sk.make_params(ladder, tol=tol, max_iters=cap, check_every=32, threshold=threshold,
+                             fused=True, storage=st)
+        ctx.solve(Wd, prm)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        t0 = time.perf_counter()
+        its = 0
+        for _ in range(steps):
+            o = ctx.solve(Wd, prm)
+            its += o["report"]["iters_total"]
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / steps
+        prof = ctx.profile_read()
+        ctx.profile(False)
+        us = prof["fused"][1] / prof["fused"][0] * 1e3 if "fused" in prof else None
+        leg = {"ms_per_step": round(el * 1e3, 3), "iters_per_step": its // steps,
+               "weight": o["weight"], "stages_capped": o["report"]["stages_capped"],
+               "kernel_us": round(us, 2) if us else None,
+               "frac": round(n * n * eb / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4) if us else None}
+        if st == "i16":
+            out.update(leg)
+        else:
+            out[st] = leg
     ctx.close()
-    us = prof["fused"][1] / prof["fused"][0] * 1e3 if "fused" in prof else None
-    return {"n": n, "ms_per_step": round(el * 1e3, 3), "iters_per_step": its // steps,
-            "weight": o["weight"], "stages_capped": o["report"]["stages_capped"],
-            "kernel_us": round(us, 2) if us else None,
-            "frac": round(n * n * 2 / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4) if us else None,
-            "matrix_reads_per_iter": 1}
+    return out
 
 
 def precision_leg(sk, torch, W, Wd, B, ladder, cap, tol, threshold, p=32, iters=3, steps=3):

@@ -23,6 +23,10 @@ namespace sk {
 
 constexpr int kFT = 1024;    // threads per workgroup
 constexpr int kFR = 2;       // rows per group
+// rows per workgroup at most: ceil(n / grid) with n <= kMaxN and a grid of
+// min(kFusedSlots, max(1, n / 2)) workgroups (64 at n = 16384, at most 3 for
+// n below 2 kFusedSlots)
+constexpr int kFusedRows = (kMaxN + kFusedSlots - 1) / kFusedSlots;
 constexpr float kL2e = 1.4426950408889634f;
 constexpr float kLn2f = 0.6931471805599453f;
 constexpr float kLo = 5.421010862427522e-20f;  // 2^-64
@@ -30,245 +34,6 @@ constexpr float kHi = 1.8446744073709552e19f;  // 2^64
 
 __device__ __forceinline__ float fex2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ float flg2(float x) { return __builtin_amdgcn_logf(x); }
-__device__ __forceinline__ float fwsum(float v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
-}
-__device__ __forceinline__ float fwmax(float v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
-    return v;
-}
-
-// 8 values of one chunk as floats: int16 w (I16) or K (BF16 / F32).
-template <int ST, bool NT>
-__device__ __forceinline__ void fload(const void *base, int64_t off, float (&x)[8]) {
-    if (ST == SK_W_I16) {
-        const int4 v = gload<NT>(reinterpret_cast<const int4 *>(reinterpret_cast<const int16_t *>(base) + off));
-        x[0] = (float)(short)(v.x & 0xffff); x[1] = (float)(v.x >> 16);
-        x[2] = (float)(short)(v.y & 0xffff); x[3] = (float)(v.y >> 16);
-        x[4] = (float)(short)(v.z & 0xffff); x[5] = (float)(v.z >> 16);
-        x[6] = (float)(short)(v.w & 0xffff); x[7] = (float)(v.w >> 16);
-    } else if (ST == SK_K_BF16) {
-        const int4 v = gload<NT>(reinterpret_cast<const int4 *>(reinterpret_cast<const uint16_t *>(base) + off));
-        const uint32_t q[4] = {(uint32_t)v.x, (uint32_t)v.y, (uint32_t)v.z, (uint32_t)v.w};
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            x[2 * k] = __uint_as_float(q[k] << 16);
-            x[2 * k + 1] = __uint_as_float(q[k] & 0xffff0000u);
-        }
-    } else {
-        const float4 *p = reinterpret_cast<const float4 *>(reinterpret_cast<const float *>(base) + off);
-        const float4 a = gload<NT>(p), b = gload<NT>(p + 1);
-        x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
-        x[4] = b.x; x[5] = b.y; x[6] = b.z; x[7] = b.w;
-    }
-}
-
-template <int ST, int CPT, bool NT>
-__global__ __launch_bounds__(kFT) void k_fused(const Inst *__restrict__ insts, int inst) {
-    __shared__ float red[kFT / kWave][kFR];
-    __shared__ float rowinv[kFR];
-    __shared__ int rowbad[kFR];
-    const Inst &I = insts[inst];
-    Ctl *ctl = I.ctl;
-    if (ctl->state != ST_RUNNING) return;
-    if (ST != SK_W_I16 && ctl->need_absorb) return;
-    const int n = I.n;
-    const int t = threadIdx.x, wave = t / kWave, lane = t % kWave;
-    const int iter = ctl->iter;
-    const int par = iter & 1;
-    const bool sent = ST == SK_W_I16 && ctl->sent != 0u;
-    const float pf = (float)ctl->p;
-    const int64_t pitch = ST == SK_W_I16 ? I.pitch : I.kpitch;
-    const void *base = ST == SK_W_I16 ? (const void *)I.W : (const void *)I.K;
-    // rows of this workgroup
-    const int per = (n + (int)gridDim.x - 1) / (int)gridDim.x;
-    const int r0 = blockIdx.x * per, r1 = min(n, r0 + per);
-    // owned columns and their potentials
-    int c0[CPT];
-    bool own[CPT];
-    float gx[CPT][8], gy[CPT][8], acc[CPT][8];
-#pragma unroll
-    for (int k = 0; k < CPT; ++k) {
-        c0[k] = (t + k * kFT) * 8;
-        own[k] = c0[k] < n;
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            acc[k][c] = 0.f;
-            if (ST == SK_W_I16) {
-                gx[k][c] = own[k] ? (float)I.G[c0[k] + c] : 0.f;
-                gy[k][c] = own[k] ? I.gam[c0[k] + c] * kL2e : 0.f;
-            } else {
-                gx[k][c] = own[k] && c0[k] + c < n ? I.b[c0[k] + c] : 0.f;
-                gy[k][c] = 0.f;
-            }
-        }
-    }
-    float resmax = 0.f, drift = 0.f;
-    for (int rb = r0; rb < r1; rb += kFR) {
-        float s[kFR][CPT][8];
-        float part[kFR];
-        float Ff[kFR];
-        // A: s_ij and row partials
-#pragma unroll
-        for (int rr = 0; rr < kFR; ++rr) {
-            const int row = rb + rr;
-            part[rr] = 0.f;
-            Ff[rr] = (ST == SK_W_I16 && row < r1) ? (float)I.F[par][row] : 0.f;
-#pragma unroll
-            for (int k = 0; k < CPT; ++k) {
-#pragma unroll
-                for (int c = 0; c < 8; ++c) s[rr][k][c] = 0.f;
-                if (row < r1 && own[k]) {
-                    float x[8];
-                    fload<ST, NT>(base, (int64_t)row * pitch + c0[k], x);
-#pragma unroll
-                    for (int c = 0; c < 8; ++c) {
-                        float e;
-                        if (ST == SK_W_I16) {
-                            const float Iv = fmaf(x[c], pf, gx[k][c]) + Ff[rr];
-                            e = fex2(fmaf(Iv, kL2e, gy[k][c]));
-                            if (sent && x[c] == -32768.0f) e = 0.f;
-                        } else {
-                            e = x[c] * gx[k][c];
-                        }
-                        s[rr][k][c] = e;
-                        part[rr] += e;
-                    }
-                }
-            }
-        }
-#pragma unroll
-        for (int rr = 0; rr < kFR; ++rr) {
-            const float v = fwsum(part[rr]);
-            if (lane == 0) red[wave][rr] = v;
-        }
-        __syncthreads();
-        if (t < kFR) {
-            const int row = rb + t;
-            float S = 0.f;
-            for (int w = 0; w < kFT / kWave; ++w) S += red[w][t];
-            int bad = 0;
-            if (row < r1) {
-                if (ST == SK_W_I16) {
-                    bad = !(S >= kLo && S <= kHi);
-                    if (!bad) {
-                        const float l2S = flg2(S);
-                        float phin = -l2S * kLn2f;
-                        const float kk = rintf(phin);
-                        I.F[par ^ 1][row] = I.F[par][row] + (int)kk;
-                        I.phi[par ^ 1][row] = phin - kk;
-                        const float r = fex2(fmaf(I.phi[par][row], kL2e, l2S));
-                        resmax = fmaxf(resmax, fabsf(r - 1.f));
-                    }
-                    rowinv[t] = bad ? 0.f : 1.f / S;
-                } else {
-                    const float Sc = fminf(fmaxf(S, kLo), kHi);
-                    const float anew = 1.f / Sc;
-                    I.a[par ^ 1][row] = anew;
-                    resmax = fmaxf(resmax, fabsf(I.a[par][row] * S - 1.f));
-                    drift = fmaxf(drift, fabsf(flg2(anew)));
-                    rowinv[t] = anew;
-                }
-            } else {
-                rowinv[t] = 0.f;
-            }
-            rowbad[t] = bad;
-        }
-        __syncthreads();
-        // exact max shift for a row whose sum left the safe range (I16 only)
-        if (ST == SK_W_I16) {
-#pragma unroll
-            for (int rr = 0; rr < kFR; ++rr) {
-                if (!rowbad[rr]) continue;  // uniform across the workgroup
-                const int row = rb + rr;
-                float m = -INFINITY;
-#pragma unroll
-                for (int k = 0; k < CPT; ++k) {
-                    if (!own[k]) continue;
-                    float x[8];
-                    fload<ST, NT>(base, (int64_t)row * pitch + c0[k], x);
-#pragma unroll
-                    for (int c = 0; c < 8; ++c) {
-                        const float Iv = fmaf(x[c], pf, gx[k][c]) + Ff[rr];
-                        float y = fmaf(Iv, kL2e, gy[k][c]);
-                        if (sent && x[c] == -32768.0f) y = -INFINITY;
-                        m = fmaxf(m, y);
-                        s[rr][k][c] = y;  // exponent, shifted below
-                    }
-                }
-                m = fwmax(m);
-                __syncthreads();
-                if (lane == 0) red[wave][0] = m;
-                __syncthreads();
-                float M = -INFINITY;
-                for (int w = 0; w < kFT / kWave; ++w) M = fmaxf(M, red[w][0]);
-                float pp = 0.f;
-#pragma unroll
-                for (int k = 0; k < CPT; ++k)
-#pragma unroll
-                    for (int c = 0; c < 8; ++c) {
-                        const float e = own[k] && M != -INFINITY ? fex2(s[rr][k][c] - M) : 0.f;
-                        s[rr][k][c] = e;
-                        pp += e;
-                    }
-                pp = fwsum(pp);
-                __syncthreads();
-                if (lane == 0) red[wave][1] = pp;
-                __syncthreads();
-                if (t == 0) {
-                    float S2 = 0.f;
-                    for (int w = 0; w < kFT / kWave; ++w) S2 += red[w][1];
-                    if (M == -INFINITY) {
-                        atomicOr(&ctl->err, ERR_EMPTY_ROW);
-                        rowinv[rr] = 0.f;
-                    } else {
-                        const float l2S = M + flg2(S2);
-                        const double phin = -(double)l2S * (double)kLn2f;
-                        const double kk = rint(phin);
-                        I.F[par ^ 1][row] = I.F[par][row] + (int)kk;
-                        I.phi[par ^ 1][row] = (float)(phin - kk);
-                        const float r = fex2(fmaf(I.phi[par][row], kL2e, l2S));
-                        resmax = fmaxf(resmax, fabsf(r - 1.f));
-                        rowinv[rr] = 1.f / S2;
-                    }
-                }
-                __syncthreads();
-            }
-        }
-        // B: column accumulation with the new row scalings
-#pragma unroll
-        for (int rr = 0; rr < kFR; ++rr) {
-            const float inv = rowinv[rr];
-#pragma unroll
-            for (int k = 0; k < CPT; ++k)
-#pragma unroll
-                for (int c = 0; c < 8; ++c) acc[k][c] = fmaf(s[rr][k][c], inv, acc[k][c]);
-        }
-        __syncthreads();  // red / rowinv are reused by the next group
-    }
-    // fixed-slot column partials of this workgroup
-    float *dst = I.colpart + (int64_t)blockIdx.x * n;
-#pragma unroll
-    for (int k = 0; k < CPT; ++k)
-        if (own[k]) {
-#pragma unroll
-            for (int c = 0; c < 8; ++c)
-                if (c0[k] + c < n) dst[c0[k] + c] = acc[k][c];
-        }
-    // residual (and drift) slot of this workgroup, reduced by the finaliser
-    if (t < kFR) {
-        red[0][t] = resmax;
-        red[1][t] = drift;
-    }
-    __syncthreads();
-    if (t == 0) {
-        I.res_slots[blockIdx.x] = fmaxf(red[0][0], red[0][1]);
-        if (ST != SK_W_I16) I.drift_slots[blockIdx.x] = fmaxf(red[1][0], red[1][1]);
-    }
-}
 
 // ---------------------------------------------------------------- int16 W
 // Sums across lanes with DPP moves in a fixed order (deterministic, no LDS
@@ -299,17 +64,32 @@ __device__ __forceinline__ float gld(const float *p) { return *(const SK_GLOBAL 
 __device__ __forceinline__ void gst(int32_t *p, int v) { *(SK_GLOBAL int32_t *)p = v; }
 __device__ __forceinline__ void gst(float *p, float v) { *(SK_GLOBAL float *)p = v; }
 
-// Rows of a group (FR) are loaded one group ahead into the other of two
-// register buffers, so the next group's loads are in flight while this one is
-// reduced. One barrier per group: the per-wave row partials are
-// double-buffered by group parity and every lane forms S_i from the 16
-// partials with dpp_sum16. The scalar work of row i (its new potentials and
-// residual) is done by lane 0 of wave (i - r0) mod 16, so no single wave falls
-// behind at every barrier.
-template <int CPT, int FR, bool SENT, bool NT>
+// Sum of the NW per-wave partials in every lane, bitwise equal in all lanes:
+// lane l passes partial l mod NW, and DPP adds equal-shaped partial sums.
+template <int NW>
+__device__ __forceinline__ float sum_partials(float x) {
+    static_assert(NW == 8 || NW == 16, "8 or 16 waves per workgroup");
+    x += dppf<0xB1>(x);   // quad_perm [1,0,3,2]
+    x += dppf<0x4E>(x);   // quad_perm [2,3,0,1]
+    x += dppf<0x141>(x);  // row_half_mirror
+    if (NW == 16) x += dppf<0x140>(x);  // row_mirror
+    return x;
+}
+
+// FT threads per workgroup (NW = FT / 64 waves), CPT 8-column chunks per
+// thread (thread t owns chunks t, t + FT, ...), FR rows per group. Groups are
+// loaded NB - 1 groups ahead into a ring of NB register buffers, so that many
+// groups' loads are in flight while one is reduced. One barrier per group:
+// the per-wave row partials are double-buffered by group parity and every
+// lane forms S_i from the NW partials. The scalar work of row i (its new
+// potentials and residual) is done by lane 0 of wave (i - r0) mod NW, so no
+// single wave falls behind at every barrier.
+template <int FT, int CPT, int FR, int NB, bool SENT, bool NT>
 __device__ __forceinline__ void fused_i16_body(const Inst &I, Ctl *ctl, const float *tab,
-                                               float (*red)[kFT / kWave][kFR], int *redm,
-                                               float *reds, float *wres, float *gl) {
+                                               float (*red)[FT / kWave][kFR], int *redm,
+                                               float *reds, float *wres, int2 *gc, int *sF,
+                                               float *sphi) {
+    constexpr int NW = FT / kWave;
     const int n = I.n;
     const int t = threadIdx.x, wave = t / kWave, lane = t % kWave;
     const int par = ctl->iter & 1;
@@ -324,31 +104,40 @@ __device__ __forceinline__ void fused_i16_body(const Inst &I, Ctl *ctl, const fl
     float *phin_p = I.phi[par ^ 1];
     int c0[CPT];
     bool own[CPT];
-    // per owned column: 4 G_j in registers, exp(gam_j) in LDS at
-    // gl[(k * 8 + c) * kFT + t] (each lane reads consecutive words)
-    int A[CPT][8];
+    // per owned column (4 G_j, exp(gam_j)) in one 8-byte LDS word at
+    // gc[(k * 8 + c) * FT + t] (the lanes of a wave read consecutive words),
+    // which leaves the registers to the terms of FR rows
     float acc[CPT][8];
 #pragma unroll
     for (int k = 0; k < CPT; ++k) {
-        c0[k] = (t + k * kFT) * 8;
+        c0[k] = (t + k * FT) * 8;
         own[k] = c0[k] < n;
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
-            A[k][c] = own[k] ? 4 * gld(I.G + c0[k] + c) : 0;
-            gl[(k * 8 + c) * kFT + t] = own[k] ? fex2(gld(I.gam + c0[k] + c) * kL2e) : 0.f;
+            gc[(k * 8 + c) * FT + t] =
+                own[k] ? make_int2(4 * gld(I.G + c0[k] + c), __float_as_int(fex2(gld(I.gam + c0[k] + c) * kL2e)))
+                       : make_int2(0, 0);
             acc[k][c] = 0.f;
         }
     }
+    // F_i and phi_i of the block's rows in LDS: read from LDS while the
+    // rows' loads are in flight (a vector load here would be counted behind
+    // them and wait for all of them)
+    for (int r = r0 + t; r < r1; r += FT) {
+        sF[r - r0] = gld(Fp + r);
+        sphi[r - r0] = gld(phip + r);
+    }
+    __syncthreads();
     float resmax = 0.f;
-    int4 ba[FR][CPT], bb[FR][CPT];
-    auto load_group = [&](int4 (&buf)[FR][CPT], int rb) {
+    int4 buf[NB][FR][CPT];
+    auto load_group = [&](int4 (&bf)[FR][CPT], int rb) {
 #pragma unroll
         for (int rr = 0; rr < FR; ++rr)
 #pragma unroll
             for (int k = 0; k < CPT; ++k)
-                buf[rr][k] = (rb + rr < r1 && own[k])
-                                 ? gload<NT>(reinterpret_cast<const int4 *>(W + (int64_t)(rb + rr) * pitch + c0[k]))
-                                 : make_int4(0, 0, 0, 0);
+                bf[rr][k] = (rb + rr < r1 && own[k])
+                                ? gload<NT>(reinterpret_cast<const int4 *>(W + (int64_t)(rb + rr) * pitch + c0[k]))
+                                : make_int4(0, 0, 0, 0);
     };
     int parity = 0;
     auto process = [&](const int4 (&cur)[FR][CPT], int rb) {
@@ -359,7 +148,7 @@ __device__ __forceinline__ void fused_i16_body(const Inst &I, Ctl *ctl, const fl
 #pragma unroll
         for (int rr = 0; rr < FR; ++rr) {
             const int row = rb + rr;
-            Fi[rr] = row < r1 ? gld(Fp + row) : 0;
+            Fi[rr] = row < r1 ? sF[row - r0] : 0;
             const int B = 4 * (Fi[rr] - kTabLo);
             part[rr] = 0.f;
 #pragma unroll
@@ -370,10 +159,11 @@ __device__ __forceinline__ void fused_i16_body(const Inst &I, Ctl *ctl, const fl
                     unpack8i(cur[rr][k], w);
 #pragma unroll
                     for (int c = 0; c < 8; ++c) {
-                        float e = tab_at(tab, tab_off(p4, w[c], A[k][c], B));
+                        const int2 ag = gc[(k * 8 + c) * FT + t];
+                        float e = tab_at(tab, tab_off(p4, w[c], ag.x, B));
                         if (SENT) e = (w[c] == SK_SENTINEL) ? 0.f : e;
                         T[rr][k][c] = e;
-                        part[rr] = fmaf(e, gl[(k * 8 + c) * kFT + t], part[rr]);
+                        part[rr] = fmaf(e, __int_as_float(ag.y), part[rr]);
                     }
                 }
             }
@@ -388,10 +178,10 @@ __device__ __forceinline__ void fused_i16_body(const Inst &I, Ctl *ctl, const fl
 #pragma unroll
         for (int rr = 0; rr < FR; ++rr) {
             const int row = rb + rr;
-            const float S = dpp_sum16(red[parity][lane & 15][rr]);
+            const float S = sum_partials<NW>(red[parity][lane & (NW - 1)][rr]);
             inv[rr] = 0.f;
             if (row >= r1) continue;  // uniform
-            const bool writer = t == ((row - r0) & 15) * kWave;
+            const bool writer = t == ((row - r0) % NW) * kWave;
             if (S >= kLo && S <= kHi) {
                 inv[rr] = __builtin_amdgcn_rcpf(S);
                 if (writer) {
@@ -401,7 +191,7 @@ __device__ __forceinline__ void fused_i16_body(const Inst &I, Ctl *ctl, const fl
                     const float kk = rintf(phin);
                     gst(Fn + row, Fi[rr] + (int)kk);
                     gst(phin_p + row, phin - kk);
-                    const float r = fex2(fmaf(gld(phip + row), kL2e, l2S));
+                    const float r = fex2(fmaf(sphi[row - r0], kL2e, l2S));
                     resmax = fmaxf(resmax, fabsf(r - 1.f));
                 }
                 continue;
@@ -417,13 +207,13 @@ __device__ __forceinline__ void fused_i16_body(const Inst &I, Ctl *ctl, const fl
 #pragma unroll
                 for (int c = 0; c < 8; ++c)
                     if (!SENT || w[c] != SK_SENTINEL)
-                        m4 = max(m4, __mul24(p4, w[c]) + A[k][c] + 4 * Fi[rr]);
+                        m4 = max(m4, __mul24(p4, w[c]) + gc[(k * 8 + c) * FT + t].x + 4 * Fi[rr]);
             }
             m4 = wave_max_i(m4);
             if (lane == 0) redm[wave] = m4;
             __syncthreads();
             int mm = INT_MIN;
-            for (int w2 = 0; w2 < kFT / kWave; ++w2) mm = max(mm, redm[w2]);
+            for (int w2 = 0; w2 < NW; ++w2) mm = max(mm, redm[w2]);
             const int M = mm >> 2;  // exact: a multiple of 4 (unused if mm == INT_MIN)
             float s2 = 0.f;
 #pragma unroll
@@ -433,19 +223,19 @@ __device__ __forceinline__ void fused_i16_body(const Inst &I, Ctl *ctl, const fl
                 unpack8i(cur[rr][k], w);
 #pragma unroll
                 for (int c = 0; c < 8; ++c) {
-                    float e = mm == INT_MIN
-                                  ? 0.f
-                                  : tab_at(tab, tab_off(p4, w[c], A[k][c], 4 * (Fi[rr] - M - kTabLo)));
+                    const int2 ag = gc[(k * 8 + c) * FT + t];
+                    float e = mm == INT_MIN ? 0.f
+                                            : tab_at(tab, tab_off(p4, w[c], ag.x, 4 * (Fi[rr] - M - kTabLo)));
                     if (SENT) e = (w[c] == SK_SENTINEL) ? 0.f : e;
                     T[rr][k][c] = e;
-                    s2 = fmaf(e, gl[(k * 8 + c) * kFT + t], s2);
+                    s2 = fmaf(e, __int_as_float(ag.y), s2);
                 }
             }
             s2 = dpp_wave_sum(s2);
             if (lane == 0) reds[wave] = s2;
             __syncthreads();
             float S2 = 0.f;
-            for (int w2 = 0; w2 < kFT / kWave; ++w2) S2 += reds[w2];
+            for (int w2 = 0; w2 < NW; ++w2) S2 += reds[w2];
             if (mm == INT_MIN) {
                 if (t == 0) atomicOr(&ctl->err, ERR_EMPTY_ROW);
             } else {
@@ -456,7 +246,7 @@ __device__ __forceinline__ void fused_i16_body(const Inst &I, Ctl *ctl, const fl
                     const float kk = rintf(phin);
                     gst(Fn + row, Fi[rr] - M + (int)kk);
                     gst(phin_p + row, phin - kk);
-                    const float r = fex2(fmaf(gld(phip + row) + (float)M, kL2e, l2S));
+                    const float r = fex2(fmaf(sphi[row - r0] + (float)M, kL2e, l2S));
                     resmax = fmaxf(resmax, fabsf(r - 1.f));
                 }
             }
@@ -475,13 +265,20 @@ __device__ __forceinline__ void fused_i16_body(const Inst &I, Ctl *ctl, const fl
         }
         parity ^= 1;
     };
-    if (r0 < r1) load_group(ba, r0);
-    for (int rb = r0; rb < r1; rb += 2 * FR) {
-        if (rb + FR < r1) load_group(bb, rb + FR);
-        process(ba, rb);
-        if (rb + FR >= r1) break;
-        if (rb + 2 * FR < r1) load_group(ba, rb + 2 * FR);
-        process(bb, rb + FR);
+    // ring of NB buffers: group g lives in buf[g mod NB]; while group g is
+    // reduced, groups g+1 .. g+NB-1 are loading
+#pragma unroll
+    for (int b = 0; b < NB - 1; ++b)
+        if (r0 + b * FR < r1) load_group(buf[b], r0 + b * FR);
+    for (int rb = r0; rb < r1; rb += NB * FR) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int rc = rb + b * FR;
+            if (rc >= r1) break;  // uniform
+            const int rn = rc + (NB - 1) * FR;
+            if (rn < r1) load_group(buf[(b + NB - 1) % NB], rn);
+            process(buf[b], rc);
+        }
     }
     float *dst = I.colpart + (int64_t)blockIdx.x * n;
 #pragma unroll
@@ -489,7 +286,7 @@ __device__ __forceinline__ void fused_i16_body(const Inst &I, Ctl *ctl, const fl
         if (own[k]) {
 #pragma unroll
             for (int c = 0; c < 8; ++c)
-                if (c0[k] + c < n) gst(dst + c0[k] + c, acc[k][c] * gl[(k * 8 + c) * kFT + t]);
+                if (c0[k] + c < n) gst(dst + c0[k] + c, acc[k][c] * __int_as_float(gc[(k * 8 + c) * FT + t].y));
         }
     // residual slot of this workgroup: lane 0 of every wave formed the
     // residuals of its rows
@@ -497,38 +294,217 @@ __device__ __forceinline__ void fused_i16_body(const Inst &I, Ctl *ctl, const fl
     __syncthreads();
     if (t == 0) {
         float m = 0.f;
-        for (int w2 = 0; w2 < kFT / kWave; ++w2) m = fmaxf(m, wres[w2]);
+        for (int w2 = 0; w2 < NW; ++w2) m = fmaxf(m, wres[w2]);
         I.res_slots[blockIdx.x] = m;
     }
 }
 
-// Rows per group: two with 8 owned columns per thread, one with 16 (register
-// budget of 128 VGPRs at 1024 threads).
-template <int CPT, bool NT>
-__global__ __launch_bounds__(kFT) void k_fused_i16(const Inst *__restrict__ insts, int inst) {
-    constexpr int FR = CPT == 1 ? 2 : 1;
+// Two shapes, both 1024 threads (four waves per SIMD, 128 VGPRs): n <= 8192
+// takes one chunk per thread and two rows per group, one group ahead; larger
+// n two chunks per thread and one row per group, two rows ahead (12 bytes
+// of spill). Measured at n = 16384: with the row potentials read from global
+// memory per row instead of LDS, 150.5 us; one row ahead 143.0 us, two rows
+// ahead 134.0 us; two rows per group (fewer barriers, more spill) 142.1 us;
+// 512 threads with four chunks each (two waves per SIMD, 238 VGPRs, up to
+// three rows ahead) 160-163 us at every depth.
+constexpr int kFusedAhead = 2;
+template <int FT, int CPT, int FR, int NB, bool NT>
+__global__ __launch_bounds__(FT) void k_fused_i16(const Inst *__restrict__ insts, int inst) {
+    __shared__ int sF[kFusedRows];
+    __shared__ float sphi[kFusedRows];
     __shared__ float tab[kTabN];
-    __shared__ float red[2][kFT / kWave][kFR];
-    __shared__ int redm[kFT / kWave];
-    __shared__ float reds[kFT / kWave];
-    __shared__ float wres[kFT / kWave];
-    __shared__ float gl[CPT * 8 * kFT];
+    __shared__ float red[2][FT / kWave][kFR];
+    __shared__ int redm[FT / kWave];
+    __shared__ float reds[FT / kWave];
+    __shared__ float wres[FT / kWave];
+    __shared__ int2 gc[CPT * 8 * FT];
     const Inst &I = insts[inst];
     Ctl *ctl = I.ctl;
     if (ctl->state != ST_RUNNING) return;
     fill_exp_table(tab);
     __syncthreads();
-    if (ctl->sent != 0u) fused_i16_body<CPT, FR, true, NT>(I, ctl, tab, red, redm, reds, wres, gl);
-    else fused_i16_body<CPT, FR, false, NT>(I, ctl, tab, red, redm, reds, wres, gl);
+    if (ctl->sent != 0u) fused_i16_body<FT, CPT, FR, NB, true, NT>(I, ctl, tab, red, redm, reds, wres, gc, sF, sphi);
+    else fused_i16_body<FT, CPT, FR, NB, false, NT>(I, ctl, tab, red, redm, reds, wres, gc, sF, sphi);
 }
 
+// ---------------------------------------------------------------- stored K
+// Raw words of one 8-entry chunk of K: BF16 (one 16-byte load) or F32 (two).
+template <int ST>
+struct KChunk {
+    int4 v[ST == SK_K_F32 ? 2 : 1];
+};
+template <int ST, bool NT>
+__device__ __forceinline__ KChunk<ST> kload(const void *K, int64_t off) {
+    KChunk<ST> ch;
+    if (ST == SK_K_BF16) {
+        ch.v[0] = gload<NT>(reinterpret_cast<const int4 *>(reinterpret_cast<const uint16_t *>(K) + off));
+    } else {
+        const int4 *q = reinterpret_cast<const int4 *>(reinterpret_cast<const float *>(K) + off);
+        ch.v[0] = gload<NT>(q);
+        ch.v[1] = gload<NT>(q + 1);
+    }
+    return ch;
+}
+template <int ST>
+__device__ __forceinline__ void kunpack(const KChunk<ST> &ch, float (&x)[8]) {
+    if (ST == SK_K_BF16) {
+        const uint32_t q[4] = {(uint32_t)ch.v[0].x, (uint32_t)ch.v[0].y, (uint32_t)ch.v[0].z, (uint32_t)ch.v[0].w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            x[2 * k] = __uint_as_float(q[k] << 16);
+            x[2 * k + 1] = __uint_as_float(q[k] & 0xffff0000u);
+        }
+    } else {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            x[4 * h] = __int_as_float(ch.v[h].x);
+            x[4 * h + 1] = __int_as_float(ch.v[h].y);
+            x[4 * h + 2] = __int_as_float(ch.v[h].z);
+            x[4 * h + 3] = __int_as_float(ch.v[h].w);
+        }
+    }
+}
+
+// Stored K: the row step a_i <- 1 / sum_j K_ij b_j (clamped to [2^-64, 2^64])
+// and the column sums sum_i K_ij a_i of the new iterate, times b_j at the
+// end. The raw K of a row stays in registers from its row sum to its column
+// update (one unpack and one FMA per entry in each), so no terms are kept and
+// NB - 1 rows are loading while one is reduced. a_i of the block's rows is
+// staged in LDS (a vector load per row would wait behind the rows' loads).
+template <int ST, int CPT, int FR, int NB, bool NT>
+__global__ __launch_bounds__(kFT) void k_fused(const Inst *__restrict__ insts, int inst) {
+    constexpr int NW = kFT / kWave;
+    __shared__ float red[2][NW][FR];
+    __shared__ float sa[kFusedRows];
+    __shared__ float wres[2][NW];
+    const Inst &I = insts[inst];
+    Ctl *ctl = I.ctl;
+    if (ctl->state != ST_RUNNING || ctl->need_absorb) return;
+    const int n = I.n;
+    const int t = threadIdx.x, wave = t / kWave, lane = t % kWave;
+    const int par = ctl->iter & 1;
+    const int64_t pitch = I.kpitch;
+    const void *K = I.K;
+    const int per = (n + (int)gridDim.x - 1) / (int)gridDim.x;
+    const int r0 = blockIdx.x * per, r1 = min(n, r0 + per);
+    int c0[CPT];
+    bool own[CPT];
+    float bj[CPT][8], acc[CPT][8];
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+        c0[k] = (t + k * kFT) * 8;
+        own[k] = c0[k] < n;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            acc[k][c] = 0.f;
+            bj[k][c] = own[k] && c0[k] + c < n ? gld(I.b + c0[k] + c) : 0.f;
+        }
+    }
+    for (int r = r0 + t; r < r1; r += kFT) sa[r - r0] = gld(I.a[par] + r);
+    __syncthreads();
+    float resmax = 0.f, drift = 0.f;
+    KChunk<ST> buf[NB][FR][CPT];
+    auto load_group = [&](KChunk<ST> (&bf)[FR][CPT], int rb) {
+#pragma unroll
+        for (int rr = 0; rr < FR; ++rr)
+#pragma unroll
+            for (int k = 0; k < CPT; ++k)
+                if (rb + rr < r1 && own[k]) bf[rr][k] = kload<ST, NT>(K, (int64_t)(rb + rr) * pitch + c0[k]);
+    };
+    int parity = 0;
+    auto process = [&](const KChunk<ST> (&cur)[FR][CPT], int rb) {
+#pragma unroll
+        for (int rr = 0; rr < FR; ++rr) {
+            float part = 0.f;
+            if (rb + rr < r1) {
+#pragma unroll
+                for (int k = 0; k < CPT; ++k)
+                    if (own[k]) {
+                        float x[8];
+                        kunpack<ST>(cur[rr][k], x);
+#pragma unroll
+                        for (int c = 0; c < 8; ++c) part = fmaf(x[c], bj[k][c], part);
+                    }
+            }
+            const float v = dpp_wave_sum(part);
+            if (lane == 0) red[parity][wave][rr] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int rr = 0; rr < FR; ++rr) {
+            const int row = rb + rr;
+            if (row >= r1) continue;  // uniform
+            const float S = sum_partials<NW>(red[parity][lane & (NW - 1)][rr]);
+            const float anew = 1.f / fminf(fmaxf(S, kLo), kHi);
+            if (t == ((row - r0) % NW) * kWave) {
+                gst(I.a[par ^ 1] + row, anew);
+                resmax = fmaxf(resmax, fabsf(sa[row - r0] * S - 1.f));
+                drift = fmaxf(drift, fabsf(flg2(anew)));
+            }
+#pragma unroll
+            for (int k = 0; k < CPT; ++k)
+                if (own[k]) {
+                    float x[8];
+                    kunpack<ST>(cur[rr][k], x);
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) acc[k][c] = fmaf(x[c], anew, acc[k][c]);
+                }
+        }
+        parity ^= 1;
+    };
+#pragma unroll
+    for (int b = 0; b < NB - 1; ++b)
+        if (r0 + b * FR < r1) load_group(buf[b], r0 + b * FR);
+    for (int rb = r0; rb < r1; rb += NB * FR) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int rc = rb + b * FR;
+            if (rc >= r1) break;  // uniform
+            if (rc + (NB - 1) * FR < r1) load_group(buf[(b + NB - 1) % NB], rc + (NB - 1) * FR);
+            process(buf[b], rc);
+        }
+    }
+    // fixed-slot column partials of this workgroup
+    float *dst = I.colpart + (int64_t)blockIdx.x * n;
+#pragma unroll
+    for (int k = 0; k < CPT; ++k)
+        if (own[k]) {
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+                if (c0[k] + c < n) gst(dst + c0[k] + c, acc[k][c] * bj[k][c]);
+        }
+    // residual and drift slots of this workgroup: lane 0 of every wave formed
+    // those of its rows
+    if (lane == 0) {
+        wres[0][wave] = resmax;
+        wres[1][wave] = drift;
+    }
+    __syncthreads();
+    if (t == 0) {
+        float m = 0.f, d = 0.f;
+        for (int w2 = 0; w2 < NW; ++w2) {
+            m = fmaxf(m, wres[0][w2]);
+            d = fmaxf(d, wres[1][w2]);
+        }
+        I.res_slots[blockIdx.x] = m;
+        I.drift_slots[blockIdx.x] = d;
+    }
+}
+
+// Stored K: two rows per group. n <= 8192 (one chunk per thread) keeps two
+// groups loading ahead; larger n two (BF16) or one (F32, whose rows are twice
+// the registers). Measured at n = 16384, BF16 / F32: one row per group at
+// depths 2-6 104-106 / 227-232 us; two rows per group 104 (two ahead) / 214
+// (one ahead; two ahead spills, 307); the earlier kernel with no rows ahead
+// and the row potentials read per row from global memory 143 / 219 us.
 template <int ST, bool NT>
 static hipError_t launch_fused_st(const Inst *d_insts, int inst, int n, int grid, hipStream_t st) {
-    const int cpt = (n / 8 + kFT - 1) / kFT;
+    const int cpt = (n + 8 * kFT - 1) / (8 * kFT);
     if (cpt <= 1)
-        hipLaunchKernelGGL((k_fused<ST, 1, NT>), dim3(grid), dim3(kFT), 0, st, d_insts, inst);
+        hipLaunchKernelGGL((k_fused<ST, 1, 2, 3, NT>), dim3(grid), dim3(kFT), 0, st, d_insts, inst);
     else
-        hipLaunchKernelGGL((k_fused<ST, 2, NT>), dim3(grid), dim3(kFT), 0, st, d_insts, inst);
+        hipLaunchKernelGGL((k_fused<ST, 2, 2, ST == SK_K_BF16 ? 3 : 2, NT>), dim3(grid), dim3(kFT), 0, st,
+                           d_insts, inst);
     return hipGetLastError();
 }
 
@@ -537,9 +513,10 @@ static hipError_t launch_fused_nt(const Inst *d_insts, int inst, int n, int grid
                                   hipStream_t st) {
     if (storage == SK_W_I16) {
         if ((n / 8 + kFT - 1) / kFT <= 1)
-            hipLaunchKernelGGL((k_fused_i16<1, NT>), dim3(grid), dim3(kFT), 0, st, d_insts, inst);
+            hipLaunchKernelGGL((k_fused_i16<kFT, 1, 2, 2, NT>), dim3(grid), dim3(kFT), 0, st, d_insts, inst);
         else
-            hipLaunchKernelGGL((k_fused_i16<2, NT>), dim3(grid), dim3(kFT), 0, st, d_insts, inst);
+            hipLaunchKernelGGL((k_fused_i16<kFT, 2, 1, kFusedAhead + 1, NT>), dim3(grid), dim3(kFT), 0, st,
+                               d_insts, inst);
         return hipGetLastError();
     }
     if (storage == SK_K_BF16) return launch_fused_st<SK_K_BF16, NT>(d_insts, inst, n, grid, st);

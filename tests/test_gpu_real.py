@@ -98,7 +98,7 @@ def test_real_fixed_iterations_match_oracle(ctx, kind, n, P, iters):
         Lg = p * (B + ub_g[:, None] + vb_g[None, :])
         Lo = p * (B + ub_o[:, None] + vb_o[None, :])
     sig = np.isfinite(Lo) & (Lo > np.log(1e-6))
-    assert np.abs(Lg - Lo)[sig].max() < 1e-4
+    assert np.abs(Lg[sig] - Lo[sig]).max() < 1e-4
     Xg = oracle.scaled_matrix(B, p, ub_g, vb_g)
     Xo = oracle.scaled_matrix(B, p, ub_o, vb_o)
     assert np.abs(Xg - Xo).max() < 1e-5
