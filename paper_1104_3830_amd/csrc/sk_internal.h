@@ -28,8 +28,9 @@ __host__ __device__ constexpr int pad8(int n) { return (n + 7) & ~7; }
 // |B| = |4 (F_i - kTabLo)| < 2^29 (the potentials stay within a few p times
 // the weight range, below 2^26), 4 p w + kPadExp4 + B lies in (-2^31, 0), so
 // the exp-table read clamps to its zero entry and the column adds exactly 0;
-// kPadG puts the exact exponent far below every skip bound of the FP64 check
-// (which also masks these columns explicitly).
+// kPadG puts the exact exponent (with w read as SK_SENTINEL there, p w >=
+// -2^26) below -2^27, far below every skip bound of the FP64 check and the
+// kept test, which therefore need no explicit mask for these columns.
 constexpr int kPadExp4 = -(1 << 30);
 constexpr int kPadG = -(1 << 28);
 
@@ -236,9 +237,9 @@ hipError_t launch_col_finalize(const Inst *d_insts, const FinUnit *d_units, int 
                                int mode, hipStream_t st);
 hipError_t launch_check_rows(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
                              double *rsum, double *rmax, double logt, int64_t *counts,
-                             int32_t *hint, size_t lds_bytes, hipStream_t st);
+                             int32_t *hint, size_t lds_bytes, int nt_loads, hipStream_t st);
 hipError_t launch_check_cols(const Inst *d_insts, int inst, int n, int nseg, int vec8,
-                             double *part, double *csum, hipStream_t st);
+                             double *part, double *csum, int nt_loads, hipStream_t st);
 hipError_t launch_prune_count(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
                               double logt, int64_t *counts, size_t lds_bytes, hipStream_t st);
 hipError_t launch_scan(const int64_t *counts, int64_t *row_ptr, int n, hipStream_t st,
@@ -247,7 +248,7 @@ hipError_t launch_check_reduce(const Inst *d_insts, int inst, const double *rsum
                                const double *rmax, const double *csum, double *out, hipStream_t st);
 hipError_t launch_prune_fill(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
                              double logt, const int64_t *row_ptr, int32_t *col, int16_t *w,
-                             size_t lds_bytes, hipStream_t st);
+                             size_t lds_bytes, int nt_loads, hipStream_t st);
 hipError_t launch_absorb(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
                          size_t lds_bytes, int storage, hipStream_t st);
 hipError_t launch_row_sweep_k(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,

@@ -603,12 +603,144 @@ __device__ __forceinline__ double logv_of(int2 q) {
 // With counts != nullptr it also counts the entries with log x_ij >= logt
 // (the row lengths of B for the scan) and stores in hint[i] the first column
 // of the row's largest x_ij (a starting matching for the exact solve).
+//
+// 8-wide rows: an entry goes through FP64 (its exp, the kept test, the row
+// maximum) only when its exact integer exponent reaches eskip; such entries
+// are few (about one per 512-column chunk at n = 16384) and scattered over
+// the lanes, so they are queued per wave in LDS as (column, w) and evaluated
+// 64 at a time, one per lane, instead of one lane at a time in every chunk.
+// The queue order is fixed (chunk, then round, then lane), so the sums are
+// the same on every run.
+template <bool SENT, bool NT>
+__device__ __forceinline__ void check_row_v8(const Inst &I, const int2 *gq, int2 *qe, int row, int lane,
+                                             int eskip, double logt, double *rsum, double *rmax,
+                                             int64_t *counts, int32_t *hint) {
+    const int n = I.n, n8 = pad8(n) >> 3;
+    const int par = I.ctl->iter & 1;
+    const int pi = I.ctl->p, Fi = I.F[par][row];
+    const double p = (double)pi;
+    const double f = (double)Fi + (double)I.phi[par][row];
+    const int16_t *wr = I.W + (int64_t)row * I.pitch;
+    double s = 0.0, m = -INFINITY;
+    int jm = -1, cnt = 0;
+    int Emax = INT_MIN;  // this lane's largest exact exponent E = p w + F_i + G_j
+    // one entry in FP64 (t = p w_ij + log v_j, log x_ij = t + log u_i)
+    auto exact = [&](int j, int w) {
+        const int2 q = gq[(j & 7) * n8 + (j >> 3)];
+        const double pw = p * (double)w, lvj = logv_of(q);
+        const double t = pw + lvj;
+        const double lx = t + f;
+        if (lx > kNegligibleLog) s += exp(lx);
+        // the kept test in the exact arithmetic order of the fill kernel
+        cnt += (pw + f + lvj >= logt);
+        if (t > m || (t == m && j < jm)) {
+            m = t;
+            jm = j;
+        }
+    };
+    int qn = 0;  // queued entries (uniform across the wave)
+    auto flush = [&]() {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        if (lane < qn) {
+            const int2 e = qe[lane];
+            exact(e.x, e.y);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        qn = 0;
+    };
+    // Pass 1 takes in FP64 only the entries with E >= eskip (the others are
+    // negligible and below the threshold). The row maximum of t is at an
+    // entry with E >= E* - 1 (E* the largest E; |phi_i|, |gam_j| <= 1/2):
+    // when E* - 1 >= eskip pass 1 has seen it; otherwise (every entry
+    // negligible) pass 2 looks at the entries with E in [E* - 1, eskip).
+    // the loop bounds are uniform across the wave (the queue needs every lane)
+    constexpr int U = kVisitLoads;
+    for (int jb0 = 0; jb0 < n; jb0 += U * 512) {
+        int4 v[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int j0 = jb0 + k * 512 + lane * 8;
+            v[k] = j0 < n ? gload<NT>(reinterpret_cast<const int4 *>(wr + j0)) : make_int4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            if (jb0 + k * 512 >= n) break;
+            const int jj = jb0 + k * 512 + lane * 8;
+            int w[8];
+            unsigned flag = 0;
+            if (jj < n) {
+                unpack8i(v[k], w);
+                mask_pad8(w, jj, n);
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    const int E = pi * w[c] + gq[c * n8 + (jj >> 3)].x + Fi;
+                    if (!SENT || w[c] != SK_SENTINEL) {
+                        Emax = max(Emax, E);
+                        if (E >= eskip) flag |= 1u << c;
+                    }
+                }
+            }
+            // queue the flagged entries: per round, every lane with one left
+            // appends its lowest, in lane order
+            for (;;) {
+                const uint64_t mask = __ballot(flag != 0u);
+                if (mask == 0ull) break;
+                const int nq = __popcll(mask);
+                if (qn + nq > kWave) flush();
+                if (flag) {
+                    const int c = __ffs(flag) - 1;
+                    const int pos = qn + __popcll(mask & ((1ull << lane) - 1ull));
+                    qe[pos] = make_int2(jj + c, w[c]);
+                    flag &= flag - 1u;
+                }
+                qn += nq;
+            }
+        }
+    }
+    if (qn) flush();
+    const int Es = wave_max_i(Emax);
+    if (Es != INT_MIN && Es - 1 < eskip) {
+        visit_row(I, wr, lane, [&](int j, int w) {
+            if (w == SK_SENTINEL) return;
+            const int2 q = gq[(j & 7) * n8 + (j >> 3)];
+            const int E = pi * w + q.x + Fi;
+            if (E < Es - 1 || E >= eskip) return;
+            const double t = p * (double)w + logv_of(q);
+            if (t > m || (t == m && j < jm)) {
+                m = t;
+                jm = j;
+            }
+        });
+    }
+    s = wave_sum_d(s);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double m2 = __shfl_xor(m, o, kWave);
+        const int j2 = __shfl_xor(jm, o, kWave);
+        if (m2 > m || (m2 == m && (unsigned)j2 < (unsigned)jm)) {
+            m = m2;
+            jm = j2;
+        }
+        cnt += __shfl_xor(cnt, o, kWave);
+    }
+    if (lane == 0) {
+        rsum[row] = s;
+        rmax[row] = m;
+        if (counts) {
+            counts[row] = cnt;
+            hint[row] = jm;
+        }
+    }
+}
+
+template <bool NT>
 __global__ __launch_bounds__(kRowWaves * kWave) void k_check_rows(const Inst *__restrict__ insts,
                                                                     const RowUnit *__restrict__ units,
                                                                     int nunits, double *rsum,
                                                                     double *rmax, double logt,
                                                                     int64_t *counts, int32_t *hint) {
     extern __shared__ int2 gq[];
+    __shared__ int2 queue[kRowWaves][kWave];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     int u0, u1;
     unit_range(nunits, u0, u1);
@@ -625,6 +757,13 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_check_rows(const Inst *__
         }
         const int n = I.n, row = un.row0 + wave;
         if (row >= n) continue;
+        if (I.vec8) {
+            if (I.ctl->sent != 0u)
+                check_row_v8<true, NT>(I, gq, queue[wave], row, lane, eskip, logt, rsum, rmax, counts, hint);
+            else
+                check_row_v8<false, NT>(I, gq, queue[wave], row, lane, eskip, logt, rsum, rmax, counts, hint);
+            continue;
+        }
         const int par = I.ctl->iter & 1;
         const int pi = I.ctl->p, Fi = I.F[par][row];
         const double p = (double)pi;
@@ -632,67 +771,25 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_check_rows(const Inst *__
         const int16_t *wr = I.W + (int64_t)row * I.pitch;
         double s = 0.0, m = -INFINITY;
         int jm = -1, cnt = 0;
-        int Emax = INT_MIN;  // this lane's largest exact exponent E = p w + F_i + G_j
-        // one entry in FP64 (t = p w_ij + log v_j, log x_ij = t + log u_i)
+        int Emax = INT_MIN;
         auto exact = [&](int j, int w, int2 q) {
             const double pw = p * (double)w, lvj = logv_of(q);
             const double t = pw + lvj;
             const double lx = t + f;
             if (lx > kNegligibleLog) s += exp(lx);
-            // the kept test in the exact arithmetic order of the fill kernel
             cnt += (pw + f + lvj >= logt);
             if (t > m) {  // a lane visits its columns in increasing order
                 m = t;
                 jm = j;
             }
         };
-        // Pass 1 takes in FP64 only the entries with E >= eskip (the others
-        // are negligible and below the threshold). The row maximum of t is at
-        // an entry with E >= E* - 1 (E* the largest E; |phi_i|, |gam_j| <=
-        // 1/2): when E* - 1 >= eskip pass 1 has seen it; otherwise (every
-        // entry negligible) pass 2 looks at the entries with E in [E* - 1,
-        // eskip).
-        if (I.vec8) {
-            const int n8 = pad8(n) >> 3;
-            constexpr int U = kVisitLoads;
-            for (int j0 = lane * 8; j0 < n; j0 += U * 512) {
-                int4 v[U];
-#pragma unroll
-                for (int k = 0; k < U; ++k)
-                    v[k] = j0 + k * 512 < n ? gload<false>(reinterpret_cast<const int4 *>(wr + j0 + k * 512))
-                                            : make_int4(0, 0, 0, 0);
-#pragma unroll
-                for (int k = 0; k < U; ++k) {
-                    const int jj = j0 + k * 512;
-                    if (jj >= n) break;
-                    int w[8];
-                    unpack8i(v[k], w);
-                    mask_pad8(w, jj, n);
-                    unsigned flag = 0;
-#pragma unroll
-                    for (int c = 0; c < 8; ++c) {
-                        const int E = pi * w[c] + gq[c * n8 + (jj >> 3)].x + Fi;
-                        if (w[c] != SK_SENTINEL) {
-                            Emax = max(Emax, E);
-                            if (E >= eskip) flag |= 1u << c;
-                        }
-                    }
-                    if (flag) {
-#pragma unroll
-                        for (int c = 0; c < 8; ++c)
-                            if (flag & (1u << c)) exact(jj + c, w[c], gq[c * n8 + (jj >> 3)]);
-                    }
-                }
-            }
-        } else {
-            visit_row(I, wr, lane, [&](int j, int w) {
-                if (w == SK_SENTINEL) return;
-                const int2 q = gq_at(I, gq, j);
-                const int E = pi * w + q.x + Fi;
-                Emax = max(Emax, E);
-                if (E >= eskip) exact(j, w, q);
-            });
-        }
+        visit_row(I, wr, lane, [&](int j, int w) {
+            if (w == SK_SENTINEL) return;
+            const int2 q = gq_at(I, gq, j);
+            const int E = pi * w + q.x + Fi;
+            Emax = max(Emax, E);
+            if (E >= eskip) exact(j, w, q);
+        });
         const int Es = wave_max_i(Emax);
         if (Es != INT_MIN && Es - 1 < eskip) {
             visit_row(I, wr, lane, [&](int j, int w) {
@@ -785,6 +882,7 @@ __device__ __forceinline__ void check_cols_add8(const int4 v, int p, int2 rf, co
     }
 }
 
+template <bool NT>
 __global__ __launch_bounds__(kColWaves * kWave) void k_check_cols_part8(const Inst *__restrict__ insts,
                                                                         int inst, double *part) {
     __shared__ double red[kColWaves][kColTile8];
@@ -827,12 +925,12 @@ __global__ __launch_bounds__(kColWaves * kWave) void k_check_cols_part8(const In
             int4 v[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k)
-                v[k] = gload<false>(reinterpret_cast<const int4 *>(w0 + (int64_t)(r + k * kColWaves) * I.pitch));
+                v[k] = gload<NT>(reinterpret_cast<const int4 *>(w0 + (int64_t)(r + k * kColWaves) * I.pitch));
 #pragma unroll
             for (int k = 0; k < 4; ++k) check_cols_add8(v[k], p, rowf[r + k * kColWaves - r0], G, gm, s);
         }
         for (; r < r1; r += kColWaves) {
-            const int4 v = gload<false>(reinterpret_cast<const int4 *>(w0 + (int64_t)r * I.pitch));
+            const int4 v = gload<NT>(reinterpret_cast<const int4 *>(w0 + (int64_t)r * I.pitch));
             check_cols_add8(v, p, rowf[r - r0], G, gm, s);
         }
     }
@@ -932,34 +1030,55 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_prune_count(const Inst *_
 __global__ __launch_bounds__(1024) void k_scan(const int64_t *__restrict__ counts,
                                                int64_t *__restrict__ row_ptr, int n,
                                                int64_t *total_out) {
-    __shared__ int64_t part[1024];
-    const int t = threadIdx.x;
+    // thread t sums a contiguous block; the block sums are scanned with
+    // shuffles within each wave and across the 16 wave totals
+    // n <= kMaxN: at most kScanPer counts per thread, all loaded at once
+    constexpr int kScanPer = kMaxN / 1024;
+    __shared__ int64_t wsum[1024 / kWave];
+    const int t = threadIdx.x, wave = t / kWave, lane = t % kWave;
     const int per = (n + 1023) / 1024;
     const int a = min(n, t * per), b = min(n, a + per);
+    int64_t c[kScanPer];
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) c[k] = a + k < b ? counts[a + k] : 0;
     int64_t s = 0;
-    for (int i = a; i < b; ++i) s += counts[i];
-    part[t] = s;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) s += c[k];
+    int64_t x = s;  // inclusive scan within the wave
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int64_t y = __shfl_up(x, o, kWave);
+        if (lane >= o) x += y;
+    }
+    if (lane == kWave - 1) wsum[wave] = x;
     __syncthreads();
-    if (t == 0) {
-        int64_t run = 0;
-        for (int k = 0; k < 1024; ++k) {
-            const int64_t v = part[k];
-            part[k] = run;
-            run += v;
+    if (wave == 0) {
+        int64_t v = lane < 1024 / kWave ? wsum[lane] : 0;
+#pragma unroll
+        for (int o = 1; o < 1024 / kWave; o <<= 1) {
+            const int64_t y = __shfl_up(v, o, kWave);
+            if (lane >= o) v += y;
         }
-        row_ptr[n] = run;
-        if (total_out) *total_out = run;
+        if (lane < 1024 / kWave) wsum[lane] = v;
     }
     __syncthreads();
-    int64_t run = part[t];
-    for (int i = a; i < b; ++i) {
-        row_ptr[i] = run;
-        run += counts[i];
+    int64_t run = x - s + (wave > 0 ? wsum[wave - 1] : 0);
+    if (t == 1023) {
+        const int64_t total = wsum[1024 / kWave - 1];
+        row_ptr[n] = total;
+        if (total_out) *total_out = total;
     }
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k)
+        if (a + k < b) {
+            row_ptr[a + k] = run;
+            run += c[k];
+        }
 }
 
 // Writes the kept columns of each row in increasing order: each wave walks
 // its row in 64-column chunks and places the kept ones with a ballot prefix.
+template <bool NT>
 __global__ __launch_bounds__(kRowWaves * kWave) void k_prune_fill(const Inst *__restrict__ insts,
                                                                     const RowUnit *__restrict__ units,
                                                                     int nunits, double logt,
@@ -995,14 +1114,19 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_prune_fill(const Inst *__
             // skipped for the chunks where no lane keeps an entry
             constexpr int U = kVisitLoads;
             const int n8 = pad8(n) >> 3;
-            for (int jb0 = 0; jb0 < n; jb0 += U * 512) {
-                int4 vb[U];
+            const bool sent = I.ctl->sent != 0u;
+            // the next kVisitLoads chunks load while these are used
+            int4 vb[U], vn[U];
+            auto load_batch = [&](int4 (&b)[U], int jb0) {
 #pragma unroll
                 for (int k = 0; k < U; ++k) {
                     const int j0 = jb0 + k * 512 + lane * 8;
-                    vb[k] = j0 < n ? gload<false>(reinterpret_cast<const int4 *>(wr + j0))
-                                   : make_int4(0, 0, 0, 0);
+                    b[k] = j0 < n ? gload<NT>(reinterpret_cast<const int4 *>(wr + j0)) : make_int4(0, 0, 0, 0);
                 }
+            };
+            load_batch(vb, 0);
+            for (int jb0 = 0; jb0 < n; jb0 += U * 512) {
+                if (jb0 + U * 512 < n) load_batch(vn, jb0 + U * 512);
 #pragma unroll
                 for (int k = 0; k < U; ++k) {
                     const int jb = jb0 + k * 512;
@@ -1019,8 +1143,12 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_prune_fill(const Inst *__
                         unsigned cand = 0;
 #pragma unroll
                         for (int c = 0; c < 8; ++c)
-                            if (wv[c] != SK_SENTINEL && pi * wv[c] + gq[c * n8 + base].x + Fi >= eskip)
-                                cand |= 1u << c;
+                            if (pi * wv[c] + gq[c * n8 + base].x + Fi >= eskip) cand |= 1u << c;
+                        if (sent) {
+#pragma unroll
+                            for (int c = 0; c < 8; ++c)
+                                if (wv[c] == SK_SENTINEL) cand &= ~(1u << c);
+                        }
                         if (cand) {
 #pragma unroll
                             for (int c = 0; c < 8; ++c)
@@ -1049,6 +1177,8 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_prune_fill(const Inst *__
                         }
                     pos += total;
                 }
+#pragma unroll
+                for (int k = 0; k < U; ++k) vb[k] = vn[k];
             }
             continue;
         }
@@ -1586,9 +1716,13 @@ hipError_t launch_iter_end(const Inst *d_insts, int count, hipStream_t st, hipEv
 }
 hipError_t launch_check_rows(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
                              double *rsum, double *rmax, double logt, int64_t *counts,
-                             int32_t *hint, size_t lds_bytes, hipStream_t st) {
-    hipLaunchKernelGGL(k_check_rows, dim3(grid), dim3(kRowWaves * kWave), lds_bytes, st, d_insts, d_units,
-                       nunits, rsum, rmax, logt, counts, hint);
+                             int32_t *hint, size_t lds_bytes, int nt_loads, hipStream_t st) {
+    if (nt_loads)
+        hipLaunchKernelGGL(k_check_rows<true>, dim3(grid), dim3(kRowWaves * kWave), lds_bytes, st, d_insts,
+                           d_units, nunits, rsum, rmax, logt, counts, hint);
+    else
+        hipLaunchKernelGGL(k_check_rows<false>, dim3(grid), dim3(kRowWaves * kWave), lds_bytes, st, d_insts,
+                           d_units, nunits, rsum, rmax, logt, counts, hint);
     return hipGetLastError();
 }
 hipError_t launch_check_reduce(const Inst *d_insts, int inst, const double *rsum,
@@ -1597,9 +1731,12 @@ hipError_t launch_check_reduce(const Inst *d_insts, int inst, const double *rsum
     return hipGetLastError();
 }
 hipError_t launch_check_cols(const Inst *d_insts, int inst, int n, int nseg, int vec8,
-                             double *part, double *csum, hipStream_t st) {
-    if (vec8)
-        hipLaunchKernelGGL(k_check_cols_part8, dim3((n + kColTile8 - 1) / kColTile8, nseg),
+                             double *part, double *csum, int nt_loads, hipStream_t st) {
+    if (vec8 && nt_loads)
+        hipLaunchKernelGGL(k_check_cols_part8<true>, dim3((n + kColTile8 - 1) / kColTile8, nseg),
+                           dim3(kColWaves * kWave), 0, st, d_insts, inst, part);
+    else if (vec8)
+        hipLaunchKernelGGL(k_check_cols_part8<false>, dim3((n + kColTile8 - 1) / kColTile8, nseg),
                            dim3(kColWaves * kWave), 0, st, d_insts, inst, part);
     else
         hipLaunchKernelGGL(k_check_cols_part, dim3((n + 255) / 256, nseg), dim3(256), 0, st, d_insts,
@@ -1616,14 +1753,19 @@ hipError_t launch_prune_count(const Inst *d_insts, const RowUnit *d_units, int n
 }
 hipError_t launch_scan(const int64_t *counts, int64_t *row_ptr, int n, hipStream_t st,
                        int64_t *total_out) {
+    if (n < 0 || n > kMaxN) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, counts, row_ptr, n, total_out);
     return hipGetLastError();
 }
 hipError_t launch_prune_fill(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
                              double logt, const int64_t *row_ptr, int32_t *col, int16_t *w,
-                             size_t lds_bytes, hipStream_t st) {
-    hipLaunchKernelGGL(k_prune_fill, dim3(grid), dim3(kRowWaves * kWave), lds_bytes, st, d_insts, d_units,
-                       nunits, logt, row_ptr, col, w);
+                             size_t lds_bytes, int nt_loads, hipStream_t st) {
+    if (nt_loads)
+        hipLaunchKernelGGL(k_prune_fill<true>, dim3(grid), dim3(kRowWaves * kWave), lds_bytes, st, d_insts,
+                           d_units, nunits, logt, row_ptr, col, w);
+    else
+        hipLaunchKernelGGL(k_prune_fill<false>, dim3(grid), dim3(kRowWaves * kWave), lds_bytes, st, d_insts,
+                           d_units, nunits, logt, row_ptr, col, w);
     return hipGetLastError();
 }
 hipError_t set_kernel_attributes() {
@@ -1634,14 +1776,12 @@ hipError_t set_kernel_attributes() {
                           (const void *)k_nt_rows<true>, (const void *)k_nt_rows<false>})
         if ((e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds)) != hipSuccess)
             return e;
-    if ((e = hipFuncSetAttribute((const void *)k_check_rows,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds)) != hipSuccess)
-        return e;
-    if ((e = hipFuncSetAttribute((const void *)k_prune_count,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds)) != hipSuccess)
-        return e;
-    return hipFuncSetAttribute((const void *)k_prune_fill, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               lds);
+    for (const void *f : {(const void *)k_check_rows<true>, (const void *)k_check_rows<false>,
+                          (const void *)k_prune_count, (const void *)k_prune_fill<true>,
+                          (const void *)k_prune_fill<false>})
+        if ((e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds)) != hipSuccess)
+            return e;
+    return hipSuccess;
 }
 
 }  // namespace sk

@@ -711,10 +711,10 @@ sk_status sk::enqueue_check(sk_ctx *ctx, Batch &B, int k, const CheckCounts *cc)
     HIPCHK(ctx, PROF(ctx, KID_CHECK_ROWS,
                      launch_check_rows(B.d_insts, B.d_rows + first, nunits, grid, B.d_rsum,
                                        B.d_rmax, cc ? cc->logt : 0.0, cc ? cc->counts : nullptr,
-                                       cc ? cc->hint : nullptr, gq_lds_bytes(nn),
+                                       cc ? cc->hint : nullptr, gq_lds_bytes(nn), I.nt,
                                        ctx->stream)));
     HIPCHK(ctx, PROF(ctx, KID_CHECK_COLS, launch_check_cols(B.d_insts, k, nn, I.nseg, I.vec8,
-                                                            B.d_cpart, B.d_csum, ctx->stream)));
+                                                            B.d_cpart, B.d_csum, I.nt, ctx->stream)));
     HIPCHK(ctx, launch_check_reduce(B.d_insts, k, B.d_rsum, B.d_rmax, B.d_csum,
                                     B.d_checkout + 4 * (size_t)k, ctx->stream));
     return SK_OK;
@@ -935,7 +935,7 @@ sk_status sk_prune(sk_ctx *ctx, const int16_t *W, int32_t n, const void *potenti
     if (total > 0) {
         if (!csr->col || !csr->w) return fail(ctx, SK_EINVAL, "null col/w buffers");
         HIPCHK(ctx, PROF(ctx, KID_PRUNE_FILL, launch_prune_fill(B.d_insts, B.d_rows, nunits, B.row_grid, logt, csr->row_ptr,
-                                      csr->col, csr->w, gq_lds_bytes(n), ctx->stream)));
+                                      csr->col, csr->w, gq_lds_bytes(n), B.h_insts[0].nt, ctx->stream)));
     }
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     return SK_OK;

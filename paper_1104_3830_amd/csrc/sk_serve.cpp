@@ -321,7 +321,7 @@ static sk_status retire_all(Server *S, const std::vector<int> &fin) {
             const int grid = std::min(nunits, ctx->num_cus * 2);
             e = launch_prune_fill(B.d_insts, B.d_rows + first, nunits, grid,
                                   std::log(r->prm.threshold), d_rp, d_col, d_w,
-                                  gq_lds_bytes(r->n), ctx->stream);
+                                  gq_lds_bytes(r->n), B.h_insts[k].nt, ctx->stream);
             r->col.resize(nnz);
             r->w.resize(nnz);
             if (e == hipSuccess)

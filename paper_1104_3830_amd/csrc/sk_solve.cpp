@@ -76,7 +76,7 @@ sk_status reduce_and_solve(sk_ctx *ctx, Batch &B, Bump &rest, int64_t *d_rp, con
             return fail(ctx, SK_ENOMEM, "the reduced matrix keeps %lld entries; the arena cannot hold them",
                         (long long)nnz);
         HIPCHK(ctx, PROF(ctx, KID_PRUNE_FILL, launch_prune_fill(B.d_insts, B.d_rows, nunits, B.row_grid,
-                                                               logt, d_rp, d_col, d_w, lds, ctx->stream)));
+                                                               logt, d_rp, d_col, d_w, lds, I.nt, ctx->stream)));
         HIPCHK(ctx, hipMemcpyAsync(col, d_col, sizeof(int32_t) * (size_t)nnz,
                                    hipMemcpyDeviceToHost, ctx->stream));
         HIPCHK(ctx, hipMemcpyAsync(w, d_w, sizeof(int16_t) * (size_t)nnz, hipMemcpyDeviceToHost,
