@@ -260,7 +260,7 @@ hipError_t launch_col_sweep_k(const Inst *d_insts, const ColUnit *d_units, int n
 hipError_t launch_fold_k(const Inst *d_insts, int count, hipStream_t st);
 hipError_t launch_advance(const Inst *d_insts, int count, hipStream_t st);
 hipError_t launch_check_k(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid, int inst,
-                          int n, int nseg, int storage, double *rsum, double *part, double *csum,
+                          int n, int nseg, int storage, int nt, double *rsum, double *part, double *csum,
                           hipStream_t st);
 hipError_t launch_fused(const Inst *d_insts, int inst, int n, int grid, int storage, int nt_loads,
                         hipStream_t st);

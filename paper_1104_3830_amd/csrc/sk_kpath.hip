@@ -15,6 +15,7 @@
 #include <cstring>
 #include <vector>
 
+#include "sk_exptab.h"
 #include "sk_runtime.h"
 
 namespace sk {
@@ -73,14 +74,23 @@ __device__ __forceinline__ int kswz(int j, int n8) { return (j & 7) * n8 + (j >>
 
 // ---------------------------------------------------------------- absorption
 // K_ij = exp(p w_ij + F_i + phi_i + G_j + gam_j) from the committed
-// potentials (exact integer part, as in the log-domain sweeps); the committed
-// F/phi are copied to both parity buffers, a = b = 1.
-template <int ST>
+// potentials: exp(E_ij) of the exact integer exponent E = p w + F_i + G_j
+// from the LDS table (as in the log-domain sweeps), times exp(gam_j) and
+// exp(phi_i); entries above 2^64 are clamped there, those with E <= -88 are
+// 0. The committed F/phi are copied to both parity buffers, a = b = 1.
+// 8-wide rows: two 16-byte loads of W in flight per lane, with the
+// non-temporal hint above the cache size; K is stored without it (measured
+// at n = 16384: 193.5 / 326 us for BF16 / F32 K, against 221 / 415 us with
+// non-temporal stores and 212 / 353 us for the float exp2 of the assembled
+// exponent with one load in flight).
+template <int ST, bool NT>
 __global__ __launch_bounds__(kRowWaves * kWave) void k_absorb(const Inst *__restrict__ insts,
                                                               const RowUnit *__restrict__ units,
                                                               int nunits) {
-    extern __shared__ float2 pot[];
+    extern __shared__ int2 pot[];  // (4 G_j, bits of exp(gam_j))
+    __shared__ float tab[kTabN];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    fill_exp_table(tab);
     int u0, u1;
     krange(nunits, u0, u1);
     int cur = -1;
@@ -94,59 +104,61 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_absorb(const Inst *__rest
             __syncthreads();
             const int n8 = pad8(n) >> 3;
             for (int j = threadIdx.x; j < n; j += blockDim.x)
-                pot[I.vec8 ? kswz(j, n8) : j] = make_float2((float)I.G[j], I.gam[j] * kLog2eK);
+                pot[I.vec8 ? kswz(j, n8) : j] = make_int2(4 * I.G[j], __float_as_int(kex2(I.gam[j] * kLog2eK)));
             if (I.vec8)  // padding columns (their K entries are set to 0 below)
                 for (int j = n + (int)threadIdx.x; j < 8 * n8; j += blockDim.x)
-                    pot[kswz(j, n8)] = make_float2(0.f, 0.f);
+                    pot[kswz(j, n8)] = make_int2(0, 0);
             __syncthreads();
             cur = un.inst;
         }
         const int row = un.row0 + wave;
         if (row >= n) continue;
         const int par = ctl->iter & 1;
-        const float pf = (float)ctl->p;
-        const float Ff = (float)I.F[par][row];
-        const float ph = I.phi[par][row] * kLog2eK;
+        const int p4 = 4 * ctl->p;
+        const int B = 4 * (I.F[par][row] - kTabLo);
+        const float eph = kex2(I.phi[par][row] * kLog2eK);
         const int16_t *wr = I.W + (int64_t)row * I.pitch;
+        auto entry = [&](int w, int2 gp) {
+            const float e = tab_at(tab, tab_off(p4, w, gp.x, B)) * __int_as_float(gp.y) * eph;
+            return w == SK_SENTINEL ? 0.f : fminf(e, kKHi);
+        };
         if (I.vec8) {
             // 8 columns per lane: one 16-byte load of W, one 16/32-byte store of
             // K (K's padding columns, j >= n, get 0 as in the 1-wide branch)
             const int n8 = pad8(n) >> 3;
-            for (int j0 = lane * 8; j0 < n; j0 += 512) {
-                const int4 v = gload<false>(reinterpret_cast<const int4 *>(wr + j0));
-                const int q[4] = {v.x, v.y, v.z, v.w};
-                float k[8];
+            constexpr int U = 2;
+            for (int j0 = lane * 8; j0 < n; j0 += U * 512) {
+                int4 v[U];
 #pragma unroll
-                for (int c = 0; c < 8; ++c) {
-                    const int w = (c & 1) ? (q[c >> 1] >> 16) : (int)(short)(q[c >> 1] & 0xffff);
-                    const float2 gp = pot[c * n8 + (j0 >> 3)];
-                    const float Iv = fmaf((float)w, pf, gp.x) + Ff;
-                    const float e = fminf(kex2(fmaf(Iv, kLog2eK, gp.y) + ph), kKHi);
-                    k[c] = (w == SK_SENTINEL || j0 + c >= n) ? 0.f : e;
-                }
-                if (ST == SK_K_BF16) {
-                    uint32_t o[4];
+                for (int k = 0; k < U; ++k)
+                    v[k] = j0 + k * 512 < n ? gload<NT>(reinterpret_cast<const int4 *>(wr + j0 + k * 512))
+                                            : make_int4(0, 0, 0, 0);
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) o[c] = bf16_rne(k[2 * c]) | (bf16_rne(k[2 * c + 1]) << 16);
-                    *reinterpret_cast<int4 *>(reinterpret_cast<uint16_t *>(I.K) + (int64_t)row * kp + j0) =
-                        make_int4((int)o[0], (int)o[1], (int)o[2], (int)o[3]);
-                } else {
-                    float4 *dst = reinterpret_cast<float4 *>(reinterpret_cast<float *>(I.K) + (int64_t)row * kp + j0);
-                    dst[0] = make_float4(k[0], k[1], k[2], k[3]);
-                    dst[1] = make_float4(k[4], k[5], k[6], k[7]);
+                for (int k = 0; k < U; ++k) {
+                    const int jj = j0 + k * 512;
+                    if (jj >= n) break;
+                    int w[8];
+                    unpack8i(v[k], w);
+                    float kv[8];
+#pragma unroll
+                    for (int c = 0; c < 8; ++c)
+                        kv[c] = jj + c < n ? entry(w[c], pot[c * n8 + (jj >> 3)]) : 0.f;
+                    if (ST == SK_K_BF16) {
+                        uint32_t o[4];
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) o[c] = bf16_rne(kv[2 * c]) | (bf16_rne(kv[2 * c + 1]) << 16);
+                        *reinterpret_cast<int4 *>(reinterpret_cast<uint16_t *>(I.K) + (int64_t)row * kp + jj) =
+                            make_int4((int)o[0], (int)o[1], (int)o[2], (int)o[3]);
+                    } else {
+                        float4 *dst = reinterpret_cast<float4 *>(reinterpret_cast<float *>(I.K) + (int64_t)row * kp + jj);
+                        dst[0] = make_float4(kv[0], kv[1], kv[2], kv[3]);
+                        dst[1] = make_float4(kv[4], kv[5], kv[6], kv[7]);
+                    }
                 }
             }
         } else {
             for (int j = lane; j < kp; j += kWave) {
-                float k = 0.f;
-                if (j < n) {
-                    const int w = wr[j];
-                    if (w != SK_SENTINEL) {
-                        const float2 gp = pot[j];
-                        const float Iv = fmaf((float)w, pf, gp.x) + Ff;
-                        k = fminf(kex2(fmaf(Iv, kLog2eK, gp.y) + ph), kKHi);
-                    }
-                }
+                const float k = j < n ? entry(wr[j], pot[j]) : 0.f;
                 if (ST == SK_K_BF16)
                     reinterpret_cast<uint16_t *>(I.K)[(int64_t)row * kp + j] = (uint16_t)bf16_rne(k);
                 else
@@ -325,12 +337,16 @@ __global__ __launch_bounds__(kColWaves * kWave) void k_col_sweep_k(const Inst *_
 
 // ---------------------------------------------------------------- fold, advance
 // log u_i += log a_i, log v_j += log b_j; a = b = 1 (one workgroup per instance).
+// Grids of (instances, kPotBlocks): the O(n) FP64 passes over the potentials
+// are spread over many workgroups.
+constexpr int kPotBlocks = 64;
+
 __global__ __launch_bounds__(256) void k_fold(const Inst *__restrict__ insts) {
     const Inst &I = insts[blockIdx.x];
     Ctl *ctl = I.ctl;
     if (ctl->state == ST_ERROR || ctl->state == ST_DONE) return;
     const int par = ctl->iter & 1;
-    for (int i = threadIdx.x; i < I.n; i += blockDim.x) {
+    for (int i = blockIdx.y * blockDim.x + threadIdx.x; i < I.n; i += gridDim.y * blockDim.x) {
         const double f = (double)I.F[par][i] + (double)I.phi[par][i] + log((double)I.a[par][i]);
         const double k = rint(f);
         I.F[0][i] = I.F[1][i] = (int32_t)k;
@@ -346,84 +362,149 @@ __global__ __launch_bounds__(256) void k_fold(const Inst *__restrict__ insts) {
 
 // Next p of the ladder (p^-1 log u, p^-1 log v held fixed), or done; after a
 // pause at the end of a stage (stored K, or a host that evaluates each stage).
-__global__ __launch_bounds__(256) void k_advance(const Inst *__restrict__ insts) {
+// (1) the potentials: p^-1 log u and p^-1 log v held fixed across the step
+// to the next p; (2) the control block (a kernel of its own, so that no
+// workgroup of (1) can see the state already moved on).
+__global__ __launch_bounds__(256) void k_advance_pot(const Inst *__restrict__ insts) {
     const Inst &I = insts[blockIdx.x];
     Ctl *ctl = I.ctl;
     if (ctl->state != ST_STAGE_END) return;
     const int n = I.n;
     const int s = ctl->stage;
     const int par = ctl->iter & 1;
+    if (s + 1 >= I.n_p) return;
+    const double ratio = (double)I.ladder[s + 1] / (double)I.ladder[s];
+    for (int i = blockIdx.y * blockDim.x + threadIdx.x; i < n; i += gridDim.y * blockDim.x) {
+        const double f = ((double)I.F[par][i] + (double)I.phi[par][i]) * ratio;
+        const double k = rint(f);
+        I.F[0][i] = (int32_t)k;
+        I.phi[0][i] = (float)(f - k);
+        const double g = ((double)I.G[i] + (double)I.gam[i]) * ratio;
+        const double kg = rint(g);
+        I.G[i] = (int32_t)kg;
+        I.gam[i] = (float)(g - kg);
+    }
+}
+__global__ void k_advance_state(const Inst *__restrict__ insts) {
+    const Inst &I = insts[blockIdx.x];
+    Ctl *ctl = I.ctl;
+    if (ctl->state != ST_STAGE_END) return;
+    const int s = ctl->stage;
     if (s + 1 < I.n_p) {
-        const double ratio = (double)I.ladder[s + 1] / (double)I.ladder[s];
-        for (int i = threadIdx.x; i < n; i += blockDim.x) {
-            const double f = ((double)I.F[par][i] + (double)I.phi[par][i]) * ratio;
-            const double k = rint(f);
-            I.F[0][i] = (int32_t)k;
-            I.phi[0][i] = (float)(f - k);
-            const double g = ((double)I.G[i] + (double)I.gam[i]) * ratio;
-            const double kg = rint(g);
-            I.G[i] = (int32_t)kg;
-            I.gam[i] = (float)(g - kg);
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            ctl->stage = s + 1;
-            ctl->p = I.ladder[s + 1];
-            ctl->iter = 0;
-            ctl->need_absorb = I.storage != SK_W_I16 ? 1u : 0u;
-            ctl->state = ST_RUNNING;
-        }
+        ctl->stage = s + 1;
+        ctl->p = I.ladder[s + 1];
+        ctl->iter = 0;
+        ctl->need_absorb = I.storage != SK_W_I16 ? 1u : 0u;
+        ctl->state = ST_RUNNING;
     } else {
-        if (threadIdx.x == 0) ctl->state = ST_DONE;
+        ctl->state = ST_DONE;
     }
 }
 
-// FP64 row and column sums of the matrix the K sweeps balance, K_ij a_i b_j.
-template <int ST>
+// FP64 row and column sums of the matrix the K sweeps balance, K_ij a_i b_j
+// (each product exact in FP64). Rows: one wave per row, 8-wide loads of K,
+// two in flight per lane, b staged in LDS as in the row sweep. Columns: a
+// workgroup per (512-column tile, row segment) whose four waves split the
+// segment's rows (eight columns per lane, the segment's a_i in LDS) and add
+// their partials in wave order into part[segment][column].
+template <int ST, bool NT>
 __global__ __launch_bounds__(kRowWaves * kWave) void k_check_k_rows(const Inst *__restrict__ insts,
                                                                     const RowUnit *__restrict__ units,
                                                                     int nunits, double *rsum) {
+    extern __shared__ float bsh[];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     int u0, u1;
     krange(nunits, u0, u1);
+    int cur = -1;
     for (int u = u0; u < u1; ++u) {
         const RowUnit un = units[u];
         const Inst &I = insts[un.inst];
-        const int n = I.n, row = un.row0 + wave, kp = I.kpitch;
+        const int n = I.n, kp = I.kpitch, n8 = kp >> 3;
+        if (un.inst != cur) {
+            __syncthreads();
+            for (int j = threadIdx.x; j < kp; j += blockDim.x) bsh[kswz(j, n8)] = j < n ? I.b[j] : 0.f;
+            __syncthreads();
+            cur = un.inst;
+        }
+        const int row = un.row0 + wave;
         if (row >= n) continue;
         const int par = I.ctl->iter & 1;
+        const int64_t rbase = (int64_t)row * kp;
         double s = 0.0;
-        for (int j = lane; j < n; j += kWave) {
-            const int64_t o = (int64_t)row * kp + j;
-            const float k = ST == SK_K_BF16
-                                ? __uint_as_float((uint32_t)reinterpret_cast<const uint16_t *>(I.K)[o] << 16)
-                                : reinterpret_cast<const float *>(I.K)[o];
-            s += (double)k * (double)I.b[j];
+        int j0 = lane * 8;
+        for (; j0 + 512 < kp; j0 += 2 * 512) {
+            float k0[8], k1[8];
+            load8<ST, NT>(I.K, rbase + j0, k0);
+            load8<ST, NT>(I.K, rbase + j0 + 512, k1);
+            const int q = j0 >> 3;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) s = fma((double)k0[c], (double)bsh[c * n8 + q], s);
+#pragma unroll
+            for (int c = 0; c < 8; ++c) s = fma((double)k1[c], (double)bsh[c * n8 + q + 64], s);
+        }
+        for (; j0 < kp; j0 += 512) {
+            float k0[8];
+            load8<ST, NT>(I.K, rbase + j0, k0);
+            const int q = j0 >> 3;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) s = fma((double)k0[c], (double)bsh[c * n8 + q], s);
         }
         s = kwave_sum_d(s);
         if (lane == 0) rsum[row] = s * (double)I.a[par][row];
     }
 }
 
-template <int ST>
-__global__ __launch_bounds__(256) void k_check_k_cols(const Inst *__restrict__ insts, int inst,
-                                                      double *part) {
+constexpr int kCheckKWaves = 4;       // waves per workgroup of the column pass
+constexpr int kCheckKTile = kWave * 8;  // columns per workgroup: 8 per lane
+
+template <int ST, bool NT>
+__global__ __launch_bounds__(kCheckKWaves * kWave) void k_check_k_cols(const Inst *__restrict__ insts,
+                                                                       int inst, double *part) {
+    __shared__ float ash[kMaxSegRows];
+    __shared__ double red[kCheckKWaves][kCheckKTile];
     const Inst &I = insts[inst];
     const int n = I.n, kp = I.kpitch;
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
     const int seg = blockIdx.y;
-    if (j >= n) return;
     const int r0 = seg * I.seg_rows, r1 = min(n, r0 + I.seg_rows);
     const int par = I.ctl->iter & 1;
-    double s = 0.0;
-    for (int r = r0; r < r1; ++r) {
-        const int64_t o = (int64_t)r * kp + j;
-        const float k = ST == SK_K_BF16
-                            ? __uint_as_float((uint32_t)reinterpret_cast<const uint16_t *>(I.K)[o] << 16)
-                            : reinterpret_cast<const float *>(I.K)[o];
-        s += (double)k * (double)I.a[par][r];
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    for (int r = r0 + (int)threadIdx.x; r < r1; r += blockDim.x) ash[r - r0] = I.a[par][r];
+    __syncthreads();
+    const int j0 = blockIdx.x * kCheckKTile + lane * 8;
+    double s[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) s[c] = 0.0;
+    if (j0 < kp) {
+        // wave w takes rows r0 + w, r0 + w + 4, ...; two rows in flight
+        int r = r0 + wave;
+        for (; r + kCheckKWaves < r1; r += 2 * kCheckKWaves) {
+            float k0[8], k1[8];
+            load8<ST, NT>(I.K, (int64_t)r * kp + j0, k0);
+            load8<ST, NT>(I.K, (int64_t)(r + kCheckKWaves) * kp + j0, k1);
+            const double a0 = (double)ash[r - r0], a1 = (double)ash[r + kCheckKWaves - r0];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) s[c] = fma((double)k1[c], a1, fma((double)k0[c], a0, s[c]));
+        }
+        if (r < r1) {
+            float k0[8];
+            load8<ST, NT>(I.K, (int64_t)r * kp + j0, k0);
+            const double a0 = (double)ash[r - r0];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) s[c] = fma((double)k0[c], a0, s[c]);
+        }
     }
-    part[(int64_t)seg * n + j] = s;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) red[wave][lane * 8 + c] = s[c];
+    __syncthreads();
+    // the waves' partials in wave order, two columns per thread
+    for (int q = threadIdx.x; q < kCheckKTile; q += blockDim.x) {
+        const int j = blockIdx.x * kCheckKTile + q;
+        if (j >= n) continue;
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < kCheckKWaves; ++w) t += red[w][q];
+        part[(int64_t)seg * n + j] = t;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_check_k_cols_sum(const Inst *__restrict__ insts, int inst,
@@ -438,15 +519,21 @@ __global__ __launch_bounds__(256) void k_check_k_cols_sum(const Inst *__restrict
 }
 
 // ---------------------------------------------------------------- launchers
-hipError_t launch_absorb(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
-                         size_t lds_bytes, int storage, hipStream_t st) {
-    if (storage == SK_K_BF16)
-        hipLaunchKernelGGL(k_absorb<SK_K_BF16>, dim3(grid), dim3(kRowWaves * kWave), lds_bytes, st,
-                           d_insts, d_units, nunits);
+template <int ST>
+static hipError_t launch_absorb_st(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
+                                   size_t lds_bytes, int nt, hipStream_t st) {
+    if (nt)
+        hipLaunchKernelGGL((k_absorb<ST, true>), dim3(grid), dim3(kRowWaves * kWave), lds_bytes, st, d_insts,
+                           d_units, nunits);
     else
-        hipLaunchKernelGGL(k_absorb<SK_K_F32>, dim3(grid), dim3(kRowWaves * kWave), lds_bytes, st,
+        hipLaunchKernelGGL((k_absorb<ST, false>), dim3(grid), dim3(kRowWaves * kWave), lds_bytes, st,
                            d_insts, d_units, nunits);
     return hipGetLastError();
+}
+hipError_t launch_absorb(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
+                         size_t lds_bytes, int storage, int nt, hipStream_t st) {
+    return storage == SK_K_BF16 ? launch_absorb_st<SK_K_BF16>(d_insts, d_units, nunits, grid, lds_bytes, nt, st)
+                                : launch_absorb_st<SK_K_F32>(d_insts, d_units, nunits, grid, lds_bytes, nt, st);
 }
 template <int ST, bool NT>
 static hipError_t launch_sweeps_k(bool rows, const Inst *d_insts, const void *d_units, int nunits,
@@ -477,29 +564,36 @@ hipError_t launch_col_sweep_k(const Inst *d_insts, const ColUnit *d_units, int n
     return launch_sweep_k(false, d_insts, d_units, nunits, grid, 0, storage, nt_loads, st);
 }
 hipError_t launch_fold_k(const Inst *d_insts, int count, hipStream_t st) {
-    hipLaunchKernelGGL(k_fold, dim3(count), dim3(256), 0, st, d_insts);
+    hipLaunchKernelGGL(k_fold, dim3(count, kPotBlocks), dim3(256), 0, st, d_insts);
     return hipGetLastError();
 }
 hipError_t launch_advance(const Inst *d_insts, int count, hipStream_t st) {
-    hipLaunchKernelGGL(k_advance, dim3(count), dim3(256), 0, st, d_insts);
+    hipLaunchKernelGGL(k_advance_pot, dim3(count, kPotBlocks), dim3(256), 0, st, d_insts);
+    hipLaunchKernelGGL(k_advance_state, dim3(count), dim3(1), 0, st, d_insts);
     return hipGetLastError();
 }
 static hipError_t launch_absorb_done(const Inst *d_insts, int count, hipStream_t st) {
     hipLaunchKernelGGL(k_absorb_done, dim3(count), dim3(256), 0, st, d_insts);
     return hipGetLastError();
 }
+template <int ST, bool NT>
+static void launch_check_k_st(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid, int inst,
+                              int n, int nseg, double *rsum, double *part, hipStream_t st) {
+    const size_t lds = sizeof(float) * (size_t)pad8(n);
+    hipLaunchKernelGGL((k_check_k_rows<ST, NT>), dim3(grid), dim3(kRowWaves * kWave), lds, st, d_insts,
+                       d_units, nunits, rsum);
+    hipLaunchKernelGGL((k_check_k_cols<ST, NT>), dim3((pad8(n) + kCheckKTile - 1) / kCheckKTile, nseg),
+                       dim3(kCheckKWaves * kWave), 0, st, d_insts, inst, part);
+}
 hipError_t launch_check_k(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid, int inst,
-                          int n, int nseg, int storage, double *rsum, double *part, double *csum,
+                          int n, int nseg, int storage, int nt, double *rsum, double *part, double *csum,
                           hipStream_t st) {
-    const dim3 cg((n + 255) / 256, nseg);
     if (storage == SK_K_BF16) {
-        hipLaunchKernelGGL(k_check_k_rows<SK_K_BF16>, dim3(grid), dim3(kRowWaves * kWave), 0, st,
-                           d_insts, d_units, nunits, rsum);
-        hipLaunchKernelGGL(k_check_k_cols<SK_K_BF16>, cg, dim3(256), 0, st, d_insts, inst, part);
+        if (nt) launch_check_k_st<SK_K_BF16, true>(d_insts, d_units, nunits, grid, inst, n, nseg, rsum, part, st);
+        else launch_check_k_st<SK_K_BF16, false>(d_insts, d_units, nunits, grid, inst, n, nseg, rsum, part, st);
     } else {
-        hipLaunchKernelGGL(k_check_k_rows<SK_K_F32>, dim3(grid), dim3(kRowWaves * kWave), 0, st,
-                           d_insts, d_units, nunits, rsum);
-        hipLaunchKernelGGL(k_check_k_cols<SK_K_F32>, cg, dim3(256), 0, st, d_insts, inst, part);
+        if (nt) launch_check_k_st<SK_K_F32, true>(d_insts, d_units, nunits, grid, inst, n, nseg, rsum, part, st);
+        else launch_check_k_st<SK_K_F32, false>(d_insts, d_units, nunits, grid, inst, n, nseg, rsum, part, st);
     }
     hipLaunchKernelGGL(k_check_k_cols_sum, dim3((n + 255) / 256), dim3(256), 0, st, d_insts, inst,
                        part, csum);
@@ -517,7 +611,7 @@ hipError_t launch_check_k(const Inst *d_insts, const RowUnit *d_units, int nunit
 static sk_status absorb(sk_ctx *ctx, Batch &B, int storage) {
     ctx->prof.begin(ctx->stream, KID_ABSORB);
     KCHK(launch_absorb(B.d_insts, B.d_rows, (int)B.h_rows.size(), B.row_grid, B.row_lds, storage,
-                       ctx->stream));
+                       B.h_insts[0].nt, ctx->stream));
     KCHK(launch_absorb_done(B.d_insts, B.count, ctx->stream));
     ctx->prof.end(ctx->stream);
     ctx->absorbs += 1;
@@ -560,7 +654,7 @@ sk_status run_single_k(sk_ctx *ctx, Batch &B, const sk_params *prm, const StageH
                 const int n = I.n;
                 ctx->prof.begin(ctx->stream, KID_CHECK_ROWS);
                 KCHK(launch_check_k(B.d_insts, B.d_rows, (int)B.h_rows.size(), B.row_grid, 0, n,
-                                    I.nseg, storage, B.d_rsum, B.d_cpart, B.d_csum, ctx->stream));
+                                    I.nseg, storage, I.nt, B.d_rsum, B.d_cpart, B.d_csum, ctx->stream));
                 ctx->prof.end(ctx->stream);
                 std::vector<double> r(n), cs(n);
                 KCHK(hipMemcpyAsync(r.data(), B.d_rsum, 8 * (size_t)n, hipMemcpyDeviceToHost,
@@ -660,12 +754,15 @@ sk_status run_single_k(sk_ctx *ctx, Batch &B, const sk_params *prm, const StageH
 hipError_t set_k_attributes() {
     hipError_t e;
     const int lds = (int)(kMaxN * sizeof(float2));
-    if ((e = hipFuncSetAttribute((const void *)k_absorb<SK_K_BF16>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds)) != hipSuccess)
-        return e;
-    if ((e = hipFuncSetAttribute((const void *)k_absorb<SK_K_F32>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds)) != hipSuccess)
-        return e;
+    for (const void *f : {(const void *)k_absorb<SK_K_BF16, true>, (const void *)k_absorb<SK_K_BF16, false>,
+                          (const void *)k_absorb<SK_K_F32, true>, (const void *)k_absorb<SK_K_F32, false>})
+        if ((e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds)) != hipSuccess)
+            return e;
+    for (const void *f : {(const void *)k_check_k_rows<SK_K_BF16, true>, (const void *)k_check_k_rows<SK_K_BF16, false>,
+                          (const void *)k_check_k_rows<SK_K_F32, true>, (const void *)k_check_k_rows<SK_K_F32, false>})
+        if ((e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)(kMaxN * sizeof(float)))) != hipSuccess)
+            return e;
     for (const void *f : {(const void *)k_row_sweep_k<SK_K_BF16, true>,
                           (const void *)k_row_sweep_k<SK_K_BF16, false>,
                           (const void *)k_row_sweep_k<SK_K_F32, true>,
