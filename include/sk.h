@@ -173,7 +173,8 @@ typedef struct {
 /* Device memory a context needs to scale one instance of size n with the
  * given storage (the arena passed to sk_create must be at least this). When
  * n is not a multiple of 8 this includes the library's copy of W at a row
- * pitch of n rounded up to 8 (so that every size takes 16-byte loads). */
+ * pitch of n rounded up to 8 (so that every size takes 16-byte loads).
+ * 0 for n outside [1, 65536]. */
 size_t sk_arena_bytes(int32_t n, int32_t storage);
 
 /* Creates a context on `device`, launching on `hip_stream` (a hipStream_t;
@@ -194,6 +195,11 @@ const char *sk_last_error(const sk_ctx *ctx);
 /* Scales A^(p) for each p of the ladder (Section 3.1 with the logarithmic
  * form of Section 4.1.2), then rechecks the result in FP64 and computes the
  * certificate of Proposition prop:aoc.
+ *   n          : 1 <= n <= 65536. Above 16384 only the two-sweep Sinkhorn
+ *                iteration on int16 W (storage SK_W_I16, fused = 0, method
+ *                SK_SINKHORN), else SK_EINVAL; the same holds for sk_solve,
+ *                sk_prune and sk_scale_static. Batches, served requests and
+ *                real-valued weights take n <= 16384.
  *   W          : device, n*n int16 (read only).
  *   potentials : device, sk_potentials_bytes(n); output, and input when
  *                params->warm_start = 1.
@@ -263,9 +269,9 @@ sk_status sk_solve(sk_ctx *ctx, const int16_t *W, int32_t n, const sk_params *pa
  * arena (arena_dev_ptr NULL).
  *   Limit: instances whose working memory (sk_arena_bytes(n, storage))
  *   exceeds SK_STATIC_SCRATCH_BYTES are rejected with SK_ENOMEM before any
- *   work is queued: int16 W up to n = 16384 when n is a multiple of 8 (else
- *   the library's padded copy of W must fit too: n <= 5423), stored BF16 K
- *   up to n = 5416, stored FP32 K up to n = 3920 (n a multiple of 8).
+ *   work is queued: int16 W up to n = 44016 when n is a multiple of 8 (else
+ *   the library's padded copy of W must fit too: n <= 5343), stored BF16 K
+ *   up to n = 5336, stored FP32 K up to n = 3888 (n a multiple of 8).
  *   Every call on a GPU shares that GPU's array and leaves its contents
  *   behind (each call initialises what it reads): calls that overlap on one
  *   GPU, from any contexts or threads, race and must be serialised by the
@@ -358,7 +364,8 @@ sk_status sk_scale_batch(sk_ctx *ctx, int32_t count, const int16_t *const *W,
                          sk_report *reports);
 
 /* Device arena bytes sk_scale_batch needs for these sizes (with the padded
- * copy of each W whose n is not a multiple of 8, as for sk_arena_bytes). */
+ * copy of each W whose n is not a multiple of 8, as for sk_arena_bytes).
+ * 0 when a size is outside [1, 16384] (or [1, 65536] for count = 1). */
 size_t sk_batch_arena_bytes(int32_t count, const int32_t *n, int32_t storage);
 
 /* Tile-shape table (process-wide). The column sweep splits the rows of an

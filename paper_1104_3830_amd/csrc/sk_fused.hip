@@ -23,10 +23,11 @@ namespace sk {
 
 constexpr int kFT = 1024;    // threads per workgroup
 constexpr int kFR = 2;       // rows per group
-// rows per workgroup at most: ceil(n / grid) with n <= kMaxN and a grid of
+// rows per workgroup at most: ceil(n / grid) with n <= kLdsMaxN (the single
+// pass takes no larger instance) and a grid of
 // min(kFusedSlots, max(1, n / 2)) workgroups (64 at n = 16384, at most 3 for
 // n below 2 kFusedSlots)
-constexpr int kFusedRows = (kMaxN + kFusedSlots - 1) / kFusedSlots;
+constexpr int kFusedRows = (kLdsMaxN + kFusedSlots - 1) / kFusedSlots;
 constexpr float kL2e = 1.4426950408889634f;
 constexpr float kLn2f = 0.6931471805599453f;
 constexpr float kLo = 5.421010862427522e-20f;  // 2^-64

@@ -14,7 +14,12 @@ constexpr int kRowWaves = 16;    // waves per workgroup in the row sweep (one ro
 constexpr int kColWaves = 4;     // waves per workgroup in the column sweep
 constexpr int kColTile8 = 512;   // columns per column tile, 8-wide vector loads
 constexpr int kColTile1 = 64;    // columns per column tile, scalar loads
-constexpr int kMaxN = 16384;     // row sweep stages all column potentials in LDS
+// Up to kLdsMaxN the kernels that need every column's data stage it in LDS
+// (8 bytes per column); above it (int16 W, two sweeps, one instance, up to
+// kMaxN) they read it from a packed per-instance buffer in global memory,
+// which stays in the L2 cache (512 KiB at kMaxN).
+constexpr int kLdsMaxN = 16384;
+constexpr int kMaxN = 65536;
 constexpr int kMaxSegRows = 1024;
 constexpr int kShortRowN = 2048;  // batches up to this n take the short-row row sweep
 constexpr int kFusedSlots = 256;  // workgroups (and column-partial slots) of the fused kernel
@@ -119,6 +124,11 @@ struct Inst {
     // p of the current stage is ctl->p * pscale: 1 for int16 W; with the
     // prescaling of Section 4.1.1, 1 / (w_max - w_min) when that exceeds 1
     double pscale;
+    // n > kLdsMaxN: pad8(n) 8-byte column entries in the layout the LDS
+    // staging would use, rewritten before each kernel that reads them (row
+    // sweep: (4 G_j, exp(gam_j)); FP64 check and CSR passes: (G_j, gam_j));
+    // nullptr otherwise
+    void *colpack;
 };
 constexpr int kRowResSlots = 64;    // = kWave: one wave reduces them
 constexpr int kRowResStride = 32;   // one 128-byte line per slot
@@ -214,9 +224,14 @@ hipError_t launch_pad_copy(const Inst *d_insts, const RowUnit *d_units, int nuni
 // sweep compiled for two workgroups per CU, sk_rowshort.hip)
 // bounds (device, grid + 1 entries, or nullptr for an even split by count):
 // workgroup b sweeps the units [bounds[b], bounds[b + 1]).
+// gcol: one instance with n > kLdsMaxN (column entries from I.colpack,
+// packed by launch_col_pack mode 0 before the launch)
 hipError_t launch_row_sweep(const Inst *d_insts, const RowUnit *d_units, int nunits,
                             const int32_t *bounds, int grid, size_t lds_bytes, int nt_loads,
-                            int short_rows, hipStream_t st, hipEvent_t stop = nullptr);
+                            int short_rows, int gcol, hipStream_t st, hipEvent_t stop = nullptr);
+// Packs instance inst's column entries into its colpack buffer (n > kLdsMaxN):
+// mode 0 for the row sweep, 1 for the FP64 check and the CSR passes.
+hipError_t launch_col_pack(const Inst *d_insts, int inst, int n, int mode, hipStream_t st);
 hipError_t launch_row_sweep_short(const Inst *d_insts, const RowUnit *d_units, int nunits,
                                   const int32_t *bounds, int grid, size_t lds_bytes, int nt_loads,
                                   hipStream_t st, hipEvent_t stop = nullptr);
@@ -237,20 +252,20 @@ hipError_t launch_col_finalize(const Inst *d_insts, const FinUnit *d_units, int 
                                int mode, hipStream_t st);
 hipError_t launch_check_rows(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
                              double *rsum, double *rmax, double logt, int64_t *counts,
-                             int32_t *hint, size_t lds_bytes, int nt_loads, hipStream_t st);
+                             int32_t *hint, size_t lds_bytes, int nt_loads, int gcol, hipStream_t st);
 hipError_t launch_check_cols(const Inst *d_insts, int inst, int n, int nseg, int vec8,
                              double *part, double *csum, int nt_loads, hipStream_t st);
 hipError_t launch_prune_count(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
-                              double logt, int64_t *counts, size_t lds_bytes, hipStream_t st);
+                              double logt, int64_t *counts, size_t lds_bytes, int gcol, hipStream_t st);
 hipError_t launch_scan(const int64_t *counts, int64_t *row_ptr, int n, hipStream_t st,
                        int64_t *total_out = nullptr);
 hipError_t launch_check_reduce(const Inst *d_insts, int inst, const double *rsum,
                                const double *rmax, const double *csum, double *out, hipStream_t st);
 hipError_t launch_prune_fill(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
                              double logt, const int64_t *row_ptr, int32_t *col, int16_t *w,
-                             size_t lds_bytes, int nt_loads, hipStream_t st);
+                             size_t lds_bytes, int nt_loads, int gcol, hipStream_t st);
 hipError_t launch_absorb(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
-                         size_t lds_bytes, int storage, hipStream_t st);
+                         size_t lds_bytes, int storage, int nt, hipStream_t st);
 hipError_t launch_row_sweep_k(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
                               size_t lds_bytes, int storage, int nt_loads,
                               hipStream_t st);

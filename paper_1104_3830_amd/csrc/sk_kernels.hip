@@ -568,10 +568,10 @@ __global__ __launch_bounds__(kIterEndThreads) void k_iter_end(const Inst *__rest
 // ---------------------------------------------------------------- FP64 recheck
 // Row sums r_i and m_i = max_j (p w_ij + log v_j) in FP64 from the committed
 // potentials (Proposition prop:aoc needs sum_i m_i - sum_j log v_j).
-// Entries with log x_ij below this contribute less than e^-46 each, i.e. at
-// most n e^-46 < 2^-52 to a row or column sum of 1 for n <= 16384 (below one
+// Entries with log x_ij below this contribute less than e^-48 each, i.e. at
+// most n e^-48 < 2^-52 to a row or column sum of 1 for n <= 65536 (below one
 // FP64 ulp of the sum); their exp is not evaluated.
-constexpr double kNegligibleLog = -46.0;
+constexpr double kNegligibleLog = -48.0;
 
 // An entry whose exact integer exponent E = p w_ij + F_i + G_j is below
 // kCheckSkip has log x_ij < kNegligibleLog: |phi_i|, |gam_j| <= 1/2.
@@ -593,11 +593,34 @@ __device__ __forceinline__ void stage_gq(const Inst &I, int2 *gq) {
     if (I.vec8)
         for (int j = n + (int)threadIdx.x; j < 8 * n8; j += blockDim.x) gq[swz8(j, n8)] = make_int2(kPadG, 0);
 }
-__device__ __forceinline__ int2 gq_at(const Inst &I, const int2 *gq, int j) {
-    return gq[I.vec8 ? swz8(j, pad8(I.n) >> 3) : j];
+// Entry i of the (G_j, gam_j) column data, through either pointer type.
+template <class GQ>
+__device__ __forceinline__ int2 gq_ld(GQ gq, int i) {
+    return make_int2(gq[i].x, gq[i].y);
+}
+template <class GQ>
+__device__ __forceinline__ int2 gq_at(const Inst &I, GQ gq, int j) {
+    return gq_ld(gq, I.vec8 ? swz8(j, pad8(I.n) >> 3) : j);
 }
 __device__ __forceinline__ double logv_of(int2 q) {
     return (double)q.x + (double)__int_as_float(q.y);
+}
+
+// n > kLdsMaxN: the column entries the LDS staging would hold, written to
+// I.colpack in the same layout (mode 0: the row sweep's (4 G_j, exp(gam_j));
+// mode 1: the FP64 check's and CSR passes' (G_j, bits of gam_j)).
+__global__ __launch_bounds__(256) void k_col_pack(const Inst *__restrict__ insts, int inst, int mode) {
+    const Inst &I = insts[inst];
+    const int n = I.n, n8 = pad8(n) >> 3;
+    const int ncols = I.vec8 ? 8 * n8 : n;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= ncols) return;
+    int2 v;
+    if (mode == 0)
+        v = j < n ? make_int2(4 * I.G[j], __float_as_int(ex2(I.gam[j] * kLog2e))) : make_int2(kPadExp4, 0);
+    else
+        v = j < n ? make_int2(I.G[j], __float_as_int(I.gam[j])) : make_int2(kPadG, 0);
+    reinterpret_cast<int2 *>(I.colpack)[I.vec8 ? swz8(j, n8) : j] = v;
 }
 
 // With counts != nullptr it also counts the entries with log x_ij >= logt
@@ -611,8 +634,8 @@ __device__ __forceinline__ double logv_of(int2 q) {
 // 64 at a time, one per lane, instead of one lane at a time in every chunk.
 // The queue order is fixed (chunk, then round, then lane), so the sums are
 // the same on every run.
-template <bool SENT, bool NT>
-__device__ __forceinline__ void check_row_v8(const Inst &I, const int2 *gq, int2 *qe, int row, int lane,
+template <bool SENT, bool NT, class GQ>
+__device__ __forceinline__ void check_row_v8(const Inst &I, GQ gq, int2 *qe, int row, int lane,
                                              int eskip, double logt, double *rsum, double *rmax,
                                              int64_t *counts, int32_t *hint) {
     const int n = I.n, n8 = pad8(n) >> 3;
@@ -626,7 +649,7 @@ __device__ __forceinline__ void check_row_v8(const Inst &I, const int2 *gq, int2
     int Emax = INT_MIN;  // this lane's largest exact exponent E = p w + F_i + G_j
     // one entry in FP64 (t = p w_ij + log v_j, log x_ij = t + log u_i)
     auto exact = [&](int j, int w) {
-        const int2 q = gq[(j & 7) * n8 + (j >> 3)];
+        const int2 q = gq_ld(gq, (j & 7) * n8 + (j >> 3));
         const double pw = p * (double)w, lvj = logv_of(q);
         const double t = pw + lvj;
         const double lx = t + f;
@@ -702,7 +725,7 @@ __device__ __forceinline__ void check_row_v8(const Inst &I, const int2 *gq, int2
     if (Es != INT_MIN && Es - 1 < eskip) {
         visit_row(I, wr, lane, [&](int j, int w) {
             if (w == SK_SENTINEL) return;
-            const int2 q = gq[(j & 7) * n8 + (j >> 3)];
+            const int2 q = gq_ld(gq, (j & 7) * n8 + (j >> 3));
             const int E = pi * w + q.x + Fi;
             if (E < Es - 1 || E >= eskip) return;
             const double t = p * (double)w + logv_of(q);
@@ -733,14 +756,21 @@ __device__ __forceinline__ void check_row_v8(const Inst &I, const int2 *gq, int2
     }
 }
 
-template <bool NT>
+// GCOL: one instance with n > kLdsMaxN, its column entries read from
+// I.colpack (packed by k_col_pack, mode 1) instead of staged in LDS.
+template <bool NT, bool GCOL>
 __global__ __launch_bounds__(kRowWaves * kWave) void k_check_rows(const Inst *__restrict__ insts,
                                                                     const RowUnit *__restrict__ units,
                                                                     int nunits, double *rsum,
                                                                     double *rmax, double logt,
                                                                     int64_t *counts, int32_t *hint) {
-    extern __shared__ int2 gq[];
+    extern __shared__ int2 gq_lds[];
     __shared__ int2 queue[kRowWaves][kWave];
+    // GCOL launches hold one instance: its packed entries, read as global
+    using GQ = std::conditional_t<GCOL, const SK_GLOBAL int2 *, const int2 *>;
+    GQ gq;
+    if constexpr (GCOL) gq = (GQ)insts[0].colpack;
+    else gq = gq_lds;
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     int u0, u1;
     unit_range(nunits, u0, u1);
@@ -750,9 +780,11 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_check_rows(const Inst *__
         const RowUnit un = units[u];
         const Inst &I = insts[un.inst];
         if (un.inst != cur) {
-            __syncthreads();
-            stage_gq(I, gq);
-            __syncthreads();
+            if (!GCOL) {
+                __syncthreads();
+                stage_gq(I, gq_lds);
+                __syncthreads();
+            }
             cur = un.inst;
         }
         const int n = I.n, row = un.row0 + wave;
@@ -986,11 +1018,17 @@ __global__ __launch_bounds__(256) void k_check_reduce(const Inst *__restrict__ i
 // ---------------------------------------------------------------- prune
 // B keeps (i, j) iff x_ij(p) >= t (eq. matrixred); the comparison is made on
 // log x_ij = p w_ij + log u_i + log v_j in FP64.
+template <bool GCOL>
 __global__ __launch_bounds__(kRowWaves * kWave) void k_prune_count(const Inst *__restrict__ insts,
                                                                      const RowUnit *__restrict__ units,
                                                                      int nunits, double logt,
                                                                      int64_t *counts) {
-    extern __shared__ int2 gq[];
+    extern __shared__ int2 gq_lds[];
+    // GCOL launches hold one instance: its packed entries, read as global
+    using GQ = std::conditional_t<GCOL, const SK_GLOBAL int2 *, const int2 *>;
+    GQ gq;
+    if constexpr (GCOL) gq = (GQ)insts[0].colpack;
+    else gq = gq_lds;
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     int u0, u1;
     unit_range(nunits, u0, u1);
@@ -1000,9 +1038,11 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_prune_count(const Inst *_
         const RowUnit un = units[u];
         const Inst &I = insts[un.inst];
         if (un.inst != cur) {
-            __syncthreads();
-            stage_gq(I, gq);
-            __syncthreads();
+            if (!GCOL) {
+                __syncthreads();
+                stage_gq(I, gq_lds);
+                __syncthreads();
+            }
             cur = un.inst;
         }
         const int n = I.n, row = un.row0 + wave;
@@ -1030,20 +1070,22 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_prune_count(const Inst *_
 __global__ __launch_bounds__(1024) void k_scan(const int64_t *__restrict__ counts,
                                                int64_t *__restrict__ row_ptr, int n,
                                                int64_t *total_out) {
-    // thread t sums a contiguous block; the block sums are scanned with
-    // shuffles within each wave and across the 16 wave totals
-    // n <= kMaxN: at most kScanPer counts per thread, all loaded at once
-    constexpr int kScanPer = kMaxN / 1024;
+    // thread t sums a contiguous block (read kScanPer at a time, their loads
+    // in flight together: one round for n <= 16384); the block sums are
+    // scanned with shuffles within each wave and across the 16 wave totals
+    constexpr int kScanPer = 16;
     __shared__ int64_t wsum[1024 / kWave];
     const int t = threadIdx.x, wave = t / kWave, lane = t % kWave;
     const int per = (n + 1023) / 1024;
     const int a = min(n, t * per), b = min(n, a + per);
-    int64_t c[kScanPer];
-#pragma unroll
-    for (int k = 0; k < kScanPer; ++k) c[k] = a + k < b ? counts[a + k] : 0;
     int64_t s = 0;
+    for (int i0 = a; i0 < b; i0 += kScanPer) {
+        int64_t c[kScanPer];
 #pragma unroll
-    for (int k = 0; k < kScanPer; ++k) s += c[k];
+        for (int k = 0; k < kScanPer; ++k) c[k] = i0 + k < b ? counts[i0 + k] : 0;
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) s += c[k];
+    }
     int64_t x = s;  // inclusive scan within the wave
 #pragma unroll
     for (int o = 1; o < kWave; o <<= 1) {
@@ -1068,24 +1110,34 @@ __global__ __launch_bounds__(1024) void k_scan(const int64_t *__restrict__ count
         row_ptr[n] = total;
         if (total_out) *total_out = total;
     }
+    for (int i0 = a; i0 < b; i0 += kScanPer) {
+        int64_t c[kScanPer];
 #pragma unroll
-    for (int k = 0; k < kScanPer; ++k)
-        if (a + k < b) {
-            row_ptr[a + k] = run;
-            run += c[k];
-        }
+        for (int k = 0; k < kScanPer; ++k) c[k] = i0 + k < b ? counts[i0 + k] : 0;
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k)
+            if (i0 + k < b) {
+                row_ptr[i0 + k] = run;
+                run += c[k];
+            }
+    }
 }
 
 // Writes the kept columns of each row in increasing order: each wave walks
 // its row in 64-column chunks and places the kept ones with a ballot prefix.
-template <bool NT>
+template <bool NT, bool GCOL>
 __global__ __launch_bounds__(kRowWaves * kWave) void k_prune_fill(const Inst *__restrict__ insts,
                                                                     const RowUnit *__restrict__ units,
                                                                     int nunits, double logt,
                                                                     const int64_t *__restrict__ row_ptr,
                                                                     int32_t *__restrict__ col,
                                                                     int16_t *__restrict__ wout) {
-    extern __shared__ int2 gq[];
+    extern __shared__ int2 gq_lds[];
+    // GCOL launches hold one instance: its packed entries, read as global
+    using GQ = std::conditional_t<GCOL, const SK_GLOBAL int2 *, const int2 *>;
+    GQ gq;
+    if constexpr (GCOL) gq = (GQ)insts[0].colpack;
+    else gq = gq_lds;
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     int u0, u1;
     unit_range(nunits, u0, u1);
@@ -1095,9 +1147,11 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_prune_fill(const Inst *__
         const RowUnit un = units[u];
         const Inst &I = insts[un.inst];
         if (un.inst != cur) {
-            __syncthreads();
-            stage_gq(I, gq);
-            __syncthreads();
+            if (!GCOL) {
+                __syncthreads();
+                stage_gq(I, gq_lds);
+                __syncthreads();
+            }
             cur = un.inst;
         }
         const int n = I.n, row = un.row0 + wave;
@@ -1153,7 +1207,7 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_prune_fill(const Inst *__
 #pragma unroll
                             for (int c = 0; c < 8; ++c)
                                 if (cand & (1u << c)) {
-                                    const double lx = p * (double)wv[c] + f + logv_of(gq[c * n8 + base]);
+                                    const double lx = p * (double)wv[c] + f + logv_of(gq_ld(gq, c * n8 + base));
                                     if (lx >= logt) keep |= 1u << c;
                                 }
                         }
@@ -1653,15 +1707,18 @@ hipError_t launch_pad_copy(const Inst *d_insts, const RowUnit *d_units, int nuni
 }
 hipError_t launch_row_sweep(const Inst *d_insts, const RowUnit *d_units, int nunits,
                             const int32_t *bounds, int grid, size_t lds_bytes, int nt_loads,
-                            int short_rows, hipStream_t st, hipEvent_t stop) {
+                            int short_rows, int gcol, hipStream_t st, hipEvent_t stop) {
     if (short_rows)
         return launch_row_sweep_short(d_insts, d_units, nunits, bounds, grid, lds_bytes, nt_loads, st,
                                       stop);
-    if (nt_loads)
-        launch_stamped(k_row_sweep<true, 1>, dim3(grid), dim3(kRowWaves * kWave), lds_bytes, st, stop,
+    if (gcol)
+        launch_stamped(k_row_sweep<true, 1, true>, dim3(grid), dim3(kRowWaves * kWave), 0, st, stop, d_insts,
+                       d_units, nunits, bounds);
+    else if (nt_loads)
+        launch_stamped(k_row_sweep<true, 1, false>, dim3(grid), dim3(kRowWaves * kWave), lds_bytes, st, stop,
                        d_insts, d_units, nunits, bounds);
     else
-        launch_stamped(k_row_sweep<false, 1>, dim3(grid), dim3(kRowWaves * kWave), lds_bytes, st, stop,
+        launch_stamped(k_row_sweep<false, 1, false>, dim3(grid), dim3(kRowWaves * kWave), lds_bytes, st, stop,
                        d_insts, d_units, nunits, bounds);
     return hipGetLastError();
 }
@@ -1716,13 +1773,21 @@ hipError_t launch_iter_end(const Inst *d_insts, int count, hipStream_t st, hipEv
 }
 hipError_t launch_check_rows(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
                              double *rsum, double *rmax, double logt, int64_t *counts,
-                             int32_t *hint, size_t lds_bytes, int nt_loads, hipStream_t st) {
-    if (nt_loads)
-        hipLaunchKernelGGL(k_check_rows<true>, dim3(grid), dim3(kRowWaves * kWave), lds_bytes, st, d_insts,
-                           d_units, nunits, rsum, rmax, logt, counts, hint);
+                             int32_t *hint, size_t lds_bytes, int nt_loads, int gcol, hipStream_t st) {
+    const dim3 g(grid), b(kRowWaves * kWave);
+    if (gcol)
+        hipLaunchKernelGGL((k_check_rows<true, true>), g, b, 0, st, d_insts, d_units, nunits, rsum, rmax, logt,
+                           counts, hint);
+    else if (nt_loads)
+        hipLaunchKernelGGL((k_check_rows<true, false>), g, b, lds_bytes, st, d_insts, d_units, nunits, rsum,
+                           rmax, logt, counts, hint);
     else
-        hipLaunchKernelGGL(k_check_rows<false>, dim3(grid), dim3(kRowWaves * kWave), lds_bytes, st, d_insts,
-                           d_units, nunits, rsum, rmax, logt, counts, hint);
+        hipLaunchKernelGGL((k_check_rows<false, false>), g, b, lds_bytes, st, d_insts, d_units, nunits, rsum,
+                           rmax, logt, counts, hint);
+    return hipGetLastError();
+}
+hipError_t launch_col_pack(const Inst *d_insts, int inst, int n, int mode, hipStream_t st) {
+    hipLaunchKernelGGL(k_col_pack, dim3((pad8(n) + 255) / 256), dim3(256), 0, st, d_insts, inst, mode);
     return hipGetLastError();
 }
 hipError_t launch_check_reduce(const Inst *d_insts, int inst, const double *rsum,
@@ -1746,9 +1811,13 @@ hipError_t launch_check_cols(const Inst *d_insts, int inst, int n, int nseg, int
     return hipGetLastError();
 }
 hipError_t launch_prune_count(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
-                              double logt, int64_t *counts, size_t lds_bytes, hipStream_t st) {
-    hipLaunchKernelGGL(k_prune_count, dim3(grid), dim3(kRowWaves * kWave), lds_bytes, st, d_insts, d_units,
-                       nunits, logt, counts);
+                              double logt, int64_t *counts, size_t lds_bytes, int gcol, hipStream_t st) {
+    if (gcol)
+        hipLaunchKernelGGL(k_prune_count<true>, dim3(grid), dim3(kRowWaves * kWave), 0, st, d_insts, d_units,
+                           nunits, logt, counts);
+    else
+        hipLaunchKernelGGL(k_prune_count<false>, dim3(grid), dim3(kRowWaves * kWave), lds_bytes, st, d_insts,
+                           d_units, nunits, logt, counts);
     return hipGetLastError();
 }
 hipError_t launch_scan(const int64_t *counts, int64_t *row_ptr, int n, hipStream_t st,
@@ -1759,26 +1828,30 @@ hipError_t launch_scan(const int64_t *counts, int64_t *row_ptr, int n, hipStream
 }
 hipError_t launch_prune_fill(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
                              double logt, const int64_t *row_ptr, int32_t *col, int16_t *w,
-                             size_t lds_bytes, int nt_loads, hipStream_t st) {
-    if (nt_loads)
-        hipLaunchKernelGGL(k_prune_fill<true>, dim3(grid), dim3(kRowWaves * kWave), lds_bytes, st, d_insts,
-                           d_units, nunits, logt, row_ptr, col, w);
+                             size_t lds_bytes, int nt_loads, int gcol, hipStream_t st) {
+    const dim3 g(grid), b(kRowWaves * kWave);
+    if (gcol)
+        hipLaunchKernelGGL((k_prune_fill<true, true>), g, b, 0, st, d_insts, d_units, nunits, logt, row_ptr,
+                           col, w);
+    else if (nt_loads)
+        hipLaunchKernelGGL((k_prune_fill<true, false>), g, b, lds_bytes, st, d_insts, d_units, nunits, logt,
+                           row_ptr, col, w);
     else
-        hipLaunchKernelGGL(k_prune_fill<false>, dim3(grid), dim3(kRowWaves * kWave), lds_bytes, st, d_insts,
-                           d_units, nunits, logt, row_ptr, col, w);
+        hipLaunchKernelGGL((k_prune_fill<false, false>), g, b, lds_bytes, st, d_insts, d_units, nunits, logt,
+                           row_ptr, col, w);
     return hipGetLastError();
 }
 hipError_t set_kernel_attributes() {
-    const int lds = (int)(kMaxN * sizeof(double));
+    const int lds = (int)(kLdsMaxN * sizeof(double));
     hipError_t e;
     if ((e = set_row_sweep_short_attributes()) != hipSuccess) return e;
-    for (const void *f : {(const void *)k_row_sweep<true, 1>, (const void *)k_row_sweep<false, 1>,
+    for (const void *f : {(const void *)k_row_sweep<true, 1, false>, (const void *)k_row_sweep<false, 1, false>,
                           (const void *)k_nt_rows<true>, (const void *)k_nt_rows<false>})
         if ((e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds)) != hipSuccess)
             return e;
-    for (const void *f : {(const void *)k_check_rows<true>, (const void *)k_check_rows<false>,
-                          (const void *)k_prune_count, (const void *)k_prune_fill<true>,
-                          (const void *)k_prune_fill<false>})
+    for (const void *f : {(const void *)k_check_rows<true, false>, (const void *)k_check_rows<false, false>,
+                          (const void *)k_prune_count<false>, (const void *)k_prune_fill<true, false>,
+                          (const void *)k_prune_fill<false, false>})
         if ((e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds)) != hipSuccess)
             return e;
     return hipSuccess;

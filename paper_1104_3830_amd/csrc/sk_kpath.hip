@@ -753,7 +753,7 @@ sk_status run_single_k(sk_ctx *ctx, Batch &B, const sk_params *prm, const StageH
 
 hipError_t set_k_attributes() {
     hipError_t e;
-    const int lds = (int)(kMaxN * sizeof(float2));
+    const int lds = (int)(kLdsMaxN * sizeof(float2));
     for (const void *f : {(const void *)k_absorb<SK_K_BF16, true>, (const void *)k_absorb<SK_K_BF16, false>,
                           (const void *)k_absorb<SK_K_F32, true>, (const void *)k_absorb<SK_K_F32, false>})
         if ((e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds)) != hipSuccess)
@@ -761,7 +761,7 @@ hipError_t set_k_attributes() {
     for (const void *f : {(const void *)k_check_k_rows<SK_K_BF16, true>, (const void *)k_check_k_rows<SK_K_BF16, false>,
                           (const void *)k_check_k_rows<SK_K_F32, true>, (const void *)k_check_k_rows<SK_K_F32, false>})
         if ((e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)(kMaxN * sizeof(float)))) != hipSuccess)
+                                     (int)(kLdsMaxN * sizeof(float)))) != hipSuccess)
             return e;
     for (const void *f : {(const void *)k_row_sweep_k<SK_K_BF16, true>,
                           (const void *)k_row_sweep_k<SK_K_BF16, false>,

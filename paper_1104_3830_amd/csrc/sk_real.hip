@@ -607,7 +607,7 @@ hipError_t launch_prune_fill_real(const Inst *d_insts, const RowUnit *d_units, i
 }
 
 hipError_t set_real_attributes() {
-    const int lds = (int)(kMaxN * sizeof(double));
+    const int lds = (int)(kLdsMaxN * sizeof(double));
     hipError_t e;
     for (const void *f :
          {(const void *)k_row_sweep_real<true, true>, (const void *)k_row_sweep_real<true, false>,

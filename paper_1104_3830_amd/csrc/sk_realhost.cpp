@@ -30,7 +30,7 @@ sk_status plan_real(sk_ctx *ctx, Bump &bump, const float *W, int32_t n, const sk
     sk_status st = check_params(ctx, params, true);
     if (st != SK_OK) return st;
     if (!W) return fail(ctx, SK_EINVAL, "null W");
-    if (n < 1 || n > kMaxN) return fail(ctx, SK_EINVAL, "n = %d outside [1, %d]", n, kMaxN);
+    if (n < 1 || n > kLdsMaxN) return fail(ctx, SK_EINVAL, "n = %d outside [1, %d]", n, kLdsMaxN);
     HIPCHK(ctx, hipSetDevice(ctx->device));
     // range scan into scratch at the start of the arena (reused by the plan)
     Bump tmp = bump;
@@ -75,7 +75,7 @@ sk_status plan_real(sk_ctx *ctx, Bump &bump, const float *W, int32_t n, const sk
 using namespace sk;
 
 size_t sk_real_arena_bytes(int32_t n, int64_t max_kept) {
-    if (n < 1 || n > kMaxN || max_kept < 0) return 0;
+    if (n < 1 || n > kLdsMaxN || max_kept < 0) return 0;
     return instance_bytes(n, 1, SK_W_I16) + shared_bytes(1, &n) + real_shared_extra(n, max_kept) + 4096;
 }
 

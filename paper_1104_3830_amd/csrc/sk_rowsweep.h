@@ -5,6 +5,8 @@
 // other's code.
 #pragma once
 
+#include <type_traits>
+
 #include "sk_exptab.h"
 
 namespace sk {
@@ -71,16 +73,27 @@ struct alignas(8) ColPot {
     float g;
 };
 
-template <bool SENT>
-__device__ __forceinline__ float chunk8(const int4 v, int q, int n8, int p4, int B,
-                                        const ColPot *__restrict__ cp,
+// CP: the column entries' pointer type, an LDS array or (n > kLdsMaxN) a
+// global-address-space pointer, so that each instantiation reads them with
+// the matching instructions.
+// Entry i of the column data, through either pointer type.
+template <class CP>
+__device__ __forceinline__ ColPot cp_at(CP cp, int i) {
+    ColPot k;
+    k.a = cp[i].a;
+    k.g = cp[i].g;
+    return k;
+}
+
+template <bool SENT, class CP>
+__device__ __forceinline__ float chunk8(const int4 v, int q, int n8, int p4, int B, CP cp,
                                         const float *__restrict__ tab) {
     int w[8];
     unpack8i(v, w);
     float s = 0.f;
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-        const ColPot k = cp[c * n8 + q];
+        const ColPot k = cp_at(cp, c * n8 + q);
         float e = tab_at(tab, tab_off(p4, w[c], k.a, B));
         if (SENT) e = (w[c] == SK_SENTINEL) ? 0.f : e;
         s = fmaf(e, k.g, s);
@@ -96,10 +109,9 @@ constexpr int kColLoads = 1;
 
 // Row partial sum for one lane: chunks lane*8 + k*512, kRowLoads 16-byte
 // loads in flight per lane.
-template <bool SENT, bool NT>
+template <bool SENT, bool NT, class CP>
 __device__ __forceinline__ float row_partial_v8(const int16_t *__restrict__ wr, int n, int p4,
-                                                int B, const ColPot *__restrict__ cp,
-                                                const float *__restrict__ tab, int lane) {
+                                                int B, CP cp, const float *__restrict__ tab, int lane) {
     constexpr int U = kRowLoads;
     const int n8 = pad8(n) >> 3;
     float acc = 0.f;
@@ -120,9 +132,9 @@ __device__ __forceinline__ float row_partial_v8(const int16_t *__restrict__ wr, 
 }
 
 // max_j of 4 (p w_ij + G_j) + B over the entries of the row (INT_MIN if none).
-template <bool SENT, bool NT>
-__device__ __forceinline__ int row_max_v8(const int16_t *__restrict__ wr, int n, int p4, int B,
-                                          const ColPot *__restrict__ cp, int lane) {
+template <bool SENT, bool NT, class CP>
+__device__ __forceinline__ int row_max_v8(const int16_t *__restrict__ wr, int n, int p4, int B, CP cp,
+                                          int lane) {
     const int n8 = pad8(n) >> 3;
     int m = INT_MIN;
     for (int j0 = lane * 8; j0 < n; j0 += 512) {
@@ -139,14 +151,13 @@ __device__ __forceinline__ int row_max_v8(const int16_t *__restrict__ wr, int n,
     return m;
 }
 
-template <bool SENT, bool NT>
+template <bool SENT, bool NT, class CP>
 __device__ __forceinline__ float row_partial_v1(const int16_t *__restrict__ wr, int n, int p4,
-                                                int B, const ColPot *__restrict__ cp,
-                                                const float *__restrict__ tab, int lane) {
+                                                int B, CP cp, const float *__restrict__ tab, int lane) {
     float acc = 0.f;
     for (int j = lane; j < n; j += kWave) {
         const int w = (int)gload<NT>(wr + j);
-        const ColPot k = cp[j];
+        const ColPot k = cp_at(cp, j);
         float e = tab_at(tab, tab_off(p4, w, k.a, B));
         if (SENT) e = (w == SK_SENTINEL) ? 0.f : e;
         acc = fmaf(e, k.g, acc);
@@ -154,9 +165,9 @@ __device__ __forceinline__ float row_partial_v1(const int16_t *__restrict__ wr, 
     return acc;
 }
 
-template <bool SENT, bool NT>
-__device__ __forceinline__ int row_max_v1(const int16_t *__restrict__ wr, int n, int p4, int B,
-                                          const ColPot *__restrict__ cp, int lane) {
+template <bool SENT, bool NT, class CP>
+__device__ __forceinline__ int row_max_v1(const int16_t *__restrict__ wr, int n, int p4, int B, CP cp,
+                                          int lane) {
     int m = INT_MIN;
     for (int j = lane; j < n; j += kWave) {
         const int w = (int)gload<NT>(wr + j);
@@ -169,10 +180,9 @@ __device__ __forceinline__ int row_max_v1(const int16_t *__restrict__ wr, int n,
 // Completes the row step of `row` from its sum S relative to the previous
 // iterate (shift 0): the exact max-shifted recompute if S left the safe
 // range, then the new potentials and the residual.
-template <bool SENT, bool V8, bool NT>
+template <bool SENT, bool V8, bool NT, class CP>
 __device__ __forceinline__ float row_finish(const Inst &I, int row, int par, int lane, int Fi,
-                                            float phi, float S, const ColPot *__restrict__ cp,
-                                            const float *__restrict__ tab) {
+                                            float phi, float S, CP cp, const float *__restrict__ tab) {
     const int n = I.n;
     const int16_t *wr = I.W + (int64_t)row * I.pitch;
     const int p4 = 4 * I.ctl->p;
@@ -208,9 +218,8 @@ __device__ __forceinline__ float row_finish(const Inst &I, int row, int par, int
     return 0.f;
 }
 
-template <bool SENT, bool V8, bool NT>
-__device__ __forceinline__ float row_step_one(const Inst &I, int row, int par, int lane,
-                                             const ColPot *__restrict__ cp,
+template <bool SENT, bool V8, bool NT, class CP>
+__device__ __forceinline__ float row_step_one(const Inst &I, int row, int par, int lane, CP cp,
                                              const float *__restrict__ tab) {
     const int n = I.n;
     const int16_t *wr = I.W + (int64_t)row * I.pitch;
@@ -295,7 +304,10 @@ __device__ __forceinline__ void stage_pad_cols(const Inst &I, ColPot *cp, int n8
 // kShortRowN; two workgroups per CU, at most 64 VGPRs). A short row is one or
 // two passes of loads, so a wave's time goes to waiting for them, and twice
 // the resident waves hide twice the latency.
-template <bool NT, int MINW>
+// GCOL: one instance with n > kLdsMaxN; the column entries are read from
+// I.colpack (k_col_pack, mode 0, in the same layout) instead of LDS, where
+// the L2 cache holds them (8 bytes per column against 2 of W per entry).
+template <bool NT, int MINW, bool GCOL = false>
 __global__ __launch_bounds__(kRowWaves * kWave, MINW) void k_row_sweep(const Inst *__restrict__ insts,
                                                                    const RowUnit *__restrict__ units,
                                                                    int nunits,
@@ -320,6 +332,11 @@ __global__ __launch_bounds__(kRowWaves * kWave, MINW) void k_row_sweep(const Ins
     fill_exp_table(tab);
     __syncthreads();
     int cur = -1;
+    // GCOL launches hold one instance: its packed entries, read as global
+    using CP = std::conditional_t<GCOL, const SK_GLOBAL ColPot *, const ColPot *>;
+    CP cp;
+    if constexpr (GCOL) cp = (CP)insts[0].colpack;
+    else cp = lds_cp;
     float wres = 0.f;  // this wave's residual maximum for instance `cur` (lane 0)
     const int slot = (int)((blockIdx.x * kRowWaves + wave) % kRowResSlots) * kRowResStride;
     auto flush = [&]() {
@@ -339,11 +356,13 @@ __global__ __launch_bounds__(kRowWaves * kWave, MINW) void k_row_sweep(const Ins
         const int iter = ctl->iter;
         if (un.inst != cur) {
             flush();
-            __syncthreads();
-            const int n8 = pad8(n) >> 3;
-            stage_col_pots<MINW == 1>(I, lds_cp, n8);
-            stage_pad_cols(I, lds_cp, n8);
-            __syncthreads();
+            if (!GCOL) {
+                __syncthreads();
+                const int n8 = pad8(n) >> 3;
+                stage_col_pots<MINW == 1>(I, lds_cp, n8);
+                stage_pad_cols(I, lds_cp, n8);
+                __syncthreads();
+            }
             cur = un.inst;
         }
         const int par = iter & 1;
@@ -352,11 +371,11 @@ __global__ __launch_bounds__(kRowWaves * kWave, MINW) void k_row_sweep(const Ins
         float e = 0.f;
         if (ra < n) {
             if (I.vec8) {
-                e = sent ? row_step_one<true, true, NT>(I, ra, par, lane, lds_cp, tab)
-                         : row_step_one<false, true, NT>(I, ra, par, lane, lds_cp, tab);
+                e = sent ? row_step_one<true, true, NT>(I, ra, par, lane, cp, tab)
+                         : row_step_one<false, true, NT>(I, ra, par, lane, cp, tab);
             } else {
-                e = sent ? row_step_one<true, false, NT>(I, ra, par, lane, lds_cp, tab)
-                         : row_step_one<false, false, NT>(I, ra, par, lane, lds_cp, tab);
+                e = sent ? row_step_one<true, false, NT>(I, ra, par, lane, cp, tab)
+                         : row_step_one<false, false, NT>(I, ra, par, lane, cp, tab);
             }
         }
         wres = fmaxf(wres, e);

@@ -21,8 +21,9 @@ TilePlan plan_tiles(int32_t n, int vec8);
 size_t instance_bytes(int32_t n, int vec8, int storage, int fused = 0);
 size_t shared_bytes(int32_t count, const int32_t *n);
 size_t pad_copy_bytes(int32_t n);
-// LDS of the kernels that stage (G_j, gam_j) per column (FP64 check, pruning)
-inline size_t gq_lds_bytes(int32_t n) { return 8 * (size_t)pad8(n); }
+// LDS of the kernels that stage (G_j, gam_j) per column (FP64 check,
+// pruning); none above kLdsMaxN (the entries are read from I.colpack)
+inline size_t gq_lds_bytes(int32_t n) { return n > kLdsMaxN ? 0 : 8 * (size_t)pad8(n); }
 
 // A set of instances swept together, with its device tables.
 struct Batch {
@@ -169,6 +170,9 @@ sk_status fail(sk_ctx *ctx, sk_status st, const char *fmt, ...);
 // real: the parameters of a real-valued entry point (prescale allowed; two
 // sweeps, Sinkhorn, W read directly)
 sk_status check_params(sk_ctx *ctx, const sk_params *p, bool real = false);
+// n of one instance: [1, kMaxN]; above kLdsMaxN only the two-sweep Sinkhorn
+// iteration on int16 W
+sk_status check_size(sk_ctx *ctx, int32_t n, const sk_params *p);
 sk_status check_range(sk_ctx *ctx, const sk_params *prm);  // p small enough for exact exponents
 sk_status status_of(const Ctl &c);  // SK_OK, SK_ENOCONV (a stage capped) or SK_ENOSUPPORT
 // Wr != nullptr: a real-valued instance (W unused; Wr read with pitch `pitch`).

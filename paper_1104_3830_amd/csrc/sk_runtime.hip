@@ -55,6 +55,7 @@ size_t instance_bytes(int32_t n, int vec8, int storage, int fused) {
     b += align_up(sizeof(float) * std::max((n + kRowWaves - 1) / kRowWaves, kFusedSlots), 256) * 2;
     b += align_up(sizeof(float) * n, 256);  // rres
     b += align_up(sizeof(uint32_t) * kRowResSlots * kRowResStride, 256);  // rowres
+    if (n > kLdsMaxN) b += align_up(8 * (size_t)pad8(n), 256);  // colpack
     if (storage == SK_K_BF16 || storage == SK_K_F32) {
         const size_t es = storage == SK_K_BF16 ? 2 : 4;
         const size_t kp = (size_t)(n + 7) / 8 * 8;
@@ -228,13 +229,15 @@ static bool g_attr_done = false;
 size_t sk_potentials_bytes(int32_t n) { return n > 0 ? (size_t)16 * n : 0; }
 
 size_t sk_arena_bytes(int32_t n, int32_t storage) {
-    if (n <= 0) return 0;
+    if (n <= 0 || n > kMaxN) return 0;
     return instance_bytes(n, 1, storage, 1) + pad_copy_bytes(n) + shared_bytes(1, &n) +
            newton_bytes(n) + 4096;
 }
 
 size_t sk_batch_arena_bytes(int32_t count, const int32_t *n, int32_t storage) {
     if (count <= 0 || !n) return 0;
+    for (int k = 0; k < count; ++k)
+        if (n[k] <= 0 || n[k] > (count == 1 ? kMaxN : kLdsMaxN)) return 0;
     size_t b = shared_bytes(count, n) + 4096;
     for (int k = 0; k < count; ++k) b += instance_bytes(n[k], 1, storage) + pad_copy_bytes(n[k]);
     return b;
@@ -301,6 +304,15 @@ sk_status sk::fail(sk_ctx *ctx, sk_status st, const char *fmt, ...) {
     va_end(ap);
     ctx->err = buf;
     return st;
+}
+
+sk_status sk::check_size(sk_ctx *ctx, int32_t n, const sk_params *p) {
+    if (n < 1 || n > kMaxN) return fail(ctx, SK_EINVAL, "n = %d outside [1, %d]", n, kMaxN);
+    if (n > kLdsMaxN && p && (p->storage != SK_W_I16 || p->fused || p->method != SK_SINKHORN))
+        return fail(ctx, SK_EINVAL,
+                    "n = %d above %d: only the two-sweep Sinkhorn iteration on int16 W (storage 0, not fused)",
+                    n, kLdsMaxN);
+    return SK_OK;
 }
 
 sk_status sk::check_params(sk_ctx *ctx, const sk_params *p, bool real) {
@@ -394,6 +406,10 @@ bool sk::carve_instance(Bump &bump, const int16_t *W, int64_t pitch, int32_t nn,
     I.rres = bump.take<float>(nn);
     I.rowres = bump.take<uint32_t>((size_t)kRowResSlots * kRowResStride);
     if (!I.res_slots || !I.drift_slots || !I.rres || !I.rowres) return false;
+    if (nn > kLdsMaxN && !Wr) {
+        I.colpack = bump.take<int2>((size_t)pad8(nn));
+        if (!I.colpack) return false;
+    }
     if (!I.F[0] || !I.F[1] || !I.phi[0] || !I.phi[1] || !I.G || !I.gam || !I.colpart ||
         !I.rescue || !I.ctl)
         return false;
@@ -450,7 +466,8 @@ sk_status sk::finish_tables(sk_ctx *ctx, Bump &bump, Batch &B) {
         !B.d_counts || !B.d_cpart || !B.d_ctl_all || !B.d_checkout || !B.d_nnz)
         return fail(ctx, SK_ENOMEM, "arena too small for the batch tables");
     // grids: row sweep stages pad8(n) columns of potentials (8 B each) in LDS
-    const size_t lds = sizeof(float2) * (size_t)pad8(B.nmax);
+    // (above kLdsMaxN it reads them from the instance's packed buffer)
+    const size_t lds = B.nmax > kLdsMaxN ? 0 : sizeof(float2) * (size_t)pad8(B.nmax);
     const int per_cu = lds <= 32768 ? 2 : 1;
     B.row_lds = lds;
     B.row_lds_k = sizeof(float) * (size_t)((B.nmax + 7) / 8 * 8);
@@ -585,17 +602,21 @@ sk_status sk::iterate_i16(sk_ctx *ctx, Batch &B, bool chained) {
     // record their own end stamps; the row sweep is timed from the previous
     // iteration's end stamp when this call follows it directly, else from a
     // marker. The short finalise launch between is not stamped.
-    const int s0 = chained && pf.iter_end_stamp >= 0 ? pf.iter_end_stamp : pf.stamp(ctx->stream);
+    const Inst &I0 = B.h_insts[0];
+    // n > kLdsMaxN (one instance): the row sweep reads the column entries
+    // packed here (timed with it)
+    const int gcol = B.count == 1 && I0.colpack != nullptr;
+    const int s0 = chained && !gcol && pf.iter_end_stamp >= 0 ? pf.iter_end_stamp : pf.stamp(ctx->stream);
+    if (gcol) HIPCHK(ctx, launch_col_pack(B.d_insts, 0, I0.n, 0, ctx->stream));
     const int nt = B.count > 0 ? B.h_insts[0].nt : 0;  // the same for the whole batch
     int s1, s2, s3;
     hipEvent_t e1 = pf.kernel_stamp(&s1);
-    const Inst &I0 = B.h_insts[0];
     if (I0.Wr)
         HIPCHK(ctx, launch_row_sweep_real(B.d_insts, B.d_rows, (int)B.h_rows.size(), B.row_grid,
                                           B.row_lds, nt, I0.vec8, ctx->stream, e1));
     else
         HIPCHK(ctx, launch_row_sweep(B.d_insts, B.d_rows, (int)B.h_rows.size(), B.d_row_bounds,
-                                     B.row_grid, B.row_lds, nt, B.nmax <= kShortRowN, ctx->stream, e1));
+                                     B.row_grid, B.row_lds, nt, B.nmax <= kShortRowN, gcol, ctx->stream, e1));
     hipEvent_t e2 = pf.kernel_stamp(&s2);
     if (I0.Wr)
         HIPCHK(ctx, launch_col_sweep_real(B.d_insts, B.d_cols, (int)B.h_cols.size(), B.col_grid, nt,
@@ -708,10 +729,13 @@ sk_status sk::enqueue_check(sk_ctx *ctx, Batch &B, int k, const CheckCounts *cc)
                                         B.d_checkout + 4 * (size_t)k, ctx->stream));
         return SK_OK;
     }
+    // n > kLdsMaxN: the row pass reads (G_j, gam_j) packed in I.colpack
+    const int gcol = I.colpack != nullptr;
+    if (gcol) HIPCHK(ctx, launch_col_pack(B.d_insts, k, nn, 1, ctx->stream));
     HIPCHK(ctx, PROF(ctx, KID_CHECK_ROWS,
                      launch_check_rows(B.d_insts, B.d_rows + first, nunits, grid, B.d_rsum,
                                        B.d_rmax, cc ? cc->logt : 0.0, cc ? cc->counts : nullptr,
-                                       cc ? cc->hint : nullptr, gq_lds_bytes(nn), I.nt,
+                                       cc ? cc->hint : nullptr, gq_lds_bytes(nn), I.nt, gcol,
                                        ctx->stream)));
     HIPCHK(ctx, PROF(ctx, KID_CHECK_COLS, launch_check_cols(B.d_insts, k, nn, I.nseg, I.vec8,
                                                             B.d_cpart, B.d_csum, I.nt, ctx->stream)));
@@ -796,7 +820,12 @@ sk_status sk::scale_impl(sk_ctx *ctx, int count, const int16_t *const *W, const 
     std::vector<int64_t> pitch(count);
     for (int k = 0; k < count; ++k) {
         if (!W[k] || !pot[k]) return fail(ctx, SK_EINVAL, "null W or potentials for instance %d", k);
-        if (n[k] < 1 || n[k] > kMaxN) return fail(ctx, SK_EINVAL, "n[%d] = %d outside [1, %d]", k, n[k], kMaxN);
+        if (count == 1) {
+            if ((st = check_size(ctx, n[0], prm)) != SK_OK) return st;
+        } else if (n[k] < 1 || n[k] > kLdsMaxN) {
+            return fail(ctx, SK_EINVAL, "n[%d] = %d outside [1, %d] (a batch; one larger instance goes to sk_scale)",
+                        k, n[k], kLdsMaxN);
+        }
         pitch[k] = n[k];
     }
     if (prm->storage != SK_W_I16 && count != 1)
@@ -920,8 +949,10 @@ sk_status sk_prune(sk_ctx *ctx, const int16_t *W, int32_t n, const void *potenti
                                ctx->stream));
     const double logt = std::log(params->threshold);
     const int nunits = (int)B.h_rows.size();
+    const int gcol = I.colpack != nullptr;  // n > kLdsMaxN: (G_j, gam_j) packed
+    if (gcol) HIPCHK(ctx, launch_col_pack(B.d_insts, 0, n, 1, ctx->stream));
     HIPCHK(ctx, PROF(ctx, KID_PRUNE_COUNT, launch_prune_count(B.d_insts, B.d_rows, nunits, B.row_grid, logt, B.d_counts,
-                                   gq_lds_bytes(n), ctx->stream)));
+                                   gq_lds_bytes(n), gcol, ctx->stream)));
     HIPCHK(ctx, PROF(ctx, KID_SCAN, launch_scan(B.d_counts, csr->row_ptr, n, ctx->stream)));
     int64_t total = 0;
     HIPCHK(ctx, hipMemcpyAsync(&total, csr->row_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost,
@@ -935,7 +966,7 @@ sk_status sk_prune(sk_ctx *ctx, const int16_t *W, int32_t n, const void *potenti
     if (total > 0) {
         if (!csr->col || !csr->w) return fail(ctx, SK_EINVAL, "null col/w buffers");
         HIPCHK(ctx, PROF(ctx, KID_PRUNE_FILL, launch_prune_fill(B.d_insts, B.d_rows, nunits, B.row_grid, logt, csr->row_ptr,
-                                      csr->col, csr->w, gq_lds_bytes(n), B.h_insts[0].nt, ctx->stream)));
+                                      csr->col, csr->w, gq_lds_bytes(n), B.h_insts[0].nt, gcol, ctx->stream)));
     }
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     return SK_OK;

@@ -231,7 +231,7 @@ static sk_status rebuild(Server *S) {
     for (Request *r : S->active) S->B.h_insts.push_back(r->inst);
     Bump tb{ctx->arena, S->tables_len};
     // the first part of the tables region holds the init-unit table
-    S->d_init_units = tb.take<RowUnit>(kMaxN / kRowWaves * 64);
+    S->d_init_units = tb.take<RowUnit>(kLdsMaxN / kRowWaves * 64);
     S->d_fresh = tb.take<int>(kMaxBatch);
     sk_status st = finish_tables(ctx, tb, S->B);
     if (st != SK_OK) return st;
@@ -279,7 +279,7 @@ static sk_status retire_all(Server *S, const std::vector<int> &fin) {
         const double logt = std::log(r->prm.threshold);
         int64_t *d_rp = (int64_t *)(ctx->arena + rp_off[q]);
         e = launch_prune_count(B.d_insts, B.d_rows + first, nunits, grid, logt, B.d_counts,
-                               gq_lds_bytes(r->n), ctx->stream);
+                               gq_lds_bytes(r->n), 0, ctx->stream);
         if (e == hipSuccess) e = launch_scan(B.d_counts, d_rp, r->n, ctx->stream, B.d_nnz + k);
     }
     if (st == SK_OK && e == hipSuccess)
@@ -321,7 +321,7 @@ static sk_status retire_all(Server *S, const std::vector<int> &fin) {
             const int grid = std::min(nunits, ctx->num_cus * 2);
             e = launch_prune_fill(B.d_insts, B.d_rows + first, nunits, grid,
                                   std::log(r->prm.threshold), d_rp, d_col, d_w,
-                                  gq_lds_bytes(r->n), B.h_insts[k].nt, ctx->stream);
+                                  gq_lds_bytes(r->n), B.h_insts[k].nt, 0, ctx->stream);
             r->col.resize(nnz);
             r->w.resize(nnz);
             if (e == hipSuccess)
@@ -419,7 +419,7 @@ static void serve_loop(Server *S) {
             size_t done = 0;
             while (e == hipSuccess && st == SK_OK && done < S->init_units.size()) {
                 const size_t chunk = std::min<size_t>(S->init_units.size() - done,
-                                                      (size_t)kMaxN / kRowWaves * 64);
+                                                      (size_t)kLdsMaxN / kRowWaves * 64);
                 e = hipMemcpyAsync(S->d_init_units, S->init_units.data() + done,
                                    sizeof(RowUnit) * chunk, hipMemcpyHostToDevice, ctx->stream);
                 if (e == hipSuccess)
@@ -549,7 +549,7 @@ extern "C" sk_status sk_submit(sk_ctx *ctx, const int16_t *W_host, int32_t n, co
     sk_status st = check_params(ctx, params);
     if (st != SK_OK) return st;
     if (params->storage != SK_W_I16) return fail(ctx, SK_EINVAL, "served path sweeps int16 W");
-    if (n < 1 || n > kMaxN) return fail(ctx, SK_EINVAL, "n = %d outside [1, %d]", n, kMaxN);
+    if (n < 1 || n > kLdsMaxN) return fail(ctx, SK_EINVAL, "n = %d outside [1, %d]", n, kLdsMaxN);
     if (!(params->threshold > 0.0)) return fail(ctx, SK_EINVAL, "threshold must be > 0");
     std::lock_guard<std::mutex> call(ctx->mu);
     Server *S = ensure_server(ctx);

@@ -41,9 +41,12 @@ sk_status reduce_and_solve(sk_ctx *ctx, Batch &B, Bump &rest, int64_t *d_rp, con
     const double logt = std::log(t);
     const int nunits = (int)B.h_rows.size();
     const size_t lds = gq_lds_bytes(n);
+    // n > kLdsMaxN: the CSR passes read (G_j, gam_j) packed in I.colpack
+    const int gcol = I.colpack != nullptr;
+    if (gcol) HIPCHK(ctx, launch_col_pack(B.d_insts, 0, n, 1, ctx->stream));
     if (!counted) {
         HIPCHK(ctx, PROF(ctx, KID_PRUNE_COUNT, launch_prune_count(B.d_insts, B.d_rows, nunits, B.row_grid,
-                                                                 logt, B.d_counts, lds, ctx->stream)));
+                                                                 logt, B.d_counts, lds, gcol, ctx->stream)));
         HIPCHK(ctx, PROF(ctx, KID_SCAN, launch_scan(B.d_counts, d_rp, n, ctx->stream, B.d_nnz)));
         HIPCHK(ctx, hipMemcpyAsync(ctx->h_nnz, B.d_nnz, sizeof(int64_t), hipMemcpyDeviceToHost,
                                    ctx->stream));
@@ -76,7 +79,8 @@ sk_status reduce_and_solve(sk_ctx *ctx, Batch &B, Bump &rest, int64_t *d_rp, con
             return fail(ctx, SK_ENOMEM, "the reduced matrix keeps %lld entries; the arena cannot hold them",
                         (long long)nnz);
         HIPCHK(ctx, PROF(ctx, KID_PRUNE_FILL, launch_prune_fill(B.d_insts, B.d_rows, nunits, B.row_grid,
-                                                               logt, d_rp, d_col, d_w, lds, I.nt, ctx->stream)));
+                                                               logt, d_rp, d_col, d_w, lds, I.nt, gcol,
+                                                               ctx->stream)));
         HIPCHK(ctx, hipMemcpyAsync(col, d_col, sizeof(int32_t) * (size_t)nnz,
                                    hipMemcpyDeviceToHost, ctx->stream));
         HIPCHK(ctx, hipMemcpyAsync(w, d_w, sizeof(int16_t) * (size_t)nnz, hipMemcpyDeviceToHost,
@@ -124,7 +128,7 @@ extern "C" sk_status sk_solve(sk_ctx *ctx, const int16_t *W, int32_t n, const sk
     sk_status st = check_params(ctx, params);
     if (st != SK_OK) return st;
     if (!W || !potentials || !perm || !weight) return fail(ctx, SK_EINVAL, "null argument");
-    if (n < 1 || n > kMaxN) return fail(ctx, SK_EINVAL, "n = %d outside [1, %d]", n, kMaxN);
+    if ((st = check_size(ctx, n, params)) != SK_OK) return st;
     if (!(params->threshold > 0.0)) return fail(ctx, SK_EINVAL, "threshold must be > 0");
     if (params->fused && params->storage == SK_W_I16 && (n % 8 != 0 || (uintptr_t)W % 16 != 0))
         return fail(ctx, SK_EINVAL, "the single-pass iteration over int16 W needs n %% 8 == 0");

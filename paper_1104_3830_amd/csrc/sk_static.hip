@@ -41,7 +41,7 @@ sk_status sk_scale_static(sk_ctx *ctx, const int16_t *W, int32_t n, const sk_par
     if (!ctx) return SK_EINVAL;
     std::lock_guard<std::mutex> g(ctx->mu);
     if (!params) return fail(ctx, SK_EINVAL, "params is NULL");
-    if (n < 1 || n > kMaxN) return fail(ctx, SK_EINVAL, "n = %d outside [1, %d]", n, kMaxN);
+    if (const sk_status st = check_size(ctx, n, params); st != SK_OK) return st;
     const size_t need = sk_arena_bytes(n, params->storage);
     if (need > (size_t)SK_STATIC_SCRATCH_BYTES)
         return fail(ctx, SK_ENOMEM,

@@ -320,3 +320,26 @@ def test_tuned_tile_table_is_valid_and_loaded():
     sk.lib()
     if not os.environ.get("SK_NO_TILE_TABLE"):
         assert sk.loaded_tile_table == ent
+
+
+def test_static_scratch_limits_documented_in_header():
+    """The sizes include/sk.h gives for sk_scale_static are the largest whose
+    sk_arena_bytes fit SK_STATIC_SCRATCH_BYTES (64 MiB): int16 W n = 44016
+    (a multiple of 8), a ragged n = 5343, BF16 K n = 5336, FP32 K n = 3888."""
+    L = sk.lib()
+    lim = 64 << 20
+    assert "SK_STATIC_SCRATCH_BYTES ((size_t)64 << 20)" in open(os.path.join(ROOT, "include", "sk.h")).read()
+    for n, step, storage in ((44016, 8, 0), (5343, 1, 0), (5336, 8, 1), (3888, 8, 2)):
+        assert L.sk_arena_bytes(n, storage) <= lim, (n, storage)
+        nxt = n + step
+        while storage == 0 and step == 1 and nxt % 8 == 0:
+            nxt += 1  # the next ragged size
+        assert L.sk_arena_bytes(nxt, storage) > lim, (nxt, storage)
+
+
+def test_size_limits():
+    """Single instances go up to n = 65536 (int16 W, two sweeps); 65537 has no
+    arena size. Batches stay at n <= 16384."""
+    L = sk.lib()
+    assert L.sk_arena_bytes(65536, 0) > L.sk_arena_bytes(16384, 0) > 0
+    assert L.sk_arena_bytes(65537, 0) == 0
