@@ -101,6 +101,7 @@ def parse():
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-algorithm1", action="store_true")
     ap.add_argument("--no-dominant", action="store_true")
+    ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--served-requests", type=int, default=1000)
     ap.add_argument("--served-loads", default="0.5,0.9,1.5",
                     help="arrival rates as multiples of the FIFO loop's measured capacity")
@@ -547,6 +548,36 @@ def dominant_leg(sk, torch, prm, n=16384, seed=5, solves=8):
             "optimal": bool(np.array_equal(out["perm"], np.arange(n)) and out["weight"] == diag)}
 
 
+def large_leg(sk, torch, ladder, cap, tol, threshold, n=32768, seed=0, solves=3):
+    """One instance above the LDS limit (n = 32768, w uniform on 0..1000, the
+    main leg's parameters): the sweeps read the column entries from the
+    packed global buffer. Whole sk_solve steps, the sweeps' average launch
+    durations and their fraction of the HBM peak (n^2 * 2 bytes each)."""
+    import skgen
+    Wd = torch.from_numpy(skgen.uniform_weights(n, 0, 1000, seed=seed)).cuda()
+    prm = sk.make_params(ladder, tol=tol, max_iters=cap, check_every=32, threshold=threshold)
+    ctx = sk.Context(0)
+    ctx.solve(Wd, prm)  # warm-up
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(solves):
+        out = ctx.solve(Wd, prm)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / solves
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    ctx.close()
+    del Wd
+    r = out["report"]
+    kern = {k: round(v[1] / max(v[0], 1) * 1e3, 2) for k, v in prof.items() if k in ("row_sweep", "col_sweep")}
+    return {"n": n, "ms_per_step": round(el * 1e3, 3), "iters_per_step": r["iters_total"],
+            "stages_capped": r["stages_capped"], "weight": out["weight"],
+            "optimal_proved": bool(r["optimal_proved"]), "sweep_avg_us": kern,
+            "frac": {k: round(n * n * 2 / (v * 1e-6) / 1e9 / HBM_PEAK_GBS, 4) for k, v in kern.items()},
+            "value_GBps": round(2 * r["iters_total"] * n * n * 2 / el / 1e9, 1)}
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -856,6 +887,8 @@ def main():
         out["algorithm1"] = algorithm1_leg(sk, torch)
     if not args.no_dominant:
         out["dominant"] = dominant_leg(sk, torch, prm)
+    if not args.no_large:
+        out["large"] = large_leg(sk, torch, ladder, args.cap, args.tol, args.threshold)
     if not args.no_served:
         out["served"] = served_leg(sk, torch, args.served_requests,
                                    [float(x) for x in args.served_loads.split(",")])

@@ -233,6 +233,45 @@ __device__ __forceinline__ float row_step_one(const Inst &I, int row, int par, i
     return row_finish<SENT, V8, NT>(I, row, par, lane, Fi, phi, S, cp, tab);
 }
 
+// Rows above kLdsMaxN (column entries from the packed global buffer): a wave
+// sweeps R rows at once, so that each chunk of column entries is loaded once
+// for the R rows (its L2 traffic per matrix entry drops from 8 bytes to
+// 8 / R). The sums of each row are formed exactly as row_partial_v8 forms
+// them (the same chunks in the same order).
+constexpr int kMultiRows = 4;
+
+template <bool SENT, bool NT, int R, class CP>
+__device__ __forceinline__ void row_partial_multi(const int16_t *const (&wr)[R], const bool (&act)[R], int n,
+                                                  int p4, const int (&B)[R], CP cp,
+                                                  const float *__restrict__ tab, int lane, float (&acc)[R]) {
+    const int n8 = pad8(n) >> 3;
+#pragma unroll
+    for (int k = 0; k < R; ++k) acc[k] = 0.f;
+    for (int j0 = lane * 8; j0 < n; j0 += 512) {
+        int4 v[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            v[k] = act[k] ? gload<NT>(reinterpret_cast<const int4 *>(wr[k] + j0)) : make_int4(0, 0, 0, 0);
+        const int q = j0 >> 3;
+        ColPot kc[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) kc[c] = cp_at(cp, c * n8 + q);
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            int w[8];
+            unpack8i(v[k], w);
+            float s = 0.f;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                float e = tab_at(tab, tab_off(p4, w[c], kc[c].a, B[k]));
+                if (SENT) e = (w[c] == SK_SENTINEL) ? 0.f : e;
+                s = fmaf(e, kc[c].g, s);
+            }
+            acc[k] += s;
+        }
+    }
+}
+
 // Column potentials of the padding columns n..pad8(n)-1 of the 8-wide layout
 // (a separate loop, so that the staging of the real columns keeps its loads
 // unconditional and in flight together).
@@ -344,6 +383,47 @@ __global__ __launch_bounds__(kRowWaves * kWave, MINW) void k_row_sweep(const Ins
             atomicMax(&insts[cur].rowres[slot], __float_as_uint(wres));
         wres = 0.f;
     };
+    if constexpr (GCOL) {
+        // one instance, 8-wide rows: kMultiRows units at a time, wave w taking
+        // row w of each
+        const Inst &I = insts[0];
+        Ctl *ctl = I.ctl;
+        if (ctl->state == ST_RUNNING && I.vec8) {
+            const int n = I.n, par = ctl->iter & 1, p4 = 4 * ctl->p;
+            const bool sent = ctl->sent != 0u;
+            cur = 0;
+            for (int u = u0; u < u1; u += kMultiRows) {
+                constexpr int R = kMultiRows;
+                const int16_t *wr[R];
+                bool act[R];
+                int row[R], Fi[R], B[R];
+                float phi[R], acc[R];
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    row[k] = u + k < u1 ? units[u + k].row0 + wave : n;
+                    act[k] = row[k] < n;
+                    const int rr = act[k] ? row[k] : 0;
+                    wr[k] = I.W + (int64_t)rr * I.pitch;
+                    Fi[k] = I.F[par][rr];
+                    phi[k] = I.phi[par][rr];
+                    B[k] = 4 * (Fi[k] - kTabLo);
+                }
+                if (sent) row_partial_multi<true, NT, R>(wr, act, n, p4, B, cp, tab, lane, acc);
+                else row_partial_multi<false, NT, R>(wr, act, n, p4, B, cp, tab, lane, acc);
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    if (!act[k]) continue;
+                    const float S = wave_sum(acc[k]);
+                    const float e = sent ? row_finish<true, true, NT>(I, row[k], par, lane, Fi[k], phi[k], S, cp, tab)
+                                         : row_finish<false, true, NT>(I, row[k], par, lane, Fi[k], phi[k], S, cp, tab);
+                    wres = fmaxf(wres, e);
+                }
+            }
+            u0 = u1;  // the loop below has nothing left
+        } else if (ctl->state == ST_RUNNING) {
+            cur = 0;
+        }
+    }
     for (int u = u0; u < u1;) {
         const RowUnit un = units[u];
         const Inst &I = insts[un.inst];
