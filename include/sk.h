@@ -87,11 +87,14 @@ typedef enum {
  *                  > 0 = the deformed Sinkhorn iteration (Section 3.2,
  *                  schedule p_m = a log(m + 1) of Theorem
  *                  logconvergencepositive): one stage in which iteration m
- *                  (from 1) runs at p_m = round(deform_a * ln(m + 1)) kept in
+ *                  (from 1) runs at p_m = deform_a * ln(m + 1) kept in
  *                  [p_ladder[0], p_ladder[n_p - 1]], with u and v carried
  *                  unscaled from one p to the next; it stops at the first
  *                  iterate computed at the last p whose residual is below
- *                  tol, or at max_iters_per_stage. int16 W only.
+ *                  tol, or at max_iters_per_stage. int16 W (storage 0)
+ *                  rounds p_m to an integer (its exact exponents need an
+ *                  integer p); real-valued weights (sk_scale_real) run p_m
+ *                  unrounded.
  *   method       : SK_SINKHORN (0) = Sinkhorn iteration; SK_NEWTON (1) =
  *                  Newton iteration (Section 5.2, the Knight-Ruiz method):
  *                  at each p, x o (S x) = 1 for S = [[0, X], [X^T, 0]] with

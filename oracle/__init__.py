@@ -430,19 +430,25 @@ def adaptive_real(B, ladder, eps, max_iters, t, opt_ratio, prescale=True):
     return best, "ratio"
 
 
-def deformed_p(a, p_min, p_max, m):
+def deformed_p(a, p_min, p_max, m, integer_p=False):
     """p of iteration m (from 1) of the deformed iteration: the schedule
-    p_m = a log(m + 1) of Theorem logconvergencepositive, rounded to an
-    integer (half to even) and kept in [p_min, p_max]."""
-    return int(min(p_max, max(p_min, round(a * math.log(m + 1)))))
+    p_m = a log(m + 1) of Theorem logconvergencepositive, kept in
+    [p_min, p_max]. integer_p: rounded to an integer (half to even) first,
+    the reading taken for integer log-weights, whose exact exponents need an
+    integer p."""
+    v = a * math.log(m + 1)
+    if integer_p:
+        return int(min(p_max, max(p_min, round(v))))
+    return float(min(p_max, max(p_min, v)))
 
 
-def deformed(B, a, p_min, p_max, eps, max_iters):
+def deformed(B, a, p_min, p_max, eps, max_iters, integer_p=False):
     """Deformed Sinkhorn iteration (Section 3.2): v_0 = 1 and, for m = 1, 2, ...,
     u_m = I(A^(p_m) v_{m-1}), v_m = I(A^(p_m)T u_m) with u and v carried as they
-    are from one p to the next (no rescaling). Stops after iteration m when
-    p_m = p_max and the column-stochastic iterate W_m has max_i |r_i - 1| < eps
-    at that p, or after max_iters iterations.
+    are from one p to the next (no rescaling), p_m from deformed_p (the
+    paper's real schedule, or rounded with integer_p). Stops after iteration
+    m when p_m = p_max and the column-stochastic iterate W_m has
+    max_i |r_i - 1| < eps at that p, or after max_iters iterations.
     Returns (log u, log v, iterations, p of the last iteration, residual)."""
     n = B.shape[0]
     logu, logv = np.zeros(n), np.zeros(n)
@@ -450,18 +456,18 @@ def deformed(B, a, p_min, p_max, eps, max_iters):
     m = 0
     while m < max_iters:
         m += 1
-        p = deformed_p(a, p_min, p_max, m)
+        p = deformed_p(a, p_min, p_max, m, integer_p)
         logu = p * row_step(B, p, logv / p)
         logv = p * col_step(B, p, logu / p)
         if p == p_max:
             res = row_residual(B, p, logu / p, logv / p)
             if res < eps:
                 break
-    return logu, logv, m, deformed_p(a, p_min, p_max, m), res
+    return logu, logv, m, deformed_p(a, p_min, p_max, m, integer_p), res
 
 
 def newton(B, p, tol, max_products, ubar=None, vbar=None, lo=0.1, hi=3.0, eta_max=0.1,
-           g=0.9):
+           g=0.9, norm="two"):
     """Newton iteration for the diagonal scaling of A^(p) (Section 5.2, the
     method of Knight and Ruiz cited there).
 
@@ -477,9 +483,15 @@ def newton(B, p, tol, max_products, ubar=None, vbar=None, lo=0.1, hi=3.0, eta_ma
     preconditioned residual falls below max(eta^2 |1 - v|^2, tol^2), with the
     forcing term eta updated after every outer step from the ratio of
     successive residuals (at most eta_max, at least tol / (2 |1 - v|)). The
-    outer loop stops when max_i |1 - v_i| <= tol or after max_products
-    products with S. Returns (ubar, vbar, outer steps, products with S, max |row or
-    column sum - 1| of the result)."""
+    outer loop stops when |1 - v| <= tol, in the 2-norm of the cited method
+    (norm="two") or the max-norm (norm="inf", the Sinkhorn stopping test's
+    norm), or after max_products products with S. Returns (ubar, vbar, outer
+    steps, products with S, max |row or column sum - 1| of the result)."""
+    if norm not in ("two", "inf"):
+        raise ValueError("norm is 'two' or 'inf'")
+
+    def size(r):
+        return math.sqrt(float(r @ r)) if norm == "two" else float(np.abs(r).max())
     n = B.shape[0]
     ubar = np.zeros(n) if ubar is None else np.array(ubar, dtype=np.float64)
     vbar = np.zeros(n) if vbar is None else np.array(vbar, dtype=np.float64)
@@ -495,7 +507,7 @@ def newton(B, p, tol, max_products, ubar=None, vbar=None, lo=0.1, hi=3.0, eta_ma
     rout = float(r @ r)
     rold = rout
     products, outer, eta = 1, 0, eta_max
-    while np.abs(r).max() > tol and products < max_products:
+    while size(r) > tol and products < max_products:
         outer += 1
         y = np.ones(2 * n)
         inner_tol = max(eta * eta * rout, rt)

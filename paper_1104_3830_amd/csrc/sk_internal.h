@@ -59,6 +59,9 @@ struct Ctl {
     uint32_t need_absorb;   // stored K: K must be recomputed before the next K sweep
     uint32_t drift_bits;    // stored K: max |log2 a_i|, |log2 b_j| since the last absorb (float bits)
     int64_t stage_iters[SK_MAX_LADDER];
+    // deformed iteration on real-valued weights: p of the current iteration
+    // unrounded (p is its rounding, used by the integer path)
+    double preal;
 };
 
 // Per-instance descriptor (device memory, constant during a launch).
@@ -133,7 +136,14 @@ struct Inst {
 constexpr int kRowResSlots = 64;    // = kWave: one wave reduces them
 constexpr int kRowResStride = 32;   // one 128-byte line per slot
 
-// p of iteration m (from 1) of the deformed iteration.
+// p of iteration m (from 1) of the deformed iteration: the schedule
+// a log(m + 1) of Theorem logconvergencepositive kept in [first, last ladder
+// entry]; unrounded for real-valued weights, rounded for int16 W (whose
+// exact exponents need an integer p).
+__device__ __forceinline__ double deform_p_real(const Inst &I, int64_t m) {
+    const double lo = (double)I.ladder[0], hi = (double)I.ladder[I.n_p - 1];
+    return fmin(hi, fmax(lo, I.deform_a * log((double)(m + 1))));
+}
 __device__ __forceinline__ int deform_p(const Inst &I, int64_t m) {
     const double v = rint(I.deform_a * log((double)(m + 1)));
     const double lo = (double)I.ladder[0], hi = (double)I.ladder[I.n_p - 1];

@@ -140,6 +140,7 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_init(const Inst *__restri
 // (its residual is then measured at that p too: the schedule stays there).
 __device__ __forceinline__ bool deform_settled(const Inst &I, const Ctl *ctl) {
     if (I.deform_a <= 0.0) return true;
+    if (I.Wr) return deform_p_real(I, ctl->iter) == (double)I.ladder[I.n_p - 1];
     return deform_p(I, ctl->iter) == I.ladder[I.n_p - 1];
 }
 
@@ -562,6 +563,7 @@ __global__ __launch_bounds__(kIterEndThreads) void k_iter_end(const Inst *__rest
     } else if (I.deform_a > 0.0 && threadIdx.x == 0) {
         // deformed iteration: the next iteration's p, potentials unscaled
         ctl->p = deform_p(I, iter + 2);
+        ctl->preal = deform_p_real(I, iter + 2);
     }
 }
 
@@ -1287,6 +1289,7 @@ __global__ __launch_bounds__(256) void k_reset_ctl(const Inst *__restrict__ inst
             memset(&c, 0, sizeof c);
             c.state = ST_RUNNING;
             c.p = I.deform_a > 0.0 ? deform_p(I, 1) : I.ladder[0];
+            c.preal = I.deform_a > 0.0 ? deform_p_real(I, 1) : (double)I.ladder[0];
             c.last_res = INFINITY;
             *I.ctl = c;
         }

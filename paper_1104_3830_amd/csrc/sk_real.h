@@ -26,9 +26,10 @@ __device__ __forceinline__ float pow2_split(double e2) {
     return ldexpf(ex2(f), mi);
 }
 
-// p of the current stage of a real-weight instance.
+// p of the current stage (of the current iteration, deformed) of a
+// real-weight instance.
 __device__ __forceinline__ double real_p(const Inst &I, const Ctl *ctl) {
-    return (double)ctl->p * I.pscale;
+    return (I.deform_a > 0.0 ? ctl->preal : (double)ctl->p) * I.pscale;
 }
 
 // Exact max-shifted recompute (Section 4.1.2) of column j of a real-weight

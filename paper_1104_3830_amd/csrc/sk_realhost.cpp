@@ -109,7 +109,9 @@ sk_status sk_scale_real(sk_ctx *ctx, const float *W, int32_t n, const sk_params 
         HIPCHK(ctx, hipMemcpyAsync(ctx->h_checkout, B.d_checkout, 4 * sizeof(double),
                                    hipMemcpyDeviceToHost, ctx->stream));
         HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-        report_from_check(ctx->h_checkout, (double)c.p * rep.p_scale, &rep, n, B.h_insts[0].wref);
+        // the deformed iteration's last p is unrounded on real-valued weights
+        const double pl = params->deform_a > 0.0 ? c.preal : (double)c.p;
+        report_from_check(ctx->h_checkout, pl * rep.p_scale, &rep, n, B.h_insts[0].wref);
     }
     if ((st = copy_potentials_out(ctx, B, 0, potentials)) != SK_OK) return st;
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
@@ -183,7 +185,8 @@ sk_status sk_solve_real(sk_ctx *ctx, const float *W, int32_t n, const sk_params 
             HIPCHK(ctx, hipMemcpyAsync(ctx->h_nnz, B.d_nnz, sizeof(int64_t), hipMemcpyDeviceToHost,
                                        ctx->stream));
             HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-            report_from_check(ctx->h_checkout, (double)c.p * pscale, &rep, n, wref);
+            report_from_check(ctx->h_checkout, (params->deform_a > 0.0 ? c.preal : (double)c.p) * pscale, &rep,
+                              n, wref);
             nnz = ctx->h_nnz[0];
             Bump tmp = rest;
             int32_t *d_col = tmp.take<int32_t>((size_t)std::max<int64_t>(nnz, 1));

@@ -335,10 +335,9 @@ sk_status sk::check_params(sk_ctx *ctx, const sk_params *p, bool real) {
     if (p->prescale != 0 && p->prescale != 1) return fail(ctx, SK_EINVAL, "prescale must be 0 or 1");
     if (!real && p->prescale)
         return fail(ctx, SK_EINVAL, "prescaling needs real-valued weights (sk_scale_real / sk_solve_real)");
-    if (real && (p->storage != SK_W_I16 || p->fused || p->deform_a > 0.0 || p->method != SK_SINKHORN))
+    if (real && (p->storage != SK_W_I16 || p->fused || p->method != SK_SINKHORN))
         return fail(ctx, SK_EINVAL,
-                    "real-valued weights run the two-sweep Sinkhorn iteration on W (storage 0, not fused, "
-                    "not deformed)");
+                    "real-valued weights run the two-sweep Sinkhorn iteration on W (storage 0, not fused)");
     return SK_OK;
 }
 

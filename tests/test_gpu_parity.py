@@ -528,7 +528,7 @@ def test_deformed_fixed_iterations_match_oracle(ctx, n, a, pmax, iters):
     res = ctx.scale(dev(W), prm)
     assert res.status == sk.SK_ENOCONV
     assert res.report["iters_total"] == iters
-    lu_o, lv_o, m, p, _ = oracle.deformed(B, a, 1, pmax, 0.0, iters)
+    lu_o, lv_o, m, p, _ = oracle.deformed(B, a, 1, pmax, 0.0, iters, integer_p=True)
     assert m == iters and res.report["p_final"] == p
     lu, lv = sk.split_potentials(res.potentials, n)
     Xg = p * B + lu[:, None] + lv[None, :]
@@ -546,7 +546,7 @@ def test_deformed_planted_solve(ctx):
     B = oracle.log_weights(W)
     prm = sk.make_params([1, 16], tol=1e-6, max_iters=5000, threshold=1e-4, deform_a=3.0)
     out = ctx.solve(dev(W), prm)
-    _, _, m, p, res = oracle.deformed(B, 3.0, 1, 16, 1e-6, 5000)
+    _, _, m, p, res = oracle.deformed(B, 3.0, 1, 16, 1e-6, 5000, integer_p=True)
     assert out["status"] == sk.SK_OK and out["report"]["p_final"] == p == 16
     assert out["report"]["iters_total"] == m
     assert out["weight"] == 1050 * n and (out["perm"] == sigma).all()

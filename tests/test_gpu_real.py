@@ -190,3 +190,49 @@ def test_real_errors(ctx):
     with pytest.raises(sk.SkError) as e:
         ctx.scale_real(dev(W), sk.make_params([100], storage="bf16"))
     assert e.value.status == sk.SK_EINVAL
+
+
+@pytest.mark.parametrize("kind,n", [("rand", 200), ("euclid", 257)])
+def test_real_deformed_schedule_matches_oracle(ctx, kind, n):
+    """The deformed iteration (Section 3.2) on real-valued weights runs the
+    paper's schedule p_m = a log(m + 1) unrounded: after 30 iterations with
+    a = 8 (p_30 = 8 ln 31, below the cap 40) X matches the oracle's iterate
+    under that schedule entry by entry, and differs from the one under the
+    schedule rounded to integers (the int16 path's reading)."""
+    W = WORKLOADS[kind](n, 5)
+    B = W.astype(np.float64)
+    a, pmax, iters = 8.0, 40, 30
+    prm = sk.make_params([1, pmax], tol=0.0, max_iters=iters, check_every=8, deform_a=a)
+    res = ctx.scale_real(dev(W), prm)
+    assert res.report["iters_total"] == iters
+    p = oracle.deformed_p(a, 1, pmax, iters)
+    assert p == pytest.approx(a * math.log(iters + 1))
+    lu, lv = sk.split_potentials(res.potentials, n)
+    wref = float(W[np.isfinite(W)].max())
+    ub_g, vb_g = lu / p - wref, lv / p
+    lu_o, lv_o, m, p_o, _ = oracle.deformed(B, a, 1, pmax, 0.0, iters)
+    assert m == iters and p_o == p
+    Lg = p * (B + ub_g[:, None] + vb_g[None, :])
+    Lo = p * B + lu_o[:, None] + lv_o[None, :]
+    sig = Lo > np.log(1e-6)
+    assert np.abs(Lg[sig] - Lo[sig]).max() < 1e-4
+    lu_i, lv_i, _, p_i, _ = oracle.deformed(B, a, 1, pmax, 0.0, iters, integer_p=True)
+    assert p_i == round(p)
+    Li = p_i * B + lu_i[:, None] + lv_i[None, :]
+    assert np.abs(np.exp(Li) - np.exp(Lo)).max() > 1e-3
+
+
+def test_real_deformed_stops_at_last_p(ctx):
+    """Stops at the first iterate computed at the last p whose residual is
+    below tol, at the oracle's iteration (within one at a borderline stop)."""
+    n = 200
+    W = WORKLOADS["rand"](n, 9)
+    B = W.astype(np.float64)
+    a, pmax, tol = 6.0, 30, 1e-5
+    prm = sk.make_params([1, pmax], tol=tol, max_iters=20000, check_every=16, deform_a=a)
+    res = ctx.scale_real(dev(W), prm)
+    assert res.status == sk.SK_OK
+    _, _, m, p_o, r = oracle.deformed(B, a, 1, pmax, tol, 20000)
+    assert p_o == pmax and r < tol
+    assert abs(res.report["iters_total"] - m) <= 1
+    assert res.report["residual_fp64"] <= 1e-5 + 1e-6

@@ -422,13 +422,24 @@ def test_deformed_constant_p_reproduces_worked_example():
     assert np.abs(X - fx["X"]).max() <= 5e-8
 
 
-def _deformed_state(B, a, pmin, pmax, m):
-    lu, lv, m2, p, _ = oracle.deformed(B, a, pmin, pmax, 0.0, m)
-    assert m2 == m and p == oracle.deformed_p(a, pmin, pmax, m)
+def _deformed_state(B, a, pmin, pmax, m, integer_p):
+    lu, lv, m2, p, _ = oracle.deformed(B, a, pmin, pmax, 0.0, m, integer_p)
+    assert m2 == m and p == oracle.deformed_p(a, pmin, pmax, m, integer_p)
     return lu, lv
 
 
-def test_deformed_hadamard_identity():
+def test_deformed_schedule():
+    """p_m = a log(m + 1) kept in [p_min, p_max] (Theorem
+    logconvergencepositive), unrounded; rounded half to even with integer_p."""
+    assert oracle.deformed_p(3.0, 1, 16, 1) == pytest.approx(3.0 * math.log(2.0), abs=0.0)
+    assert oracle.deformed_p(0.1, 1, 16, 1) == 1
+    assert oracle.deformed_p(3.0, 1, 16, 10**6) == 16
+    assert oracle.deformed_p(3.0, 1, 16, 1, integer_p=True) == 2  # round(2.079)
+    assert oracle.deformed_p(2.0 / math.log(2.0), 1, 16, 1, integer_p=True) == 2
+
+
+@pytest.mark.parametrize("integer_p", [False, True])
+def test_deformed_hadamard_identity(integer_p):
     """Section 3.2, proposition on the iterates: with W_m = diag(u_m) A^(p_m)
     diag(v_m) and Z_m = diag(u_{m+1}) A^(p_{m+1}) diag(v_m),
     Z_m = ROWS(W_m o A^(p_{m+1} - p_m)), checked across steps where p changes."""
@@ -438,10 +449,10 @@ def test_deformed_hadamard_identity():
     a, pmin, pmax = 2.0, 1, 9
     changed = 0
     for m in range(1, 14):
-        pm, pm1 = (oracle.deformed_p(a, pmin, pmax, k) for k in (m, m + 1))
+        pm, pm1 = (oracle.deformed_p(a, pmin, pmax, k, integer_p) for k in (m, m + 1))
         changed += pm1 != pm
-        lu_m, lv_m = _deformed_state(B, a, pmin, pmax, m)
-        lu_n, _ = _deformed_state(B, a, pmin, pmax, m + 1)
+        lu_m, lv_m = _deformed_state(B, a, pmin, pmax, m, integer_p)
+        lu_n, _ = _deformed_state(B, a, pmin, pmax, m + 1, integer_p)
         Wm = np.exp(pm * B + lu_m[:, None] + lv_m[None, :])
         Zm = np.exp(pm1 * B + lu_n[:, None] + lv_m[None, :])
         H = Wm * A ** (pm1 - pm)
@@ -450,7 +461,8 @@ def test_deformed_hadamard_identity():
     assert changed >= 3
 
 
-def test_deformed_permutation_ratio():
+@pytest.mark.parametrize("integer_p", [False, True])
+def test_deformed_permutation_ratio(integer_p):
     """Section 3.2: for permutations sigma, pi of A,
     w_sigma(Z_m) / w_pi(Z_m) = (w_sigma(A) / w_pi(A))^(p_{m+1}), by enumeration
     of all permutations of a 4 x 4 matrix."""
@@ -460,9 +472,9 @@ def test_deformed_permutation_ratio():
     a, pmin, pmax = 3.0, 1, 12
     perms = list(itertools.permutations(range(4)))
     for m in (1, 4, 9):
-        pm1 = oracle.deformed_p(a, pmin, pmax, m + 1)
-        _, lv_m = _deformed_state(B, a, pmin, pmax, m)
-        lu_n, _ = _deformed_state(B, a, pmin, pmax, m + 1)
+        pm1 = oracle.deformed_p(a, pmin, pmax, m + 1, integer_p)
+        _, lv_m = _deformed_state(B, a, pmin, pmax, m, integer_p)
+        lu_n, _ = _deformed_state(B, a, pmin, pmax, m + 1, integer_p)
         logZ = pm1 * B + lu_n[:, None] + lv_m[None, :]
         s0 = perms[0]
         for q in perms[1:]:
@@ -471,13 +483,14 @@ def test_deformed_permutation_ratio():
             assert abs(lhs - rhs) < 1e-10
 
 
-def test_deformed_planted_converges_to_permutation():
+@pytest.mark.parametrize("integer_p", [False, True])
+def test_deformed_planted_converges_to_permutation(integer_p):
     """Theorem optimalassign: the limit's support is the optimal permutation
     (planted, unique); its weight is the closed form 1050 n."""
     n = 32
     W, sigma = skgen.planted(n, 3)
     B = oracle.log_weights(W)
-    lu, lv, m, p, res = oracle.deformed(B, 3.0, 1, 16, 1e-9, 5000)
+    lu, lv, m, p, res = oracle.deformed(B, 3.0, 1, 16, 1e-9, 5000, integer_p)
     X = np.exp(p * B + lu[:, None] + lv[None, :])
     assert p == 16 and res < 1e-9
     assert np.abs(X[np.arange(n), sigma] - 1.0).max() < 1e-6
@@ -512,18 +525,36 @@ def test_newton_worked_example():
     assert np.abs(X - fx["X"]).max() < 1e-4
 
 
-def test_newton_equals_sinkhorn_limit():
+@pytest.mark.parametrize("norm", ["two", "inf"])
+def test_newton_equals_sinkhorn_limit(norm):
     """X(p) is unique (Section 2.1): Newton and a converged Sinkhorn
-    iteration give the same matrix; Newton needs far fewer products with A."""
+    iteration give the same matrix; Newton needs far fewer products with A.
+    Under either stopping norm (2-norm of the cited method, max-norm)."""
     W = skgen.uniform_weights(64, 0, 100, seed=2)
     B = oracle.log_weights(W)
     ub0 = -B.max(axis=1)
-    ub, vb, outer, prods, res = oracle.newton(B, 1.0, 1e-11, 5000, ubar=ub0)
+    ub, vb, outer, prods, res = oracle.newton(B, 1.0, 1e-11, 5000, ubar=ub0, norm=norm)
     us, vs, m, r2 = oracle.sinkhorn(B, 1.0, 1e-13, 200000, ub0, None)
     assert res < 1e-10 and r2 < 1e-13
     Xn, Xs = oracle.scaled_matrix(B, 1.0, ub, vb), oracle.scaled_matrix(B, 1.0, us, vs)
     assert np.abs(Xn - Xs).max() < 1e-10
     assert prods < m / 4
+
+
+def test_newton_stopping_norms():
+    """The 2-norm stop is the stricter one (|r|_inf <= |r|_2): at the same
+    loose tolerance it takes at least as many products and ends with
+    |1 - x o (S x)|_2 <= tol, while the max-norm stop ends with
+    max |row or column sum - 1| <= tol."""
+    W = skgen.uniform_weights(256, 0, 100, seed=4)
+    B = oracle.log_weights(W)
+    ub0 = -B.max(axis=1)
+    tol = 1e-4
+    u2, v2, _, prods2, _ = oracle.newton(B, 1.0, tol, 5000, ubar=ub0, norm="two")
+    ui, vi, _, prodsi, resi = oracle.newton(B, 1.0, tol, 5000, ubar=ub0, norm="inf")
+    assert prods2 >= prodsi and resi <= tol
+    rs, cs = oracle.sums(B, 1.0, u2, v2)
+    assert math.sqrt(float(((rs - 1) ** 2).sum() + ((cs - 1) ** 2).sum())) <= tol
 
 
 # ---------------------------------------------------------------- real log-weights
