@@ -247,7 +247,7 @@ hipError_t launch_row_sweep_short(const Inst *d_insts, const RowUnit *d_units, i
                                   hipStream_t st, hipEvent_t stop = nullptr);
 hipError_t set_row_sweep_short_attributes();
 hipError_t launch_col_sweep(const Inst *d_insts, const ColUnit *d_units, int nunits, int grid,
-                            int nt_loads, hipStream_t st, hipEvent_t stop = nullptr);
+                            int nt_loads, int short_rows, hipStream_t st, hipEvent_t stop = nullptr);
 hipError_t launch_nt_product(const Inst *d_insts, const RowUnit *d_rows, int nrows, int row_grid,
                              size_t row_lds, const ColUnit *d_cols, int ncols, int col_grid,
                              const NtCtl *nt, NtVec vec, int n, int nt_loads, hipStream_t st);

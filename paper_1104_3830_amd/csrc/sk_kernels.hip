@@ -155,90 +155,102 @@ struct alignas(8) RowPot {
     float r;
 };
 
-template <bool SENT, bool V8, bool NT>
-__device__ __forceinline__ void col_partial(const Inst &I, int tile, int r0, int r1, int wave,
-                                            int lane, const RowPot *__restrict__ rowpot,
-                                            const float *__restrict__ tab, float (&acc)[8]) {
+// Start of a lane's 8 columns of a tile (c0 < n): their 4 G_j in A
+// (kPadExp4 for padding columns) and the wave's first row of the segment,
+// requested now and used by col_partial_v8.
+template <bool NT>
+__device__ __forceinline__ void col_tile_start(const Inst &I, int c0, int r0, int r1, int wave, int (&A)[8],
+                                               int4 &first) {
     const int n = I.n;
-    const int p4 = 4 * I.ctl->p;
-#pragma unroll
-    for (int c = 0; c < 8; ++c) acc[c] = 0.f;
-    if (V8) {
-        const int c0 = tile * kColTile8 + lane * 8;
-        if (c0 >= n) return;
-        int A[8];  // padding columns (c0 + c >= n) add exactly 0 and are not written
-        if (c0 + 8 <= n) {
-            const int4 g0 = *reinterpret_cast<const int4 *>(I.G + c0);
-            const int4 g1 = *reinterpret_cast<const int4 *>(I.G + c0 + 4);
-            A[0] = 4 * g0.x; A[1] = 4 * g0.y; A[2] = 4 * g0.z; A[3] = 4 * g0.w;
-            A[4] = 4 * g1.x; A[5] = 4 * g1.y; A[6] = 4 * g1.z; A[7] = 4 * g1.w;
-        } else {
-#pragma unroll
-            for (int c = 0; c < 8; ++c) A[c] = c0 + c < n ? 4 * I.G[c0 + c] : kPadExp4;
-        }
-        const int16_t *base = I.W + c0;
-        const int64_t pitch = I.pitch;
-        auto body = [&](const int4 v, const RowPot rp) {
-            int w[8];
-            unpack8i(v, w);
-#pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                float e = tab_at(tab, tab_off(p4, w[c], A[c], rp.b));
-                if (SENT) e = (w[c] == SK_SENTINEL) ? 0.f : e;
-                acc[c] = fmaf(e, rp.r, acc[c]);
-            }
-        };
-        int r = r0 + wave;
-        constexpr int S = kColWaves;
-        constexpr int U = kColLoads;
-        // two register buffers: the next U rows are requested before the
-        // current U are used, so loads stay in flight during the arithmetic
-        // (rows are still added in order)
-        auto ld = [&](int4 (&v)[U], int rr) {
-#pragma unroll
-            for (int k = 0; k < U; ++k)
-                v[k] = gload<NT>(reinterpret_cast<const int4 *>(base + (int64_t)(rr + k * S) * pitch));
-        };
-        auto use = [&](const int4 (&v)[U], int rr) {
-#pragma unroll
-            for (int k = 0; k < U; ++k) body(v[k], rowpot[rr + k * S - r0]);
-        };
-        if (r + (U - 1) * S < r1) {
-            int4 va[U], vb[U];
-            ld(va, r);
-            for (;;) {
-                const int r2 = r + U * S;
-                const bool more = r2 + (U - 1) * S < r1;
-                if (more) ld(vb, r2);
-                use(va, r);
-                r = r2;
-                if (!more) break;
-                const int r3 = r + U * S;
-                const bool more2 = r3 + (U - 1) * S < r1;
-                if (more2) ld(va, r3);
-                use(vb, r);
-                r = r3;
-                if (!more2) break;
-            }
-        }
-        for (; r < r1; r += S) body(gload<NT>(reinterpret_cast<const int4 *>(base + (int64_t)r * pitch)),
-                                    rowpot[r - r0]);
+    first = make_int4(0, 0, 0, 0);
+    if (r0 + wave < r1)
+        first = gload<NT>(reinterpret_cast<const int4 *>(I.W + c0 + (int64_t)(r0 + wave) * I.pitch));
+    if (c0 + 8 <= n) {
+        const int4 g0 = *reinterpret_cast<const int4 *>(I.G + c0);
+        const int4 g1 = *reinterpret_cast<const int4 *>(I.G + c0 + 4);
+        A[0] = 4 * g0.x; A[1] = 4 * g0.y; A[2] = 4 * g0.z; A[3] = 4 * g0.w;
+        A[4] = 4 * g1.x; A[5] = 4 * g1.y; A[6] = 4 * g1.z; A[7] = 4 * g1.w;
     } else {
-        const int c0 = tile * kColTile1 + lane;
-        if (c0 >= n) return;
-        const int A = 4 * I.G[c0];
-        for (int r = r0 + wave; r < r1; r += kColWaves) {
-            const RowPot rp = rowpot[r - r0];
-            const int w = (int)gload<NT>(I.W + (int64_t)r * I.pitch + c0);
-            float e = tab_at(tab, tab_off(p4, w, A, rp.b));
-            if (SENT) e = (w == SK_SENTINEL) ? 0.f : e;
-            acc[0] = fmaf(e, rp.r, acc[0]);
-        }
+#pragma unroll
+        for (int c = 0; c < 8; ++c) A[c] = c0 + c < n ? 4 * I.G[c0 + c] : kPadExp4;
     }
 }
 
-template <bool NT>
-__global__ __launch_bounds__(kColWaves * kWave) void k_col_sweep(const Inst *__restrict__ insts,
+// Column sums of one (512-column tile, row segment) unit over 8-wide rows.
+// A: the lane's 4 G_j (kPadExp4 for padding columns); first: the wave's
+// first row of the tile, already requested by the caller.
+template <bool SENT, bool NT>
+__device__ __forceinline__ void col_partial_v8(const Inst &I, int p4, int c0, int r0, int r1, int wave,
+                                               const int (&A)[8], int4 first, const RowPot *__restrict__ rowpot,
+                                               const float *__restrict__ tab, float (&acc)[8]) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc[c] = 0.f;
+    const int16_t *base = I.W + c0;
+    const int64_t pitch = I.pitch;
+    auto body = [&](const int4 v, const RowPot rp) {
+        int w[8];
+        unpack8i(v, w);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            float e = tab_at(tab, tab_off(p4, w[c], A[c], rp.b));
+            if (SENT) e = (w[c] == SK_SENTINEL) ? 0.f : e;
+            acc[c] = fmaf(e, rp.r, acc[c]);
+        }
+    };
+    constexpr int S = kColWaves;
+    int r = r0 + wave;
+    if (r >= r1) return;
+    // two register buffers: the next row is requested before the current one
+    // is used, so a load stays in flight during the arithmetic (rows are
+    // still added in order)
+    int4 va = first, vb;
+    for (;;) {
+        const int r2 = r + S;
+        const bool more = r2 < r1;
+        if (more) vb = gload<NT>(reinterpret_cast<const int4 *>(base + (int64_t)r2 * pitch));
+        body(va, rowpot[r - r0]);
+        r = r2;
+        if (!more) break;
+        const int r3 = r + S;
+        const bool more2 = r3 < r1;
+        if (more2) va = gload<NT>(reinterpret_cast<const int4 *>(base + (int64_t)r3 * pitch));
+        body(vb, rowpot[r - r0]);
+        r = r3;
+        if (!more2) break;
+    }
+}
+
+// The same over a W without the 8-wide layout: one column per lane.
+template <bool SENT, bool NT>
+__device__ __forceinline__ void col_partial_v1(const Inst &I, int p4, int tile, int r0, int r1, int wave,
+                                               int lane, const RowPot *__restrict__ rowpot,
+                                               const float *__restrict__ tab, float &acc) {
+    acc = 0.f;
+    const int n = I.n;
+    const int c0 = tile * kColTile1 + lane;
+    if (c0 >= n) return;
+    const int A = 4 * I.G[c0];
+    for (int r = r0 + wave; r < r1; r += kColWaves) {
+        const RowPot rp = rowpot[r - r0];
+        const int w = (int)gload<NT>(I.W + (int64_t)r * I.pitch + c0);
+        float e = tab_at(tab, tab_off(p4, w, A, rp.b));
+        if (SENT) e = (w == SK_SENTINEL) ? 0.f : e;
+        acc = fmaf(e, rp.r, acc);
+    }
+}
+
+// Row potentials a workgroup thread stages per unit: seg_rows <= kMaxSegRows.
+constexpr int kColStage = kMaxSegRows / (kColWaves * kWave);
+
+// EARLY (launches whose largest instance has long rows): every load of a
+// unit that does not depend on the controller goes out before it is read:
+// the wave's first row of the tile, the tile's column potentials, and the
+// segment's row potentials of both parities (the parity comes from the
+// controller); so the unit's start costs one memory round trip instead of a
+// chain of dependent ones. Batches of short rows keep the registers this
+// takes (20 per thread) for resident waves, and load at the unit.
+template <bool NT, bool EARLY>
+__global__ __launch_bounds__(kColWaves * kWave, EARLY ? 1 : 6) void k_col_sweep(const Inst *__restrict__ insts,
                                                                    const ColUnit *__restrict__ units,
                                                                    int nunits) {
     __shared__ float red[kColWaves][kColTile8];
@@ -247,6 +259,7 @@ __global__ __launch_bounds__(kColWaves * kWave) void k_col_sweep(const Inst *__r
     __shared__ float wmax[kColWaves];
     __shared__ float rowres_max;
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    constexpr int NTH = kColWaves * kWave;
     int u0, u1;
     unit_range(nunits, u0, u1);
     fill_exp_table(tab);
@@ -254,34 +267,75 @@ __global__ __launch_bounds__(kColWaves * kWave) void k_col_sweep(const Inst *__r
         const ColUnit un = units[u];
         const Inst &I = insts[un.inst];
         Ctl *ctl = I.ctl;
-        if (ctl->state != ST_RUNNING) continue;
         const int n = I.n;
-        const int npar = (ctl->iter + 1) & 1;  // row potentials written by this iteration's row sweep
         const int tc = I.tile_cols;
         const int ctile0 = un.tile * tc;
         const int ncols = min(tc, n - ctile0);
         const int r0 = un.seg * I.seg_rows, r1 = min(n, r0 + I.seg_rows);
+        const bool v8 = I.vec8 != 0;
+        const bool tile0 = un.tile == 0;
+        const int c0 = un.tile * kColTile8 + lane * 8;
+        int4 first;
+        int A[8];
+        int sF[2][kColStage];
+        float sP[2][kColStage], sR[kColStage];
+        if constexpr (EARLY) {
+            if (v8 && c0 < n) col_tile_start<NT>(I, c0, r0, r1, wave, A, first);
+#pragma unroll
+            for (int k = 0; k < kColStage; ++k) {
+                const int r = r0 + (int)threadIdx.x + k * NTH;
+                if (r < r1) {
+                    sF[0][k] = I.F[0][r];
+                    sF[1][k] = I.F[1][r];
+                    sP[0][k] = I.phi[0][r];
+                    sP[1][k] = I.phi[1][r];
+                    sR[k] = tile0 ? I.rres[r] : 0.f;
+                }
+            }
+        }
+        float rres_w = 0.f;
+        if (EARLY && wave == 0) rres_w = __uint_as_float(I.rowres[lane * kRowResStride]);
+        if (ctl->state != ST_RUNNING) continue;
+        if (!EARLY && wave == 0) rres_w = __uint_as_float(I.rowres[lane * kRowResStride]);
+        const int iter = ctl->iter;
+        const int npar = (iter + 1) & 1;  // row potentials written by this iteration's row sweep
+        const int p4 = 4 * ctl->p;
+        const bool sent = ctl->sent != 0u;
         __syncthreads();
         float rm = 0.f;
-        for (int r = r0 + (int)threadIdx.x; r < r1; r += blockDim.x) {
-            RowPot k;
-            k.b = 4 * (I.F[npar][r] - kTabLo);
-            k.r = ex2(I.phi[npar][r] * kLog2e);
-            rowpot[r - r0] = k;
-            if (un.tile == 0) rm = fmaxf(rm, I.rres[r]);
+        if constexpr (EARLY) {
+#pragma unroll
+            for (int k = 0; k < kColStage; ++k) {
+                const int r = r0 + (int)threadIdx.x + k * NTH;
+                if (r < r1) {
+                    RowPot kk;
+                    kk.b = 4 * ((npar ? sF[1][k] : sF[0][k]) - kTabLo);
+                    kk.r = ex2((npar ? sP[1][k] : sP[0][k]) * kLog2e);
+                    rowpot[r - r0] = kk;
+                    rm = fmaxf(rm, sR[k]);
+                }
+            }
+        } else {
+            for (int r = r0 + (int)threadIdx.x; r < r1; r += NTH) {
+                RowPot kk;
+                kk.b = 4 * (I.F[npar][r] - kTabLo);
+                kk.r = ex2(I.phi[npar][r] * kLog2e);
+                rowpot[r - r0] = kk;
+                if (tile0) rm = fmaxf(rm, I.rres[r]);
+            }
         }
-        if (un.tile == 0) {
+        if (tile0) {
             // residual slot of this row segment (read by the finalise kernel)
             rm = wave_max(rm);
             if (lane == 0) wmax[wave] = rm;
         }
         if (wave == 0) {
             // the row sweep's residual (see k_row_sweep)
-            const float rr = wave_max(__uint_as_float(I.rowres[lane * kRowResStride]));
+            const float rr = wave_max(rres_w);
             if (lane == 0) rowres_max = rr;
         }
         __syncthreads();
-        if (un.tile == 0 && threadIdx.x == 0) {
+        if (tile0 && threadIdx.x == 0) {
             float m = wmax[0];
 #pragma unroll
             for (int w2 = 1; w2 < kColWaves; ++w2) m = fmaxf(m, wmax[w2]);
@@ -289,18 +343,21 @@ __global__ __launch_bounds__(kColWaves * kWave) void k_col_sweep(const Inst *__r
         }
         // the row sweep measured a converged iterate: the finalise will end
         // the stage without a column step, so no column sums are needed
-        if (ctl->iter >= 1 && rowres_max < I.tol && deform_settled(I, ctl)) continue;
-        float acc[8];
-        const bool sent = ctl->sent != 0u;
-        if (I.vec8) {
-            if (sent) col_partial<true, true, NT>(I, un.tile, r0, r1, wave, lane, rowpot, tab, acc);
-            else col_partial<false, true, NT>(I, un.tile, r0, r1, wave, lane, rowpot, tab, acc);
+        if (iter >= 1 && rowres_max < I.tol && deform_settled(I, ctl)) continue;
+        if (v8) {
+            float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            if (c0 < n) {
+                if constexpr (!EARLY) col_tile_start<NT>(I, c0, r0, r1, wave, A, first);
+                if (sent) col_partial_v8<true, NT>(I, p4, c0, r0, r1, wave, A, first, rowpot, tab, acc);
+                else col_partial_v8<false, NT>(I, p4, c0, r0, r1, wave, A, first, rowpot, tab, acc);
+            }
 #pragma unroll
             for (int c = 0; c < 8; ++c) red[wave][lane * 8 + c] = acc[c];
         } else {
-            if (sent) col_partial<true, false, NT>(I, un.tile, r0, r1, wave, lane, rowpot, tab, acc);
-            else col_partial<false, false, NT>(I, un.tile, r0, r1, wave, lane, rowpot, tab, acc);
-            red[wave][lane] = acc[0];
+            float acc;
+            if (sent) col_partial_v1<true, NT>(I, p4, un.tile, r0, r1, wave, lane, rowpot, tab, acc);
+            else col_partial_v1<false, NT>(I, p4, un.tile, r0, r1, wave, lane, rowpot, tab, acc);
+            red[wave][lane] = acc;
         }
         __syncthreads();
         float *dst = I.colpart + (int64_t)un.seg * n + ctile0;
@@ -1375,16 +1432,24 @@ __global__ __launch_bounds__(kColWaves * kWave) void k_nt_cols(const Inst *__res
             rowpot[r - r0] = k;
         }
         __syncthreads();
-        float acc[8];
+        const int p4 = 4 * I.ctl->p;
         if (I.vec8) {
-            if (sent) col_partial<true, true, NT>(I, un.tile, r0, r1, wave, lane, rowpot, tab, acc);
-            else col_partial<false, true, NT>(I, un.tile, r0, r1, wave, lane, rowpot, tab, acc);
+            float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            const int c0 = un.tile * kColTile8 + lane * 8;
+            if (c0 < n) {
+                int A[8];
+                int4 first;
+                col_tile_start<NT>(I, c0, r0, r1, wave, A, first);
+                if (sent) col_partial_v8<true, NT>(I, p4, c0, r0, r1, wave, A, first, rowpot, tab, acc);
+                else col_partial_v8<false, NT>(I, p4, c0, r0, r1, wave, A, first, rowpot, tab, acc);
+            }
 #pragma unroll
             for (int c = 0; c < 8; ++c) red[wave][lane * 8 + c] = acc[c];
         } else {
-            if (sent) col_partial<true, false, NT>(I, un.tile, r0, r1, wave, lane, rowpot, tab, acc);
-            else col_partial<false, false, NT>(I, un.tile, r0, r1, wave, lane, rowpot, tab, acc);
-            red[wave][lane] = acc[0];
+            float acc;
+            if (sent) col_partial_v1<true, NT>(I, p4, un.tile, r0, r1, wave, lane, rowpot, tab, acc);
+            else col_partial_v1<false, NT>(I, p4, un.tile, r0, r1, wave, lane, rowpot, tab, acc);
+            red[wave][lane] = acc;
         }
         __syncthreads();
         float *dst = I.colpart + (int64_t)un.seg * n + ctile0;
@@ -1726,13 +1791,21 @@ hipError_t launch_row_sweep(const Inst *d_insts, const RowUnit *d_units, int nun
     return hipGetLastError();
 }
 hipError_t launch_col_sweep(const Inst *d_insts, const ColUnit *d_units, int nunits, int grid,
-                            int nt_loads, hipStream_t st, hipEvent_t stop) {
-    if (nt_loads)
-        launch_stamped(k_col_sweep<true>, dim3(grid), dim3(kColWaves * kWave), 0, st, stop, d_insts,
+                            int nt_loads, int short_rows, hipStream_t st, hipEvent_t stop) {
+    if (short_rows) {
+        if (nt_loads)
+            launch_stamped(k_col_sweep<true, false>, dim3(grid), dim3(kColWaves * kWave), 0, st, stop, d_insts,
+                           d_units, nunits);
+        else
+            launch_stamped(k_col_sweep<false, false>, dim3(grid), dim3(kColWaves * kWave), 0, st, stop, d_insts,
+                           d_units, nunits);
+    } else if (nt_loads) {
+        launch_stamped(k_col_sweep<true, true>, dim3(grid), dim3(kColWaves * kWave), 0, st, stop, d_insts,
                        d_units, nunits);
-    else
-        launch_stamped(k_col_sweep<false>, dim3(grid), dim3(kColWaves * kWave), 0, st, stop, d_insts,
+    } else {
+        launch_stamped(k_col_sweep<false, true>, dim3(grid), dim3(kColWaves * kWave), 0, st, stop, d_insts,
                        d_units, nunits);
+    }
     return hipGetLastError();
 }
 hipError_t launch_col_finalize(const Inst *d_insts, const FinUnit *d_units, int nunits, int grid,

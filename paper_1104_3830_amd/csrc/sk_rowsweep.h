@@ -177,15 +177,49 @@ __device__ __forceinline__ int row_max_v1(const int16_t *__restrict__ wr, int n,
     return m;
 }
 
+// What a row step reads from its instance besides W: none of it changes
+// during a launch (the controller moves the iterate on between launches), so
+// the row sweep loads it once per instance and a row's start waits on no
+// chain of dependent loads (unit -> instance -> controller -> potentials).
+// The potentials are global-address-space pointers: their loads then count
+// only against the vector-memory counter, so that a row's LDS reads never
+// wait for the next row's potentials in flight.
+struct RowCtx {
+    const int16_t *W;
+    int64_t pitch;
+    const SK_GLOBAL int32_t *F;  // current iterate
+    const SK_GLOBAL float *phi;
+    SK_GLOBAL int32_t *Fn;       // next iterate
+    SK_GLOBAL float *phin;
+    SK_GLOBAL float *rres;
+    Ctl *ctl;
+    int n, p4;
+};
+
+__device__ __forceinline__ RowCtx row_ctx(const Inst &I, int par) {
+    RowCtx c;
+    c.W = I.W;
+    c.pitch = I.pitch;
+    c.F = (const SK_GLOBAL int32_t *)(par ? I.F[1] : I.F[0]);
+    c.phi = (const SK_GLOBAL float *)(par ? I.phi[1] : I.phi[0]);
+    c.Fn = (SK_GLOBAL int32_t *)(par ? I.F[0] : I.F[1]);
+    c.phin = (SK_GLOBAL float *)(par ? I.phi[0] : I.phi[1]);
+    c.rres = (SK_GLOBAL float *)I.rres;
+    c.ctl = I.ctl;
+    c.n = I.n;
+    c.p4 = 4 * I.ctl->p;
+    return c;
+}
+
 // Completes the row step of `row` from its sum S relative to the previous
 // iterate (shift 0): the exact max-shifted recompute if S left the safe
 // range, then the new potentials and the residual.
 template <bool SENT, bool V8, bool NT, class CP>
-__device__ __forceinline__ float row_finish(const Inst &I, int row, int par, int lane, int Fi,
-                                            float phi, float S, CP cp, const float *__restrict__ tab) {
+__device__ __forceinline__ float row_finish(const RowCtx &I, int row, int lane, int Fi, float phi, float S,
+                                            CP cp, const float *__restrict__ tab) {
     const int n = I.n;
     const int16_t *wr = I.W + (int64_t)row * I.pitch;
-    const int p4 = 4 * I.ctl->p;
+    const int p4 = I.p4;
     int M = 0;
     if (!(S >= kSafeLo && S <= kSafeHi)) {
         // exact max-shift (Section 4.1.2): M = max_j (p w_ij + F_i + G_j)
@@ -207,8 +241,8 @@ __device__ __forceinline__ float row_finish(const Inst &I, int row, int par, int
         const float l2S = lg2(S);
         const float phin = -l2S * kLn2;
         const float k = rintf(phin);
-        I.F[par ^ 1][row] = Fi - M + (int)k;
-        I.phi[par ^ 1][row] = phin - k;
+        I.Fn[row] = Fi - M + (int)k;
+        I.phin[row] = phin - k;
         // r_i = exp(phi_i + M) S: row sum of the current iterate
         const float r = ex2(fmaf(phi + (float)M, kLog2e, l2S));
         const float res = fabsf(r - 1.f);
@@ -218,19 +252,16 @@ __device__ __forceinline__ float row_finish(const Inst &I, int row, int par, int
     return 0.f;
 }
 
+// Fi, phi: the row's potentials, loaded by the caller ahead of the row.
 template <bool SENT, bool V8, bool NT, class CP>
-__device__ __forceinline__ float row_step_one(const Inst &I, int row, int par, int lane, CP cp,
+__device__ __forceinline__ float row_step_one(const RowCtx &I, int row, int lane, int Fi, float phi, CP cp,
                                              const float *__restrict__ tab) {
     const int n = I.n;
     const int16_t *wr = I.W + (int64_t)row * I.pitch;
-    const int Fi = I.F[par][row];
-    // loaded with F_i so that the end of the row does not wait for it
-    const float phi = I.phi[par][row];
-    const int p4 = 4 * I.ctl->p;
-    float S = V8 ? row_partial_v8<SENT, NT>(wr, n, p4, 4 * (Fi - kTabLo), cp, tab, lane)
-                 : row_partial_v1<SENT, NT>(wr, n, p4, 4 * (Fi - kTabLo), cp, tab, lane);
+    float S = V8 ? row_partial_v8<SENT, NT>(wr, n, I.p4, 4 * (Fi - kTabLo), cp, tab, lane)
+                 : row_partial_v1<SENT, NT>(wr, n, I.p4, 4 * (Fi - kTabLo), cp, tab, lane);
     S = wave_sum(S);
-    return row_finish<SENT, V8, NT>(I, row, par, lane, Fi, phi, S, cp, tab);
+    return row_finish<SENT, V8, NT>(I, row, lane, Fi, phi, S, cp, tab);
 }
 
 // Rows above kLdsMaxN (column entries from the packed global buffer): a wave
@@ -389,7 +420,8 @@ __global__ __launch_bounds__(kRowWaves * kWave, MINW) void k_row_sweep(const Ins
         const Inst &I = insts[0];
         Ctl *ctl = I.ctl;
         if (ctl->state == ST_RUNNING && I.vec8) {
-            const int n = I.n, par = ctl->iter & 1, p4 = 4 * ctl->p;
+            const RowCtx rc = row_ctx(I, ctl->iter & 1);
+            const int n = rc.n, p4 = rc.p4;
             const bool sent = ctl->sent != 0u;
             cur = 0;
             for (int u = u0; u < u1; u += kMultiRows) {
@@ -403,9 +435,9 @@ __global__ __launch_bounds__(kRowWaves * kWave, MINW) void k_row_sweep(const Ins
                     row[k] = u + k < u1 ? units[u + k].row0 + wave : n;
                     act[k] = row[k] < n;
                     const int rr = act[k] ? row[k] : 0;
-                    wr[k] = I.W + (int64_t)rr * I.pitch;
-                    Fi[k] = I.F[par][rr];
-                    phi[k] = I.phi[par][rr];
+                    wr[k] = rc.W + (int64_t)rr * rc.pitch;
+                    Fi[k] = rc.F[rr];
+                    phi[k] = rc.phi[rr];
                     B[k] = 4 * (Fi[k] - kTabLo);
                 }
                 if (sent) row_partial_multi<true, NT, R>(wr, act, n, p4, B, cp, tab, lane, acc);
@@ -414,8 +446,8 @@ __global__ __launch_bounds__(kRowWaves * kWave, MINW) void k_row_sweep(const Ins
                 for (int k = 0; k < R; ++k) {
                     if (!act[k]) continue;
                     const float S = wave_sum(acc[k]);
-                    const float e = sent ? row_finish<true, true, NT>(I, row[k], par, lane, Fi[k], phi[k], S, cp, tab)
-                                         : row_finish<false, true, NT>(I, row[k], par, lane, Fi[k], phi[k], S, cp, tab);
+                    const float e = sent ? row_finish<true, true, NT>(rc, row[k], lane, Fi[k], phi[k], S, cp, tab)
+                                         : row_finish<false, true, NT>(rc, row[k], lane, Fi[k], phi[k], S, cp, tab);
                     wres = fmaxf(wres, e);
                 }
             }
@@ -424,42 +456,102 @@ __global__ __launch_bounds__(kRowWaves * kWave, MINW) void k_row_sweep(const Ins
             cur = 0;
         }
     }
-    for (int u = u0; u < u1;) {
-        const RowUnit un = units[u];
-        const Inst &I = insts[un.inst];
-        Ctl *ctl = I.ctl;
-        if (ctl->state != ST_RUNNING) {
-            ++u;
-            continue;
+    if constexpr (MINW == 1) {
+        // The instance of the units in hand: whether it runs, and what its rows
+        // read, loaded at each change of instance. With it, lane l of each wave
+        // loads the potentials of the wave's row in unit ubase + l (up to 64
+        // units ahead; the staging's wait covers these loads), and each row takes
+        // its own from that lane with a register read.
+        RowCtx rc{};
+        bool run = false, sent = false, v8 = false;
+        int ucur = -1, ubase = 0;
+        int lF = 0;
+        float lphi = 0.f;
+        for (int u = u0; u < u1; ++u) {
+            const RowUnit un = units[u];
+            if (un.inst != ucur || u - ubase >= kWave) {
+                if (un.inst != ucur) flush();
+                const Inst &I = insts[un.inst];
+                Ctl *ctl = I.ctl;
+                run = ctl->state == ST_RUNNING;
+                ucur = un.inst;
+                ubase = u;
+                if (run) {
+                    rc = row_ctx(I, ctl->iter & 1);
+                    sent = ctl->sent != 0u;
+                    v8 = I.vec8 != 0;
+                    const int ul = u + lane;
+                    if (ul < u1) {
+                        const RowUnit x = units[ul];
+                        const int r = x.row0 + wave;
+                        if (x.inst == un.inst && r < rc.n) {
+                            lF = rc.F[r];
+                            lphi = rc.phi[r];
+                        }
+                    }
+                    if (!GCOL) {
+                        __syncthreads();
+                        const int n8 = pad8(rc.n) >> 3;
+                        stage_col_pots<MINW == 1>(I, lds_cp, n8);
+                        stage_pad_cols(I, lds_cp, n8);
+                        __syncthreads();
+                    }
+                    // an empty use: the wait for these loads falls here, once per
+                    // window, not before every row's register read
+                    asm volatile("" : "+v"(lF), "+v"(lphi));
+                }
+                cur = run ? un.inst : -1;
+            }
+            if (!run) continue;
+            const int ra = un.row0 + wave;
+            if (ra >= rc.n) continue;
+            const int k = u - ubase;
+            const int Fi = __builtin_amdgcn_readlane(lF, k);
+            const float phi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lphi), k));
+            float e;
+            if (v8) {
+                e = sent ? row_step_one<true, true, NT>(rc, ra, lane, Fi, phi, cp, tab)
+                         : row_step_one<false, true, NT>(rc, ra, lane, Fi, phi, cp, tab);
+            } else {
+                e = sent ? row_step_one<true, false, NT>(rc, ra, lane, Fi, phi, cp, tab)
+                         : row_step_one<false, false, NT>(rc, ra, lane, Fi, phi, cp, tab);
+            }
+            wres = fmaxf(wres, e);
         }
-        const int n = I.n;
-        const int iter = ctl->iter;
-        if (un.inst != cur) {
-            flush();
-            if (!GCOL) {
+    } else {
+        // Short rows (batches of small instances; 64 registers): the unit's
+        // values are loaded at the unit, which keeps the registers free.
+        for (int u = u0; u < u1; ++u) {
+            const RowUnit un = units[u];
+            const Inst &I = insts[un.inst];
+            Ctl *ctl = I.ctl;
+            if (ctl->state != ST_RUNNING) continue;
+            const int n = I.n;
+            if (un.inst != cur) {
+                flush();
                 __syncthreads();
                 const int n8 = pad8(n) >> 3;
-                stage_col_pots<MINW == 1>(I, lds_cp, n8);
+                stage_col_pots<false>(I, lds_cp, n8);
                 stage_pad_cols(I, lds_cp, n8);
                 __syncthreads();
+                cur = un.inst;
             }
-            cur = un.inst;
-        }
-        const int par = iter & 1;
-        const bool sent = ctl->sent != 0u;
-        const int ra = un.row0 + wave;
-        float e = 0.f;
-        if (ra < n) {
+            const RowCtx rc = row_ctx(I, ctl->iter & 1);
+            const bool sent = ctl->sent != 0u;
+            const int ra = un.row0 + wave;
+            if (ra >= n) continue;
+            const int Fi = rc.F[ra];
+            const float phi = rc.phi[ra];
+            float e;
             if (I.vec8) {
-                e = sent ? row_step_one<true, true, NT>(I, ra, par, lane, cp, tab)
-                         : row_step_one<false, true, NT>(I, ra, par, lane, cp, tab);
+                e = sent ? row_step_one<true, true, NT>(rc, ra, lane, Fi, phi, cp, tab)
+                         : row_step_one<false, true, NT>(rc, ra, lane, Fi, phi, cp, tab);
             } else {
-                e = sent ? row_step_one<true, false, NT>(I, ra, par, lane, cp, tab)
-                         : row_step_one<false, false, NT>(I, ra, par, lane, cp, tab);
+                e = sent ? row_step_one<true, false, NT>(rc, ra, lane, Fi, phi, cp, tab)
+                         : row_step_one<false, false, NT>(rc, ra, lane, Fi, phi, cp, tab);
             }
+            wres = fmaxf(wres, e);
         }
-        wres = fmaxf(wres, e);
-        ++u;
     }
     // every wave ends on the same instance: the waves' maxima meet in LDS and
     // the last wave to finish sends the workgroup's to the slot

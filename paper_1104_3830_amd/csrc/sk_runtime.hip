@@ -622,7 +622,7 @@ sk_status sk::iterate_i16(sk_ctx *ctx, Batch &B, bool chained) {
                                           I0.vec8, ctx->stream, e2));
     else
         HIPCHK(ctx, launch_col_sweep(B.d_insts, B.d_cols, (int)B.h_cols.size(), B.col_grid, nt,
-                                     ctx->stream, e2));
+                                     B.nmax <= kShortRowN, ctx->stream, e2));
     pf.add(KID_ROW, s0, s1);
     pf.add(KID_COL, s1, s2);
     HIPCHK(ctx, launch_col_finalize(B.d_insts, B.d_fins, (int)B.h_fins.size(), B.fin_grid, 0,
