@@ -382,22 +382,39 @@ __global__ __launch_bounds__(kColWaves * kWave, EARLY ? 1 : 6) void k_col_sweep(
 //   stored K 1 pass:     slots hold b_j sum_i K_ij a_i:                  b_j <- b_j / C_j
 // A log-domain column whose sum leaves [2^-64, 2^64] is queued for the exact
 // recompute of the end-of-iteration kernel.
+// Column slots a thread holds in registers (4 threads per column): up to
+// 4 * kFinPre slots (the sweeps' row segments) are requested at the unit's
+// start, before the controller is read, so that the unit costs one memory
+// round trip; more slots (the single pass) are read in the loop.
+constexpr int kFinPre = 8;
+
 __global__ __launch_bounds__(256) void k_col_finalize(const Inst *__restrict__ insts,
                                                       const FinUnit *__restrict__ units, int nunits,
                                                       int mode) {
     __shared__ float part[4][kFinCols];
-    __shared__ float rmax[256], dmax[256];
-    const int t = threadIdx.x;
+    __shared__ float rmax[4], dmax[4];
+    const int t = threadIdx.x, lane = t % kWave, wave = t / kWave;
+    const bool kpath = (mode & kFinStoredK) != 0;   // slots written by the stored-K kernels
+    const bool onepass = (mode & kFinOnePass) != 0; // slots written by the single-pass kernel
     int u0, u1;
     unit_range(nunits, u0, u1);
     for (int u = u0; u < u1; ++u) {
         const FinUnit un = units[u];
         const Inst &I = insts[un.inst];
         Ctl *ctl = I.ctl;
-        if (ctl->state != ST_RUNNING) continue;
-        const bool kpath = (mode & kFinStoredK) != 0;   // slots written by the stored-K kernels
-        const bool onepass = (mode & kFinOnePass) != 0; // slots written by the single-pass kernel
-        if (kpath && ctl->need_absorb) continue;
+        const int n = I.n;
+        const int c = t & (kFinCols - 1), g = t / kFinCols;
+        const int j = un.group * kFinCols + c;
+        const int ns = I.ncolslots;
+        const bool pre = ns <= 4 * kFinPre;
+        float pv[kFinPre];
+        if (pre && j < n) {
+#pragma unroll
+            for (int k = 0; k < kFinPre; ++k) {
+                const int q = g + 4 * k;
+                pv[k] = q < ns ? I.colpart[(int64_t)q * n + j] : 0.f;
+            }
+        }
         // residual (and drift) of this iteration's row step: one slot per
         // workgroup of the single pass and of the stored-K row sweep, per
         // row segment of the log-domain sweeps
@@ -407,37 +424,44 @@ __global__ __launch_bounds__(256) void k_col_finalize(const Inst *__restrict__ i
             m = fmaxf(m, I.res_slots[q]);
             if (kpath) d = fmaxf(d, I.drift_slots[q]);
         }
-        __syncthreads();
-        rmax[t] = m;
-        dmax[t] = d;
-        __syncthreads();
-        for (int o = 128; o > 0; o >>= 1) {
-            if (t < o) {
-                rmax[t] = fmaxf(rmax[t], rmax[t + o]);
-                dmax[t] = fmaxf(dmax[t], dmax[t + o]);
-            }
-            __syncthreads();
+        if (ctl->state != ST_RUNNING) continue;
+        if (kpath && ctl->need_absorb) continue;
+        m = wave_max(m);
+        d = wave_max(d);
+        __syncthreads();  // the previous unit's readers of rmax, dmax and part are done
+        if (lane == 0) {
+            rmax[wave] = m;
+            dmax[wave] = d;
         }
-        const float res = rmax[0];
+        __syncthreads();
+        const float res = fmaxf(fmaxf(rmax[0], rmax[1]), fmaxf(rmax[2], rmax[3]));
+        const float dm = fmaxf(fmaxf(dmax[0], dmax[1]), fmaxf(dmax[2], dmax[3]));
         const bool conv = ctl->iter >= 1 && res < I.tol && deform_settled(I, ctl);
         if (un.group == 0 && t == 0) {
             ctl->res_bits = __float_as_uint(res);
-            if (kpath && dmax[0] > 0.f) atomicMax(&ctl->drift_bits, __float_as_uint(dmax[0]));
+            if (kpath && dm > 0.f) atomicMax(&ctl->drift_bits, __float_as_uint(dm));
         }
         if (conv) continue;
-        const int n = I.n;
-        const int c = t & (kFinCols - 1), g = t / kFinCols;
-        const int j = un.group * kFinCols + c;
+        // each thread adds the slots g, g + 4, ... of its column, alternately
+        // into two sums (fixed order)
         float s0 = 0.f, s1 = 0.f;
         if (j < n) {
-            int q = g;
-            for (; q + 4 < I.ncolslots; q += 8) {
-                s0 += I.colpart[(int64_t)q * n + j];
-                s1 += I.colpart[(int64_t)(q + 4) * n + j];
+            if (pre) {
+#pragma unroll
+                for (int k = 0; k < kFinPre; ++k) {
+                    if (g + 4 * k >= ns) break;
+                    if (k & 1) s1 += pv[k];
+                    else s0 += pv[k];
+                }
+            } else {
+                int q = g;
+                for (; q + 4 < ns; q += 8) {
+                    s0 += I.colpart[(int64_t)q * n + j];
+                    s1 += I.colpart[(int64_t)(q + 4) * n + j];
+                }
+                for (; q < ns; q += 4) s0 += I.colpart[(int64_t)q * n + j];
             }
-            for (; q < I.ncolslots; q += 4) s0 += I.colpart[(int64_t)q * n + j];
         }
-        __syncthreads();
         part[g][c] = s0 + s1;
         __syncthreads();
         float drift = 0.f;
