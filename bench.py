@@ -114,7 +114,7 @@ def parse():
                          "and those longer than 20 us (launches that did work)")
     ap.add_argument("--counter-summary", metavar="CSV",
                     help="only summarise a rocprofv3 --pmc counter CSV: per kernel and counter, the "
-                         "mean over dispatches that did work (value above 1%% of the kernel's max)")
+                         "mean over full-work dispatches (value at least half the kernel's max)")
     ap.add_argument("--traffic-report", nargs=6,
                     metavar=("KERNEL", "WORKLOAD", "FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV",
                              "COPY_WRITE_CSV"),
@@ -196,7 +196,9 @@ def _counter_means(path, counter):
     for k, d in per.items():
         v = list(d.values())
         hi = max(v) if v else 0.0
-        work = [x for x in v if x > 0.01 * hi]
+        # full-work dispatches: at least half the kernel's largest (launches
+        # that only detected a stage's end read a few MB at most)
+        work = [x for x in v if x >= 0.5 * hi]
         out[k] = (sum(work) / len(work) if work else 0.0, len(work), len(v))
     return out
 
@@ -218,8 +220,8 @@ def traffic_report(kernel, workload, fcsv, wcsv, cfcsv, cwcsv):
     print(f"copy_write_kib: {cw:.1f}")
     print(f"fetch_scale: {fs:.4f}")
     print(f"write_scale: {ws:.4f}")
-    print(f"fetch_kib_per_launch_raw: {f[0]:.1f} (mean over {f[1]} of {f[2]} dispatches that did work)")
-    print(f"write_kib_per_launch_raw: {w[0]:.1f} (mean over {w[1]} of {w[2]} dispatches that did work)")
+    print(f"fetch_kib_per_launch_raw: {f[0]:.1f} (mean over the {f[1]} full-work dispatches of {f[2]})")
+    print(f"write_kib_per_launch_raw: {w[0]:.1f} (mean over the {w[1]} full-work dispatches of {w[2]})")
     print(f"bytes_per_launch: {total:.0f}")
 
 
@@ -239,7 +241,9 @@ def _counter_means_full(path, counter):
     for k, d in per.items():
         v = list(d.values())
         hi = max(v) if v else 0.0
-        work = [x for x in v if x > 0.01 * hi]
+        # full-work dispatches: at least half the kernel's largest (launches
+        # that only detected a stage's end read a few MB at most)
+        work = [x for x in v if x >= 0.5 * hi]
         out[k] = (sum(work) / len(work) if work else 0.0, len(work), len(v))
     return out
 

@@ -295,12 +295,13 @@ __global__ __launch_bounds__(kColWaves * kWave, EARLY ? 1 : 6) void k_col_sweep(
         }
         float rres_w = 0.f;
         if (EARLY && wave == 0) rres_w = __uint_as_float(I.rowres[lane * kRowResStride]);
-        if (ctl->state != ST_RUNNING) continue;
+        // controller values are the same in every lane: read as scalars
+        if (__builtin_amdgcn_readfirstlane(ctl->state) != ST_RUNNING) continue;
         if (!EARLY && wave == 0) rres_w = __uint_as_float(I.rowres[lane * kRowResStride]);
-        const int iter = ctl->iter;
+        const int iter = __builtin_amdgcn_readfirstlane(ctl->iter);
         const int npar = (iter + 1) & 1;  // row potentials written by this iteration's row sweep
-        const int p4 = 4 * ctl->p;
-        const bool sent = ctl->sent != 0u;
+        const int p4 = 4 * __builtin_amdgcn_readfirstlane(ctl->p);
+        const bool sent = __builtin_amdgcn_readfirstlane(ctl->sent) != 0u;
         __syncthreads();
         float rm = 0.f;
         if constexpr (EARLY) {

@@ -202,21 +202,31 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_row_sweep_k(const Inst *_
     // its residual and drift slots at the end, so the waves run their rows
     // without a barrier
     float resmax = 0.f, drift = 0.f;
+    // the controller is read once per instance (its values do not change
+    // during a launch), as scalars
+    bool run = false;
+    int par = 0;
     for (int u = u0; u < u1; ++u) {
         const RowUnit un = units[u];
         const Inst &I = insts[un.inst];
-        Ctl *ctl = I.ctl;
-        if (ctl->state != ST_RUNNING || ctl->need_absorb) continue;
         const int n = I.n, kp = I.kpitch, n8 = kp >> 3;
         if (un.inst != cur) {
-            __syncthreads();
-            for (int j = threadIdx.x; j < kp; j += blockDim.x) bsh[kswz(j, n8)] = j < n ? I.b[j] : 0.f;
-            __syncthreads();
+            Ctl *ctl = I.ctl;
+            run = __builtin_amdgcn_readfirstlane(ctl->state) == ST_RUNNING &&
+                  !__builtin_amdgcn_readfirstlane(ctl->need_absorb);
+            par = __builtin_amdgcn_readfirstlane(ctl->iter) & 1;
             cur = un.inst;
+            if (run) {
+                __syncthreads();
+                for (int j = threadIdx.x; j < kp; j += blockDim.x) bsh[kswz(j, n8)] = j < n ? I.b[j] : 0.f;
+                __syncthreads();
+            }
         }
+        if (!run) continue;
         const int row = un.row0 + wave;
         if (row < n) {
-            const int par = ctl->iter & 1;
+            // requested before the row's matrix loads, used at its end
+            const float aold = I.a[par][row];
             float acc = 0.f;
             const int64_t rbase = (int64_t)row * kp;
             int j0 = lane * 8;
@@ -245,7 +255,6 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_row_sweep_k(const Inst *_
             }
             const float S = kwave_sum(acc);
             if (lane == 0) {
-                const float aold = I.a[par][row];
                 const float anew = 1.f / fminf(fmaxf(S, kKLo), kKHi);
                 I.a[par ^ 1][row] = anew;
                 resmax = fmaxf(resmax, fabsf(aold * S - 1.f));

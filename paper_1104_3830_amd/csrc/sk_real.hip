@@ -174,6 +174,14 @@ __device__ __forceinline__ double real_row_max(const float *__restrict__ wr, int
     return m;
 }
 
+// A value that is the same in every lane, as a scalar.
+__device__ __forceinline__ double rfl_d(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 template <bool NT, bool V4>
 __global__ __launch_bounds__(kRowWaves * kWave) void k_row_sweep_real(const Inst *__restrict__ insts,
                                                                         const RowUnit *__restrict__ units,
@@ -187,35 +195,79 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_row_sweep_real(const Inst
         wg_res = 0u;
         wg_done = 0u;
     }
-    int cur = -1;
+    int cur = -1;  // running instance whose column data is staged
     float wres = 0.f;
     const int slot = (int)((blockIdx.x * kRowWaves + wave) % kRowResSlots) * kRowResStride;
+    // What the rows of the instance in hand read, loaded at each change of
+    // instance (none of it changes during a launch), and the potentials of
+    // the wave's row in unit ubase + l in lane l (up to 64 units ahead): a
+    // row then starts without a chain of dependent loads.
+    bool run = false, sent = false;
+    int ucur = -1, ubase = 0, n = 0;
+    double p2 = 0.0, wref = 0.0;
+    const float *Wr = nullptr;
+    int64_t pitch = 0;
+    const SK_GLOBAL int32_t *Fp = nullptr;
+    SK_GLOBAL int32_t *Fn = nullptr;
+    SK_GLOBAL float *phin_p = nullptr, *rres = nullptr;
+    Ctl *cctl = nullptr;
+    int lF = 0;
+    float lphi = 0.f;
     for (int u = u0; u < u1; ++u) {
         const RowUnit un = units[u];
-        const Inst &I = insts[un.inst];
-        Ctl *ctl = I.ctl;
-        if (ctl->state != ST_RUNNING) continue;
-        const int n = I.n;
-        if (un.inst != cur) {
-            if (cur >= 0 && lane == 0 && wres > 0.f)
-                atomicMax(&insts[cur].rowres[slot], __float_as_uint(wres));
-            wres = 0.f;
-            __syncthreads();
-            const int n4 = (n + 3) >> 2;
-            for (int j = threadIdx.x; j < n; j += blockDim.x)
-                lv2[V4 ? swz4(j, n4) : j] = ((double)I.G[j] + (double)I.gam[j]) * kLog2eD;
-            __syncthreads();
-            cur = un.inst;
+        if (un.inst != ucur || u - ubase >= kWave) {
+            if (un.inst != ucur) {
+                if (cur >= 0 && lane == 0 && wres > 0.f) atomicMax(&insts[cur].rowres[slot], __float_as_uint(wres));
+                wres = 0.f;
+            }
+            const Inst &I = insts[un.inst];
+            Ctl *ctl = I.ctl;
+            // controller values are the same in every lane: read as scalars,
+            // so that what depends on them stays in scalar registers
+            run = __builtin_amdgcn_readfirstlane(ctl->state) == ST_RUNNING;
+            ucur = un.inst;
+            ubase = u;
+            if (run) {
+                n = I.n;
+                const int par = __builtin_amdgcn_readfirstlane(ctl->iter) & 1;
+                p2 = rfl_d(real_p(I, ctl) * kLog2eD);
+                wref = (double)I.wref;
+                Wr = I.Wr;
+                pitch = I.pitch;
+                sent = __builtin_amdgcn_readfirstlane(ctl->sent) != 0u;
+                cctl = ctl;
+                Fp = (const SK_GLOBAL int32_t *)(par ? I.F[1] : I.F[0]);
+                const SK_GLOBAL float *phip = (const SK_GLOBAL float *)(par ? I.phi[1] : I.phi[0]);
+                Fn = (SK_GLOBAL int32_t *)(par ? I.F[0] : I.F[1]);
+                phin_p = (SK_GLOBAL float *)(par ? I.phi[0] : I.phi[1]);
+                rres = (SK_GLOBAL float *)I.rres;
+                const int ul = u + lane;
+                if (ul < u1) {
+                    const RowUnit x = units[ul];
+                    const int r = x.row0 + wave;
+                    if (x.inst == un.inst && r < n) {
+                        lF = Fp[r];
+                        lphi = phip[r];
+                    }
+                }
+                __syncthreads();
+                const int n4 = (n + 3) >> 2;
+                for (int j = threadIdx.x; j < n; j += blockDim.x)
+                    lv2[V4 ? swz4(j, n4) : j] = ((double)I.G[j] + (double)I.gam[j]) * kLog2eD;
+                __syncthreads();
+                // an empty use: the wait for these loads falls here, once per
+                // window, not before every row's register read
+                asm volatile("" : "+v"(lF), "+v"(lphi));
+            }
+            cur = run ? un.inst : -1;
         }
+        if (!run) continue;
         const int row = un.row0 + wave;
         if (row >= n) continue;
-        const int par = ctl->iter & 1;
-        const int Fi = I.F[par][row];
-        const float phi = I.phi[par][row];
-        const double p2 = real_p(I, ctl) * kLog2eD;
-        const double wref = (double)I.wref;
-        const float *wr = I.Wr + (int64_t)row * I.pitch;
-        const bool sent = ctl->sent != 0u;
+        const int kk = u - ubase;
+        const int Fi = __builtin_amdgcn_readlane(lF, kk);
+        const float phi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lphi), kk));
+        const float *wr = Wr + (int64_t)row * pitch;
         auto rsum = [&](int shift) {
             const double f2 = (double)(Fi - shift) * kLog2eD;
             return wave_sum(sent ? real_row_sum<true, NT, V4>(wr, n, p2, wref, f2, lv2, lane)
@@ -227,7 +279,7 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_row_sweep_real(const Inst
             // exact max shift (Section 4.1.2): M = rint(max_j (p w'_ij + F_i + log v_j))
             const double m2 = wave_max_d(real_row_max<V4>(wr, n, p2, wref, (double)Fi * kLog2eD, lv2, lane));
             if (m2 == -INFINITY) {
-                if (lane == 0) atomicOr(&ctl->err, ERR_EMPTY_ROW);
+                if (lane == 0) atomicOr(&cctl->err, ERR_EMPTY_ROW);
                 S = 1.f;
             } else {
                 M = (int)rint(m2 * kLn2D);
@@ -239,11 +291,11 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_row_sweep_real(const Inst
             const float l2S = lg2(S);
             const float phin = -l2S * kLn2;
             const float k = rintf(phin);
-            I.F[par ^ 1][row] = Fi - M + (int)k;
-            I.phi[par ^ 1][row] = phin - k;
+            Fn[row] = Fi - M + (int)k;
+            phin_p[row] = phin - k;
             const float r = ex2(fmaf(phi + (float)M, kLog2e, l2S));
             const float res = fabsf(r - 1.f);
-            I.rres[row] = res;
+            rres[row] = res;
             wres = fmaxf(wres, res);
         }
     }

@@ -207,7 +207,7 @@ __device__ __forceinline__ RowCtx row_ctx(const Inst &I, int par) {
     c.rres = (SK_GLOBAL float *)I.rres;
     c.ctl = I.ctl;
     c.n = I.n;
-    c.p4 = 4 * I.ctl->p;
+    c.p4 = 4 * __builtin_amdgcn_readfirstlane(I.ctl->p);
     return c;
 }
 
@@ -473,12 +473,15 @@ __global__ __launch_bounds__(kRowWaves * kWave, MINW) void k_row_sweep(const Ins
                 if (un.inst != ucur) flush();
                 const Inst &I = insts[un.inst];
                 Ctl *ctl = I.ctl;
-                run = ctl->state == ST_RUNNING;
+                // controller values are the same in every lane: read as
+                // scalars, so that what depends on them stays in scalar
+                // registers
+                run = __builtin_amdgcn_readfirstlane(ctl->state) == ST_RUNNING;
                 ucur = un.inst;
                 ubase = u;
                 if (run) {
-                    rc = row_ctx(I, ctl->iter & 1);
-                    sent = ctl->sent != 0u;
+                    rc = row_ctx(I, __builtin_amdgcn_readfirstlane(ctl->iter) & 1);
+                    sent = __builtin_amdgcn_readfirstlane(ctl->sent) != 0u;
                     v8 = I.vec8 != 0;
                     const int ul = u + lane;
                     if (ul < u1) {
@@ -525,7 +528,7 @@ __global__ __launch_bounds__(kRowWaves * kWave, MINW) void k_row_sweep(const Ins
             const RowUnit un = units[u];
             const Inst &I = insts[un.inst];
             Ctl *ctl = I.ctl;
-            if (ctl->state != ST_RUNNING) continue;
+            if (__builtin_amdgcn_readfirstlane(ctl->state) != ST_RUNNING) continue;
             const int n = I.n;
             if (un.inst != cur) {
                 flush();
@@ -536,8 +539,8 @@ __global__ __launch_bounds__(kRowWaves * kWave, MINW) void k_row_sweep(const Ins
                 __syncthreads();
                 cur = un.inst;
             }
-            const RowCtx rc = row_ctx(I, ctl->iter & 1);
-            const bool sent = ctl->sent != 0u;
+            const RowCtx rc = row_ctx(I, __builtin_amdgcn_readfirstlane(ctl->iter) & 1);
+            const bool sent = __builtin_amdgcn_readfirstlane(ctl->sent) != 0u;
             const int ra = un.row0 + wave;
             if (ra >= n) continue;
             const int Fi = rc.F[ra];
