@@ -1396,11 +1396,29 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_nt_rows(const Inst *__res
     const Inst &I = insts[0];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int n = I.n, n8 = pad8(n) >> 3;
-    const int par = I.ctl->iter & 1;
-    const int p4 = 4 * I.ctl->p;
-    const bool sent = I.ctl->sent != 0u;
+    const int par = __builtin_amdgcn_readfirstlane(I.ctl->iter) & 1;
+    const int p4 = 4 * __builtin_amdgcn_readfirstlane(I.ctl->p);
+    const bool sent = __builtin_amdgcn_readfirstlane(I.ctl->sent) != 0u;
     int u0, u1;
     unit_range(nunits, u0, u1);
+    // lane l holds F_i, phi_i of the wave's row in unit ubase + l, so that a
+    // row starts and ends without waiting on a load of its own
+    const SK_GLOBAL int32_t *Fp = (const SK_GLOBAL int32_t *)I.F[par];
+    const SK_GLOBAL float *phip = (const SK_GLOBAL float *)I.phi[par];
+    int lF = 0, ubase = u0;
+    float lphi = 0.f;
+    auto window = [&](int ub) {
+        ubase = ub;
+        const int ul = ub + lane;
+        if (ul < u1) {
+            const int r = units[ul].row0 + wave;
+            if (r < n) {
+                lF = Fp[r];
+                lphi = phip[r];
+            }
+        }
+    };
+    window(u0);
     fill_exp_table(tab);
     for (int j = threadIdx.x; j < n; j += blockDim.x) {
         ColPot k;
@@ -1410,18 +1428,26 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_nt_rows(const Inst *__res
     }
     stage_pad_cols(I, lds_cp, n8);
     __syncthreads();
+    // an empty use: the wait for the window's loads falls here
+    asm volatile("" : "+v"(lF), "+v"(lphi));
     for (int u = u0; u < u1; ++u) {
+        if (u - ubase >= kWave) {
+            window(u);
+            asm volatile("" : "+v"(lF), "+v"(lphi));
+        }
         const int row = units[u].row0 + wave;
         if (row >= n) continue;
+        const int Fi = __builtin_amdgcn_readlane(lF, u - ubase);
+        const float phi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lphi), u - ubase));
         const int16_t *wr = I.W + (int64_t)row * I.pitch;
-        const int B = 4 * (I.F[par][row] - kTabLo);
+        const int B = 4 * (Fi - kTabLo);
         float S;
         if (I.vec8) S = sent ? row_partial_v8<true, NT>(wr, n, p4, B, lds_cp, tab, lane)
                              : row_partial_v8<false, NT>(wr, n, p4, B, lds_cp, tab, lane);
         else S = sent ? row_partial_v1<true, NT>(wr, n, p4, B, lds_cp, tab, lane)
                       : row_partial_v1<false, NT>(wr, n, p4, B, lds_cp, tab, lane);
         S = wave_sum(S);
-        if (lane == 0) sd[row] = ex2(I.phi[par][row] * kLog2e) * S;
+        if (lane == 0) sd[row] = ex2(phi * kLog2e) * S;
     }
 }
 

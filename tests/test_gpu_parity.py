@@ -287,6 +287,29 @@ def test_row_sweep_instantiations_agree_bitwise(ctx):
         assert alone.report["iters_stage"] == b.report["iters_stage"]
 
 
+def test_row_window_reload_bitwise(ctx):
+    """The long-row row sweep loads the row potentials of up to 64 of a
+    workgroup's units at a time. A batch of n = 16384 instances with more
+    than 64 row units per workgroup (16 rows per unit, one workgroup per CU)
+    reloads that window in the middle of an instance; every instance's
+    potentials after three iterations equal its run alone, bit for bit.
+    The instances are one seeded matrix shifted by 13 k mod 1001 on the
+    device."""
+    n = 16384
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    count = (65 * cus) // (n // 16) + 1
+    assert count * (n // 16) > 64 * cus
+    base = dev(skgen.uniform_weights(n, 0, 1000, seed=5))
+    Ws = [torch.remainder(base + 13 * k, 1001).to(torch.int16) for k in range(count)]
+    del base
+    prm = sk.make_params([8], tol=0.0, max_iters=3, check_every=3)
+    batch = ctx.scale_batch(Ws, prm)
+    for W, b in zip(Ws, batch):
+        alone = ctx.scale(W, prm)
+        assert alone.report["iters_total"] == 3
+        assert torch.equal(alone.potentials, b.potentials)
+
+
 def test_repeat_runs_bitwise(ctx):
     W = skgen.uniform_weights(1024, 0, 1000, seed=1)
     prm = sk.make_params([4, 8], tol=1e-5, max_iters=300)
