@@ -780,7 +780,8 @@ __device__ __forceinline__ void check_row_v8(const Inst &I, GQ gq, int2 *qe, int
                 mask_pad8(w, jj, n);
 #pragma unroll
                 for (int c = 0; c < 8; ++c) {
-                    const int E = pi * w[c] + gq[c * n8 + (jj >> 3)].x + Fi;
+                    // 24-bit multiply, exact: |p w| <= 2048 * 32768 = 2^26
+                    const int E = __mul24(pi, w[c]) + gq[c * n8 + (jj >> 3)].x + Fi;
                     if (!SENT || w[c] != SK_SENTINEL) {
                         Emax = max(Emax, E);
                         if (E >= eskip) flag |= 1u << c;
@@ -810,7 +811,7 @@ __device__ __forceinline__ void check_row_v8(const Inst &I, GQ gq, int2 *qe, int
         visit_row(I, wr, lane, [&](int j, int w) {
             if (w == SK_SENTINEL) return;
             const int2 q = gq_ld(gq, (j & 7) * n8 + (j >> 3));
-            const int E = pi * w + q.x + Fi;
+            const int E = __mul24(pi, w) + q.x + Fi;
             if (E < Es - 1 || E >= eskip) return;
             const double t = p * (double)w + logv_of(q);
             if (t > m || (t == m && j < jm)) {
@@ -902,7 +903,7 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_check_rows(const Inst *__
         visit_row(I, wr, lane, [&](int j, int w) {
             if (w == SK_SENTINEL) return;
             const int2 q = gq_at(I, gq, j);
-            const int E = pi * w + q.x + Fi;
+            const int E = __mul24(pi, w) + q.x + Fi;
             Emax = max(Emax, E);
             if (E >= eskip) exact(j, w, q);
         });
@@ -911,7 +912,7 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_check_rows(const Inst *__
             visit_row(I, wr, lane, [&](int j, int w) {
                 if (w == SK_SENTINEL) return;
                 const int2 q = gq_at(I, gq, j);
-                const int E = pi * w + q.x + Fi;
+                const int E = __mul24(pi, w) + q.x + Fi;
                 if (E < Es - 1 || E >= eskip) return;
                 const double t = p * (double)w + logv_of(q);
                 if (t > m || (t == m && j < jm)) {
@@ -990,7 +991,7 @@ __device__ __forceinline__ void check_cols_add8(const int4 v, int p, int2 rf, co
     const double ph = (double)__int_as_float(rf.y);
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-        const int E = p * w[c] + rf.x + G[c];
+        const int E = __mul24(p, w[c]) + rf.x + G[c];
         if (w[c] != SK_SENTINEL && E >= kCheckSkip) {
             const double lx = (double)E + (ph + gm[c]);
             if (lx > kNegligibleLog) s[c] += exp(lx);
@@ -1140,7 +1141,7 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_prune_count(const Inst *_
         visit_row(I, wr, lane, [&](int j, int w) {
             if (w == SK_SENTINEL) return;
             const int2 q = gq_at(I, gq, j);
-            if (pi * w + q.x + Fi < eskip) return;  // cannot reach t
+            if (__mul24(pi, w) + q.x + Fi < eskip) return;  // cannot reach t
             const double lx = p * (double)w + f + logv_of(q);
             cnt += (lx >= logt);
         });
@@ -1281,7 +1282,7 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_prune_fill(const Inst *__
                         unsigned cand = 0;
 #pragma unroll
                         for (int c = 0; c < 8; ++c)
-                            if (pi * wv[c] + gq[c * n8 + base].x + Fi >= eskip) cand |= 1u << c;
+                            if (__mul24(pi, wv[c]) + gq[c * n8 + base].x + Fi >= eskip) cand |= 1u << c;
                         if (sent) {
 #pragma unroll
                             for (int c = 0; c < 8; ++c)
@@ -1328,7 +1329,7 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_prune_fill(const Inst *__
                 w = wr[j];
                 if (w != SK_SENTINEL) {
                     const int2 q = gq_at(I, gq, j);
-                    if (pi * w + q.x + Fi >= eskip) {
+                    if (__mul24(pi, w) + q.x + Fi >= eskip) {
                         const double lx = p * (double)w + f + logv_of(q);
                         keep = lx >= logt;
                     }
