@@ -84,8 +84,8 @@ SWEEP_KERNELS = {"i16": ("row_sweep", "col_sweep", "fused"),
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=16384)
     ap.add_argument("--storage", default="i16", choices=sorted(ELEM_BYTES))
     ap.add_argument("--ladder", default="1,2,4,8,16,32")

@@ -730,7 +730,10 @@ __device__ __forceinline__ void check_row_v8(const Inst &I, GQ gq, int2 *qe, int
     const int16_t *wr = I.W + (int64_t)row * I.pitch;
     double s = 0.0, m = -INFINITY;
     int jm = -1, cnt = 0;
-    int Emax = INT_MIN;  // this lane's largest exact exponent E = p w + F_i + G_j
+    // this lane's largest p w + G_j (E = p w + F_i + G_j without the row's
+    // F_i, which moves into the threshold: E >= eskip <=> p w + G_j >= T)
+    int Emax = INT_MIN;
+    const int T = eskip - Fi;
     // one entry in FP64 (t = p w_ij + log v_j, log x_ij = t + log u_i)
     auto exact = [&](int j, int w) {
         const int2 q = gq_ld(gq, (j & 7) * n8 + (j >> 3));
@@ -773,20 +776,29 @@ __device__ __forceinline__ void check_row_v8(const Inst &I, GQ gq, int2 *qe, int
         for (int k = 0; k < U; ++k) {
             if (jb0 + k * 512 >= n) break;
             const int jj = jb0 + k * 512 + lane * 8;
-            int w[8];
-            unsigned flag = 0;
+            int w[8], e8[8];
+            bool hit = false;
             if (jj < n) {
                 unpack8i(v[k], w);
                 mask_pad8(w, jj, n);
+                int m8 = INT_MIN;
 #pragma unroll
                 for (int c = 0; c < 8; ++c) {
-                    // 24-bit multiply, exact: |p w| <= 2048 * 32768 = 2^26
-                    const int E = __mul24(pi, w[c]) + gq[c * n8 + (jj >> 3)].x + Fi;
-                    if (!SENT || w[c] != SK_SENTINEL) {
-                        Emax = max(Emax, E);
-                        if (E >= eskip) flag |= 1u << c;
-                    }
+                    // 24-bit multiply-add, exact: |p w| <= 2048 * 32768 = 2^26
+                    e8[c] = (!SENT || w[c] != SK_SENTINEL) ? __mul24(pi, w[c]) + gq[c * n8 + (jj >> 3)].x : INT_MIN;
+                    m8 = max(m8, e8[c]);
                 }
+                Emax = max(Emax, m8);
+                hit = m8 >= T;
+            }
+            // the per-entry flags only where a lane's chunk reaches the
+            // threshold (about one chunk in three has none in the wave)
+            if (__ballot(hit) == 0ull) continue;
+            unsigned flag = 0;
+            if (hit) {
+#pragma unroll
+                for (int c = 0; c < 8; ++c)
+                    if (e8[c] >= T) flag |= 1u << c;
             }
             // queue the flagged entries: per round, every lane with one left
             // appends its lowest, in lane order
@@ -806,7 +818,7 @@ __device__ __forceinline__ void check_row_v8(const Inst &I, GQ gq, int2 *qe, int
         }
     }
     if (qn) flush();
-    const int Es = wave_max_i(Emax);
+    const int Es = wave_max_i(Emax == INT_MIN ? INT_MIN : Emax + Fi);
     if (Es != INT_MIN && Es - 1 < eskip) {
         visit_row(I, wr, lane, [&](int j, int w) {
             if (w == SK_SENTINEL) return;
