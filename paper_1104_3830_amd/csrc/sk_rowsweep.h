@@ -182,8 +182,8 @@ __device__ __forceinline__ int row_max_v1(const int16_t *__restrict__ wr, int n,
 // the row sweep loads it once per instance and a row's start waits on no
 // chain of dependent loads (unit -> instance -> controller -> potentials).
 // The potentials are global-address-space pointers: their loads then count
-// only against the vector-memory counter, so that a row's LDS reads never
-// wait for the next row's potentials in flight.
+// only against the vector-memory counter (a flat load counts against the LDS
+// counter too, and every LDS wait would include it).
 struct RowCtx {
     const int16_t *W;
     int64_t pitch;
