@@ -718,54 +718,62 @@ __global__ __launch_bounds__(256) void k_col_pack(const Inst *__restrict__ insts
 // 64 at a time, one per lane, instead of one lane at a time in every chunk.
 // The queue order is fixed (chunk, then round, then lane), so the sums are
 // the same on every run.
-template <bool SENT, bool NT, class GQ>
-__device__ __forceinline__ void check_row_v8(const Inst &I, GQ gq, int2 *qe, int row, int lane,
-                                             int eskip, double logt, double *rsum, double *rmax,
-                                             int64_t *counts, int32_t *hint) {
+// The running state of one row's check: its FP64 sum, the row maximum of
+// t = p w_ij + log v_j and its first column, the kept entries, the lane's
+// largest p w + G_j, and the entries queued for FP64.
+struct RowCheck {
+    double s, m;
+    int jm, cnt, Emax, qn;
+};
+
+// One entry in FP64 (t = p w_ij + log v_j, log x_ij = t + log u_i); gq in
+// the full swizzled layout.
+template <class GQ>
+__device__ __forceinline__ void check_exact(GQ gq, int n8, int j, int w, double p, double f, double logt,
+                                            RowCheck &a) {
+    const int2 q = gq_ld(gq, (j & 7) * n8 + (j >> 3));
+    const double pw = p * (double)w, lvj = logv_of(q);
+    const double t = pw + lvj;
+    const double lx = t + f;
+    if (lx > kNegligibleLog) a.s += exp(lx);
+    // the kept test in the exact arithmetic order of the fill kernel
+    a.cnt += (pw + f + lvj >= logt);
+    if (t > a.m || (t == a.m && j < a.jm)) {
+        a.m = t;
+        a.jm = j;
+    }
+}
+
+template <class GQ>
+__device__ __forceinline__ void check_flush(GQ gq, int n8, const int2 *qe, int lane, double p, double f,
+                                            double logt, RowCheck &a) {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    if (lane < a.qn) {
+        const int2 e = qe[lane];
+        check_exact(gq, n8, e.x, e.y, p, f, logt, a);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    a.qn = 0;
+}
+
+// Pass 1 over the row's columns [lo, hi) (lo a multiple of the step of
+// kVisitLoads chunks): the exact integer exponents, with G_j from gs(c, jj)
+// (column jj + c); the entries with E >= eskip (T = eskip - F_i) are queued
+// for FP64 (check_exact through gq).
+// Pass 1 takes in FP64 only the entries with E >= eskip (the others are
+// negligible and below the threshold). The row maximum of t is at an
+// entry with E >= E* - 1 (E* the largest E; |phi_i|, |gam_j| <= 1/2):
+// when E* - 1 >= eskip pass 1 has seen it; otherwise (every entry
+// negligible) pass 2 (check_row_finish) looks at the entries with E in
+// [E* - 1, eskip).
+template <bool SENT, bool NT, class GQ, class GS>
+__device__ __forceinline__ void check_row_scan(const Inst &I, GQ gq, GS gs, int2 *qe, const int16_t *wr, int lane,
+                                               int lo, int hi, int pi, double p, double f, int T, double logt,
+                                               RowCheck &a) {
     const int n = I.n, n8 = pad8(n) >> 3;
-    const int par = I.ctl->iter & 1;
-    const int pi = I.ctl->p, Fi = I.F[par][row];
-    const double p = (double)pi;
-    const double f = (double)Fi + (double)I.phi[par][row];
-    const int16_t *wr = I.W + (int64_t)row * I.pitch;
-    double s = 0.0, m = -INFINITY;
-    int jm = -1, cnt = 0;
-    // this lane's largest p w + G_j (E = p w + F_i + G_j without the row's
-    // F_i, which moves into the threshold: E >= eskip <=> p w + G_j >= T)
-    int Emax = INT_MIN;
-    const int T = eskip - Fi;
-    // one entry in FP64 (t = p w_ij + log v_j, log x_ij = t + log u_i)
-    auto exact = [&](int j, int w) {
-        const int2 q = gq_ld(gq, (j & 7) * n8 + (j >> 3));
-        const double pw = p * (double)w, lvj = logv_of(q);
-        const double t = pw + lvj;
-        const double lx = t + f;
-        if (lx > kNegligibleLog) s += exp(lx);
-        // the kept test in the exact arithmetic order of the fill kernel
-        cnt += (pw + f + lvj >= logt);
-        if (t > m || (t == m && j < jm)) {
-            m = t;
-            jm = j;
-        }
-    };
-    int qn = 0;  // queued entries (uniform across the wave)
-    auto flush = [&]() {
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        if (lane < qn) {
-            const int2 e = qe[lane];
-            exact(e.x, e.y);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        qn = 0;
-    };
-    // Pass 1 takes in FP64 only the entries with E >= eskip (the others are
-    // negligible and below the threshold). The row maximum of t is at an
-    // entry with E >= E* - 1 (E* the largest E; |phi_i|, |gam_j| <= 1/2):
-    // when E* - 1 >= eskip pass 1 has seen it; otherwise (every entry
-    // negligible) pass 2 looks at the entries with E in [E* - 1, eskip).
     // the loop bounds are uniform across the wave (the queue needs every lane)
     constexpr int U = kVisitLoads;
-    for (int jb0 = 0; jb0 < n; jb0 += U * 512) {
+    for (int jb0 = lo; jb0 < hi; jb0 += U * 512) {
         int4 v[U];
 #pragma unroll
         for (int k = 0; k < U; ++k) {
@@ -785,10 +793,10 @@ __device__ __forceinline__ void check_row_v8(const Inst &I, GQ gq, int2 *qe, int
 #pragma unroll
                 for (int c = 0; c < 8; ++c) {
                     // 24-bit multiply-add, exact: |p w| <= 2048 * 32768 = 2^26
-                    e8[c] = (!SENT || w[c] != SK_SENTINEL) ? __mul24(pi, w[c]) + gq[c * n8 + (jj >> 3)].x : INT_MIN;
+                    e8[c] = (!SENT || w[c] != SK_SENTINEL) ? __mul24(pi, w[c]) + gs(c, jj) : INT_MIN;
                     m8 = max(m8, e8[c]);
                 }
-                Emax = max(Emax, m8);
+                a.Emax = max(a.Emax, m8);
                 hit = m8 >= T;
             }
             // the per-entry flags only where a lane's chunk reaches the
@@ -806,19 +814,31 @@ __device__ __forceinline__ void check_row_v8(const Inst &I, GQ gq, int2 *qe, int
                 const uint64_t mask = __ballot(flag != 0u);
                 if (mask == 0ull) break;
                 const int nq = __popcll(mask);
-                if (qn + nq > kWave) flush();
+                if (a.qn + nq > kWave) check_flush(gq, n8, qe, lane, p, f, logt, a);
                 if (flag) {
                     const int c = __ffs(flag) - 1;
-                    const int pos = qn + __popcll(mask & ((1ull << lane) - 1ull));
+                    const int pos = a.qn + __popcll(mask & ((1ull << lane) - 1ull));
                     qe[pos] = make_int2(jj + c, w[c]);
                     flag &= flag - 1u;
                 }
-                qn += nq;
+                a.qn += nq;
             }
         }
     }
-    if (qn) flush();
-    const int Es = wave_max_i(Emax == INT_MIN ? INT_MIN : Emax + Fi);
+}
+
+// The rest of the row's check after its pass 1: the queued entries, pass 2
+// when every entry was negligible, the wave reductions and the results.
+template <bool SENT, class GQ>
+__device__ __forceinline__ void check_row_finish(const Inst &I, GQ gq, const int2 *qe, const int16_t *wr, int row,
+                                                 int lane, int eskip, int pi, double p, int Fi, double f,
+                                                 double logt, double *rsum, double *rmax, int64_t *counts,
+                                                 int32_t *hint, RowCheck &a) {
+    const int n8 = pad8(I.n) >> 3;
+    if (a.qn) check_flush(gq, n8, qe, lane, p, f, logt, a);
+    double s = a.s, m = a.m;
+    int jm = a.jm, cnt = a.cnt;
+    const int Es = wave_max_i(a.Emax == INT_MIN ? INT_MIN : a.Emax + Fi);
     if (Es != INT_MIN && Es - 1 < eskip) {
         visit_row(I, wr, lane, [&](int j, int w) {
             if (w == SK_SENTINEL) return;
@@ -853,6 +873,47 @@ __device__ __forceinline__ void check_row_v8(const Inst &I, GQ gq, int2 *qe, int
     }
 }
 
+// A wave-uniform value moved to scalar registers (every lane holds it).
+__device__ __forceinline__ float rfl_f(float x) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, x)));
+}
+__device__ __forceinline__ int64_t rfl_i64(int64_t x) {
+    const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(x >> 32));
+    return (int64_t)((hi << 32) | (uint32_t)__builtin_amdgcn_readfirstlane((int)x));
+}
+
+// n > kLdsMaxN: G_j of the row's columns staged in LDS kGTile at a time for
+// the integer scan, column j of the tile starting at lo at
+// (j mod 8) kGT8 + (j - lo) / 8 (the lanes of a wave read consecutive
+// words). 128 KiB: one tile up to n = 32768.
+constexpr int kGTile = 32768;
+constexpr int kGT8 = kGTile / 8;
+
+__device__ __forceinline__ void stage_g_tile(const Inst &I, int *gG, int lo) {
+    const int n = I.n, hi = min(lo + kGTile, pad8(n));
+    for (int j = lo + (int)threadIdx.x; j < hi; j += blockDim.x)
+        gG[(j & 7) * kGT8 + ((j - lo) >> 3)] = j < n ? I.G[j] : kPadG;
+}
+
+// The whole row with its column entries in one layout (LDS, n <= kLdsMaxN).
+template <bool SENT, bool NT, class GQ>
+__device__ __forceinline__ void check_row_v8(const Inst &I, GQ gq, int2 *qe, int row, int lane,
+                                             int eskip, double logt, double *rsum, double *rmax,
+                                             int64_t *counts, int32_t *hint) {
+    const int n = I.n, n8 = pad8(n) >> 3;
+    const int par = I.ctl->iter & 1;
+    const int pi = I.ctl->p, Fi = I.F[par][row];
+    const double p = (double)pi;
+    const double f = (double)Fi + (double)I.phi[par][row];
+    const int16_t *wr = I.W + (int64_t)row * I.pitch;
+    // Emax: the lane's largest p w + G_j (E = p w + F_i + G_j without the
+    // row's F_i, which moves into the threshold: E >= eskip <=> p w + G_j >= T)
+    RowCheck a{0.0, -INFINITY, -1, 0, INT_MIN, 0};
+    auto gs = [&](int c, int jj) { return gq[c * n8 + (jj >> 3)].x; };
+    check_row_scan<SENT, NT>(I, gq, gs, qe, wr, lane, 0, n, pi, p, f, eskip - Fi, logt, a);
+    check_row_finish<SENT>(I, gq, qe, wr, row, lane, eskip, pi, p, Fi, f, logt, rsum, rmax, counts, hint, a);
+}
+
 // GCOL: one instance with n > kLdsMaxN, its column entries read from
 // I.colpack (packed by k_col_pack, mode 1) instead of staged in LDS.
 template <bool NT, bool GCOL>
@@ -872,6 +933,54 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_check_rows(const Inst *__
     int u0, u1;
     unit_range(nunits, u0, u1);
     const int eskip = counts ? min(kCheckSkip, kept_skip(logt)) : kCheckSkip;
+    if constexpr (GCOL) {
+        if (insts[0].vec8) {
+            // The integer scan reads G_j from LDS tiles (staged once when the
+            // row fits one tile); the FP64 entries and pass 2 read (G_j,
+            // gam_j) from the packed buffer, as the whole-row form does, so
+            // the queue and the results are the same.
+            __shared__ int gG[kGTile];
+            const Inst &I = insts[0];
+            const int n = I.n, ntile = (n + kGTile - 1) / kGTile;
+            // the row's state is wave-uniform: kept in scalar registers
+            const bool sent = __builtin_amdgcn_readfirstlane(I.ctl->sent) != 0u;
+            const int par = __builtin_amdgcn_readfirstlane(I.ctl->iter) & 1;
+            const int pi = __builtin_amdgcn_readfirstlane(I.ctl->p);
+            const double p = (double)pi;
+            for (int u = u0; u < u1; ++u) {
+                const int row = __builtin_amdgcn_readfirstlane(units[u].row0 + wave);
+                const bool on = row < n;
+                const int Fi = on ? __builtin_amdgcn_readfirstlane(I.F[par][row]) : 0;
+                const double f = (double)Fi + (double)(on ? rfl_f(I.phi[par][row]) : 0.0f);
+                const int16_t *wr = I.W + (int64_t)(on ? row : 0) * I.pitch;
+                RowCheck a{0.0, -INFINITY, -1, 0, INT_MIN, 0};
+                for (int t = 0; t < ntile; ++t) {
+                    const int lo = t * kGTile, hi = min(n, lo + kGTile);
+                    if (ntile > 1 || u == u0) {
+                        __syncthreads();
+                        stage_g_tile(I, gG, lo);
+                        __syncthreads();
+                    }
+                    if (!on) continue;
+                    auto gs = [&](int c, int jj) { return gG[c * kGT8 + ((jj - lo) >> 3)]; };
+                    if (sent)
+                        check_row_scan<true, NT>(I, gq, gs, queue[wave], wr, lane, lo, hi, pi, p, f, eskip - Fi, logt,
+                                                 a);
+                    else
+                        check_row_scan<false, NT>(I, gq, gs, queue[wave], wr, lane, lo, hi, pi, p, f, eskip - Fi, logt,
+                                                  a);
+                }
+                if (!on) continue;
+                if (sent)
+                    check_row_finish<true>(I, gq, queue[wave], wr, row, lane, eskip, pi, p, Fi, f, logt, rsum, rmax,
+                                           counts, hint, a);
+                else
+                    check_row_finish<false>(I, gq, queue[wave], wr, row, lane, eskip, pi, p, Fi, f, logt, rsum, rmax,
+                                            counts, hint, a);
+            }
+            return;
+        }
+    }
     int cur = -1;
     for (int u = u0; u < u1; ++u) {
         const RowUnit un = units[u];
@@ -1222,6 +1331,89 @@ __global__ __launch_bounds__(1024) void k_scan(const int64_t *__restrict__ count
 
 // Writes the kept columns of each row in increasing order: each wave walks
 // its row in 64-column chunks and places the kept ones with a ballot prefix.
+// The CSR entries of one 8-wide row over its columns [lo, hi) (lo a
+// multiple of the step of kVisitLoads chunks), placed from pos on: each lane
+// tests 8 consecutive columns; kept entries are placed by a wave prefix sum
+// of the per-lane counts (column order kept), skipped for the chunks where no
+// lane keeps an entry. G_j for the integer test from gs(c, j0) (column
+// j0 + c), (G_j, gam_j) for the FP64 test from gq in the full layout.
+template <bool NT, bool SPOS, class GQ, class GS>
+__device__ __forceinline__ void fill_row_range(const Inst &I, GQ gq, GS gs, const int16_t *wr, int lane, int lo,
+                                               int hi, int pi, double p, int Fi, double f, int eskip,
+                                               double logt, bool sent, int64_t &pos, int32_t *__restrict__ col,
+                                               int16_t *__restrict__ wout) {
+    constexpr int U = kVisitLoads;
+    const int n = I.n, n8 = pad8(n) >> 3;
+    // the next kVisitLoads chunks load while these are used
+    int4 vb[U], vn[U];
+    auto load_batch = [&](int4 (&b)[U], int jb0) {
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int j0 = jb0 + k * 512 + lane * 8;
+            b[k] = j0 < n ? gload<NT>(reinterpret_cast<const int4 *>(wr + j0)) : make_int4(0, 0, 0, 0);
+        }
+    };
+    load_batch(vb, lo);
+    for (int jb0 = lo; jb0 < hi; jb0 += U * 512) {
+        if (jb0 + U * 512 < hi) load_batch(vn, jb0 + U * 512);
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int jb = jb0 + k * 512;
+            if (jb >= n) break;
+            const int j0 = jb + lane * 8;
+            int wv[8];
+            unsigned keep = 0;
+            if (j0 < n) {
+                unpack8i(vb[k], wv);
+                mask_pad8(wv, j0, n);
+                // exact integer test first (below eskip an entry
+                // cannot reach t), then FP64 for the few that can
+                const int base = j0 >> 3;
+                unsigned cand = 0;
+#pragma unroll
+                for (int c = 0; c < 8; ++c)
+                    if (__mul24(pi, wv[c]) + gs(c, j0) + Fi >= eskip) cand |= 1u << c;
+                if (sent) {
+#pragma unroll
+                    for (int c = 0; c < 8; ++c)
+                        if (wv[c] == SK_SENTINEL) cand &= ~(1u << c);
+                }
+                if (cand) {
+#pragma unroll
+                    for (int c = 0; c < 8; ++c)
+                        if (cand & (1u << c)) {
+                            const double lx = p * (double)wv[c] + f + logv_of(gq_ld(gq, c * n8 + base));
+                            if (lx >= logt) keep |= 1u << c;
+                        }
+                }
+            }
+            if (__ballot(keep != 0u) == 0ull) continue;  // nothing kept in this chunk
+            const int cnt = __popc(keep);
+            int incl = cnt;
+#pragma unroll
+            for (int o = 1; o < kWave; o <<= 1) {
+                const int y = __shfl_up(incl, o, kWave);
+                if (lane >= o) incl += y;
+            }
+            // every lane is active here: with SPOS the wave's count is moved
+            // to a scalar register, so pos stays scalar
+            int total = __shfl(incl, kWave - 1, kWave);
+            if constexpr (SPOS) total = __builtin_amdgcn_readfirstlane(total);
+            int64_t q = pos + (incl - cnt);
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+                if (keep & (1u << c)) {
+                    col[q] = j0 + c;
+                    wout[q] = (int16_t)wv[c];
+                    ++q;
+                }
+            pos += total;
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k) vb[k] = vn[k];
+    }
+}
+
 template <bool NT, bool GCOL>
 __global__ __launch_bounds__(kRowWaves * kWave) void k_prune_fill(const Inst *__restrict__ insts,
                                                                     const RowUnit *__restrict__ units,
@@ -1239,6 +1431,41 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_prune_fill(const Inst *__
     int u0, u1;
     unit_range(nunits, u0, u1);
     const int eskip = kept_skip(logt);
+    if constexpr (GCOL) {
+        if (insts[0].vec8) {
+            // the integer test reads G_j from LDS tiles (as the row check);
+            // the FP64 test reads (G_j, gam_j) from the packed buffer
+            __shared__ int gG[kGTile];
+            const Inst &I = insts[0];
+            const int n = I.n, ntile = (n + kGTile - 1) / kGTile;
+            // the row's state is wave-uniform: kept in scalar registers
+            const bool sent = __builtin_amdgcn_readfirstlane(I.ctl->sent) != 0u;
+            const int par = __builtin_amdgcn_readfirstlane(I.ctl->iter) & 1;
+            const int pi = __builtin_amdgcn_readfirstlane(I.ctl->p);
+            const double p = (double)pi;
+            for (int u = u0; u < u1; ++u) {
+                const int row = __builtin_amdgcn_readfirstlane(units[u].row0 + wave);
+                const bool on = row < n;
+                const int Fi = on ? __builtin_amdgcn_readfirstlane(I.F[par][row]) : 0;
+                const double f = (double)Fi + (double)(on ? rfl_f(I.phi[par][row]) : 0.0f);
+                const int16_t *wr = I.W + (int64_t)(on ? row : 0) * I.pitch;
+                int64_t pos = on ? rfl_i64(row_ptr[row]) : 0;
+                for (int t = 0; t < ntile; ++t) {
+                    const int lo = t * kGTile, hi = min(n, lo + kGTile);
+                    if (ntile > 1 || u == u0) {
+                        __syncthreads();
+                        stage_g_tile(I, gG, lo);
+                        __syncthreads();
+                    }
+                    if (!on) continue;
+                    auto gs = [&](int c, int j0) { return gG[c * kGT8 + ((j0 - lo) >> 3)]; };
+                    fill_row_range<NT, true>(I, gq, gs, wr, lane, lo, hi, pi, p, Fi, f, eskip, logt, sent, pos, col,
+                                             wout);
+                }
+            }
+            return;
+        }
+    }
     int cur = -1;
     for (int u = u0; u < u1; ++u) {
         const RowUnit un = units[u];
@@ -1260,77 +1487,10 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_prune_fill(const Inst *__
         const int16_t *wr = I.W + (int64_t)row * I.pitch;
         int64_t pos = row_ptr[row];
         if (I.vec8) {
-            // each lane tests 8 consecutive columns; kept entries are placed
-            // by a wave prefix sum of the per-lane counts (column order kept),
-            // skipped for the chunks where no lane keeps an entry
-            constexpr int U = kVisitLoads;
             const int n8 = pad8(n) >> 3;
-            const bool sent = I.ctl->sent != 0u;
-            // the next kVisitLoads chunks load while these are used
-            int4 vb[U], vn[U];
-            auto load_batch = [&](int4 (&b)[U], int jb0) {
-#pragma unroll
-                for (int k = 0; k < U; ++k) {
-                    const int j0 = jb0 + k * 512 + lane * 8;
-                    b[k] = j0 < n ? gload<NT>(reinterpret_cast<const int4 *>(wr + j0)) : make_int4(0, 0, 0, 0);
-                }
-            };
-            load_batch(vb, 0);
-            for (int jb0 = 0; jb0 < n; jb0 += U * 512) {
-                if (jb0 + U * 512 < n) load_batch(vn, jb0 + U * 512);
-#pragma unroll
-                for (int k = 0; k < U; ++k) {
-                    const int jb = jb0 + k * 512;
-                    if (jb >= n) break;
-                    const int j0 = jb + lane * 8;
-                    int wv[8];
-                    unsigned keep = 0;
-                    if (j0 < n) {
-                        unpack8i(vb[k], wv);
-                        mask_pad8(wv, j0, n);
-                        // exact integer test first (below eskip an entry
-                        // cannot reach t), then FP64 for the few that can
-                        const int base = j0 >> 3;
-                        unsigned cand = 0;
-#pragma unroll
-                        for (int c = 0; c < 8; ++c)
-                            if (__mul24(pi, wv[c]) + gq[c * n8 + base].x + Fi >= eskip) cand |= 1u << c;
-                        if (sent) {
-#pragma unroll
-                            for (int c = 0; c < 8; ++c)
-                                if (wv[c] == SK_SENTINEL) cand &= ~(1u << c);
-                        }
-                        if (cand) {
-#pragma unroll
-                            for (int c = 0; c < 8; ++c)
-                                if (cand & (1u << c)) {
-                                    const double lx = p * (double)wv[c] + f + logv_of(gq_ld(gq, c * n8 + base));
-                                    if (lx >= logt) keep |= 1u << c;
-                                }
-                        }
-                    }
-                    if (__ballot(keep != 0u) == 0ull) continue;  // nothing kept in this chunk
-                    const int cnt = __popc(keep);
-                    int incl = cnt;
-#pragma unroll
-                    for (int o = 1; o < kWave; o <<= 1) {
-                        const int y = __shfl_up(incl, o, kWave);
-                        if (lane >= o) incl += y;
-                    }
-                    const int total = __shfl(incl, kWave - 1, kWave);
-                    int64_t q = pos + (incl - cnt);
-#pragma unroll
-                    for (int c = 0; c < 8; ++c)
-                        if (keep & (1u << c)) {
-                            col[q] = j0 + c;
-                            wout[q] = (int16_t)wv[c];
-                            ++q;
-                        }
-                    pos += total;
-                }
-#pragma unroll
-                for (int k = 0; k < U; ++k) vb[k] = vn[k];
-            }
+            auto gs = [&](int c, int j0) { return gq[c * n8 + (j0 >> 3)].x; };
+            fill_row_range<NT, false>(I, gq, gs, wr, lane, 0, n, pi, p, Fi, f, eskip, logt, I.ctl->sent != 0u, pos,
+                                      col, wout);
             continue;
         }
         for (int j0 = 0; j0 < n; j0 += kWave) {

@@ -71,10 +71,16 @@ def unit(z: np.ndarray) -> np.ndarray:
 
 def uniform_weights(n: int, lo: int, hi: int, seed: int, chunk_rows: int = 1024) -> np.ndarray:
     """n x n int16 matrix with entries uniform on the integers lo..hi."""
+    return uniform_rows(n, n, lo, hi, seed, chunk_rows)
+
+
+def uniform_rows(k: int, n: int, lo: int, hi: int, seed: int, chunk_rows: int = 1024) -> np.ndarray:
+    """The first k rows of the n-column uniform matrix of (seed): k x n int16,
+    entries uniform on the integers lo..hi (uniform_weights(n) for k = n)."""
     assert W_MIN <= lo <= hi <= W_MAX
-    W = np.empty((n, n), dtype=np.int16)
-    for r0 in range(0, n, chunk_rows):
-        r1 = min(n, r0 + chunk_rows)
+    W = np.empty((k, n), dtype=np.int16)
+    for r0 in range(0, k, chunk_rows):
+        r1 = min(k, r0 + chunk_rows)
         z = stream(seed, TAG_W, (r1 - r0) * n, offset=r0 * n)
         W[r0:r1] = (bounded(z, hi - lo + 1).astype(np.int64) + lo).reshape(r1 - r0, n)
     return W

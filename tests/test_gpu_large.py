@@ -105,3 +105,59 @@ def test_large_other_paths_refuse(ctx):
     with pytest.raises(sk.SkError) as e:
         ctx.scale_real(Wr, sk.make_params([8], tol=1e-5, max_iters=10))
     assert e.value.status in (sk.SK_EINVAL, sk.SK_ENOMEM)
+
+
+def test_large_two_tile_rows_solve_and_prune(ctx):
+    """n = 40000: in the row check and the CSR fill each row spans two LDS
+    tiles of G_j (32768 columns each). The matrix: 4096 seeded rows uniform on
+    0..1000, row i being row (i mod 4096) rotated right by 8 (i div 4096)
+    columns. sk_solve (ladder 1..32, tol 1e-5, t = 1e-4; its counts and CSR
+    from the tiled check and fill) returns a permutation whose weight is that
+    of W and at most the certificate's bound (log gamma >= 0; with this many
+    ties it proves nothing at p = 32); sk_prune on the same potentials
+    (its own count pass) keeps as many entries as the solve counted, and the
+    CSR of sampled rows is the oracle's kept set x_ij >= t (entries within
+    1e-9 of log t aside) with the weights of W, in column order."""
+    n, k, p, t = 40000, 4096, 32, 1e-4
+    base = skgen.uniform_rows(k, n, 0, 1000, seed=31)
+
+    def host_row(i):
+        return np.roll(base[i % k], 8 * (i // k))
+
+    bd = dev(base)
+    Wd = torch.empty((n, n), dtype=torch.int16, device="cuda")
+    for b in range((n + k - 1) // k):
+        r0, r1 = b * k, min(n, (b + 1) * k)
+        Wd[r0:r1] = torch.roll(bd[:r1 - r0], shifts=8 * b, dims=1)
+    del bd
+    prm = sk.make_params([1, 2, 4, 8, 16, p], tol=1e-5 - MARGIN, max_iters=5000, check_every=64,
+                         threshold=t)
+    out = ctx.solve(Wd, prm)
+    rep = out["report"]
+    assert out["status"] == sk.SK_OK and rep["stages_capped"] == 0
+    perm = np.asarray(out["perm"])
+    assert np.array_equal(np.sort(perm), np.arange(n))
+    pd = torch.from_numpy(perm.astype(np.int64)).cuda()
+    assert out["weight"] == int(Wd.gather(1, pd[:, None]).to(torch.int64).sum())
+    assert out["log_gamma"] >= 0.0 and out["weight"] <= 1000 * n
+    row_ptr, col, w = ctx.prune(Wd, out["potentials"], prm)
+    rp, cc, ww = row_ptr.cpu().numpy(), col.cpu().numpy(), w.cpu().numpy()
+    assert rp[-1] == out["nnz"] == len(cc)
+    ub, vb = bars(out["potentials"], n, p)
+    rng = np.random.default_rng(5)
+    rows = np.sort(np.r_[0, 1, rng.choice(np.arange(2, n - 4), 60, replace=False), np.arange(n - 4, n)])
+    Wr = np.stack([host_row(i) for i in rows])
+    assert np.array_equal(Wr[:, :64], Wd[torch.from_numpy(rows).cuda(), :64].cpu().numpy())
+    lx = p * (oracle.log_weights(Wr) + ub[rows][:, None] + vb[None, :])
+    keep = oracle.scaled_matrix(oracle.log_weights(Wr), p, ub[rows], vb) >= t
+    band = np.abs(lx - np.log(t)) < 1e-9
+    beyond = 0
+    for r, i in enumerate(rows):
+        seg = cc[rp[i]:rp[i + 1]]
+        assert np.all(np.diff(seg) > 0)
+        assert np.array_equal(ww[rp[i]:rp[i + 1]], Wr[r, seg])
+        got = np.zeros(n, dtype=bool)
+        got[seg] = True
+        assert np.array_equal(got[~band[r]], keep[r][~band[r]]), i
+        beyond += int(np.sum(seg >= 32768))
+    assert beyond > 0  # kept entries in the second tile were compared
