@@ -756,6 +756,70 @@ __device__ __forceinline__ void check_flush(GQ gq, int n8, const int2 *qe, int l
     a.qn = 0;
 }
 
+// Visits the 8-wide chunks of a row's columns [lo, hi) (lo a multiple of the
+// step of kVisitLoads chunks) in column order: body(jj, w) with w the int16
+// entries of columns jj..jj+7 of this lane (those past n unspecified; the
+// loop bounds are uniform across the wave). The loads run as a ring of
+// kVisitLoads per lane: slot k is refilled with the chunk kVisitLoads ahead
+// once its own is unpacked; loads past the row's end read its last chunk
+// (unused), so every load is issued and each chunk waits for its own load
+// only. Slot 0 is unpacked a batch ahead (at the last chunk of the batch
+// before), and the full batches run in a loop of their own with the partial
+// last batch after it (from the slots already loaded): with either, the
+// compiler's count of loads in flight stays exact at every wait.
+template <bool NT, class Body>
+__device__ __forceinline__ void ring_row_chunks(const int16_t *wr, int n, int lane, int lo, int hi, Body body) {
+    constexpr int U = kVisitLoads;
+    const int jlast = pad8(n) - 8;
+    auto at = [&](int j) { return reinterpret_cast<const int4 *>(wr + min(j, jlast)); };
+    int4 v[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+        v[k] = gload<NT>(at(lo + k * 512 + lane * 8));
+        // issued in slot order, as the loop refills them
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    int w0[8];
+    unpack8i(v[0], w0);
+    v[0] = gload<NT>(at(lo + U * 512 + lane * 8));
+    int jb0 = lo;
+    for (; jb0 + U * 512 <= hi; jb0 += U * 512) {
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int jj = jb0 + k * 512 + lane * 8;
+            int w[8];
+            if (k == 0) {
+#pragma unroll
+                for (int c = 0; c < 8; ++c) w[c] = w0[c];
+            } else {
+                unpack8i(v[k], w);
+                v[k] = gload<NT>(at(jj + U * 512));
+            }
+            if (k == U - 1) {
+                unpack8i(v[0], w0);
+                // kept here, ahead of the refill of its slot (not sunk past it)
+                asm volatile("" : "+v"(w0[0]), "+v"(w0[1]), "+v"(w0[2]), "+v"(w0[3]), "+v"(w0[4]), "+v"(w0[5]),
+                             "+v"(w0[6]), "+v"(w0[7]));
+                v[0] = gload<NT>(at(jj + (U + 1) * 512));
+            }
+            body(jj, w);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+        if (jb0 + k * 512 >= hi) break;
+        const int jj = jb0 + k * 512 + lane * 8;
+        int w[8];
+        if (k == 0) {
+#pragma unroll
+            for (int c = 0; c < 8; ++c) w[c] = w0[c];
+        } else {
+            unpack8i(v[k], w);
+        }
+        body(jj, w);
+    }
+}
+
 // Pass 1 over the row's columns [lo, hi) (lo a multiple of the step of
 // kVisitLoads chunks): the exact integer exponents, with G_j from gs(c, jj)
 // (column jj + c); the entries with E >= eskip (T = eskip - F_i) are queued
@@ -771,60 +835,48 @@ __device__ __forceinline__ void check_row_scan(const Inst &I, GQ gq, GS gs, int2
                                                int lo, int hi, int pi, double p, double f, int T, double logt,
                                                RowCheck &a) {
     const int n = I.n, n8 = pad8(n) >> 3;
-    // the loop bounds are uniform across the wave (the queue needs every lane)
-    constexpr int U = kVisitLoads;
-    for (int jb0 = lo; jb0 < hi; jb0 += U * 512) {
-        int4 v[U];
+    // The entries of one 8-wide chunk (columns jj..jj+7 of this lane).
+    auto chunk = [&](int jj, int (&w)[8]) {
+        int e8[8];
+        bool hit = false;
+        if (jj < n) {
+            mask_pad8(w, jj, n);
+            int m8 = INT_MIN;
 #pragma unroll
-        for (int k = 0; k < U; ++k) {
-            const int j0 = jb0 + k * 512 + lane * 8;
-            v[k] = j0 < n ? gload<NT>(reinterpret_cast<const int4 *>(wr + j0)) : make_int4(0, 0, 0, 0);
+            for (int c = 0; c < 8; ++c) {
+                // 24-bit multiply-add, exact: |p w| <= 2048 * 32768 = 2^26
+                e8[c] = (!SENT || w[c] != SK_SENTINEL) ? __mul24(pi, w[c]) + gs(c, jj) : INT_MIN;
+                m8 = max(m8, e8[c]);
+            }
+            a.Emax = max(a.Emax, m8);
+            hit = m8 >= T;
         }
+        // the per-entry flags only where a lane's chunk reaches the
+        // threshold (about one chunk in three has none in the wave)
+        if (__ballot(hit) == 0ull) return;
+        unsigned flag = 0;
+        if (hit) {
 #pragma unroll
-        for (int k = 0; k < U; ++k) {
-            if (jb0 + k * 512 >= n) break;
-            const int jj = jb0 + k * 512 + lane * 8;
-            int w[8], e8[8];
-            bool hit = false;
-            if (jj < n) {
-                unpack8i(v[k], w);
-                mask_pad8(w, jj, n);
-                int m8 = INT_MIN;
-#pragma unroll
-                for (int c = 0; c < 8; ++c) {
-                    // 24-bit multiply-add, exact: |p w| <= 2048 * 32768 = 2^26
-                    e8[c] = (!SENT || w[c] != SK_SENTINEL) ? __mul24(pi, w[c]) + gs(c, jj) : INT_MIN;
-                    m8 = max(m8, e8[c]);
-                }
-                a.Emax = max(a.Emax, m8);
-                hit = m8 >= T;
-            }
-            // the per-entry flags only where a lane's chunk reaches the
-            // threshold (about one chunk in three has none in the wave)
-            if (__ballot(hit) == 0ull) continue;
-            unsigned flag = 0;
-            if (hit) {
-#pragma unroll
-                for (int c = 0; c < 8; ++c)
-                    if (e8[c] >= T) flag |= 1u << c;
-            }
-            // queue the flagged entries: per round, every lane with one left
-            // appends its lowest, in lane order
-            for (;;) {
-                const uint64_t mask = __ballot(flag != 0u);
-                if (mask == 0ull) break;
-                const int nq = __popcll(mask);
-                if (a.qn + nq > kWave) check_flush(gq, n8, qe, lane, p, f, logt, a);
-                if (flag) {
-                    const int c = __ffs(flag) - 1;
-                    const int pos = a.qn + __popcll(mask & ((1ull << lane) - 1ull));
-                    qe[pos] = make_int2(jj + c, w[c]);
-                    flag &= flag - 1u;
-                }
-                a.qn += nq;
-            }
+            for (int c = 0; c < 8; ++c)
+                if (e8[c] >= T) flag |= 1u << c;
         }
-    }
+        // queue the flagged entries: per round, every lane with one left
+        // appends its lowest, in lane order
+        for (;;) {
+            const uint64_t mask = __ballot(flag != 0u);
+            if (mask == 0ull) break;
+            const int nq = __popcll(mask);
+            if (a.qn + nq > kWave) check_flush(gq, n8, qe, lane, p, f, logt, a);
+            if (flag) {
+                const int c = __ffs(flag) - 1;
+                const int pos = a.qn + __popcll(mask & ((1ull << lane) - 1ull));
+                qe[pos] = make_int2(jj + c, w[c]);
+                flag &= flag - 1u;
+            }
+            a.qn += nq;
+        }
+    };
+    ring_row_chunks<NT>(wr, n, lane, lo, hi, chunk);
 }
 
 // The rest of the row's check after its pass 1: the queued entries, pass 2
@@ -1342,76 +1394,54 @@ __device__ __forceinline__ void fill_row_range(const Inst &I, GQ gq, GS gs, cons
                                                int hi, int pi, double p, int Fi, double f, int eskip,
                                                double logt, bool sent, int64_t &pos, int32_t *__restrict__ col,
                                                int16_t *__restrict__ wout) {
-    constexpr int U = kVisitLoads;
     const int n = I.n, n8 = pad8(n) >> 3;
-    // the next kVisitLoads chunks load while these are used
-    int4 vb[U], vn[U];
-    auto load_batch = [&](int4 (&b)[U], int jb0) {
-#pragma unroll
-        for (int k = 0; k < U; ++k) {
-            const int j0 = jb0 + k * 512 + lane * 8;
-            b[k] = j0 < n ? gload<NT>(reinterpret_cast<const int4 *>(wr + j0)) : make_int4(0, 0, 0, 0);
-        }
-    };
-    load_batch(vb, lo);
-    for (int jb0 = lo; jb0 < hi; jb0 += U * 512) {
-        if (jb0 + U * 512 < hi) load_batch(vn, jb0 + U * 512);
-#pragma unroll
-        for (int k = 0; k < U; ++k) {
-            const int jb = jb0 + k * 512;
-            if (jb >= n) break;
-            const int j0 = jb + lane * 8;
-            int wv[8];
-            unsigned keep = 0;
-            if (j0 < n) {
-                unpack8i(vb[k], wv);
-                mask_pad8(wv, j0, n);
-                // exact integer test first (below eskip an entry
-                // cannot reach t), then FP64 for the few that can
-                const int base = j0 >> 3;
-                unsigned cand = 0;
-#pragma unroll
-                for (int c = 0; c < 8; ++c)
-                    if (__mul24(pi, wv[c]) + gs(c, j0) + Fi >= eskip) cand |= 1u << c;
-                if (sent) {
-#pragma unroll
-                    for (int c = 0; c < 8; ++c)
-                        if (wv[c] == SK_SENTINEL) cand &= ~(1u << c);
-                }
-                if (cand) {
-#pragma unroll
-                    for (int c = 0; c < 8; ++c)
-                        if (cand & (1u << c)) {
-                            const double lx = p * (double)wv[c] + f + logv_of(gq_ld(gq, c * n8 + base));
-                            if (lx >= logt) keep |= 1u << c;
-                        }
-                }
-            }
-            if (__ballot(keep != 0u) == 0ull) continue;  // nothing kept in this chunk
-            const int cnt = __popc(keep);
-            int incl = cnt;
-#pragma unroll
-            for (int o = 1; o < kWave; o <<= 1) {
-                const int y = __shfl_up(incl, o, kWave);
-                if (lane >= o) incl += y;
-            }
-            // every lane is active here: with SPOS the wave's count is moved
-            // to a scalar register, so pos stays scalar
-            int total = __shfl(incl, kWave - 1, kWave);
-            if constexpr (SPOS) total = __builtin_amdgcn_readfirstlane(total);
-            int64_t q = pos + (incl - cnt);
+    ring_row_chunks<NT>(wr, n, lane, lo, hi, [&](int j0, int (&wv)[8]) {
+        unsigned keep = 0;
+        if (j0 < n) {
+            mask_pad8(wv, j0, n);
+            // exact integer test first (below eskip an entry cannot reach
+            // t), then FP64 for the few that can
+            const int base = j0 >> 3;
+            unsigned cand = 0;
 #pragma unroll
             for (int c = 0; c < 8; ++c)
-                if (keep & (1u << c)) {
-                    col[q] = j0 + c;
-                    wout[q] = (int16_t)wv[c];
-                    ++q;
-                }
-            pos += total;
-        }
+                if (__mul24(pi, wv[c]) + gs(c, j0) + Fi >= eskip) cand |= 1u << c;
+            if (sent) {
 #pragma unroll
-        for (int k = 0; k < U; ++k) vb[k] = vn[k];
-    }
+                for (int c = 0; c < 8; ++c)
+                    if (wv[c] == SK_SENTINEL) cand &= ~(1u << c);
+            }
+            if (cand) {
+#pragma unroll
+                for (int c = 0; c < 8; ++c)
+                    if (cand & (1u << c)) {
+                        const double lx = p * (double)wv[c] + f + logv_of(gq_ld(gq, c * n8 + base));
+                        if (lx >= logt) keep |= 1u << c;
+                    }
+            }
+        }
+        if (__ballot(keep != 0u) == 0ull) return;  // nothing kept in this chunk
+        const int cnt = __popc(keep);
+        int incl = cnt;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const int y = __shfl_up(incl, o, kWave);
+            if (lane >= o) incl += y;
+        }
+        // every lane is active here: with SPOS the wave's count is moved
+        // to a scalar register, so pos stays scalar
+        int total = __shfl(incl, kWave - 1, kWave);
+        if constexpr (SPOS) total = __builtin_amdgcn_readfirstlane(total);
+        int64_t q = pos + (incl - cnt);
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+            if (keep & (1u << c)) {
+                col[q] = j0 + c;
+                wout[q] = (int16_t)wv[c];
+                ++q;
+            }
+        pos += total;
+    });
 }
 
 template <bool NT, bool GCOL>
