@@ -266,7 +266,8 @@ hipError_t launch_check_rows(const Inst *d_insts, const RowUnit *d_units, int nu
 hipError_t launch_check_cols(const Inst *d_insts, int inst, int n, int nseg, int vec8,
                              double *part, double *csum, int nt_loads, hipStream_t st);
 hipError_t launch_prune_count(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
-                              double logt, int64_t *counts, size_t lds_bytes, int gcol, hipStream_t st);
+                              double logt, int64_t *counts, size_t lds_bytes, int nt_loads, int gcol,
+                              hipStream_t st);
 hipError_t launch_scan(const int64_t *counts, int64_t *row_ptr, int n, hipStream_t st,
                        int64_t *total_out = nullptr);
 hipError_t launch_check_reduce(const Inst *d_insts, int inst, const double *rsum,

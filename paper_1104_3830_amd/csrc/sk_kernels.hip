@@ -1157,18 +1157,84 @@ __global__ __launch_bounds__(256) void k_check_cols_sum(const Inst *__restrict__
 // fixed order. The exact integer part E = p w_ij + F_i + G_j decides first
 // (E < kCheckSkip: negligible).
 
-__device__ __forceinline__ void check_cols_add8(const int4 v, int p, int2 rf, const int (&G)[8],
+__device__ __forceinline__ void check_cols_add8(const int (&w)[8], int p, int2 rf, const int (&G)[8],
                                                 const double (&gm)[8], double (&s)[8]) {
-    int w[8];
-    unpack8i(v, w);
+    // E = p w + F_i + G_j; the chunk's largest p w + G_j first: when it is
+    // below kCheckSkip - F_i (the usual case) no entry is taken
+    int e[8];
+    int m8 = INT_MIN;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        e[c] = __mul24(p, w[c]) + G[c];
+        m8 = max(m8, e[c]);
+    }
+    if (m8 < kCheckSkip - rf.x) return;
     const double ph = (double)__int_as_float(rf.y);
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-        const int E = __mul24(p, w[c]) + rf.x + G[c];
+        const int E = e[c] + rf.x;
         if (w[c] != SK_SENTINEL && E >= kCheckSkip) {
             const double lx = (double)E + (ph + gm[c]);
             if (lx > kNegligibleLog) s[c] += exp(lx);
         }
+    }
+}
+
+// The column check's walk down its rows: chunks m = 0..m_end-1 (m_end
+// uniform across the wave) of 8 int16 entries per lane, loaded from at(m)
+// (for m >= m_end a valid address whose entries are unused), handed to
+// body(m, w) in order. The same ring as the row scans use (kVisitLoads
+// loads per lane, each slot refilled once its chunk is unpacked, slot 0
+// unpacked a batch ahead, the partial last batch after the loop); here
+// scheduling barriers also keep each refill after its slot's unpack, which
+// the compiler otherwise hoists, copying the slots at every batch.
+template <bool NT, class At, class Body>
+__device__ __forceinline__ void ring_col_chunks(int m_end, At at, Body body) {
+    constexpr int U = kVisitLoads;
+    int4 v[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+        v[k] = gload<NT>(at(k));
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    int w0[8];
+    unpack8i(v[0], w0);
+    __builtin_amdgcn_sched_barrier(0);
+    v[0] = gload<NT>(at(U));
+    int mb = 0;
+    for (; mb + U <= m_end; mb += U) {
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            int w[8];
+            if (k == 0) {
+#pragma unroll
+                for (int c = 0; c < 8; ++c) w[c] = w0[c];
+            } else {
+                unpack8i(v[k], w);
+                __builtin_amdgcn_sched_barrier(0);
+                v[k] = gload<NT>(at(mb + k + U));
+            }
+            if (k == U - 1) {
+                unpack8i(v[0], w0);
+                asm volatile("" : "+v"(w0[0]), "+v"(w0[1]), "+v"(w0[2]), "+v"(w0[3]), "+v"(w0[4]), "+v"(w0[5]),
+                             "+v"(w0[6]), "+v"(w0[7]));
+                __builtin_amdgcn_sched_barrier(0);
+                v[0] = gload<NT>(at(mb + 2 * U));
+            }
+            body(mb + k, w);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+        if (mb + k >= m_end) break;
+        int w[8];
+        if (k == 0) {
+#pragma unroll
+            for (int c = 0; c < 8; ++c) w[c] = w0[c];
+        } else {
+            unpack8i(v[k], w);
+        }
+        body(mb + k, w);
     }
 }
 
@@ -1209,20 +1275,16 @@ __global__ __launch_bounds__(kColWaves * kWave) void k_check_cols_part8(const In
                 gm[c] = j0 + c < n ? (double)I.gam[j0 + c] : 0.0;
             }
         }
-        const int16_t *w0 = I.W + j0;
-        int r = r0 + wave;
-        for (; r + 3 * kColWaves < r1; r += 4 * kColWaves) {
-            int4 v[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                v[k] = gload<NT>(reinterpret_cast<const int4 *>(w0 + (int64_t)(r + k * kColWaves) * I.pitch));
-#pragma unroll
-            for (int k = 0; k < 4; ++k) check_cols_add8(v[k], p, rowf[r + k * kColWaves - r0], G, gm, s);
-        }
-        for (; r < r1; r += kColWaves) {
-            const int4 v = gload<NT>(reinterpret_cast<const int4 *>(w0 + (int64_t)r * I.pitch));
-            check_cols_add8(v, p, rowf[r - r0], G, gm, s);
-        }
+        // this wave's rows r0 + wave + m kColWaves of the segment, through the
+        // load ring (loads past the segment read its last row, unused); the
+        // row index is wave-uniform and kept in a scalar register
+        const int ra = __builtin_amdgcn_readfirstlane(r0 + wave);
+        ring_col_chunks<NT>(
+            r1 > ra ? (r1 - ra + kColWaves - 1) / kColWaves : 0,
+            [&](int m) {
+                return reinterpret_cast<const int4 *>(I.W + (int64_t)min(ra + m * kColWaves, r1 - 1) * I.pitch + j0);
+            },
+            [&](int m, int (&w)[8]) { check_cols_add8(w, p, rowf[ra + m * kColWaves - r0], G, gm, s); });
     }
 #pragma unroll
     for (int c = 0; c < 8; ++c) red[wave][lane * 8 + c] = s[c];
@@ -1276,7 +1338,51 @@ __global__ __launch_bounds__(256) void k_check_reduce(const Inst *__restrict__ i
 // ---------------------------------------------------------------- prune
 // B keeps (i, j) iff x_ij(p) >= t (eq. matrixred); the comparison is made on
 // log x_ij = p w_ij + log u_i + log v_j in FP64.
-template <bool GCOL>
+
+// The kept entries (x_ij >= t) of one 8-wide chunk, columns j0..j0+7 with
+// j0 < n, as a bit mask: the exact integer exponent first (below eskip an
+// entry cannot reach t), FP64 only for the few that pass. G_j for the
+// integer test from gs(c, j0), (G_j, gam_j) for FP64 from gq in the full
+// layout. The CSR count and fill both decide through this function, so the
+// fill places exactly the entries counted.
+template <class GQ, class GS>
+__device__ __forceinline__ unsigned kept8(GQ gq, GS gs, int (&wv)[8], int j0, int n, int n8, int pi, double p, int Fi,
+                                          double f, int eskip, double logt, bool sent) {
+    mask_pad8(wv, j0, n);
+    const int base = j0 >> 3;
+    unsigned cand = 0, keep = 0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+        if (__mul24(pi, wv[c]) + gs(c, j0) + Fi >= eskip) cand |= 1u << c;
+    if (sent) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+            if (wv[c] == SK_SENTINEL) cand &= ~(1u << c);
+    }
+    if (cand) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+            if (cand & (1u << c)) {
+                const double lx = p * (double)wv[c] + f + logv_of(gq_ld(gq, c * n8 + base));
+                if (lx >= logt) keep |= 1u << c;
+            }
+    }
+    return keep;
+}
+
+// The number of kept entries of one 8-wide row over its columns [lo, hi)
+// (lo a multiple of the step of kVisitLoads chunks), added to cnt.
+template <bool NT, class GQ, class GS>
+__device__ __forceinline__ void count_row_range(const Inst &I, GQ gq, GS gs, const int16_t *wr, int lane, int lo,
+                                                int hi, int pi, double p, int Fi, double f, int eskip,
+                                                double logt, bool sent, int &cnt) {
+    const int n = I.n, n8 = pad8(n) >> 3;
+    ring_row_chunks<NT>(wr, n, lane, lo, hi, [&](int j0, int (&wv)[8]) {
+        if (j0 < n) cnt += __popc(kept8(gq, gs, wv, j0, n, n8, pi, p, Fi, f, eskip, logt, sent));
+    });
+}
+
+template <bool NT, bool GCOL>
 __global__ __launch_bounds__(kRowWaves * kWave) void k_prune_count(const Inst *__restrict__ insts,
                                                                      const RowUnit *__restrict__ units,
                                                                      int nunits, double logt,
@@ -1291,6 +1397,43 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_prune_count(const Inst *_
     int u0, u1;
     unit_range(nunits, u0, u1);
     const int eskip = kept_skip(logt);
+    if constexpr (GCOL) {
+        if (insts[0].vec8) {
+            // the integer test reads G_j from LDS tiles (as the CSR fill)
+            __shared__ int gG[kGTile];
+            const Inst &I = insts[0];
+            const int n = I.n, ntile = (n + kGTile - 1) / kGTile;
+            // the row's state is wave-uniform: kept in scalar registers
+            const bool sent = __builtin_amdgcn_readfirstlane(I.ctl->sent) != 0u;
+            const int par = __builtin_amdgcn_readfirstlane(I.ctl->iter) & 1;
+            const int pi = __builtin_amdgcn_readfirstlane(I.ctl->p);
+            const double p = (double)pi;
+            for (int u = u0; u < u1; ++u) {
+                const int row = __builtin_amdgcn_readfirstlane(units[u].row0 + wave);
+                const bool on = row < n;
+                const int Fi = on ? __builtin_amdgcn_readfirstlane(I.F[par][row]) : 0;
+                const double f = (double)Fi + (double)(on ? rfl_f(I.phi[par][row]) : 0.0f);
+                const int16_t *wr = I.W + (int64_t)(on ? row : 0) * I.pitch;
+                int cnt = 0;
+                for (int t = 0; t < ntile; ++t) {
+                    const int lo = t * kGTile, hi = min(n, lo + kGTile);
+                    if (ntile > 1 || u == u0) {
+                        __syncthreads();
+                        stage_g_tile(I, gG, lo);
+                        __syncthreads();
+                    }
+                    if (!on) continue;
+                    auto gs = [&](int c, int j0) { return gG[c * kGT8 + ((j0 - lo) >> 3)]; };
+                    count_row_range<NT>(I, gq, gs, wr, lane, lo, hi, pi, p, Fi, f, eskip, logt, sent, cnt);
+                }
+                if (!on) continue;
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, kWave);
+                if (lane == 0) counts[row] = cnt;
+            }
+            return;
+        }
+    }
     int cur = -1;
     for (int u = u0; u < u1; ++u) {
         const RowUnit un = units[u];
@@ -1311,13 +1454,19 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_prune_count(const Inst *_
         const double f = (double)Fi + (double)I.phi[par][row];
         const int16_t *wr = I.W + (int64_t)row * I.pitch;
         int cnt = 0;
-        visit_row(I, wr, lane, [&](int j, int w) {
-            if (w == SK_SENTINEL) return;
-            const int2 q = gq_at(I, gq, j);
-            if (__mul24(pi, w) + q.x + Fi < eskip) return;  // cannot reach t
-            const double lx = p * (double)w + f + logv_of(q);
-            cnt += (lx >= logt);
-        });
+        if (I.vec8) {
+            const int n8 = pad8(n) >> 3;
+            auto gs = [&](int c, int j0) { return gq[c * n8 + (j0 >> 3)].x; };
+            count_row_range<NT>(I, gq, gs, wr, lane, 0, n, pi, p, Fi, f, eskip, logt, I.ctl->sent != 0u, cnt);
+        } else {
+            visit_row(I, wr, lane, [&](int j, int w) {
+                if (w == SK_SENTINEL) return;
+                const int2 q = gq_at(I, gq, j);
+                if (__mul24(pi, w) + q.x + Fi < eskip) return;  // cannot reach t
+                const double lx = p * (double)w + f + logv_of(q);
+                cnt += (lx >= logt);
+            });
+        }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, kWave);
         if (lane == 0) counts[row] = cnt;
@@ -1387,8 +1536,7 @@ __global__ __launch_bounds__(1024) void k_scan(const int64_t *__restrict__ count
 // multiple of the step of kVisitLoads chunks), placed from pos on: each lane
 // tests 8 consecutive columns; kept entries are placed by a wave prefix sum
 // of the per-lane counts (column order kept), skipped for the chunks where no
-// lane keeps an entry. G_j for the integer test from gs(c, j0) (column
-// j0 + c), (G_j, gam_j) for the FP64 test from gq in the full layout.
+// lane keeps an entry. The kept test is kept8's.
 template <bool NT, bool SPOS, class GQ, class GS>
 __device__ __forceinline__ void fill_row_range(const Inst &I, GQ gq, GS gs, const int16_t *wr, int lane, int lo,
                                                int hi, int pi, double p, int Fi, double f, int eskip,
@@ -1396,30 +1544,7 @@ __device__ __forceinline__ void fill_row_range(const Inst &I, GQ gq, GS gs, cons
                                                int16_t *__restrict__ wout) {
     const int n = I.n, n8 = pad8(n) >> 3;
     ring_row_chunks<NT>(wr, n, lane, lo, hi, [&](int j0, int (&wv)[8]) {
-        unsigned keep = 0;
-        if (j0 < n) {
-            mask_pad8(wv, j0, n);
-            // exact integer test first (below eskip an entry cannot reach
-            // t), then FP64 for the few that can
-            const int base = j0 >> 3;
-            unsigned cand = 0;
-#pragma unroll
-            for (int c = 0; c < 8; ++c)
-                if (__mul24(pi, wv[c]) + gs(c, j0) + Fi >= eskip) cand |= 1u << c;
-            if (sent) {
-#pragma unroll
-                for (int c = 0; c < 8; ++c)
-                    if (wv[c] == SK_SENTINEL) cand &= ~(1u << c);
-            }
-            if (cand) {
-#pragma unroll
-                for (int c = 0; c < 8; ++c)
-                    if (cand & (1u << c)) {
-                        const double lx = p * (double)wv[c] + f + logv_of(gq_ld(gq, c * n8 + base));
-                        if (lx >= logt) keep |= 1u << c;
-                    }
-            }
-        }
+        const unsigned keep = j0 < n ? kept8(gq, gs, wv, j0, n, n8, pi, p, Fi, f, eskip, logt, sent) : 0u;
         if (__ballot(keep != 0u) == 0ull) return;  // nothing kept in this chunk
         const int cnt = __popc(keep);
         int incl = cnt;
@@ -2141,13 +2266,17 @@ hipError_t launch_check_cols(const Inst *d_insts, int inst, int n, int nseg, int
     return hipGetLastError();
 }
 hipError_t launch_prune_count(const Inst *d_insts, const RowUnit *d_units, int nunits, int grid,
-                              double logt, int64_t *counts, size_t lds_bytes, int gcol, hipStream_t st) {
+                              double logt, int64_t *counts, size_t lds_bytes, int nt_loads, int gcol,
+                              hipStream_t st) {
+    const dim3 g(grid), b(kRowWaves * kWave);
     if (gcol)
-        hipLaunchKernelGGL(k_prune_count<true>, dim3(grid), dim3(kRowWaves * kWave), 0, st, d_insts, d_units,
-                           nunits, logt, counts);
+        hipLaunchKernelGGL((k_prune_count<true, true>), g, b, 0, st, d_insts, d_units, nunits, logt, counts);
+    else if (nt_loads)
+        hipLaunchKernelGGL((k_prune_count<true, false>), g, b, lds_bytes, st, d_insts, d_units, nunits, logt,
+                           counts);
     else
-        hipLaunchKernelGGL(k_prune_count<false>, dim3(grid), dim3(kRowWaves * kWave), lds_bytes, st, d_insts,
-                           d_units, nunits, logt, counts);
+        hipLaunchKernelGGL((k_prune_count<false, false>), g, b, lds_bytes, st, d_insts, d_units, nunits, logt,
+                           counts);
     return hipGetLastError();
 }
 hipError_t launch_scan(const int64_t *counts, int64_t *row_ptr, int n, hipStream_t st,
@@ -2180,8 +2309,8 @@ hipError_t set_kernel_attributes() {
         if ((e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds)) != hipSuccess)
             return e;
     for (const void *f : {(const void *)k_check_rows<true, false>, (const void *)k_check_rows<false, false>,
-                          (const void *)k_prune_count<false>, (const void *)k_prune_fill<true, false>,
-                          (const void *)k_prune_fill<false, false>})
+                          (const void *)k_prune_count<true, false>, (const void *)k_prune_count<false, false>,
+                          (const void *)k_prune_fill<true, false>, (const void *)k_prune_fill<false, false>})
         if ((e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds)) != hipSuccess)
             return e;
     return hipSuccess;

@@ -951,7 +951,7 @@ sk_status sk_prune(sk_ctx *ctx, const int16_t *W, int32_t n, const void *potenti
     const int gcol = I.colpack != nullptr;  // n > kLdsMaxN: (G_j, gam_j) packed
     if (gcol) HIPCHK(ctx, launch_col_pack(B.d_insts, 0, n, 1, ctx->stream));
     HIPCHK(ctx, PROF(ctx, KID_PRUNE_COUNT, launch_prune_count(B.d_insts, B.d_rows, nunits, B.row_grid, logt, B.d_counts,
-                                   gq_lds_bytes(n), gcol, ctx->stream)));
+                                   gq_lds_bytes(n), B.h_insts[0].nt, gcol, ctx->stream)));
     HIPCHK(ctx, PROF(ctx, KID_SCAN, launch_scan(B.d_counts, csr->row_ptr, n, ctx->stream)));
     int64_t total = 0;
     HIPCHK(ctx, hipMemcpyAsync(&total, csr->row_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost,

@@ -279,7 +279,7 @@ static sk_status retire_all(Server *S, const std::vector<int> &fin) {
         const double logt = std::log(r->prm.threshold);
         int64_t *d_rp = (int64_t *)(ctx->arena + rp_off[q]);
         e = launch_prune_count(B.d_insts, B.d_rows + first, nunits, grid, logt, B.d_counts,
-                               gq_lds_bytes(r->n), 0, ctx->stream);
+                               gq_lds_bytes(r->n), B.h_insts[k].nt, 0, ctx->stream);
         if (e == hipSuccess) e = launch_scan(B.d_counts, d_rp, r->n, ctx->stream, B.d_nnz + k);
     }
     if (st == SK_OK && e == hipSuccess)

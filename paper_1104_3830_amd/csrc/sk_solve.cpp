@@ -46,7 +46,8 @@ sk_status reduce_and_solve(sk_ctx *ctx, Batch &B, Bump &rest, int64_t *d_rp, con
     if (gcol) HIPCHK(ctx, launch_col_pack(B.d_insts, 0, n, 1, ctx->stream));
     if (!counted) {
         HIPCHK(ctx, PROF(ctx, KID_PRUNE_COUNT, launch_prune_count(B.d_insts, B.d_rows, nunits, B.row_grid,
-                                                                 logt, B.d_counts, lds, gcol, ctx->stream)));
+                                                                 logt, B.d_counts, lds, I.nt, gcol,
+                                                                 ctx->stream)));
         HIPCHK(ctx, PROF(ctx, KID_SCAN, launch_scan(B.d_counts, d_rp, n, ctx->stream, B.d_nnz)));
         HIPCHK(ctx, hipMemcpyAsync(ctx->h_nnz, B.d_nnz, sizeof(int64_t), hipMemcpyDeviceToHost,
                                    ctx->stream));
