@@ -1350,10 +1350,19 @@ __device__ __forceinline__ unsigned kept8(GQ gq, GS gs, int (&wv)[8], int j0, in
                                           double f, int eskip, double logt, bool sent) {
     mask_pad8(wv, j0, n);
     const int base = j0 >> 3;
+    // the chunk's largest p w + G_j first: below eskip - F_i (the usual
+    // case) no entry is a candidate
+    int e[8], m8 = INT_MIN;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        e[c] = __mul24(pi, wv[c]) + gs(c, j0);
+        m8 = max(m8, e[c]);
+    }
+    if (m8 < eskip - Fi) return 0u;
     unsigned cand = 0, keep = 0;
 #pragma unroll
     for (int c = 0; c < 8; ++c)
-        if (__mul24(pi, wv[c]) + gs(c, j0) + Fi >= eskip) cand |= 1u << c;
+        if (e[c] + Fi >= eskip) cand |= 1u << c;
     if (sent) {
 #pragma unroll
         for (int c = 0; c < 8; ++c)
