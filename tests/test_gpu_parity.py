@@ -252,6 +252,49 @@ def test_prune_matches_oracle_on_same_potentials(ctx, n):
     assert np.array_equal(mask[~band], keep[~band])
 
 
+@pytest.mark.parametrize("n", [5000, 5003])
+def test_check_count_fill_ragged_batches(ctx, n):
+    """n = 5000 and 5003 (the padded copy, a ragged last chunk): the row check,
+    the CSR count and the fill stream each row as full batches of four
+    512-column chunks followed by a partial one, and the column check walks
+    its row segments the same way. Through sk_solve (w uniform on 0..1000,
+    ladder 1..32, tol 1e-5, t = 1e-4, at most 5000 iterations per stage): the
+    FP64 row and column residuals equal the oracle's sums on the returned
+    potentials, the permutation's weight is
+    that of W; sk_prune on the same potentials counts as many entries as the
+    solve's check did, and its CSR is the oracle's kept set x_ij >= t (entries
+    within 1e-9 of log t aside) with the weights of W, in column order."""
+    W = skgen.uniform_weights(n, 0, 1000, seed=n)
+    p, t = 32, 1e-4
+    prm = sk.make_params([1, 2, 4, 8, 16, p], tol=1e-5 - MARGIN, max_iters=5000, check_every=64, threshold=t)
+    out = ctx.solve(dev(W), prm)
+    rep = out["report"]
+    # (a stage may reach the iteration cap here: the comparisons below hold
+    # on whatever potentials are returned)
+    assert out["status"] == sk.SK_OK
+    perm = np.asarray(out["perm"])
+    assert np.array_equal(np.sort(perm), np.arange(n))
+    assert out["weight"] == int(W[np.arange(n), perm].astype(np.int64).sum())
+    B = oracle.log_weights(W)
+    ub, vb = bars(out["potentials"], n, p)
+    r, c = oracle.sums(B, p, ub, vb)
+    assert abs(np.abs(r - 1).max() - rep["residual_fp64"]) < 1e-9
+    assert abs(np.abs(c - 1).max() - rep["col_residual_fp64"]) < 1e-9
+    row_ptr, col, w = ctx.prune(dev(W), out["potentials"], prm)
+    rp, cc, ww = row_ptr.cpu().numpy(), col.cpu().numpy(), w.cpu().numpy()
+    assert rp[-1] == out["nnz"] == len(cc)
+    mask = np.zeros((n, n), dtype=bool)
+    for i in range(n):
+        seg = cc[rp[i]:rp[i + 1]]
+        assert np.all(np.diff(seg) > 0)
+        mask[i, seg] = True
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    assert np.array_equal(ww, W[rows, cc])
+    keep = oracle.prune(B, p, ub, vb, t)
+    band = np.abs(logx(B, p, ub, vb) - np.log(t)) < 1e-9
+    assert np.array_equal(mask[~band], keep[~band])
+
+
 # ---------------------------------------------------------------- batch, determinism
 
 def test_batch_equals_single_bitwise(ctx):
