@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "sk_exptab.h"
+#include "sk_ring.h"
 #include "sk_runtime.h"
 
 namespace sk {
@@ -123,39 +124,28 @@ __global__ __launch_bounds__(kRowWaves * kWave) void k_absorb(const Inst *__rest
             return w == SK_SENTINEL ? 0.f : fminf(e, kKHi);
         };
         if (I.vec8) {
-            // 8 columns per lane: one 16-byte load of W, one 16/32-byte store of
-            // K (K's padding columns, j >= n, get 0 as in the 1-wide branch)
+            // 8 columns per lane: the row of W through the load ring, one
+            // 16/32-byte global store of K per chunk (K's padding columns,
+            // j >= n, get 0 as in the 1-wide branch)
             const int n8 = pad8(n) >> 3;
-            constexpr int U = 2;
-            for (int j0 = lane * 8; j0 < n; j0 += U * 512) {
-                int4 v[U];
+            ring_row_chunks<NT>(wr, n, lane, 0, n, [&](int jj, int (&w)[8]) {
+                if (jj >= n) return;
+                float kv[8];
 #pragma unroll
-                for (int k = 0; k < U; ++k)
-                    v[k] = j0 + k * 512 < n ? gload<NT>(reinterpret_cast<const int4 *>(wr + j0 + k * 512))
-                                            : make_int4(0, 0, 0, 0);
+                for (int c = 0; c < 8; ++c) kv[c] = jj + c < n ? entry(w[c], pot[c * n8 + (jj >> 3)]) : 0.f;
+                if (ST == SK_K_BF16) {
+                    sk_gi4 o;
 #pragma unroll
-                for (int k = 0; k < U; ++k) {
-                    const int jj = j0 + k * 512;
-                    if (jj >= n) break;
-                    int w[8];
-                    unpack8i(v[k], w);
-                    float kv[8];
-#pragma unroll
-                    for (int c = 0; c < 8; ++c)
-                        kv[c] = jj + c < n ? entry(w[c], pot[c * n8 + (jj >> 3)]) : 0.f;
-                    if (ST == SK_K_BF16) {
-                        uint32_t o[4];
-#pragma unroll
-                        for (int c = 0; c < 4; ++c) o[c] = bf16_rne(kv[2 * c]) | (bf16_rne(kv[2 * c + 1]) << 16);
-                        *reinterpret_cast<int4 *>(reinterpret_cast<uint16_t *>(I.K) + (int64_t)row * kp + jj) =
-                            make_int4((int)o[0], (int)o[1], (int)o[2], (int)o[3]);
-                    } else {
-                        float4 *dst = reinterpret_cast<float4 *>(reinterpret_cast<float *>(I.K) + (int64_t)row * kp + jj);
-                        dst[0] = make_float4(kv[0], kv[1], kv[2], kv[3]);
-                        dst[1] = make_float4(kv[4], kv[5], kv[6], kv[7]);
-                    }
+                    for (int c = 0; c < 4; ++c)
+                        o[c] = (int)(bf16_rne(kv[2 * c]) | (bf16_rne(kv[2 * c + 1]) << 16));
+                    *(SK_GLOBAL sk_gi4 *)(reinterpret_cast<uint16_t *>(I.K) + (int64_t)row * kp + jj) = o;
+                } else {
+                    SK_GLOBAL sk_gf4 *dst =
+                        (SK_GLOBAL sk_gf4 *)(reinterpret_cast<float *>(I.K) + (int64_t)row * kp + jj);
+                    dst[0] = sk_gf4{kv[0], kv[1], kv[2], kv[3]};
+                    dst[1] = sk_gf4{kv[4], kv[5], kv[6], kv[7]};
                 }
-            }
+            });
         } else {
             for (int j = lane; j < kp; j += kWave) {
                 const float k = j < n ? entry(wr[j], pot[j]) : 0.f;
